@@ -1,0 +1,70 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module holds no arithmetic of the method: it only draws particle positions
+and complex charges.  It is shared by the tests, bench.py and the oracle checks.
+
+Layered-medium conventions: ``d`` lists the L interfaces top to bottom (strictly
+decreasing); ``k`` lists the L+1 real wavenumbers, layer 0 on top (z > d[0]),
+layer l between d[l] (below) and d[l-1] (above).
+
+The three-layer geometry (interfaces z = 0, -1.2) follows the paper's Section 4
+test problem; the unit cubes centred at (0,0,0.6), (0,0,-0.6), (0,0,-1.8) keep
+every particle at least 0.1 away from an interface.  The paper's own irregular
+domains are replaced by these cubes.
+"""
+import numpy as np
+
+THREE_LAYER_D = (0.0, -1.2)
+THREE_LAYER_K = (0.8, 1.5, 2.0)
+THREE_LAYER_CENTERS = (0.6, -0.6, -1.8)
+
+
+def split_even(n, parts):
+    """n split into `parts` counts, the remainder going to the top layers."""
+    base, rem = divmod(n, parts)
+    return [base + (1 if i < rem else 0) for i in range(parts)]
+
+
+def layered_cubes(d, k, counts, centers, side=1.0, seed=0, shuffle=False):
+    """Uniform particles in axis-aligned cubes (one per layer) with complex charges
+    whose real and imaginary parts are uniform on [-1, 1]."""
+    rng = np.random.default_rng(seed)
+    xs, ys, zs, ls = [], [], [], []
+    for l, (n, c) in enumerate(zip(counts, centers)):
+        xs.append(rng.uniform(-0.5, 0.5, n) * side)
+        ys.append(rng.uniform(-0.5, 0.5, n) * side)
+        zs.append(c + rng.uniform(-0.5, 0.5, n) * side)
+        ls.append(np.full(n, l, dtype=np.int32))
+    x = np.concatenate(xs)
+    y = np.concatenate(ys)
+    z = np.concatenate(zs)
+    layer = np.concatenate(ls).astype(np.int32)
+    nt = len(x)
+    q = rng.uniform(-1.0, 1.0, nt) + 1j * rng.uniform(-1.0, 1.0, nt)
+    if shuffle:
+        perm = rng.permutation(nt)
+        x, y, z, layer, q = x[perm], y[perm], z[perm], layer[perm], q[perm]
+    return dict(d=np.array(d, dtype=np.float64), k=np.array(k, dtype=np.float64), x=x, y=y, z=z,
+                layer=layer, q=q.astype(np.complex128))
+
+
+def config1(seed=1):
+    """Plain FP64 case: 3 layers, 1000 uniform particles per unit cube, p = 5, leaf <= 50."""
+    w = layered_cubes(THREE_LAYER_D, THREE_LAYER_K, [1000, 1000, 1000], THREE_LAYER_CENTERS, seed=seed)
+    w.update(p=5, leaf=50, name="3-layer cubes, N=3000, p=5, leaf<=50")
+    return w
+
+
+def config2(n=1048576, seed=2, p=8, leaf=64):
+    """N = 1,048,576 split evenly over the three cubes, p = 8."""
+    counts = split_even(n, 3)
+    w = layered_cubes(THREE_LAYER_D, THREE_LAYER_K, counts, THREE_LAYER_CENTERS, seed=seed)
+    w.update(p=p, leaf=leaf, name="3-layer cubes, N=%d, p=%d, leaf<=%d" % (n, p, leaf))
+    return w
+
+
+def small_three_layer(n_per_layer=100, seed=0, p=4, leaf=16, shuffle=False):
+    w = layered_cubes(THREE_LAYER_D, THREE_LAYER_K, [n_per_layer] * 3, THREE_LAYER_CENTERS, seed=seed,
+                      shuffle=shuffle)
+    w.update(p=p, leaf=leaf, name="3-layer cubes, %d per layer" % n_per_layer)
+    return w
