@@ -1,0 +1,148 @@
+/*
+ * lfmm -- fast multipole method for the 3-D Helmholtz equation in layered media
+ * on AMD MI355X (gfx950).  C ABI of the HIP library liblfmm.so.
+ *
+ * Method: Wang, Zhang & Cai, "Fast multipole method for 3-D Helmholtz equation
+ * in layered media", SIAM J. Sci. Comput. (2019).  The library evaluates, for N
+ * particles with complex charges Q_j in a medium of L+1 layers,
+ *
+ *   Phi_l(r_i) = sum_{j in layer l, j != i} Q_j h0(k_l |r_i - r_j|)
+ *              + sum over the four reaction components (up/down target part x
+ *                up/down source part) of sum_j Q_j u^{**}_{l l'}(r_i, r_j),
+ *
+ * the total interaction of Section 3.4 eq. (totalinteraction), with the reaction
+ * components (Section 3.1 eqs. (greenfuncomponent), (totaldensity)) scaled by
+ * 4 pi / (i k_l) so that the free part is h0(x) = e^{ix}/(ix).  The reaction
+ * components are evaluated by FMMs on equivalent polarisation sources
+ * (Section 3.3 eq. (eqpolarizedsource), Algorithm 1), the free part by the classic
+ * FMM, truncated at order p.
+ *
+ * Geometry: L interfaces z = d[0] > d[1] > ... > d[L-1]; layer 0 is z > d[0],
+ * layer l (0 < l < L) is d[l] < z < d[l-1], layer L is z < d[L-1]; k[0..L] are
+ * the real wavenumbers, layer 0 first.  Particles must not lie on an interface.
+ *
+ * Error behaviour: every call returns an lfmm_status code; nothing is printed
+ * and no call aborts the process.
+ */
+#ifndef LFMM_H
+#define LFMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LFMM_OK = 0,
+  LFMM_EINVAL = 1,  /* invalid argument: plan parameters, particle data (non-finite coordinate,
+                       layer id inconsistent with z, particle closer than min_gap to an interface) */
+  LFMM_ENOMEM = 2,  /* device or host allocation failed */
+  LFMM_EHIP = 3,    /* a HIP runtime call failed */
+  LFMM_ENOTSUP = 4  /* the configuration is outside what this build supports */
+} lfmm_status;
+
+/* Plan options; pass NULL for the defaults shown. */
+typedef struct {
+  double contour_b; /* depth of the deformed Sommerfeld contour (Section 3.5, b): 0.5 */
+  int max_depth;    /* largest octree depth, <= 8: 8 */
+  double min_gap;   /* smallest allowed particle-to-interface distance: 1e-9 */
+  int profile;      /* 1: record per-stage times (adds stream events): 0 */
+} lfmm_options;
+
+typedef struct lfmm_plan_s lfmm_plan_t;
+
+/* Per-evaluation report of the last lfmm_eval / lfmm_eval_device call. */
+typedef struct {
+  int n_trees;
+  int free_depth[17];      /* octree depth of each layer's free-space tree (-1: empty layer) */
+  int reaction_depth;      /* common depth of every reaction tree (-1: none) */
+  int64_t n_boxes;         /* boxes over all trees and levels */
+  int64_t n_ops_free;      /* free-space translation operators generated */
+  int64_t n_react_classes; /* reaction M2L integral classes (each an (p+1)^2 x (p+1)^2 matrix) */
+  int64_t n_react_nodes;   /* contour nodes summed over the classes */
+  int64_t n_ops_react;     /* reaction M2L operators */
+  int64_t m2l_pairs;       /* (target box, source box) M2L products, free + reaction */
+  int64_t p2p_pairs_bound; /* upper bound of free-space near-field pairs */
+  int64_t nf_react_pairs;  /* near-field reaction pairs */
+  double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
+} lfmm_report;
+
+/*
+ * lfmm_plan -- fix the layered medium and the FMM parameters.
+ *   L        number of interfaces (0 <= L <= 16; L = 0 is free space)
+ *   d        host array of L interface heights, strictly decreasing (copied)
+ *   k        host array of L+1 wavenumbers, each > 0 (copied)
+ *   p        truncation order of the expansions, 1 <= p <= 10 ((p+1)^2 coefficients)
+ *   leaf_max largest number of particles allowed in a leaf before refinement (>= 1)
+ *   opt      NULL or options
+ *   out      receives the plan (owned by the library; release with lfmm_destroy)
+ * Returns LFMM_EINVAL for invalid parameters, LFMM_EHIP/LFMM_ENOMEM on device errors.
+ */
+int lfmm_plan(int L, const double* d, const double* k, int p, int leaf_max, const lfmm_options* opt,
+              lfmm_plan_t** out);
+
+/*
+ * lfmm_eval_device -- Phi at every particle (targets = sources), device memory.
+ *   n        number of particles (0 <= n < 2^31)
+ *   xyz      device, 3*n doubles, structure of arrays: x[0..n), y[0..n), z[0..n)
+ *   layer    device, n int32 layer ids or NULL (then derived from z); when given,
+ *            each id must equal the layer containing z, else LFMM_EINVAL
+ *   q        device, 2*n doubles, charges interleaved (re, im)
+ *   phi      device, 2*n doubles, output interleaved (re, im); written entirely
+ *   stream   hipStream_t to run on (NULL: the default stream); the call returns
+ *            after the result is complete on that stream
+ * Buffers are owned by the caller and must not overlap phi.  The plan keeps a
+ * device workspace between calls; calls on one plan must not overlap.
+ */
+int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q,
+                     double* phi, void* stream);
+
+/* lfmm_eval -- the same with host buffers (copied to and from the device). */
+int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi);
+
+/* Report of the last evaluation on this plan. */
+int lfmm_last_report(const lfmm_plan_t* plan, lfmm_report* rep);
+
+/* Name of stage index i of lfmm_report.stage_ms (NULL past the last). */
+const char* lfmm_stage_name(int i);
+
+/* Release a plan and its device memory (NULL is ignored). */
+void lfmm_destroy(lfmm_plan_t* plan);
+
+/* Text of a status code. */
+const char* lfmm_status_string(int status);
+
+/* ---- component entry points (the same kernels the evaluation runs) ---- */
+
+/*
+ * Free-space translation operator of the addition theorems (Section 2.1):
+ * new_{nm} = sum_{nu,mu} Op[(n,m)][(nu,mu)] old_{nu,mu}; kind 0 regular (M2M with
+ * b = parent - child centre, L2L with b = child - parent centre), kind 1 singular
+ * (M2L with b = target - source centre).  Computed on the GPU for wavenumber kw;
+ * out: host, (p+1)^4 complex as re/im pairs, row-major over idx(n,m) = n*n+n+m.
+ */
+int lfmm_translation(lfmm_plan_t* plan, int kind, double kw, const double* b, double* out);
+
+/*
+ * Reaction M2L operator T (Section 3.3 eqs. (metoleimage1)-(metoleimage2), in the
+ * Phi normalisation and the polarisation frame): target layer l with direction a
+ * (0 up, 1 down), source layer lp with direction b, lateral offset (dx, dy) of the
+ * target centre from the polarisation-source centre, target-centre height zt > 0
+ * above the interface and source-centre depth zs > 0 below it.  Computed on the
+ * GPU by contour quadrature; out as for lfmm_translation.
+ */
+int lfmm_reaction_operator(lfmm_plan_t* plan, int l, int a, int lp, int b, double dx, double dy, double zt, double zs,
+                           double* out);
+
+/*
+ * Reaction densities sigma^{ab}_{l,lp}(k_rho) (Section 3.1) at n complex points
+ * (host, re/im pairs) computed on the GPU; out: host, n x 4 complex
+ * (up-up, up-down, down-up, down-down), zero where the component does not exist.
+ */
+int lfmm_densities(lfmm_plan_t* plan, int n, const double* krho, int l, int lp, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LFMM_H */

@@ -1,0 +1,1117 @@
+// Host orchestration and C ABI of the layered-media Helmholtz FMM library.
+//
+// One lfmm_eval_device call runs every stage of the method on the GPU:
+// layer classification, octrees (free-space tree per layer; target and
+// polarisation-source trees per reaction direction sharing one root split at
+// the interface), operator generation, the upward pass (P2M, M2M), M2L (free and
+// the four reaction types), the downward pass (L2L, L2P), near-field sums and
+// the component sum.  The host only does bookkeeping on counts read back at a
+// few synchronisation points.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/lfmm.h"
+#include "lfmm_internal.h"
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+#define HIPCHK(x)                       \
+  do {                                  \
+    hipError_t _e = (x);                \
+    if (_e != hipSuccess) throw Fail{LFMM_EHIP}; \
+  } while (0)
+
+struct Fail {
+  int code;
+};
+
+enum {
+  ST_CLASSIFY, ST_TREE, ST_OPS_FREE, ST_OPS_REACT, ST_JOBS, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P,
+  ST_NEAR_REACT, ST_SUM, ST_COUNT
+};
+const char* kStageNames[ST_COUNT] = {"classify", "tree", "ops_free", "ops_reaction", "jobs", "p2m", "m2m",
+                                     "m2l", "l2l", "l2p", "p2p_free", "near_reaction", "sum"};
+
+// ---------------------------------------------------------------------------
+// Host-side constants owned by the library (independent of any checker):
+// Gauss-Legendre rules by Newton iteration on P_n and Gaunt coefficients by
+// exact Gauss-Legendre quadrature of triple products of normalised Legendre
+// functions, G(nu,mu; q,s; n) = 2 pi int_{-1}^{1} Phat_nu^mu Phat_q^s Phat_n^{mu+s} dx.
+// ---------------------------------------------------------------------------
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; i++) {
+    double t = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; it++) {
+      double p0 = 1.0, p1 = t;
+      for (int kk = 2; kk <= n; kk++) {
+        double p2 = ((2.0 * kk - 1.0) * t * p1 - (kk - 1.0) * p0) / kk;
+        p0 = p1;
+        p1 = p2;
+      }
+      double dp = n * (t * p1 - p0) / (t * t - 1.0);
+      double dt = p1 / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = t;
+    for (int kk = 2; kk <= n; kk++) {
+      double p2 = ((2.0 * kk - 1.0) * t * p1 - (kk - 1.0) * p0) / kk;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (t * p1 - p0) / (t * t - 1.0);
+    x[i] = t;
+    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+// Phat_n^m(x) for 0 <= m <= n <= P at real x, table [n][m]
+void host_phat(int P, double x, std::vector<double>& T) {
+  T.assign((P + 1) * (P + 1), 0.0);
+  double s = std::sqrt(std::max(0.0, 1.0 - x * x));
+  double pmm = 1.0 / std::sqrt(4.0 * M_PI);
+  for (int m = 0; m <= P; m++) {
+    if (m > 0) pmm *= std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * s;
+    T[m * (P + 1) + m] = pmm;
+    if (m + 1 <= P) {
+      double p0 = pmm, p1 = std::sqrt(2.0 * m + 3.0) * x * pmm;
+      T[(m + 1) * (P + 1) + m] = p1;
+      for (int n = m + 2; n <= P; n++) {
+        double a = std::sqrt((2.0 * n - 1.0) * (2.0 * n + 1.0) / ((double)(n - m) * (n + m)));
+        double b = std::sqrt((2.0 * n + 1.0) * (n - m - 1.0) * (n + m - 1.0) / ((2.0 * n - 3.0) * (n + m) * (double)(n - m)));
+        double p2 = a * x * p1 - b * p0;
+        T[n * (P + 1) + m] = p2;
+        p0 = p1;
+        p1 = p2;
+      }
+    }
+  }
+}
+
+std::vector<double> gaunt_table(int p) {
+  int NC = (p + 1) * (p + 1), P2 = 2 * p, NQ = 3 * p + 4;
+  std::vector<double> gx, gw;
+  gauss_rule(NQ, gx, gw);
+  std::vector<std::vector<double>> tabs(NQ);
+  for (int g = 0; g < NQ; g++) host_phat(P2, gx[g], tabs[g]);
+  auto ph = [&](int g, int n, int m) {
+    double v = tabs[g][n * (P2 + 1) + std::abs(m)];
+    return (m < 0 && (std::abs(m) & 1)) ? -v : v;
+  };
+  std::vector<double> G((size_t)NC * NC * (p + 1), 0.0);
+  for (int n = 0; n <= p; n++)
+    for (int m = -n; m <= n; m++)
+      for (int nu = 0; nu <= p; nu++)
+        for (int mu = -nu; mu <= nu; mu++) {
+          int s = m - mu, q0 = std::abs(n - nu);
+          int jmax = std::min(n, nu);
+          for (int j = 0; j <= jmax; j++) {
+            int q = q0 + 2 * j;
+            if (std::abs(s) > q) continue;
+            double acc = 0.0;
+            for (int g = 0; g < NQ; g++) acc += gw[g] * ph(g, nu, mu) * ph(g, q, s) * ph(g, n, m);
+            G[((size_t)cidx(n, m) * NC + cidx(nu, mu)) * (p + 1) + j] = 2.0 * M_PI * acc;
+          }
+        }
+  return G;
+}
+
+// x such that the decay x^N e^{-x} has fallen by e^{-c} from its peak at x = N
+double decay_length(int N, double c) {
+  if (N <= 0) return c;
+  double lo = N, hi = N + c + 10.0 * N + 10.0;
+  for (int it = 0; it < 200; it++) {
+    double mid = 0.5 * (lo + hi);
+    double v = mid - N * std::log(mid / N) - N;
+    if (v >= c) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+}  // namespace
+
+struct lfmm_plan_s {
+  Stack st;
+  int p, leaf_max, NC, NCK, NRT, NKS, NT, opsz;
+  double b, min_gap;
+  int max_depth, profile;
+  double kmax;
+  double* d_gaunt = nullptr;
+  EntryDesc* d_ent = nullptr;
+  int nent = 0;
+  std::map<std::string, DevBuf> bufs;
+  std::vector<char> hbuf;
+  lfmm_report rep;
+  hipEvent_t ev[ST_COUNT + 1];
+  bool ev_ok = false;
+
+  template <typename T>
+  T* dev(const char* name, size_t count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    DevBuf& B = bufs[name];
+    if (B.cap < bytes) {
+      if (B.p) HIPCHK(hipFree(B.p));
+      B.p = nullptr;
+      B.cap = 0;
+      size_t nb = bytes + bytes / 8;
+      if (hipMalloc(&B.p, nb) != hipSuccess) {
+        B.p = nullptr;
+        throw Fail{LFMM_ENOMEM};
+      }
+      B.cap = nb;
+    }
+    return (T*)B.p;
+  }
+  template <typename T>
+  T* upload(const char* name, const std::vector<T>& v, hipStream_t s) {
+    T* d = dev<T>(name, std::max<size_t>(v.size(), 1));
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+  }
+  Rule make_rule(double dz, double rho, int npow) const {
+    Rule r;
+    r.b = b;
+    r.T0 = 0.5 * std::ceil(2.0 * (kmax + 2.0));
+    r.hn = 0.5;
+    r.nnear = (int)std::lround(r.T0 / r.hn);
+    double U = decay_length(npow, 40.0);
+    double tfar = U / dz;
+    double hf = 4.0 / dz;
+    if (rho > 0.0) hf = std::min(hf, 3.5 / rho);
+    hf = std::min(hf, 4.0);
+    r.nfar = std::max(1, (int)std::ceil(tfar / hf));
+    r.hf = tfar / r.nfar;
+    return r;
+  }
+};
+
+namespace {
+
+int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, const lfmm_options* opt,
+              lfmm_plan_t** out) {
+  if (!out) return LFMM_EINVAL;
+  *out = nullptr;
+  if (L < 0 || L > LFMM_MAXL || p < 1 || p > 10 || leaf_max < 1) return LFMM_EINVAL;
+  if (L > 0 && !d) return LFMM_EINVAL;
+  if (!k) return LFMM_EINVAL;
+  for (int i = 0; i <= L; i++)
+    if (!(k[i] > 0.0) || !std::isfinite(k[i])) return LFMM_EINVAL;
+  for (int i = 0; i < L; i++) {
+    if (!std::isfinite(d[i])) return LFMM_EINVAL;
+    if (i > 0 && !(d[i] < d[i - 1])) return LFMM_EINVAL;
+  }
+  lfmm_plan_s* P = new lfmm_plan_s();
+  P->st.L = L;
+  for (int i = 0; i < LFMM_MAXL; i++) P->st.d[i] = (i < L) ? d[i] : 0.0;
+  P->kmax = 0;
+  for (int i = 0; i <= LFMM_MAXL; i++) {
+    P->st.k[i] = (i <= L) ? k[i] : 1.0;
+    if (i <= L) P->kmax = std::max(P->kmax, k[i]);
+  }
+  P->p = p;
+  P->leaf_max = leaf_max;
+  P->NC = (p + 1) * (p + 1);
+  P->NCK = (P->NC + 3) / 4 * 4;
+  P->NRT = (P->NC + 15) / 16;
+  P->NKS = P->NCK / 4;
+  P->NT = (p + 1) * (p + 2) / 2;
+  P->opsz = P->NRT * P->NKS * 128;
+  P->b = 0.5;
+  P->min_gap = 1e-9;
+  P->max_depth = 8;
+  P->profile = 0;
+  if (opt) {
+    if (opt->contour_b > 0) P->b = opt->contour_b;
+    if (opt->max_depth > 0) P->max_depth = std::min(8, opt->max_depth);
+    if (opt->min_gap > 0) P->min_gap = opt->min_gap;
+    P->profile = opt->profile;
+  }
+  memset(&P->rep, 0, sizeof(P->rep));
+  try {
+    std::vector<double> gx, gw;
+    gauss_rule(LFMM_NGL, gx, gw);
+    lk_set_gl(gx.data(), gw.data());
+    std::vector<double> G = gaunt_table(p);
+    HIPCHK(hipMalloc(&P->d_gaunt, G.size() * sizeof(double)));
+    HIPCHK(hipMemcpy(P->d_gaunt, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
+    // canonical entries of the reaction integral matrices
+    std::vector<EntryDesc> ent;
+    for (int n = 0; n <= p; n++)
+      for (int m = 0; m <= n; m++)
+        for (int n2 = 0; n2 <= p; n2++)
+          for (int m2 = -n2; m2 <= n2; m2++) {
+            if (m == 0 && m2 < 0) continue;
+            EntryDesc E;
+            int q = m2 - m;
+            E.ia = (short)tix(n, m);
+            E.ib = (short)tix(n2, std::abs(m2));
+            E.iq = (short)std::abs(q);
+            int sg = 1;
+            if (m2 < 0 && (std::abs(m2) & 1)) sg = -sg;
+            if (q < 0 && (std::abs(q) & 1)) sg = -sg;
+            E.sg = (short)sg;
+            E.row = cidx(n, m);
+            E.col = cidx(n2, m2);
+            E.mrow = cidx(n, -m);
+            E.mcol = cidx(n2, -m2);
+            ent.push_back(E);
+          }
+    P->nent = (int)ent.size();
+    HIPCHK(hipMalloc(&P->d_ent, ent.size() * sizeof(EntryDesc)));
+    HIPCHK(hipMemcpy(P->d_ent, ent.data(), ent.size() * sizeof(EntryDesc), hipMemcpyHostToDevice));
+    P->ev_ok = true;
+    for (int i = 0; i <= ST_COUNT; i++)
+      if (hipEventCreate(&P->ev[i]) != hipSuccess) P->ev_ok = false;
+  } catch (Fail& f) {
+    lfmm_destroy(P);
+    return f.code;
+  }
+  *out = P;
+  return LFMM_OK;
+}
+
+inline int has_dir(const Stack& st, int l, int a) { return a == 0 ? (l <= st.L - 1) : (l >= 1); }
+
+struct Group {
+  int seq0, K;
+};
+
+// Build the GEMM block table of one job from its sorted group ids and counts.
+void build_blocks(const std::vector<int>& counts, const std::vector<Group>& groups, std::vector<GBlock>& blocks,
+                  std::vector<int>& gstart, std::vector<int>& blk_first, std::vector<int>& blk_count,
+                  const std::vector<int>& group_level, int nlev) {
+  int ng = (int)groups.size();
+  gstart.assign(ng + 1, 0);
+  for (int g = 0; g < ng; g++) gstart[g + 1] = gstart[g] + counts[g];
+  blocks.clear();
+  blk_first.assign(nlev, -1);
+  blk_count.assign(nlev, 0);
+  for (int g = 0; g < ng; g++) {
+    int lv = group_level.empty() ? 0 : group_level[g];
+    for (int e = gstart[g]; e < gstart[g + 1]; e += 64) {
+      GBlock b;
+      b.e0 = e;
+      b.nt = std::min(64, gstart[g + 1] - e);
+      b.seq0 = groups[g].seq0;
+      b.K = groups[g].K;
+      if (blk_first[lv] < 0) blk_first[lv] = (int)blocks.size();
+      blk_count[lv]++;
+      blocks.push_back(b);
+    }
+  }
+}
+
+int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* layer_in, const double* q,
+              double* phi, hipStream_t s) {
+  if (!P || n64 < 0 || n64 >= (int64_t)1 << 31) return LFMM_EINVAL;
+  if (n64 > 0 && (!xyz || !q || !phi)) return LFMM_EINVAL;
+  int n = (int)n64;
+  lfmm_report& rep = P->rep;
+  memset(&rep, 0, sizeof(rep));
+  if (n == 0) return LFMM_OK;
+  const Stack& st = P->st;
+  const int L = st.L, NL = L + 1, p = P->p, NC = P->NC, NCK = P->NCK, NKS = P->NKS, opsz = P->opsz;
+  const double* x = xyz;
+  const double* y = xyz + n;
+  const double* z = xyz + 2 * (size_t)n;
+  bool prof = P->profile && P->ev_ok;
+  auto mark = [&](int i) {
+    if (prof) HIPCHK(hipEventRecord(P->ev[i], s));
+  };
+  mark(0);
+  // ---------------- classification and statistics
+  int nbk = std::min(1024, (n + 255) / 256);
+  double* partial = P->dev<double>("partial", (size_t)nbk * NL * LFMM_NSTAT);
+  double* stats = P->dev<double>("stats", (size_t)NL * LFMM_NSTAT);
+  int* layer = P->dev<int>("layer", n);
+  lk_classify(n, x, y, z, layer_in, layer, st, partial, nbk, s);
+  lk_reduce_stats(nbk, NL, partial, stats, s);
+  std::vector<double> hs((size_t)NL * LFMM_NSTAT);
+  HIPCHK(hipMemcpyAsync(hs.data(), stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double bad = 0;
+  for (int l = 0; l < NL; l++) bad += hs[l * LFMM_NSTAT + 11];
+  if (bad > 0) return LFMM_EINVAL;
+  std::vector<int> cnt(NL), layer_start(NL + 1, 0);
+  for (int l = 0; l < NL; l++) {
+    const double* S = &hs[l * LFMM_NSTAT];
+    cnt[l] = (int)std::llround(S[0]);
+    layer_start[l + 1] = layer_start[l] + cnt[l];
+    if (cnt[l] > 0) {
+      if (l <= L - 1 && S[7] < P->min_gap) return LFMM_EINVAL;
+      if (l >= 1 && S[9] < P->min_gap) return LFMM_EINVAL;
+    }
+  }
+  mark(1);
+  // ---------------- trees
+  std::vector<TreeInfo> trees;
+  std::vector<int> free_tree(NL, -1);
+  double xlo = INFINITY, xhi = -INFINITY, ylo = INFINITY, yhi = -INFINITY, H = 0;
+  for (int l = 0; l < NL; l++) {
+    if (cnt[l] == 0) continue;
+    const double* S = &hs[l * LFMM_NSTAT];
+    xlo = std::min(xlo, S[1]);
+    xhi = std::max(xhi, S[2]);
+    ylo = std::min(ylo, S[3]);
+    yhi = std::max(yhi, S[4]);
+    if (l <= L - 1) H = std::max(H, S[8]);
+    if (l >= 1) H = std::max(H, S[10]);
+    TreeInfo T;
+    memset(&T, 0, sizeof(T));
+    double ext[3] = {S[2] - S[1], S[4] - S[3], S[6] - S[5]};
+    double Sd = std::max(ext[0], std::max(ext[1], ext[2]));
+    if (Sd == 0.0) Sd = 1.0;
+    T.lo[0] = 0.5 * (S[1] + S[2]) - 0.5 * Sd;
+    T.lo[1] = 0.5 * (S[3] + S[4]) - 0.5 * Sd;
+    T.lo[2] = 0.5 * (S[5] + S[6]) - 0.5 * Sd;
+    T.S = Sd;
+    T.k = st.k[l];
+    T.kind = 0;
+    T.layer = l;
+    T.dir = 0;
+    T.npts = cnt[l];
+    free_tree[l] = (int)trees.size();
+    trees.push_back(T);
+  }
+  double Sr = std::max(xhi - xlo, std::max(yhi - ylo, 2.0 * H));
+  double rlox = 0.5 * (xlo + xhi) - 0.5 * Sr, rloy = 0.5 * (ylo + yhi) - 0.5 * Sr;
+  std::vector<int> tgt_tree(2 * NL, -1), src_tree(2 * NL, -1);
+  for (int kind = 1; kind <= 2 && L >= 1; kind++)
+    for (int l = 0; l < NL; l++)
+      for (int a = 0; a < 2; a++) {
+        if (!has_dir(st, l, a) || cnt[l] == 0) continue;
+        TreeInfo T;
+        memset(&T, 0, sizeof(T));
+        T.lo[0] = rlox;
+        T.lo[1] = rloy;
+        T.lo[2] = -0.5 * Sr;
+        T.S = Sr;
+        T.k = st.k[l];
+        T.kind = kind;
+        T.layer = l;
+        T.dir = a;
+        T.npts = cnt[l];
+        (kind == 1 ? tgt_tree : src_tree)[2 * l + a] = (int)trees.size();
+        trees.push_back(T);
+      }
+  int ntrees = (int)trees.size();
+  int ntp = 0;
+  for (auto& T : trees) {
+    T.pt_off = ntp;
+    T.depth = 8;
+    ntp += T.npts;
+  }
+  rep.n_trees = ntrees;
+  // ---------------- layer sort
+  int* iota = P->dev<int>("iota", n);
+  int* perm = P->dev<int>("perm", n);
+  int* lsorted = P->dev<int>("lsorted", n);
+  int* inv_perm = P->dev<int>("inv_perm", n);
+  lk_iota(n, iota, s);
+  int lbits = 1;
+  while ((1 << lbits) <= L) lbits++;
+  size_t tb1 = 0;
+  HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb1, layer, lsorted, iota, perm, n, 0, lbits, s));
+  void* tmp = P->dev<char>("cubtmp1", tb1);
+  HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb1, layer, lsorted, iota, perm, n, 0, lbits, s));
+  lk_inverse_perm(n, perm, inv_perm, s);
+  int* d_lstart = P->upload("layer_start", layer_start, s);
+  TreeInfo* d_trees = P->upload("trees", trees, s);
+  // ---------------- keys and sort
+  unsigned* keys = P->dev<unsigned>("keys", ntp);
+  unsigned* skeys = P->dev<unsigned>("skeys", ntp);
+  int* vals = P->dev<int>("vals", ntp);
+  int* sg = P->dev<int>("sg", ntp);
+  lk_tree_points(ntp, ntrees, d_trees, perm, d_lstart, x, y, z, st, keys, vals, s);
+  int tbits = 1;
+  while ((1 << tbits) < ntrees) tbits++;
+  size_t tb2 = 0;
+  HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, keys, skeys, vals, sg, ntp, 0, 24 + tbits, s));
+  tmp = P->dev<char>("cubtmp2", tb2);
+  HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb2, keys, skeys, vals, sg, ntp, 0, 24 + tbits, s));
+  int* occ = P->dev<int>("occ", ntrees * 9);
+  int* slab = P->dev<int>("slab", ntrees * 18);
+  HIPCHK(hipMemsetAsync(occ, 0, sizeof(int) * ntrees * 9, s));
+  HIPCHK(hipMemsetAsync(slab, 0, sizeof(int) * ntrees * 18, s));
+  lk_occupancy(ntp, skeys, d_trees, occ, slab, s);
+  std::vector<int> hocc(ntrees * 9), hslab(ntrees * 18);
+  HIPCHK(hipMemcpyAsync(hocc.data(), occ, sizeof(int) * ntrees * 9, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hslab.data(), slab, sizeof(int) * ntrees * 18, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  // depth rule: smallest depth whose fullest cell holds <= leaf_max points
+  int Dr = -1;
+  for (int t = 0; t < ntrees; t++) {
+    int dmin = trees[t].kind == 0 ? 0 : 1;
+    int D = P->max_depth;
+    for (int l = dmin; l <= P->max_depth; l++)
+      if (hocc[t * 9 + l] <= P->leaf_max) {
+        D = l;
+        break;
+      }
+    trees[t].depth = D;
+    if (trees[t].kind != 0) Dr = std::max(Dr, D);
+  }
+  for (int t = 0; t < ntrees; t++)
+    if (trees[t].kind != 0) trees[t].depth = Dr;
+  int Dmax = 0;
+  for (auto& T : trees) Dmax = std::max(Dmax, T.depth);
+  for (int l = 0; l < 17; l++) rep.free_depth[l] = -1;
+  for (int l = 0; l < NL && l < 17; l++)
+    if (free_tree[l] >= 0) rep.free_depth[l] = trees[free_tree[l]].depth;
+  rep.reaction_depth = Dr;
+  d_trees = P->upload("trees", trees, s);
+  // ---------------- boxes
+  int nlev = Dmax + 1;
+  int* flags_all = P->dev<int>("flags_all", (size_t)nlev * ntp);
+  int* scan_all = P->dev<int>("scan_all", (size_t)nlev * ntp);
+  int* tb = P->dev<int>("tb", ntrees * 18);
+  HIPCHK(hipMemsetAsync(tb, 0, sizeof(int) * ntrees * 18, s));
+  size_t tb3 = 0;
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb3, flags_all, scan_all, ntp, s));
+  tmp = P->dev<char>("cubtmp3", tb3);
+  for (int l = 0; l < nlev; l++) {
+    int* fl = flags_all + (size_t)l * ntp;
+    int* sc = scan_all + (size_t)l * ntp;
+    lk_box_flags(ntp, l, skeys, d_trees, fl, s);
+    HIPCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb3, fl, sc, ntp, s));
+    lk_tree_box_range(ntrees, l, ntp, d_trees, fl, sc, tb, s);
+  }
+  std::vector<int> htb(ntrees * 18);
+  HIPCHK(hipMemcpyAsync(htb.data(), tb, sizeof(int) * ntrees * 18, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int> lvl_count(9, 0), lvl_off(10, 0);
+  for (int l = 0; l < nlev; l++)
+    for (int t = 0; t < ntrees; t++) lvl_count[l] += htb[(t * 9 + l) * 2 + 1];
+  for (int l = 0; l < 9; l++) lvl_off[l + 1] = lvl_off[l] + lvl_count[l];
+  int NR = lvl_off[nlev];
+  rep.n_boxes = NR;
+  auto first_row = [&](int t, int l) { return lvl_off[l] + htb[(t * 9 + l) * 2]; };
+  auto nbox = [&](int t, int l) { return htb[(t * 9 + l) * 2 + 1]; };
+  int* box_start = P->dev<int>("box_start", NR + 1);
+  int* box_code = P->dev<int>("box_code", NR + 1);
+  int* box_tree = P->dev<int>("box_tree", NR + 1);
+  int* box_level = P->dev<int>("box_level", NR + 1);
+  int* box_cnt = P->dev<int>("box_cnt", NR + 1);
+  for (int l = 0; l < nlev; l++)
+    lk_box_fill(ntp, l, skeys, flags_all + (size_t)l * ntp, scan_all + (size_t)l * ntp, lvl_off[l], d_trees,
+                box_start, box_code, box_tree, box_level, box_cnt, s);
+  int* d_lvl_off = P->upload("lvl_off", lvl_off, s);
+  int* leafrow = P->dev<int>("leafrow", ntp);
+  lk_point_leaf(ntp, skeys, d_trees, flags_all, scan_all, d_lvl_off, leafrow, s);
+  // dense cell -> row grids
+  std::vector<long long> grid_off(ntrees * 9, -1);
+  long long gtot = 0;
+  for (int t = 0; t < ntrees; t++)
+    for (int l = 0; l <= trees[t].depth; l++) {
+      grid_off[t * 9 + l] = gtot;
+      gtot += 1LL << (3 * l);
+    }
+  int* grid = P->dev<int>("grid", (size_t)gtot);
+  lk_fill_int(grid, (size_t)gtot, -1, s);
+  long long* d_grid_off = P->upload("grid_off", grid_off, s);
+  for (int l = 0; l < nlev; l++) lk_grid_fill(lvl_count[l], lvl_off[l], l, box_code, box_tree, d_grid_off, 9, grid, s);
+  // particle data in sorted order, frame coordinates
+  double* px = P->dev<double>("px", ntp);
+  double* py = P->dev<double>("py", ntp);
+  double* pz = P->dev<double>("pz", ntp);
+  double* pq = P->dev<double>("pq", 2 * (size_t)ntp);
+  lk_gather(ntp, sg, d_trees, ntrees, perm, d_lstart, x, y, z, q, st, px, py, pz, pq, s);
+  mark(2);
+  // ---------------- operators
+  // op 0 is the zero operator
+  int nops = 1;
+  std::vector<OpDesc> fops;
+  std::vector<int> m2l_op((size_t)ntrees * 9 * 343, 0), m2m_op((size_t)ntrees * 9 * 8, 0),
+      l2l_op((size_t)ntrees * 9 * 8, 0);
+  for (int t = 0; t < ntrees; t++) {
+    const TreeInfo& T = trees[t];
+    int D = T.depth;
+    for (int l = 2; l <= D; l++) {
+      double h = T.S / (double)(1 << l);
+      if (T.kind == 0)
+        for (int o = 0; o < 343; o++) {
+          int dx = o / 49 - 3, dy = (o / 7) % 7 - 3, dz = o % 7 - 3;
+          if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+          OpDesc od{dx * h, dy * h, dz * h, T.k, 1, nops};
+          m2l_op[((size_t)t * 9 + l) * 343 + o] = nops++;
+          fops.push_back(od);
+        }
+      if (l >= 3)
+        for (int ch = 0; ch < 8; ch++) {
+          double cx = (((ch >> 2) & 1) - 0.5) * h, cy = (((ch >> 1) & 1) - 0.5) * h, cz = ((ch & 1) - 0.5) * h;
+          if (T.kind == 0 || T.kind == 2) {  // M2M: b = parent - child
+            OpDesc od{-cx, -cy, -cz, T.k, 0, nops};
+            m2m_op[((size_t)t * 9 + l) * 8 + ch] = nops++;
+            fops.push_back(od);
+          }
+          if (T.kind == 0 || T.kind == 1) {  // L2L: b = child - parent
+            OpDesc od{cx, cy, cz, T.k, 0, nops};
+            l2l_op[((size_t)t * 9 + l) * 8 + ch] = nops++;
+            fops.push_back(od);
+          }
+        }
+    }
+  }
+  rep.n_ops_free = (int64_t)fops.size();
+  // reaction M2L classes and operators
+  std::vector<ClassDesc> classes;
+  std::vector<ROpDesc> rops;
+  // rop index: [tt][ts][l][j][i][dx+3][dy+3]
+  std::map<long long, int> rop_id;
+  auto rkey = [&](int tt, int ts, int l, int j, int i, int dx, int dy) {
+    return ((((((long long)tt * 128 + ts) * 9 + l) * 2 + j) * 2 + i) * 7 + (dx + 3)) * 7 + (dy + 3);
+  };
+  const int r2vals[10] = {0, 1, 2, 4, 5, 8, 9, 10, 13, 18};
+  int64_t nodes_total = 0;
+  if (L >= 1)
+    for (int l = 0; l < NL; l++)
+      for (int a = 0; a < 2; a++) {
+        int tt = tgt_tree[2 * l + a];
+        if (tt < 0) continue;
+        for (int lp = 0; lp < NL; lp++)
+          for (int b = 0; b < 2; b++) {
+            int ts = src_tree[2 * lp + b];
+            if (ts < 0) continue;
+            for (int lv = 2; lv <= Dr; lv++) {
+              double h = Sr / (double)(1 << lv);
+              for (int j = 0; j < 2; j++) {
+                if (!hslab[(tt * 9 + lv) * 2 + j]) continue;
+                for (int i = 0; i < 2; i++) {
+                  if (!hslab[(ts * 9 + lv) * 2 + i]) continue;
+                  int cls_of_r2[19];
+                  for (int r = 0; r < 19; r++) cls_of_r2[r] = -1;
+                  for (int ri = 0; ri < 10; ri++) {
+                    int r2 = r2vals[ri];
+                    if (i == 0 && j == 0 && r2 <= 2) continue;
+                    ClassDesc C;
+                    memset(&C, 0, sizeof(C));
+                    C.zt = (j + 0.5) * h;
+                    C.zs = (i + 0.5) * h;
+                    C.rho = h * std::sqrt((double)r2);
+                    C.rule = P->make_rule(C.zt + C.zs, C.rho, 2 * p + 1);
+                    C.lt = l;
+                    C.ls = lp;
+                    C.a = a;
+                    C.b = b;
+                    C.out = (int)classes.size();
+                    nodes_total += rule_nodes(C.rule);
+                    cls_of_r2[r2] = C.out;
+                    classes.push_back(C);
+                  }
+                  for (int dx = -3; dx <= 3; dx++)
+                    for (int dy = -3; dy <= 3; dy++) {
+                      if (i == 0 && j == 0 && std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                      ROpDesc R;
+                      R.dx = dx * h;
+                      R.dy = dy * h;
+                      R.kt = st.k[l];
+                      R.cls = cls_of_r2[dx * dx + dy * dy];
+                      R.op = nops++;
+                      rop_id[rkey(tt, ts, lv, j, i, dx, dy)] = R.op;
+                      rops.push_back(R);
+                    }
+                }
+              }
+            }
+          }
+      }
+  rep.n_react_classes = (int64_t)classes.size();
+  rep.n_react_nodes = nodes_total;
+  rep.n_ops_react = (int64_t)rops.size();
+  double* ops = P->dev<double>("ops", (size_t)nops * opsz);
+  lk_zero(ops, opsz, s);
+  OpDesc* d_fops = P->upload("fops", fops, s);
+  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, s);
+  mark(3);
+  if (!classes.empty()) {
+    ClassDesc* d_cls = P->upload("classes", classes, s);
+    double* Iall = P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
+    lk_react_I((int)classes.size(), d_cls, st, p, P->d_ent, P->nent, Iall, NC, s);
+    ROpDesc* d_rops = P->upload("rops", rops, s);
+    lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, s);
+  }
+  mark(4);
+  // ---------------- GEMM jobs
+  // group tables (host): M2M groups per (tree, parent level), level-major descending;
+  // L2L groups per (tree, level, class) level-major ascending; M2L groups per (tree, level, class)
+  std::vector<int> gb_m2m(ntrees * 9, -1), gb_l2l(ntrees * 9, -1), gb_m2l(ntrees * 9, -1);
+  std::vector<Group> g_m2m, g_l2l, g_m2l;
+  std::vector<int> lv_m2m, lv_l2l;
+  std::vector<int> seq_m2m, seq_l2l, seq_m2l;
+  std::vector<Tmpl> tmpl_m2l;
+  for (int lp = Dmax - 1; lp >= 2; lp--)
+    for (int t = 0; t < ntrees; t++) {
+      const TreeInfo& T = trees[t];
+      if (!(T.kind == 0 || T.kind == 2) || lp + 1 > T.depth) continue;
+      gb_m2m[t * 9 + lp] = (int)g_m2m.size();
+      Group G{(int)seq_m2m.size(), 8};
+      for (int ch = 0; ch < 8; ch++) seq_m2m.push_back(m2m_op[((size_t)t * 9 + lp + 1) * 8 + ch]);
+      g_m2m.push_back(G);
+      lv_m2m.push_back(lp);
+    }
+  for (int l = 3; l <= Dmax; l++)
+    for (int t = 0; t < ntrees; t++) {
+      const TreeInfo& T = trees[t];
+      if (!(T.kind == 0 || T.kind == 1) || l > T.depth) continue;
+      gb_l2l[t * 9 + l] = (int)g_l2l.size();
+      for (int c = 0; c < 8; c++) {
+        Group G{(int)seq_l2l.size(), 1};
+        seq_l2l.push_back(l2l_op[((size_t)t * 9 + l) * 8 + c]);
+        g_l2l.push_back(G);
+        lv_l2l.push_back(l);
+      }
+    }
+  int kmax_m2l = 1;
+  for (int t = 0; t < ntrees; t++) {
+    const TreeInfo& T = trees[t];
+    if (T.kind == 2) continue;
+    for (int l = 2; l <= T.depth; l++) {
+      gb_m2l[t * 9 + l] = (int)g_m2l.size();
+      for (int c = 0; c < 8; c++) {
+        Group G{(int)seq_m2l.size(), 0};
+        if (T.kind == 0) {
+          int cx = (c >> 2) & 1, cy = (c >> 1) & 1, cz = c & 1;
+          for (int dx = -3 + cx; dx <= 2 + cx; dx++)
+            for (int dy = -3 + cy; dy <= 2 + cy; dy++)
+              for (int dz = -3 + cz; dz <= 2 + cz; dz++) {
+                if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                int o = (dx + 3) * 49 + (dy + 3) * 7 + (dz + 3);
+                Tmpl tm;
+                tm.op = m2l_op[((size_t)t * 9 + l) * 343 + o];
+                tm.stree = t;
+                tm.dx = (short)dx;
+                tm.dy = (short)dy;
+                tm.dz = (short)dz;
+                tm.zabs = 0;
+                tmpl_m2l.push_back(tm);
+                seq_m2l.push_back(tm.op);
+                G.K++;
+              }
+        } else {
+          int j = c >> 2, cx = (c >> 1) & 1, cy = c & 1;
+          if (hslab[(t * 9 + l) * 2 + j])
+            for (int lp = 0; lp < NL; lp++)
+              for (int b = 0; b < 2; b++) {
+                int ts = src_tree[2 * lp + b];
+                if (ts < 0) continue;
+                for (int i = 0; i < 2; i++) {
+                  if (!hslab[(ts * 9 + l) * 2 + i]) continue;
+                  for (int dx = -3 + cx; dx <= 2 + cx; dx++)
+                    for (int dy = -3 + cy; dy <= 2 + cy; dy++) {
+                      if (i == 0 && j == 0 && std::abs(dx) <= 1 && std::abs(dy) <= 1) continue;
+                      Tmpl tm;
+                      tm.op = rop_id[rkey(t, ts, l, j, i, dx, dy)];
+                      tm.stree = ts;
+                      tm.dx = (short)dx;
+                      tm.dy = (short)dy;
+                      tm.dz = (short)((1 << (l - 1)) - 1 - i);
+                      tm.zabs = 1;
+                      tmpl_m2l.push_back(tm);
+                      seq_m2l.push_back(tm.op);
+                      G.K++;
+                    }
+                }
+              }
+        }
+        kmax_m2l = std::max(kmax_m2l, G.K);
+        g_m2l.push_back(G);
+      }
+    }
+  }
+  // device: group ids for every box row, sort, count
+  struct JobDev {
+    int* gid;
+    int* rowid;
+    int* sgid;
+    int* srowid;
+    int* cnt;
+  };
+  auto job_prep = [&](const char* tag, int mode, const std::vector<int>& gbase, int ngroups, JobDev& J) {
+    std::string t(tag);
+    J.gid = P->dev<int>((t + "_gid").c_str(), NR + 1);
+    J.rowid = P->dev<int>((t + "_row").c_str(), NR + 1);
+    J.sgid = P->dev<int>((t + "_sgid").c_str(), NR + 1);
+    J.srowid = P->dev<int>((t + "_srow").c_str(), NR + 1);
+    J.cnt = P->dev<int>((t + "_cnt").c_str(), ngroups + 1);
+    int* d_gb = P->upload((t + "_gb").c_str(), gbase, s);
+    lk_group_ids(NR, 0, mode, box_code, box_tree, box_level, d_trees, d_gb, 9, J.gid, J.rowid, s);
+    size_t tbb = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, s));
+    void* tt = P->dev<char>((t + "_tmp").c_str(), tbb);
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tt, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, s));
+    // histogram of valid group ids
+    size_t tbh = 0;
+    HIPCHK(hipcub::DeviceHistogram::HistogramEven(nullptr, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, s));
+    void* th = P->dev<char>((t + "_htmp").c_str(), tbh);
+    HIPCHK(hipcub::DeviceHistogram::HistogramEven(th, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, s));
+  };
+  JobDev J_m2m{}, J_l2l{}, J_m2l{};
+  int ng_m2m = (int)g_m2m.size(), ng_l2l = (int)g_l2l.size(), ng_m2l = (int)g_m2l.size();
+  if (ng_m2m) job_prep("m2m", 0, gb_m2m, ng_m2m, J_m2m);
+  if (ng_l2l) job_prep("l2l", 1, gb_l2l, ng_l2l, J_l2l);
+  if (ng_m2l) job_prep("m2l", 2, gb_m2l, ng_m2l, J_m2l);
+  std::vector<int> c_m2m(ng_m2m + 1), c_l2l(ng_l2l + 1), c_m2l(ng_m2l + 1);
+  if (ng_m2m) HIPCHK(hipMemcpyAsync(c_m2m.data(), J_m2m.cnt, sizeof(int) * ng_m2m, hipMemcpyDeviceToHost, s));
+  if (ng_l2l) HIPCHK(hipMemcpyAsync(c_l2l.data(), J_l2l.cnt, sizeof(int) * ng_l2l, hipMemcpyDeviceToHost, s));
+  if (ng_m2l) HIPCHK(hipMemcpyAsync(c_m2l.data(), J_m2l.cnt, sizeof(int) * ng_m2l, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c_m2m.resize(ng_m2m);
+  c_l2l.resize(ng_l2l);
+  c_m2l.resize(ng_m2l);
+  std::vector<GBlock> b_m2m, b_l2l, b_m2l;
+  std::vector<int> gs_m2m, gs_l2l, gs_m2l, bf_m2m, bc_m2m, bf_l2l, bc_l2l, bf_m2l, bc_m2l;
+  build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9);
+  build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9);
+  build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1);
+  int ne_m2m = ng_m2m ? gs_m2m[ng_m2m] : 0, ne_l2l = ng_l2l ? gs_l2l[ng_l2l] : 0,
+      ne_m2l = ng_m2l ? gs_m2l[ng_m2l] : 0;
+  int64_t m2l_pairs = 0;
+  for (int g = 0; g < ng_m2l; g++) m2l_pairs += (int64_t)c_m2l[g] * g_m2l[g].K;
+  rep.m2l_pairs = m2l_pairs;
+  // source rows
+  int* sr_m2m = P->dev<int>("sr_m2m", (size_t)ne_m2m * 8 + 1);
+  int* sr_l2l = P->dev<int>("sr_l2l", (size_t)ne_l2l + 1);
+  int* sr_m2l = P->dev<int>("sr_m2l", (size_t)ne_m2l * kmax_m2l + 1);
+  if (ne_m2m) lk_src_m2m(ne_m2m, J_m2m.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_m2m, s);
+  if (ne_l2l) lk_src_l2l(ne_l2l, J_l2l.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_l2l, s);
+  std::vector<int> gseq0(ng_m2l), gK(ng_m2l);
+  for (int g = 0; g < ng_m2l; g++) {
+    gseq0[g] = g_m2l[g].seq0;
+    gK[g] = g_m2l[g].K;
+  }
+  int* d_gseq0 = P->upload("m2l_gseq0", gseq0, s);
+  int* d_gK = P->upload("m2l_gK", gK, s);
+  Tmpl* d_tmpl = P->upload("m2l_tmpl", tmpl_m2l, s);
+  if (ne_m2l)
+    lk_src_m2l(ne_m2l, J_m2l.srowid, J_m2l.sgid, d_gseq0, d_gK, d_tmpl, kmax_m2l, box_code, box_level, d_lvl_off,
+               d_grid_off, 9, grid, nullptr, sr_m2l, s);
+  GBlock* d_bm2m = P->upload("b_m2m", b_m2m, s);
+  GBlock* d_bl2l = P->upload("b_l2l", b_l2l, s);
+  GBlock* d_bm2l = P->upload("b_m2l", b_m2l, s);
+  int* d_sq_m2m = P->upload("sq_m2m", seq_m2m, s);
+  int* d_sq_l2l = P->upload("sq_l2l", seq_l2l, s);
+  int* d_sq_m2l = P->upload("sq_m2l", seq_m2l, s);
+  mark(5);
+  // ---------------- upward pass
+  double* M = P->dev<double>("M", (size_t)NR * NCK * 2);
+  double* Lx = P->dev<double>("L", (size_t)NR * NCK * 2);
+  lk_zero(M, (size_t)NR * NCK * 2, s);
+  lk_zero(Lx, (size_t)NR * NCK * 2, s);
+  // leaf segments of trees with a far field
+  std::vector<int> seg_row0, seg_prefix;
+  int ptot = 0;
+  for (int t = 0; t < ntrees; t++) {
+    const TreeInfo& T = trees[t];
+    if ((T.kind == 0 || T.kind == 2) && T.depth >= 2) {
+      seg_row0.push_back(first_row(t, T.depth));
+      seg_prefix.push_back(ptot);
+      ptot += nbox(t, T.depth);
+    }
+  }
+  if (ptot) {
+    int* d_r0 = P->upload("p2m_r0", seg_row0, s);
+    int* d_pf = P->upload("p2m_pf", seg_prefix, s);
+    lk_p2m((int)seg_row0.size(), d_r0, d_pf, ptot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, px, py,
+           pz, pq, p, NCK, M, s);
+  }
+  mark(6);
+  for (int lp = Dmax - 1; lp >= 2; lp--)
+    if (bc_m2m[lp] > 0)
+      lk_gemm(P->NRT, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M, NCK,
+              NC, s);
+  mark(7);
+  // ---------------- M2L (every level, free and reaction)
+  if (!b_m2l.empty())
+    lk_gemm(P->NRT, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M, Lx, NCK,
+            NC, s);
+  mark(8);
+  // ---------------- downward pass
+  for (int l = 3; l <= Dmax; l++)
+    if (bc_l2l[l] > 0)
+      lk_gemm(P->NRT, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx, NCK,
+              NC, s);
+  mark(9);
+  double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
+  lk_zero(phi_tp, 2 * (size_t)ntp, s);
+  {
+    std::vector<int> s0, pf;
+    int tot = 0;
+    for (int t = 0; t < ntrees; t++) {
+      const TreeInfo& T = trees[t];
+      if ((T.kind == 0 || T.kind == 1) && T.depth >= 2) {
+        s0.push_back(T.pt_off);
+        pf.push_back(tot);
+        tot += T.npts;
+      }
+    }
+    if (tot) {
+      int* d_s0 = P->upload("l2p_s0", s0, s);
+      int* d_pf = P->upload("l2p_pf", pf, s);
+      lk_l2p((int)s0.size(), d_s0, d_pf, tot, leafrow, box_code, box_tree, box_level, d_trees, px, py, pz, sg, p, NCK,
+             Lx, phi_tp, s);
+    }
+  }
+  mark(10);
+  // ---------------- free-space near field
+  {
+    std::vector<int> r0, pf;
+    int tot = 0;
+    int64_t pairs = 0;
+    for (int t = 0; t < ntrees; t++) {
+      const TreeInfo& T = trees[t];
+      if (T.kind != 0) continue;
+      r0.push_back(first_row(t, T.depth));
+      pf.push_back(tot);
+      tot += nbox(t, T.depth);
+      pairs += (int64_t)T.npts * std::min<int64_t>(T.npts, 27LL * hocc[t * 9 + T.depth]);
+    }
+    rep.p2p_pairs_bound = pairs;
+    if (tot) {
+      int* d_r0 = P->upload("p2p_r0", r0, s);
+      int* d_pf = P->upload("p2p_pf", pf, s);
+      lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
+                  d_lvl_off, d_grid_off, 9, grid, px, py, pz, pq, sg, phi_tp, s);
+    }
+  }
+  mark(11);
+  // ---------------- reaction near field (adjacent leaves across the interface)
+  if (L >= 1 && Dr >= 1) {
+    for (int l = 0; l < NL; l++)
+      for (int a = 0; a < 2; a++) {
+        int tt = tgt_tree[2 * l + a];
+        if (tt < 0 || !hslab[(tt * 9 + Dr) * 2 + 0]) continue;
+        std::vector<NFComp> comps;
+        std::vector<Rule> rules;
+        std::vector<int> lts, lss, as, bs;
+        int node_tot = 0;
+        double ht_min = hs[l * LFMM_NSTAT + (a == 0 ? 7 : 9)];
+        for (int lp = 0; lp < NL; lp++)
+          for (int b = 0; b < 2; b++) {
+            int ts = src_tree[2 * lp + b];
+            if (ts < 0 || !hslab[(ts * 9 + Dr) * 2 + 0]) continue;
+            double hs_min = hs[lp * LFMM_NSTAT + (b == 0 ? 7 : 9)];
+            double hD = Sr / (double)(1 << Dr);
+            Rule r = P->make_rule(ht_min + hs_min, 2.0 * std::sqrt(2.0) * hD, 0);
+            NFComp C;
+            C.node0 = node_tot;
+            C.nnodes = rule_nodes(r);
+            C.stree = ts;
+            C.pad = 0;
+            node_tot += C.nnodes;
+            comps.push_back(C);
+            rules.push_back(r);
+            lts.push_back(l);
+            lss.push_back(lp);
+            as.push_back(a);
+            bs.push_back(b);
+          }
+        if (comps.empty()) continue;
+        std::string tag = "nf" + std::to_string(tt);
+        double* nkr = P->dev<double>((tag + "kr").c_str(), 2 * (size_t)node_tot);
+        double* nfac = P->dev<double>((tag + "fac").c_str(), 2 * (size_t)node_tot);
+        double* nkzt = P->dev<double>((tag + "kzt").c_str(), 2 * (size_t)node_tot);
+        double* nkzs = P->dev<double>((tag + "kzs").c_str(), 2 * (size_t)node_tot);
+        for (size_t c = 0; c < comps.size(); c++)
+          lk_nf_nodes(comps[c].nnodes, rules[c], st, lts[c], lss[c], as[c], bs[c], nkr + 2 * comps[c].node0,
+                      nfac + 2 * comps[c].node0, nkzt + 2 * comps[c].node0, nkzs + 2 * comps[c].node0, s);
+        NFComp* d_comps = P->upload((tag + "comps").c_str(), comps, s);
+        lk_nf_react(nbox(tt, Dr), first_row(tt, Dr), tt, (int)comps.size(), d_comps, box_start, box_cnt, box_code,
+                    d_trees, d_grid_off, grid, px, py, pz, pq, sg, nkr, nfac, nkzt, nkzs, phi_tp, s);
+        rep.nf_react_pairs += 1;
+      }
+  }
+  mark(12);
+  // ---------------- component sum
+  int max_tt = 3;
+  std::vector<int> tgt_list(NL * max_tt, -1);
+  for (int l = 0; l < NL; l++) {
+    tgt_list[l * max_tt + 0] = free_tree[l];
+    tgt_list[l * max_tt + 1] = tgt_tree[2 * l + 0];
+    tgt_list[l * max_tt + 2] = tgt_tree[2 * l + 1];
+  }
+  int* d_tl = P->upload("tgt_list", tgt_list, s);
+  lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, s);
+  mark(13);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  if (prof) {
+    // stage i spans events i+1 .. i+2 of the marks above (classify = 0..1)
+    int map_ev[ST_COUNT][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7},
+                               {7, 8}, {8, 9}, {9, 10}, {10, 11}, {11, 12}, {12, 13}};
+    for (int i = 0; i < ST_COUNT; i++) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, P->ev[map_ev[i][0]], P->ev[map_ev[i][1]]) == hipSuccess) rep.stage_ms[i] = ms;
+    }
+  }
+  return LFMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lfmm_plan(int L, const double* d, const double* k, int p, int leaf_max, const lfmm_options* opt,
+              lfmm_plan_t** out) {
+  return plan_impl(L, d, k, p, leaf_max, opt, out);
+}
+
+int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q,
+                     double* phi, void* stream) {
+  try {
+    return eval_impl(plan, n, xyz, layer, q, phi, (hipStream_t)stream);
+  } catch (Fail& f) {
+    return f.code;
+  }
+}
+
+int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi) {
+  if (!plan || n < 0) return LFMM_EINVAL;
+  if (n == 0) return LFMM_OK;
+  if (!xyz || !q || !phi) return LFMM_EINVAL;
+  try {
+    double* dx = plan->dev<double>("h_xyz", 3 * (size_t)n);
+    double* dq = plan->dev<double>("h_q", 2 * (size_t)n);
+    double* dp = plan->dev<double>("h_phi", 2 * (size_t)n);
+    int* dl = nullptr;
+    HIPCHK(hipMemcpy(dx, xyz, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dq, q, sizeof(double) * 2 * n, hipMemcpyHostToDevice));
+    if (layer) {
+      dl = plan->dev<int>("h_layer", n);
+      HIPCHK(hipMemcpy(dl, layer, sizeof(int) * n, hipMemcpyHostToDevice));
+    }
+    int rc = eval_impl(plan, n, dx, dl, dq, dp, nullptr);
+    if (rc != LFMM_OK) return rc;
+    HIPCHK(hipMemcpy(phi, dp, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
+    return LFMM_OK;
+  } catch (Fail& f) {
+    return f.code;
+  }
+}
+
+int lfmm_last_report(const lfmm_plan_t* plan, lfmm_report* rep) {
+  if (!plan || !rep) return LFMM_EINVAL;
+  *rep = plan->rep;
+  return LFMM_OK;
+}
+
+const char* lfmm_stage_name(int i) { return (i >= 0 && i < ST_COUNT) ? kStageNames[i] : nullptr; }
+
+void lfmm_destroy(lfmm_plan_t* plan) {
+  if (!plan) return;
+  for (auto& kv : plan->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  if (plan->d_gaunt) (void)hipFree(plan->d_gaunt);
+  if (plan->d_ent) (void)hipFree(plan->d_ent);
+  if (plan->ev_ok)
+    for (int i = 0; i <= ST_COUNT; i++) (void)hipEventDestroy(plan->ev[i]);
+  delete plan;
+}
+
+const char* lfmm_status_string(int status) {
+  switch (status) {
+    case LFMM_OK: return "ok";
+    case LFMM_EINVAL: return "invalid argument";
+    case LFMM_ENOMEM: return "out of memory";
+    case LFMM_EHIP: return "HIP runtime error";
+    case LFMM_ENOTSUP: return "not supported";
+    default: return "unknown status";
+  }
+}
+
+static void unpack_op(const std::vector<double>& pk, int NC, int NKS, double* out) {
+  for (int r = 0; r < NC; r++)
+    for (int c = 0; c < NC; c++) {
+      size_t pp = ((size_t)((r >> 4) * NKS + (c >> 2)) << 7) + (size_t)((r & 15) | ((c & 3) << 4));
+      out[2 * ((size_t)r * NC + c)] = pk[pp];
+      out[2 * ((size_t)r * NC + c) + 1] = pk[pp + 64];
+    }
+}
+
+int lfmm_translation(lfmm_plan_t* plan, int kind, double kw, const double* b, double* out) {
+  if (!plan || !b || !out || (kind != 0 && kind != 1) || !(kw > 0)) return LFMM_EINVAL;
+  if (kind == 1 && b[0] == 0 && b[1] == 0 && b[2] == 0) return LFMM_EINVAL;
+  try {
+    std::vector<OpDesc> d(1);
+    d[0] = OpDesc{b[0], b[1], b[2], kw, kind, 0};
+    OpDesc* dd = plan->upload("dbg_op", d, nullptr);
+    double* ops = plan->dev<double>("dbg_ops", plan->opsz);
+    lk_transop(1, dd, ops, plan->opsz, plan->p, plan->NC, plan->NKS, plan->d_gaunt, nullptr);
+    std::vector<double> pk(plan->opsz);
+    HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
+    unpack_op(pk, plan->NC, plan->NKS, out);
+  } catch (Fail& f) {
+    return f.code;
+  }
+  return LFMM_OK;
+}
+
+int lfmm_reaction_operator(lfmm_plan_t* plan, int l, int a, int lp, int b, double dx, double dy, double zt, double zs,
+                           double* out) {
+  if (!plan || !out) return LFMM_EINVAL;
+  const Stack& st = plan->st;
+  if (st.L < 1 || l < 0 || l > st.L || lp < 0 || lp > st.L || (a != 0 && a != 1) || (b != 0 && b != 1))
+    return LFMM_EINVAL;
+  if (!has_dir(st, l, a) || !has_dir(st, lp, b) || !(zt > 0) || !(zs > 0)) return LFMM_EINVAL;
+  try {
+    int NC = plan->NC;
+    std::vector<ClassDesc> c(1);
+    memset(&c[0], 0, sizeof(ClassDesc));
+    c[0].zt = zt;
+    c[0].zs = zs;
+    c[0].rho = std::sqrt(dx * dx + dy * dy);
+    c[0].rule = plan->make_rule(zt + zs, c[0].rho, 2 * plan->p + 1);
+    c[0].lt = l;
+    c[0].ls = lp;
+    c[0].a = a;
+    c[0].b = b;
+    c[0].out = 0;
+    ClassDesc* dc = plan->upload("dbg_cls", c, nullptr);
+    double* I = plan->dev<double>("dbg_I", (size_t)NC * NC * 2);
+    lk_react_I(1, dc, st, plan->p, plan->d_ent, plan->nent, I, NC, nullptr);
+    std::vector<ROpDesc> r(1);
+    r[0] = ROpDesc{dx, dy, st.k[l], 0, 0};
+    ROpDesc* dr = plan->upload("dbg_rop", r, nullptr);
+    double* ops = plan->dev<double>("dbg_ops", plan->opsz);
+    lk_react_expand(1, dr, I, ops, plan->opsz, plan->p, NC, plan->NKS, nullptr);
+    std::vector<double> pk(plan->opsz);
+    HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
+    unpack_op(pk, NC, plan->NKS, out);
+  } catch (Fail& f) {
+    return f.code;
+  }
+  return LFMM_OK;
+}
+
+int lfmm_densities(lfmm_plan_t* plan, int n, const double* krho, int l, int lp, double* out) {
+  if (!plan || n < 0 || (n > 0 && (!krho || !out))) return LFMM_EINVAL;
+  if (l < 0 || l > plan->st.L || lp < 0 || lp > plan->st.L) return LFMM_EINVAL;
+  if (n == 0) return LFMM_OK;
+  try {
+    double* dk = plan->dev<double>("dbg_kr", 2 * (size_t)n);
+    double* dout = plan->dev<double>("dbg_sig", 8 * (size_t)n);
+    HIPCHK(hipMemcpy(dk, krho, sizeof(double) * 2 * n, hipMemcpyHostToDevice));
+    lk_dbg_dens(n, dk, plan->st, l, lp, dout, nullptr);
+    HIPCHK(hipMemcpy(out, dout, sizeof(double) * 8 * n, hipMemcpyDeviceToHost));
+  } catch (Fail& f) {
+    return f.code;
+  }
+  return LFMM_OK;
+}
+
+}  // extern "C"

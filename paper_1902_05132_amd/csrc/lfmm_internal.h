@@ -1,0 +1,144 @@
+// Shared declarations between the host orchestration and the kernels.
+#pragma once
+#include "lfmm_device.h"
+
+#define LFMM_NSTAT 12  // per-layer statistics gathered by the classification kernel
+
+// One octree of the evaluation: a free-space tree of one layer, a reaction
+// target tree (layer l, direction a) or a reaction polarisation-source tree
+// (layer lp, direction b).  kind: 0 free, 1 reaction target, 2 reaction source.
+struct TreeInfo {
+  double lo[3];
+  double S;
+  double k;
+  int kind;
+  int layer;
+  int dir;     // 0 up, 1 down (reaction trees)
+  int depth;
+  int npts;
+  int pt_off;  // first tree-point index
+  int pad0, pad1;
+};
+
+// Free-space translation operator request.
+struct OpDesc {
+  double bx, by, bz, k;
+  int kind;  // 0: regular (j_q), 1: singular (h_q)
+  int op;    // destination operator index
+};
+
+// One geometry class of the reaction M2L integrals.
+struct ClassDesc {
+  Rule rule;
+  double zt, zs, rho;
+  int lt, ls, a, b;  // target layer, source layer, directions
+  int out;           // index of the integral matrix
+  int pad;
+};
+
+// One reaction M2L operator: phase/prefactor applied to a class integral.
+struct ROpDesc {
+  double dx, dy;  // lateral offset target - source (in box units times h)
+  double kt;
+  int cls;        // integral matrix index
+  int op;         // destination operator index
+};
+
+// Canonical entry of the reaction integral matrix (m >= 0 half, see k_react_I).
+struct EntryDesc {
+  short ia, ib, iq, sg;
+  int row, col, mrow, mcol;
+};
+
+// Interaction template entry of a GEMM group.
+struct Tmpl {
+  int op;
+  int stree;
+  short dx, dy, dz, zabs;
+};
+
+// GEMM block: up to 64 targets of one group.
+struct GBlock {
+  int e0;     // first entry
+  int nt;     // targets in the block
+  int seq0;   // first template / op entry of the group
+  int K;      // number of operators in the group
+};
+
+// Near-field reaction pair table for one (target tree, source tree) component.
+struct NFComp {
+  int node0, nnodes;  // node range in the node tables
+  int stree;
+  int pad;
+};
+
+extern "C" {
+// kernel launch wrappers (lfmm_kernels.hip)
+void lk_set_gl(const double* x, const double* w);
+void lk_zero(double* p, size_t n, hipStream_t s);
+void lk_fill_int(int* p, size_t n, int v, hipStream_t s);
+void lk_iota(int n, int* a, hipStream_t s);
+void lk_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out, hipStream_t s);
+void lk_classify(int n, const double* x, const double* y, const double* z, const int* lin, int* lout, Stack st,
+                 double* partial, int nblocks, hipStream_t s);
+void lk_reduce_stats(int nblocks, int nl, const double* partial, double* stats, hipStream_t s);
+void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s);
+void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
+                    const double* x, const double* y, const double* z, Stack st, unsigned* keys, int* vals,
+                    hipStream_t s);
+void lk_occupancy(int ntp, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab, hipStream_t s);
+void lk_box_flags(int ntp, int level, const unsigned* skeys, const TreeInfo* trees, int* flags, hipStream_t s);
+void lk_box_fill(int ntp, int level, const unsigned* skeys, const int* flags, const int* scan, int lvl_off,
+                 const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level, int* box_cnt,
+                 hipStream_t s);
+void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all, const int* scan_all,
+                   const int* lvl_off, int* leafrow, hipStream_t s);
+void lk_tree_box_range(int ntrees, int level, int ntp, const TreeInfo* trees, const int* flags, const int* scan,
+                       int* tb, hipStream_t s);
+void lk_grid_fill(int nrows_level, int row0, int level, const int* box_code, const int* box_tree,
+                  const long long* grid_off, int nlev1, int* grid, hipStream_t s);
+void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm, const int* layer_start,
+               const double* x, const double* y, const double* z, const double* q, Stack st, double* px,
+               double* py, double* pz, double* pq, hipStream_t s);
+void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS, const double* gaunt,
+                hipStream_t s);
+void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const EntryDesc* ent, int nent, double* Iout,
+                int NC, hipStream_t s);
+void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p, int NC,
+                     int NKS, hipStream_t s);
+void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
+            const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
+            const TreeInfo* trees, const double* px, const double* py, const double* pz, const double* pq, int p,
+            int NCK, double* M, hipStream_t s);
+void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int total, const int* leafrow, const int* box_code,
+            const int* box_tree, const int* box_level, const TreeInfo* trees, const double* px, const double* py,
+            const double* pz, const int* sg, int p, int NCK, const double* Lc, double* phi_tp, hipStream_t s);
+void lk_gemm(int nrt, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
+             int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D, int NCK, int NC,
+             hipStream_t s);
+void lk_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree, const int* box_level,
+                  const TreeInfo* trees, const int* gbase, int nlev1, int* gid, int* rowid, hipStream_t s);
+void lk_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
+                const Tmpl* tmpl, int stride, const int* box_code, const int* box_level, const int* lvl_off,
+                const long long* grid_off, int nlev1, const int* grid, int* seq_out, int* srow, hipStream_t s);
+void lk_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
+                const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
+                hipStream_t s);
+void lk_src_l2l(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
+                const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
+                hipStream_t s);
+void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
+                 const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
+                 const TreeInfo* trees, const int* lvl_off, const long long* grid_off, int nlev1, const int* grid,
+                 const double* px, const double* py, const double* pz, const double* pq, const int* sg,
+                 double* phi_tp, hipStream_t s);
+void lk_nf_nodes(int nnodes, Rule rule, Stack st, int lt, int ls, int a, int b, double* nkr, double* nfac,
+                 double* nkzt, double* nkzs, hipStream_t s);
+void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps, const int* box_start,
+                 const int* box_cnt, const int* box_code, const TreeInfo* trees, const long long* grid_off,
+                 const int* grid, const double* px, const double* py, const double* pz, const double* pq,
+                 const int* sg, const double* nkr, const double* nfac, const double* nkzt, const double* nkzs,
+                 double* phi_tp, hipStream_t s);
+void lk_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
+                  int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, hipStream_t s);
+}

@@ -1,0 +1,1135 @@
+// HIP kernels of the layered-media Helmholtz FMM for gfx950 (MI355X).
+//
+// Stages (paper Section 3.4, Algorithm 1 per reaction component plus the classic
+// FMM per free-space layer): layer classification, octree construction on
+// Morton keys, operator generation (free-space translations from the addition
+// theorems of Section 2.1; reaction M2L operators from the Sommerfeld-type
+// integrals of Section 3.5 by contour quadrature), P2M, M2M / M2L / L2L as
+// batched complex GEMMs on FP64 MFMA, L2P, near-field sums.
+#include <hip/hip_runtime.h>
+
+#include "lfmm_internal.h"
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__constant__ double c_glx[LFMM_NGL];
+__constant__ double c_glw[LFMM_NGL];
+
+extern "C" void lk_set_gl(const double* x, const double* w) {
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_glx), x, sizeof(double) * LFMM_NGL);
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(double) * LFMM_NGL);
+}
+
+static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Utilities
+// ---------------------------------------------------------------------------
+__global__ void k_zero(double* p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0.0;
+}
+__global__ void k_fill_int(int* p, size_t n, int v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+extern "C" void lk_zero(double* p, size_t n, hipStream_t s) {
+  if (n == 0) return;
+  int g = (int)((n + 255) / 256);
+  if (g > 65536) g = 65536;
+  k_zero<<<g, 256, 0, s>>>(p, n);
+}
+extern "C" void lk_fill_int(int* p, size_t n, int v, hipStream_t s) {
+  if (n == 0) return;
+  int g = (int)((n + 255) / 256);
+  if (g > 65536) g = 65536;
+  k_fill_int<<<g, 256, 0, s>>>(p, n, v);
+}
+
+__device__ __forceinline__ unsigned morton3(unsigned ix, unsigned iy, unsigned iz) {
+  unsigned c = 0;
+  for (int b = 0; b < 8; b++) {
+    c |= ((ix >> b) & 1u) << (3 * b + 2);
+    c |= ((iy >> b) & 1u) << (3 * b + 1);
+    c |= ((iz >> b) & 1u) << (3 * b);
+  }
+  return c;
+}
+__device__ __forceinline__ void demorton3(unsigned c, int l, int* ix, int* iy, int* iz) {
+  unsigned x = 0, y = 0, z = 0;
+  for (int b = 0; b < l; b++) {
+    x |= ((c >> (3 * b + 2)) & 1u) << b;
+    y |= ((c >> (3 * b + 1)) & 1u) << b;
+    z |= ((c >> (3 * b)) & 1u) << b;
+  }
+  *ix = (int)x;
+  *iy = (int)y;
+  *iz = (int)z;
+}
+__device__ __forceinline__ int axis_cell(double v, double lo, double S) {
+  double u = (v - lo) / S;
+  double f = floor(u * 256.0);
+  if (f < 0.0) return 0;
+  if (f > 255.0) return 255;
+  return (int)f;
+}
+__device__ __forceinline__ int half_cell(double h, double S) {
+  double u = h / S;
+  double f = floor(u * 256.0);
+  if (f < 0.0) return 0;
+  if (f > 127.0) return 127;
+  return (int)f;
+}
+__device__ __forceinline__ double layer_h(const Stack& st, int l, int dir, double z) {
+  return dir == 0 ? z - st.d[l] : st.d[l - 1] - z;
+}
+__device__ __forceinline__ int tree_of(const TreeInfo* trees, int ntrees, int g) {
+  int t = 0;
+  while (t + 1 < ntrees && g >= trees[t + 1].pt_off) t++;
+  return t;
+}
+// frame coordinates of a tree point (free: physical; reaction target: +height; source: -depth)
+__device__ __forceinline__ void frame_xyz(const TreeInfo& T, const Stack& st, double x, double y, double z,
+                                          double* fx, double* fy, double* fz) {
+  *fx = x;
+  *fy = y;
+  if (T.kind == 0) *fz = z;
+  else if (T.kind == 1) *fz = layer_h(st, T.layer, T.dir, z);
+  else *fz = -layer_h(st, T.layer, T.dir, z);
+}
+__device__ __forceinline__ void box_center(const TreeInfo& T, unsigned code, int l, double* c) {
+  int ix, iy, iz;
+  demorton3(code, l, &ix, &iy, &iz);
+  double h = T.S / (double)(1 << l);
+  c[0] = T.lo[0] + (ix + 0.5) * h;
+  c[1] = T.lo[1] + (iy + 0.5) * h;
+  c[2] = (T.kind == 0) ? T.lo[2] + (iz + 0.5) * h : (iz + 0.5) * h - 0.5 * T.S;
+}
+
+// ---------------------------------------------------------------------------
+// Layer classification and per-layer statistics
+// stats per layer: 0 count, 1/2 x min/max, 3/4 y, 5/6 z, 7/8 up-height min/max,
+// 9/10 down-height min/max, 11 invalid count
+// ---------------------------------------------------------------------------
+#define NSTAT LFMM_NSTAT
+__global__ __launch_bounds__(256) void k_classify(int n, const double* x, const double* y, const double* z,
+                                                  const int* lin, int* lout, Stack st, double* partial) {
+  __shared__ double red[256];
+  int L = st.L;
+  double v[NSTAT];
+  for (int l = 0; l <= L; l++) {
+    double cnt = 0, bad = 0;
+    double xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY, zmn = INFINITY, zmx = -INFINITY;
+    double umn = INFINITY, umx = -INFINITY, dmn = INFINITY, dmx = -INFINITY;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+      double zi = z[i];
+      int lc = 0;
+      for (int j = 0; j < L; j++) lc += (zi < st.d[j]) ? 1 : 0;
+      bool ok = isfinite(x[i]) && isfinite(y[i]) && isfinite(zi);
+      for (int j = 0; j < L; j++) ok = ok && (zi != st.d[j]);
+      if (lin && lin[i] != lc) ok = false;
+      if (l == 0) lout[i] = ok ? lc : -1;
+      if (!ok) {
+        if (l == 0) bad += 1;
+        continue;
+      }
+      if (lc != l) continue;
+      cnt += 1;
+      xmn = fmin(xmn, x[i]); xmx = fmax(xmx, x[i]);
+      ymn = fmin(ymn, y[i]); ymx = fmax(ymx, y[i]);
+      zmn = fmin(zmn, zi); zmx = fmax(zmx, zi);
+      if (l <= L - 1) { double h = zi - st.d[l]; umn = fmin(umn, h); umx = fmax(umx, h); }
+      if (l >= 1) { double h = st.d[l - 1] - zi; dmn = fmin(dmn, h); dmx = fmax(dmx, h); }
+    }
+    v[0] = cnt; v[1] = xmn; v[2] = xmx; v[3] = ymn; v[4] = ymx; v[5] = zmn; v[6] = zmx;
+    v[7] = umn; v[8] = umx; v[9] = dmn; v[10] = dmx; v[11] = bad;
+    for (int s = 0; s < NSTAT; s++) {
+      bool ismin = (s == 1 || s == 3 || s == 5 || s == 7 || s == 9);
+      bool ismax = (s == 2 || s == 4 || s == 6 || s == 8 || s == 10);
+      red[threadIdx.x] = v[s];
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+          double a = red[threadIdx.x], b = red[threadIdx.x + w];
+          red[threadIdx.x] = ismin ? fmin(a, b) : ismax ? fmax(a, b) : a + b;
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) partial[((size_t)blockIdx.x * (L + 1) + l) * NSTAT + s] = red[0];
+      __syncthreads();
+    }
+  }
+}
+__global__ void k_reduce_stats(int nblocks, int nl, const double* partial, double* stats) {
+  int idx = threadIdx.x;
+  if (idx >= nl * NSTAT) return;
+  int s = idx % NSTAT;
+  bool ismin = (s == 1 || s == 3 || s == 5 || s == 7 || s == 9);
+  bool ismax = (s == 2 || s == 4 || s == 6 || s == 8 || s == 10);
+  double acc = ismin ? INFINITY : ismax ? -INFINITY : 0.0;
+  for (int b = 0; b < nblocks; b++) {
+    double v = partial[(size_t)b * nl * NSTAT + idx];
+    acc = ismin ? fmin(acc, v) : ismax ? fmax(acc, v) : acc + v;
+  }
+  stats[idx] = acc;
+}
+extern "C" void lk_classify(int n, const double* x, const double* y, const double* z, const int* lin, int* lout,
+                            Stack st, double* partial, int nblocks, hipStream_t s) {
+  k_classify<<<nblocks, 256, 0, s>>>(n, x, y, z, lin, lout, st, partial);
+}
+extern "C" void lk_reduce_stats(int nblocks, int nl, const double* partial, double* stats, hipStream_t s) {
+  k_reduce_stats<<<1, 256, 0, s>>>(nblocks, nl, partial, stats);
+}
+
+__global__ void k_iota(int n, int* a) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) a[i] = i;
+}
+extern "C" void lk_iota(int n, int* a, hipStream_t s) {
+  if (n) k_iota<<<nblk(n, 256), 256, 0, s>>>(n, a);
+}
+
+__global__ void k_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  cd sig[2][2];
+  dev_densities(st, mk(kr[2 * i], kr[2 * i + 1]), l, lp, sig);
+  for (int a = 0; a < 2; a++)
+    for (int b = 0; b < 2; b++) {
+      out[8 * i + 2 * (2 * a + b)] = sig[a][b].x;
+      out[8 * i + 2 * (2 * a + b) + 1] = sig[a][b].y;
+    }
+}
+extern "C" void lk_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out, hipStream_t s) {
+  if (n) k_dbg_dens<<<nblk(n, 256), 256, 0, s>>>(n, kr, st, l, lp, out);
+}
+
+__global__ void k_inverse_perm(int n, const int* perm, int* inv) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) inv[perm[i]] = i;
+}
+extern "C" void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s) {
+  if (n) k_inverse_perm<<<nblk(n, 256), 256, 0, s>>>(n, perm, inv);
+}
+
+// ---------------------------------------------------------------------------
+// Tree points: keys = (tree << 24) | Morton code of the depth-8 cell
+// ---------------------------------------------------------------------------
+__global__ void k_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
+                              const double* x, const double* y, const double* z, Stack st, unsigned* keys,
+                              int* vals) {
+  int g = blockIdx.x * 256 + threadIdx.x;
+  if (g >= ntp) return;
+  int t = tree_of(trees, ntrees, g);
+  TreeInfo T = trees[t];
+  int i = perm[layer_start[T.layer] + (g - T.pt_off)];
+  double fx, fy, fz;
+  frame_xyz(T, st, x[i], y[i], z[i], &fx, &fy, &fz);
+  int ix = axis_cell(fx, T.lo[0], T.S), iy = axis_cell(fy, T.lo[1], T.S), iz;
+  if (T.kind == 0) iz = axis_cell(fz, T.lo[2], T.S);
+  else if (T.kind == 1) iz = 128 + half_cell(fz, T.S);
+  else iz = 127 - half_cell(-fz, T.S);
+  keys[g] = ((unsigned)t << 24) | morton3(ix, iy, iz);
+  vals[g] = g;
+}
+extern "C" void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
+                               const double* x, const double* y, const double* z, Stack st, unsigned* keys, int* vals,
+                               hipStream_t s) {
+  if (ntp) k_tree_points<<<nblk(ntp, 256), 256, 0, s>>>(ntp, ntrees, trees, perm, layer_start, x, y, z, st, keys, vals);
+}
+
+// end (exclusive) of the run of keys sharing key >> sh, starting at s, within [s, hi)
+__device__ __forceinline__ int run_end(const unsigned* keys, int s, int hi, int sh) {
+  unsigned pre = keys[s] >> sh;
+  int lo = s + 1, h = hi;
+  while (lo < h) {
+    int mid = (lo + h) >> 1;
+    if ((keys[mid] >> sh) == pre) lo = mid + 1;
+    else h = mid;
+  }
+  return lo;
+}
+
+// occupancy[t*9 + l] = fullest cell of tree t at level l; slab flags of reaction trees
+__global__ void k_occupancy(int ntp, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp) return;
+  unsigned key = skeys[s];
+  int t = key >> 24;
+  TreeInfo T = trees[t];
+  int hi = T.pt_off + T.npts;
+  int ix, iy, iz;
+  demorton3(key & 0xFFFFFFu, 8, &ix, &iy, &iz);
+  for (int l = 0; l <= 8; l++) {
+    int sh = 3 * (8 - l);
+    if (s == T.pt_off || (skeys[s - 1] >> sh) != (key >> sh)) {
+      int e = run_end(skeys, s, hi, sh);
+      atomicMax(&occ[t * 9 + l], e - s);
+    }
+    if (l >= 1 && T.kind != 0) {
+      int izl = iz >> (8 - l), half = 1 << (l - 1);
+      int hgt = (T.kind == 1) ? izl - half : half - 1 - izl;
+      if (hgt == 0 || hgt == 1) slab[(t * 9 + l) * 2 + hgt] = 1;
+    }
+  }
+}
+extern "C" void lk_occupancy(int ntp, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab, hipStream_t s) {
+  if (ntp) k_occupancy<<<nblk(ntp, 256), 256, 0, s>>>(ntp, skeys, trees, occ, slab);
+}
+
+// run-start flags of the level-l boxes (only for trees of depth >= l)
+__global__ void k_box_flags(int ntp, int level, const unsigned* skeys, const TreeInfo* trees, int* flags) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp) return;
+  unsigned key = skeys[s];
+  int t = key >> 24;
+  int sh = 3 * (8 - level);
+  int f = 0;
+  if (level <= trees[t].depth) f = (s == 0 || (skeys[s - 1] >> sh) != (key >> sh)) ? 1 : 0;
+  flags[s] = f;
+}
+extern "C" void lk_box_flags(int ntp, int level, const unsigned* skeys, const TreeInfo* trees, int* flags, hipStream_t s) {
+  if (ntp) k_box_flags<<<nblk(ntp, 256), 256, 0, s>>>(ntp, level, skeys, trees, flags);
+}
+
+__global__ void k_box_fill(int ntp, int level, const unsigned* skeys, const int* flags, const int* scan, int lvl_off,
+                           const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
+                           int* box_cnt) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp || !flags[s]) return;
+  unsigned key = skeys[s];
+  int t = key >> 24;
+  int sh = 3 * (8 - level);
+  int R = lvl_off + scan[s];
+  box_start[R] = s;
+  box_code[R] = (int)((key & 0xFFFFFFu) >> sh);
+  box_tree[R] = t;
+  box_level[R] = level;
+  box_cnt[R] = run_end(skeys, s, trees[t].pt_off + trees[t].npts, sh) - s;
+}
+extern "C" void lk_box_fill(int ntp, int level, const unsigned* skeys, const int* flags, const int* scan, int lvl_off,
+                             const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
+                             int* box_cnt, hipStream_t s) {
+  if (ntp)
+    k_box_fill<<<nblk(ntp, 256), 256, 0, s>>>(ntp, level, skeys, flags, scan, lvl_off, trees, box_start, box_code,
+                                              box_tree, box_level, box_cnt);
+}
+
+// leaf row of every sorted point (flags/scans of all levels stored level-major)
+__global__ void k_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all,
+                             const int* scan_all, const int* lvl_off, int* leafrow) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp) return;
+  int t = skeys[s] >> 24;
+  int D = trees[t].depth;
+  size_t o = (size_t)D * ntp + s;
+  leafrow[s] = lvl_off[D] + scan_all[o] + flags_all[o] - 1;
+}
+extern "C" void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all,
+                               const int* scan_all, const int* lvl_off, int* leafrow, hipStream_t s) {
+  if (ntp) k_point_leaf<<<nblk(ntp, 256), 256, 0, s>>>(ntp, skeys, trees, flags_all, scan_all, lvl_off, leafrow);
+}
+
+// per (tree, level): first box (level-local) and number of boxes
+__global__ void k_tree_box_range(int ntrees, int level, int ntp, const TreeInfo* trees, const int* flags,
+                                 const int* scan, int* tb) {
+  int t = threadIdx.x;
+  if (t >= ntrees) return;
+  TreeInfo T = trees[t];
+  int first = 0, cnt = 0;
+  if (T.npts > 0 && level <= T.depth) {
+    first = scan[T.pt_off];
+    int last = T.pt_off + T.npts - 1;
+    cnt = scan[last] + flags[last] - first;
+  }
+  tb[(t * 9 + level) * 2] = first;
+  tb[(t * 9 + level) * 2 + 1] = cnt;
+}
+extern "C" void lk_tree_box_range(int ntrees, int level, int ntp, const TreeInfo* trees, const int* flags,
+                                  const int* scan, int* tb, hipStream_t s) {
+  k_tree_box_range<<<1, 256, 0, s>>>(ntrees, level, ntp, trees, flags, scan, tb);
+}
+
+__global__ void k_grid_fill(int nrows, int row0, int level, const int* box_code, const int* box_tree,
+                            const long long* grid_off, int* grid) {
+  int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nrows) return;
+  int R = row0 + r;
+  int t = box_tree[R];
+  long long go = grid_off[t * 9 + level];
+  if (go < 0) return;
+  grid[go + box_code[R]] = R;
+}
+extern "C" void lk_grid_fill(int nrows_level, int row0, int level, const int* box_code, const int* box_tree,
+                             const long long* grid_off, int nlev1, int* grid, hipStream_t s) {
+  (void)nlev1;
+  if (nrows_level) k_grid_fill<<<nblk(nrows_level, 256), 256, 0, s>>>(nrows_level, row0, level, box_code, box_tree, grid_off, grid);
+}
+
+__global__ void k_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm,
+                         const int* layer_start, const double* x, const double* y, const double* z, const double* q,
+                         Stack st, double* px, double* py, double* pz, double* pq) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp) return;
+  int g = sg[s];
+  int t = tree_of(trees, ntrees, g);
+  TreeInfo T = trees[t];
+  int i = perm[layer_start[T.layer] + (g - T.pt_off)];
+  double fx, fy, fz;
+  frame_xyz(T, st, x[i], y[i], z[i], &fx, &fy, &fz);
+  px[s] = fx;
+  py[s] = fy;
+  pz[s] = fz;
+  pq[2 * s] = q[2 * i];
+  pq[2 * s + 1] = q[2 * i + 1];
+}
+extern "C" void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm,
+                          const int* layer_start, const double* x, const double* y, const double* z, const double* q,
+                          Stack st, double* px, double* py, double* pz, double* pq, hipStream_t s) {
+  if (ntp)
+    k_gather<<<nblk(ntp, 256), 256, 0, s>>>(ntp, sg, trees, ntrees, perm, layer_start, x, y, z, q, st, px, py, pz, pq);
+}
+
+// ---------------------------------------------------------------------------
+// Operator layout for the MFMA GEMM: an (NRT*16) x (NKS*4) complex matrix is
+// stored as tiles of 16 rows x 4 columns; tile (rt, ks) holds 64 real parts in
+// MFMA A-operand lane order (lane = row%16 + 16*(col%4)) followed by 64
+// imaginary parts.  Padding rows/columns are zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ size_t packed_pos(int row, int col, int NKS) {
+  return ((size_t)((row >> 4) * NKS + (col >> 2)) << 7) + (size_t)((row & 15) | ((col & 3) << 4));
+}
+__device__ __forceinline__ void decode_nm(int r, int* n, int* m) {
+  int nn = (int)floor(sqrt((double)r) + 1e-9);
+  while (nn * nn > r) nn--;
+  while ((nn + 1) * (nn + 1) <= r) nn++;
+  *n = nn;
+  *m = r - nn * nn - nn;
+}
+
+// Free-space translation operators (Section 2.1 addition theorems):
+//   Op[(n,m),(nu,mu)] = 4 pi i^{n-nu} sum_q i^q z_q(k|b|) conj(Y_q^{m-mu}(b^)) G(nu,mu; q,m-mu; n)
+// G tabulated per (row, col, j), q = |n - nu| + 2 j.  One workgroup per operator.
+__global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
+                                                 const double* gaunt) {
+  __shared__ cd zq[64];
+  __shared__ cd Yq[64 * 64];
+  OpDesc D = descs[blockIdx.x];
+  int Q = 2 * p;
+  double bb = sqrt(D.bx * D.bx + D.by * D.by + D.bz * D.bz);
+  if (threadIdx.x == 0) {
+    if (D.kind == 0) {
+      double jj[64];
+      dev_sph_j(Q, D.k * bb, jj);
+      for (int q = 0; q <= Q; q++) zq[q] = mk(jj[q], 0);
+    } else {
+      dev_sph_h(Q, D.k * bb, zq);
+    }
+  }
+  int m = threadIdx.x;
+  if (m <= Q) {
+    double ct = D.bz / bb, st = sqrt(D.bx * D.bx + D.by * D.by) / bb;
+    double ph = atan2(D.by, D.bx);
+    double pmm = 0.28209479177387814347;
+    for (int mm = 1; mm <= m; mm++) pmm *= sqrt((2.0 * mm + 1.0) / (2.0 * mm)) * st;
+    double sn, cs;
+    sincos(m * ph, &sn, &cs);
+    double sgn = (m & 1) ? -1.0 : 1.0;
+    double p0 = pmm, p1 = 0.0;
+    for (int q = m; q <= Q; q++) {
+      double val;
+      if (q == m) val = pmm;
+      else if (q == m + 1) { p1 = sqrt(2.0 * m + 3.0) * ct * pmm; val = p1; }
+      else {
+        double a = sqrt((2.0 * q - 1.0) * (2.0 * q + 1.0) / ((double)(q - m) * (q + m)));
+        double b = sqrt((2.0 * q + 1.0) * (q - m - 1.0) * (q + m - 1.0) / ((2.0 * q - 3.0) * (q + m) * (double)(q - m)));
+        double p2 = a * ct * p1 - b * p0;
+        p0 = p1;
+        p1 = p2;
+        val = p2;
+      }
+      Yq[cidx(q, m)] = mk(val * cs, val * sn);
+      if (m > 0) Yq[cidx(q, -m)] = mk(sgn * val * cs, -sgn * val * sn);
+    }
+  }
+  __syncthreads();
+  double* out = ops + (size_t)D.op * opsz;
+  int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
+  int P1 = p + 1;
+  for (int e = threadIdx.x; e < NR * NK; e += 256) {
+    int row = e / NK, col = e % NK;
+    cd val = mk(0, 0);
+    if (row < NC && col < NC) {
+      int n, mm, nu, mu;
+      decode_nm(row, &n, &mm);
+      decode_nm(col, &nu, &mu);
+      int s = mm - mu;
+      const double* g = gaunt + ((size_t)row * NC + col) * P1;
+      int q0 = abs(n - nu);
+      cd acc = mk(0, 0);
+      int jmax = (n < nu) ? n : nu;
+      for (int j = 0; j <= jmax; j++) {
+        int q = q0 + 2 * j;
+        if (abs(s) > q) continue;
+        double gv = g[j];
+        if (gv == 0.0) continue;
+        acc = acc + gv * (ipow(q) * zq[q] * cconj(Yq[cidx(q, s)]));
+      }
+      val = (4.0 * LFMM_PI) * (ipow(n - nu) * acc);
+    }
+    size_t pp = packed_pos(row, col, NKS);
+    out[pp] = val.x;
+    out[pp + 64] = val.y;
+  }
+}
+extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
+                           const double* gaunt, hipStream_t s) {
+  if (nops) k_transop<<<nops, 256, 0, s>>>(descs, ops, opsz, p, NC, NKS, gaunt);
+}
+
+// ---------------------------------------------------------------------------
+// Reaction M2L integrals (Section 3.5 eq. (me2lesimplified) in the polarisation
+// frame): for one geometry class (target centre height zt, source centre depth
+// zs, lateral distance rho)
+//   I[(n,m),(n',m')] = int_Gamma k_rho J_{m'-m}(k_rho rho) e^{i kz_t zt + i kz_s zs}
+//                      sigma^{ab}(k_rho)/kz_t Phat_n^m(kz_t/k_t) Phat_{n'}^{m'}(kz_s/k_s) dk_rho
+// Only the half m > 0 or (m = 0, m' >= 0) is integrated; the other half follows
+// from Phat_n^{-m} = (-1)^m Phat_n^m and J_{-q} = (-1)^q J_q.
+// One workgroup per class; nodes are generated CH at a time into LDS.
+// ---------------------------------------------------------------------------
+template <int CH>
+__global__ __launch_bounds__(256) void k_react_I(const ClassDesc* cls, Stack st, int p, const EntryDesc* ent,
+                                                 int nent, double* Iout, int NC) {
+  extern __shared__ cd sh[];
+  int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
+  cd* FJ = sh;                      // [CH][Q+1]
+  cd* PT = FJ + CH * (Q + 1);       // [CH][NT]
+  cd* PS = PT + CH * NT;            // [CH][NT]
+  ClassDesc C = cls[blockIdx.x];
+  double kt = st.k[C.lt], ks = st.k[C.ls];
+  int nn = rule_nodes(C.rule);
+  const int MAXE = 32;
+  cd acc[MAXE];
+  int ne = (nent + 255) / 256;
+  for (int r = 0; r < MAXE; r++) acc[r] = mk(0, 0);
+  for (int c0 = 0; c0 < nn; c0 += CH) {
+    int tid = threadIdx.x;
+    if (tid < CH) {
+      int node = c0 + tid;
+      if (node < nn) {
+        cd kr, w;
+        rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
+        cd kr2 = kr * kr;
+        cd kzt = csqrtd(mk(kt * kt, 0) - kr2), kzs = csqrtd(mk(ks * ks, 0) - kr2);
+        cd sig[2][2];
+        dev_densities(st, kr, C.lt, C.ls, sig);
+        cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
+        cd f = w * kr * ex * sig[C.a][C.b] / kzt;
+        dev_besselJ(Q, kr * C.rho, FJ + tid * (Q + 1), 1);
+        for (int q = 0; q <= Q; q++) FJ[tid * (Q + 1) + q] = f * FJ[tid * (Q + 1) + q];
+        dev_legendre_c(p, kzt / kt, kr / kt, PT + tid * NT, 1);
+        dev_legendre_c(p, kzs / ks, kr / ks, PS + tid * NT, 1);
+      } else {
+        for (int q = 0; q <= Q; q++) FJ[tid * (Q + 1) + q] = mk(0, 0);
+        for (int i = 0; i < NT; i++) { PT[tid * NT + i] = mk(0, 0); PS[tid * NT + i] = mk(0, 0); }
+      }
+    }
+    __syncthreads();
+    for (int r = 0; r < ne && r < MAXE; r++) {
+      int e = threadIdx.x + 256 * r;
+      if (e >= nent) break;
+      EntryDesc E = ent[e];
+      cd a = acc[r];
+      for (int c = 0; c < CH; c++) a = a + (PT[c * NT + E.ia] * PS[c * NT + E.ib]) * FJ[c * (Q + 1) + E.iq];
+      acc[r] = a;
+    }
+    __syncthreads();
+  }
+  double* out = Iout + (size_t)C.out * NC * NC * 2;
+  for (int r = 0; r < ne && r < MAXE; r++) {
+    int e = threadIdx.x + 256 * r;
+    if (e >= nent) break;
+    EntryDesc E = ent[e];
+    cd v = (double)E.sg * acc[r];
+    out[2 * ((size_t)E.row * NC + E.col)] = v.x;
+    out[2 * ((size_t)E.row * NC + E.col) + 1] = v.y;
+    out[2 * ((size_t)E.mrow * NC + E.mcol)] = v.x;
+    out[2 * ((size_t)E.mrow * NC + E.mcol) + 1] = v.y;
+  }
+}
+extern "C" void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const EntryDesc* ent, int nent,
+                           double* Iout, int NC, hipStream_t s) {
+  if (!ncls) return;
+  int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
+  if (p <= 8) {
+    size_t lds = sizeof(cd) * 64 * (Q + 1 + 2 * NT);
+    (void)hipFuncSetAttribute((const void*)k_react_I<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_react_I<64><<<ncls, 256, lds, s>>>(cls, st, p, ent, nent, Iout, NC);
+  } else {
+    size_t lds = sizeof(cd) * 32 * (Q + 1 + 2 * NT);
+    (void)hipFuncSetAttribute((const void*)k_react_I<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    k_react_I<32><<<ncls, 256, lds, s>>>(cls, st, p, ent, nent, Iout, NC);
+  }
+}
+
+// T[(n,m),(n',m')] = (4 pi/k_t) i^n (-i)^{n'} i^q e^{i q phi} I[(n,m),(n',m')], q = m' - m,
+// phi = arg of the lateral offset target - source.  One workgroup per operator.
+__global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const double* Iall, double* ops, int opsz,
+                                                      int p, int NC, int NKS) {
+  ROpDesc R = rops[blockIdx.x];
+  double phi = atan2(R.dy, R.dx);
+  const double* I = Iall + (size_t)R.cls * NC * NC * 2;
+  double* out = ops + (size_t)R.op * opsz;
+  int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
+  double pre = 4.0 * LFMM_PI / R.kt;
+  for (int e = threadIdx.x; e < NR * NK; e += 256) {
+    int row = e / NK, col = e % NK;
+    cd val = mk(0, 0);
+    if (row < NC && col < NC) {
+      int n, m, n2, m2;
+      decode_nm(row, &n, &m);
+      decode_nm(col, &n2, &m2);
+      int q = m2 - m;
+      double sn, cs;
+      sincos(q * phi, &sn, &cs);
+      cd iv = mk(I[2 * ((size_t)row * NC + col)], I[2 * ((size_t)row * NC + col) + 1]);
+      val = pre * (ipow(n - n2 + q) * (mk(cs, sn) * iv));
+    }
+    size_t pp = packed_pos(row, col, NKS);
+    out[pp] = val.x;
+    out[pp + 64] = val.y;
+  }
+}
+extern "C" void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p,
+                                int NC, int NKS, hipStream_t s) {
+  if (nops) k_react_expand<<<nops, 256, 0, s>>>(rops, Iall, ops, opsz, p, NC, NKS);
+}
+
+// ---------------------------------------------------------------------------
+// P2M: M_nm = sum_j Q_j 4 pi j_n(k r_j) conj(Y_n^m(r_j^)) about the leaf centre
+// (eq. (melecoeffree); at polarisation sources for reaction trees, eq.
+// (melayerupgoingimage)).  One thread per (leaf, |m|).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int seg_find(const int* prefix, int nseg, int x) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total,
+                                             const int* box_start, const int* box_cnt, const int* box_code,
+                                             const int* box_tree, const int* box_level, const TreeInfo* trees,
+                                             const double* px, const double* py, const double* pz, const double* pq,
+                                             int p, int NCK, double* M) {
+  int gid = blockIdx.x * 256 + threadIdx.x;
+  int P1 = p + 1;
+  if (gid >= total * P1) return;
+  int li = gid / P1, m = gid % P1;
+  int sgm = seg_find(seg_prefix, nseg, li);
+  int R = seg_row0[sgm] + (li - seg_prefix[sgm]);
+  TreeInfo T = trees[box_tree[R]];
+  double c[3];
+  box_center(T, (unsigned)box_code[R], box_level[R], c);
+  cd accp[24], accn[24];
+  for (int n = m; n <= p; n++) { accp[n - m] = mk(0, 0); accn[n - m] = mk(0, 0); }
+  int s0 = box_start[R], s1 = s0 + box_cnt[R];
+  double cm = (m & 1) ? -1.0 : 1.0;
+  for (int s = s0; s < s1; s++) {
+    double dx = px[s] - c[0], dy = py[s] - c[1], dz = pz[s] - c[2];
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    double jn[24];
+    dev_sph_j(p, T.k * r, jn);
+    double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? sqrt(dx * dx + dy * dy) / r : 0.0;
+    double ph = atan2(dy, dx);
+    double sn, cs;
+    sincos(m * ph, &sn, &cs);
+    cd q = mk(pq[2 * s], pq[2 * s + 1]);
+    double pmm = 0.28209479177387814347;
+    for (int mm = 1; mm <= m; mm++) pmm *= sqrt((2.0 * mm + 1.0) / (2.0 * mm)) * st;
+    double p0 = pmm, p1 = 0.0;
+    for (int n = m; n <= p; n++) {
+      double val;
+      if (n == m) val = pmm;
+      else if (n == m + 1) { p1 = sqrt(2.0 * m + 3.0) * ct * pmm; val = p1; }
+      else {
+        double a = sqrt((2.0 * n - 1.0) * (2.0 * n + 1.0) / ((double)(n - m) * (n + m)));
+        double b = sqrt((2.0 * n + 1.0) * (n - m - 1.0) * (n + m - 1.0) / ((2.0 * n - 3.0) * (n + m) * (double)(n - m)));
+        double p2 = a * ct * p1 - b * p0;
+        p0 = p1;
+        p1 = p2;
+        val = p2;
+      }
+      double base = 4.0 * LFMM_PI * jn[n] * val;
+      // conj(Y_n^m) = Phat e^{-i m phi};  conj(Y_n^{-m}) = (-1)^m Phat e^{+i m phi}
+      accp[n - m] = accp[n - m] + q * mk(base * cs, -base * sn);
+      if (m > 0) accn[n - m] = accn[n - m] + q * mk(cm * base * cs, cm * base * sn);
+    }
+  }
+  double* Mr = M + (size_t)R * NCK * 2;
+  for (int n = m; n <= p; n++) {
+    Mr[2 * cidx(n, m)] = accp[n - m].x;
+    Mr[2 * cidx(n, m) + 1] = accp[n - m].y;
+    if (m > 0) {
+      Mr[2 * cidx(n, -m)] = accn[n - m].x;
+      Mr[2 * cidx(n, -m) + 1] = accn[n - m].y;
+    }
+  }
+}
+extern "C" void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
+                       const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
+                       const TreeInfo* trees, const double* px, const double* py, const double* pz, const double* pq,
+                       int p, int NCK, double* M, hipStream_t s) {
+  if (total)
+    k_p2m<<<nblk((size_t)total * (p + 1), 256), 256, 0, s>>>(nseg, seg_row0, seg_prefix, total, box_start, box_cnt,
+                                                            box_code, box_tree, box_level, trees, px, py, pz, pq, p,
+                                                            NCK, M);
+}
+
+// ---------------------------------------------------------------------------
+// L2P: phi += sum_nm L_nm j_n(k r) Y_n^m(r^) (eq. (freespace3dlocexp) / (lelayerimage)),
+// one thread per target point of the listed trees (sorted-position segments).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int total,
+                                             const int* leafrow, const int* box_code, const int* box_tree,
+                                             const int* box_level, const TreeInfo* trees, const double* px,
+                                             const double* py, const double* pz, const int* sg, int p, int NCK,
+                                             const double* Lc, double* phi_tp) {
+  int gid = blockIdx.x * 256 + threadIdx.x;
+  if (gid >= total) return;
+  int sgm = seg_find(seg_prefix, nseg, gid);
+  int s = seg_s0[sgm] + (gid - seg_prefix[sgm]);
+  int R = leafrow[s];
+  TreeInfo T = trees[box_tree[R]];
+  double c[3];
+  box_center(T, (unsigned)box_code[R], box_level[R], c);
+  double dx = px[s] - c[0], dy = py[s] - c[1], dz = pz[s] - c[2];
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  double jn[24];
+  dev_sph_j(p, T.k * r, jn);
+  double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? sqrt(dx * dx + dy * dy) / r : 0.0;
+  double ph = atan2(dy, dx);
+  const double* L = Lc + (size_t)R * NCK * 2;
+  cd acc = mk(0, 0);
+  double pmm = 0.28209479177387814347;
+  for (int m = 0; m <= p; m++) {
+    if (m > 0) pmm *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * st;
+    double sn, cs;
+    sincos(m * ph, &sn, &cs);
+    double cm = (m & 1) ? -1.0 : 1.0;
+    double p0 = pmm, p1 = 0.0;
+    for (int n = m; n <= p; n++) {
+      double val;
+      if (n == m) val = pmm;
+      else if (n == m + 1) { p1 = sqrt(2.0 * m + 3.0) * ct * pmm; val = p1; }
+      else {
+        double a = sqrt((2.0 * n - 1.0) * (2.0 * n + 1.0) / ((double)(n - m) * (n + m)));
+        double b = sqrt((2.0 * n + 1.0) * (n - m - 1.0) * (n + m - 1.0) / ((2.0 * n - 3.0) * (n + m) * (double)(n - m)));
+        double p2 = a * ct * p1 - b * p0;
+        p0 = p1;
+        p1 = p2;
+        val = p2;
+      }
+      double base = jn[n] * val;
+      cd Lp = mk(L[2 * cidx(n, m)], L[2 * cidx(n, m) + 1]);
+      acc = acc + Lp * mk(base * cs, base * sn);
+      if (m > 0) {
+        cd Ln = mk(L[2 * cidx(n, -m)], L[2 * cidx(n, -m) + 1]);
+        acc = acc + Ln * mk(cm * base * cs, -cm * base * sn);
+      }
+    }
+  }
+  int g = sg[s];
+  phi_tp[2 * g] += acc.x;
+  phi_tp[2 * g + 1] += acc.y;
+}
+extern "C" void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int total, const int* leafrow,
+                       const int* box_code, const int* box_tree, const int* box_level, const TreeInfo* trees,
+                       const double* px, const double* py, const double* pz, const int* sg, int p, int NCK,
+                       const double* Lc, double* phi_tp, hipStream_t s) {
+  if (total)
+    k_l2p<<<nblk(total, 256), 256, 0, s>>>(nseg, seg_s0, seg_prefix, total, leafrow, box_code, box_tree, box_level,
+                                           trees, px, py, pz, sg, p, NCK, Lc, phi_tp);
+}
+
+// ---------------------------------------------------------------------------
+// Batched complex GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64):
+//   D[trow(e)] += sum_k Op[seq(k)] * S[srow(e, k)]
+// for every target e of a block; one block = up to 64 targets of one group that
+// share the operator sequence.  Each wave owns 16 targets (MFMA columns) and all
+// NRT row tiles; complex products use four real MFMAs.
+// f64 16x16x4 lane layout: A lane l = (row l%16, k l/16); B lane l = (k l/16,
+// col l%16); D lane l element r = (row l/16 + 4r, col l%16).
+// ---------------------------------------------------------------------------
+template <int NRT>
+__global__ __launch_bounds__(256) void k_gemm(const GBlock* blocks, const int* seq, const int* trow, const int* srow,
+                                              int srow_stride, const double* __restrict__ ops, int opsz, int NKS,
+                                              const double2* __restrict__ S, double2* D, int NCK, int NC) {
+  GBlock bd = blocks[blockIdx.x];
+  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int col = lane & 15, kr = lane >> 4;
+  int t = wave * 16 + col;
+  bool tvalid = t < bd.nt;
+  int e = bd.e0 + t;
+  const int* mys = srow + (size_t)e * srow_stride;
+  v4d accr[NRT], acci[NRT];
+  for (int i = 0; i < NRT; i++) {
+    accr[i] = (v4d){0, 0, 0, 0};
+    acci[i] = (v4d){0, 0, 0, 0};
+  }
+  for (int kk = 0; kk < bd.K; kk++) {
+    int sr = tvalid ? mys[kk] : -1;
+    if (__ballot(sr >= 0) == 0) continue;
+    int op = seq[bd.seq0 + kk];
+    const double* A = ops + (size_t)op * opsz;
+    const double2* B = S + (size_t)(sr >= 0 ? sr : 0) * NCK;
+    for (int ks = 0; ks < NKS; ks++) {
+      double2 bv = (sr >= 0) ? B[ks * 4 + kr] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int rt = 0; rt < NRT; rt++) {
+        const double* Ap = A + ((size_t)(rt * NKS + ks) << 7);
+        double are = Ap[lane], aim = Ap[64 + lane];
+        accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bv.x, accr[rt], 0, 0, 0);
+        accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim, bv.y, accr[rt], 0, 0, 0);
+        acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bv.y, acci[rt], 0, 0, 0);
+        acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bv.x, acci[rt], 0, 0, 0);
+      }
+    }
+  }
+  if (!tvalid) return;
+  double2* Dr = D + (size_t)trow[e] * NCK;
+#pragma unroll
+  for (int rt = 0; rt < NRT; rt++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      int row = rt * 16 + kr + 4 * r;
+      if (row < NC) {
+        double2 v = Dr[row];
+        v.x += accr[rt][r];
+        v.y += acci[rt][r];
+        Dr[row] = v;
+      }
+    }
+}
+extern "C" void lk_gemm(int nrt, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
+                        int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D, int NCK,
+                        int NC, hipStream_t s) {
+  if (!nblocks) return;
+  const double2* S2 = (const double2*)S;
+  double2* D2 = (double2*)D;
+#define GEMM_CASE(N) \
+  case N: k_gemm<N><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, NC); break;
+  switch (nrt) {
+    GEMM_CASE(1) GEMM_CASE(2) GEMM_CASE(3) GEMM_CASE(4) GEMM_CASE(5) GEMM_CASE(6) GEMM_CASE(7) GEMM_CASE(8)
+    GEMM_CASE(9) GEMM_CASE(10)
+    default: break;
+  }
+#undef GEMM_CASE
+}
+
+// ---------------------------------------------------------------------------
+// GEMM job construction: group ids per target box, then source rows.
+// mode 0: M2M targets (parents), mode 1: L2L targets, mode 2: M2L targets.
+// gbase[t*9 + l] = first group id of (tree, level) or -1.
+// ---------------------------------------------------------------------------
+__global__ void k_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree,
+                            const int* box_level, const TreeInfo* trees, const int* gbase, int* gid, int* rowid) {
+  int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= nrows) return;
+  int R = row0 + r;
+  int t = box_tree[R], l = box_level[R];
+  unsigned code = (unsigned)box_code[R];
+  int gb = gbase[t * 9 + l];
+  int g = 0x7fffffff;
+  if (gb >= 0) {
+    if (mode == 0) g = gb;
+    else if (mode == 1) g = gb + (int)(code & 7u);
+    else {
+      TreeInfo T = trees[t];
+      if (T.kind == 0) g = gb + (int)(code & 7u);
+      else {
+        int ix, iy, iz;
+        demorton3(code, l, &ix, &iy, &iz);
+        int j = iz - (1 << (l - 1));
+        if (j == 0 || j == 1) g = gb + j * 4 + (((ix & 1) << 1) | (iy & 1));
+      }
+    }
+  }
+  gid[r] = g;
+  rowid[r] = R;
+}
+extern "C" void lk_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree,
+                             const int* box_level, const TreeInfo* trees, const int* gbase, int nlev1, int* gid,
+                             int* rowid, hipStream_t s) {
+  (void)nlev1;
+  if (nrows) k_group_ids<<<nblk(nrows, 256), 256, 0, s>>>(nrows, row0, mode, box_code, box_tree, box_level, trees, gbase, gid, rowid);
+}
+
+__device__ __forceinline__ int grid_get(const long long* grid_off, const int* grid, int t, int l, int ix, int iy,
+                                        int iz) {
+  int n = 1 << l;
+  if (ix < 0 || iy < 0 || iz < 0 || ix >= n || iy >= n || iz >= n) return -1;
+  long long go = grid_off[t * 9 + l];
+  if (go < 0) return -1;
+  return grid[go + morton3(ix, iy, iz)];
+}
+
+// M2L sources from interaction templates (free: offsets within the same tree;
+// reaction: absolute source depth in a polarisation-source tree)
+__global__ void k_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
+                          const Tmpl* tmpl, int stride, const int* box_code, const int* box_level,
+                          const long long* grid_off, const int* grid, int* srow) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nent) return;
+  int g = egrp[e];
+  int R = trow[e];
+  int l = box_level[R];
+  int ix, iy, iz;
+  demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
+  int s0 = grp_seq0[g], K = grp_K[g];
+  for (int kk = 0; kk < K; kk++) {
+    Tmpl T = tmpl[s0 + kk];
+    int sz = T.zabs ? T.dz : iz - T.dz;
+    srow[(size_t)e * stride + kk] = grid_get(grid_off, grid, T.stree, l, ix - T.dx, iy - T.dy, sz);
+  }
+}
+extern "C" void lk_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
+                           const Tmpl* tmpl, int stride, const int* box_code, const int* box_level, const int* lvl_off,
+                           const long long* grid_off, int nlev1, const int* grid, int* seq_out, int* srow,
+                           hipStream_t s) {
+  (void)lvl_off; (void)nlev1; (void)seq_out;
+  if (nent) k_src_m2l<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, egrp, grp_seq0, grp_K, tmpl, stride, box_code, box_level, grid_off, grid, srow);
+}
+
+__global__ void k_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
+                          const long long* grid_off, const int* grid, int* srow) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nent) return;
+  int R = trow[e];
+  int t = box_tree[R], l = box_level[R] + 1;
+  unsigned code = (unsigned)box_code[R];
+  long long go = grid_off[t * 9 + l];
+  for (int ch = 0; ch < 8; ch++) srow[(size_t)e * 8 + ch] = (go < 0) ? -1 : grid[go + code * 8 + ch];
+}
+extern "C" void lk_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
+                           const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
+                           hipStream_t s) {
+  (void)lvl_off; (void)nlev1;
+  if (nent) k_src_m2m<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, box_code, box_tree, box_level, grid_off, grid, srow);
+}
+
+__global__ void k_src_l2l(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
+                          const long long* grid_off, const int* grid, int* srow) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nent) return;
+  int R = trow[e];
+  int t = box_tree[R], l = box_level[R];
+  unsigned code = (unsigned)box_code[R];
+  long long go = grid_off[t * 9 + (l - 1)];
+  srow[e] = (go < 0) ? -1 : grid[go + (code >> 3)];
+}
+extern "C" void lk_src_l2l(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
+                           const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
+                           hipStream_t s) {
+  (void)lvl_off; (void)nlev1;
+  if (nent) k_src_l2l<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, box_code, box_tree, box_level, grid_off, grid, srow);
+}
+
+// ---------------------------------------------------------------------------
+// Free-space near field: phi_i += sum_{j in adjacent leaves, j != i} Q_j h0(k r_ij),
+// h0(x) = e^{ix}/(ix) (eq. (totalinteraction)).  One workgroup per target leaf;
+// threads split as (target, stripe of sources), stripes reduced through LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix,
+                                                  const int* box_start, const int* box_cnt, const int* box_code,
+                                                  const int* box_tree, const int* box_level, const TreeInfo* trees,
+                                                  const long long* grid_off, const int* grid, const double* px,
+                                                  const double* py, const double* pz, const double* pq, const int* sg,
+                                                  double* phi_tp) {
+  __shared__ double red[2][256];
+  int li = blockIdx.x;
+  int sgm = seg_find(seg_prefix, nseg, li);
+  int R = seg_row0[sgm] + (li - seg_prefix[sgm]);
+  int t = box_tree[R], l = box_level[R];
+  double k = trees[t].k;
+  int ix, iy, iz;
+  demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
+  int s0 = box_start[R], nt = box_cnt[R];
+  // neighbour leaves
+  __shared__ int nb_start[27], nb_cnt[27];
+  if (threadIdx.x < 27) {
+    int dx = threadIdx.x / 9 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x % 3 - 1;
+    int Rn = grid_get(grid_off, grid, t, l, ix + dx, iy + dy, iz + dz);
+    nb_start[threadIdx.x] = Rn >= 0 ? box_start[Rn] : 0;
+    nb_cnt[threadIdx.x] = Rn >= 0 ? box_cnt[Rn] : 0;
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < nt; c0 += 256) {
+    int ntc = nt - c0 < 256 ? nt - c0 : 256;
+    int T = 1;
+    while (T < ntc) T <<= 1;
+    int NS = 256 / T;
+    int ti = threadIdx.x % T, stripe = threadIdx.x / T;
+    double accx = 0, accy = 0;
+    if (ti < ntc) {
+      int st = s0 + c0 + ti;
+      double x0 = px[st], y0 = py[st], z0 = pz[st];
+      for (int nbi = 0; nbi < 27; nbi++) {
+        int a = nb_start[nbi], cnt = nb_cnt[nbi];
+        for (int j = stripe; j < cnt; j += NS) {
+          int ss = a + j;
+          if (ss == st) continue;
+          double dx = x0 - px[ss], dy = y0 - py[ss], dz = z0 - pz[ss];
+          double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) continue;
+          double r = sqrt(r2);
+          double kr = k * r;
+          double sn, cs;
+          sincos(kr, &sn, &cs);
+          double inv = 1.0 / kr;
+          // h0 = (sin kr - i cos kr)/kr
+          double hr = sn * inv, hi = -cs * inv;
+          double qr = pq[2 * ss], qi = pq[2 * ss + 1];
+          accx += qr * hr - qi * hi;
+          accy += qr * hi + qi * hr;
+        }
+      }
+    }
+    red[0][threadIdx.x] = accx;
+    red[1][threadIdx.x] = accy;
+    __syncthreads();
+    if (threadIdx.x < ntc) {
+      double sx = 0, sy = 0;
+      for (int k2 = 0; k2 < NS; k2++) {
+        sx += red[0][threadIdx.x + k2 * T];
+        sy += red[1][threadIdx.x + k2 * T];
+      }
+      int g = sg[s0 + c0 + threadIdx.x];
+      phi_tp[2 * g] += sx;
+      phi_tp[2 * g + 1] += sy;
+    }
+    __syncthreads();
+  }
+}
+extern "C" void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
+                            const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
+                            const TreeInfo* trees, const int* lvl_off, const long long* grid_off, int nlev1,
+                            const int* grid, const double* px, const double* py, const double* pz, const double* pq,
+                            const int* sg, double* phi_tp, hipStream_t s) {
+  (void)lvl_off; (void)nlev1;
+  if (total)
+    k_p2p_free<<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code, box_tree, box_level,
+                                     trees, grid_off, grid, px, py, pz, pq, sg, phi_tp);
+}
+
+// ---------------------------------------------------------------------------
+// Reaction near field (Algorithm 1, local direct interactions): for adjacent
+// leaves across the interface, the kernel
+//   G = (1/k_t) int k_rho J0(k_rho rho) e^{i kz_t h + i kz_s h'} sigma/kz_t dk_rho
+// by contour quadrature.  Node tables per component: kr, fac = w kr sigma/(kz_t k_t), kz_t, kz_s.
+// ---------------------------------------------------------------------------
+__global__ void k_nf_nodes(int nnodes, Rule rule, Stack st, int lt, int ls, int a, int b, double* nkr, double* nfac,
+                           double* nkzt, double* nkzs) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nnodes) return;
+  cd kr, w;
+  rule_node(rule, i, c_glx, c_glw, &kr, &w);
+  double kt = st.k[lt], ks = st.k[ls];
+  cd kr2 = kr * kr;
+  cd kzt = csqrtd(mk(kt * kt, 0) - kr2), kzs = csqrtd(mk(ks * ks, 0) - kr2);
+  cd sig[2][2];
+  dev_densities(st, kr, lt, ls, sig);
+  cd fac = w * kr * sig[a][b] / kzt / kt;
+  nkr[2 * i] = kr.x; nkr[2 * i + 1] = kr.y;
+  nfac[2 * i] = fac.x; nfac[2 * i + 1] = fac.y;
+  nkzt[2 * i] = kzt.x; nkzt[2 * i + 1] = kzt.y;
+  nkzs[2 * i] = kzs.x; nkzs[2 * i + 1] = kzs.y;
+}
+extern "C" void lk_nf_nodes(int nnodes, Rule rule, Stack st, int lt, int ls, int a, int b, double* nkr, double* nfac,
+                             double* nkzt, double* nkzs, hipStream_t s) {
+  if (nnodes) k_nf_nodes<<<nblk(nnodes, 256), 256, 0, s>>>(nnodes, rule, st, lt, ls, a, b, nkr, nfac, nkzt, nkzs);
+}
+
+__global__ __launch_bounds__(256) void k_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps,
+                                                  const int* box_start, const int* box_cnt, const int* box_code,
+                                                  const TreeInfo* trees, const long long* grid_off, const int* grid,
+                                                  const double* px, const double* py, const double* pz,
+                                                  const double* pq, const int* sg, const double* nkr,
+                                                  const double* nfac, const double* nkzt, const double* nkzs,
+                                                  double* phi_tp) {
+  int R = row0 + blockIdx.x;
+  TreeInfo T = trees[ttree];
+  int l = T.depth;
+  int ix, iy, iz;
+  demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
+  if (iz != (1 << (l - 1))) return;  // only leaves touching the interface
+  int s0 = box_start[R], nt = box_cnt[R];
+  for (int tt = threadIdx.x; tt < nt; tt += 256) {
+    int st = s0 + tt;
+    double x0 = px[st], y0 = py[st], h0 = pz[st];
+    cd acc = mk(0, 0);
+    for (int c = 0; c < ncomp; c++) {
+      NFComp C = comps[c];
+      for (int dx = -1; dx <= 1; dx++)
+        for (int dy = -1; dy <= 1; dy++) {
+          int Rs = grid_get(grid_off, grid, C.stree, l, ix + dx, iy + dy, (1 << (l - 1)) - 1);
+          if (Rs < 0) continue;
+          int a0 = box_start[Rs], cn = box_cnt[Rs];
+          for (int j = 0; j < cn; j++) {
+            int ss = a0 + j;
+            double ddx = x0 - px[ss], ddy = y0 - py[ss];
+            double rho = sqrt(ddx * ddx + ddy * ddy), hs = -pz[ss];
+            cd g = mk(0, 0);
+            for (int nd = C.node0; nd < C.node0 + C.nnodes; nd++) {
+              cd kr = mk(nkr[2 * nd], nkr[2 * nd + 1]);
+              cd kzt = mk(nkzt[2 * nd], nkzt[2 * nd + 1]), kzs = mk(nkzs[2 * nd], nkzs[2 * nd + 1]);
+              cd fac = mk(nfac[2 * nd], nfac[2 * nd + 1]);
+              cd e = cexpd(cmul_i(kzt * h0 + kzs * hs));
+              g = g + fac * dev_besselJ0(kr * rho) * e;
+            }
+            acc = acc + mk(pq[2 * ss], pq[2 * ss + 1]) * g;
+          }
+        }
+    }
+    int gg = sg[st];
+    phi_tp[2 * gg] += acc.x;
+    phi_tp[2 * gg + 1] += acc.y;
+  }
+}
+extern "C" void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps, const int* box_start,
+                             const int* box_cnt, const int* box_code, const TreeInfo* trees, const long long* grid_off,
+                             const int* grid, const double* px, const double* py, const double* pz, const double* pq,
+                             const int* sg, const double* nkr, const double* nfac, const double* nkzt,
+                             const double* nkzs, double* phi_tp, hipStream_t s) {
+  if (nleaf && ncomp)
+    k_nf_react<<<nleaf, 256, 0, s>>>(nleaf, row0, ttree, ncomp, comps, box_start, box_cnt, box_code, trees, grid_off,
+                                     grid, px, py, pz, pq, sg, nkr, nfac, nkzt, nkzs, phi_tp);
+}
+
+// ---------------------------------------------------------------------------
+// Final sum over the trees in which particle i is a target (eq. (totalinteraction))
+// ---------------------------------------------------------------------------
+__global__ void k_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
+                            int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  int l = layer[i];
+  double sx = 0, sy = 0;
+  if (l >= 0) {
+    int j = inv_perm[i] - layer_start[l];
+    for (int c = 0; c < max_tt; c++) {
+      int t = tgt_trees[l * max_tt + c];
+      if (t < 0) continue;
+      int g = trees[t].pt_off + j;
+      sx += phi_tp[2 * g];
+      sy += phi_tp[2 * g + 1];
+    }
+  }
+  phi[2 * i] = sx;
+  phi[2 * i + 1] = sy;
+}
+extern "C" void lk_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
+                             int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, hipStream_t s) {
+  if (n) k_final_sum<<<nblk(n, 256), 256, 0, s>>>(n, layer, inv_perm, layer_start, tgt_trees, max_tt, trees, phi_tp, phi);
+}

@@ -1,0 +1,196 @@
+"""Python binding of liblfmm.so (argument marshalling only).
+
+Every stage of the evaluation runs in the HIP library; PyTorch only provides
+device memory and the stream.  Loading fails loudly when the library is missing:
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblfmm.so")
+
+LFMM_OK = 0
+_STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "not supported"}
+
+
+class LfmmError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed: %s (status %d)" % (what, _STATUS.get(code, "?"), code))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("contour_b", ctypes.c_double), ("max_depth", ctypes.c_int), ("min_gap", ctypes.c_double),
+                ("profile", ctypes.c_int)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("n_trees", ctypes.c_int), ("free_depth", ctypes.c_int * 17), ("reaction_depth", ctypes.c_int),
+                ("n_boxes", ctypes.c_int64), ("n_ops_free", ctypes.c_int64), ("n_react_classes", ctypes.c_int64),
+                ("n_react_nodes", ctypes.c_int64), ("n_ops_react", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
+                ("p2p_pairs_bound", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
+                ("stage_ms", ctypes.c_double * 16)]
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def load():
+    """Load liblfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # loading torch first makes liblfmm.so bind to that single runtime
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblfmm.so not found at %s: build it first (python -m paper_1902_05132_amd.build "
+                          "or __graft_entry__.build())" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.lfmm_plan.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options),
+                            ctypes.POINTER(vp)]
+    L.lfmm_eval_device.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    L.lfmm_eval.argtypes = [vp, ctypes.c_int64, _D, ctypes.c_void_p, _D, _D]
+    L.lfmm_last_report.argtypes = [vp, ctypes.POINTER(Report)]
+    L.lfmm_stage_name.argtypes = [ctypes.c_int]
+    L.lfmm_stage_name.restype = ctypes.c_char_p
+    L.lfmm_destroy.argtypes = [vp]
+    L.lfmm_destroy.restype = None
+    L.lfmm_status_string.argtypes = [ctypes.c_int]
+    L.lfmm_status_string.restype = ctypes.c_char_p
+    L.lfmm_translation.argtypes = [vp, ctypes.c_int, ctypes.c_double, _D, _D]
+    L.lfmm_reaction_operator.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
+    L.lfmm_densities.argtypes = [vp, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, _D]
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc != LFMM_OK:
+        raise LfmmError(rc, what)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Plan:
+    """lfmm_plan wrapper: d (L interfaces, decreasing), k (L+1 wavenumbers), order p, leaf size."""
+
+    def __init__(self, d, k, p, leaf_max, contour_b=0.5, max_depth=8, min_gap=1e-9, profile=False):
+        self.lib = load()
+        self.d = _f64(d)
+        self.k = _f64(k)
+        self.p = int(p)
+        self.L = len(self.d)
+        opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0)
+        h = ctypes.c_void_p()
+        dptr = self.d.ctypes.data_as(_D) if self.L else None
+        _check(self.lib.lfmm_plan(self.L, dptr, self.k.ctypes.data_as(_D), self.p, int(leaf_max),
+                                  ctypes.byref(opt), ctypes.byref(h)), "lfmm_plan")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.lfmm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- device evaluation (torch tensors on the GPU) ----
+    def eval_device(self, xyz, q, phi, layer=None, stream=None):
+        """xyz: float64 (3, n) contiguous; q, phi: complex128 (n,) contiguous; layer: int32 (n,) or None."""
+        import torch
+        n = xyz.shape[1]
+        assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.is_cuda
+        assert q.dtype == torch.complex128 and q.is_contiguous() and phi.dtype == torch.complex128
+        s = stream if stream is not None else torch.cuda.current_stream()
+        lp = layer.data_ptr() if layer is not None else None
+        _check(self.lib.lfmm_eval_device(self.h, n, xyz.data_ptr(), lp, q.data_ptr(), phi.data_ptr(),
+                                         ctypes.c_void_p(s.cuda_stream)), "lfmm_eval_device")
+        return phi
+
+    def eval_torch(self, x, y, z, q, layer=None):
+        import torch
+        dev = torch.device("cuda")
+        xyz = torch.stack([torch.as_tensor(np.asarray(v, dtype=np.float64)) for v in (x, y, z)]).to(dev)
+        qq = torch.as_tensor(np.asarray(q, dtype=np.complex128)).to(dev)
+        lt = None if layer is None else torch.as_tensor(np.asarray(layer, dtype=np.int32)).to(dev)
+        phi = torch.empty(len(x), dtype=torch.complex128, device=dev)
+        self.eval_device(xyz.contiguous(), qq.contiguous(), phi, lt)
+        torch.cuda.synchronize()
+        return phi.cpu().numpy()
+
+    # ---- host evaluation ----
+    def eval_host(self, x, y, z, q, layer=None):
+        n = len(x)
+        xyz = np.ascontiguousarray(np.concatenate([_f64(x), _f64(y), _f64(z)]))
+        qq = np.ascontiguousarray(np.asarray(q, dtype=np.complex128)).view(np.float64)
+        out = np.zeros(2 * n)
+        lay = None if layer is None else np.ascontiguousarray(np.asarray(layer, dtype=np.int32))
+        lp = lay.ctypes.data_as(ctypes.c_void_p) if lay is not None else None
+        _check(self.lib.lfmm_eval(self.h, n, xyz.ctypes.data_as(_D), lp, qq.ctypes.data_as(_D),
+                                  out.ctypes.data_as(_D)), "lfmm_eval")
+        return out[0::2] + 1j * out[1::2]
+
+    def report(self):
+        r = Report()
+        _check(self.lib.lfmm_last_report(self.h, ctypes.byref(r)), "lfmm_last_report")
+        stages = {}
+        i = 0
+        while True:
+            nm = self.lib.lfmm_stage_name(i)
+            if nm is None:
+                break
+            stages[nm.decode()] = r.stage_ms[i]
+            i += 1
+        return dict(n_trees=r.n_trees, free_depth=[r.free_depth[i] for i in range(self.L + 1)],
+                    reaction_depth=r.reaction_depth, n_boxes=r.n_boxes, n_ops_free=r.n_ops_free,
+                    n_react_classes=r.n_react_classes, n_react_nodes=r.n_react_nodes, n_ops_react=r.n_ops_react,
+                    m2l_pairs=r.m2l_pairs, p2p_pairs_bound=r.p2p_pairs_bound, nf_react_pairs=r.nf_react_pairs,
+                    stage_ms=stages)
+
+    # ---- component entry points ----
+    def translation(self, kind, kw, b):
+        nc = (self.p + 1) ** 2
+        out = np.zeros(2 * nc * nc)
+        bb = _f64(b)
+        _check(self.lib.lfmm_translation(self.h, int(kind), float(kw), bb.ctypes.data_as(_D),
+                                         out.ctypes.data_as(_D)), "lfmm_translation")
+        return (out[0::2] + 1j * out[1::2]).reshape(nc, nc)
+
+    def reaction_operator(self, l, a, lp, b, dx, dy, zt, zs):
+        nc = (self.p + 1) ** 2
+        out = np.zeros(2 * nc * nc)
+        _check(self.lib.lfmm_reaction_operator(self.h, l, a, lp, b, float(dx), float(dy), float(zt), float(zs),
+                                               out.ctypes.data_as(_D)), "lfmm_reaction_operator")
+        return (out[0::2] + 1j * out[1::2]).reshape(nc, nc)
+
+    def densities(self, krho, l, lp):
+        kr = np.ascontiguousarray(np.asarray(krho, dtype=np.complex128)).view(np.float64)
+        n = len(kr) // 2
+        out = np.zeros(8 * n)
+        _check(self.lib.lfmm_densities(self.h, n, kr.ctypes.data_as(_D), l, lp, out.ctypes.data_as(_D)),
+               "lfmm_densities")
+        return (out[0::2] + 1j * out[1::2]).reshape(n, 2, 2)
+
+
+def exported_symbols_from_header(path=None):
+    """Function names declared in include/lfmm.h."""
+    import re
+    path = path or os.path.join(os.path.dirname(HERE), "include", "lfmm.h")
+    text = open(path).read()
+    return sorted(set(re.findall(r"\b(lfmm_[a-z_]+)\s*\(", text)))
