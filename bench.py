@@ -1,0 +1,133 @@
+#!/usr/bin/env python3
+"""Benchmark: potential evaluations per second of the layered-media Helmholtz FMM.
+
+Workload (default): the paper's three-layer medium (interfaces z = 0, -1.2;
+k = 0.8, 1.5, 2.0), N = 1,048,576 particles uniform in three unit cubes (one per
+layer), complex charges uniform on [-1,1]^2, expansion order p = 8, FP64.
+One step = one lfmm_eval_device call (every stage of the method, inputs already
+resident in HBM).  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "potential evals/sec at N=1M, rel-err≤1e-6 vs FP64; surrogate/FP32 vs plain speedup"
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s=15.0, seed=7):
+    """Oracle direct summation timed on the host cores on a bounded sample:
+    a few targets against a random subset of the sources, scaled by the pair
+    throughput to evaluations per second at the full N."""
+    import oracle
+
+    rng = np.random.default_rng(seed)
+    n = len(w["x"])
+    nt = 3
+    targets = rng.choice(n, nt, replace=False)
+
+    def run(ns):
+        src = np.unique(np.concatenate([targets, rng.choice(n, ns, replace=False)]))
+        pos = {int(t): int(np.searchsorted(src, t)) for t in targets}
+        t0 = time.perf_counter()
+        oracle.direct(w["d"], w["k"], w["x"][src], w["y"][src], w["z"][src], w["layer"][src], w["q"][src],
+                      [pos[int(t)] for t in targets])
+        return time.perf_counter() - t0, len(src)
+
+    dt, ns = run(600)
+    per_pair = dt / (nt * ns)
+    ns2 = int(min(n - nt, max(1000, budget_s / (per_pair * nt))))
+    dt2, ns2 = run(ns2)
+    pairs_per_s = nt * ns2 / dt2
+    return {"value": pairs_per_s / n, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d targets x %d of the %d sources, direct summation (closed-form free part + Sommerfeld "
+                      "quadrature reaction part), scaled to N=%d by pair throughput; %.1f s"
+                      % (nt, ns2, n, n, dt2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1048576)
+    ap.add_argument("--p", type=int, default=8)
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it (got --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1902_05132_amd import lfmm
+    from paper_1902_05132_amd import workloads as W
+
+    w = W.config2(n=args.n, seed=args.seed, p=args.p, leaf=args.leaf)
+    n = len(w["x"])
+    log("bench: workload %s" % w["name"])
+    dev = torch.device("cuda:0")
+    xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+    q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+    phi = torch.empty(n, dtype=torch.complex128, device=dev)
+    plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True)
+    stream = torch.cuda.current_stream()
+    for i in range(args.warmup):
+        plan.eval_device(xyz, q, phi, stream=stream)
+        torch.cuda.synchronize()
+        log("bench: warmup %d done" % (i + 1))
+    stage_acc = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        plan.eval_device(xyz, q, phi, stream=stream)
+        rep = plan.report()
+        for kname, v in rep["stage_ms"].items():
+            stage_acc[kname] = stage_acc.get(kname, 0.0) + v
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1000.0 / args.steps
+    value = n / (ms / 1000.0)
+    stages = {kname: v / args.steps for kname, v in stage_acc.items()}
+    log("bench: %d steps, %.3f ms/step, %.4g evals/s" % (args.steps, ms, value))
+    if args.stages:
+        for kname, v in stages.items():
+            log("  stage %-14s %9.3f ms" % (kname, v))
+        log("  report: %s" % {k: v for k, v in rep.items() if k != "stage_ms"})
+    nc = (args.p + 1) ** 2
+    m2l_flops = 8.0 * nc * nc * rep["m2l_pairs"]
+    m2l_s = stages["m2l"] / 1000.0
+    achieved = m2l_flops / m2l_s / 1e12 if m2l_s > 0 else 0.0
+    roofline = {"kernel": "k_gemm (M2L, batched complex FP64 MFMA)", "bound": "mfma", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None, "algorithmic_flops_per_launch": m2l_flops, "launch_ms": stages["m2l"]}
+    out = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "strong",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": w["name"], "N": n, "p": args.p, "leaf": args.leaf, "layers": 3,
+                      "interfaces": list(map(float, w["d"])), "k": list(map(float, w["k"]))},
+           "stages_ms": stages, "roofline": roofline}
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(w)
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

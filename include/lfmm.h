@@ -63,6 +63,9 @@ typedef struct {
   int64_t n_react_nodes;   /* contour nodes summed over the classes */
   int64_t n_ops_react;     /* reaction M2L operators */
   int64_t m2l_pairs;       /* (target box, source box) M2L products, free + reaction */
+  int64_t m2l_slots;       /* M2L products issued to the GEMM (including absent sources) */
+  int64_t m2m_pairs;       /* (parent, child) M2M products */
+  int64_t l2l_pairs;       /* (child, parent) L2L products */
   int64_t p2p_pairs_bound; /* upper bound of free-space near-field pairs */
   int64_t nf_react_pairs;  /* near-field reaction pairs */
   double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */

@@ -781,9 +781,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1);
   int ne_m2m = ng_m2m ? gs_m2m[ng_m2m] : 0, ne_l2l = ng_l2l ? gs_l2l[ng_l2l] : 0,
       ne_m2l = ng_m2l ? gs_m2l[ng_m2l] : 0;
-  int64_t m2l_pairs = 0;
-  for (int g = 0; g < ng_m2l; g++) m2l_pairs += (int64_t)c_m2l[g] * g_m2l[g].K;
-  rep.m2l_pairs = m2l_pairs;
+  int64_t m2l_slots = 0;
+  for (int g = 0; g < ng_m2l; g++) m2l_slots += (int64_t)c_m2l[g] * g_m2l[g].K;
+  rep.m2l_slots = m2l_slots;
   // source rows
   int* sr_m2m = P->dev<int>("sr_m2m", (size_t)ne_m2m * 8 + 1);
   int* sr_l2l = P->dev<int>("sr_l2l", (size_t)ne_l2l + 1);
@@ -801,6 +801,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   if (ne_m2l)
     lk_src_m2l(ne_m2l, J_m2l.srowid, J_m2l.sgid, d_gseq0, d_gK, d_tmpl, kmax_m2l, box_code, box_level, d_lvl_off,
                d_grid_off, 9, grid, nullptr, sr_m2l, s);
+  unsigned long long* d_cnt = P->dev<unsigned long long>("pair_counts", 4);
+  HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * 4, s));
+  if (ne_m2l) lk_count_valid(ne_m2l, J_m2l.sgid, d_gK, 0, sr_m2l, kmax_m2l, d_cnt + 0, s);
+  if (ne_m2m) lk_count_valid(ne_m2m, nullptr, nullptr, 8, sr_m2m, 8, d_cnt + 1, s);
+  if (ne_l2l) lk_count_valid(ne_l2l, nullptr, nullptr, 1, sr_l2l, 1, d_cnt + 2, s);
   GBlock* d_bm2m = P->upload("b_m2m", b_m2m, s);
   GBlock* d_bl2l = P->upload("b_l2l", b_l2l, s);
   GBlock* d_bm2l = P->upload("b_m2l", b_m2l, s);
@@ -949,7 +954,12 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, s);
   mark(13);
   HIPCHK(hipGetLastError());
+  unsigned long long hcnt[4] = {0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(hcnt, d_cnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  rep.m2l_pairs = (int64_t)hcnt[0];
+  rep.m2m_pairs = (int64_t)hcnt[1];
+  rep.l2l_pairs = (int64_t)hcnt[2];
   if (prof) {
     // stage i spans events i+1 .. i+2 of the marks above (classify = 0..1)
     int map_ev[ST_COUNT][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7},

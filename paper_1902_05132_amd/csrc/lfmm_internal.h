@@ -139,6 +139,8 @@ void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps,
                  const int* grid, const double* px, const double* py, const double* pz, const double* pq,
                  const int* sg, const double* nkr, const double* nfac, const double* nkzt, const double* nkzs,
                  double* phi_tp, hipStream_t s);
+void lk_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, const int* srow, int stride,
+                    unsigned long long* counter, hipStream_t s);
 void lk_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
                   int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, hipStream_t s);
 }

@@ -260,14 +260,14 @@ __global__ void k_occupancy(int ntp, const unsigned* skeys, const TreeInfo* tree
   demorton3(key & 0xFFFFFFu, 8, &ix, &iy, &iz);
   for (int l = 0; l <= 8; l++) {
     int sh = 3 * (8 - l);
-    if (s == T.pt_off || (skeys[s - 1] >> sh) != (key >> sh)) {
+    if (s == T.pt_off || (skeys[s - 1] >> sh) != (key >> sh)) {  // first point of its cell
       int e = run_end(skeys, s, hi, sh);
       atomicMax(&occ[t * 9 + l], e - s);
-    }
-    if (l >= 1 && T.kind != 0) {
-      int izl = iz >> (8 - l), half = 1 << (l - 1);
-      int hgt = (T.kind == 1) ? izl - half : half - 1 - izl;
-      if (hgt == 0 || hgt == 1) slab[(t * 9 + l) * 2 + hgt] = 1;
+      if (l >= 1 && T.kind != 0) {
+        int izl = iz >> (8 - l), half = 1 << (l - 1);
+        int hgt = (T.kind == 1) ? izl - half : half - 1 - izl;
+        if (hgt == 0 || hgt == 1) slab[(t * 9 + l) * 2 + hgt] = 1;
+      }
     }
   }
 }
@@ -900,6 +900,22 @@ extern "C" void lk_src_m2l(int nent, const int* trow, const int* egrp, const int
                            hipStream_t s) {
   (void)lvl_off; (void)nlev1; (void)seq_out;
   if (nent) k_src_m2l<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, egrp, grp_seq0, grp_K, tmpl, stride, box_code, box_level, grid_off, grid, srow);
+}
+
+// number of (target, source) products with a source present
+__global__ void k_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, const int* srow, int stride,
+                              unsigned long long* counter) {
+  int e = blockIdx.x * 256 + threadIdx.x;
+  unsigned long long c = 0;
+  if (e < nent) {
+    int K = egrp ? grp_K[egrp[e]] : fixedK;
+    for (int kk = 0; kk < K; kk++) c += (srow[(size_t)e * stride + kk] >= 0) ? 1ull : 0ull;
+  }
+  if (c) atomicAdd(counter, c);
+}
+extern "C" void lk_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, const int* srow, int stride,
+                               unsigned long long* counter, hipStream_t s) {
+  if (nent) k_count_valid<<<nblk(nent, 256), 256, 0, s>>>(nent, egrp, grp_K, fixedK, srow, stride, counter);
 }
 
 __global__ void k_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
