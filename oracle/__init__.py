@@ -70,6 +70,8 @@ def _declare(L):
         "orc_eval_expansion": [c_int, c_double, _D, _D, c_int, _D],
         "orc_reaction_T": [c_int, _D, _D, c_int, c_int, c_int, c_int, c_double, c_double, c_double, c_double,
                            c_int, c_double, _D],
+        "orc_reaction_T_mass": [c_int, _D, _D, c_int, c_int, c_int, c_int, c_double, c_double, c_double,
+                                c_double, c_int, c_double, _D],
         "orc_reaction_kernel": [c_int, _D, _D, c_int, c_int, c_int, c_int, c_double, c_double, c_double,
                                 c_double, _D],
         "orc_reaction_me_basis": [c_int, _D, _D, c_int, c_int, c_int, c_int, c_double, c_double, c_double,
@@ -258,6 +260,17 @@ def reaction_T(d, k, l, a, lp, b, dx, dy, zt, zs, p, qb=0.5):
     lib().orc_reaction_T(len(d), _dp(d), _dp(k), l, a, lp, b, float(dx), float(dy), float(zt), float(zs), p,
                          float(qb), _dp(out))
     return _cplx(out).reshape(nc, nc)
+
+
+def reaction_T_mass(d, k, l, a, lp, b, dx, dy, zt, zs, p, qb=0.5):
+    """Per-entry sum of |quadrature terms| of reaction_T (its rounding scale)."""
+    nc = (p + 1) ** 2
+    d = _f64(d)
+    k = _f64(k)
+    out = np.zeros(nc * nc)
+    lib().orc_reaction_T_mass(len(d), _dp(d), _dp(k), l, a, lp, b, float(dx), float(dy), float(zt), float(zs), p,
+                              float(qb), _dp(out))
+    return out.reshape(nc, nc)
 
 
 def reaction_kernel(d, k, l, a, lp, b, rho, ht, hs, qb=0.5):

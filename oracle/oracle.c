@@ -872,6 +872,46 @@ static void reaction_T(const stack_t *st, int l, int a, int lp, int b, double dx
   free_rule(&qr);
 }
 
+/* Rounding scale of reaction_T: the same quadrature with every term replaced by
+ * its modulus, sum_i |w_i k_rho J_q e^{...} sigma/kz_t Phat Phat| times the
+ * prefactor modulus.  Differences between two correct quadratures of the
+ * oscillatory integrals (Section 3.5) are bounded by a small multiple of
+ * eps times this mass. */
+void orc_reaction_T_mass(int L, const double *d, const double *k, int l, int a, int lp, int b, double dx, double dy,
+                         double zt, double zs, int p, double qb, double *out) {
+  stack_t st;
+  make_stack(&st, L, d, k);
+  int NC = (p + 1) * (p + 1), NT = (p + 1) * (p + 2) / 2, Q = 2 * p;
+  double rho = sqrt(dx * dx + dy * dy);
+  double kt = st.k[l], ks = st.k[lp];
+  qrule_t qr = make_rule(qb, stack_kmax(&st), zt + zs, rho, 2 * p + 1);
+  double *mass = (double *)calloc((size_t)NC * NC, sizeof(double));
+  cplx *Pt = (cplx *)malloc(sizeof(cplx) * NT), *Ps = (cplx *)malloc(sizeof(cplx) * NT);
+  cplx *J = (cplx *)malloc(sizeof(cplx) * (Q + 1));
+  for (int i = 0; i < qr.n; i++) {
+    cplx kr = qr.kr[i], kzt = kz_of(kt, kr), kzs = kz_of(ks, kr);
+    cplx sig[2][2];
+    orc_densities_c(&st, kr, l, lp, sig);
+    double f = cabs(qr.w[i] * kr * cexp(I * kzt * zt + I * kzs * zs) * sig[a][b] / kzt);
+    orc_bessel_J(Q, kr * rho, J);
+    orc_legendre(p, kzt / kt, orc_branch_sqrt(kzt / kt), Pt);
+    orc_legendre(p, kzs / ks, orc_branch_sqrt(kzs / ks), Ps);
+    for (int n = 0; n <= p; n++)
+      for (int m = -n; m <= n; m++)
+        for (int n2 = 0; n2 <= p; n2++)
+          for (int m2 = -n2; m2 <= n2; m2++) {
+            int qq = abs(m2 - m);
+            mass[(size_t)idx(n, m) * NC + idx(n2, m2)] += f * cabs(phat(Pt, n, m)) * cabs(phat(Ps, n2, m2)) * cabs(J[qq]);
+          }
+  }
+  for (int i = 0; i < NC * NC; i++) out[i] = 4.0 * PI / kt * mass[i];
+  free(mass);
+  free(Pt);
+  free(Ps);
+  free(J);
+  free_rule(&qr);
+}
+
 void orc_reaction_T(int L, const double *d, const double *k, int l, int a, int lp, int b, double dx, double dy,
                     double zt, double zs, int p, double qb, double *out) {
   stack_t st;

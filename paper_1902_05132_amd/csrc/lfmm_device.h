@@ -68,21 +68,41 @@ __host__ __device__ __forceinline__ int tix(int n, int m) { return n * (n + 1) /
 // j_n(x), n = 0..p: power series for x < 1, otherwise Miller's backward
 // recurrence normalised to sin(x)/x or the closed form of j_1.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double sph_j_series(int n, double x) {
+  // j_n(x) = x^n/(2n+1)!! sum_k (-x^2/2)^k / (k! (2n+3)(2n+5)...(2n+2k+1))
+  double xn = 1.0, dfac = 1.0;
+  for (int i = 1; i <= n; i++) {
+    xn *= x;
+    dfac *= (2.0 * i + 1.0);
+  }
+  double x2 = 0.5 * x * x, term = 1.0, s = 1.0;
+  for (int k = 1; k < 30; k++) {
+    term *= -x2 / (k * (2.0 * n + 2.0 * k + 1.0));
+    s += term;
+    if (fabs(term) < 1e-17 * fabs(s)) break;
+  }
+  return xn / dfac * s;
+}
 __device__ __forceinline__ void dev_sph_j(int p, double x, double* j) {
-  if (x < 1.0) {
-    double x2 = 0.5 * x * x, xn = 1.0, dfac = 1.0;  // x^n / (2n+1)!!
+  if (x < 1e-3) {  // two terms of the series per order are exact to rounding
+    double xn = 1.0, dfac = 1.0, x2 = 0.5 * x * x;
     for (int n = 0; n <= p; n++) {
       if (n > 0) {
         xn *= x;
         dfac *= (2.0 * n + 1.0);
       }
-      double term = 1.0, s = 1.0;
-      for (int k = 1; k < 24; k++) {
-        term *= -x2 / (k * (2.0 * n + 2.0 * k + 1.0));
-        s += term;
-        if (fabs(term) < 1e-18) break;
-      }
-      j[n] = xn / dfac * s;
+      j[n] = xn / dfac * (1.0 - x2 / (2.0 * n + 3.0) + x2 * x2 / (2.0 * (2.0 * n + 3.0) * (2.0 * n + 5.0)));
+    }
+    return;
+  }
+  if (x < 1.0) {  // series for the two highest orders, then the stable downward recurrence
+    double jp = sph_j_series(p + 1, x), jc = sph_j_series(p, x);
+    j[p] = jc;
+    for (int n = p; n >= 1; n--) {
+      double jm = (2.0 * n + 1.0) / x * jc - jp;
+      jp = jc;
+      jc = jm;
+      j[n - 1] = jc;
     }
     return;
   }
@@ -107,6 +127,63 @@ __device__ __forceinline__ void dev_sph_j(int p, double x, double* j) {
   for (int n = 0; n <= p; n++) j[n] *= sc;
 }
 
+// Same as dev_sph_j with a compile-time order so that j[] stays in registers.
+template <int P>
+__device__ __forceinline__ void dev_sph_j_t(double x, double (&j)[P + 1]) {
+  if (x < 1e-3) {
+    double xn = 1.0, dfac = 1.0, x2 = 0.5 * x * x;
+#pragma unroll
+    for (int n = 0; n <= P; n++) {
+      if (n > 0) {
+        xn *= x;
+        dfac *= (2.0 * n + 1.0);
+      }
+      j[n] = xn / dfac * (1.0 - x2 / (2.0 * n + 3.0) + x2 * x2 / (2.0 * (2.0 * n + 3.0) * (2.0 * n + 5.0)));
+    }
+    return;
+  }
+  double fp1, f;
+  if (x < 1.0) {
+    fp1 = sph_j_series(P + 1, x);
+    f = sph_j_series(P, x);
+    j[P] = f;
+#pragma unroll
+    for (int n = P; n >= 1; n--) {
+      double fm = (2.0 * n + 1.0) / x * f - fp1;
+      fp1 = f;
+      f = fm;
+      j[n - 1] = f;
+    }
+    return;
+  }
+  int N = P + 24 + (int)x;
+  fp1 = 0.0;
+  f = 1e-200;
+  for (int n = N; n >= P + 2; n--) {  // f_{n-1} from f_n, f_{n+1}; nothing stored yet
+    double fm = (2.0 * n + 1.0) / x * f - fp1;
+    fp1 = f;
+    f = fm;
+    if (fabs(f) > 1e200) {
+      f *= 1e-200;
+      fp1 *= 1e-200;
+    }
+  }
+  // f = f_{P+1}, fp1 = f_{P+2}
+#pragma unroll
+  for (int n = P + 1; n >= 1; n--) {
+    double fm = (2.0 * n + 1.0) / x * f - fp1;
+    fp1 = f;
+    f = fm;
+    j[n - 1] = f;
+  }
+  double s, c;
+  sincos(x, &s, &c);
+  double j0 = s / x, j1 = s / (x * x) - c / x;
+  double sc = (fabs(j0) >= fabs(j1)) ? j0 / j[0] : j1 / j[1];
+#pragma unroll
+  for (int n = 0; n <= P; n++) j[n] *= sc;
+}
+
 // h_n^{(1)}(x) = j_n + i y_n, n = 0..p, x > 0 (y_n by upward recurrence)
 __device__ __forceinline__ void dev_sph_h(int p, double x, cd* h) {
   double jj[48];
@@ -121,6 +198,37 @@ __device__ __forceinline__ void dev_sph_h(int p, double x, cd* h) {
     y0 = y1;
     y1 = y2;
     h[n + 1] = mk(jj[n + 1], y1);
+  }
+}
+
+// Hankel's asymptotic expansions of J_0 and J_1 (|z| >= 25, |arg z| < pi/2):
+// J_nu ~ sqrt(2/(pi z)) (P cos w - Q sin w), w = z - nu pi/2 - pi/4.
+__device__ __forceinline__ void dev_hankel_J01(cd z, cd* J0, cd* J1) {
+  cd iz = mk(1, 0) / z;
+  cd P0 = mk(1, 0), Q0 = mk(0, 0), P1 = mk(1, 0), Q1 = mk(0, 0), t0 = mk(1, 0), t1 = mk(1, 0);
+  for (int k = 1; k < 40; k++) {
+    double o = (2.0 * k - 1.0) * (2.0 * k - 1.0);
+    t0 = t0 * ((0.0 - o) / (8.0 * k)) * iz;
+    t1 = t1 * ((4.0 - o) / (8.0 * k)) * iz;
+    double sg = (k & 1) ? ((((k - 1) >> 1) & 1) ? -1.0 : 1.0) : (((k >> 1) & 1) ? -1.0 : 1.0);
+    if (k & 1) {
+      Q0 = Q0 + sg * t0;
+      Q1 = Q1 + sg * t1;
+    } else {
+      P0 = P0 + sg * t0;
+      P1 = P1 + sg * t1;
+    }
+    if (cabs2(t0) < 1e-36 && cabs2(t1) < 1e-36) break;
+  }
+  cd pre = csqrtd(mk(2.0 / LFMM_PI, 0) / z);
+  for (int nu = 0; nu < 2; nu++) {
+    cd w = mk(z.x - (0.25 + 0.5 * nu) * LFMM_PI, z.y);
+    double sx, cx;
+    sincos(w.x, &sx, &cx);
+    double ch = cosh(w.y), sh = sinh(w.y);
+    cd cw = mk(cx * ch, -sx * sh), sw = mk(sx * ch, cx * sh);
+    if (nu == 0) *J0 = pre * (P0 * cw - Q0 * sw);
+    else *J1 = pre * (P1 * cw - Q1 * sw);
   }
 }
 
@@ -150,6 +258,21 @@ __device__ __forceinline__ void dev_besselJ(int qmax, cd z, cd* out, int stride)
         if (cabs2(term) < 1e-36 * cabs2(s)) break;
       }
       out[q * stride] = s;
+    }
+    return;
+  }
+  if (az > 25.0 && az > 2.0 * qmax) {
+    // Hankel's expansion for J_0, J_1 then forward recurrence (stable for q < |z|)
+    cd J0, J1;
+    dev_hankel_J01(z, &J0, &J1);
+    out[0] = J0;
+    if (qmax >= 1) out[stride] = J1;
+    cd inv2 = mk(2.0, 0) / z, jm = J0, jc = J1;
+    for (int q = 1; q < qmax; q++) {
+      cd jn = (double)q * (inv2 * jc) - jm;
+      jm = jc;
+      jc = jn;
+      out[(q + 1) * stride] = jc;
     }
     return;
   }
@@ -261,34 +384,51 @@ struct Stack {
   double k[LFMM_MAXL + 1];
 };
 
-__device__ __forceinline__ void dev_densities(const Stack& st, cd kr, int l, int lp, cd sig[2][2]) {
-  int L = st.L;
-  cd kz[LFMM_MAXL + 1], a[LFMM_MAXL + 1], E[LFMM_MAXL + 1];
+// LL > 0: the stack has exactly LL interfaces (arrays stay in registers);
+// LL = 0: any L <= LFMM_MAXL.
+template <int LL>
+__device__ __forceinline__ void dev_densities_t(const Stack& st, cd kr, int l, int lp, cd sig[2][2]) {
+  constexpr int NL = (LL > 0) ? LL : LFMM_MAXL;
+  const int L = (LL > 0) ? LL : st.L;
+  cd kz[NL + 1], a[NL + 1], E[NL + 1], Rd[NL + 1], Ru[NL + 1];
   cd kr2 = kr * kr;
-  for (int m = 0; m <= L; m++) {
+#pragma unroll
+  for (int m = 0; m <= NL; m++) {
+    kz[m] = mk(1, 0);
+    a[m] = mk(1, 0);
+    E[m] = mk(0, 0);
+    if (m > L) continue;
     kz[m] = csqrtd(mk(st.k[m] * st.k[m], 0) - kr2);
     a[m] = st.k[m] * kz[m];
-    E[m] = mk(0, 0);
     if (m >= 1 && m <= L - 1) E[m] = cexpd(cmul_i(kz[m] * (st.d[m - 1] - st.d[m])));
   }
-  // down-looking reflection at the bottom of layers lo..L-1 and up-looking at the top of layers 1..hi
-  cd Rd[LFMM_MAXL + 1], Ru[LFMM_MAXL + 1];
-  Rd[L] = mk(0, 0);
-  for (int m = L - 1; m >= 0; m--) {
+  // Rd[m]: reflection looking down from layer m at d_m; Ru[m]: looking up from layer m at d_{m-1}
+#pragma unroll
+  for (int m = NL; m >= 0; m--) {
+    Rd[m] = mk(0, 0);
+    if (m >= L) continue;
     cd r = (a[m] - a[m + 1]) / (a[m] + a[m + 1]);
-    cd rho = (m + 1 <= L - 1) ? Rd[m + 1] * E[m + 1] * E[m + 1] : mk(0, 0);
+    cd rho = (m + 1 <= L - 1) ? Rd[(m + 1 <= NL) ? m + 1 : NL] * E[(m + 1 <= NL) ? m + 1 : NL] * E[(m + 1 <= NL) ? m + 1 : NL] : mk(0, 0);
     Rd[m] = (r + rho) / (mk(1, 0) + r * rho);
   }
-  Ru[0] = mk(0, 0);
-  for (int m = 1; m <= L; m++) {
+#pragma unroll
+  for (int m = 0; m <= NL; m++) {
+    Ru[m] = mk(0, 0);
+    if (m < 1 || m > L) continue;
     cd r = (a[m] - a[m - 1]) / (a[m] + a[m - 1]);
     cd rho = (m - 1 >= 1) ? Ru[m - 1] * E[m - 1] * E[m - 1] : mk(0, 0);
     Ru[m] = (r + rho) / (mk(1, 0) + r * rho);
   }
-  cd Rb = (lp <= L - 1) ? Rd[lp] : mk(0, 0);
-  cd Rt = (lp >= 1) ? Ru[lp] : mk(0, 0);
-  cd Ep = (lp >= 1 && lp <= L - 1) ? E[lp] : mk(0, 0);
+  cd Rb = mk(0, 0), Rt = mk(0, 0), Ep = mk(0, 0);
+#pragma unroll
+  for (int m = 0; m <= NL; m++)
+    if (m == lp) {
+      if (lp <= L - 1) Rb = Rd[m];
+      if (lp >= 1) Rt = Ru[m];
+      if (lp >= 1 && lp <= L - 1) Ep = E[m];
+    }
   cd Delta = mk(1, 0) - Rb * Rt * Ep * Ep;
+#pragma unroll
   for (int b = 0; b < 2; b++) {
     bool exists = (b == 0) ? (lp <= L - 1) : (lp >= 1);
     sig[0][b] = mk(0, 0);
@@ -297,39 +437,48 @@ __device__ __forceinline__ void dev_densities(const Stack& st, cd kr, int l, int
     cd Xb = (b == 0) ? mk(1, 0) : mk(0, 0), Xt = (b == 1) ? mk(1, 0) : mk(0, 0);
     cd U = Rb * (Xb + Ep * Rt * Xt) / Delta;  // up-going in the source layer (ref. d_lp)
     cd D = Rt * (Xt + Ep * Rb * Xb) / Delta;  // down-going (ref. d_{lp-1})
-    cd Ul, Dl;
-    if (l == lp) {
-      Ul = U;
-      Dl = D;
-    } else if (l < lp) {
-      // total up-going wave at the top of the source layer, then transmit upward
-      cd A = Xt + ((lp <= L - 1) ? Ep * U : mk(0, 0));
-      cd Um = A;
-      for (int m = lp; m > l; m--) {
+    cd Ul = U, Dl = D;
+    if (l < lp) {
+      // total up-going wave at the top of the source layer, transmitted upward layer by layer
+      cd Um = Xt + ((lp <= L - 1) ? Ep * U : mk(0, 0));
+#pragma unroll
+      for (int m = NL; m >= 1; m--) {
+        if (m > lp || m <= l) continue;
         cd r = (a[m] - a[m - 1]) / (a[m] + a[m - 1]);
         cd rho = (m - 1 >= 1) ? Ru[m - 1] * E[m - 1] * E[m - 1] : mk(0, 0);
         cd T = (kz[m - 1] / kz[m]) * (mk(1, 0) + r) / (mk(1, 0) + r * rho);
-        Um = T * Um;           // U_{m-1}, referenced at d_{m-1}
-        if (m - 1 > l) Um = E[m - 1] * Um;  // carry to the top of layer m-1
+        Um = T * Um;                        // U_{m-1}, referenced at d_{m-1}
+        if (m - 1 > l) Um = E[m - 1] * Um;  // carried to the top of layer m-1
       }
       Ul = Um;
-      Dl = (l >= 1) ? Ru[l] * E[l] * Ul : mk(0, 0);
-    } else {
-      cd B = Xb + ((lp >= 1) ? Ep * D : mk(0, 0));
-      cd Dm = B;
-      for (int m = lp; m < l; m++) {
+      Dl = mk(0, 0);
+#pragma unroll
+      for (int m = 0; m <= NL; m++)
+        if (m == l && l >= 1) Dl = Ru[m] * E[m] * Ul;
+    } else if (l > lp) {
+      cd Dm = Xb + ((lp >= 1) ? Ep * D : mk(0, 0));
+#pragma unroll
+      for (int m = 0; m < NL; m++) {
+        if (m < lp || m >= l) continue;
         cd r = (a[m] - a[m + 1]) / (a[m] + a[m + 1]);
         cd rho = (m + 1 <= L - 1) ? Rd[m + 1] * E[m + 1] * E[m + 1] : mk(0, 0);
         cd T = (kz[m + 1] / kz[m]) * (mk(1, 0) + r) / (mk(1, 0) + r * rho);
-        Dm = T * Dm;           // D_{m+1}, referenced at d_m
+        Dm = T * Dm;                        // D_{m+1}, referenced at d_m
         if (m + 1 < l) Dm = E[m + 1] * Dm;
       }
       Dl = Dm;
-      Ul = (l <= L - 1) ? Rd[l] * E[l] * Dl : mk(0, 0);
+      Ul = mk(0, 0);
+#pragma unroll
+      for (int m = 0; m <= NL; m++)
+        if (m == l && l <= L - 1) Ul = Rd[m] * E[m] * Dl;
     }
     sig[0][b] = (l <= L - 1) ? Ul : mk(0, 0);
     sig[1][b] = (l >= 1) ? Dl : mk(0, 0);
   }
+}
+
+__device__ __forceinline__ void dev_densities(const Stack& st, cd kr, int l, int lp, cd sig[2][2]) {
+  dev_densities_t<0>(st, kr, l, lp, sig);
 }
 
 // ---------------------------------------------------------------------------

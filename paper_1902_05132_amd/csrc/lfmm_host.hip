@@ -153,7 +153,7 @@ struct lfmm_plan_s {
   int max_depth, profile;
   double kmax;
   double* d_gaunt = nullptr;
-  EntryDesc* d_ent = nullptr;
+  TaskDesc* d_ent = nullptr;
   int nent = 0;
   std::map<std::string, DevBuf> bufs;
   std::vector<char> hbuf;
@@ -192,9 +192,9 @@ struct lfmm_plan_s {
     r.nnear = (int)std::lround(r.T0 / r.hn);
     double U = decay_length(npow, 40.0);
     double tfar = U / dz;
-    double hf = 4.0 / dz;
-    if (rho > 0.0) hf = std::min(hf, 3.5 / rho);
-    hf = std::min(hf, 4.0);
+    double hf = 8.0 / dz;
+    if (rho > 0.0) hf = std::min(hf, 7.0 / rho);
+    hf = std::min(hf, 8.0);
     r.nfar = std::max(1, (int)std::ceil(tfar / hf));
     r.hf = tfar / r.nfar;
     return r;
@@ -250,31 +250,32 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     std::vector<double> G = gaunt_table(p);
     HIPCHK(hipMalloc(&P->d_gaunt, G.size() * sizeof(double)));
     HIPCHK(hipMemcpy(P->d_gaunt, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
-    // canonical entries of the reaction integral matrices
-    std::vector<EntryDesc> ent;
-    for (int n = 0; n <= p; n++)
-      for (int m = 0; m <= n; m++)
-        for (int n2 = 0; n2 <= p; n2++)
-          for (int m2 = -n2; m2 <= n2; m2++) {
-            if (m == 0 && m2 < 0) continue;
-            EntryDesc E;
-            int q = m2 - m;
-            E.ia = (short)tix(n, m);
-            E.ib = (short)tix(n2, std::abs(m2));
-            E.iq = (short)std::abs(q);
-            int sg = 1;
-            if (m2 < 0 && (std::abs(m2) & 1)) sg = -sg;
-            if (q < 0 && (std::abs(q) & 1)) sg = -sg;
-            E.sg = (short)sg;
-            E.row = cidx(n, m);
-            E.col = cidx(n2, m2);
-            E.mrow = cidx(n, -m);
-            E.mcol = cidx(n2, -m2);
-            ent.push_back(E);
+    // 4 x 4 tiles of the reaction integral matrices over the half m > 0 or (m = 0, m' >= 0)
+    std::vector<TaskDesc> tasks;
+    for (int m = 0; m <= p; m++)
+      for (int mp = -p; mp <= p; mp++) {
+        if (m == 0 && mp < 0) continue;
+        int am = std::abs(mp), q = mp - m;
+        int sg = 1;
+        if (mp < 0 && (am & 1)) sg = -sg;
+        if (q < 0 && (std::abs(q) & 1)) sg = -sg;
+        for (int n0 = m; n0 <= p; n0 += 4)
+          for (int n0p = am; n0p <= p; n0p += 4) {
+            TaskDesc T;
+            T.m = (short)m;
+            T.mp = (short)mp;
+            T.n0 = (short)n0;
+            T.n0p = (short)n0p;
+            T.nr = (short)std::min(4, p + 1 - n0);
+            T.nc = (short)std::min(4, p + 1 - n0p);
+            T.iq = (short)std::abs(q);
+            T.sg = (short)sg;
+            tasks.push_back(T);
           }
-    P->nent = (int)ent.size();
-    HIPCHK(hipMalloc(&P->d_ent, ent.size() * sizeof(EntryDesc)));
-    HIPCHK(hipMemcpy(P->d_ent, ent.data(), ent.size() * sizeof(EntryDesc), hipMemcpyHostToDevice));
+      }
+    P->nent = (int)tasks.size();
+    HIPCHK(hipMalloc(&P->d_ent, tasks.size() * sizeof(TaskDesc)));
+    HIPCHK(hipMemcpy(P->d_ent, tasks.data(), tasks.size() * sizeof(TaskDesc), hipMemcpyHostToDevice));
     P->ev_ok = true;
     for (int i = 0; i <= ST_COUNT; i++)
       if (hipEventCreate(&P->ev[i]) != hipSuccess) P->ev_ok = false;
@@ -572,10 +573,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // reaction M2L classes and operators
   std::vector<ClassDesc> classes;
   std::vector<ROpDesc> rops;
-  // rop index: [tt][ts][l][j][i][dx+3][dy+3]
-  std::map<long long, int> rop_id;
+  // rop index: [tt][ts][l][j][i][dx+3][dy+3] (0 = the zero operator)
+  std::vector<int> rop_id((size_t)ntrees * ntrees * 9 * 2 * 2 * 49, 0);
   auto rkey = [&](int tt, int ts, int l, int j, int i, int dx, int dy) {
-    return ((((((long long)tt * 128 + ts) * 9 + l) * 2 + j) * 2 + i) * 7 + (dx + 3)) * 7 + (dy + 3);
+    return (((((size_t)tt * ntrees + ts) * 9 + l) * 2 + j) * 2 + i) * 49 + (size_t)(dx + 3) * 7 + (dy + 3);
   };
   const int r2vals[10] = {0, 1, 2, 4, 5, 8, 9, 10, 13, 18};
   int64_t nodes_total = 0;

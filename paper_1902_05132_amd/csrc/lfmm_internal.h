@@ -44,10 +44,10 @@ struct ROpDesc {
   int op;         // destination operator index
 };
 
-// Canonical entry of the reaction integral matrix (m >= 0 half, see k_react_I).
-struct EntryDesc {
-  short ia, ib, iq, sg;
-  int row, col, mrow, mcol;
+// 4 x 4 tile of the reaction integral matrix for fixed (m >= 0, m'): rows
+// n0..n0+nr-1, columns n0p..n0p+nc-1; iq = |m' - m|; sg = sign from negative orders.
+struct TaskDesc {
+  short m, mp, n0, n0p, nr, nc, iq, sg;
 };
 
 // Interaction template entry of a GEMM group.
@@ -102,7 +102,7 @@ void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const 
                double* py, double* pz, double* pq, hipStream_t s);
 void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS, const double* gaunt,
                 hipStream_t s);
-void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const EntryDesc* ent, int nent, double* Iout,
+void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks, int ntask, double* Iout,
                 int NC, hipStream_t s);
 void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p, int NC,
                      int NKS, hipStream_t s);

@@ -14,10 +14,29 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 __constant__ double c_glx[LFMM_NGL];
 __constant__ double c_glw[LFMM_NGL];
+// three-term recurrence coefficients of Phat_n^m (Section 2.2): a_n^m, b_n^m, and the
+// diagonal factors sqrt((2m+1)/(2m)); index n * 16 + m, n, m <= 15
+__constant__ double c_la[256];
+__constant__ double c_lb[256];
+__constant__ double c_ld[16];
 
 extern "C" void lk_set_gl(const double* x, const double* w) {
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_glx), x, sizeof(double) * LFMM_NGL);
   (void)hipMemcpyToSymbol(HIP_SYMBOL(c_glw), w, sizeof(double) * LFMM_NGL);
+  double la[256], lb[256], ld[16];
+  for (int n = 0; n < 16; n++) {
+    ld[n] = n > 0 ? sqrt((2.0 * n + 1.0) / (2.0 * n)) : 1.0;
+    for (int m = 0; m < 16; m++) {
+      double a = 0.0, b = 0.0;
+      if (n > m) a = sqrt((2.0 * n - 1.0) * (2.0 * n + 1.0) / ((double)(n - m) * (n + m)));
+      if (n > m + 1) b = sqrt((2.0 * n + 1.0) * (n - m - 1.0) * (n + m - 1.0) / ((2.0 * n - 3.0) * (n + m) * (double)(n - m)));
+      la[n * 16 + m] = a;
+      lb[n * 16 + m] = b;
+    }
+  }
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_la), la, sizeof(la));
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_lb), lb, sizeof(lb));
+  (void)hipMemcpyToSymbol(HIP_SYMBOL(c_ld), ld, sizeof(ld));
 }
 
 static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
@@ -248,26 +267,42 @@ __device__ __forceinline__ int run_end(const unsigned* keys, int s, int hi, int 
   return lo;
 }
 
-// occupancy[t*9 + l] = fullest cell of tree t at level l; slab flags of reaction trees
+// occupancy[t*9 + l] = fullest cell of tree t at level l; slab flags of reaction trees.
+// Run lengths are reduced over the wave before one atomic per wave (when the
+// whole wave lies in one tree) to avoid same-address atomic contention.
 __global__ void k_occupancy(int ntp, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab) {
   int s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= ntp) return;
-  unsigned key = skeys[s];
-  int t = key >> 24;
-  TreeInfo T = trees[t];
-  int hi = T.pt_off + T.npts;
+  bool valid = s < ntp;
+  unsigned key = valid ? skeys[s] : 0u;
+  int t = valid ? (int)(key >> 24) : -1;
+  int t0 = __shfl(t, 0);
+  bool same = __all(t == t0);
+  int lane = threadIdx.x & 63;
+  int hi = 0, pt0 = 0, kind = 0;
+  if (valid) {
+    TreeInfo T = trees[t];
+    hi = T.pt_off + T.npts;
+    pt0 = T.pt_off;
+    kind = T.kind;
+  }
   int ix, iy, iz;
   demorton3(key & 0xFFFFFFu, 8, &ix, &iy, &iz);
   for (int l = 0; l <= 8; l++) {
     int sh = 3 * (8 - l);
-    if (s == T.pt_off || (skeys[s - 1] >> sh) != (key >> sh)) {  // first point of its cell
-      int e = run_end(skeys, s, hi, sh);
-      atomicMax(&occ[t * 9 + l], e - s);
-      if (l >= 1 && T.kind != 0) {
+    int v = 0;
+    if (valid && (s == pt0 || (skeys[s - 1] >> sh) != (key >> sh))) {  // first point of its cell
+      v = run_end(skeys, s, hi, sh) - s;
+      if (l >= 1 && kind != 0) {
         int izl = iz >> (8 - l), half = 1 << (l - 1);
-        int hgt = (T.kind == 1) ? izl - half : half - 1 - izl;
+        int hgt = (kind == 1) ? izl - half : half - 1 - izl;
         if (hgt == 0 || hgt == 1) slab[(t * 9 + l) * 2 + hgt] = 1;
       }
+    }
+    if (same) {
+      for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+      if (lane == 0 && v > 0) atomicMax(&occ[t0 * 9 + l], v);
+    } else if (v > 0) {
+      atomicMax(&occ[t * 9 + l], v);
     }
   }
 }
@@ -415,13 +450,24 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
   OpDesc D = descs[blockIdx.x];
   int Q = 2 * p;
   double bb = sqrt(D.bx * D.bx + D.by * D.by + D.bz * D.bz);
+  __shared__ double jj[64];
   if (threadIdx.x == 0) {
+    double x = D.k * bb;
+    dev_sph_j(Q, x, jj);
     if (D.kind == 0) {
-      double jj[64];
-      dev_sph_j(Q, D.k * bb, jj);
       for (int q = 0; q <= Q; q++) zq[q] = mk(jj[q], 0);
     } else {
-      dev_sph_h(Q, D.k * bb, zq);
+      double sn, cs;
+      sincos(x, &sn, &cs);
+      double y0 = -cs / x, y1 = -cs / (x * x) - sn / x;
+      zq[0] = mk(jj[0], y0);
+      if (Q >= 1) zq[1] = mk(jj[1], y1);
+      for (int n = 1; n < Q; n++) {
+        double y2 = (2.0 * n + 1.0) / x * y1 - y0;
+        y0 = y1;
+        y1 = y2;
+        zq[n + 1] = mk(jj[n + 1], y1);
+      }
     }
   }
   int m = threadIdx.x;
@@ -493,81 +539,151 @@ extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz,
 //                      sigma^{ab}(k_rho)/kz_t Phat_n^m(kz_t/k_t) Phat_{n'}^{m'}(kz_s/k_s) dk_rho
 // Only the half m > 0 or (m = 0, m' >= 0) is integrated; the other half follows
 // from Phat_n^{-m} = (-1)^m Phat_n^m and J_{-q} = (-1)^q J_q.
-// One workgroup per class; nodes are generated CH at a time into LDS.
+// One workgroup per class.  Nodes are generated CH at a time into LDS, one wave
+// per quantity (weight x density x exponential; J_q; Phat at the target
+// wavenumber; Phat at the source wavenumber).  The contraction over nodes works
+// on 4 x 4 tiles of (n, n') for fixed (m, m') so every loaded value is reused.
 // ---------------------------------------------------------------------------
-template <int CH>
-__global__ __launch_bounds__(256) void k_react_I(const ClassDesc* cls, Stack st, int p, const EntryDesc* ent,
-                                                 int nent, double* Iout, int NC) {
+template <int CH, int TPT, int LL>
+__global__ __launch_bounds__(256) void k_react_I(const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks,
+                                                 int ntask, double* Iout, int NC) {
   extern __shared__ cd sh[];
   int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
-  cd* FJ = sh;                      // [CH][Q+1]
-  cd* PT = FJ + CH * (Q + 1);       // [CH][NT]
-  cd* PS = PT + CH * NT;            // [CH][NT]
+  cd* FJ = sh;                      // [CH][Q+1]  J_q(k_rho rho)
+  cd* PT = FJ + CH * (Q + 1);       // [CH][NT]   Phat(kz_t/k_t)
+  cd* PS = PT + CH * NT;            // [CH][NT]   Phat(kz_s/k_s)
+  cd* F = PS + CH * NT;             // [CH]       w k_rho e^{...} sigma / kz_t
   ClassDesc C = cls[blockIdx.x];
   double kt = st.k[C.lt], ks = st.k[C.ls];
   int nn = rule_nodes(C.rule);
-  const int MAXE = 32;
-  cd acc[MAXE];
-  int ne = (nent + 255) / 256;
-  for (int r = 0; r < MAXE; r++) acc[r] = mk(0, 0);
+  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  cd acc[TPT][16];
+  TaskDesc tk[TPT];
+  bool tv[TPT];
+#pragma unroll
+  for (int r = 0; r < TPT; r++) {
+    int t = threadIdx.x + 256 * r;
+    tv[r] = t < ntask;
+    tk[r] = tasks[tv[r] ? t : 0];
+#pragma unroll
+    for (int e = 0; e < 16; e++) acc[r][e] = mk(0, 0);
+  }
   for (int c0 = 0; c0 < nn; c0 += CH) {
-    int tid = threadIdx.x;
-    if (tid < CH) {
-      int node = c0 + tid;
-      if (node < nn) {
-        cd kr, w;
-        rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
-        cd kr2 = kr * kr;
-        cd kzt = csqrtd(mk(kt * kt, 0) - kr2), kzs = csqrtd(mk(ks * ks, 0) - kr2);
-        cd sig[2][2];
-        dev_densities(st, kr, C.lt, C.ls, sig);
-        cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
-        cd f = w * kr * ex * sig[C.a][C.b] / kzt;
-        dev_besselJ(Q, kr * C.rho, FJ + tid * (Q + 1), 1);
-        for (int q = 0; q <= Q; q++) FJ[tid * (Q + 1) + q] = f * FJ[tid * (Q + 1) + q];
-        dev_legendre_c(p, kzt / kt, kr / kt, PT + tid * NT, 1);
-        dev_legendre_c(p, kzs / ks, kr / ks, PS + tid * NT, 1);
+    if (lane < CH) {
+      int node = c0 + lane;
+      bool ok = node < nn;
+      cd kr = mk(0, 0), w = mk(0, 0);
+      if (ok) rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
+      cd kr2 = kr * kr;
+      if (wave == 0) {
+        cd f = mk(0, 0);
+        if (ok) {
+          cd kzt = csqrtd(mk(kt * kt, 0) - kr2), kzs = csqrtd(mk(ks * ks, 0) - kr2);
+          cd sig[2][2];
+          dev_densities_t<LL>(st, kr, C.lt, C.ls, sig);
+          cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
+          f = w * kr * ex * sig[C.a][C.b] / kzt;
+        }
+        F[lane] = f;
+      } else if (wave == 1) {
+        if (ok) dev_besselJ(Q, kr * C.rho, FJ + lane * (Q + 1), 1);
+        else
+          for (int q = 0; q <= Q; q++) FJ[lane * (Q + 1) + q] = mk(0, 0);
+      } else if (wave == 2) {
+        if (ok) {
+          cd kzt = csqrtd(mk(kt * kt, 0) - kr2);
+          dev_legendre_c(p, kzt / kt, kr / kt, PT + lane * NT, 1);
+        } else
+          for (int i = 0; i < NT; i++) PT[lane * NT + i] = mk(0, 0);
       } else {
-        for (int q = 0; q <= Q; q++) FJ[tid * (Q + 1) + q] = mk(0, 0);
-        for (int i = 0; i < NT; i++) { PT[tid * NT + i] = mk(0, 0); PS[tid * NT + i] = mk(0, 0); }
+        if (ok) {
+          cd kzs = csqrtd(mk(ks * ks, 0) - kr2);
+          dev_legendre_c(p, kzs / ks, kr / ks, PS + lane * NT, 1);
+        } else
+          for (int i = 0; i < NT; i++) PS[lane * NT + i] = mk(0, 0);
       }
     }
     __syncthreads();
-    for (int r = 0; r < ne && r < MAXE; r++) {
-      int e = threadIdx.x + 256 * r;
-      if (e >= nent) break;
-      EntryDesc E = ent[e];
-      cd a = acc[r];
-      for (int c = 0; c < CH; c++) a = a + (PT[c * NT + E.ia] * PS[c * NT + E.ib]) * FJ[c * (Q + 1) + E.iq];
-      acc[r] = a;
+#pragma unroll
+    for (int r = 0; r < TPT; r++) {
+      if (!tv[r]) continue;
+      TaskDesc T = tk[r];
+      int am = abs((int)T.mp);
+      int ia[4], ib[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) {
+        int n = min(T.n0 + i, p), n2 = min(T.n0p + i, p);
+        ia[i] = tix(n, T.m);
+        ib[i] = tix(n2 < am ? am : n2, am);
+      }
+      for (int c = 0; c < CH; c++) {
+        cd fj = F[c] * FJ[c * (Q + 1) + T.iq];
+        cd a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+          a[i] = PT[c * NT + ia[i]] * fj;
+          b[i] = PS[c * NT + ib[i]];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            cd& A = acc[r][i * 4 + j];
+            A.x += a[i].x * b[j].x - a[i].y * b[j].y;
+            A.y += a[i].x * b[j].y + a[i].y * b[j].x;
+          }
+      }
     }
     __syncthreads();
   }
   double* out = Iout + (size_t)C.out * NC * NC * 2;
-  for (int r = 0; r < ne && r < MAXE; r++) {
-    int e = threadIdx.x + 256 * r;
-    if (e >= nent) break;
-    EntryDesc E = ent[e];
-    cd v = (double)E.sg * acc[r];
-    out[2 * ((size_t)E.row * NC + E.col)] = v.x;
-    out[2 * ((size_t)E.row * NC + E.col) + 1] = v.y;
-    out[2 * ((size_t)E.mrow * NC + E.mcol)] = v.x;
-    out[2 * ((size_t)E.mrow * NC + E.mcol) + 1] = v.y;
+#pragma unroll
+  for (int r = 0; r < TPT; r++) {
+    if (!tv[r]) continue;
+    TaskDesc T = tk[r];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        if (i >= T.nr || j >= T.nc) continue;
+        int n = T.n0 + i, n2 = T.n0p + j;
+        cd v = (double)T.sg * acc[r][i * 4 + j];
+        size_t o1 = (size_t)cidx(n, T.m) * NC + cidx(n2, T.mp);
+        size_t o2 = (size_t)cidx(n, -T.m) * NC + cidx(n2, -T.mp);
+        out[2 * o1] = v.x;
+        out[2 * o1 + 1] = v.y;
+        out[2 * o2] = v.x;
+        out[2 * o2 + 1] = v.y;
+      }
   }
 }
-extern "C" void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const EntryDesc* ent, int nent,
+template <int CH, int TPT>
+static void launch_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks, int ntask,
+                           double* Iout, int NC, size_t lds, hipStream_t s) {
+#define RI_CASE(LLV)                                                                                        \
+  case LLV:                                                                                                 \
+    (void)hipFuncSetAttribute((const void*)k_react_I<CH, TPT, LLV>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                              (int)lds);                                                                    \
+    k_react_I<CH, TPT, LLV><<<ncls, 256, lds, s>>>(cls, st, p, tasks, ntask, Iout, NC);                      \
+    break;
+  switch (st.L) {
+    RI_CASE(1) RI_CASE(2) RI_CASE(3) RI_CASE(4)
+    default:
+      (void)hipFuncSetAttribute((const void*)k_react_I<CH, TPT, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+      k_react_I<CH, TPT, 0><<<ncls, 256, lds, s>>>(cls, st, p, tasks, ntask, Iout, NC);
+  }
+#undef RI_CASE
+}
+extern "C" void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks, int ntask,
                            double* Iout, int NC, hipStream_t s) {
   if (!ncls) return;
   int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
-  if (p <= 8) {
-    size_t lds = sizeof(cd) * 64 * (Q + 1 + 2 * NT);
-    (void)hipFuncSetAttribute((const void*)k_react_I<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_react_I<64><<<ncls, 256, lds, s>>>(cls, st, p, ent, nent, Iout, NC);
-  } else {
-    size_t lds = sizeof(cd) * 32 * (Q + 1 + 2 * NT);
-    (void)hipFuncSetAttribute((const void*)k_react_I<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    k_react_I<32><<<ncls, 256, lds, s>>>(cls, st, p, ent, nent, Iout, NC);
-  }
+  int tpt = (ntask + 255) / 256;
+  if (p <= 8 && tpt <= 2)
+    launch_react_I<64, 2>(ncls, cls, st, p, tasks, ntask, Iout, NC, sizeof(cd) * 64 * (Q + 2 + 2 * NT), s);
+  else
+    launch_react_I<32, 3>(ncls, cls, st, p, tasks, ntask, Iout, NC, sizeof(cd) * 32 * (Q + 2 + 2 * NT), s);
 }
 
 // T[(n,m),(n',m')] = (4 pi/k_t) i^n (-i)^{n'} i^q e^{i q phi} I[(n,m),(n',m')], q = m' - m,
@@ -618,13 +734,14 @@ __device__ __forceinline__ int seg_find(const int* prefix, int nseg, int x) {
   return lo;
 }
 
+template <int P>
 __global__ __launch_bounds__(256) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total,
                                              const int* box_start, const int* box_cnt, const int* box_code,
                                              const int* box_tree, const int* box_level, const TreeInfo* trees,
                                              const double* px, const double* py, const double* pz, const double* pq,
-                                             int p, int NCK, double* M) {
+                                             int NCK, double* M) {
   int gid = blockIdx.x * 256 + threadIdx.x;
-  int P1 = p + 1;
+  const int P1 = P + 1;
   if (gid >= total * P1) return;
   int li = gid / P1, m = gid % P1;
   int sgm = seg_find(seg_prefix, nseg, li);
@@ -632,48 +749,50 @@ __global__ __launch_bounds__(256) void k_p2m(int nseg, const int* seg_row0, cons
   TreeInfo T = trees[box_tree[R]];
   double c[3];
   box_center(T, (unsigned)box_code[R], box_level[R], c);
-  cd accp[24], accn[24];
-  for (int n = m; n <= p; n++) { accp[n - m] = mk(0, 0); accn[n - m] = mk(0, 0); }
+  cd accp[P1], accn[P1];
+#pragma unroll
+  for (int n = 0; n <= P; n++) { accp[n] = mk(0, 0); accn[n] = mk(0, 0); }
   int s0 = box_start[R], s1 = s0 + box_cnt[R];
   double cm = (m & 1) ? -1.0 : 1.0;
+#pragma unroll 1
   for (int s = s0; s < s1; s++) {
     double dx = px[s] - c[0], dy = py[s] - c[1], dz = pz[s] - c[2];
     double r = sqrt(dx * dx + dy * dy + dz * dz);
-    double jn[24];
-    dev_sph_j(p, T.k * r, jn);
+    double jn[P1];
+    dev_sph_j_t<P>(T.k * r, jn);
     double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? sqrt(dx * dx + dy * dy) / r : 0.0;
     double ph = atan2(dy, dx);
     double sn, cs;
     sincos(m * ph, &sn, &cs);
     cd q = mk(pq[2 * s], pq[2 * s + 1]);
     double pmm = 0.28209479177387814347;
-    for (int mm = 1; mm <= m; mm++) pmm *= sqrt((2.0 * mm + 1.0) / (2.0 * mm)) * st;
-    double p0 = pmm, p1 = 0.0;
-    for (int n = m; n <= p; n++) {
+    for (int mm = 1; mm <= m; mm++) pmm *= c_ld[mm] * st;
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int n = 0; n <= P; n++) {
+      if (n < m) continue;
       double val;
-      if (n == m) val = pmm;
-      else if (n == m + 1) { p1 = sqrt(2.0 * m + 3.0) * ct * pmm; val = p1; }
+      if (n == m) { val = pmm; p1 = pmm; }
       else {
-        double a = sqrt((2.0 * n - 1.0) * (2.0 * n + 1.0) / ((double)(n - m) * (n + m)));
-        double b = sqrt((2.0 * n + 1.0) * (n - m - 1.0) * (n + m - 1.0) / ((2.0 * n - 3.0) * (n + m) * (double)(n - m)));
-        double p2 = a * ct * p1 - b * p0;
+        val = c_la[n * 16 + m] * ct * p1 - c_lb[n * 16 + m] * p0;
         p0 = p1;
-        p1 = p2;
-        val = p2;
+        p1 = val;
       }
       double base = 4.0 * LFMM_PI * jn[n] * val;
       // conj(Y_n^m) = Phat e^{-i m phi};  conj(Y_n^{-m}) = (-1)^m Phat e^{+i m phi}
-      accp[n - m] = accp[n - m] + q * mk(base * cs, -base * sn);
-      if (m > 0) accn[n - m] = accn[n - m] + q * mk(cm * base * cs, cm * base * sn);
+      accp[n] = accp[n] + q * mk(base * cs, -base * sn);
+      accn[n] = accn[n] + q * mk(cm * base * cs, cm * base * sn);
     }
   }
   double* Mr = M + (size_t)R * NCK * 2;
-  for (int n = m; n <= p; n++) {
-    Mr[2 * cidx(n, m)] = accp[n - m].x;
-    Mr[2 * cidx(n, m) + 1] = accp[n - m].y;
+#pragma unroll
+  for (int n = 0; n <= P; n++) {
+    if (n < m) continue;
+    Mr[2 * cidx(n, m)] = accp[n].x;
+    Mr[2 * cidx(n, m) + 1] = accp[n].y;
     if (m > 0) {
-      Mr[2 * cidx(n, -m)] = accn[n - m].x;
-      Mr[2 * cidx(n, -m) + 1] = accn[n - m].y;
+      Mr[2 * cidx(n, -m)] = accn[n].x;
+      Mr[2 * cidx(n, -m) + 1] = accn[n].y;
     }
   }
 }
@@ -681,20 +800,27 @@ extern "C" void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int
                        const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
                        const TreeInfo* trees, const double* px, const double* py, const double* pz, const double* pq,
                        int p, int NCK, double* M, hipStream_t s) {
-  if (total)
-    k_p2m<<<nblk((size_t)total * (p + 1), 256), 256, 0, s>>>(nseg, seg_row0, seg_prefix, total, box_start, box_cnt,
-                                                            box_code, box_tree, box_level, trees, px, py, pz, pq, p,
-                                                            NCK, M);
+  if (!total) return;
+  int g = nblk((size_t)total * (p + 1), 256);
+#define P2M_CASE(PP)                                                                                          \
+  case PP:                                                                                                    \
+    k_p2m<PP><<<g, 256, 0, s>>>(nseg, seg_row0, seg_prefix, total, box_start, box_cnt, box_code, box_tree,    \
+                                box_level, trees, px, py, pz, pq, NCK, M);                                    \
+    break;
+  switch (p) { P2M_CASE(1) P2M_CASE(2) P2M_CASE(3) P2M_CASE(4) P2M_CASE(5) P2M_CASE(6) P2M_CASE(7) P2M_CASE(8)
+               P2M_CASE(9) P2M_CASE(10) default: break; }
+#undef P2M_CASE
 }
 
 // ---------------------------------------------------------------------------
 // L2P: phi += sum_nm L_nm j_n(k r) Y_n^m(r^) (eq. (freespace3dlocexp) / (lelayerimage)),
 // one thread per target point of the listed trees (sorted-position segments).
 // ---------------------------------------------------------------------------
+template <int P>
 __global__ __launch_bounds__(256) void k_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int total,
                                              const int* leafrow, const int* box_code, const int* box_tree,
                                              const int* box_level, const TreeInfo* trees, const double* px,
-                                             const double* py, const double* pz, const int* sg, int p, int NCK,
+                                             const double* py, const double* pz, const int* sg, int NCK,
                                              const double* Lc, double* phi_tp) {
   int gid = blockIdx.x * 256 + threadIdx.x;
   if (gid >= total) return;
@@ -706,30 +832,29 @@ __global__ __launch_bounds__(256) void k_l2p(int nseg, const int* seg_s0, const 
   box_center(T, (unsigned)box_code[R], box_level[R], c);
   double dx = px[s] - c[0], dy = py[s] - c[1], dz = pz[s] - c[2];
   double r = sqrt(dx * dx + dy * dy + dz * dz);
-  double jn[24];
-  dev_sph_j(p, T.k * r, jn);
+  double jn[P + 1];
+  dev_sph_j_t<P>(T.k * r, jn);
   double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? sqrt(dx * dx + dy * dy) / r : 0.0;
   double ph = atan2(dy, dx);
   const double* L = Lc + (size_t)R * NCK * 2;
   cd acc = mk(0, 0);
   double pmm = 0.28209479177387814347;
-  for (int m = 0; m <= p; m++) {
-    if (m > 0) pmm *= sqrt((2.0 * m + 1.0) / (2.0 * m)) * st;
+#pragma unroll 1
+  for (int m = 0; m <= P; m++) {
+    if (m > 0) pmm *= c_ld[m] * st;
     double sn, cs;
     sincos(m * ph, &sn, &cs);
     double cm = (m & 1) ? -1.0 : 1.0;
-    double p0 = pmm, p1 = 0.0;
-    for (int n = m; n <= p; n++) {
+    double p0 = 0.0, p1 = pmm;
+#pragma unroll
+    for (int n = 0; n <= P; n++) {
+      if (n < m) continue;
       double val;
       if (n == m) val = pmm;
-      else if (n == m + 1) { p1 = sqrt(2.0 * m + 3.0) * ct * pmm; val = p1; }
       else {
-        double a = sqrt((2.0 * n - 1.0) * (2.0 * n + 1.0) / ((double)(n - m) * (n + m)));
-        double b = sqrt((2.0 * n + 1.0) * (n - m - 1.0) * (n + m - 1.0) / ((2.0 * n - 3.0) * (n + m) * (double)(n - m)));
-        double p2 = a * ct * p1 - b * p0;
+        val = c_la[n * 16 + m] * ct * p1 - c_lb[n * 16 + m] * p0;
         p0 = p1;
-        p1 = p2;
-        val = p2;
+        p1 = val;
       }
       double base = jn[n] * val;
       cd Lp = mk(L[2 * cidx(n, m)], L[2 * cidx(n, m) + 1]);
@@ -748,9 +873,16 @@ extern "C" void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int t
                        const int* box_code, const int* box_tree, const int* box_level, const TreeInfo* trees,
                        const double* px, const double* py, const double* pz, const int* sg, int p, int NCK,
                        const double* Lc, double* phi_tp, hipStream_t s) {
-  if (total)
-    k_l2p<<<nblk(total, 256), 256, 0, s>>>(nseg, seg_s0, seg_prefix, total, leafrow, box_code, box_tree, box_level,
-                                           trees, px, py, pz, sg, p, NCK, Lc, phi_tp);
+  if (!total) return;
+  int g = nblk(total, 256);
+#define L2P_CASE(PP)                                                                                          \
+  case PP:                                                                                                    \
+    k_l2p<PP><<<g, 256, 0, s>>>(nseg, seg_s0, seg_prefix, total, leafrow, box_code, box_tree, box_level,      \
+                                trees, px, py, pz, sg, NCK, Lc, phi_tp);                                      \
+    break;
+  switch (p) { L2P_CASE(1) L2P_CASE(2) L2P_CASE(3) L2P_CASE(4) L2P_CASE(5) L2P_CASE(6) L2P_CASE(7) L2P_CASE(8)
+               L2P_CASE(9) L2P_CASE(10) default: break; }
+#undef L2P_CASE
 }
 
 // ---------------------------------------------------------------------------

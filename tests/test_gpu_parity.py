@@ -68,11 +68,16 @@ def test_reaction_operators_match_oracle(p):
     d, k = (0.0, -1.2), (0.8, 1.5, 2.0)
     P = lf.Plan(d, k, p=p, leaf_max=16)
     cases = [(0, 0, 1, 0, 0.55, -0.3, 0.4, 0.5), (1, 1, 2, 1, 0.0, 0.0, 0.3, 0.3), (2, 1, 0, 0, -1.1, 0.6, 0.15, 0.9),
-             (1, 0, 1, 1, 0.275, 0.55, 0.1375, 0.4125)]
+             (1, 0, 1, 1, 0.275, 0.55, 0.1375, 0.4125), (0, 0, 0, 0, 0.2, 0.0, 0.05, 0.05),
+             (2, 1, 2, 1, 0.6, -0.6, 0.1, 0.1), (1, 1, 0, 0, -0.35, 0.3, 0.2, 0.06)]
     for l, a, lp, b, dx, dy, zt, zs in cases:
         G = P.reaction_operator(l, a, lp, b, dx, dy, zt, zs)
         R = O.reaction_T(d, k, l, a, lp, b, dx, dy, zt, zs, p)
-        assert rel(G, R) < TOL_OP, (l, a, lp, b, rel(G, R))
+        # two correct quadratures of these oscillatory integrals differ by rounding of
+        # the order of eps times the sum of |terms| (plus a tiny relative floor)
+        mass = O.reaction_T_mass(d, k, l, a, lp, b, dx, dy, zt, zs, p)
+        bound = 64 * 2.2e-16 * mass + TOL_OP * np.max(np.abs(R))
+        assert np.all(np.abs(G - R) <= bound), (l, a, lp, b, rel(G, R), np.max(np.abs(G - R) / bound))
 
 
 def _check_fmm(w, p, leaf, tol=TOL_FMM):
