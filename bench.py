@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run one 512 MiB device copy (calibrates hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; multi-GPU runs are not part of it (got --gpus %d)"
@@ -122,6 +124,13 @@ def main():
            "config": {"workload": w["name"], "N": n, "p": args.p, "leaf": args.leaf, "layers": 3,
                       "interfaces": list(map(float, w["d"])), "k": list(map(float, w["k"]))},
            "stages_ms": stages, "roofline": roofline}
+    if args.copy_calib:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 2.0, out=dst)  # one elementwise kernel: reads 512 MiB, writes 512 MiB
+        torch.cuda.synchronize()
+        log("bench: streamed 512 MiB through one elementwise kernel for counter calibration")
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)

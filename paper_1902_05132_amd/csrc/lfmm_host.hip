@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -151,6 +152,7 @@ struct lfmm_plan_s {
   int p, leaf_max, NC, NCK, NRT, NKS, NT, opsz;
   double b, min_gap;
   int max_depth, profile;
+  int gemm_nct;  // MFMA column tiles (16 targets each) per wave in the batched GEMM
   double kmax;
   double* d_gaunt = nullptr;
   TaskDesc* d_ent = nullptr;
@@ -184,13 +186,21 @@ struct lfmm_plan_s {
     if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
     return d;
   }
+  mutable std::map<int, double> decay_memo;
+  double decay_cached(int npow) const {
+    auto it = decay_memo.find(npow);
+    if (it != decay_memo.end()) return it->second;
+    double U = decay_length(npow, 40.0);
+    decay_memo[npow] = U;
+    return U;
+  }
   Rule make_rule(double dz, double rho, int npow) const {
     Rule r;
     r.b = b;
     r.T0 = 0.5 * std::ceil(2.0 * (kmax + 2.0));
     r.hn = 0.5;
     r.nnear = (int)std::lround(r.T0 / r.hn);
-    double U = decay_length(npow, 40.0);
+    double U = decay_cached(npow);
     double tfar = U / dz;
     double hf = 8.0 / dz;
     if (rho > 0.0) hf = std::min(hf, 7.0 / rho);
@@ -232,6 +242,11 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
   P->NKS = P->NCK / 4;
   P->NT = (p + 1) * (p + 2) / 2;
   P->opsz = P->NRT * P->NKS * 128;
+  P->gemm_nct = 1;
+  if (const char* e = getenv("LFMM_GEMM_NCT")) {  // tile-shape override for tuning runs
+    int v = atoi(e);
+    if ((v == 1 || v == 2) && P->NRT <= 6) P->gemm_nct = v;
+  }
   P->b = 0.5;
   P->min_gap = 1e-9;
   P->max_depth = 8;
@@ -296,7 +311,7 @@ struct Group {
 // Build the GEMM block table of one job from its sorted group ids and counts.
 void build_blocks(const std::vector<int>& counts, const std::vector<Group>& groups, std::vector<GBlock>& blocks,
                   std::vector<int>& gstart, std::vector<int>& blk_first, std::vector<int>& blk_count,
-                  const std::vector<int>& group_level, int nlev) {
+                  const std::vector<int>& group_level, int nlev, int bsize) {
   int ng = (int)groups.size();
   gstart.assign(ng + 1, 0);
   for (int g = 0; g < ng; g++) gstart[g + 1] = gstart[g] + counts[g];
@@ -305,10 +320,10 @@ void build_blocks(const std::vector<int>& counts, const std::vector<Group>& grou
   blk_count.assign(nlev, 0);
   for (int g = 0; g < ng; g++) {
     int lv = group_level.empty() ? 0 : group_level[g];
-    for (int e = gstart[g]; e < gstart[g + 1]; e += 64) {
+    for (int e = gstart[g]; e < gstart[g + 1]; e += bsize) {
       GBlock b;
       b.e0 = e;
-      b.nt = std::min(64, gstart[g + 1] - e);
+      b.nt = std::min(bsize, gstart[g + 1] - e);
       b.seq0 = groups[g].seq0;
       b.K = groups[g].K;
       if (blk_first[lv] < 0) blk_first[lv] = (int)blocks.size();
@@ -777,9 +792,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   c_m2l.resize(ng_m2l);
   std::vector<GBlock> b_m2m, b_l2l, b_m2l;
   std::vector<int> gs_m2m, gs_l2l, gs_m2l, bf_m2m, bc_m2m, bf_l2l, bc_l2l, bf_m2l, bc_m2l;
-  build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9);
-  build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9);
-  build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1);
+  const int nct = P->gemm_nct, bsz = 64 * nct;
+  build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9, bsz);
+  build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9, bsz);
+  build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1, bsz);
   int ne_m2m = ng_m2m ? gs_m2m[ng_m2m] : 0, ne_l2l = ng_l2l ? gs_l2l[ng_l2l] : 0,
       ne_m2l = ng_m2l ? gs_m2l[ng_m2l] : 0;
   int64_t m2l_slots = 0;
@@ -839,18 +855,18 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   mark(6);
   for (int lp = Dmax - 1; lp >= 2; lp--)
     if (bc_m2m[lp] > 0)
-      lk_gemm(P->NRT, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M, NCK,
+      lk_gemm(P->NRT, nct, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M, NCK,
               NC, s);
   mark(7);
   // ---------------- M2L (every level, free and reaction)
   if (!b_m2l.empty())
-    lk_gemm(P->NRT, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M, Lx, NCK,
+    lk_gemm(P->NRT, nct, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M, Lx, NCK,
             NC, s);
   mark(8);
   // ---------------- downward pass
   for (int l = 3; l <= Dmax; l++)
     if (bc_l2l[l] > 0)
-      lk_gemm(P->NRT, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx, NCK,
+      lk_gemm(P->NRT, nct, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx, NCK,
               NC, s);
   mark(9);
   double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
@@ -1048,9 +1064,9 @@ const char* lfmm_status_string(int status) {
 static void unpack_op(const std::vector<double>& pk, int NC, int NKS, double* out) {
   for (int r = 0; r < NC; r++)
     for (int c = 0; c < NC; c++) {
-      size_t pp = ((size_t)((r >> 4) * NKS + (c >> 2)) << 7) + (size_t)((r & 15) | ((c & 3) << 4));
+      size_t pp = ((size_t)((r >> 4) * NKS + (c >> 2)) << 7) + 2 * (size_t)((r & 15) | ((c & 3) << 4));
       out[2 * ((size_t)r * NC + c)] = pk[pp];
-      out[2 * ((size_t)r * NC + c) + 1] = pk[pp + 64];
+      out[2 * ((size_t)r * NC + c) + 1] = pk[pp + 1];
     }
 }
 

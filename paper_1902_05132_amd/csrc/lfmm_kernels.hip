@@ -425,12 +425,12 @@ extern "C" void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntr
 
 // ---------------------------------------------------------------------------
 // Operator layout for the MFMA GEMM: an (NRT*16) x (NKS*4) complex matrix is
-// stored as tiles of 16 rows x 4 columns; tile (rt, ks) holds 64 real parts in
-// MFMA A-operand lane order (lane = row%16 + 16*(col%4)) followed by 64
-// imaginary parts.  Padding rows/columns are zero.
+// stored as tiles of 16 rows x 4 columns; tile (rt, ks) holds 64 (re, im) pairs
+// in MFMA A-operand lane order (lane = row%16 + 16*(col%4)), so each lane loads
+// its operand with one 128-bit load.  Padding rows/columns are zero.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ size_t packed_pos(int row, int col, int NKS) {
-  return ((size_t)((row >> 4) * NKS + (col >> 2)) << 7) + (size_t)((row & 15) | ((col & 3) << 4));
+  return ((size_t)((row >> 4) * NKS + (col >> 2)) << 7) + 2 * (size_t)((row & 15) | ((col & 3) << 4));
 }
 __device__ __forceinline__ void decode_nm(int r, int* n, int* m) {
   int nn = (int)floor(sqrt((double)r) + 1e-9);
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
     }
     size_t pp = packed_pos(row, col, NKS);
     out[pp] = val.x;
-    out[pp + 64] = val.y;
+    out[pp + 1] = val.y;
   }
 }
 extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
@@ -711,7 +711,7 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
     }
     size_t pp = packed_pos(row, col, NKS);
     out[pp] = val.x;
-    out[pp + 64] = val.y;
+    out[pp + 1] = val.y;
   }
 }
 extern "C" void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p,
@@ -894,69 +894,108 @@ extern "C" void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int t
 // f64 16x16x4 lane layout: A lane l = (row l%16, k l/16); B lane l = (k l/16,
 // col l%16); D lane l element r = (row l/16 + 4r, col l%16).
 // ---------------------------------------------------------------------------
-template <int NRT>
+template <int NRT, int NCT>
 __global__ __launch_bounds__(256) void k_gemm(const GBlock* blocks, const int* seq, const int* trow, const int* srow,
                                               int srow_stride, const double* __restrict__ ops, int opsz, int NKS,
                                               const double2* __restrict__ S, double2* D, int NCK, int NC) {
+  // each wave owns NCT column tiles of 16 targets and all NRT row tiles
   GBlock bd = blocks[blockIdx.x];
   int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int col = lane & 15, kr = lane >> 4;
-  int t = wave * 16 + col;
-  bool tvalid = t < bd.nt;
-  int e = bd.e0 + t;
-  const int* mys = srow + (size_t)e * srow_stride;
-  v4d accr[NRT], acci[NRT];
-  for (int i = 0; i < NRT; i++) {
-    accr[i] = (v4d){0, 0, 0, 0};
-    acci[i] = (v4d){0, 0, 0, 0};
+  int tt[NCT], ee[NCT];
+  bool tv[NCT];
+#pragma unroll
+  for (int c = 0; c < NCT; c++) {
+    tt[c] = (wave * NCT + c) * 16 + col;
+    tv[c] = tt[c] < bd.nt;
+    ee[c] = bd.e0 + tt[c];
   }
+  v4d accr[NCT][NRT], acci[NCT][NRT];
+#pragma unroll
+  for (int c = 0; c < NCT; c++)
+#pragma unroll
+    for (int i = 0; i < NRT; i++) {
+      accr[c][i] = (v4d){0, 0, 0, 0};
+      acci[c][i] = (v4d){0, 0, 0, 0};
+    }
+  const double2* A2 = (const double2*)ops;
   for (int kk = 0; kk < bd.K; kk++) {
-    int sr = tvalid ? mys[kk] : -1;
-    if (__ballot(sr >= 0) == 0) continue;
+    int sr[NCT];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < NCT; c++) {
+      sr[c] = tv[c] ? srow[(size_t)ee[c] * srow_stride + kk] : -1;
+      any = any || (sr[c] >= 0);
+    }
+    if (__ballot(any) == 0) continue;
     int op = seq[bd.seq0 + kk];
-    const double* A = ops + (size_t)op * opsz;
-    const double2* B = S + (size_t)(sr >= 0 ? sr : 0) * NCK;
+    const double2* A = A2 + (size_t)op * (opsz >> 1);
+    const double2* B[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; c++) B[c] = S + (size_t)(sr[c] >= 0 ? sr[c] : 0) * NCK + kr;
+    // software pipeline: operands of step ks+1 are loaded while step ks runs
+    double2 a_cur[NRT], b_cur[NCT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; rt++) a_cur[rt] = A[((size_t)(rt * NKS) << 6) + lane];
+#pragma unroll
+    for (int c = 0; c < NCT; c++) b_cur[c] = (sr[c] >= 0) ? B[c][0] : make_double2(0.0, 0.0);
     for (int ks = 0; ks < NKS; ks++) {
-      double2 bv = (sr >= 0) ? B[ks * 4 + kr] : make_double2(0.0, 0.0);
+      double2 a_nxt[NRT], b_nxt[NCT];
+      int kn = (ks + 1 < NKS) ? ks + 1 : ks;
+#pragma unroll
+      for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS + kn) << 6) + lane];
+#pragma unroll
+      for (int c = 0; c < NCT; c++) b_nxt[c] = (sr[c] >= 0) ? B[c][kn * 4] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int rt = 0; rt < NRT; rt++) {
-        const double* Ap = A + ((size_t)(rt * NKS + ks) << 7);
-        double are = Ap[lane], aim = Ap[64 + lane];
-        accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bv.x, accr[rt], 0, 0, 0);
-        accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-aim, bv.y, accr[rt], 0, 0, 0);
-        acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bv.y, acci[rt], 0, 0, 0);
-        acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bv.x, acci[rt], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < NCT; c++) {
+          accr[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur[c].x, accr[c][rt], 0, 0, 0);
+          acci[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur[c].y, acci[c][rt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int c = 0; c < NCT; c++) {
+          accr[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_cur[rt].y, b_cur[c].y, accr[c][rt], 0, 0, 0);
+          acci[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].y, b_cur[c].x, acci[c][rt], 0, 0, 0);
+        }
       }
+#pragma unroll
+      for (int rt = 0; rt < NRT; rt++) a_cur[rt] = a_nxt[rt];
+#pragma unroll
+      for (int c = 0; c < NCT; c++) b_cur[c] = b_nxt[c];
     }
   }
-  if (!tvalid) return;
-  double2* Dr = D + (size_t)trow[e] * NCK;
 #pragma unroll
-  for (int rt = 0; rt < NRT; rt++)
+  for (int c = 0; c < NCT; c++) {
+    if (!tv[c]) continue;
+    double2* Dr = D + (size_t)trow[ee[c]] * NCK;
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      int row = rt * 16 + kr + 4 * r;
-      if (row < NC) {
-        double2 v = Dr[row];
-        v.x += accr[rt][r];
-        v.y += acci[rt][r];
-        Dr[row] = v;
+    for (int rt = 0; rt < NRT; rt++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        int row = rt * 16 + kr + 4 * r;
+        if (row < NC) {
+          double2 v = Dr[row];
+          v.x += accr[c][rt][r];
+          v.y += acci[c][rt][r];
+          Dr[row] = v;
+        }
       }
-    }
+  }
 }
-extern "C" void lk_gemm(int nrt, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
-                        int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D, int NCK,
-                        int NC, hipStream_t s) {
+extern "C" void lk_gemm(int nrt, int nct, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+                        const int* srow, int srow_stride, const double* ops, int opsz, int NKS, const double* S,
+                        double* D, int NCK, int NC, hipStream_t s) {
   if (!nblocks) return;
   const double2* S2 = (const double2*)S;
   double2* D2 = (double2*)D;
-#define GEMM_CASE(N) \
-  case N: k_gemm<N><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, NC); break;
-  switch (nrt) {
-    GEMM_CASE(1) GEMM_CASE(2) GEMM_CASE(3) GEMM_CASE(4) GEMM_CASE(5) GEMM_CASE(6) GEMM_CASE(7) GEMM_CASE(8)
-    GEMM_CASE(9) GEMM_CASE(10)
-    default: break;
+#define GEMM_CASE(N, C)                                                                                         \
+  if (nrt == N && nct == C) {                                                                                   \
+    k_gemm<N, C><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, NC); \
+    return;                                                                                                     \
   }
+  GEMM_CASE(1, 1) GEMM_CASE(2, 1) GEMM_CASE(3, 1) GEMM_CASE(4, 1) GEMM_CASE(5, 1) GEMM_CASE(6, 1) GEMM_CASE(7, 1)
+  GEMM_CASE(8, 1) GEMM_CASE(1, 2) GEMM_CASE(2, 2) GEMM_CASE(3, 2) GEMM_CASE(4, 2) GEMM_CASE(5, 2) GEMM_CASE(6, 2)
 #undef GEMM_CASE
 }
 
