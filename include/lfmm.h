@@ -66,7 +66,7 @@ typedef struct {
   int64_t m2l_slots;       /* M2L products issued to the GEMM (including absent sources) */
   int64_t m2m_pairs;       /* (parent, child) M2M products */
   int64_t l2l_pairs;       /* (child, parent) L2L products */
-  int64_t p2p_pairs_bound; /* upper bound of free-space near-field pairs */
+  int64_t p2p_pairs;       /* free-space near-field (target, source) pairs evaluated */
   int64_t nf_react_pairs;  /* near-field reaction pairs */
   double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
 } lfmm_report;

@@ -153,6 +153,8 @@ struct lfmm_plan_s {
   double b, min_gap;
   int max_depth, profile;
   int gemm_nct;  // MFMA column tiles (16 targets each) per wave in the batched GEMM
+  int p2p_ta;    // near field: targets per wave step (64 / p2p_ta sources)
+  int p2p_ch;    // near field: sources per LDS tile
   double kmax;
   double* d_gaunt = nullptr;
   TaskDesc* d_ent = nullptr;
@@ -243,6 +245,10 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
   P->NT = (p + 1) * (p + 2) / 2;
   P->opsz = P->NRT * P->NKS * 128;
   P->gemm_nct = 1;
+  P->p2p_ta = 8;
+  P->p2p_ch = 256;
+  if (const char* e = getenv("LFMM_P2P_TA")) P->p2p_ta = atoi(e);  // tile-shape overrides for tuning runs
+  if (const char* e = getenv("LFMM_P2P_CH")) P->p2p_ch = atoi(e);
   if (const char* e = getenv("LFMM_GEMM_NCT")) {  // tile-shape override for tuning runs
     int v = atoi(e);
     if ((v == 1 || v == 2) && P->NRT <= 6) P->gemm_nct = v;
@@ -894,21 +900,22 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   {
     std::vector<int> r0, pf;
     int tot = 0;
-    int64_t pairs = 0;
+    double krmax = 0.0;  // bound on k r over adjacent leaves: the diagonal of two boxes side by side
     for (int t = 0; t < ntrees; t++) {
       const TreeInfo& T = trees[t];
       if (T.kind != 0) continue;
       r0.push_back(first_row(t, T.depth));
       pf.push_back(tot);
       tot += nbox(t, T.depth);
-      pairs += (int64_t)T.npts * std::min<int64_t>(T.npts, 27LL * hocc[t * 9 + T.depth]);
+      double h = T.S / (double)(1 << T.depth);
+      krmax = std::max(krmax, T.k * 2.0 * h * std::sqrt(3.0));
     }
-    rep.p2p_pairs_bound = pairs;
     if (tot) {
       int* d_r0 = P->upload("p2p_r0", r0, s);
       int* d_pf = P->upload("p2p_pf", pf, s);
       lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
-                  d_lvl_off, d_grid_off, 9, grid, px, py, pz, pq, sg, phi_tp, s);
+                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, krmax <= 1.0 ? 1 : 0, P->p2p_ta, P->p2p_ch,
+                  d_cnt + 3, s);
     }
   }
   mark(11);
@@ -977,6 +984,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.m2l_pairs = (int64_t)hcnt[0];
   rep.m2m_pairs = (int64_t)hcnt[1];
   rep.l2l_pairs = (int64_t)hcnt[2];
+  rep.p2p_pairs = (int64_t)hcnt[3];
   if (prof) {
     // stage i spans events i+1 .. i+2 of the marks above (classify = 0..1)
     int map_ev[ST_COUNT][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7},

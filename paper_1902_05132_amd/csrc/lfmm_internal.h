@@ -129,9 +129,9 @@ void lk_src_l2l(int nent, const int* trow, const int* box_code, const int* box_t
                 hipStream_t s);
 void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
                  const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
-                 const TreeInfo* trees, const int* lvl_off, const long long* grid_off, int nlev1, const int* grid,
-                 const double* px, const double* py, const double* pz, const double* pq, const int* sg,
-                 double* phi_tp, hipStream_t s);
+                 const TreeInfo* trees, const long long* grid_off, const int* grid, const double* px,
+                 const double* py, const double* pz, const double* pq, const int* sg, double* phi_tp, int poly,
+                 int ta, int ch, unsigned long long* npairs, hipStream_t s);
 void lk_nf_nodes(int nnodes, Rule rule, Stack st, int lt, int ls, int a, int b, double* nkr, double* nfac,
                  double* nkzt, double* nkzs, hipStream_t s);
 void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps, const int* box_start,

@@ -1125,89 +1125,199 @@ extern "C" void lk_src_l2l(int nent, const int* trow, const int* box_code, const
 
 // ---------------------------------------------------------------------------
 // Free-space near field: phi_i += sum_{j in adjacent leaves, j != i} Q_j h0(k r_ij),
-// h0(x) = e^{ix}/(ix) (eq. (totalinteraction)).  One workgroup per target leaf;
-// threads split as (target, stripe of sources), stripes reduced through LDS.
+// h0(x) = e^{ix}/(ix) = sin(x)/x - i cos(x)/x (eq. (totalinteraction)).
+// One workgroup per target leaf.  The targets of the leaf and tiles of the
+// sources of its 27 neighbour leaves are staged in LDS (SoA).  A wave works on
+// TA targets x (64/TA) sources per step (lane = target row a, source column b),
+// so a leaf of any size keeps nearly every lane busy; the partial sums of the
+// 64/TA source columns are combined by a butterfly over lanes, and each wave owns
+// whole target blocks, so the sums are formed in a fixed order.
+// When k r <= 1 holds for every pair the kernel can meet (host-checked bound),
+// sin(x)/x and cos(x) are evaluated as their Taylor series in u = x^2 (ten
+// terms each: truncation below 1e-18 relative on u <= 1), and 1/r comes from the
+// hardware reciprocal square root refined by two Newton steps, so a pair costs
+// no division, no square root and no argument reduction.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix,
+__device__ constexpr double inv_fact(int n) { return n <= 1 ? 1.0 : inv_fact(n - 1) / (double)n; }
+__device__ __forceinline__ double rsqrt_nr(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  double hh = 0.5 * r2;
+  y = y * fma(-hh, y * y, 1.5);
+  y = y * fma(-hh, y * y, 1.5);
+  return y;
+}
+// h0(k r) for r^2 = r2 > 0 (hr + i hi); k2 = k^2, invk = 1/k
+template <bool POLY>
+__device__ __forceinline__ void h0_pair(double r2, double k, double k2, double invk, double& hr, double& hi) {
+  double y = rsqrt_nr(r2);
+  if (POLY) {
+    constexpr double s1 = inv_fact(3), s2 = inv_fact(5), s3 = inv_fact(7), s4 = inv_fact(9), s5 = inv_fact(11),
+                     s6 = inv_fact(13), s7 = inv_fact(15), s8 = inv_fact(17), s9 = inv_fact(19);
+    constexpr double c1 = inv_fact(2), c2 = inv_fact(4), c3 = inv_fact(6), c4 = inv_fact(8), c5 = inv_fact(10),
+                     c6 = inv_fact(12), c7 = inv_fact(14), c8 = inv_fact(16), c9 = inv_fact(18), c10 = inv_fact(20);
+    double v = -k2 * r2;  // -(kr)^2
+    double ps = fma(s9, v, s8);
+    ps = fma(ps, v, s7);
+    ps = fma(ps, v, s6);
+    ps = fma(ps, v, s5);
+    ps = fma(ps, v, s4);
+    ps = fma(ps, v, s3);
+    ps = fma(ps, v, s2);
+    ps = fma(ps, v, s1);
+    ps = fma(ps, v, 1.0);
+    double pc = fma(c10, v, c9);
+    pc = fma(pc, v, c8);
+    pc = fma(pc, v, c7);
+    pc = fma(pc, v, c6);
+    pc = fma(pc, v, c5);
+    pc = fma(pc, v, c4);
+    pc = fma(pc, v, c3);
+    pc = fma(pc, v, c2);
+    pc = fma(pc, v, c1);
+    pc = fma(pc, v, 1.0);
+    hr = ps;                // sin(kr)/(kr)
+    hi = -pc * (y * invk);  // -cos(kr)/(kr)
+  } else {
+    double kr = k * (r2 * y);
+    double sn, cs;
+    sincos(kr, &sn, &cs);
+    double ikr = y * invk;
+    hr = sn * ikr;
+    hi = -cs * ikr;
+  }
+}
+#define P2P_TMAX 256
+template <bool POLY, int TA, int CH>
+__global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix,
                                                   const int* box_start, const int* box_cnt, const int* box_code,
                                                   const int* box_tree, const int* box_level, const TreeInfo* trees,
                                                   const long long* grid_off, const int* grid, const double* px,
                                                   const double* py, const double* pz, const double* pq, const int* sg,
-                                                  double* phi_tp) {
-  __shared__ double red[2][256];
+                                                  double* phi_tp, unsigned long long* npairs) {
+  constexpr int TB = 64 / TA;
+  __shared__ double s_x[CH], s_y[CH], s_z[CH], s_qr[CH], s_qi[CH];
+  __shared__ double t_x[P2P_TMAX], t_y[P2P_TMAX], t_z[P2P_TMAX], acc_r[P2P_TMAX], acc_i[P2P_TMAX];
+  __shared__ int nb_start[27], nb_pre[28];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int a = lane / TB, b = lane % TB;
   int li = blockIdx.x;
   int sgm = seg_find(seg_prefix, nseg, li);
   int R = seg_row0[sgm] + (li - seg_prefix[sgm]);
   int t = box_tree[R], l = box_level[R];
-  double k = trees[t].k;
+  const double k = trees[t].k;
   int ix, iy, iz;
   demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
-  int s0 = box_start[R], nt = box_cnt[R];
-  // neighbour leaves
-  __shared__ int nb_start[27], nb_cnt[27];
-  if (threadIdx.x < 27) {
-    int dx = threadIdx.x / 9 - 1, dy = (threadIdx.x / 3) % 3 - 1, dz = threadIdx.x % 3 - 1;
+  const int s0 = box_start[R], nt = box_cnt[R];
+  if (tid < 27) {
+    int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
     int Rn = grid_get(grid_off, grid, t, l, ix + dx, iy + dy, iz + dz);
-    nb_start[threadIdx.x] = Rn >= 0 ? box_start[Rn] : 0;
-    nb_cnt[threadIdx.x] = Rn >= 0 ? box_cnt[Rn] : 0;
+    nb_start[tid] = Rn >= 0 ? box_start[Rn] : 0;
+    nb_pre[tid + 1] = Rn >= 0 ? box_cnt[Rn] : 0;
   }
   __syncthreads();
-  for (int c0 = 0; c0 < nt; c0 += 256) {
-    int ntc = nt - c0 < 256 ? nt - c0 : 256;
-    int T = 1;
-    while (T < ntc) T <<= 1;
-    int NS = 256 / T;
-    int ti = threadIdx.x % T, stripe = threadIdx.x / T;
-    double accx = 0, accy = 0;
-    if (ti < ntc) {
-      int st = s0 + c0 + ti;
-      double x0 = px[st], y0 = py[st], z0 = pz[st];
-      for (int nbi = 0; nbi < 27; nbi++) {
-        int a = nb_start[nbi], cnt = nb_cnt[nbi];
-        for (int j = stripe; j < cnt; j += NS) {
-          int ss = a + j;
-          if (ss == st) continue;
-          double dx = x0 - px[ss], dy = y0 - py[ss], dz = z0 - pz[ss];
-          double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 == 0.0) continue;
-          double r = sqrt(r2);
-          double kr = k * r;
-          double sn, cs;
-          sincos(kr, &sn, &cs);
-          double inv = 1.0 / kr;
-          // h0 = (sin kr - i cos kr)/kr
-          double hr = sn * inv, hi = -cs * inv;
-          double qr = pq[2 * ss], qi = pq[2 * ss + 1];
-          accx += qr * hr - qi * hi;
-          accy += qr * hi + qi * hr;
+  if (tid == 0) {
+    nb_pre[0] = 0;
+    for (int i = 1; i <= 27; i++) nb_pre[i] += nb_pre[i - 1];
+    if (nt) atomicAdd(npairs, (unsigned long long)nt * (unsigned long long)(nb_pre[27] - 1));
+  }
+  __syncthreads();
+  const int total = nb_pre[27];
+  const double k2 = k * k, invk = 1.0 / k;
+  for (int c0 = 0; c0 < nt; c0 += P2P_TMAX) {
+    const int ntp = nt - c0 < P2P_TMAX ? nt - c0 : P2P_TMAX;
+    const int ntb = (ntp + TA - 1) / TA;
+    if (tid < ntp) {
+      t_x[tid] = px[s0 + c0 + tid];
+      t_y[tid] = py[s0 + c0 + tid];
+      t_z[tid] = pz[s0 + c0 + tid];
+      acc_r[tid] = 0.0;
+      acc_i[tid] = 0.0;
+    }
+    for (int base = 0; base < total; base += CH) {
+      const int nch = total - base < CH ? total - base : CH;
+      __syncthreads();
+      for (int f = tid; f < nch; f += 256) {
+        int g = base + f;
+        int lo = 0, hi = 26;  // last neighbour whose prefix is <= g
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (nb_pre[mid] <= g) lo = mid;
+          else hi = mid - 1;
+        }
+        int ss = nb_start[lo] + (g - nb_pre[lo]);
+        s_x[f] = px[ss];
+        s_y[f] = py[ss];
+        s_z[f] = pz[ss];
+        s_qr[f] = pq[2 * ss];
+        s_qi[f] = pq[2 * ss + 1];
+      }
+      __syncthreads();
+      for (int tb = wave; tb < ntb; tb += 4) {
+        const int ti = tb * TA + a;
+        const bool tv = ti < ntp;
+        const int tr = tv ? ti : 0;
+        const double x0 = t_x[tr], y0 = t_y[tr], z0 = t_z[tr];
+        double ax = 0.0, ay = 0.0;
+#pragma unroll 2
+        for (int j = b; j < nch; j += TB) {
+          double dx = x0 - s_x[j], dy = y0 - s_y[j], dz = z0 - s_z[j];
+          double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          bool ok = r2 > 0.0;  // the target itself (and coincident points) contribute nothing
+          double hr, hi;
+          h0_pair<POLY>(ok ? r2 : 1.0, k, k2, invk, hr, hi);
+          hr = ok ? hr : 0.0;
+          hi = ok ? hi : 0.0;
+          double qr = s_qr[j], qi = s_qi[j];
+          ax = fma(qr, hr, fma(-qi, hi, ax));
+          ay = fma(qr, hi, fma(qi, hr, ay));
+        }
+#pragma unroll
+        for (int m = TB / 2; m >= 1; m >>= 1) {
+          ax += __shfl_xor(ax, m, 64);
+          ay += __shfl_xor(ay, m, 64);
+        }
+        if (b == 0 && tv) {
+          acc_r[ti] += ax;
+          acc_i[ti] += ay;
         }
       }
     }
-    red[0][threadIdx.x] = accx;
-    red[1][threadIdx.x] = accy;
     __syncthreads();
-    if (threadIdx.x < ntc) {
-      double sx = 0, sy = 0;
-      for (int k2 = 0; k2 < NS; k2++) {
-        sx += red[0][threadIdx.x + k2 * T];
-        sy += red[1][threadIdx.x + k2 * T];
-      }
-      int g = sg[s0 + c0 + threadIdx.x];
-      phi_tp[2 * g] += sx;
-      phi_tp[2 * g + 1] += sy;
+    if (tid < ntp) {
+      int g = sg[s0 + c0 + tid];
+      phi_tp[2 * g] += acc_r[tid];
+      phi_tp[2 * g + 1] += acc_i[tid];
     }
     __syncthreads();
   }
 }
 extern "C" void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
                             const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
-                            const TreeInfo* trees, const int* lvl_off, const long long* grid_off, int nlev1,
-                            const int* grid, const double* px, const double* py, const double* pz, const double* pq,
-                            const int* sg, double* phi_tp, hipStream_t s) {
-  (void)lvl_off; (void)nlev1;
-  if (total)
-    k_p2p_free<<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code, box_tree, box_level,
-                                     trees, grid_off, grid, px, py, pz, pq, sg, phi_tp);
+                            const TreeInfo* trees, const long long* grid_off, const int* grid, const double* px,
+                            const double* py, const double* pz, const double* pq, const int* sg, double* phi_tp,
+                            int poly, int ta, int ch, unsigned long long* npairs, hipStream_t s) {
+  if (!total) return;
+#define P2P_CASE(PO, T, C)                                                                                      \
+  if ((poly != 0) == PO && ta == T && ch == C) {                                                                \
+    k_p2p_free<PO, T, C><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,        \
+                                              box_tree, box_level, trees, grid_off, grid, px, py, pz, pq, sg,   \
+                                              phi_tp, npairs);                                                  \
+    return;                                                                                                     \
+  }
+  P2P_CASE(true, 4, 128) P2P_CASE(true, 8, 128) P2P_CASE(true, 16, 128)
+  P2P_CASE(true, 4, 256) P2P_CASE(true, 8, 256) P2P_CASE(true, 16, 256)
+  P2P_CASE(true, 4, 512) P2P_CASE(true, 8, 512) P2P_CASE(true, 16, 512)
+  P2P_CASE(false, 4, 256) P2P_CASE(false, 8, 256) P2P_CASE(false, 16, 256)
+#undef P2P_CASE
+  // any other request falls back to the general-purpose shape
+  if (poly)
+    k_p2p_free<true, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
+                                                   box_tree, box_level, trees, grid_off, grid, px, py, pz, pq, sg,
+                                                   phi_tp, npairs);
+  else
+    k_p2p_free<false, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
+                                                    box_tree, box_level, trees, grid_off, grid, px, py, pz, pq, sg,
+                                                    phi_tp, npairs);
 }
 
 // ---------------------------------------------------------------------------

@@ -113,3 +113,95 @@ def test_fmm_config1_full():
     tg = np.arange(0, len(w["x"]), 97)
     ex = O.direct(w["d"], w["k"], w["x"], w["y"], w["z"], w["layer"], w["q"], tg)
     assert np.linalg.norm(phi[tg] - ex) / np.linalg.norm(ex) < 1e-3
+
+
+def _cube(n, side, centre, seed):
+    rng = np.random.default_rng(seed)
+    pts = centre + side * (rng.random((n, 3)) - 0.5)
+    q = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    return pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(), q
+
+
+@pytest.mark.parametrize("side,k", [(0.1, 2.0), (1.0, 2.0), (0.05, 9.0)])
+def test_near_field_only_free_space(side, k):
+    """One medium, every particle in one leaf: the result is the plain pair sum.
+    Side 0.1 with k = 2 bounds k r by 2 k side sqrt(3) = 0.69 <= 1 and takes the
+    series path for sin(x)/x and cos(x); side 1 with k = 2 (6.9) and side 0.05
+    with k = 9 (1.56) exceed the bound and take the library sincos path."""
+    lf = _lfmm()
+    x, y, z, q = _cube(700, side, np.array([0.2, -0.1, 0.3]), seed=21)
+    P = lf.Plan((), (k,), p=4, leaf_max=1000)
+    phi = P.eval_torch(x, y, z, q)
+    rep = P.report()
+    assert rep["free_depth"][0] == 0
+    assert rep["p2p_pairs"] == 700 * 699
+    ref = O.direct((), (k,), x, y, z, np.zeros(700, np.int32), q, np.arange(700))
+    assert rel(phi, ref) < 1e-12, rel(phi, ref)
+
+
+def test_free_space_fmm_single_layer():
+    """L = 0 (homogeneous medium): free-space FMM only, against the oracle's FMM."""
+    rng = np.random.default_rng(5)
+    n = 1500
+    x, y, z = rng.random(n), rng.random(n), rng.random(n)
+    q = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    w = dict(d=(), k=(1.7,), x=x, y=y, z=z, layer=np.zeros(n, np.int32), q=q)
+    _check_fmm(w, p=6, leaf=20)
+
+
+def test_empty_and_single_particle():
+    lf = _lfmm()
+    d, k = W.THREE_LAYER_D, W.THREE_LAYER_K
+    P = lf.Plan(d, k, p=4, leaf_max=16)
+    assert len(P.eval_torch([], [], [], [])) == 0
+    one = ([0.1], [0.2], [0.5], [1.0 + 2.0j])
+    phi = P.eval_torch(*one)
+    # a lone particle sees only its own reaction field
+    ref, _ = O.fmm(d, k, 4, 16, *one[:3], [0], one[3])
+    assert abs(phi[0] - ref[0]) <= 1e-10 * abs(ref[0])
+    ex = O.direct(d, k, *one[:3], [0], one[3], [0])
+    assert abs(phi[0] - ex[0]) <= 1e-3 * abs(ex[0])
+
+
+def test_empty_layer():
+    """Particles in the top and bottom layers only: the middle layer has no tree."""
+    w = W.layered_cubes(W.THREE_LAYER_D, W.THREE_LAYER_K, [300, 0, 250], W.THREE_LAYER_CENTERS, seed=13)
+    _check_fmm(w, p=4, leaf=12)
+
+
+def test_given_layers_match_derived_and_permutation():
+    """Passing layer ids gives the same result as deriving them from z, and a
+    permutation of the particles permutes the potentials."""
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=80, seed=17)
+    P = lf.Plan(w["d"], w["k"], p=4, leaf_max=12)
+    a = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
+    b = P.eval_torch(w["x"], w["y"], w["z"], w["q"], layer=w["layer"])
+    assert np.array_equal(a, b)
+    perm = np.random.default_rng(3).permutation(len(a))
+    c = P.eval_torch(w["x"][perm], w["y"][perm], w["z"][perm], w["q"][perm])
+    assert rel(c, a[perm]) < 1e-13
+
+
+def test_particle_on_interface_rejected():
+    lf = _lfmm()
+    P = lf.Plan(W.THREE_LAYER_D, W.THREE_LAYER_K, p=4, leaf_max=12)
+    with pytest.raises(lf.LfmmError) as e:
+        P.eval_torch([0.1, 0.2], [0.0, 0.1], [0.5, 0.0], [1.0, 1.0])
+    assert e.value.code == 1
+
+
+def test_host_entry_point_matches_device():
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=50, seed=19)
+    P = lf.Plan(w["d"], w["k"], p=4, leaf_max=12)
+    a = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
+    b = P.eval_host(w["x"], w["y"], w["z"], w["q"])
+    assert np.array_equal(a, b)
+
+
+def test_five_layer_fmm():
+    d, k = (0.0, -0.6, -1.2, -1.8), (0.5, 1.2, 2.0, 2.8, 3.0)
+    cen = (0.35, -0.3, -0.9, -1.5, -2.15)
+    w = W.layered_cubes(d, k, [90, 70, 70, 70, 90], cen, side=0.5, seed=23)
+    _check_fmm(w, p=4, leaf=10)
