@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lfmm.h"
@@ -152,13 +153,11 @@ struct lfmm_plan_s {
   int p, leaf_max, NC, NCK, NRT, NKS, NT, opsz;
   double b, min_gap;
   int max_depth, profile;
-  int gemm_nct;  // MFMA column tiles (16 targets each) per wave in the batched GEMM
+  int gemm_ks;   // M2L GEMM: waves sharing a 16-target tile (0 = chosen from the tile count)
   int p2p_ta;    // near field: targets per wave step (64 / p2p_ta sources)
   int p2p_ch;    // near field: sources per LDS tile
   double kmax;
   double* d_gaunt = nullptr;
-  TaskDesc* d_ent = nullptr;
-  int nent = 0;
   std::map<std::string, DevBuf> bufs;
   std::vector<char> hbuf;
   lfmm_report rep;
@@ -182,10 +181,48 @@ struct lfmm_plan_s {
     }
     return (T*)B.p;
   }
+  // Host-to-device uploads go through a pinned staging arena so that they are
+  // truly asynchronous (a copy from pageable memory can hold the host until the
+  // stream drains).  The arena is reset at the start of every evaluation, after
+  // the last copy out of it has completed; it grows to the size the previous
+  // evaluation needed (uploads that do not fit fall back to pageable copies).
+  char* pin = nullptr;
+  size_t pin_cap = 0, pin_used = 0, pin_need = 0;
+  hipEvent_t pin_ev = nullptr;
+  bool pin_pending = false;
+  void pin_reset() {
+    if (pin_pending) {
+      HIPCHK(hipEventSynchronize(pin_ev));
+      pin_pending = false;
+    }
+    if (pin_need > pin_cap) {
+      if (pin) (void)hipHostFree(pin);
+      pin = nullptr;
+      pin_cap = 0;
+      size_t nb = pin_need + pin_need / 4;
+      if (hipHostMalloc((void**)&pin, nb, hipHostMallocDefault) == hipSuccess) pin_cap = nb;
+      else pin = nullptr;
+    }
+    pin_used = 0;
+    pin_need = 0;
+  }
   template <typename T>
   T* upload(const char* name, const std::vector<T>& v, hipStream_t s) {
     T* d = dev<T>(name, std::max<size_t>(v.size(), 1));
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    size_t bytes = v.size() * sizeof(T);
+    if (!bytes) return d;
+    size_t off = (pin_used + 255) & ~(size_t)255;
+    pin_used = off + bytes;
+    pin_need = std::max(pin_need, pin_used);
+    if (pin && off + bytes <= pin_cap) {
+      memcpy(pin + off, v.data(), bytes);
+      HIPCHK(hipMemcpyAsync(d, pin + off, bytes, hipMemcpyHostToDevice, s));
+      if (!pin_ev) HIPCHK(hipEventCreateWithFlags(&pin_ev, hipEventDisableTiming));
+      HIPCHK(hipEventRecord(pin_ev, s));
+      pin_pending = true;
+    } else {
+      HIPCHK(hipMemcpyAsync(d, v.data(), bytes, hipMemcpyHostToDevice, s));
+    }
     return d;
   }
   mutable std::map<int, double> decay_memo;
@@ -244,14 +281,14 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
   P->NKS = P->NCK / 4;
   P->NT = (p + 1) * (p + 2) / 2;
   P->opsz = P->NRT * P->NKS * 128;
-  P->gemm_nct = 1;
+  P->gemm_ks = 0;
   P->p2p_ta = 8;
   P->p2p_ch = 256;
   if (const char* e = getenv("LFMM_P2P_TA")) P->p2p_ta = atoi(e);  // tile-shape overrides for tuning runs
   if (const char* e = getenv("LFMM_P2P_CH")) P->p2p_ch = atoi(e);
-  if (const char* e = getenv("LFMM_GEMM_NCT")) {  // tile-shape override for tuning runs
+  if (const char* e = getenv("LFMM_GEMM_KS")) {  // tile-shape override for tuning runs
     int v = atoi(e);
-    if ((v == 1 || v == 2) && P->NRT <= 6) P->gemm_nct = v;
+    if (v == 1 || v == 2 || v == 4) P->gemm_ks = v;
   }
   P->b = 0.5;
   P->min_gap = 1e-9;
@@ -272,31 +309,6 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     HIPCHK(hipMalloc(&P->d_gaunt, G.size() * sizeof(double)));
     HIPCHK(hipMemcpy(P->d_gaunt, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
     // 4 x 4 tiles of the reaction integral matrices over the half m > 0 or (m = 0, m' >= 0)
-    std::vector<TaskDesc> tasks;
-    for (int m = 0; m <= p; m++)
-      for (int mp = -p; mp <= p; mp++) {
-        if (m == 0 && mp < 0) continue;
-        int am = std::abs(mp), q = mp - m;
-        int sg = 1;
-        if (mp < 0 && (am & 1)) sg = -sg;
-        if (q < 0 && (std::abs(q) & 1)) sg = -sg;
-        for (int n0 = m; n0 <= p; n0 += 4)
-          for (int n0p = am; n0p <= p; n0p += 4) {
-            TaskDesc T;
-            T.m = (short)m;
-            T.mp = (short)mp;
-            T.n0 = (short)n0;
-            T.n0p = (short)n0p;
-            T.nr = (short)std::min(4, p + 1 - n0);
-            T.nc = (short)std::min(4, p + 1 - n0p);
-            T.iq = (short)std::abs(q);
-            T.sg = (short)sg;
-            tasks.push_back(T);
-          }
-      }
-    P->nent = (int)tasks.size();
-    HIPCHK(hipMalloc(&P->d_ent, tasks.size() * sizeof(TaskDesc)));
-    HIPCHK(hipMemcpy(P->d_ent, tasks.data(), tasks.size() * sizeof(TaskDesc), hipMemcpyHostToDevice));
     P->ev_ok = true;
     for (int i = 0; i <= ST_COUNT; i++)
       if (hipEventCreate(&P->ev[i]) != hipSuccess) P->ev_ok = false;
@@ -306,6 +318,86 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
   }
   *out = P;
   return LFMM_OK;
+}
+
+// Reaction integral matrices of the given classes into Iall (class c at c.out):
+// node tables per rule group (classes with the same quadrature rule and rho),
+// F per class, then the MFMA node sum.
+static void reaction_integrals(lfmm_plan_s* P, const char* tag, std::vector<ClassDesc>& classes, double* Iall,
+                               hipStream_t s) {
+  if (classes.empty()) return;
+  const int p = P->p, Q = 2 * p, NT = P->NT, NL = P->st.L + 1;
+  std::map<std::tuple<double, double, double, double, int, int, double>, int> key_rg;
+  std::vector<RGDesc> rgs;
+  int Ntot = 0, Ftot = 0, maxnn = 0;
+  for (auto& C : classes) {
+    auto key = std::make_tuple(C.rule.b, C.rule.T0, C.rule.hn, C.rule.hf, C.rule.nnear, C.rule.nfar, C.rho);
+    auto it = key_rg.find(key);
+    int nn = rule_nodes(C.rule);
+    if (it == key_rg.end()) {
+      RGDesc R;
+      memset(&R, 0, sizeof(R));
+      R.rule = C.rule;
+      R.rho = C.rho;
+      R.off = Ntot;
+      R.nn = nn;
+      Ntot += nn;
+      it = key_rg.emplace(key, (int)rgs.size()).first;
+      rgs.push_back(R);
+    }
+    C.rg_off = rgs[it->second].off;
+    C.f_off = Ftot;
+    Ftot += nn;
+    maxnn = std::max(maxnn, nn);
+  }
+  // stacks: classes with the same rule group and source layer, at most SC_GMAX
+  // of them and three target layers each
+  const int NTILE = (P->NC + 15) / 16;
+  std::map<std::pair<int, int>, std::vector<int>> by_rg_ls;
+  for (int c = 0; c < (int)classes.size(); c++) by_rg_ls[{classes[c].rg_off, classes[c].ls}].push_back(c);
+  std::vector<SCDesc> scs;
+  std::vector<int> members;
+  int nwg = 0;
+  for (auto& kv : by_rg_ls) {
+    std::vector<int>& mem = kv.second;
+    std::stable_sort(mem.begin(), mem.end(), [&](int a, int b) { return classes[a].lt < classes[b].lt; });
+    size_t i = 0;
+    while (i < mem.size()) {
+      SCDesc S;
+      memset(&S, 0, sizeof(S));
+      S.rg_off = kv.first.first;
+      S.ls = kv.first.second;
+      S.nn = rule_nodes(classes[mem[i]].rule);
+      S.mem0 = (int)members.size();
+      while (i < mem.size() && S.G < SC_GMAX) {
+        int lt = classes[mem[i]].lt, slot = -1;
+        for (int k = 0; k < S.nlt; k++)
+          if (S.lt[k] == lt) slot = k;
+        if (slot < 0) {
+          if (S.nlt == 3) break;
+          S.lt[S.nlt++] = lt;
+        }
+        members.push_back(mem[i]);
+        S.G++;
+        i++;
+      }
+      for (int m = 0; m <= p; m++) S.NU += ((S.G * (p + 1 - m) + 15) / 16) * NTILE;
+      S.wg0 = nwg;
+      nwg += (S.NU + 8 * SC_UPW - 1) / (8 * SC_UPW);
+      scs.push_back(S);
+    }
+  }
+  std::string t(tag);
+  ClassDesc* d_cls = P->upload((t + "_cls").c_str(), classes, s);
+  RGDesc* d_rgs = P->upload((t + "_rgs").c_str(), rgs, s);
+  SCDesc* d_scs = P->upload((t + "_scs").c_str(), scs, s);
+  int* d_mem = P->upload((t + "_mem").c_str(), members, s);
+  double* J = P->dev<double>((t + "_J").c_str(), (size_t)Ntot * (Q + 1) * 2);
+  double* Pt = P->dev<double>((t + "_P").c_str(), (size_t)NL * Ntot * NT * 2);
+  double* F = P->dev<double>((t + "_F").c_str(), (size_t)Ftot * 2);
+  lk_react_tables((int)rgs.size(), d_rgs, Ntot, P->st, p, J, Pt, s);
+  lk_react_F((int)classes.size(), d_cls, maxnn, P->st, F, s);
+  lk_react_mfma(nwg, (int)scs.size(), d_scs, d_mem, d_cls, p, Ntot, J, Pt, F, Iall, P->NC, s);
 }
 
 inline int has_dir(const Stack& st, int l, int a) { return a == 0 ? (l <= st.L - 1) : (l >= 1); }
@@ -347,6 +439,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   lfmm_report& rep = P->rep;
   memset(&rep, 0, sizeof(rep));
   if (n == 0) return LFMM_OK;
+  P->pin_reset();
   const Stack& st = P->st;
   const int L = st.L, NL = L + 1, p = P->p, NC = P->NC, NCK = P->NCK, NKS = P->NKS, opsz = P->opsz;
   const double* x = xyz;
@@ -471,7 +564,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* slab = P->dev<int>("slab", ntrees * 18);
   HIPCHK(hipMemsetAsync(occ, 0, sizeof(int) * ntrees * 9, s));
   HIPCHK(hipMemsetAsync(slab, 0, sizeof(int) * ntrees * 18, s));
-  lk_occupancy(ntp, skeys, d_trees, occ, slab, s);
+  if (ntrees > 96) throw Fail{LFMM_ENOTSUP};  // at most 5 L + 1 trees: never for L <= 16
+  lk_occupancy(ntp, ntrees, skeys, d_trees, occ, slab, s);
   std::vector<int> hocc(ntrees * 9), hslab(ntrees * 18);
   HIPCHK(hipMemcpyAsync(hocc.data(), occ, sizeof(int) * ntrees * 9, hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(hslab.data(), slab, sizeof(int) * ntrees * 18, hipMemcpyDeviceToHost, s));
@@ -662,9 +756,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, s);
   mark(3);
   if (!classes.empty()) {
-    ClassDesc* d_cls = P->upload("classes", classes, s);
     double* Iall = P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-    lk_react_I((int)classes.size(), d_cls, st, p, P->d_ent, P->nent, Iall, NC, s);
+    reaction_integrals(P, "ri", classes, Iall, s);
     ROpDesc* d_rops = P->upload("rops", rops, s);
     lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, s);
   }
@@ -798,10 +891,12 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   c_m2l.resize(ng_m2l);
   std::vector<GBlock> b_m2m, b_l2l, b_m2l;
   std::vector<int> gs_m2m, gs_l2l, gs_m2l, bf_m2m, bc_m2m, bf_l2l, bc_l2l, bf_m2l, bc_m2l;
-  const int nct = P->gemm_nct, bsz = 64 * nct;
-  build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9, bsz);
-  build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9, bsz);
-  build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1, bsz);
+  // M2L: four waves share each 16-target tile and split its operator sequence
+  // (fastest on both shallow and deep trees)
+  int ks_m2l = P->gemm_ks > 0 ? P->gemm_ks : 4;
+  build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9, 64);
+  build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9, 64);
+  build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1, 64 / ks_m2l);
   int ne_m2m = ng_m2m ? gs_m2m[ng_m2m] : 0, ne_l2l = ng_l2l ? gs_l2l[ng_l2l] : 0,
       ne_m2l = ng_m2l ? gs_m2l[ng_m2l] : 0;
   int64_t m2l_slots = 0;
@@ -861,19 +956,19 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   mark(6);
   for (int lp = Dmax - 1; lp >= 2; lp--)
     if (bc_m2m[lp] > 0)
-      lk_gemm(P->NRT, nct, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M, NCK,
-              NC, s);
+      lk_gemm(0, P->NRT, 1, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
+              NCK, NC, s);
   mark(7);
   // ---------------- M2L (every level, free and reaction)
   if (!b_m2l.empty())
-    lk_gemm(P->NRT, nct, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M, Lx, NCK,
-            NC, s);
+    lk_gemm(1, P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
+            Lx, NCK, NC, s);
   mark(8);
   // ---------------- downward pass
   for (int l = 3; l <= Dmax; l++)
     if (bc_l2l[l] > 0)
-      lk_gemm(P->NRT, nct, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx, NCK,
-              NC, s);
+      lk_gemm(0, P->NRT, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx,
+              NCK, NC, s);
   mark(9);
   double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
   lk_zero(phi_tp, 2 * (size_t)ntp, s);
@@ -1052,7 +1147,9 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   for (auto& kv : plan->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   if (plan->d_gaunt) (void)hipFree(plan->d_gaunt);
-  if (plan->d_ent) (void)hipFree(plan->d_ent);
+  if (plan->pin_pending) (void)hipEventSynchronize(plan->pin_ev);
+  if (plan->pin) (void)hipHostFree(plan->pin);
+  if (plan->pin_ev) (void)hipEventDestroy(plan->pin_ev);
   if (plan->ev_ok)
     for (int i = 0; i <= ST_COUNT; i++) (void)hipEventDestroy(plan->ev[i]);
   delete plan;
@@ -1116,9 +1213,8 @@ int lfmm_reaction_operator(lfmm_plan_t* plan, int l, int a, int lp, int b, doubl
     c[0].a = a;
     c[0].b = b;
     c[0].out = 0;
-    ClassDesc* dc = plan->upload("dbg_cls", c, nullptr);
     double* I = plan->dev<double>("dbg_I", (size_t)NC * NC * 2);
-    lk_react_I(1, dc, st, plan->p, plan->d_ent, plan->nent, I, NC, nullptr);
+    reaction_integrals(plan, "dbg", c, I, nullptr);
     std::vector<ROpDesc> r(1);
     r[0] = ROpDesc{dx, dy, st.k[l], 0, 0};
     ROpDesc* dr = plan->upload("dbg_rop", r, nullptr);

@@ -33,7 +33,31 @@ struct ClassDesc {
   double zt, zs, rho;
   int lt, ls, a, b;  // target layer, source layer, directions
   int out;           // index of the integral matrix
+  int rg_off;        // first node of its rule group in the node tables
+  int f_off;         // first entry of its F values
   int pad;
+};
+
+// A stack of reaction classes contracted together: same quadrature rule group
+// and source layer, at most SC_GMAX classes and three target layers.
+#define SC_GMAX 16
+#define SC_UPW 6  // MFMA units per wave
+struct SCDesc {
+  int rg_off, nn, ls, G;
+  int mem0;   // first member in the member list
+  int nlt;    // distinct target layers
+  int lt[3];
+  int wg0;    // first workgroup
+  int NU;     // (m, row tile, column tile) units
+  int pad;
+};
+
+// Quadrature rule group: classes with the same (zt + zs, rho) share these nodes.
+struct RGDesc {
+  Rule rule;
+  double rho;
+  int off;  // first node in the node tables
+  int nn;
 };
 
 // One reaction M2L operator: phase/prefactor applied to a class integral.
@@ -42,12 +66,6 @@ struct ROpDesc {
   double kt;
   int cls;        // integral matrix index
   int op;         // destination operator index
-};
-
-// 4 x 4 tile of the reaction integral matrix for fixed (m >= 0, m'): rows
-// n0..n0+nr-1, columns n0p..n0p+nc-1; iq = |m' - m|; sg = sign from negative orders.
-struct TaskDesc {
-  short m, mp, n0, n0p, nr, nc, iq, sg;
 };
 
 // Interaction template entry of a GEMM group.
@@ -86,7 +104,8 @@ void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s);
 void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
                     const double* x, const double* y, const double* z, Stack st, unsigned* keys, int* vals,
                     hipStream_t s);
-void lk_occupancy(int ntp, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab, hipStream_t s);
+void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab,
+                  hipStream_t s);
 void lk_box_flags(int ntp, int level, const unsigned* skeys, const TreeInfo* trees, int* flags, hipStream_t s);
 void lk_box_fill(int ntp, int level, const unsigned* skeys, const int* flags, const int* scan, int lvl_off,
                  const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level, int* box_cnt,
@@ -102,8 +121,11 @@ void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const 
                double* py, double* pz, double* pq, hipStream_t s);
 void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS, const double* gaunt,
                 hipStream_t s);
-void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks, int ntask, double* Iout,
-                int NC, hipStream_t s);
+void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, int p, double* Jtab, double* Ptab,
+                     hipStream_t s);
+void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, double* Ftab, hipStream_t s);
+void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p, int Ntot,
+                   const double* Jtab, const double* Ptab, const double* Ftab, double* Iout, int NC, hipStream_t s);
 void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p, int NC,
                      int NKS, hipStream_t s);
 void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
@@ -113,9 +135,9 @@ void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, con
 void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int total, const int* leafrow, const int* box_code,
             const int* box_tree, const int* box_level, const TreeInfo* trees, const double* px, const double* py,
             const double* pz, const int* sg, int p, int NCK, const double* Lc, double* phi_tp, hipStream_t s);
-void lk_gemm(int nrt, int nct, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
-             int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D, int NCK, int NC,
-             hipStream_t s);
+void lk_gemm(int m2l, int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+             const int* srow, int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D,
+             int NCK, int NC, hipStream_t s);
 void lk_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree, const int* box_level,
                   const TreeInfo* trees, const int* gbase, int nlev1, int* gid, int* rowid, hipStream_t s);
 void lk_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,

@@ -268,46 +268,47 @@ __device__ __forceinline__ int run_end(const unsigned* keys, int s, int hi, int 
 }
 
 // occupancy[t*9 + l] = fullest cell of tree t at level l; slab flags of reaction trees.
-// Run lengths are reduced over the wave before one atomic per wave (when the
-// whole wave lies in one tree) to avoid same-address atomic contention.
-__global__ void k_occupancy(int ntp, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab) {
-  int s = blockIdx.x * 256 + threadIdx.x;
-  bool valid = s < ntp;
-  unsigned key = valid ? skeys[s] : 0u;
-  int t = valid ? (int)(key >> 24) : -1;
-  int t0 = __shfl(t, 0);
-  bool same = __all(t == t0);
-  int lane = threadIdx.x & 63;
-  int hi = 0, pt0 = 0, kind = 0;
-  if (valid) {
+// A workgroup scans a contiguous segment of the sorted keys and keeps its maxima
+// and flags in LDS (the keys are sorted by tree, so a segment touches few
+// trees); one flush per workgroup then updates the global tables.
+#define OCC_SEG 8192
+#define OCC_TMAX 96
+__global__ __launch_bounds__(256) void k_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees,
+                                                   int* occ, int* slab) {
+  __shared__ int s_occ[OCC_TMAX * 9], s_slab[OCC_TMAX * 18];
+  for (int i = threadIdx.x; i < ntrees * 9; i += 256) s_occ[i] = 0;
+  for (int i = threadIdx.x; i < ntrees * 18; i += 256) s_slab[i] = 0;
+  __syncthreads();
+  const int seg0 = blockIdx.x * OCC_SEG, seg1 = min(ntp, seg0 + OCC_SEG);
+  for (int s = seg0 + threadIdx.x; s < seg1; s += 256) {
+    unsigned key = skeys[s];
+    int t = (int)(key >> 24);
     TreeInfo T = trees[t];
-    hi = T.pt_off + T.npts;
-    pt0 = T.pt_off;
-    kind = T.kind;
-  }
-  int ix, iy, iz;
-  demorton3(key & 0xFFFFFFu, 8, &ix, &iy, &iz);
-  for (int l = 0; l <= 8; l++) {
-    int sh = 3 * (8 - l);
-    int v = 0;
-    if (valid && (s == pt0 || (skeys[s - 1] >> sh) != (key >> sh))) {  // first point of its cell
-      v = run_end(skeys, s, hi, sh) - s;
-      if (l >= 1 && kind != 0) {
-        int izl = iz >> (8 - l), half = 1 << (l - 1);
-        int hgt = (kind == 1) ? izl - half : half - 1 - izl;
-        if (hgt == 0 || hgt == 1) slab[(t * 9 + l) * 2 + hgt] = 1;
+    int hi = T.pt_off + T.npts, pt0 = T.pt_off;
+    int ix, iy, iz;
+    demorton3(key & 0xFFFFFFu, 8, &ix, &iy, &iz);
+    for (int l = 0; l <= 8; l++) {
+      int sh = 3 * (8 - l);
+      if (s == pt0 || (skeys[s - 1] >> sh) != (key >> sh)) {  // first point of its cell
+        int v = run_end(skeys, s, hi, sh) - s;
+        atomicMax(&s_occ[t * 9 + l], v);
+        if (l >= 1 && T.kind != 0) {
+          int izl = iz >> (8 - l), half = 1 << (l - 1);
+          int hgt = (T.kind == 1) ? izl - half : half - 1 - izl;
+          if (hgt == 0 || hgt == 1) s_slab[(t * 9 + l) * 2 + hgt] = 1;
+        }
       }
     }
-    if (same) {
-      for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-      if (lane == 0 && v > 0) atomicMax(&occ[t0 * 9 + l], v);
-    } else if (v > 0) {
-      atomicMax(&occ[t * 9 + l], v);
-    }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ntrees * 9; i += 256)
+    if (s_occ[i] > 0) atomicMax(&occ[i], s_occ[i]);
+  for (int i = threadIdx.x; i < ntrees * 18; i += 256)
+    if (s_slab[i]) slab[i] = 1;
 }
-extern "C" void lk_occupancy(int ntp, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab, hipStream_t s) {
-  if (ntp) k_occupancy<<<nblk(ntp, 256), 256, 0, s>>>(ntp, skeys, trees, occ, slab);
+extern "C" void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab,
+                             hipStream_t s) {
+  if (ntp) k_occupancy<<<(ntp + OCC_SEG - 1) / OCC_SEG, 256, 0, s>>>(ntp, ntrees, skeys, trees, occ, slab);
 }
 
 // run-start flags of the level-l boxes (only for trees of depth >= l)
@@ -533,157 +534,260 @@ extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz,
 
 // ---------------------------------------------------------------------------
 // Reaction M2L integrals (Section 3.5 eq. (me2lesimplified) in the polarisation
-// frame): for one geometry class (target centre height zt, source centre depth
-// zs, lateral distance rho)
-//   I[(n,m),(n',m')] = int_Gamma k_rho J_{m'-m}(k_rho rho) e^{i kz_t zt + i kz_s zs}
-//                      sigma^{ab}(k_rho)/kz_t Phat_n^m(kz_t/k_t) Phat_{n'}^{m'}(kz_s/k_s) dk_rho
-// Only the half m > 0 or (m = 0, m' >= 0) is integrated; the other half follows
-// from Phat_n^{-m} = (-1)^m Phat_n^m and J_{-q} = (-1)^q J_q.
-// One workgroup per class.  Nodes are generated CH at a time into LDS, one wave
-// per quantity (weight x density x exponential; J_q; Phat at the target
-// wavenumber; Phat at the source wavenumber).  The contraction over nodes works
-// on 4 x 4 tiles of (n, n') for fixed (m, m') so every loaded value is reused.
+// frame of Section 3.3): for a class (target/source layer and direction, target
+// height zt, source depth zs, lateral distance rho)
+//   I[(n,m),(n',m')] = int_Gamma k_rho J_q(k_rho rho) e^{i kz_t zt + i kz_s zs}
+//                      sigma_ab(k_rho) / kz_t  Phat_n^m(kz_t/k_t) Phat_{n'}^{m'}(kz_s/k_s) dk_rho,
+// q = m' - m, by Gauss-Legendre panels on the contour.  Only m >= 0 is
+// integrated: Phat_n^{-m} = (-1)^m Phat_n^m and J_{-q} = (-1)^q J_q give the rest.  Classes with the same
+// (zt + zs, rho) share the quadrature nodes and J_q, and Phat depends only on
+// the layer and the node, so the node tables are built once per rule group:
+//   k_react_tables: J_q(k rho) (q = 0..2p) and Phat(kz_l/k_l) for every layer l;
+//   k_react_F:      F = w k_rho e^{...} sigma_ab / kz_t per class and node;
+//   k_react_mfma:   the node sum as FP64 MFMA products (below).
 // ---------------------------------------------------------------------------
-template <int CH, int TPT, int LL>
-__global__ __launch_bounds__(256) void k_react_I(const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks,
-                                                 int ntask, double* Iout, int NC) {
-  extern __shared__ cd sh[];
-  int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
-  cd* FJ = sh;                      // [CH][Q+1]  J_q(k_rho rho)
-  cd* PT = FJ + CH * (Q + 1);       // [CH][NT]   Phat(kz_t/k_t)
-  cd* PS = PT + CH * NT;            // [CH][NT]   Phat(kz_s/k_s)
-  cd* F = PS + CH * NT;             // [CH]       w k_rho e^{...} sigma / kz_t
-  ClassDesc C = cls[blockIdx.x];
+__global__ __launch_bounds__(256) void k_react_tables(const RGDesc* rgs, int nrg, int Ntot, Stack st, int p,
+                                                      cd* Jtab, cd* Ptab) {
+  const int NL = st.L + 1, Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
+  long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (long long)(NL + 1) * Ntot) return;
+  int kind = (int)(t / Ntot), g = (int)(t % Ntot);
+  int lo = 0, hi = nrg - 1;  // rule group holding global node g
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (rgs[mid].off <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  const RGDesc R = rgs[lo];
+  cd kr, w;
+  rule_node(R.rule, g - R.off, c_glx, c_glw, &kr, &w);
+  if (kind == 0) {
+    dev_besselJ(Q, kr * R.rho, Jtab + (size_t)g * (Q + 1), 1);
+  } else {
+    int l = kind - 1;
+    double kl = st.k[l];
+    cd kz = csqrtd(mk(kl * kl, 0) - kr * kr);
+    dev_legendre_c(p, kz / kl, kr / kl, Ptab + ((size_t)l * Ntot + g) * NT, 1);
+  }
+}
+template <int LL>
+__global__ __launch_bounds__(256) void k_react_F(const ClassDesc* cls, Stack st, cd* Ftab) {
+  const ClassDesc C = cls[blockIdx.y];
+  int node = blockIdx.x * 256 + threadIdx.x;
+  if (node >= rule_nodes(C.rule)) return;
+  cd kr, w;
+  rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
   double kt = st.k[C.lt], ks = st.k[C.ls];
-  int nn = rule_nodes(C.rule);
-  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  cd acc[TPT][16];
-  TaskDesc tk[TPT];
-  bool tv[TPT];
-#pragma unroll
-  for (int r = 0; r < TPT; r++) {
-    int t = threadIdx.x + 256 * r;
-    tv[r] = t < ntask;
-    tk[r] = tasks[tv[r] ? t : 0];
-#pragma unroll
-    for (int e = 0; e < 16; e++) acc[r][e] = mk(0, 0);
+  cd kr2 = kr * kr;
+  cd kzt = csqrtd(mk(kt * kt, 0) - kr2), kzs = csqrtd(mk(ks * ks, 0) - kr2);
+  cd sig[2][2];
+  dev_densities_t<LL>(st, kr, C.lt, C.ls, sig);
+  cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
+  Ftab[C.f_off + node] = w * kr * ex * sig[C.a][C.b] / kzt;
+}
+// The node sum on the FP64 matrix cores.  For a fixed order m the block
+//   I_g[(n, m), (n', m')] = sum_c (F_{g,c} Phat_n^m(t_c)) (s J_{|q|}(k_c rho) Phat_{n'}^{|m'|}(s_c))
+// of class g (s = the sign from the negative orders m' < 0 and q < 0) is a
+// product of a (p+1-m) x nodes matrix and a nodes x NC matrix.  The right-hand
+// factor depends only on the quadrature rule group and the source layer, so the
+// classes sharing both (a stack of G <= 16 classes, with at most three target
+// layers) are contracted together: for each m the left-hand rows (g, n) of all
+// G classes are packed into 16-row tiles, and the products run as 16x16x4
+// complex MFMA steps (four real MFMAs each) against column tiles (n', m') in NC
+// order.  The (m, row tile, column tile) units of a stack are spread over the
+// eight waves of one or more workgroups (UPW units per wave); the node tables of
+// a chunk of CH nodes are staged in LDS.  Entries with -m, -m' equal those with
+// m, m' and are written too.
+template <int UPW, int CH>
+__global__ __launch_bounds__(512) void k_react_mfma(const SCDesc* scs, int nsc, const int* members,
+                                                    const ClassDesc* cls, int p, int Ntot, const cd* Jtab,
+                                                    const cd* Ptab, const cd* Ftab, double* Iout, int NC) {
+  extern __shared__ cd sh[];
+  const int Q = 2 * p, NT = (p + 1) * (p + 2) / 2, NTILE = (NC + 15) / 16;
+  __shared__ int s_slot[SC_GMAX], s_out[SC_GMAX], s_foff[SC_GMAX];
+  int lo = 0, hi = nsc - 1;  // stack of this workgroup
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (scs[mid].wg0 <= (int)blockIdx.x) lo = mid;
+    else hi = mid - 1;
   }
+  const SCDesc S = scs[lo];
+  const int ug = blockIdx.x - S.wg0, G = S.G, nlt = S.nlt;
+  cd* FJ = sh;                  // [CH][Q+1]
+  cd* PS = FJ + CH * (Q + 1);   // [CH][NT]
+  cd* PT = PS + CH * NT;        // [nlt][CH][NT]
+  cd* F = PT + 3 * CH * NT;     // [G][CH]
+  if (threadIdx.x < G) {
+    const ClassDesc C = cls[members[S.mem0 + threadIdx.x]];
+    int slot = 0;
+    for (int i = 0; i < nlt; i++)
+      if (S.lt[i] == C.lt) slot = i;
+    s_slot[threadIdx.x] = slot;
+    s_out[threadIdx.x] = C.out;
+    s_foff[threadIdx.x] = C.f_off;
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  int um[UPW], urt[UPW], uct[UPW], apt[UPW], ag[UPW], psi[UPW], jq[UPW];
+  double sgn[UPW];
+  bool uv[UPW];
+  const int u0 = (ug * 8 + wave) * UPW;
+#pragma unroll
+  for (int i = 0; i < UPW; i++) {
+    int u = u0 + i;
+    uv[i] = u < S.NU;
+    int m = 0, rem = uv[i] ? u : 0;
+    while (m <= p) {
+      int nu_m = ((G * (p + 1 - m) + 15) / 16) * NTILE;
+      if (rem < nu_m) break;
+      rem -= nu_m;
+      m++;
+    }
+    if (m > p) {  // not reached for u < NU
+      uv[i] = false;
+      m = 0;
+      rem = 0;
+    }
+    const int Rm = p + 1 - m, rt = rem / NTILE, ct = rem % NTILE;
+    um[i] = m;
+    urt[i] = rt;
+    uct[i] = ct;
+    // left-hand row of this lane
+    int r = rt * 16 + col;
+    ag[i] = -1;
+    apt[i] = 0;
+    if (uv[i] && r < G * Rm) {
+      int g = r / Rm, n = m + r % Rm;
+      ag[i] = g;
+      apt[i] = s_slot[g] * CH * NT + tix(n, m);
+    }
+    // right-hand column of this lane
+    int j = 16 * ct + col;
+    psi[i] = 0;
+    jq[i] = 0;
+    sgn[i] = 0.0;
+    if (uv[i] && j < NC) {
+      int n2 = (int)sqrt((double)j);
+      while (n2 * n2 > j) n2--;
+      while ((n2 + 1) * (n2 + 1) <= j) n2++;
+      int m2 = j - n2 * n2 - n2, am = m2 < 0 ? -m2 : m2, q = m2 - m;
+      int sg = 1;
+      if (m2 < 0 && (am & 1)) sg = -sg;
+      if (q < 0 && ((-q) & 1)) sg = -sg;
+      psi[i] = tix(n2, am);
+      jq[i] = q < 0 ? -q : q;
+      sgn[i] = (double)sg;
+    }
+  }
+  v4d accr[UPW], acci[UPW];
+#pragma unroll
+  for (int i = 0; i < UPW; i++) {
+    accr[i] = (v4d){0, 0, 0, 0};
+    acci[i] = (v4d){0, 0, 0, 0};
+  }
+  const int nn = S.nn;
+  const cd* Jg = Jtab + (size_t)S.rg_off * (Q + 1);
+  const cd* PSg = Ptab + ((size_t)S.ls * Ntot + S.rg_off) * NT;
   for (int c0 = 0; c0 < nn; c0 += CH) {
-    if (lane < CH) {
-      int node = c0 + lane;
-      bool ok = node < nn;
-      cd kr = mk(0, 0), w = mk(0, 0);
-      if (ok) rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
-      cd kr2 = kr * kr;
-      if (wave == 0) {
-        cd f = mk(0, 0);
-        if (ok) {
-          cd kzt = csqrtd(mk(kt * kt, 0) - kr2), kzs = csqrtd(mk(ks * ks, 0) - kr2);
-          cd sig[2][2];
-          dev_densities_t<LL>(st, kr, C.lt, C.ls, sig);
-          cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
-          f = w * kr * ex * sig[C.a][C.b] / kzt;
-        }
-        F[lane] = f;
-      } else if (wave == 1) {
-        if (ok) dev_besselJ(Q, kr * C.rho, FJ + lane * (Q + 1), 1);
-        else
-          for (int q = 0; q <= Q; q++) FJ[lane * (Q + 1) + q] = mk(0, 0);
-      } else if (wave == 2) {
-        if (ok) {
-          cd kzt = csqrtd(mk(kt * kt, 0) - kr2);
-          dev_legendre_c(p, kzt / kt, kr / kt, PT + lane * NT, 1);
-        } else
-          for (int i = 0; i < NT; i++) PT[lane * NT + i] = mk(0, 0);
-      } else {
-        if (ok) {
-          cd kzs = csqrtd(mk(ks * ks, 0) - kr2);
-          dev_legendre_c(p, kzs / ks, kr / ks, PS + lane * NT, 1);
-        } else
-          for (int i = 0; i < NT; i++) PS[lane * NT + i] = mk(0, 0);
-      }
+    const int nc = nn - c0 < CH ? nn - c0 : CH;
+    __syncthreads();
+    for (int e = threadIdx.x; e < CH * (Q + 1); e += 512)
+      FJ[e] = e < nc * (Q + 1) ? Jg[(size_t)c0 * (Q + 1) + e] : mk(0, 0);
+    for (int e = threadIdx.x; e < CH * NT; e += 512) PS[e] = e < nc * NT ? PSg[(size_t)c0 * NT + e] : mk(0, 0);
+    for (int sl = 0; sl < nlt; sl++) {
+      const cd* PTg = Ptab + ((size_t)S.lt[sl] * Ntot + S.rg_off + c0) * NT;
+      for (int e = threadIdx.x; e < CH * NT; e += 512) PT[sl * CH * NT + e] = e < nc * NT ? PTg[e] : mk(0, 0);
+    }
+    for (int e = threadIdx.x; e < G * CH; e += 512) {
+      int g = e / CH, c = e % CH;
+      F[e] = c < nc ? Ftab[s_foff[g] + c0 + c] : mk(0, 0);
     }
     __syncthreads();
+    for (int kst = 0; kst < (nc + 3) / 4; kst++) {
+      const int c = kst * 4 + kq;
+      int cm = -1, crt = -1;
+      double ar = 0.0, ai = 0.0;
 #pragma unroll
-    for (int r = 0; r < TPT; r++) {
-      if (!tv[r]) continue;
-      TaskDesc T = tk[r];
-      int am = abs((int)T.mp);
-      int ia[4], ib[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) {
-        int n = min(T.n0 + i, p), n2 = min(T.n0p + i, p);
-        ia[i] = tix(n, T.m);
-        ib[i] = tix(n2 < am ? am : n2, am);
-      }
-      for (int c = 0; c < CH; c++) {
-        cd fj = F[c] * FJ[c * (Q + 1) + T.iq];
-        cd a[4], b[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-          a[i] = PT[c * NT + ia[i]] * fj;
-          b[i] = PS[c * NT + ib[i]];
+      for (int i = 0; i < UPW; i++) {
+        if (!uv[i]) continue;
+        if (um[i] != cm || urt[i] != crt) {
+          cm = um[i];
+          crt = urt[i];
+          cd x = ag[i] >= 0 ? F[ag[i] * CH + c] * PT[apt[i] + c * NT] : mk(0, 0);
+          ar = x.x;
+          ai = x.y;
         }
-#pragma unroll
-        for (int i = 0; i < 4; i++)
-#pragma unroll
-          for (int j = 0; j < 4; j++) {
-            cd& A = acc[r][i * 4 + j];
-            A.x += a[i].x * b[j].x - a[i].y * b[j].y;
-            A.y += a[i].x * b[j].y + a[i].y * b[j].x;
-          }
+        cd y = sgn[i] * (FJ[c * (Q + 1) + jq[i]] * PS[c * NT + psi[i]]);
+        accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.x, accr[i], 0, 0, 0);
+        acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.y, acci[i], 0, 0, 0);
+        accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, y.y, accr[i], 0, 0, 0);
+        acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, y.x, acci[i], 0, 0, 0);
       }
     }
-    __syncthreads();
   }
-  double* out = Iout + (size_t)C.out * NC * NC * 2;
 #pragma unroll
-  for (int r = 0; r < TPT; r++) {
-    if (!tv[r]) continue;
-    TaskDesc T = tk[r];
+  for (int i = 0; i < UPW; i++) {
+    if (!uv[i]) continue;
+    const int m = um[i], Rm = p + 1 - m, j = 16 * uct[i] + col;
+    if (j >= NC) continue;
+    int n2 = (int)sqrt((double)j);
+    while (n2 * n2 > j) n2--;
+    while ((n2 + 1) * (n2 + 1) <= j) n2++;
+    const int m2 = j - n2 * n2 - n2;
 #pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        if (i >= T.nr || j >= T.nc) continue;
-        int n = T.n0 + i, n2 = T.n0p + j;
-        cd v = (double)T.sg * acc[r][i * 4 + j];
-        size_t o1 = (size_t)cidx(n, T.m) * NC + cidx(n2, T.mp);
-        size_t o2 = (size_t)cidx(n, -T.m) * NC + cidx(n2, -T.mp);
-        out[2 * o1] = v.x;
-        out[2 * o1 + 1] = v.y;
-        out[2 * o2] = v.x;
-        out[2 * o2 + 1] = v.y;
+    for (int r = 0; r < 4; r++) {
+      int row = urt[i] * 16 + kq + 4 * r;
+      if (row >= G * Rm) continue;
+      int g = row / Rm, n = m + row % Rm;
+      double* out = Iout + (size_t)s_out[g] * NC * NC * 2;
+      size_t o1 = (size_t)cidx(n, m) * NC + j;
+      out[2 * o1] = accr[i][r];
+      out[2 * o1 + 1] = acci[i][r];
+      if (m > 0) {
+        size_t o2 = (size_t)cidx(n, -m) * NC + cidx(n2, -m2);
+        out[2 * o2] = accr[i][r];
+        out[2 * o2 + 1] = acci[i][r];
       }
+    }
   }
 }
-template <int CH, int TPT>
-static void launch_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks, int ntask,
-                           double* Iout, int NC, size_t lds, hipStream_t s) {
-#define RI_CASE(LLV)                                                                                        \
-  case LLV:                                                                                                 \
-    (void)hipFuncSetAttribute((const void*)k_react_I<CH, TPT, LLV>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                              (int)lds);                                                                    \
-    k_react_I<CH, TPT, LLV><<<ncls, 256, lds, s>>>(cls, st, p, tasks, ntask, Iout, NC);                      \
-    break;
+extern "C" void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, int p, double* Jtab, double* Ptab,
+                                hipStream_t s) {
+  long long nt = (long long)(st.L + 2) * Ntot;
+  if (nrg && nt) k_react_tables<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(rgs, nrg, Ntot, st, p, (cd*)Jtab, (cd*)Ptab);
+}
+extern "C" void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, double* Ftab, hipStream_t s) {
+  if (!ncls || !maxnn) return;
+  dim3 g((maxnn + 255) / 256, ncls);
   switch (st.L) {
-    RI_CASE(1) RI_CASE(2) RI_CASE(3) RI_CASE(4)
-    default:
-      (void)hipFuncSetAttribute((const void*)k_react_I<CH, TPT, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds);
-      k_react_I<CH, TPT, 0><<<ncls, 256, lds, s>>>(cls, st, p, tasks, ntask, Iout, NC);
+    case 1: k_react_F<1><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
+    case 2: k_react_F<2><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
+    case 3: k_react_F<3><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
+    case 4: k_react_F<4><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
+    default: k_react_F<0><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
   }
-#undef RI_CASE
 }
-extern "C" void lk_react_I(int ncls, const ClassDesc* cls, Stack st, int p, const TaskDesc* tasks, int ntask,
-                           double* Iout, int NC, hipStream_t s) {
-  if (!ncls) return;
-  int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
-  int tpt = (ntask + 255) / 256;
-  if (p <= 8 && tpt <= 2)
-    launch_react_I<64, 2>(ncls, cls, st, p, tasks, ntask, Iout, NC, sizeof(cd) * 64 * (Q + 2 + 2 * NT), s);
-  else
-    launch_react_I<32, 3>(ncls, cls, st, p, tasks, ntask, Iout, NC, sizeof(cd) * 32 * (Q + 2 + 2 * NT), s);
+template <int UPW, int CH>
+static void launch_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p,
+                              int Ntot, const cd* J, const cd* P, const cd* F, double* Iout, int NC, size_t lds,
+                              hipStream_t s) {
+  (void)hipFuncSetAttribute((const void*)k_react_mfma<UPW, CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  k_react_mfma<UPW, CH><<<nwg, 512, lds, s>>>(scs, nsc, members, cls, p, Ntot, J, P, F, Iout, NC);
+}
+extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p,
+                              int Ntot, const double* Jtab, const double* Ptab, const double* Ftab, double* Iout,
+                              int NC, hipStream_t s) {
+  if (!nwg) return;
+  const int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
+  const cd *J = (const cd*)Jtab, *P = (const cd*)Ptab, *F = (const cd*)Ftab;
+  if (p <= 8) {
+    const size_t lds = sizeof(cd) * (32 * (Q + 1 + 4 * NT) + SC_GMAX * 32);
+    launch_react_mfma<SC_UPW, 32>(nwg, nsc, scs, members, cls, p, Ntot, J, P, F, Iout, NC, lds, s);
+  } else {
+    const size_t lds = sizeof(cd) * (16 * (Q + 1 + 4 * NT) + SC_GMAX * 16);
+    launch_react_mfma<SC_UPW, 16>(nwg, nsc, scs, members, cls, p, Ntot, J, P, F, Iout, NC, lds, s);
+  }
 }
 
 // T[(n,m),(n',m')] = (4 pi/k_t) i^n (-i)^{n'} i^q e^{i q phi} I[(n,m),(n',m')], q = m' - m,
@@ -888,114 +992,178 @@ extern "C" void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int t
 // ---------------------------------------------------------------------------
 // Batched complex GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64):
 //   D[trow(e)] += sum_k Op[seq(k)] * S[srow(e, k)]
-// for every target e of a block; one block = up to 64 targets of one group that
-// share the operator sequence.  Each wave owns 16 targets (MFMA columns) and all
-// NRT row tiles; complex products use four real MFMAs.
+// for every target e of a block; one block = the targets of one group that share
+// the operator sequence.  A wave owns a tile of 16 targets (MFMA columns) and all
+// NRT row tiles; complex products use four real MFMAs.  KS waves share a target
+// tile and split its operator sequence (wave kw takes k = kw, kw + KS, ...); their
+// partial sums are combined through LDS in a fixed order, so a level with few
+// targets still spreads over the whole chip.  The operands of the next MFMA step
+// (including the first step of the next operator) are loaded while the current
+// step runs.
 // f64 16x16x4 lane layout: A lane l = (row l%16, k l/16); B lane l = (k l/16,
 // col l%16); D lane l element r = (row l/16 + 4r, col l%16).
 // ---------------------------------------------------------------------------
-template <int NRT, int NCT>
-__global__ __launch_bounds__(256) void k_gemm(const GBlock* blocks, const int* seq, const int* trow, const int* srow,
-                                              int srow_stride, const double* __restrict__ ops, int opsz, int NKS,
-                                              const double2* __restrict__ S, double2* D, int NCK, int NC) {
-  // each wave owns NCT column tiles of 16 targets and all NRT row tiles
+template <int NRT, int KS>
+__device__ __forceinline__ void gemm_body(const GBlock* blocks, const int* seq, const int* trow, const int* srow,
+                                          int srow_stride, const double* __restrict__ ops, int opsz, int NKS,
+                                          const double2* __restrict__ S, double2* D, int NCK, int NC) {
   GBlock bd = blocks[blockIdx.x];
-  int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int col = lane & 15, kr = lane >> 4;
-  int tt[NCT], ee[NCT];
-  bool tv[NCT];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kr = lane >> 4;
+  const int cg = wave / KS, kw = wave % KS;
+  const int tt = cg * 16 + col;
+  const bool tv = tt < bd.nt;
+  const int ee = bd.e0 + (tv ? tt : 0);
+  const int* my_srow = srow + (size_t)ee * srow_stride;
+  v4d accr[NRT], acci[NRT];
 #pragma unroll
-  for (int c = 0; c < NCT; c++) {
-    tt[c] = (wave * NCT + c) * 16 + col;
-    tv[c] = tt[c] < bd.nt;
-    ee[c] = bd.e0 + tt[c];
+  for (int i = 0; i < NRT; i++) {
+    accr[i] = (v4d){0, 0, 0, 0};
+    acci[i] = (v4d){0, 0, 0, 0};
   }
-  v4d accr[NCT][NRT], acci[NCT][NRT];
-#pragma unroll
-  for (int c = 0; c < NCT; c++)
-#pragma unroll
-    for (int i = 0; i < NRT; i++) {
-      accr[c][i] = (v4d){0, 0, 0, 0};
-      acci[c][i] = (v4d){0, 0, 0, 0};
-    }
   const double2* A2 = (const double2*)ops;
-  for (int kk = 0; kk < bd.K; kk++) {
-    int sr[NCT];
-    bool any = false;
-#pragma unroll
-    for (int c = 0; c < NCT; c++) {
-      sr[c] = tv[c] ? srow[(size_t)ee[c] * srow_stride + kk] : -1;
-      any = any || (sr[c] >= 0);
-    }
-    if (__ballot(any) == 0) continue;
-    int op = seq[bd.seq0 + kk];
-    const double2* A = A2 + (size_t)op * (opsz >> 1);
-    const double2* B[NCT];
-#pragma unroll
-    for (int c = 0; c < NCT; c++) B[c] = S + (size_t)(sr[c] >= 0 ? sr[c] : 0) * NCK + kr;
-    // software pipeline: operands of step ks+1 are loaded while step ks runs
-    double2 a_cur[NRT], b_cur[NCT];
+  const size_t opstride = (size_t)(opsz >> 1);
+  // first operator with a source for at least one target of the tile
+  int kk = kw, sr = -1;
+  while (kk < bd.K) {
+    sr = tv ? my_srow[kk] : -1;
+    if (__ballot(sr >= 0)) break;
+    kk += KS;
+  }
+  if (kk < bd.K) {
+    const double2* A = A2 + (size_t)seq[bd.seq0 + kk] * opstride;
+    const double2* B = S + (size_t)(sr >= 0 ? sr : 0) * NCK + kr;
+    bool bv = sr >= 0;
+    double2 a_cur[NRT], b_cur;
 #pragma unroll
     for (int rt = 0; rt < NRT; rt++) a_cur[rt] = A[((size_t)(rt * NKS) << 6) + lane];
-#pragma unroll
-    for (int c = 0; c < NCT; c++) b_cur[c] = (sr[c] >= 0) ? B[c][0] : make_double2(0.0, 0.0);
-    for (int ks = 0; ks < NKS; ks++) {
-      double2 a_nxt[NRT], b_nxt[NCT];
-      int kn = (ks + 1 < NKS) ? ks + 1 : ks;
-#pragma unroll
-      for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS + kn) << 6) + lane];
-#pragma unroll
-      for (int c = 0; c < NCT; c++) b_nxt[c] = (sr[c] >= 0) ? B[c][kn * 4] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int rt = 0; rt < NRT; rt++) {
-#pragma unroll
-        for (int c = 0; c < NCT; c++) {
-          accr[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur[c].x, accr[c][rt], 0, 0, 0);
-          acci[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur[c].y, acci[c][rt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int c = 0; c < NCT; c++) {
-          accr[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_cur[rt].y, b_cur[c].y, accr[c][rt], 0, 0, 0);
-          acci[c][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].y, b_cur[c].x, acci[c][rt], 0, 0, 0);
-        }
+    b_cur = bv ? B[0] : make_double2(0.0, 0.0);
+    while (true) {
+      // look-ahead of the next operator (its source row and operator index)
+      int kn = kk + KS, srn = -1, opn = 0;
+      if (kn < bd.K) {
+        srn = tv ? my_srow[kn] : -1;
+        opn = seq[bd.seq0 + kn];
       }
+      for (int ks = 0; ks < NKS; ks++) {
+        double2 a_nxt[NRT], b_nxt;
+        if (ks + 1 < NKS) {
 #pragma unroll
-      for (int rt = 0; rt < NRT; rt++) a_cur[rt] = a_nxt[rt];
+          for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS + ks + 1) << 6) + lane];
+          b_nxt = bv ? B[(ks + 1) * 4] : make_double2(0.0, 0.0);
+        } else {
+          // skip operators with no source for the whole tile
+          while (kn < bd.K && !__ballot(srn >= 0)) {
+            kn += KS;
+            if (kn < bd.K) {
+              srn = tv ? my_srow[kn] : -1;
+              opn = seq[bd.seq0 + kn];
+            }
+          }
+          if (kn < bd.K) {
+            A = A2 + (size_t)opn * opstride;
+            B = S + (size_t)(srn >= 0 ? srn : 0) * NCK + kr;
+            bv = srn >= 0;
 #pragma unroll
-      for (int c = 0; c < NCT; c++) b_cur[c] = b_nxt[c];
+            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS) << 6) + lane];
+            b_nxt = bv ? B[0] : make_double2(0.0, 0.0);
+          } else {
+#pragma unroll
+            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = a_cur[rt];
+            b_nxt = b_cur;
+          }
+        }
+#pragma unroll
+        for (int rt = 0; rt < NRT; rt++) {
+          accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur.x, accr[rt], 0, 0, 0);
+          acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur.y, acci[rt], 0, 0, 0);
+          accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_cur[rt].y, b_cur.y, accr[rt], 0, 0, 0);
+          acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].y, b_cur.x, acci[rt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int rt = 0; rt < NRT; rt++) a_cur[rt] = a_nxt[rt];
+        b_cur = b_nxt;
+      }
+      if (kn >= bd.K) break;
+      kk = kn;
     }
   }
+  if constexpr (KS > 1) {
+    // partial sums of waves kw > 0 go through LDS, one row tile at a time
+    __shared__ double red[4][8][64];
 #pragma unroll
-  for (int c = 0; c < NCT; c++) {
-    if (!tv[c]) continue;
-    double2* Dr = D + (size_t)trow[ee[c]] * NCK;
+    for (int rt = 0; rt < NRT; rt++) {
+      if (kw > 0) {
 #pragma unroll
-    for (int rt = 0; rt < NRT; rt++)
-#pragma unroll
-      for (int r = 0; r < 4; r++) {
-        int row = rt * 16 + kr + 4 * r;
-        if (row < NC) {
-          double2 v = Dr[row];
-          v.x += accr[c][rt][r];
-          v.y += acci[c][rt][r];
-          Dr[row] = v;
+        for (int r = 0; r < 4; r++) {
+          red[wave][r][lane] = accr[rt][r];
+          red[wave][4 + r][lane] = acci[rt][r];
         }
       }
+      __syncthreads();
+      if (kw == 0) {
+        for (int w = 1; w < KS; w++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            accr[rt][r] += red[wave + w][r][lane];
+            acci[rt][r] += red[wave + w][4 + r][lane];
+          }
+      }
+      __syncthreads();
+    }
   }
+  if (kw != 0 || !tv) return;
+  double2* Dr = D + (size_t)trow[ee] * NCK;
+#pragma unroll
+  for (int rt = 0; rt < NRT; rt++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      int row = rt * 16 + kr + 4 * r;
+      if (row < NC) {
+        double2 v = Dr[row];
+        v.x += accr[rt][r];
+        v.y += acci[rt][r];
+        Dr[row] = v;
+      }
+    }
 }
-extern "C" void lk_gemm(int nrt, int nct, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+// M2L (free-space and reaction operators): its own kernel name so that traces
+// time it apart from the shift GEMMs
+template <int NRT, int KS>
+__global__ __launch_bounds__(256) void k_m2l_gemm(const GBlock* blocks, const int* seq, const int* trow,
+                                                  const int* srow, int srow_stride, const double* __restrict__ ops,
+                                                  int opsz, int NKS, const double2* __restrict__ S, double2* D,
+                                                  int NCK, int NC) {
+  gemm_body<NRT, KS>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S, D, NCK, NC);
+}
+// M2M and L2L
+template <int NRT, int KS>
+__global__ __launch_bounds__(256) void k_shift_gemm(const GBlock* blocks, const int* seq, const int* trow,
+                                                    const int* srow, int srow_stride, const double* __restrict__ ops,
+                                                    int opsz, int NKS, const double2* __restrict__ S, double2* D,
+                                                    int NCK, int NC) {
+  gemm_body<NRT, KS>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S, D, NCK, NC);
+}
+extern "C" void lk_gemm(int m2l, int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
                         const int* srow, int srow_stride, const double* ops, int opsz, int NKS, const double* S,
                         double* D, int NCK, int NC, hipStream_t s) {
   if (!nblocks) return;
   const double2* S2 = (const double2*)S;
   double2* D2 = (double2*)D;
-#define GEMM_CASE(N, C)                                                                                         \
-  if (nrt == N && nct == C) {                                                                                   \
-    k_gemm<N, C><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, NC); \
-    return;                                                                                                     \
+#define GEMM_CASE(N, K)                                                                                          \
+  if (nrt == N && ks == K) {                                                                                     \
+    if (m2l)                                                                                                     \
+      k_m2l_gemm<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, \
+                                               NC);                                                              \
+    else                                                                                                         \
+      k_shift_gemm<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2,   \
+                                                 NCK, NC);                                                       \
+    return;                                                                                                      \
   }
   GEMM_CASE(1, 1) GEMM_CASE(2, 1) GEMM_CASE(3, 1) GEMM_CASE(4, 1) GEMM_CASE(5, 1) GEMM_CASE(6, 1) GEMM_CASE(7, 1)
   GEMM_CASE(8, 1) GEMM_CASE(1, 2) GEMM_CASE(2, 2) GEMM_CASE(3, 2) GEMM_CASE(4, 2) GEMM_CASE(5, 2) GEMM_CASE(6, 2)
+  GEMM_CASE(7, 2) GEMM_CASE(8, 2) GEMM_CASE(1, 4) GEMM_CASE(2, 4) GEMM_CASE(3, 4) GEMM_CASE(4, 4) GEMM_CASE(5, 4)
+  GEMM_CASE(6, 4) GEMM_CASE(7, 4) GEMM_CASE(8, 4)
 #undef GEMM_CASE
 }
 

@@ -62,7 +62,7 @@ def test_translation_operators_match_oracle(kind, p):
         assert rel(G, R) < TOL_OP, (kind, p, kw, b, rel(G, R))
 
 
-@pytest.mark.parametrize("p", [3, 5])
+@pytest.mark.parametrize("p", [3, 5, 8, 10])
 def test_reaction_operators_match_oracle(p):
     lf = _lfmm()
     d, k = (0.0, -1.2), (0.8, 1.5, 2.0)
