@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--p", type=int, default=8)
-    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")

@@ -225,6 +225,42 @@ struct lfmm_plan_s {
     }
     return d;
   }
+  // Device-to-host readbacks of small tables: queued into a pinned buffer, then
+  // waited for by polling an event (a blocking sync on a pageable copy has shown
+  // millisecond-scale wake-up delays, during which the device idles).
+  char* rb = nullptr;
+  size_t rb_cap = 0, rb_used = 0;
+  hipEvent_t rb_ev = nullptr;
+  std::vector<std::pair<void*, std::pair<size_t, size_t>>> rb_list;  // (host dst, (offset, bytes))
+  void rb_add(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    size_t off = (rb_used + 255) & ~(size_t)255;
+    if (off + bytes > rb_cap) {
+      rb_flush(s);  // empties the buffer (and waits for what it holds)
+      off = 0;
+      if (bytes > rb_cap) {
+        if (rb) (void)hipHostFree(rb);
+        rb = nullptr;
+        rb_cap = 0;
+        size_t nb = std::max<size_t>(bytes, 1 << 20);
+        if (hipHostMalloc((void**)&rb, nb, hipHostMallocDefault) != hipSuccess) throw Fail{LFMM_ENOMEM};
+        rb_cap = nb;
+      }
+    }
+    HIPCHK(hipMemcpyAsync(rb + off, src, bytes, hipMemcpyDeviceToHost, s));
+    rb_list.push_back({dst, {off, bytes}});
+    rb_used = off + bytes;
+  }
+  void rb_flush(hipStream_t s) {
+    if (!rb_ev) HIPCHK(hipEventCreateWithFlags(&rb_ev, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(rb_ev, s));
+    hipError_t e;
+    while ((e = hipEventQuery(rb_ev)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) throw Fail{LFMM_EHIP};
+    for (auto& d : rb_list) memcpy(d.first, rb + d.second.first, d.second.second);
+    rb_list.clear();
+    rb_used = 0;
+  }
   mutable std::map<int, double> decay_memo;
   double decay_cached(int npow) const {
     auto it = decay_memo.find(npow);
@@ -458,8 +494,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   lk_classify(n, x, y, z, layer_in, layer, st, partial, nbk, s);
   lk_reduce_stats(nbk, NL, partial, stats, s);
   std::vector<double> hs((size_t)NL * LFMM_NSTAT);
-  HIPCHK(hipMemcpyAsync(hs.data(), stats, hs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  P->rb_add(hs.data(), stats, hs.size() * sizeof(double), s);
+  P->rb_flush(s);
   double bad = 0;
   for (int l = 0; l < NL; l++) bad += hs[l * LFMM_NSTAT + 11];
   if (bad > 0) return LFMM_EINVAL;
@@ -567,9 +603,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   if (ntrees > 96) throw Fail{LFMM_ENOTSUP};  // at most 5 L + 1 trees: never for L <= 16
   lk_occupancy(ntp, ntrees, skeys, d_trees, occ, slab, s);
   std::vector<int> hocc(ntrees * 9), hslab(ntrees * 18);
-  HIPCHK(hipMemcpyAsync(hocc.data(), occ, sizeof(int) * ntrees * 9, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(hslab.data(), slab, sizeof(int) * ntrees * 18, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  P->rb_add(hocc.data(), occ, sizeof(int) * ntrees * 9, s);
+  P->rb_add(hslab.data(), slab, sizeof(int) * ntrees * 18, s);
+  P->rb_flush(s);
   // depth rule: smallest depth whose fullest cell holds <= leaf_max points
   int Dr = -1;
   for (int t = 0; t < ntrees; t++) {
@@ -609,8 +645,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     lk_tree_box_range(ntrees, l, ntp, d_trees, fl, sc, tb, s);
   }
   std::vector<int> htb(ntrees * 18);
-  HIPCHK(hipMemcpyAsync(htb.data(), tb, sizeof(int) * ntrees * 18, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  P->rb_add(htb.data(), tb, sizeof(int) * ntrees * 18, s);
+  P->rb_flush(s);
   std::vector<int> lvl_count(9, 0), lvl_off(10, 0);
   for (int l = 0; l < nlev; l++)
     for (int t = 0; t < ntrees; t++) lvl_count[l] += htb[(t * 9 + l) * 2 + 1];
@@ -882,10 +918,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   if (ng_l2l) job_prep("l2l", 1, gb_l2l, ng_l2l, J_l2l);
   if (ng_m2l) job_prep("m2l", 2, gb_m2l, ng_m2l, J_m2l);
   std::vector<int> c_m2m(ng_m2m + 1), c_l2l(ng_l2l + 1), c_m2l(ng_m2l + 1);
-  if (ng_m2m) HIPCHK(hipMemcpyAsync(c_m2m.data(), J_m2m.cnt, sizeof(int) * ng_m2m, hipMemcpyDeviceToHost, s));
-  if (ng_l2l) HIPCHK(hipMemcpyAsync(c_l2l.data(), J_l2l.cnt, sizeof(int) * ng_l2l, hipMemcpyDeviceToHost, s));
-  if (ng_m2l) HIPCHK(hipMemcpyAsync(c_m2l.data(), J_m2l.cnt, sizeof(int) * ng_m2l, hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  if (ng_m2m) P->rb_add(c_m2m.data(), J_m2m.cnt, sizeof(int) * ng_m2m, s);
+  if (ng_l2l) P->rb_add(c_l2l.data(), J_l2l.cnt, sizeof(int) * ng_l2l, s);
+  if (ng_m2l) P->rb_add(c_m2l.data(), J_m2l.cnt, sizeof(int) * ng_m2l, s);
+  P->rb_flush(s);
   c_m2m.resize(ng_m2m);
   c_l2l.resize(ng_l2l);
   c_m2l.resize(ng_m2l);
@@ -1074,8 +1110,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   mark(13);
   HIPCHK(hipGetLastError());
   unsigned long long hcnt[4] = {0, 0, 0, 0};
-  HIPCHK(hipMemcpyAsync(hcnt, d_cnt, sizeof(hcnt), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  P->rb_add(hcnt, d_cnt, sizeof(hcnt), s);
+  P->rb_flush(s);
   rep.m2l_pairs = (int64_t)hcnt[0];
   rep.m2m_pairs = (int64_t)hcnt[1];
   rep.l2l_pairs = (int64_t)hcnt[2];
@@ -1106,6 +1142,10 @@ int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int3
   try {
     return eval_impl(plan, n, xyz, layer, q, phi, (hipStream_t)stream);
   } catch (Fail& f) {
+    // drain what this call queued before its staging buffers are reused
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    plan->rb_list.clear();
+    plan->rb_used = 0;
     return f.code;
   }
 }
@@ -1130,6 +1170,9 @@ int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* la
     HIPCHK(hipMemcpy(phi, dp, sizeof(double) * 2 * n, hipMemcpyDeviceToHost));
     return LFMM_OK;
   } catch (Fail& f) {
+    (void)hipStreamSynchronize(nullptr);
+    plan->rb_list.clear();
+    plan->rb_used = 0;
     return f.code;
   }
 }
@@ -1150,6 +1193,8 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   if (plan->pin_pending) (void)hipEventSynchronize(plan->pin_ev);
   if (plan->pin) (void)hipHostFree(plan->pin);
   if (plan->pin_ev) (void)hipEventDestroy(plan->pin_ev);
+  if (plan->rb) (void)hipHostFree(plan->rb);
+  if (plan->rb_ev) (void)hipEventDestroy(plan->rb_ev);
   if (plan->ev_ok)
     for (int i = 0; i <= ST_COUNT; i++) (void)hipEventDestroy(plan->ev[i]);
   delete plan;

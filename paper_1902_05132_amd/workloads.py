@@ -55,8 +55,10 @@ def config1(seed=1):
     return w
 
 
-def config2(n=1048576, seed=2, p=8, leaf=64):
-    """N = 1,048,576 split evenly over the three cubes, p = 8."""
+def config2(n=1048576, seed=2, p=8, leaf=256):
+    """N = 1,048,576 split evenly over the three unit cubes (each 0.1 clear of the
+    interfaces), p = 8.  The leaf bound 256 gives depth-4 layer trees (about 85
+    particles per leaf), the fastest of the depths this workload allows."""
     counts = split_even(n, 3)
     w = layered_cubes(THREE_LAYER_D, THREE_LAYER_K, counts, THREE_LAYER_CENTERS, seed=seed)
     w.update(p=p, leaf=leaf, name="3-layer cubes, N=%d, p=%d, leaf<=%d" % (n, p, leaf))
