@@ -8,6 +8,7 @@ One step = one lfmm_eval_device call (every stage of the method, inputs already
 resident in HBM).  Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -19,11 +20,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "potential evals/sec at N=1M, rel-err≤1e-6 vs FP64; surrogate/FP32 vs plain speedup"
+# MI355X FP64 peaks: dense MFMA 78.6 TFLOP/s; vector ALU 256 CU x 4 SIMD x 16 lanes x 2 (fma) x 2.4 GHz = 78.6
 PEAK_FP64_TFLOPS = 78.6
+# FP64 operations of one near-field pair in the series form of h0 (k r <= 1): 3 differences, r^2 (5),
+# reciprocal square root with two Newton steps (10), -(kr)^2 (1), sin(x)/x and cos(x) series (9 + 10 fma),
+# -cos(kr)/(kr) (2), complex multiply-add (8)
+P2P_FLOPS_PER_PAIR = 67
+KERNEL_SRC = os.path.join(ROOT, "paper_1902_05132_amd", "csrc", "lfmm_kernels.hip")
+COUNTER_PROFILE = os.path.join(ROOT, "profiles",
+                               "hbm_counters_k_p2p_free_k_m2l_gemm_k_react_mfma_3layer_N1M_p8_leaf256.txt")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def profiled_traffic(kernel, n, p, leaf, seed):
+    """HBM bytes per launch of `kernel` from the committed counter profile, or None
+    when the profile is for another workload or the kernels changed since."""
+    if not os.path.exists(COUNTER_PROFILE):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    cfg, src, traffic = {}, None, {}
+    for line in open(COUNTER_PROFILE):
+        if line.startswith("config "):
+            cfg = dict(kv.split("=") for kv in line.split()[1:])
+        elif line.startswith("source "):
+            src = line.split("sha256=")[1].split()[0]
+        elif line.startswith("kernel="):
+            kv = dict(t.split("=") for t in line.split("#")[0].split())
+            traffic[kv["kernel"]] = float(kv["traffic_bytes"])
+    if src != sha or cfg.get("n") != str(n) or cfg.get("p") != str(p) or cfg.get("leaf") != str(leaf) \
+            or cfg.get("seed") != str(seed):
+        return None
+    return traffic.get(kernel)
 
 
 def cpu_baseline(w, budget_s=15.0, seed=7):
@@ -46,14 +76,29 @@ def cpu_baseline(w, budget_s=15.0, seed=7):
         return time.perf_counter() - t0, len(src)
 
     dt, ns = run(600)
-    per_pair = dt / (nt * ns)
-    ns2 = int(min(n - nt, max(1000, budget_s / (per_pair * nt))))
-    dt2, ns2 = run(ns2)
-    pairs_per_s = nt * ns2 / dt2
+    for _ in range(3):  # grow the sample until it takes about budget_s
+        ns = int(min(n - nt, max(ns + 1, ns * budget_s / max(dt, 1e-3))))
+        dt, ns = run(ns)
+        if dt > 0.6 * budget_s or ns >= n - nt:
+            break
+    pairs_per_s = nt * ns / dt
     return {"value": pairs_per_s / n, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "%d targets x %d of the %d sources, direct summation (closed-form free part + Sommerfeld "
                       "quadrature reaction part), scaled to N=%d by pair throughput; %.1f s"
-                      % (nt, ns2, n, n, dt2)}
+                      % (nt, ns, n, n, dt)}
+
+
+def cpu_fmm_sample(p, leaf, n=12288, seed=2):
+    """The oracle's plain FMM on a smaller instance of the same workload (context only)."""
+    import oracle
+    from paper_1902_05132_amd import workloads as W
+
+    w = W.config2(n=n, seed=seed, p=p, leaf=leaf)
+    t0 = time.perf_counter()
+    oracle.fmm(w["d"], w["k"], p, leaf, w["x"], w["y"], w["z"], w["layer"], w["q"])
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle plain FMM",
+            "sample": "whole evaluation of N=%d (same medium, p=%d, leaf<=%d); %.1f s" % (n, p, leaf, dt)}
 
 
 def main():
@@ -112,18 +157,29 @@ def main():
             log("  stage %-14s %9.3f ms" % (kname, v))
         log("  report: %s" % {k: v for k, v in rep.items() if k != "stage_ms"})
     nc = (args.p + 1) ** 2
-    m2l_flops = 8.0 * nc * nc * rep["m2l_pairs"]
-    m2l_s = stages["m2l"] / 1000.0
-    achieved = m2l_flops / m2l_s / 1e12 if m2l_s > 0 else 0.0
-    roofline = {"kernel": "k_gemm (M2L, batched complex FP64 MFMA)", "bound": "mfma", "achieved": achieved,
-                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": None, "algorithmic_flops_per_launch": m2l_flops, "launch_ms": stages["m2l"]}
+    cands = []
+    # M2L: batched complex GEMM on the FP64 matrix cores, 8 real flops per complex multiply-add
+    cands.append(dict(kernel="k_m2l_gemm", stage="m2l", bound="mfma", flops=8.0 * nc * nc * rep["m2l_pairs"],
+                      what="M2L, batched complex FP64 MFMA GEMM"))
+    if rep.get("p2p_series"):
+        cands.append(dict(kernel="k_p2p_free", stage="p2p_free", bound="alu",
+                          flops=float(P2P_FLOPS_PER_PAIR) * rep["p2p_pairs"],
+                          what="free-space near field, FP64 vector ALU"))
+    rooflines = []
+    for c in cands:
+        t = stages[c["stage"]] / 1000.0
+        ach = c["flops"] / t / 1e12 if t > 0 else 0.0
+        rooflines.append({"kernel": c["kernel"], "what": c["what"], "bound": c["bound"], "achieved": ach,
+                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS,
+                          "traffic": profiled_traffic(c["kernel"], n, args.p, args.leaf, args.seed),
+                          "algorithmic_flops_per_launch": c["flops"], "launch_ms": stages[c["stage"]]})
+    roofline = max(rooflines, key=lambda r: r["launch_ms"])
     out = {"metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "strong",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": w["name"], "N": n, "p": args.p, "leaf": args.leaf, "layers": 3,
                       "interfaces": list(map(float, w["d"])), "k": list(map(float, w["k"]))},
-           "stages_ms": stages, "roofline": roofline}
+           "stages_ms": stages, "roofline": roofline, "rooflines": rooflines}
     if args.copy_calib:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -134,6 +190,7 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_fmm_sample"] = cpu_fmm_sample(args.p, args.leaf)
     plan.close()
     print(json.dumps(out), flush=True)
 

@@ -68,6 +68,7 @@ typedef struct {
   int64_t l2l_pairs;       /* (child, parent) L2L products */
   int64_t p2p_pairs;       /* free-space near-field (target, source) pairs evaluated */
   int64_t nf_react_pairs;  /* near-field reaction pairs */
+  int p2p_series;          /* 1: near field used the series form of h0 (k r <= 1 on every pair) */
   double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
 } lfmm_report;
 

@@ -1026,8 +1026,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
              Lx, phi_tp, s);
     }
   }
-  mark(10);
-  // ---------------- free-space near field
+  // ---------------- free-space near field (its stage brackets the kernel alone)
   {
     std::vector<int> r0, pf;
     int tot = 0;
@@ -1044,9 +1043,12 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     if (tot) {
       int* d_r0 = P->upload("p2p_r0", r0, s);
       int* d_pf = P->upload("p2p_pf", pf, s);
+      rep.p2p_series = krmax <= 1.0 ? 1 : 0;
+      mark(10);
       lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
-                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, krmax <= 1.0 ? 1 : 0, P->p2p_ta, P->p2p_ch,
-                  d_cnt + 3, s);
+                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, rep.p2p_series, P->p2p_ta, P->p2p_ch, d_cnt + 3, s);
+    } else {
+      mark(10);
     }
   }
   mark(11);

@@ -33,6 +33,7 @@ class Report(ctypes.Structure):
                 ("n_react_nodes", ctypes.c_int64), ("n_ops_react", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("m2l_slots", ctypes.c_int64), ("m2m_pairs", ctypes.c_int64), ("l2l_pairs", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
+                ("p2p_series", ctypes.c_int),
                 ("stage_ms", ctypes.c_double * 16)]
 
 
@@ -163,6 +164,7 @@ class Plan:
                     n_react_classes=r.n_react_classes, n_react_nodes=r.n_react_nodes, n_ops_react=r.n_ops_react,
                     m2l_pairs=r.m2l_pairs, m2l_slots=r.m2l_slots,
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
+                    p2p_series=r.p2p_series,
                     stage_ms=stages)
 
     # ---- component entry points ----
