@@ -48,6 +48,10 @@ typedef struct {
   int max_depth;    /* largest octree depth, <= 8: 8 */
   double min_gap;   /* smallest allowed particle-to-interface distance: 1e-9 */
   int profile;      /* 1: record per-stage times (adds stream events): 0 */
+  int precision;    /* 0: FP64 throughout.  1: mixed precision -- near field in FP32 and the M2L
+                       on FP32 matrix cores (operators and multipole expansions rescaled per
+                       level), with the Bessel/Legendre recurrences, the Sommerfeld quadrature,
+                       the local-expansion accumulation and the final sums in FP64: 0 */
 } lfmm_options;
 
 typedef struct lfmm_plan_s lfmm_plan_t;
@@ -69,6 +73,7 @@ typedef struct {
   int64_t p2p_pairs;       /* free-space near-field (target, source) pairs evaluated */
   int64_t nf_react_pairs;  /* near-field reaction pairs */
   int p2p_series;          /* 1: near field used the series form of h0 (k r <= 1 on every pair) */
+  int precision;           /* the plan's precision option */
   double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
 } lfmm_report;
 

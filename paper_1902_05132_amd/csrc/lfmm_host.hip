@@ -153,6 +153,8 @@ struct lfmm_plan_s {
   int p, leaf_max, NC, NCK, NRT, NKS, NT, opsz;
   double b, min_gap;
   int max_depth, profile;
+  int prec;      // 0: FP64; 1: mixed (FP32 near field and FP32-MFMA M2L)
+  int prec_parts;  // which stages the mixed path runs in FP32: 1 near field, 2 M2L (both by default)
   int gemm_ks;   // M2L GEMM: waves sharing a 16-target tile (0 = chosen from the tile count)
   int p2p_ta;    // near field: targets per wave step (64 / p2p_ta sources)
   int p2p_ch;    // near field: sources per LDS tile
@@ -330,11 +332,19 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
   P->min_gap = 1e-9;
   P->max_depth = 8;
   P->profile = 0;
+  P->prec = 0;
+  P->prec_parts = 3;
+  if (const char* e = getenv("LFMM_PREC_PARTS")) P->prec_parts = atoi(e) & 3;  // accuracy studies
   if (opt) {
     if (opt->contour_b > 0) P->b = opt->contour_b;
     if (opt->max_depth > 0) P->max_depth = std::min(8, opt->max_depth);
     if (opt->min_gap > 0) P->min_gap = opt->min_gap;
     P->profile = opt->profile;
+    if (opt->precision < 0 || opt->precision > 1) {
+      delete P;
+      return LFMM_EINVAL;
+    }
+    P->prec = opt->precision;
   }
   memset(&P->rep, 0, sizeof(P->rep));
   try {
@@ -474,6 +484,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int n = (int)n64;
   lfmm_report& rep = P->rep;
   memset(&rep, 0, sizeof(rep));
+  rep.precision = P->prec;
   if (n == 0) return LFMM_OK;
   P->pin_reset();
   const Stack& st = P->st;
@@ -686,6 +697,20 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   lk_gather(ntp, sg, d_trees, ntrees, perm, d_lstart, x, y, z, q, st, px, py, pz, pq, s);
   mark(2);
   // ---------------- operators
+  // expansion scales of the mixed-precision M2L: c = 2^round(log2(1/(k h))) per (tree, level)
+  std::vector<double> hsc((size_t)ntrees * 9, 1.0);
+  for (int t = 0; t < ntrees; t++)
+    for (int l = 0; l <= trees[t].depth && l < 9; l++) {
+      double h = trees[t].S / (double)(1 << l);
+      hsc[(size_t)t * 9 + l] = std::ldexp(1.0, (int)std::lround(std::log2(1.0 / (trees[t].k * h))));
+    }
+  auto scl = [&](int t, int l) { return hsc[(size_t)t * 9 + l]; };
+  std::vector<double> opsc;  // (c_target, c_source) per operator (M2L operators only)
+  auto set_opsc = [&](int op, double ct, double cs) {
+    if ((size_t)(2 * op + 2) > opsc.size()) opsc.resize(2 * (size_t)op + 2, 1.0);
+    opsc[2 * (size_t)op] = ct;
+    opsc[2 * (size_t)op + 1] = cs;
+  };
   // op 0 is the zero operator
   int nops = 1;
   std::vector<OpDesc> fops;
@@ -701,6 +726,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
           int dx = o / 49 - 3, dy = (o / 7) % 7 - 3, dz = o % 7 - 3;
           if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
           OpDesc od{dx * h, dy * h, dz * h, T.k, 1, nops};
+          set_opsc(nops, scl(t, l), scl(t, l));
           m2l_op[((size_t)t * 9 + l) * 343 + o] = nops++;
           fops.push_back(od);
         }
@@ -774,6 +800,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
                       R.dy = dy * h;
                       R.kt = st.k[l];
                       R.cls = cls_of_r2[dx * dx + dy * dy];
+                      set_opsc(nops, scl(tt, lv), scl(ts, lv));
                       R.op = nops++;
                       rop_id[rkey(tt, ts, lv, j, i, dx, dy)] = R.op;
                       rops.push_back(R);
@@ -788,14 +815,24 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.n_ops_react = (int64_t)rops.size();
   double* ops = P->dev<double>("ops", (size_t)nops * opsz);
   lk_zero(ops, opsz, s);
+  float* ops32 = nullptr;
+  double* d_opsc = nullptr;
+  double* d_sc = P->upload("exp_scale", hsc, s);
+  const bool m2l32 = P->prec && (P->prec_parts & 2), p2p32 = P->prec && (P->prec_parts & 1);
+  if (m2l32) {
+    ops32 = P->dev<float>("ops32", (size_t)nops * opsz);
+    lk_zero((double*)ops32, opsz / 2, s);
+    opsc.resize(2 * (size_t)nops, 1.0);
+    d_opsc = P->upload("op_scale", opsc, s);
+  }
   OpDesc* d_fops = P->upload("fops", fops, s);
-  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, s);
+  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s);
   mark(3);
   if (!classes.empty()) {
     double* Iall = P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
     reaction_integrals(P, "ri", classes, Iall, s);
     ROpDesc* d_rops = P->upload("rops", rops, s);
-    lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, s);
+    lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s);
   }
   mark(4);
   // ---------------- GEMM jobs
@@ -996,7 +1033,15 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
               NCK, NC, s);
   mark(7);
   // ---------------- M2L (every level, free and reaction)
-  if (!b_m2l.empty())
+  if (!b_m2l.empty() && m2l32) {
+    // mixed precision: rescaled FP32 copy of the multipole expansions (its time is
+    // counted with the upward pass, so that the m2l stage brackets the GEMM alone)
+    float* M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
+    lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, s);
+    mark(7);
+    lk_gemm32(P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops32, opsz, NKS,
+              M32, Lx, NCK, NC, box_tree, box_level, d_sc, s);
+  } else if (!b_m2l.empty())
     lk_gemm(1, P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
             Lx, NCK, NC, s);
   mark(8);
@@ -1046,7 +1091,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       rep.p2p_series = krmax <= 1.0 ? 1 : 0;
       mark(10);
       lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
-                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, rep.p2p_series, P->p2p_ta, P->p2p_ch, d_cnt + 3, s);
+                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, rep.p2p_series, P->p2p_ta, P->p2p_ch, p2p32 ? 1 : 0,
+                  d_cnt + 3, s);
     } else {
       mark(10);
     }
@@ -1230,7 +1276,7 @@ int lfmm_translation(lfmm_plan_t* plan, int kind, double kw, const double* b, do
     d[0] = OpDesc{b[0], b[1], b[2], kw, kind, 0};
     OpDesc* dd = plan->upload("dbg_op", d, nullptr);
     double* ops = plan->dev<double>("dbg_ops", plan->opsz);
-    lk_transop(1, dd, ops, plan->opsz, plan->p, plan->NC, plan->NKS, plan->d_gaunt, nullptr);
+    lk_transop(1, dd, ops, plan->opsz, plan->p, plan->NC, plan->NKS, plan->d_gaunt, nullptr, nullptr, nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
     unpack_op(pk, plan->NC, plan->NKS, out);
@@ -1266,7 +1312,7 @@ int lfmm_reaction_operator(lfmm_plan_t* plan, int l, int a, int lp, int b, doubl
     r[0] = ROpDesc{dx, dy, st.k[l], 0, 0};
     ROpDesc* dr = plan->upload("dbg_rop", r, nullptr);
     double* ops = plan->dev<double>("dbg_ops", plan->opsz);
-    lk_react_expand(1, dr, I, ops, plan->opsz, plan->p, NC, plan->NKS, nullptr);
+    lk_react_expand(1, dr, I, ops, plan->opsz, plan->p, NC, plan->NKS, nullptr, nullptr, nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
     unpack_op(pk, NC, plan->NKS, out);

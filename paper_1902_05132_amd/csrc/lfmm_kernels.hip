@@ -11,6 +11,7 @@
 #include "lfmm_internal.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __constant__ double c_glx[LFMM_NGL];
 __constant__ double c_glw[LFMM_NGL];
@@ -444,8 +445,11 @@ __device__ __forceinline__ void decode_nm(int r, int* n, int* m) {
 // Free-space translation operators (Section 2.1 addition theorems):
 //   Op[(n,m),(nu,mu)] = 4 pi i^{n-nu} sum_q i^q z_q(k|b|) conj(Y_q^{m-mu}(b^)) G(nu,mu; q,m-mu; n)
 // G tabulated per (row, col, j), q = |n - nu| + 2 j.  One workgroup per operator.
+// With ops32 given, singular (M2L) operators are written in FP32 to ops32 instead,
+// scaled as Op[(n,m),(nu,mu)] c_t^{-n} c_s^{-nu} with (c_t, c_s) = opsc[op] (the
+// per-level expansion scales of the FP32 path).
 __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
-                                                 const double* gaunt) {
+                                                 const double* gaunt, float* ops32, const double2* opsc) {
   __shared__ cd zq[64];
   __shared__ cd Yq[64 * 64];
   OpDesc D = descs[blockIdx.x];
@@ -499,6 +503,9 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
   }
   __syncthreads();
   double* out = ops + (size_t)D.op * opsz;
+  const bool f32 = ops32 != nullptr && D.kind == 1;
+  float* out32 = f32 ? ops32 + (size_t)D.op * opsz : nullptr;
+  const double2 sc = f32 ? opsc[D.op] : make_double2(1.0, 1.0);
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   int P1 = p + 1;
   for (int e = threadIdx.x; e < NR * NK; e += 256) {
@@ -521,15 +528,24 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
         acc = acc + gv * (ipow(q) * zq[q] * cconj(Yq[cidx(q, s)]));
       }
       val = (4.0 * LFMM_PI) * (ipow(n - nu) * acc);
+      if (f32) {
+        int ns = (int)sqrt((double)row), nus = (int)sqrt((double)col);
+        val = (pow(sc.x, -(double)ns) * pow(sc.y, -(double)nus)) * val;
+      }
     }
     size_t pp = packed_pos(row, col, NKS);
-    out[pp] = val.x;
-    out[pp + 1] = val.y;
+    if (f32) {
+      out32[pp] = (float)val.x;
+      out32[pp + 1] = (float)val.y;
+    } else {
+      out[pp] = val.x;
+      out[pp + 1] = val.y;
+    }
   }
 }
 extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
-                           const double* gaunt, hipStream_t s) {
-  if (nops) k_transop<<<nops, 256, 0, s>>>(descs, ops, opsz, p, NC, NKS, gaunt);
+                           const double* gaunt, float* ops32, const double* opsc, hipStream_t s) {
+  if (nops) k_transop<<<nops, 256, 0, s>>>(descs, ops, opsz, p, NC, NKS, gaunt, ops32, (const double2*)opsc);
 }
 
 // ---------------------------------------------------------------------------
@@ -793,11 +809,13 @@ extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* me
 // T[(n,m),(n',m')] = (4 pi/k_t) i^n (-i)^{n'} i^q e^{i q phi} I[(n,m),(n',m')], q = m' - m,
 // phi = arg of the lateral offset target - source.  One workgroup per operator.
 __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const double* Iall, double* ops, int opsz,
-                                                      int p, int NC, int NKS) {
+                                                      int p, int NC, int NKS, float* ops32, const double2* opsc) {
   ROpDesc R = rops[blockIdx.x];
   double phi = atan2(R.dy, R.dx);
   const double* I = Iall + (size_t)R.cls * NC * NC * 2;
   double* out = ops + (size_t)R.op * opsz;
+  float* out32 = ops32 ? ops32 + (size_t)R.op * opsz : nullptr;
+  const double2 sc = ops32 ? opsc[R.op] : make_double2(1.0, 1.0);
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   double pre = 4.0 * LFMM_PI / R.kt;
   for (int e = threadIdx.x; e < NR * NK; e += 256) {
@@ -812,15 +830,21 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
       sincos(q * phi, &sn, &cs);
       cd iv = mk(I[2 * ((size_t)row * NC + col)], I[2 * ((size_t)row * NC + col) + 1]);
       val = pre * (ipow(n - n2 + q) * (mk(cs, sn) * iv));
+      if (out32) val = (pow(sc.x, -(double)n) * pow(sc.y, -(double)n2)) * val;
     }
     size_t pp = packed_pos(row, col, NKS);
-    out[pp] = val.x;
-    out[pp + 1] = val.y;
+    if (out32) {
+      out32[pp] = (float)val.x;
+      out32[pp + 1] = (float)val.y;
+    } else {
+      out[pp] = val.x;
+      out[pp + 1] = val.y;
+    }
   }
 }
 extern "C" void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p,
-                                int NC, int NKS, hipStream_t s) {
-  if (nops) k_react_expand<<<nops, 256, 0, s>>>(rops, Iall, ops, opsz, p, NC, NKS);
+                                int NC, int NKS, float* ops32, const double* opsc, hipStream_t s) {
+  if (nops) k_react_expand<<<nops, 256, 0, s>>>(rops, Iall, ops, opsz, p, NC, NKS, ops32, (const double2*)opsc);
 }
 
 // ---------------------------------------------------------------------------
@@ -1168,6 +1192,200 @@ extern "C" void lk_gemm(int m2l, int nrt, int ks, int nblocks, const GBlock* blo
 }
 
 // ---------------------------------------------------------------------------
+// FP32 path of the M2L (mixed precision).  Expansions of a box at level l of a
+// tree with wavenumber k are rescaled by powers c^n of c = 2^round(log2(1/(k h_l)))
+// (h_l the box size), which brings M_n ~ (k h)^n and L_n ~ (k h)^{-n} to O(1) and
+// keeps FP32 away from overflow (h_{2p}(k r) reaches 1e44 at p = 10 on fine
+// levels); the operators are stored pre-scaled, T[(n,m),(nu,mu)] c_t^{-n} c_s^{-nu}.
+// The GEMM runs on v_mfma_f32_16x16x4f32 (D element r of lane l = (row
+// 4 (l/16) + r, col l%16)); each operator's FP32 partial sum is moved into FP64
+// accumulators when the operator is done, and the result is added, unscaled, to
+// the FP64 local expansions.
+// ---------------------------------------------------------------------------
+__global__ void k_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const double* sc,
+                           const double2* M, float2* M32) {
+  long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long long)nrows * NCK) return;
+  int row = (int)(e / NCK), col = (int)(e % NCK);
+  float2 v = make_float2(0.f, 0.f);
+  if (col < NC) {
+    double c = sc[box_tree[row] * 9 + box_level[row]];
+    int n = (int)sqrt((double)col);
+    while (n * n > col) n--;
+    double f = pow(c, (double)n);
+    double2 m = M[e];
+    v = make_float2((float)(m.x * f), (float)(m.y * f));
+  }
+  M32[e] = v;
+}
+extern "C" void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const double* sc,
+                            const double* M, float* M32, hipStream_t s) {
+  long long n = (long long)nrows * NCK;
+  if (n) k_m_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(nrows, NCK, NC, box_tree, box_level, sc,
+                                                                (const double2*)M, (float2*)M32);
+}
+template <int NRT, int KS>
+__global__ __launch_bounds__(256) void k_m2l_gemm32(const GBlock* blocks, const int* seq, const int* trow,
+                                                    const int* srow, int srow_stride, const float* __restrict__ ops,
+                                                    int opsz, int NKS, const float2* __restrict__ S, double2* D,
+                                                    int NCK, int NC, const int* box_tree, const int* box_level,
+                                                    const double* sc) {
+  GBlock bd = blocks[blockIdx.x];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kr = lane >> 4;
+  const int cg = wave / KS, kw = wave % KS;
+  const int tt = cg * 16 + col;
+  const bool tv = tt < bd.nt;
+  const int ee = bd.e0 + (tv ? tt : 0);
+  const int* my_srow = srow + (size_t)ee * srow_stride;
+  v4f accr[NRT], acci[NRT];
+  v4d dr[NRT], di[NRT];  // FP64 sums of the per-operator FP32 partial sums
+#pragma unroll
+  for (int i = 0; i < NRT; i++) {
+    accr[i] = (v4f){0, 0, 0, 0};
+    acci[i] = (v4f){0, 0, 0, 0};
+    dr[i] = (v4d){0, 0, 0, 0};
+    di[i] = (v4d){0, 0, 0, 0};
+  }
+  const float2* A2 = (const float2*)ops;
+  const size_t opstride = (size_t)(opsz >> 1);
+  int kk = kw, sr = -1;
+  while (kk < bd.K) {
+    sr = tv ? my_srow[kk] : -1;
+    if (__ballot(sr >= 0)) break;
+    kk += KS;
+  }
+  if (kk < bd.K) {
+    const float2* A = A2 + (size_t)seq[bd.seq0 + kk] * opstride;
+    const float2* B = S + (size_t)(sr >= 0 ? sr : 0) * NCK + kr;
+    bool bv = sr >= 0;
+    float2 a_cur[NRT], b_cur;
+#pragma unroll
+    for (int rt = 0; rt < NRT; rt++) a_cur[rt] = A[((size_t)(rt * NKS) << 6) + lane];
+    b_cur = bv ? B[0] : make_float2(0.f, 0.f);
+    while (true) {
+      int kn = kk + KS, srn = -1, opn = 0;
+      if (kn < bd.K) {
+        srn = tv ? my_srow[kn] : -1;
+        opn = seq[bd.seq0 + kn];
+      }
+      for (int ks = 0; ks < NKS; ks++) {
+        float2 a_nxt[NRT], b_nxt;
+        if (ks + 1 < NKS) {
+#pragma unroll
+          for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS + ks + 1) << 6) + lane];
+          b_nxt = bv ? B[(ks + 1) * 4] : make_float2(0.f, 0.f);
+        } else {
+          while (kn < bd.K && !__ballot(srn >= 0)) {
+            kn += KS;
+            if (kn < bd.K) {
+              srn = tv ? my_srow[kn] : -1;
+              opn = seq[bd.seq0 + kn];
+            }
+          }
+          if (kn < bd.K) {
+            A = A2 + (size_t)opn * opstride;
+            B = S + (size_t)(srn >= 0 ? srn : 0) * NCK + kr;
+            bv = srn >= 0;
+#pragma unroll
+            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS) << 6) + lane];
+            b_nxt = bv ? B[0] : make_float2(0.f, 0.f);
+          } else {
+#pragma unroll
+            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = a_cur[rt];
+            b_nxt = b_cur;
+          }
+        }
+#pragma unroll
+        for (int rt = 0; rt < NRT; rt++) {
+          accr[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[rt].x, b_cur.x, accr[rt], 0, 0, 0);
+          acci[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[rt].x, b_cur.y, acci[rt], 0, 0, 0);
+          accr[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_cur[rt].y, b_cur.y, accr[rt], 0, 0, 0);
+          acci[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[rt].y, b_cur.x, acci[rt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int rt = 0; rt < NRT; rt++) a_cur[rt] = a_nxt[rt];
+        b_cur = b_nxt;
+      }
+      // one operator done: move its partial sums to FP64
+#pragma unroll
+      for (int rt = 0; rt < NRT; rt++) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          dr[rt][r] += (double)accr[rt][r];
+          di[rt][r] += (double)acci[rt][r];
+        }
+        accr[rt] = (v4f){0, 0, 0, 0};
+        acci[rt] = (v4f){0, 0, 0, 0};
+      }
+      if (kn >= bd.K) break;
+      kk = kn;
+    }
+  }
+  if constexpr (KS > 1) {
+    __shared__ double red[4][8][64];
+#pragma unroll
+    for (int rt = 0; rt < NRT; rt++) {
+      if (kw > 0) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+          red[wave][r][lane] = dr[rt][r];
+          red[wave][4 + r][lane] = di[rt][r];
+        }
+      }
+      __syncthreads();
+      if (kw == 0) {
+        for (int w = 1; w < KS; w++)
+#pragma unroll
+          for (int r = 0; r < 4; r++) {
+            dr[rt][r] += red[wave + w][r][lane];
+            di[rt][r] += red[wave + w][4 + r][lane];
+          }
+      }
+      __syncthreads();
+    }
+  }
+  if (kw != 0 || !tv) return;
+  const int tr = trow[ee];
+  const double c = sc[box_tree[tr] * 9 + box_level[tr]];
+  double2* Dr = D + (size_t)tr * NCK;
+#pragma unroll
+  for (int rt = 0; rt < NRT; rt++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      int row = rt * 16 + 4 * kr + r;
+      if (row < NC) {
+        int n = (int)sqrt((double)row);
+        while (n * n > row) n--;
+        double f = pow(c, (double)n);
+        double2 v = Dr[row];
+        v.x += f * dr[rt][r];
+        v.y += f * di[rt][r];
+        Dr[row] = v;
+      }
+    }
+}
+extern "C" void lk_gemm32(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+                          const int* srow, int srow_stride, const float* ops, int opsz, int NKS, const float* S,
+                          double* D, int NCK, int NC, const int* box_tree, const int* box_level, const double* sc,
+                          hipStream_t s) {
+  if (!nblocks) return;
+  const float2* S2 = (const float2*)S;
+  double2* D2 = (double2*)D;
+#define GEMM32_CASE(N, K)                                                                                     \
+  if (nrt == N && ks == K) {                                                                                  \
+    k_m2l_gemm32<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2,  \
+                                               NCK, NC, box_tree, box_level, sc);                             \
+    return;                                                                                                   \
+  }
+  GEMM32_CASE(1, 1) GEMM32_CASE(2, 1) GEMM32_CASE(3, 1) GEMM32_CASE(4, 1) GEMM32_CASE(5, 1) GEMM32_CASE(6, 1)
+  GEMM32_CASE(7, 1) GEMM32_CASE(8, 1) GEMM32_CASE(1, 2) GEMM32_CASE(2, 2) GEMM32_CASE(3, 2) GEMM32_CASE(4, 2)
+  GEMM32_CASE(5, 2) GEMM32_CASE(6, 2) GEMM32_CASE(7, 2) GEMM32_CASE(8, 2) GEMM32_CASE(1, 4) GEMM32_CASE(2, 4)
+  GEMM32_CASE(3, 4) GEMM32_CASE(4, 4) GEMM32_CASE(5, 4) GEMM32_CASE(6, 4) GEMM32_CASE(7, 4) GEMM32_CASE(8, 4)
+#undef GEMM32_CASE
+}
+
+// ---------------------------------------------------------------------------
 // GEMM job construction: group ids per target box, then source rows.
 // mode 0: M2M targets (parents), mode 1: L2L targets, mode 2: M2L targets.
 // gbase[t*9 + l] = first group id of (tree, level) or -1.
@@ -1459,12 +1677,175 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
     __syncthreads();
   }
 }
+// FP32 variant of the near field (mixed precision).  Coordinates relative to the
+// target leaf's first particle are formed in FP64 and kept as FP32 hi + lo pairs,
+// so a pair difference (hi - hi) + (lo - lo) is accurate to FP32 rounding of the
+// difference itself, also for the closest pairs; pairs are evaluated and
+// partially summed in FP32 (seven-term series of sin(x)/x and cos(x), truncation
+// below 1e-11 for u <= 1; v_rsq_f32), and each target's sum is accumulated in FP64.
+template <bool POLY, int TA, int CH>
+__global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row0, const int* seg_prefix,
+                                                    const int* box_start, const int* box_cnt, const int* box_code,
+                                                    const int* box_tree, const int* box_level, const TreeInfo* trees,
+                                                    const long long* grid_off, const int* grid, const double* px,
+                                                    const double* py, const double* pz, const double* pq,
+                                                    const int* sg, double* phi_tp, unsigned long long* npairs) {
+  constexpr int TB = 64 / TA;
+  __shared__ float s_x[CH], s_y[CH], s_z[CH], s_xl[CH], s_yl[CH], s_zl[CH], s_qr[CH], s_qi[CH];
+  __shared__ float t_x[P2P_TMAX], t_y[P2P_TMAX], t_z[P2P_TMAX], t_xl[P2P_TMAX], t_yl[P2P_TMAX], t_zl[P2P_TMAX];
+  __shared__ double acc_r[P2P_TMAX], acc_i[P2P_TMAX];
+  __shared__ int nb_start[27], nb_pre[28];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int a = lane / TB, b = lane % TB;
+  int li = blockIdx.x;
+  int sgm = seg_find(seg_prefix, nseg, li);
+  int R = seg_row0[sgm] + (li - seg_prefix[sgm]);
+  int t = box_tree[R], l = box_level[R];
+  const double k = trees[t].k;
+  int ix, iy, iz;
+  demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
+  const int s0 = box_start[R], nt = box_cnt[R];
+  if (tid < 27) {
+    int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+    int Rn = grid_get(grid_off, grid, t, l, ix + dx, iy + dy, iz + dz);
+    nb_start[tid] = Rn >= 0 ? box_start[Rn] : 0;
+    nb_pre[tid + 1] = Rn >= 0 ? box_cnt[Rn] : 0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    nb_pre[0] = 0;
+    for (int i = 1; i <= 27; i++) nb_pre[i] += nb_pre[i - 1];
+    if (nt) atomicAdd(npairs, (unsigned long long)nt * (unsigned long long)(nb_pre[27] - 1));
+  }
+  __syncthreads();
+  if (nt == 0) return;
+  const int total = nb_pre[27];
+  const double xr = px[s0], yr = py[s0], zr = pz[s0];
+  const float kf = (float)k, k2 = (float)(k * k), invk = (float)(1.0 / k);
+  for (int c0 = 0; c0 < nt; c0 += P2P_TMAX) {
+    const int ntp = nt - c0 < P2P_TMAX ? nt - c0 : P2P_TMAX;
+    const int ntb = (ntp + TA - 1) / TA;
+    if (tid < ntp) {
+      double ux = px[s0 + c0 + tid] - xr, uy = py[s0 + c0 + tid] - yr, uz = pz[s0 + c0 + tid] - zr;
+      t_x[tid] = (float)ux;
+      t_y[tid] = (float)uy;
+      t_z[tid] = (float)uz;
+      t_xl[tid] = (float)(ux - (double)t_x[tid]);
+      t_yl[tid] = (float)(uy - (double)t_y[tid]);
+      t_zl[tid] = (float)(uz - (double)t_z[tid]);
+      acc_r[tid] = 0.0;
+      acc_i[tid] = 0.0;
+    }
+    for (int base = 0; base < total; base += CH) {
+      const int nch = total - base < CH ? total - base : CH;
+      __syncthreads();
+      for (int f = tid; f < nch; f += 256) {
+        int g = base + f;
+        int lo = 0, hi = 26;
+        while (lo < hi) {
+          int mid = (lo + hi + 1) >> 1;
+          if (nb_pre[mid] <= g) lo = mid;
+          else hi = mid - 1;
+        }
+        int ss = nb_start[lo] + (g - nb_pre[lo]);
+        double ux = px[ss] - xr, uy = py[ss] - yr, uz = pz[ss] - zr;
+        float hx = (float)ux, hy = (float)uy, hz = (float)uz;
+        s_x[f] = hx;
+        s_y[f] = hy;
+        s_z[f] = hz;
+        s_xl[f] = (float)(ux - (double)hx);
+        s_yl[f] = (float)(uy - (double)hy);
+        s_zl[f] = (float)(uz - (double)hz);
+        s_qr[f] = (float)pq[2 * ss];
+        s_qi[f] = (float)pq[2 * ss + 1];
+      }
+      __syncthreads();
+      for (int tb = wave; tb < ntb; tb += 4) {
+        const int ti = tb * TA + a;
+        const bool tv = ti < ntp;
+        const int tr = tv ? ti : 0;
+        const float x0 = t_x[tr], y0 = t_y[tr], z0 = t_z[tr], x0l = t_xl[tr], y0l = t_yl[tr], z0l = t_zl[tr];
+        float ax = 0.f, ay = 0.f;
+#pragma unroll 2
+        for (int j = b; j < nch; j += TB) {
+          float dx = (x0 - s_x[j]) + (x0l - s_xl[j]), dy = (y0 - s_y[j]) + (y0l - s_yl[j]),
+                dz = (z0 - s_z[j]) + (z0l - s_zl[j]);
+          float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+          bool ok = r2 > 0.f;
+          float r2s = ok ? r2 : 1.f;
+          float y = __builtin_amdgcn_rsqf(r2s);
+          float hr, hi;
+          if (POLY) {
+            constexpr float s1 = (float)inv_fact(3), s2 = (float)inv_fact(5), s3 = (float)inv_fact(7),
+                            s4 = (float)inv_fact(9), s5 = (float)inv_fact(11), s6 = (float)inv_fact(13);
+            constexpr float c1 = (float)inv_fact(2), c2 = (float)inv_fact(4), c3 = (float)inv_fact(6),
+                            c4 = (float)inv_fact(8), c5 = (float)inv_fact(10), c6 = (float)inv_fact(12);
+            float v = -k2 * r2s;
+            float ps = fmaf(s6, v, s5);
+            ps = fmaf(ps, v, s4);
+            ps = fmaf(ps, v, s3);
+            ps = fmaf(ps, v, s2);
+            ps = fmaf(ps, v, s1);
+            ps = fmaf(ps, v, 1.f);
+            float pc = fmaf(c6, v, c5);
+            pc = fmaf(pc, v, c4);
+            pc = fmaf(pc, v, c3);
+            pc = fmaf(pc, v, c2);
+            pc = fmaf(pc, v, c1);
+            pc = fmaf(pc, v, 1.f);
+            hr = ps;
+            hi = -pc * (y * invk);
+          } else {
+            float kr = kf * (r2s * y);
+            float sn, cs;
+            sincosf(kr, &sn, &cs);
+            float ikr = y * invk;
+            hr = sn * ikr;
+            hi = -cs * ikr;
+          }
+          hr = ok ? hr : 0.f;
+          hi = ok ? hi : 0.f;
+          float qr = s_qr[j], qi = s_qi[j];
+          ax = fmaf(qr, hr, fmaf(-qi, hi, ax));
+          ay = fmaf(qr, hi, fmaf(qi, hr, ay));
+        }
+#pragma unroll
+        for (int m = TB / 2; m >= 1; m >>= 1) {
+          ax += __shfl_xor(ax, m, 64);
+          ay += __shfl_xor(ay, m, 64);
+        }
+        if (b == 0 && tv) {
+          acc_r[ti] += (double)ax;
+          acc_i[ti] += (double)ay;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < ntp) {
+      int g = sg[s0 + c0 + tid];
+      phi_tp[2 * g] += acc_r[tid];
+      phi_tp[2 * g + 1] += acc_i[tid];
+    }
+    __syncthreads();
+  }
+}
 extern "C" void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
                             const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
                             const TreeInfo* trees, const long long* grid_off, const int* grid, const double* px,
                             const double* py, const double* pz, const double* pq, const int* sg, double* phi_tp,
-                            int poly, int ta, int ch, unsigned long long* npairs, hipStream_t s) {
+                            int poly, int ta, int ch, int f32, unsigned long long* npairs, hipStream_t s) {
   if (!total) return;
+  if (f32) {
+    if (poly)
+      k_p2p_free32<true, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
+                                                       box_tree, box_level, trees, grid_off, grid, px, py, pz, pq,
+                                                       sg, phi_tp, npairs);
+    else
+      k_p2p_free32<false, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
+                                                        box_tree, box_level, trees, grid_off, grid, px, py, pz, pq,
+                                                        sg, phi_tp, npairs);
+    return;
+  }
 #define P2P_CASE(PO, T, C)                                                                                      \
   if ((poly != 0) == PO && ta == T && ch == C) {                                                                \
     k_p2p_free<PO, T, C><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,        \

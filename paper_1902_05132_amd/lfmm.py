@@ -24,7 +24,7 @@ class LfmmError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("contour_b", ctypes.c_double), ("max_depth", ctypes.c_int), ("min_gap", ctypes.c_double),
-                ("profile", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("precision", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -33,7 +33,7 @@ class Report(ctypes.Structure):
                 ("n_react_nodes", ctypes.c_int64), ("n_ops_react", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("m2l_slots", ctypes.c_int64), ("m2m_pairs", ctypes.c_int64), ("l2l_pairs", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
-                ("p2p_series", ctypes.c_int),
+                ("p2p_series", ctypes.c_int), ("precision", ctypes.c_int),
                 ("stage_ms", ctypes.c_double * 16)]
 
 
@@ -88,13 +88,14 @@ def _f64(a):
 class Plan:
     """lfmm_plan wrapper: d (L interfaces, decreasing), k (L+1 wavenumbers), order p, leaf size."""
 
-    def __init__(self, d, k, p, leaf_max, contour_b=0.5, max_depth=8, min_gap=1e-9, profile=False):
+    def __init__(self, d, k, p, leaf_max, contour_b=0.5, max_depth=8, min_gap=1e-9, profile=False, precision=0):
+        """precision 0: FP64 throughout; 1: mixed (FP32 near field and FP32-MFMA M2L)."""
         self.lib = load()
         self.d = _f64(d)
         self.k = _f64(k)
         self.p = int(p)
         self.L = len(self.d)
-        opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0)
+        opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0, int(precision))
         h = ctypes.c_void_p()
         dptr = self.d.ctypes.data_as(_D) if self.L else None
         _check(self.lib.lfmm_plan(self.L, dptr, self.k.ctypes.data_as(_D), self.p, int(leaf_max),
@@ -164,7 +165,7 @@ class Plan:
                     n_react_classes=r.n_react_classes, n_react_nodes=r.n_react_nodes, n_ops_react=r.n_ops_react,
                     m2l_pairs=r.m2l_pairs, m2l_slots=r.m2l_slots,
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
-                    p2p_series=r.p2p_series,
+                    p2p_series=r.p2p_series, precision=r.precision,
                     stage_ms=stages)
 
     # ---- component entry points ----

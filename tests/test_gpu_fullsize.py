@@ -78,3 +78,20 @@ def test_full_size_linearity(full):
     rhs = a * phi.cpu().numpy() + b * phi2.cpu().numpy()
     rel = np.max(np.abs(lhs - rhs)) / np.max(np.abs(rhs))
     assert rel < 1e-12, rel
+
+
+def test_full_size_mixed_precision(full):
+    """The mixed-precision path at full size against the FP64 result (same trees)."""
+    import torch
+    from paper_1902_05132_amd import lfmm
+    w, P, xyz, q, phi = full
+    P32 = lfmm.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], precision=1)
+    phi32 = torch.empty_like(q)
+    P32.eval_device(xyz, q, phi32)
+    torch.cuda.synchronize()
+    assert P32.report()["free_depth"] == P.report()["free_depth"]
+    a, b = phi32.cpu().numpy(), phi.cpu().numpy()
+    e2 = np.linalg.norm(a - b) / np.linalg.norm(b)
+    emax = np.max(np.abs(a - b)) / np.max(np.abs(b))
+    print("full size mixed vs FP64: Err2 %.2e Errmax %.2e" % (e2, emax))
+    assert e2 < 1e-6 and emax < 1e-6
