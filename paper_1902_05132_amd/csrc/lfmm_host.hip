@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <tuple>
@@ -41,11 +42,11 @@ struct Fail {
 };
 
 enum {
-  ST_CLASSIFY, ST_TREE, ST_OPS_FREE, ST_OPS_REACT, ST_JOBS, ST_P2M, ST_M2M, ST_M2L, ST_L2L, ST_L2P, ST_P2P,
-  ST_NEAR_REACT, ST_SUM, ST_COUNT
+  ST_CLASSIFY, ST_TREE, ST_OPS_FREE, ST_REACT_TABLES, ST_REACT_MFMA, ST_REACT_EXPAND, ST_JOBS, ST_P2M, ST_M2M,
+  ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_NEAR_REACT, ST_SUM, ST_COUNT
 };
-const char* kStageNames[ST_COUNT] = {"classify", "tree", "ops_free", "ops_reaction", "jobs", "p2m", "m2m",
-                                     "m2l", "l2l", "l2p", "p2p_free", "near_reaction", "sum"};
+const char* kStageNames[ST_COUNT] = {"classify", "tree", "ops_free", "react_tables", "react_mfma", "react_expand",
+                                     "jobs", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p_free", "near_reaction", "sum"};
 
 // ---------------------------------------------------------------------------
 // Host-side constants owned by the library (independent of any checker):
@@ -370,7 +371,7 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
 // node tables per rule group (classes with the same quadrature rule and rho),
 // F per class, then the MFMA node sum.
 static void reaction_integrals(lfmm_plan_s* P, const char* tag, std::vector<ClassDesc>& classes, double* Iall,
-                               hipStream_t s) {
+                               hipStream_t s, const std::function<void()>& after_tables = nullptr) {
   if (classes.empty()) return;
   const int p = P->p, Q = 2 * p, NT = P->NT, NL = P->st.L + 1;
   std::map<std::tuple<double, double, double, double, int, int, double>, int> key_rg;
@@ -443,6 +444,7 @@ static void reaction_integrals(lfmm_plan_s* P, const char* tag, std::vector<Clas
   double* F = P->dev<double>((t + "_F").c_str(), (size_t)Ftot * 2);
   lk_react_tables((int)rgs.size(), d_rgs, Ntot, P->st, p, J, Pt, s);
   lk_react_F((int)classes.size(), d_cls, maxnn, P->st, F, s);
+  if (after_tables) after_tables();
   lk_react_mfma(nwg, (int)scs.size(), d_scs, d_mem, d_cls, p, Ntot, J, Pt, F, Iall, P->NC, s);
 }
 
@@ -830,11 +832,15 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   mark(3);
   if (!classes.empty()) {
     double* Iall = P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-    reaction_integrals(P, "ri", classes, Iall, s);
+    reaction_integrals(P, "ri", classes, Iall, s, [&]() { mark(4); });
+    mark(5);
     ROpDesc* d_rops = P->upload("rops", rops, s);
     lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s);
+  } else {
+    mark(4);
+    mark(5);
   }
-  mark(4);
+  mark(6);
   // ---------------- GEMM jobs
   // group tables (host): M2M groups per (tree, parent level), level-major descending;
   // L2L groups per (tree, level, class) level-major ascending; M2L groups per (tree, level, class)
@@ -1003,7 +1009,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* d_sq_m2m = P->upload("sq_m2m", seq_m2m, s);
   int* d_sq_l2l = P->upload("sq_l2l", seq_l2l, s);
   int* d_sq_m2l = P->upload("sq_m2l", seq_m2l, s);
-  mark(5);
+  mark(7);
   // ---------------- upward pass
   double* M = P->dev<double>("M", (size_t)NR * NCK * 2);
   double* Lx = P->dev<double>("L", (size_t)NR * NCK * 2);
@@ -1026,31 +1032,31 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     lk_p2m((int)seg_row0.size(), d_r0, d_pf, ptot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, px, py,
            pz, pq, p, NCK, M, s);
   }
-  mark(6);
+  mark(8);
   for (int lp = Dmax - 1; lp >= 2; lp--)
     if (bc_m2m[lp] > 0)
       lk_gemm(0, P->NRT, 1, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
               NCK, NC, s);
-  mark(7);
+  mark(9);
   // ---------------- M2L (every level, free and reaction)
   if (!b_m2l.empty() && m2l32) {
     // mixed precision: rescaled FP32 copy of the multipole expansions (its time is
     // counted with the upward pass, so that the m2l stage brackets the GEMM alone)
     float* M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
     lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, s);
-    mark(7);
+    mark(9);
     lk_gemm32(P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops32, opsz, NKS,
               M32, Lx, NCK, NC, box_tree, box_level, d_sc, s);
   } else if (!b_m2l.empty())
     lk_gemm(1, P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
             Lx, NCK, NC, s);
-  mark(8);
+  mark(10);
   // ---------------- downward pass
   for (int l = 3; l <= Dmax; l++)
     if (bc_l2l[l] > 0)
       lk_gemm(0, P->NRT, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx,
               NCK, NC, s);
-  mark(9);
+  mark(11);
   double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
   lk_zero(phi_tp, 2 * (size_t)ntp, s);
   {
@@ -1089,15 +1095,15 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       int* d_r0 = P->upload("p2p_r0", r0, s);
       int* d_pf = P->upload("p2p_pf", pf, s);
       rep.p2p_series = krmax <= 1.0 ? 1 : 0;
-      mark(10);
+      mark(12);
       lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
                   d_grid_off, grid, px, py, pz, pq, sg, phi_tp, rep.p2p_series, P->p2p_ta, P->p2p_ch, p2p32 ? 1 : 0,
                   d_cnt + 3, s);
     } else {
-      mark(10);
+      mark(12);
     }
   }
-  mark(11);
+  mark(13);
   // ---------------- reaction near field (adjacent leaves across the interface)
   if (L >= 1 && Dr >= 1) {
     for (int l = 0; l < NL; l++)
@@ -1144,7 +1150,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
         rep.nf_react_pairs += 1;
       }
   }
-  mark(12);
+  mark(14);
   // ---------------- component sum
   int max_tt = 3;
   std::vector<int> tgt_list(NL * max_tt, -1);
@@ -1155,7 +1161,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   int* d_tl = P->upload("tgt_list", tgt_list, s);
   lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, s);
-  mark(13);
+  mark(15);
   HIPCHK(hipGetLastError());
   unsigned long long hcnt[4] = {0, 0, 0, 0};
   P->rb_add(hcnt, d_cnt, sizeof(hcnt), s);
@@ -1165,12 +1171,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.l2l_pairs = (int64_t)hcnt[2];
   rep.p2p_pairs = (int64_t)hcnt[3];
   if (prof) {
-    // stage i spans events i+1 .. i+2 of the marks above (classify = 0..1)
-    int map_ev[ST_COUNT][2] = {{0, 1}, {1, 2}, {2, 3}, {3, 4}, {4, 5}, {5, 6}, {6, 7},
-                               {7, 8}, {8, 9}, {9, 10}, {10, 11}, {11, 12}, {12, 13}};
+    // stage i spans events i .. i+1 of the marks above
     for (int i = 0; i < ST_COUNT; i++) {
       float ms = 0;
-      if (hipEventElapsedTime(&ms, P->ev[map_ev[i][0]], P->ev[map_ev[i][1]]) == hipSuccess) rep.stage_ms[i] = ms;
+      if (hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]) == hipSuccess) rep.stage_ms[i] = ms;
     }
   }
   return LFMM_OK;
