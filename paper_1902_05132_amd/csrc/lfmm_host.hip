@@ -699,19 +699,19 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   lk_gather(ntp, sg, d_trees, ntrees, perm, d_lstart, x, y, z, q, st, px, py, pz, pq, s);
   mark(2);
   // ---------------- operators
-  // expansion scales of the mixed-precision M2L: c = 2^round(log2(1/(k h))) per (tree, level)
-  std::vector<double> hsc((size_t)ntrees * 9, 1.0);
+  // expansion scale exponents of the mixed-precision M2L: c = 2^e, e = round(log2(1/(k h))) per (tree, level)
+  std::vector<int> hse((size_t)ntrees * 9, 0);
   for (int t = 0; t < ntrees; t++)
     for (int l = 0; l <= trees[t].depth && l < 9; l++) {
       double h = trees[t].S / (double)(1 << l);
-      hsc[(size_t)t * 9 + l] = std::ldexp(1.0, (int)std::lround(std::log2(1.0 / (trees[t].k * h))));
+      hse[(size_t)t * 9 + l] = (int)std::lround(std::log2(1.0 / (trees[t].k * h)));
     }
-  auto scl = [&](int t, int l) { return hsc[(size_t)t * 9 + l]; };
-  std::vector<double> opsc;  // (c_target, c_source) per operator (M2L operators only)
-  auto set_opsc = [&](int op, double ct, double cs) {
-    if ((size_t)(2 * op + 2) > opsc.size()) opsc.resize(2 * (size_t)op + 2, 1.0);
-    opsc[2 * (size_t)op] = ct;
-    opsc[2 * (size_t)op + 1] = cs;
+  auto scl = [&](int t, int l) { return hse[(size_t)t * 9 + l]; };
+  std::vector<int> opse;  // (e_target, e_source) per operator (M2L operators only)
+  auto set_opsc = [&](int op, int et, int es) {
+    if ((size_t)(2 * op + 2) > opse.size()) opse.resize(2 * (size_t)op + 2, 0);
+    opse[2 * (size_t)op] = et;
+    opse[2 * (size_t)op + 1] = es;
   };
   // op 0 is the zero operator
   int nops = 1;
@@ -818,14 +818,14 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   double* ops = P->dev<double>("ops", (size_t)nops * opsz);
   lk_zero(ops, opsz, s);
   float* ops32 = nullptr;
-  double* d_opsc = nullptr;
-  double* d_sc = P->upload("exp_scale", hsc, s);
+  int* d_opsc = nullptr;
+  int* d_sc = P->upload("exp_scale", hse, s);
   const bool m2l32 = P->prec && (P->prec_parts & 2), p2p32 = P->prec && (P->prec_parts & 1);
   if (m2l32) {
     ops32 = P->dev<float>("ops32", (size_t)nops * opsz);
     lk_zero((double*)ops32, opsz / 2, s);
-    opsc.resize(2 * (size_t)nops, 1.0);
-    d_opsc = P->upload("op_scale", opsc, s);
+    opse.resize(2 * (size_t)nops, 0);
+    d_opsc = P->upload("op_scale", opse, s);
   }
   OpDesc* d_fops = P->upload("fops", fops, s);
   lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s);

@@ -120,14 +120,14 @@ void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const 
                const double* x, const double* y, const double* z, const double* q, Stack st, double* px,
                double* py, double* pz, double* pq, hipStream_t s);
 void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS, const double* gaunt,
-                float* ops32, const double* opsc, hipStream_t s);
+                float* ops32, const int* opse, hipStream_t s);
 void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, int p, double* Jtab, double* Ptab,
                      hipStream_t s);
 void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, double* Ftab, hipStream_t s);
 void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p, int Ntot,
                    const double* Jtab, const double* Ptab, const double* Ftab, double* Iout, int NC, hipStream_t s);
 void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p, int NC,
-                     int NKS, float* ops32, const double* opsc, hipStream_t s);
+                     int NKS, float* ops32, const int* opse, hipStream_t s);
 void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
             const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
             const TreeInfo* trees, const double* px, const double* py, const double* pz, const double* pq, int p,
@@ -154,11 +154,11 @@ void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total
                  const TreeInfo* trees, const long long* grid_off, const int* grid, const double* px,
                  const double* py, const double* pz, const double* pq, const int* sg, double* phi_tp, int poly,
                  int ta, int ch, int f32, unsigned long long* npairs, hipStream_t s);
-void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const double* sc,
+void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const int* se,
                  const double* M, float* M32, hipStream_t s);
 void lk_gemm32(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
                int srow_stride, const float* ops, int opsz, int NKS, const float* S, double* D, int NCK, int NC,
-               const int* box_tree, const int* box_level, const double* sc, hipStream_t s);
+               const int* box_tree, const int* box_level, const int* se, hipStream_t s);
 void lk_nf_nodes(int nnodes, Rule rule, Stack st, int lt, int ls, int a, int b, double* nkr, double* nfac,
                  double* nkzt, double* nkzs, hipStream_t s);
 void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps, const int* box_start,

@@ -178,25 +178,29 @@ __global__ __launch_bounds__(256) void k_classify(int n, const double* x, const 
     }
   }
 }
-__global__ void k_reduce_stats(int nblocks, int nl, const double* partial, double* stats) {
-  int idx = threadIdx.x;
-  if (idx >= nl * NSTAT) return;
+// one wave per (layer, statistic): lanes stride over the per-block partials
+__global__ __launch_bounds__(64) void k_reduce_stats(int nblocks, int nl, const double* partial, double* stats) {
+  int idx = blockIdx.x, lane = threadIdx.x;
   int s = idx % NSTAT;
   bool ismin = (s == 1 || s == 3 || s == 5 || s == 7 || s == 9);
   bool ismax = (s == 2 || s == 4 || s == 6 || s == 8 || s == 10);
   double acc = ismin ? INFINITY : ismax ? -INFINITY : 0.0;
-  for (int b = 0; b < nblocks; b++) {
+  for (int b = lane; b < nblocks; b += 64) {
     double v = partial[(size_t)b * nl * NSTAT + idx];
     acc = ismin ? fmin(acc, v) : ismax ? fmax(acc, v) : acc + v;
   }
-  stats[idx] = acc;
+  for (int off = 32; off > 0; off >>= 1) {
+    double v = __shfl_xor(acc, off, 64);
+    acc = ismin ? fmin(acc, v) : ismax ? fmax(acc, v) : acc + v;
+  }
+  if (lane == 0) stats[idx] = acc;
 }
 extern "C" void lk_classify(int n, const double* x, const double* y, const double* z, const int* lin, int* lout,
                             Stack st, double* partial, int nblocks, hipStream_t s) {
   k_classify<<<nblocks, 256, 0, s>>>(n, x, y, z, lin, lout, st, partial);
 }
 extern "C" void lk_reduce_stats(int nblocks, int nl, const double* partial, double* stats, hipStream_t s) {
-  k_reduce_stats<<<1, 256, 0, s>>>(nblocks, nl, partial, stats);
+  k_reduce_stats<<<nl * NSTAT, 64, 0, s>>>(nblocks, nl, partial, stats);
 }
 
 __global__ void k_iota(int n, int* a) {
@@ -446,10 +450,10 @@ __device__ __forceinline__ void decode_nm(int r, int* n, int* m) {
 //   Op[(n,m),(nu,mu)] = 4 pi i^{n-nu} sum_q i^q z_q(k|b|) conj(Y_q^{m-mu}(b^)) G(nu,mu; q,m-mu; n)
 // G tabulated per (row, col, j), q = |n - nu| + 2 j.  One workgroup per operator.
 // With ops32 given, singular (M2L) operators are written in FP32 to ops32 instead,
-// scaled as Op[(n,m),(nu,mu)] c_t^{-n} c_s^{-nu} with (c_t, c_s) = opsc[op] (the
-// per-level expansion scales of the FP32 path).
+// scaled as Op[(n,m),(nu,mu)] 2^{-(e_t n + e_s nu)} with (e_t, e_s) = opse[op] (the
+// per-level expansion scale exponents of the FP32 path).
 __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
-                                                 const double* gaunt, float* ops32, const double2* opsc) {
+                                                 const double* gaunt, float* ops32, const int2* opse) {
   __shared__ cd zq[64];
   __shared__ cd Yq[64 * 64];
   OpDesc D = descs[blockIdx.x];
@@ -505,7 +509,7 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
   double* out = ops + (size_t)D.op * opsz;
   const bool f32 = ops32 != nullptr && D.kind == 1;
   float* out32 = f32 ? ops32 + (size_t)D.op * opsz : nullptr;
-  const double2 sc = f32 ? opsc[D.op] : make_double2(1.0, 1.0);
+  const int2 se = f32 ? opse[D.op] : make_int2(0, 0);
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   int P1 = p + 1;
   for (int e = threadIdx.x; e < NR * NK; e += 256) {
@@ -529,8 +533,8 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
       }
       val = (4.0 * LFMM_PI) * (ipow(n - nu) * acc);
       if (f32) {
-        int ns = (int)sqrt((double)row), nus = (int)sqrt((double)col);
-        val = (pow(sc.x, -(double)ns) * pow(sc.y, -(double)nus)) * val;
+        int sh = -(se.x * n + se.y * nu);
+        val = mk(ldexp(val.x, sh), ldexp(val.y, sh));
       }
     }
     size_t pp = packed_pos(row, col, NKS);
@@ -544,8 +548,8 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
   }
 }
 extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
-                           const double* gaunt, float* ops32, const double* opsc, hipStream_t s) {
-  if (nops) k_transop<<<nops, 256, 0, s>>>(descs, ops, opsz, p, NC, NKS, gaunt, ops32, (const double2*)opsc);
+                           const double* gaunt, float* ops32, const int* opse, hipStream_t s) {
+  if (nops) k_transop<<<nops, 256, 0, s>>>(descs, ops, opsz, p, NC, NKS, gaunt, ops32, (const int2*)opse);
 }
 
 // ---------------------------------------------------------------------------
@@ -809,13 +813,22 @@ extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* me
 // T[(n,m),(n',m')] = (4 pi/k_t) i^n (-i)^{n'} i^q e^{i q phi} I[(n,m),(n',m')], q = m' - m,
 // phi = arg of the lateral offset target - source.  One workgroup per operator.
 __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const double* Iall, double* ops, int opsz,
-                                                      int p, int NC, int NKS, float* ops32, const double2* opsc) {
+                                                      int p, int NC, int NKS, float* ops32, const int2* opse) {
+  __shared__ cd ph[64];  // i^q e^{i q phi}, q = -2p..2p
   ROpDesc R = rops[blockIdx.x];
-  double phi = atan2(R.dy, R.dx);
+  const double phi = atan2(R.dy, R.dx);
+  const int Q = 2 * p;
+  if ((int)threadIdx.x <= 2 * Q) {
+    int q = (int)threadIdx.x - Q;
+    double sn, cs;
+    sincos(q * phi, &sn, &cs);
+    ph[threadIdx.x] = ipow(q) * mk(cs, sn);
+  }
+  __syncthreads();
   const double* I = Iall + (size_t)R.cls * NC * NC * 2;
   double* out = ops + (size_t)R.op * opsz;
   float* out32 = ops32 ? ops32 + (size_t)R.op * opsz : nullptr;
-  const double2 sc = ops32 ? opsc[R.op] : make_double2(1.0, 1.0);
+  const int2 se = ops32 ? opse[R.op] : make_int2(0, 0);
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   double pre = 4.0 * LFMM_PI / R.kt;
   for (int e = threadIdx.x; e < NR * NK; e += 256) {
@@ -825,12 +838,12 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
       int n, m, n2, m2;
       decode_nm(row, &n, &m);
       decode_nm(col, &n2, &m2);
-      int q = m2 - m;
-      double sn, cs;
-      sincos(q * phi, &sn, &cs);
       cd iv = mk(I[2 * ((size_t)row * NC + col)], I[2 * ((size_t)row * NC + col) + 1]);
-      val = pre * (ipow(n - n2 + q) * (mk(cs, sn) * iv));
-      if (out32) val = (pow(sc.x, -(double)n) * pow(sc.y, -(double)n2)) * val;
+      val = pre * (ipow(n - n2) * (ph[m2 - m + Q] * iv));
+      if (out32) {
+        int sh = -(se.x * n + se.y * n2);
+        val = mk(ldexp(val.x, sh), ldexp(val.y, sh));
+      }
     }
     size_t pp = packed_pos(row, col, NKS);
     if (out32) {
@@ -843,14 +856,14 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
   }
 }
 extern "C" void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p,
-                                int NC, int NKS, float* ops32, const double* opsc, hipStream_t s) {
-  if (nops) k_react_expand<<<nops, 256, 0, s>>>(rops, Iall, ops, opsz, p, NC, NKS, ops32, (const double2*)opsc);
+                                int NC, int NKS, float* ops32, const int* opse, hipStream_t s) {
+  if (nops) k_react_expand<<<nops, 256, 0, s>>>(rops, Iall, ops, opsz, p, NC, NKS, ops32, (const int2*)opse);
 }
 
 // ---------------------------------------------------------------------------
 // P2M: M_nm = sum_j Q_j 4 pi j_n(k r_j) conj(Y_n^m(r_j^)) about the leaf centre
 // (eq. (melecoeffree); at polarisation sources for reaction trees, eq.
-// (melayerupgoingimage)).  One thread per (leaf, |m|).
+// (melayerupgoingimage)).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int seg_find(const int* prefix, int nseg, int x) {
   int lo = 0, hi = nseg - 1;
@@ -862,65 +875,117 @@ __device__ __forceinline__ int seg_find(const int* prefix, int nseg, int x) {
   return lo;
 }
 
+// One workgroup of 128 threads per leaf.  The per-particle quantities (j_n(k r),
+// the angles and the charge) are computed once per particle into LDS; then thread
+// (m, stripe) runs the Legendre recurrence in n for order m over its stripe of the
+// particles and accumulates M_{n,m} and M_{n,-m}; the stripes are summed through
+// LDS in a fixed order.
 template <int P>
-__global__ __launch_bounds__(256) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total,
+__global__ __launch_bounds__(128) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix,
                                              const int* box_start, const int* box_cnt, const int* box_code,
                                              const int* box_tree, const int* box_level, const TreeInfo* trees,
                                              const double* px, const double* py, const double* pz, const double* pq,
                                              int NCK, double* M) {
-  int gid = blockIdx.x * 256 + threadIdx.x;
-  const int P1 = P + 1;
-  if (gid >= total * P1) return;
-  int li = gid / P1, m = gid % P1;
-  int sgm = seg_find(seg_prefix, nseg, li);
-  int R = seg_row0[sgm] + (li - seg_prefix[sgm]);
-  TreeInfo T = trees[box_tree[R]];
+  constexpr int P1 = P + 1, NSTR = 128 / P1;
+  __shared__ double s_ct[128], s_st[128], s_cp[128], s_sp[128], s_qr[128], s_qi[128], s_j[P1][128];
+  __shared__ double red[NSTR * P1 * P1 * 2];
+  const int tid = threadIdx.x;
+  const int li = blockIdx.x;
+  const int sgm = seg_find(seg_prefix, nseg, li);
+  const int R = seg_row0[sgm] + (li - seg_prefix[sgm]);
+  const TreeInfo T = trees[box_tree[R]];
   double c[3];
   box_center(T, (unsigned)box_code[R], box_level[R], c);
+  const int s0 = box_start[R], nt = box_cnt[R];
+  const int m = tid % P1, str = tid / P1;
+  const bool active = str < NSTR;
+  const double cm = (m & 1) ? -1.0 : 1.0;
   cd accp[P1], accn[P1];
 #pragma unroll
-  for (int n = 0; n <= P; n++) { accp[n] = mk(0, 0); accn[n] = mk(0, 0); }
-  int s0 = box_start[R], s1 = s0 + box_cnt[R];
-  double cm = (m & 1) ? -1.0 : 1.0;
-#pragma unroll 1
-  for (int s = s0; s < s1; s++) {
-    double dx = px[s] - c[0], dy = py[s] - c[1], dz = pz[s] - c[2];
-    double r = sqrt(dx * dx + dy * dy + dz * dz);
-    double jn[P1];
-    dev_sph_j_t<P>(T.k * r, jn);
-    double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? sqrt(dx * dx + dy * dy) / r : 0.0;
-    double ph = atan2(dy, dx);
-    double sn, cs;
-    sincos(m * ph, &sn, &cs);
-    cd q = mk(pq[2 * s], pq[2 * s + 1]);
-    double pmm = 0.28209479177387814347;
-    for (int mm = 1; mm <= m; mm++) pmm *= c_ld[mm] * st;
-    double p0 = 0.0, p1 = 0.0;
+  for (int n = 0; n <= P; n++) {
+    accp[n] = mk(0, 0);
+    accn[n] = mk(0, 0);
+  }
+  for (int c0 = 0; c0 < nt; c0 += 128) {
+    const int nc = nt - c0 < 128 ? nt - c0 : 128;
+    __syncthreads();
+    if (tid < nc) {
+      const int i = s0 + c0 + tid;
+      double dx = px[i] - c[0], dy = py[i] - c[1], dz = pz[i] - c[2];
+      double rho = sqrt(dx * dx + dy * dy), r = sqrt(rho * rho + dz * dz);
+      double jn[P1];
+      dev_sph_j_t<P>(T.k * r, jn);
 #pragma unroll
-    for (int n = 0; n <= P; n++) {
-      if (n < m) continue;
-      double val;
-      if (n == m) { val = pmm; p1 = pmm; }
-      else {
-        val = c_la[n * 16 + m] * ct * p1 - c_lb[n * 16 + m] * p0;
-        p0 = p1;
-        p1 = val;
+      for (int n = 0; n <= P; n++) s_j[n][tid] = 4.0 * LFMM_PI * jn[n];
+      s_ct[tid] = r > 0 ? dz / r : 1.0;
+      s_st[tid] = r > 0 ? rho / r : 0.0;
+      s_cp[tid] = rho > 0 ? dx / rho : 1.0;
+      s_sp[tid] = rho > 0 ? dy / rho : 0.0;
+      s_qr[tid] = pq[2 * i];
+      s_qi[tid] = pq[2 * i + 1];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll 1
+      for (int i = str; i < nc; i += NSTR) {
+        const double ct = s_ct[i], st = s_st[i];
+        // e^{i m phi} by repeated multiplication
+        double cs = 1.0, sn = 0.0;
+        const double cp = s_cp[i], sp = s_sp[i];
+        for (int k = 0; k < m; k++) {
+          double t = cs * cp - sn * sp;
+          sn = sn * cp + cs * sp;
+          cs = t;
+        }
+        const cd q = mk(s_qr[i], s_qi[i]);
+        const cd qp = q * mk(cs, -sn), qn = cm * (q * mk(cs, sn));
+        double pmm = 0.28209479177387814347;
+        for (int mm = 1; mm <= m; mm++) pmm *= c_ld[mm] * st;
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int n = 0; n <= P; n++) {
+          if (n < m) continue;
+          double val;
+          if (n == m) {
+            val = pmm;
+            p1 = pmm;
+          } else {
+            val = c_la[n * 16 + m] * ct * p1 - c_lb[n * 16 + m] * p0;
+            p0 = p1;
+            p1 = val;
+          }
+          const double base = s_j[n][i] * val;
+          // conj(Y_n^m) = Phat e^{-i m phi};  conj(Y_n^{-m}) = (-1)^m Phat e^{+i m phi}
+          accp[n] = accp[n] + base * qp;
+          accn[n] = accn[n] + base * qn;
+        }
       }
-      double base = 4.0 * LFMM_PI * jn[n] * val;
-      // conj(Y_n^m) = Phat e^{-i m phi};  conj(Y_n^{-m}) = (-1)^m Phat e^{+i m phi}
-      accp[n] = accp[n] + q * mk(base * cs, -base * sn);
-      accn[n] = accn[n] + q * mk(cm * base * cs, cm * base * sn);
     }
   }
   double* Mr = M + (size_t)R * NCK * 2;
+  for (int half = 0; half < 2; half++) {
+    __syncthreads();
+    if (active) {
 #pragma unroll
-  for (int n = 0; n <= P; n++) {
-    if (n < m) continue;
-    Mr[2 * cidx(n, m)] = accp[n].x;
-    Mr[2 * cidx(n, m) + 1] = accp[n].y;
-    if (m > 0) {
-      Mr[2 * cidx(n, -m)] = accn[n].x;
-      Mr[2 * cidx(n, -m) + 1] = accn[n].y;
+      for (int n = 0; n <= P; n++) {
+        const cd v = half ? accn[n] : accp[n];
+        red[((str * P1 + m) * P1 + n) * 2] = v.x;
+        red[((str * P1 + m) * P1 + n) * 2 + 1] = v.y;
+      }
+    }
+    __syncthreads();
+    if (tid < P1 && (half == 0 || tid > 0)) {
+      const int mm = tid;
+      for (int n = mm; n <= P; n++) {
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < NSTR; k++) {
+          sx += red[((k * P1 + mm) * P1 + n) * 2];
+          sy += red[((k * P1 + mm) * P1 + n) * 2 + 1];
+        }
+        const int o = cidx(n, half ? -mm : mm);
+        Mr[2 * o] = sx;
+        Mr[2 * o + 1] = sy;
+      }
     }
   }
 }
@@ -929,11 +994,10 @@ extern "C" void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int
                        const TreeInfo* trees, const double* px, const double* py, const double* pz, const double* pq,
                        int p, int NCK, double* M, hipStream_t s) {
   if (!total) return;
-  int g = nblk((size_t)total * (p + 1), 256);
 #define P2M_CASE(PP)                                                                                          \
   case PP:                                                                                                    \
-    k_p2m<PP><<<g, 256, 0, s>>>(nseg, seg_row0, seg_prefix, total, box_start, box_cnt, box_code, box_tree,    \
-                                box_level, trees, px, py, pz, pq, NCK, M);                                    \
+    k_p2m<PP><<<total, 128, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code, box_tree,       \
+                                    box_level, trees, px, py, pz, pq, NCK, M);                                \
     break;
   switch (p) { P2M_CASE(1) P2M_CASE(2) P2M_CASE(3) P2M_CASE(4) P2M_CASE(5) P2M_CASE(6) P2M_CASE(7) P2M_CASE(8)
                P2M_CASE(9) P2M_CASE(10) default: break; }
@@ -1193,35 +1257,35 @@ extern "C" void lk_gemm(int m2l, int nrt, int ks, int nblocks, const GBlock* blo
 
 // ---------------------------------------------------------------------------
 // FP32 path of the M2L (mixed precision).  Expansions of a box at level l of a
-// tree with wavenumber k are rescaled by powers c^n of c = 2^round(log2(1/(k h_l)))
+// tree with wavenumber k are rescaled by powers c^n of c = 2^e, e = round(log2(1/(k h_l)))
 // (h_l the box size), which brings M_n ~ (k h)^n and L_n ~ (k h)^{-n} to O(1) and
 // keeps FP32 away from overflow (h_{2p}(k r) reaches 1e44 at p = 10 on fine
-// levels); the operators are stored pre-scaled, T[(n,m),(nu,mu)] c_t^{-n} c_s^{-nu}.
+// levels); the operators are stored pre-scaled, T[(n,m),(nu,mu)] c_t^{-n} c_s^{-nu}
+// (powers of two: the scalings are exact).
 // The GEMM runs on v_mfma_f32_16x16x4f32 (D element r of lane l = (row
 // 4 (l/16) + r, col l%16)); each operator's FP32 partial sum is moved into FP64
 // accumulators when the operator is done, and the result is added, unscaled, to
 // the FP64 local expansions.
 // ---------------------------------------------------------------------------
-__global__ void k_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const double* sc,
+__global__ void k_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const int* se,
                            const double2* M, float2* M32) {
   long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= (long long)nrows * NCK) return;
   int row = (int)(e / NCK), col = (int)(e % NCK);
   float2 v = make_float2(0.f, 0.f);
   if (col < NC) {
-    double c = sc[box_tree[row] * 9 + box_level[row]];
     int n = (int)sqrt((double)col);
     while (n * n > col) n--;
-    double f = pow(c, (double)n);
+    int sh = se[box_tree[row] * 9 + box_level[row]] * n;
     double2 m = M[e];
-    v = make_float2((float)(m.x * f), (float)(m.y * f));
+    v = make_float2((float)ldexp(m.x, sh), (float)ldexp(m.y, sh));
   }
   M32[e] = v;
 }
-extern "C" void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const double* sc,
+extern "C" void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const int* se,
                             const double* M, float* M32, hipStream_t s) {
   long long n = (long long)nrows * NCK;
-  if (n) k_m_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(nrows, NCK, NC, box_tree, box_level, sc,
+  if (n) k_m_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(nrows, NCK, NC, box_tree, box_level, se,
                                                                 (const double2*)M, (float2*)M32);
 }
 template <int NRT, int KS>
@@ -1229,7 +1293,7 @@ __global__ __launch_bounds__(256) void k_m2l_gemm32(const GBlock* blocks, const 
                                                     const int* srow, int srow_stride, const float* __restrict__ ops,
                                                     int opsz, int NKS, const float2* __restrict__ S, double2* D,
                                                     int NCK, int NC, const int* box_tree, const int* box_level,
-                                                    const double* sc) {
+                                                    const int* se) {
   GBlock bd = blocks[blockIdx.x];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kr = lane >> 4;
@@ -1347,7 +1411,7 @@ __global__ __launch_bounds__(256) void k_m2l_gemm32(const GBlock* blocks, const 
   }
   if (kw != 0 || !tv) return;
   const int tr = trow[ee];
-  const double c = sc[box_tree[tr] * 9 + box_level[tr]];
+  const int e_t = se[box_tree[tr] * 9 + box_level[tr]];
   double2* Dr = D + (size_t)tr * NCK;
 #pragma unroll
   for (int rt = 0; rt < NRT; rt++)
@@ -1357,17 +1421,16 @@ __global__ __launch_bounds__(256) void k_m2l_gemm32(const GBlock* blocks, const 
       if (row < NC) {
         int n = (int)sqrt((double)row);
         while (n * n > row) n--;
-        double f = pow(c, (double)n);
         double2 v = Dr[row];
-        v.x += f * dr[rt][r];
-        v.y += f * di[rt][r];
+        v.x += ldexp(dr[rt][r], e_t * n);
+        v.y += ldexp(di[rt][r], e_t * n);
         Dr[row] = v;
       }
     }
 }
 extern "C" void lk_gemm32(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
                           const int* srow, int srow_stride, const float* ops, int opsz, int NKS, const float* S,
-                          double* D, int NCK, int NC, const int* box_tree, const int* box_level, const double* sc,
+                          double* D, int NCK, int NC, const int* box_tree, const int* box_level, const int* se,
                           hipStream_t s) {
   if (!nblocks) return;
   const float2* S2 = (const float2*)S;
@@ -1375,7 +1438,7 @@ extern "C" void lk_gemm32(int nrt, int ks, int nblocks, const GBlock* blocks, co
 #define GEMM32_CASE(N, K)                                                                                     \
   if (nrt == N && ks == K) {                                                                                  \
     k_m2l_gemm32<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2,  \
-                                               NCK, NC, box_tree, box_level, sc);                             \
+                                               NCK, NC, box_tree, box_level, se);                             \
     return;                                                                                                   \
   }
   GEMM32_CASE(1, 1) GEMM32_CASE(2, 1) GEMM32_CASE(3, 1) GEMM32_CASE(4, 1) GEMM32_CASE(5, 1) GEMM32_CASE(6, 1)
