@@ -164,8 +164,12 @@ struct lfmm_plan_s {
   std::map<std::string, DevBuf> bufs;
   std::vector<char> hbuf;
   lfmm_report rep;
-  hipEvent_t ev[ST_COUNT + 1];
+  hipEvent_t evb[ST_COUNT], eve[ST_COUNT];  // begin / end of each stage (profiling)
   bool ev_ok = false;
+  // second stream for the reaction-operator chain, which depends only on the trees
+  // and runs beside the free-space operators, job tables, P2M, M2M and near field
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
   template <typename T>
   T* dev(const char* name, size_t count) {
@@ -357,8 +361,11 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     HIPCHK(hipMemcpy(P->d_gaunt, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
     // 4 x 4 tiles of the reaction integral matrices over the half m > 0 or (m = 0, m' >= 0)
     P->ev_ok = true;
-    for (int i = 0; i <= ST_COUNT; i++)
-      if (hipEventCreate(&P->ev[i]) != hipSuccess) P->ev_ok = false;
+    for (int i = 0; i < ST_COUNT; i++)
+      if (hipEventCreate(&P->evb[i]) != hipSuccess || hipEventCreate(&P->eve[i]) != hipSuccess) P->ev_ok = false;
+    HIPCHK(hipStreamCreateWithFlags(&P->s2, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
   } catch (Fail& f) {
     lfmm_destroy(P);
     return f.code;
@@ -495,9 +502,17 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   const double* y = xyz + n;
   const double* z = xyz + 2 * (size_t)n;
   bool prof = P->profile && P->ev_ok;
-  auto mark = [&](int i) {
-    if (prof) HIPCHK(hipEventRecord(P->ev[i], s));
+  auto sbeg = [&](int i, hipStream_t st_) {
+    if (prof) HIPCHK(hipEventRecord(P->evb[i], st_));
   };
+  auto send = [&](int i, hipStream_t st_) {
+    if (prof) HIPCHK(hipEventRecord(P->eve[i], st_));
+  };
+  auto mark = [&](int i) {  // boundary between stages i-1 and i on the main stream
+    if (i > 0) send(i - 1, s);
+    if (i < ST_COUNT) sbeg(i, s);
+  };
+  hipStream_t s2 = P->s2;
   mark(0);
   // ---------------- classification and statistics
   int nbk = std::min(1024, (n + 255) / 256);
@@ -827,20 +842,33 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     opse.resize(2 * (size_t)nops, 0);
     d_opsc = P->upload("op_scale", opse, s);
   }
-  OpDesc* d_fops = P->upload("fops", fops, s);
-  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s);
-  mark(3);
+  // the reaction-operator chain forks onto the second stream here and joins before the M2L
+  HIPCHK(hipEventRecord(P->fork_ev, s));
+  HIPCHK(hipStreamWaitEvent(s2, P->fork_ev, 0));
+  sbeg(ST_REACT_TABLES, s2);
   if (!classes.empty()) {
     double* Iall = P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-    reaction_integrals(P, "ri", classes, Iall, s, [&]() { mark(4); });
-    mark(5);
-    ROpDesc* d_rops = P->upload("rops", rops, s);
-    lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s);
+    reaction_integrals(P, "ri", classes, Iall, s2, [&]() {
+      send(ST_REACT_TABLES, s2);
+      sbeg(ST_REACT_MFMA, s2);
+    });
+    send(ST_REACT_MFMA, s2);
+    sbeg(ST_REACT_EXPAND, s2);
+    ROpDesc* d_rops = P->upload("rops", rops, s2);
+    lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s2);
   } else {
-    mark(4);
-    mark(5);
+    send(ST_REACT_TABLES, s2);
+    sbeg(ST_REACT_MFMA, s2);
+    send(ST_REACT_MFMA, s2);
+    sbeg(ST_REACT_EXPAND, s2);
   }
-  mark(6);
+  send(ST_REACT_EXPAND, s2);
+  HIPCHK(hipEventRecord(P->join_ev, s2));
+  // free-space operators on the main stream
+  OpDesc* d_fops = P->upload("fops", fops, s);
+  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s);
+  send(ST_OPS_FREE, s);
+  sbeg(ST_JOBS, s);
   // ---------------- GEMM jobs
   // group tables (host): M2M groups per (tree, parent level), level-major descending;
   // L2L groups per (tree, level, class) level-major ascending; M2L groups per (tree, level, class)
@@ -1037,46 +1065,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     if (bc_m2m[lp] > 0)
       lk_gemm(0, P->NRT, 1, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
               NCK, NC, s);
-  mark(9);
-  // ---------------- M2L (every level, free and reaction)
-  if (!b_m2l.empty() && m2l32) {
-    // mixed precision: rescaled FP32 copy of the multipole expansions (its time is
-    // counted with the upward pass, so that the m2l stage brackets the GEMM alone)
-    float* M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
-    lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, s);
-    mark(9);
-    lk_gemm32(P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops32, opsz, NKS,
-              M32, Lx, NCK, NC, box_tree, box_level, d_sc, s);
-  } else if (!b_m2l.empty())
-    lk_gemm(1, P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
-            Lx, NCK, NC, s);
-  mark(10);
-  // ---------------- downward pass
-  for (int l = 3; l <= Dmax; l++)
-    if (bc_l2l[l] > 0)
-      lk_gemm(0, P->NRT, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx,
-              NCK, NC, s);
-  mark(11);
+  send(ST_M2M, s);
   double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
   lk_zero(phi_tp, 2 * (size_t)ntp, s);
-  {
-    std::vector<int> s0, pf;
-    int tot = 0;
-    for (int t = 0; t < ntrees; t++) {
-      const TreeInfo& T = trees[t];
-      if ((T.kind == 0 || T.kind == 1) && T.depth >= 2) {
-        s0.push_back(T.pt_off);
-        pf.push_back(tot);
-        tot += T.npts;
-      }
-    }
-    if (tot) {
-      int* d_s0 = P->upload("l2p_s0", s0, s);
-      int* d_pf = P->upload("l2p_pf", pf, s);
-      lk_l2p((int)s0.size(), d_s0, d_pf, tot, leafrow, box_code, box_tree, box_level, d_trees, px, py, pz, sg, p, NCK,
-             Lx, phi_tp, s);
-    }
-  }
   // ---------------- free-space near field (its stage brackets the kernel alone)
   {
     std::vector<int> r0, pf;
@@ -1095,15 +1086,57 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       int* d_r0 = P->upload("p2p_r0", r0, s);
       int* d_pf = P->upload("p2p_pf", pf, s);
       rep.p2p_series = krmax <= 1.0 ? 1 : 0;
-      mark(12);
+      sbeg(ST_P2P, s);
       lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
                   d_grid_off, grid, px, py, pz, pq, sg, phi_tp, rep.p2p_series, P->p2p_ta, P->p2p_ch, p2p32 ? 1 : 0,
                   d_cnt + 3, s);
     } else {
-      mark(12);
+      sbeg(ST_P2P, s);
+    }
+    send(ST_P2P, s);
+  }
+  // the reaction operators are needed from here on
+  HIPCHK(hipStreamWaitEvent(s, P->join_ev, 0));
+  sbeg(ST_M2L, s);
+  // ---------------- M2L (every level, free and reaction)
+  if (!b_m2l.empty() && m2l32) {
+    // mixed precision: rescaled FP32 copy of the multipole expansions (its time is
+    // counted with the upward pass, so that the m2l stage brackets the GEMM alone)
+    float* M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
+    lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, s);
+    sbeg(ST_M2L, s);
+    lk_gemm32(P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops32, opsz, NKS,
+              M32, Lx, NCK, NC, box_tree, box_level, d_sc, s);
+  } else if (!b_m2l.empty())
+    lk_gemm(1, P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
+            Lx, NCK, NC, s);
+  mark(10);
+  // ---------------- downward pass
+  for (int l = 3; l <= Dmax; l++)
+    if (bc_l2l[l] > 0)
+      lk_gemm(0, P->NRT, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx,
+              NCK, NC, s);
+  mark(11);
+  {
+    std::vector<int> s0, pf;
+    int tot = 0;
+    for (int t = 0; t < ntrees; t++) {
+      const TreeInfo& T = trees[t];
+      if ((T.kind == 0 || T.kind == 1) && T.depth >= 2) {
+        s0.push_back(T.pt_off);
+        pf.push_back(tot);
+        tot += T.npts;
+      }
+    }
+    if (tot) {
+      int* d_s0 = P->upload("l2p_s0", s0, s);
+      int* d_pf = P->upload("l2p_pf", pf, s);
+      lk_l2p((int)s0.size(), d_s0, d_pf, tot, leafrow, box_code, box_tree, box_level, d_trees, px, py, pz, sg, p, NCK,
+             Lx, phi_tp, s);
     }
   }
-  mark(13);
+  send(ST_L2P, s);
+  sbeg(ST_NEAR_REACT, s);
   // ---------------- reaction near field (adjacent leaves across the interface)
   if (L >= 1 && Dr >= 1) {
     for (int l = 0; l < NL; l++)
@@ -1171,10 +1204,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.l2l_pairs = (int64_t)hcnt[2];
   rep.p2p_pairs = (int64_t)hcnt[3];
   if (prof) {
-    // stage i spans events i .. i+1 of the marks above
     for (int i = 0; i < ST_COUNT; i++) {
       float ms = 0;
-      if (hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]) == hipSuccess) rep.stage_ms[i] = ms;
+      if (hipEventElapsedTime(&ms, P->evb[i], P->eve[i]) == hipSuccess) rep.stage_ms[i] = ms;
     }
   }
   return LFMM_OK;
@@ -1196,6 +1228,7 @@ int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int3
   } catch (Fail& f) {
     // drain what this call queued before its staging buffers are reused
     (void)hipStreamSynchronize((hipStream_t)stream);
+    (void)hipStreamSynchronize(plan->s2);
     plan->rb_list.clear();
     plan->rb_used = 0;
     return f.code;
@@ -1223,6 +1256,7 @@ int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* la
     return LFMM_OK;
   } catch (Fail& f) {
     (void)hipStreamSynchronize(nullptr);
+    (void)hipStreamSynchronize(plan->s2);
     plan->rb_list.clear();
     plan->rb_used = 0;
     return f.code;
@@ -1247,8 +1281,16 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   if (plan->pin_ev) (void)hipEventDestroy(plan->pin_ev);
   if (plan->rb) (void)hipHostFree(plan->rb);
   if (plan->rb_ev) (void)hipEventDestroy(plan->rb_ev);
-  if (plan->ev_ok)
-    for (int i = 0; i <= ST_COUNT; i++) (void)hipEventDestroy(plan->ev[i]);
+  for (int i = 0; i < ST_COUNT; i++) {
+    if (plan->evb[i]) (void)hipEventDestroy(plan->evb[i]);
+    if (plan->eve[i]) (void)hipEventDestroy(plan->eve[i]);
+  }
+  if (plan->s2) {
+    (void)hipStreamSynchronize(plan->s2);
+    (void)hipStreamDestroy(plan->s2);
+  }
+  if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
+  if (plan->join_ev) (void)hipEventDestroy(plan->join_ev);
   delete plan;
 }
 

@@ -260,16 +260,24 @@ extern "C" void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const
   if (ntp) k_tree_points<<<nblk(ntp, 256), 256, 0, s>>>(ntp, ntrees, trees, perm, layer_start, x, y, z, st, keys, vals);
 }
 
-// end (exclusive) of the run of keys sharing key >> sh, starting at s, within [s, hi)
+// end (exclusive) of the run of keys sharing key >> sh, starting at s, within [s, hi):
+// galloping search (steps 1, 2, 4, ... until the prefix changes), then bisection
+// inside the last step, so a run of length r costs O(log r) probes
 __device__ __forceinline__ int run_end(const unsigned* keys, int s, int hi, int sh) {
-  unsigned pre = keys[s] >> sh;
-  int lo = s + 1, h = hi;
-  while (lo < h) {
-    int mid = (lo + h) >> 1;
-    if ((keys[mid] >> sh) == pre) lo = mid + 1;
-    else h = mid;
+  const unsigned pre = keys[s] >> sh;
+  int lo = s, step = 1, probe = s + 1;  // keys[lo] is in the run
+  while (probe < hi && (keys[probe] >> sh) == pre) {
+    lo = probe;
+    step <<= 1;
+    probe = s + step;
   }
-  return lo;
+  int a = lo + 1, b = probe < hi ? probe : hi;  // the run ends in [a, b]
+  while (a < b) {
+    int mid = (a + b) >> 1;
+    if ((keys[mid] >> sh) == pre) a = mid + 1;
+    else b = mid;
+  }
+  return a;
 }
 
 // occupancy[t*9 + l] = fullest cell of tree t at level l; slab flags of reaction trees.
@@ -1091,11 +1099,18 @@ extern "C" void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int t
 // f64 16x16x4 lane layout: A lane l = (row l%16, k l/16); B lane l = (k l/16,
 // col l%16); D lane l element r = (row l/16 + 4r, col l%16).
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2):
+// map the dispatch index so that consecutive logical blocks -- which share their
+// group's operator sequence -- run on the same XCD and reuse its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
 template <int NRT, int KS>
 __device__ __forceinline__ void gemm_body(const GBlock* blocks, const int* seq, const int* trow, const int* srow,
                                           int srow_stride, const double* __restrict__ ops, int opsz, int NKS,
                                           const double2* __restrict__ S, double2* D, int NCK, int NC) {
-  GBlock bd = blocks[blockIdx.x];
+  GBlock bd = blocks[xcd_block(blockIdx.x, gridDim.x)];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kr = lane >> 4;
   const int cg = wave / KS, kw = wave % KS;
@@ -1294,7 +1309,7 @@ __global__ __launch_bounds__(256) void k_m2l_gemm32(const GBlock* blocks, const 
                                                     int opsz, int NKS, const float2* __restrict__ S, double2* D,
                                                     int NCK, int NC, const int* box_tree, const int* box_level,
                                                     const int* se) {
-  GBlock bd = blocks[blockIdx.x];
+  GBlock bd = blocks[xcd_block(blockIdx.x, gridDim.x)];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kr = lane >> 4;
   const int cg = wave / KS, kw = wave % KS;
