@@ -110,6 +110,43 @@ int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int3
 /* lfmm_eval -- the same with host buffers (copied to and from the device). */
 int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi);
 
+/*
+ * lfmm_eval_targets_device -- Phi at a separate set of target points (the total
+ * interaction of Section 3.4 eq. (totalinteraction) evaluated at r = target):
+ *   Phi_l(t) = sum_{sources j in layer l, |t - r_j| > 0} Q_j h0(k_l |t - r_j|)
+ *            + sum over all sources of the reaction components,
+ * l being the target's layer.  A source at exactly the target's position is left
+ * out of the free part (the kernel is singular there), as for targets = sources.
+ *   n_src, src_xyz, src_layer, q   sources as in lfmm_eval_device
+ *   n_tgt, tgt_xyz, tgt_layer      targets (device, SoA 3*n_tgt doubles; layer ids or NULL --
+ *                                  src_layer and tgt_layer are both given or both NULL)
+ *   phi                            device, 2*n_tgt doubles, output interleaved (re, im)
+ * The method runs on the union of sources and targets (targets with zero charge),
+ * so the plan's trees cover both; n_src + n_tgt < 2^31.  Errors as lfmm_eval_device.
+ */
+int lfmm_eval_targets_device(lfmm_plan_t* plan, int64_t n_src, const double* src_xyz, const int32_t* src_layer,
+                             const double* q, int64_t n_tgt, const double* tgt_xyz, const int32_t* tgt_layer,
+                             double* phi, void* stream);
+
+/* lfmm_eval_targets -- the same with host buffers. */
+int lfmm_eval_targets(lfmm_plan_t* plan, int64_t n_src, const double* src_xyz, const int32_t* src_layer,
+                      const double* q, int64_t n_tgt, const double* tgt_xyz, const int32_t* tgt_layer, double* phi);
+
+/*
+ * lfmm_eval_batch -- many independent problems at once (each its own medium and
+ * particles, each with its own plan).  Problem i evaluates Phi at its n[i]
+ * particles exactly as lfmm_eval_device(plans[i], n[i], xyz[i], layer ? layer[i]
+ * : NULL, q[i], phi[i], ...) would.  nworkers host threads (<= 0: 8) take problems
+ * in turn, each on a stream of its own, so the problems' kernels overlap on the
+ * GPU.  All pointers in xyz/layer/q/phi are device pointers; layer may be NULL.
+ * The plans must be distinct.  status (host, nprob ints, may be NULL) receives
+ * each problem's code; the return value is LFMM_OK if every problem succeeded,
+ * else the first failing code.  Returns after every problem is complete.
+ */
+int lfmm_eval_batch(int nprob, lfmm_plan_t* const* plans, const int64_t* n, const double* const* xyz,
+                    const int32_t* const* layer, const double* const* q, double* const* phi, int nworkers,
+                    int* status);
+
 /* Report of the last evaluation on this plan. */
 int lfmm_last_report(const lfmm_plan_t* plan, lfmm_report* rep);
 

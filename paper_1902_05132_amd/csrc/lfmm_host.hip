@@ -16,7 +16,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <atomic>
 #include <map>
+#include <set>
+#include <thread>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1261,6 +1264,129 @@ int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* la
     plan->rb_used = 0;
     return f.code;
   }
+}
+
+// Targets apart from the sources: the union (sources, then targets with zero
+// charge) goes through the ordinary evaluation; zero charges add nothing and the
+// free part skips coincident points, so the union's potentials at the target
+// entries are the requested ones.
+static int eval_targets_impl(lfmm_plan_t* P, int64_t ns, const double* sxyz, const int32_t* slay, const double* q,
+                             int64_t nt, const double* txyz, const int32_t* tlay, double* phi, hipStream_t s) {
+  if (!P || ns < 0 || nt < 0 || ns + nt >= ((int64_t)1 << 31)) return LFMM_EINVAL;
+  if (nt == 0) return LFMM_OK;
+  if ((ns > 0 && (!sxyz || !q)) || !txyz || !phi) return LFMM_EINVAL;
+  if ((slay == nullptr) != (tlay == nullptr) && ns > 0) return LFMM_EINVAL;  // both or neither
+  const size_t nu = (size_t)(ns + nt);
+  double* ux = P->dev<double>("u_xyz", 3 * nu);
+  double* uq = P->dev<double>("u_q", 2 * nu);
+  double* up = P->dev<double>("u_phi", 2 * nu);
+  int* ul = nullptr;
+  for (int c = 0; c < 3; c++) {
+    if (ns) HIPCHK(hipMemcpyAsync(ux + c * nu, sxyz + c * (size_t)ns, sizeof(double) * ns, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ux + c * nu + ns, txyz + c * (size_t)nt, sizeof(double) * nt, hipMemcpyDeviceToDevice, s));
+  }
+  if (ns) HIPCHK(hipMemcpyAsync(uq, q, sizeof(double) * 2 * ns, hipMemcpyDeviceToDevice, s));
+  lk_zero(uq + 2 * ns, 2 * (size_t)nt, s);
+  if (tlay) {
+    ul = P->dev<int>("u_layer", nu);
+    if (ns) HIPCHK(hipMemcpyAsync(ul, slay, sizeof(int) * ns, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(ul + ns, tlay, sizeof(int) * nt, hipMemcpyDeviceToDevice, s));
+  }
+  int rc = eval_impl(P, (int64_t)nu, ux, ul, uq, up, s);
+  if (rc != LFMM_OK) return rc;
+  HIPCHK(hipMemcpyAsync(phi, up + 2 * ns, sizeof(double) * 2 * nt, hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return LFMM_OK;
+}
+
+int lfmm_eval_targets_device(lfmm_plan_t* plan, int64_t n_src, const double* src_xyz, const int32_t* src_layer,
+                             const double* q, int64_t n_tgt, const double* tgt_xyz, const int32_t* tgt_layer,
+                             double* phi, void* stream) {
+  try {
+    return eval_targets_impl(plan, n_src, src_xyz, src_layer, q, n_tgt, tgt_xyz, tgt_layer, phi, (hipStream_t)stream);
+  } catch (Fail& f) {
+    (void)hipStreamSynchronize((hipStream_t)stream);
+    if (plan) {
+      (void)hipStreamSynchronize(plan->s2);
+      plan->rb_list.clear();
+      plan->rb_used = 0;
+    }
+    return f.code;
+  }
+}
+
+int lfmm_eval_targets(lfmm_plan_t* plan, int64_t n_src, const double* src_xyz, const int32_t* src_layer,
+                      const double* q, int64_t n_tgt, const double* tgt_xyz, const int32_t* tgt_layer, double* phi) {
+  if (!plan || n_src < 0 || n_tgt < 0) return LFMM_EINVAL;
+  if (n_tgt == 0) return LFMM_OK;
+  if ((n_src > 0 && (!src_xyz || !q)) || !tgt_xyz || !phi) return LFMM_EINVAL;
+  try {
+    double* ds = plan->dev<double>("hs_xyz", 3 * (size_t)std::max<int64_t>(n_src, 1));
+    double* dq = plan->dev<double>("hs_q", 2 * (size_t)std::max<int64_t>(n_src, 1));
+    double* dt = plan->dev<double>("ht_xyz", 3 * (size_t)n_tgt);
+    double* dp = plan->dev<double>("ht_phi", 2 * (size_t)n_tgt);
+    int *dsl = nullptr, *dtl = nullptr;
+    if (n_src) {
+      HIPCHK(hipMemcpy(ds, src_xyz, sizeof(double) * 3 * n_src, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(dq, q, sizeof(double) * 2 * n_src, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(dt, tgt_xyz, sizeof(double) * 3 * n_tgt, hipMemcpyHostToDevice));
+    if (src_layer && n_src) {
+      dsl = plan->dev<int>("hs_layer", n_src);
+      HIPCHK(hipMemcpy(dsl, src_layer, sizeof(int) * n_src, hipMemcpyHostToDevice));
+    }
+    if (tgt_layer) {
+      dtl = plan->dev<int>("ht_layer", n_tgt);
+      HIPCHK(hipMemcpy(dtl, tgt_layer, sizeof(int) * n_tgt, hipMemcpyHostToDevice));
+    }
+    int rc = eval_targets_impl(plan, n_src, ds, dsl, dq, n_tgt, dt, dtl, dp, nullptr);
+    if (rc != LFMM_OK) return rc;
+    HIPCHK(hipMemcpy(phi, dp, sizeof(double) * 2 * n_tgt, hipMemcpyDeviceToHost));
+    return LFMM_OK;
+  } catch (Fail& f) {
+    (void)hipStreamSynchronize(nullptr);
+    (void)hipStreamSynchronize(plan->s2);
+    plan->rb_list.clear();
+    plan->rb_used = 0;
+    return f.code;
+  }
+}
+
+int lfmm_eval_batch(int nprob, lfmm_plan_t* const* plans, const int64_t* n, const double* const* xyz,
+                    const int32_t* const* layer, const double* const* q, double* const* phi, int nworkers,
+                    int* status) {
+  if (nprob < 0 || (nprob > 0 && (!plans || !n || !xyz || !q || !phi))) return LFMM_EINVAL;
+  if (nprob == 0) return LFMM_OK;
+  {
+    std::set<const lfmm_plan_t*> seen;
+    for (int i = 0; i < nprob; i++)
+      if (!plans[i] || !seen.insert(plans[i]).second) return LFMM_EINVAL;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LFMM_EHIP;
+  const int nw = std::max(1, std::min(nworkers > 0 ? nworkers : 8, nprob));
+  std::vector<int> st(nprob, LFMM_OK);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    hipStream_t ws = nullptr;
+    if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
+      for (int i; (i = next.fetch_add(1)) < nprob;) st[i] = LFMM_EHIP;
+      return;
+    }
+    for (int i; (i = next.fetch_add(1)) < nprob;)
+      st[i] = lfmm_eval_device(plans[i], n[i], xyz[i], layer ? layer[i] : nullptr, q[i], phi[i], ws);
+    (void)hipStreamSynchronize(ws);
+    (void)hipStreamDestroy(ws);
+  };
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; w++) th.emplace_back(worker);
+  for (auto& t : th) t.join();
+  int rc = LFMM_OK;
+  for (int i = 0; i < nprob; i++) {
+    if (status) status[i] = st[i];
+    if (rc == LFMM_OK && st[i] != LFMM_OK) rc = st[i];
+  }
+  return rc;
 }
 
 int lfmm_last_report(const lfmm_plan_t* plan, lfmm_report* rep) {

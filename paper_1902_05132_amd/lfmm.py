@@ -61,6 +61,11 @@ def load():
                             ctypes.POINTER(vp)]
     L.lfmm_eval_device.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
     L.lfmm_eval.argtypes = [vp, ctypes.c_int64, _D, ctypes.c_void_p, _D, _D]
+    L.lfmm_eval_targets_device.argtypes = [vp, ctypes.c_int64, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.lfmm_eval_targets.argtypes = [vp, ctypes.c_int64, _D, vp, _D, ctypes.c_int64, _D, vp, _D]
+    L.lfmm_eval_batch.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                  ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.lfmm_last_report.argtypes = [vp, ctypes.POINTER(Report)]
     L.lfmm_stage_name.argtypes = [ctypes.c_int]
     L.lfmm_stage_name.restype = ctypes.c_char_p
@@ -137,6 +142,39 @@ class Plan:
         torch.cuda.synchronize()
         return phi.cpu().numpy()
 
+    def eval_targets_device(self, src_xyz, q, tgt_xyz, phi, src_layer=None, tgt_layer=None, stream=None):
+        """Phi at separate targets.  src_xyz (3, ns), tgt_xyz (3, nt) float64 contiguous on the
+        GPU; q (ns,), phi (nt,) complex128; layer ids int32 or None (both or neither)."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        sl = src_layer.data_ptr() if src_layer is not None else None
+        tl = tgt_layer.data_ptr() if tgt_layer is not None else None
+        _check(self.lib.lfmm_eval_targets_device(self.h, src_xyz.shape[1], src_xyz.data_ptr(), sl, q.data_ptr(),
+                                                 tgt_xyz.shape[1], tgt_xyz.data_ptr(), tl, phi.data_ptr(),
+                                                 ctypes.c_void_p(s.cuda_stream)), "lfmm_eval_targets_device")
+        return phi
+
+    def eval_targets_torch(self, sx, sy, sz, q, tx, ty, tz):
+        import torch
+        dev = torch.device("cuda")
+        S = torch.stack([torch.as_tensor(np.asarray(v, dtype=np.float64)) for v in (sx, sy, sz)]).to(dev)
+        T = torch.stack([torch.as_tensor(np.asarray(v, dtype=np.float64)) for v in (tx, ty, tz)]).to(dev)
+        qq = torch.as_tensor(np.asarray(q, dtype=np.complex128)).to(dev)
+        phi = torch.empty(len(tx), dtype=torch.complex128, device=dev)
+        self.eval_targets_device(S.contiguous(), qq.contiguous(), T.contiguous(), phi)
+        torch.cuda.synchronize()
+        return phi.cpu().numpy()
+
+    def eval_targets_host(self, sx, sy, sz, q, tx, ty, tz):
+        S = np.ascontiguousarray(np.concatenate([_f64(sx), _f64(sy), _f64(sz)]))
+        T = np.ascontiguousarray(np.concatenate([_f64(tx), _f64(ty), _f64(tz)]))
+        qq = np.ascontiguousarray(np.asarray(q, dtype=np.complex128)).view(np.float64)
+        out = np.zeros(2 * len(tx))
+        _check(self.lib.lfmm_eval_targets(self.h, len(sx), S.ctypes.data_as(_D), None, qq.ctypes.data_as(_D),
+                                          len(tx), T.ctypes.data_as(_D), None, out.ctypes.data_as(_D)),
+               "lfmm_eval_targets")
+        return out[0::2] + 1j * out[1::2]
+
     # ---- host evaluation ----
     def eval_host(self, x, y, z, q, layer=None):
         n = len(x)
@@ -191,6 +229,25 @@ class Plan:
         _check(self.lib.lfmm_densities(self.h, n, kr.ctypes.data_as(_D), l, lp, out.ctypes.data_as(_D)),
                "lfmm_densities")
         return (out[0::2] + 1j * out[1::2]).reshape(n, 2, 2)
+
+
+def eval_batch(plans, xyzs, qs, phis, layers=None, nworkers=8):
+    """lfmm_eval_batch over torch device tensors: plans[i] with xyzs[i] (3, n_i) float64,
+    qs[i] / phis[i] (n_i,) complex128 (all contiguous, on the GPU).  Returns the
+    per-problem status codes; raises on failure."""
+    L = load()
+    m = len(plans)
+    vp = ctypes.c_void_p
+    P = (vp * m)(*[pl.h.value for pl in plans])
+    N = (ctypes.c_int64 * m)(*[x.shape[1] for x in xyzs])
+    X = (vp * m)(*[x.data_ptr() for x in xyzs])
+    Q = (vp * m)(*[x.data_ptr() for x in qs])
+    F = (vp * m)(*[x.data_ptr() for x in phis])
+    Ly = (vp * m)(*[x.data_ptr() for x in layers]) if layers is not None else None
+    st = (ctypes.c_int * m)()
+    rc = L.lfmm_eval_batch(m, P, N, X, Ly, Q, F, int(nworkers), st)
+    _check(rc, "lfmm_eval_batch")
+    return list(st)
 
 
 def exported_symbols_from_header(path=None):

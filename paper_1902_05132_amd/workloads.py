@@ -70,3 +70,29 @@ def small_three_layer(n_per_layer=100, seed=0, p=4, leaf=16, shuffle=False):
                       shuffle=shuffle)
     w.update(p=p, leaf=leaf, name="3-layer cubes, %d per layer" % n_per_layer)
     return w
+
+
+def config3(seed=3, nprob=256, nmin=2048, nmax=65536, p=6, leaf=64):
+    """Batching case: independent three-layer problems, interfaces at 0 and -g with
+    g uniform on [1.0, 2.0], k per layer uniform on [0.5, 2.5], N log-uniform on
+    [nmin, nmax] split evenly over the layers; uniform particles in the top cube
+    [-0.5, 0.5]^2 x [0.1, 1.1], a middle cube of side g - 0.2 centred at (0, 0, -g/2)
+    (0.1 clear of both interfaces) and the bottom cube [-0.5, 0.5]^2 x [-g-1.1, -g-0.1]."""
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(nprob):
+        g = rng.uniform(1.0, 2.0)
+        k = rng.uniform(0.5, 2.5, 3)
+        n = int(round(np.exp(rng.uniform(np.log(nmin), np.log(nmax)))))
+        counts = split_even(n, 3)
+        sm = g - 0.2
+        xs, ys, zs, ls = [], [], [], []
+        for l, (c, side, zc) in enumerate(zip(counts, (1.0, sm, 1.0), (0.6, -g / 2, -g - 0.6))):
+            xs.append(rng.uniform(-0.5, 0.5, c) * side)
+            ys.append(rng.uniform(-0.5, 0.5, c) * side)
+            zs.append(zc + rng.uniform(-0.5, 0.5, c) * side)
+            ls.append(np.full(c, l, dtype=np.int32))
+        q = rng.uniform(-1.0, 1.0, n) + 1j * rng.uniform(-1.0, 1.0, n)
+        probs.append(dict(d=np.array([0.0, -g]), k=k, x=np.concatenate(xs), y=np.concatenate(ys),
+                          z=np.concatenate(zs), layer=np.concatenate(ls), q=q.astype(np.complex128), p=p, leaf=leaf))
+    return probs

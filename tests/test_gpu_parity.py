@@ -205,3 +205,71 @@ def test_five_layer_fmm():
     cen = (0.35, -0.3, -0.9, -1.5, -2.15)
     w = W.layered_cubes(d, k, [90, 70, 70, 70, 90], cen, side=0.5, seed=23)
     _check_fmm(w, p=4, leaf=10)
+
+
+def test_separate_targets():
+    """Targets apart from the sources (every layer, one on a source position):
+    against the oracle's FMM on the union with zero target charges (same trees,
+    1e-10) and against the exact sum (truncation)."""
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=120, seed=41)
+    rng = np.random.default_rng(42)
+    tx = rng.uniform(-0.5, 0.5, 30)
+    ty = rng.uniform(-0.5, 0.5, 30)
+    tz = np.concatenate([rng.uniform(0.1, 1.1, 10), rng.uniform(-1.1, -0.1, 10), rng.uniform(-2.3, -1.3, 10)])
+    tx[0], ty[0], tz[0] = w["x"][0], w["y"][0], w["z"][0]  # coincides with a source
+    P = lf.Plan(w["d"], w["k"], p=5, leaf_max=12)
+    phi = P.eval_targets_torch(w["x"], w["y"], w["z"], w["q"], tx, ty, tz)
+    assert np.array_equal(phi, P.eval_targets_host(w["x"], w["y"], w["z"], w["q"], tx, ty, tz))
+    ns = len(w["x"])
+    ux, uy, uz = np.concatenate([w["x"], tx]), np.concatenate([w["y"], ty]), np.concatenate([w["z"], tz])
+    ul = np.concatenate([w["layer"], (tz < 0).astype(np.int32) + (tz < -1.2).astype(np.int32)])
+    uq = np.concatenate([w["q"], np.zeros(30, complex)])
+    ref, _ = O.fmm(w["d"], w["k"], 5, 12, ux, uy, uz, ul, uq)
+    assert rel(phi, ref[ns:]) < TOL_FMM, rel(phi, ref[ns:])
+    ex = O.direct(w["d"], w["k"], ux, uy, uz, ul, uq, np.arange(ns, ns + 30))
+    assert np.linalg.norm(phi - ex) / np.linalg.norm(ex) < 1e-3
+
+
+def test_batch_matches_single_and_oracle():
+    """lfmm_eval_batch over independent media (the batching workload's recipe,
+    smaller N): every problem equals its own single evaluation bit for bit, and
+    the smallest problem matches the oracle's FMM (same trees, 1e-10)."""
+    import torch
+    lf = _lfmm()
+    probs = W.config3(seed=5, nprob=12, nmin=1500, nmax=6000)
+    dev = torch.device("cuda")
+    plans, xyzs, qs, phis, singles = [], [], [], [], []
+    for w in probs:
+        P = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"])
+        xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+        q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+        plans.append(P)
+        xyzs.append(xyz)
+        qs.append(q)
+        phis.append(torch.empty_like(q))
+        s1 = torch.empty_like(q)
+        P.eval_device(xyz, q, s1)
+        singles.append(s1)
+    torch.cuda.synchronize()
+    st = lf.eval_batch(plans, xyzs, qs, phis, nworkers=4)
+    torch.cuda.synchronize()
+    assert st == [0] * len(probs)
+    for a, b in zip(phis, singles):
+        assert torch.equal(a, b)
+    i = int(np.argmin([len(w["x"]) for w in probs]))
+    w = probs[i]
+    ref, _ = O.fmm(w["d"], w["k"], w["p"], w["leaf"], w["x"], w["y"], w["z"], w["layer"], w["q"])
+    assert rel(phis[i].cpu().numpy(), ref) < TOL_FMM
+
+
+def test_batch_rejects_repeated_plan():
+    import torch
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=30, seed=43)
+    P = lf.Plan(w["d"], w["k"], p=4, leaf_max=12)
+    dev = torch.device("cuda")
+    xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+    q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+    with pytest.raises(lf.LfmmError):
+        lf.eval_batch([P, P], [xyz, xyz], [q, q], [torch.empty_like(q), torch.empty_like(q)])
