@@ -118,6 +118,8 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
+    ap.add_argument("--scaling", action="store_true",
+                    help="also time N = 2^17 .. 2^21 of the same workload (both precisions), to show O(N) cost")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run one 512 MiB device copy (calibrates hardware byte counters)")
     args = ap.parse_args()
@@ -208,6 +210,33 @@ def main():
            "stages_ms": head["stages"], "roofline": roofline, "rooflines": head["rooflines"],
            "plain_fp64": {"value": plain["value"], "ms_per_step": plain["ms"], "dtype": "f64",
                           "stages_ms": plain["stages"], "rooflines": plain["rooflines"]}}
+    if args.scaling:
+        rows = []
+        for n2 in (1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21):
+            ws = W.config2(n=n2, seed=args.seed, p=args.p, leaf=args.leaf)
+            xs = torch.tensor(np.stack([ws["x"], ws["y"], ws["z"]]), dtype=torch.float64, device=dev).contiguous()
+            qq = torch.tensor(ws["q"], dtype=torch.complex128, device=dev)
+            ph = torch.empty_like(qq)
+            row = {"N": n2}
+            for prec in (0, 1):
+                pl = lfmm.Plan(ws["d"], ws["k"], p=args.p, leaf_max=args.leaf, precision=prec)
+                for i in range(args.warmup):
+                    pl.eval_device(xs, qq, ph, stream=stream)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for i in range(args.steps):
+                    pl.eval_device(xs, qq, ph, stream=stream)
+                torch.cuda.synchronize()
+                ms2 = (time.perf_counter() - t0) * 1000.0 / args.steps
+                rep2 = pl.report()
+                pl.close()
+                row["ms_fp64" if prec == 0 else "ms_mixed"] = ms2
+                row["free_depth"] = rep2["free_depth"][0]
+            row["ns_per_particle_mixed"] = row["ms_mixed"] * 1e6 / n2
+            log("bench: scaling N=%d: FP64 %.3f ms, mixed %.3f ms, free depth %d"
+                % (n2, row["ms_fp64"], row["ms_mixed"], row["free_depth"]))
+            rows.append(row)
+        out["scaling_N"] = rows
     if args.copy_calib:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

@@ -76,7 +76,7 @@ def _declare(L):
                                 c_double, _D],
         "orc_reaction_me_basis": [c_int, _D, _D, c_int, c_int, c_int, c_int, c_double, c_double, c_double,
                                   c_double, c_int, c_double, _D],
-        "orc_fmm": [c_int, _D, _D, c_int, c_int, c_double, c_int, _D, _D, _D, _I, _D, c_int, _D, _I],
+        "orc_fmm": [c_int, _D, _D, c_int, c_int, c_int, c_double, c_int, _D, _D, _D, _I, _D, c_int, _D, _I],
         "orc_num_threads": [],
     }
     for name, args in sig.items():
@@ -292,9 +292,10 @@ def reaction_me_basis(d, k, l, a, lp, b, dx, dy, ht, hc, p, qb=0.5):
 
 
 # ---------------------------------------------------------------- plain FMM
-def fmm(d, k, p, leaf_max, x, y, z, layer, q, what=3, qb=0.5):
+def fmm(d, k, p, leaf_max, x, y, z, layer, q, what=3, qb=0.5, max_depth=8):
     """Plain FMM potentials for every particle; returns (phi, info) with info =
-    [free-tree depth per layer..., reaction-tree depth]."""
+    [free-tree depth per layer..., reaction-tree depth].  Tree depths are capped at
+    max_depth (1..8)."""
     d = _f64(d)
     k = _f64(k)
     x, y, z = _f64(x), _f64(y), _f64(z)
@@ -303,8 +304,8 @@ def fmm(d, k, p, leaf_max, x, y, z, layer, q, what=3, qb=0.5):
     n = len(x)
     out = np.zeros(2 * n)
     info = np.zeros(len(d) + 2, dtype=np.int32)
-    lib().orc_fmm(len(d), _dp(d), _dp(k), int(p), int(leaf_max), float(qb), n, _dp(x), _dp(y), _dp(z),
-                  _ip(layer), _dp(q), int(what), _dp(out), _ip(info))
+    lib().orc_fmm(len(d), _dp(d), _dp(k), int(p), int(leaf_max), int(max_depth), float(qb), n, _dp(x), _dp(y),
+                  _dp(z), _ip(layer), _dp(q), int(what), _dp(out), _ip(info))
     return _cplx(out), info
 
 

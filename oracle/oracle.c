@@ -1065,8 +1065,8 @@ static void pset_free(pset_t *ps) {
   free(ps->q); free(ps->id);
 }
 
-static int occupancy_depth(const pset_t *ps, int leaf_max, int Dmin) {
-  for (int D = Dmin; D <= DMAX; D++) {
+static int occupancy_depth(const pset_t *ps, int leaf_max, int Dmin, int Dlim) {
+  for (int D = Dmin; D <= Dlim; D++) {
     size_t nc = (size_t)1 << (3 * D);
     int *cnt = (int *)calloc(nc, sizeof(int));
     int mx = 0, sh = DMAX - D;
@@ -1077,7 +1077,7 @@ static int occupancy_depth(const pset_t *ps, int leaf_max, int Dmin) {
     free(cnt);
     if (mx <= leaf_max) return D;
   }
-  return DMAX;
+  return Dlim;
 }
 
 static void tree_build(tree_t *t) {
@@ -1322,7 +1322,7 @@ static void free_m2l(void *vctx, int l, const int *tc, const int *sc, cplx *Op) 
 }
 
 /* Free-space FMM of one layer (targets = sources = the layer's particles). */
-static void fmm_free_layer(const stack_t *st, int l, int p, int leaf_max, int N, const double *x, const double *y,
+static void fmm_free_layer(const stack_t *st, int l, int p, int leaf_max, int Dlim, int N, const double *x, const double *y,
                            const double *z, const int *lay, const double *q, cplx *phi, int *depth_out) {
   int n = 0;
   for (int i = 0; i < N; i++) n += (lay[i] == l);
@@ -1363,7 +1363,7 @@ static void fmm_free_layer(const stack_t *st, int l, int p, int leaf_max, int N,
     t.ps.iy[i] = axis_cell(t.ps.fy[i], t.lo[1], S, DMAX);
     t.ps.iz[i] = axis_cell(t.ps.fz[i], t.lo[2], S, DMAX);
   }
-  t.D = occupancy_depth(&t.ps, leaf_max, 0);
+  t.D = occupancy_depth(&t.ps, leaf_max, 0, Dlim);
   *depth_out = t.D;
   tree_build(&t);
   double k = st->k[l];
@@ -1526,7 +1526,7 @@ static void fill_react_cache(react_ctx_t *c, const tree_t *tt, const tree_t *ts)
 }
 
 /* Reaction FMM for all components; common root and depth for every reaction tree. */
-static void fmm_reaction(const stack_t *st, int p, int leaf_max, double qb, int N, const double *x, const double *y,
+static void fmm_reaction(const stack_t *st, int p, int leaf_max, int Dlim, double qb, int N, const double *x, const double *y,
                          const double *z, const int *lay, const double *q, cplx *phi, int *depth_out) {
   int L = st->L;
   if (L < 1) {
@@ -1576,10 +1576,24 @@ static void fmm_reaction(const stack_t *st, int p, int leaf_max, double qb, int 
         Sx->iz[c] = (1 << (DMAX - 1)) - 1 - half_cell(hh, S, DMAX);
         c++;
       }
-      int d1 = occupancy_depth(&tset[l][a], leaf_max, 1), d2 = occupancy_depth(&sset[l][a], leaf_max, 1);
+      int d1 = occupancy_depth(&tset[l][a], leaf_max, 1, Dlim), d2 = occupancy_depth(&sset[l][a], leaf_max, 1, Dlim);
       if (d1 > Dr) Dr = d1;
       if (d2 > Dr) Dr = d2;
     }
+  /* and deep enough that the finest boxes are no thicker than the smallest
+   * particle-to-interface distance: then no target and no polarisation image
+   * share the two boxes next to the interface, and the near field of the
+   * reaction components is empty (within the depth limit) */
+  double gmin = INFINITY;
+  for (int i = 0; i < N; i++)
+    for (int a = 0; a < 2; a++)
+      if (has_dir(st, lay[i], a)) {
+        double hh = hdist(st, lay[i], a, z[i]);
+        if (hh < gmin) gmin = hh;
+      }
+  int Dg = 1;
+  while (Dg < Dlim && S / (double)(1 << Dg) > gmin) Dg++;
+  if (Dg > Dr) Dr = Dg;
   *depth_out = Dr;
   for (int l = 0; l <= L; l++)
     for (int a = 0; a < 2; a++) {
@@ -1690,10 +1704,22 @@ static void fmm_reaction(const stack_t *st, int p, int leaf_max, double qb, int 
 
 /* Plain FMM potentials Phi_l(r_i) for every particle (targets = sources).
  * what: 1 free part, 2 reaction part, 3 both.  info_out[0..L] = free-tree depths
- * (-1 for an empty layer), info_out[L+1] = depth of the reaction trees. */
-void orc_fmm(int L, const double *d, const double *k, int p, int leaf_max, double qb, int N, const double *x,
-             const double *y, const double *z, const int *lay, const double *q, int what, double *phi_out,
-             int *info_out) {
+ * (-1 for an empty layer), info_out[L+1] = depth of the reaction trees.
+ *
+ * Tree rule (the paper leaves tree construction to its FMM package): every tree is
+ * a uniform octree.  A layer's free-space tree has the bounding cube of the
+ * layer's particles as root and the smallest depth at which no cell holds more
+ * than leaf_max particles.  The reaction trees share one root of side
+ * max(x extent, y extent, 2 H) (H the largest particle-to-interface distance),
+ * split at the interface into the target half and the polarisation-image half;
+ * they all get the largest depth (>= 1) that any of them needs by the occupancy
+ * rule, and at least the smallest depth at which the finest boxes are no thicker
+ * than the smallest particle-to-interface distance.  Depths are capped at
+ * max_depth (1..8). */
+void orc_fmm(int L, const double *d, const double *k, int p, int leaf_max, int max_depth, double qb, int N,
+             const double *x, const double *y, const double *z, const int *lay, const double *q, int what,
+             double *phi_out, int *info_out) {
+  const int Dlim = (max_depth >= 1 && max_depth <= DMAX) ? max_depth : DMAX;
   stack_t st;
   make_stack(&st, L, d, k);
   gl_init();
@@ -1701,10 +1727,10 @@ void orc_fmm(int L, const double *d, const double *k, int p, int leaf_max, doubl
   cplx *phi = (cplx *)calloc(N, sizeof(cplx));
   for (int l = 0; l <= L; l++) {
     info_out[l] = -1;
-    if (what & 1) fmm_free_layer(&st, l, p, leaf_max, N, x, y, z, lay, q, phi, &info_out[l]);
+    if (what & 1) fmm_free_layer(&st, l, p, leaf_max, Dlim, N, x, y, z, lay, q, phi, &info_out[l]);
   }
   info_out[L + 1] = -1;
-  if (what & 2) fmm_reaction(&st, p, leaf_max, qb, N, x, y, z, lay, q, phi, &info_out[L + 1]);
+  if (what & 2) fmm_reaction(&st, p, leaf_max, Dlim, qb, N, x, y, z, lay, q, phi, &info_out[L + 1]);
   for (int i = 0; i < N; i++) {
     phi_out[2 * i] = creal(phi[i]);
     phi_out[2 * i + 1] = cimag(phi[i]);

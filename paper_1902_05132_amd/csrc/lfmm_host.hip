@@ -152,6 +152,9 @@ double decay_length(int N, double c) {
 
 }  // namespace
 
+// widest far panel of the Sommerfeld contour rule (tuning override LFMM_FAR_CAP)
+static const double P_FAR_CAP_DEFAULT = 16.0;
+
 struct lfmm_plan_s {
   Stack st;
   int p, leaf_max, NC, NCK, NRT, NKS, NT, opsz;
@@ -163,6 +166,7 @@ struct lfmm_plan_s {
   int p2p_ta;    // near field: targets per wave step (64 / p2p_ta sources)
   int p2p_ch;    // near field: sources per LDS tile
   double kmax;
+  double far_cap = P_FAR_CAP_DEFAULT;
   double* d_gaunt = nullptr;
   std::map<std::string, DevBuf> bufs;
   std::vector<char> hbuf;
@@ -174,10 +178,12 @@ struct lfmm_plan_s {
   hipStream_t s2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
+  // device workspace in use: the plan's own, or one lent by a batch worker
+  std::map<std::string, DevBuf>* bufp = &bufs;
   template <typename T>
   T* dev(const char* name, size_t count) {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
-    DevBuf& B = bufs[name];
+    DevBuf& B = (*bufp)[name];
     if (B.cap < bytes) {
       if (B.p) HIPCHK(hipFree(B.p));
       B.p = nullptr;
@@ -287,9 +293,11 @@ struct lfmm_plan_s {
     r.nnear = (int)std::lround(r.T0 / r.hn);
     double U = decay_cached(npow);
     double tfar = U / dz;
+    // far panels: a few decay lengths of e^{-t dz} wide, at most a fraction of the
+    // oscillation period 2 pi / rho of J_q(t rho)
     double hf = 8.0 / dz;
     if (rho > 0.0) hf = std::min(hf, 7.0 / rho);
-    hf = std::min(hf, 8.0);
+    hf = std::min(hf, far_cap);
     r.nfar = std::max(1, (int)std::ceil(tfar / hf));
     r.hf = tfar / r.nfar;
     return r;
@@ -336,6 +344,7 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     int v = atoi(e);
     if (v == 1 || v == 2 || v == 4) P->gemm_ks = v;
   }
+  if (const char* e = getenv("LFMM_FAR_CAP")) P->far_cap = atof(e);
   P->b = 0.5;
   P->min_gap = 1e-9;
   P->max_depth = 8;
@@ -649,6 +658,22 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       }
     trees[t].depth = D;
     if (trees[t].kind != 0) Dr = std::max(Dr, D);
+  }
+  if (Dr >= 0) {
+    // and deep enough that the finest boxes are no thicker than the smallest
+    // particle-to-interface distance, so that (within the depth limit) no target
+    // and no polarisation image share the two boxes next to the interface and the
+    // reaction near field is empty
+    double gmin = INFINITY;
+    for (int l = 0; l < NL; l++) {
+      const double* S = &hs[(size_t)l * LFMM_NSTAT];
+      if (S[0] <= 0) continue;
+      if (l <= L - 1) gmin = std::min(gmin, S[7]);
+      if (l >= 1) gmin = std::min(gmin, S[9]);
+    }
+    int Dg = 1;
+    while (Dg < P->max_depth && Sr / (double)(1 << Dg) > gmin) Dg++;
+    Dr = std::max(Dr, Dg);
   }
   for (int t = 0; t < ntrees; t++)
     if (trees[t].kind != 0) trees[t].depth = Dr;
@@ -1367,16 +1392,24 @@ int lfmm_eval_batch(int nprob, lfmm_plan_t* const* plans, const int64_t* n, cons
   const int nw = std::max(1, std::min(nworkers > 0 ? nworkers : 8, nprob));
   std::vector<int> st(nprob, LFMM_OK);
   std::atomic<int> next(0);
+  // each worker owns one device workspace and lends it to the plans it runs, so
+  // the batch needs nworkers workspaces rather than one per problem
   auto worker = [&]() {
     hipStream_t ws = nullptr;
     if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
       for (int i; (i = next.fetch_add(1)) < nprob;) st[i] = LFMM_EHIP;
       return;
     }
-    for (int i; (i = next.fetch_add(1)) < nprob;)
+    std::map<std::string, DevBuf> wbufs;
+    for (int i; (i = next.fetch_add(1)) < nprob;) {
+      plans[i]->bufp = &wbufs;
       st[i] = lfmm_eval_device(plans[i], n[i], xyz[i], layer ? layer[i] : nullptr, q[i], phi[i], ws);
+      plans[i]->bufp = &plans[i]->bufs;
+    }
     (void)hipStreamSynchronize(ws);
     (void)hipStreamDestroy(ws);
+    for (auto& kv : wbufs)
+      if (kv.second.p) (void)hipFree(kv.second.p);
   };
   std::vector<std::thread> th;
   for (int w = 0; w < nw; w++) th.emplace_back(worker);

@@ -8,6 +8,8 @@
 // batched complex GEMMs on FP64 MFMA, L2P, near-field sums.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "lfmm_internal.h"
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -809,7 +811,8 @@ extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* me
   if (!nwg) return;
   const int Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
   const cd *J = (const cd*)Jtab, *P = (const cd*)Ptab, *F = (const cd*)Ftab;
-  if (p <= 8) {
+  static const int ch_env = getenv("LFMM_REACT_CH") ? atoi(getenv("LFMM_REACT_CH")) : 0;  // tuning override
+  if (p <= 8 && ch_env != 16) {
     const size_t lds = sizeof(cd) * (32 * (Q + 1 + 4 * NT) + SC_GMAX * 32);
     launch_react_mfma<SC_UPW, 32>(nwg, nsc, scs, members, cls, p, Ntot, J, P, F, Iout, NC, lds, s);
   } else {

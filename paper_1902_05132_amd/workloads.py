@@ -96,3 +96,46 @@ def config3(seed=3, nprob=256, nmin=2048, nmax=65536, p=6, leaf=64):
         probs.append(dict(d=np.array([0.0, -g]), k=k, x=np.concatenate(xs), y=np.concatenate(ys),
                           z=np.concatenate(zs), layer=np.concatenate(ls), q=q.astype(np.complex128), p=p, leaf=leaf))
     return probs
+
+
+FIVE_LAYER_D = (0.0, -0.6, -1.2, -1.8)
+FIVE_LAYER_K = (0.5, 1.2, 2.0, 2.8, 3.0)
+
+
+def config5(n=16777216, seed=5, clusters=8, sigma=0.05, gap=0.05, p=10, leaf=64):
+    """Five-layer medium, N split evenly over the layers (remainder to the top); in
+    each layer a mixture of `clusters` Gaussian clusters (standard deviation sigma)
+    with centres uniform in x, y in [-0.5, 0.5] and z in the layer's admissible band
+    (top [0.05, 1.05], middle layers [d_l + gap, d_{l-1} - gap], bottom
+    [-2.85, -1.85]); draws outside the layer or closer than `gap` to an interface
+    are redrawn.  Complex charges with Re, Im uniform on [-1, 1]."""
+    d = np.array(FIVE_LAYER_D)
+    rng = np.random.default_rng(seed)
+    counts = split_even(n, 5)
+    bands = [(0.05, 1.05)] + [(d[l] + gap, d[l - 1] - gap) for l in range(1, 4)] + [(-2.85, -1.85)]
+    lo_z = [d[0] + gap] + [d[l] + gap for l in range(1, 4)] + [-np.inf]
+    hi_z = [np.inf] + [d[l - 1] - gap for l in range(1, 4)] + [d[3] - gap]
+    xs, ys, zs, ls = [], [], [], []
+    for l in range(5):
+        cx = rng.uniform(-0.5, 0.5, clusters)
+        cy = rng.uniform(-0.5, 0.5, clusters)
+        cz = rng.uniform(bands[l][0], bands[l][1], clusters)
+        want = counts[l]
+        px, py, pz = [], [], []
+        got = 0
+        while got < want:
+            m = int((want - got) * 1.3) + 16
+            c = rng.integers(0, clusters, m)
+            x = cx[c] + sigma * rng.standard_normal(m)
+            y = cy[c] + sigma * rng.standard_normal(m)
+            z = cz[c] + sigma * rng.standard_normal(m)
+            ok = (z > lo_z[l]) & (z < hi_z[l])
+            px.append(x[ok]); py.append(y[ok]); pz.append(z[ok])
+            got += int(ok.sum())
+        xs.append(np.concatenate(px)[:want]); ys.append(np.concatenate(py)[:want]); zs.append(np.concatenate(pz)[:want])
+        ls.append(np.full(want, l, dtype=np.int32))
+    nt = sum(counts)
+    q = rng.uniform(-1.0, 1.0, nt) + 1j * rng.uniform(-1.0, 1.0, nt)
+    return dict(d=d, k=np.array(FIVE_LAYER_K), x=np.concatenate(xs), y=np.concatenate(ys), z=np.concatenate(zs),
+                layer=np.concatenate(ls), q=q.astype(np.complex128), p=p, leaf=leaf,
+                name="5-layer Gaussian clusters, N=%d, p=%d, leaf<=%d" % (nt, p, leaf))

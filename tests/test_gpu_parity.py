@@ -273,3 +273,28 @@ def test_batch_rejects_repeated_plan():
     q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
     with pytest.raises(lf.LfmmError):
         lf.eval_batch([P, P], [xyz, xyz], [q, q], [torch.empty_like(q), torch.empty_like(q)])
+
+
+def test_reaction_near_field_only():
+    """Reaction trees of depth 1 (max_depth = 1): every reaction interaction is in
+    the near field, summed pair by pair with the Sommerfeld quadrature; against
+    the oracle's FMM with the same cap (1e-10) and the exact sum."""
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=40, seed=47)
+    P = lf.Plan(w["d"], w["k"], p=4, leaf_max=1000, max_depth=1)
+    phi = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
+    rep = P.report()
+    assert rep["reaction_depth"] == 1 and rep["nf_react_pairs"] > 0
+    ref, info = O.fmm(w["d"], w["k"], 4, 1000, w["x"], w["y"], w["z"], w["layer"], w["q"], max_depth=1)
+    assert int(info[3]) == 1
+    assert rel(phi, ref) < TOL_FMM, rel(phi, ref)
+    ex = O.direct(w["d"], w["k"], w["x"], w["y"], w["z"], w["layer"], w["q"], np.arange(len(w["x"])))
+    assert rel(phi, ex) < 1e-11, rel(phi, ex)
+
+
+def test_five_layer_clustered():
+    """The five-layer Gaussian-cluster workload (its recipe, N = 5000, p = 5):
+    clustered particles 0.05 from the interfaces give uneven, deeper trees."""
+    w = W.config5(n=5000, p=5, leaf=64)
+    phi, ref, rep = _check_fmm(w, p=5, leaf=64)
+    assert rep["reaction_depth"] >= 5
