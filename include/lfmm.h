@@ -39,7 +39,8 @@ typedef enum {
                        layer id inconsistent with z, particle closer than min_gap to an interface) */
   LFMM_ENOMEM = 2,  /* device or host allocation failed */
   LFMM_EHIP = 3,    /* a HIP runtime call failed */
-  LFMM_ENOTSUP = 4  /* the configuration is outside what this build supports */
+  LFMM_ENOTSUP = 4, /* the configuration is outside what this build supports */
+  LFMM_EIO = 5      /* a surrogate file could not be read or written, or does not match the plan */
 } lfmm_status;
 
 /* Plan options; pass NULL for the defaults shown. */
@@ -75,6 +76,8 @@ typedef struct {
   int p2p_series;          /* 1: near field used the series form of h0 (k r <= 1 on every pair) */
   int precision;           /* the plan's precision option */
   double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
+  int64_t n_react_surrogate; /* reaction classes whose integrals came from the surrogate (gate hits);
+                                the other n_react_classes - n_react_surrogate used the quadrature */
 } lfmm_report;
 
 /*
@@ -158,6 +161,87 @@ void lfmm_destroy(lfmm_plan_t* plan);
 
 /* Text of a status code. */
 const char* lfmm_status_string(int status);
+
+/* ---- learned surrogate of the reaction M2L integrals ----
+ *
+ * The integral matrices I[(n,m),(n',m')] of the reaction M2L operators (Section 3.5,
+ * eq. (me2lesimplified) with the integrals written out in Section 3.5) depend on a
+ * class geometry: component (target layer and direction, source layer and direction),
+ * box size h, the heights j, i in {0, 1} of the target and source boxes above and
+ * below the interface and the lateral offset class rho^2/h^2 in {0,1,2,4,5,8,9,10,13,18}.
+ * The surrogate is a multilayer perceptron (SiLU hidden layers, linear output) that
+ * maps this geometry to the whole matrix (the m >= 0 rows), normalised by the
+ * low-frequency size of each entry and per-output statistics.  It stands where the
+ * paper uses pre-computed interpolation tables; the quadrature stays the fallback
+ * and the judge of every value.  Its weights and activations are BF16 on the matrix
+ * cores with FP32 accumulation; the FP32 master weights are trained on the GPU by
+ * the library's own forward and backward kernels (mean squared error, Adam).
+ *
+ * Gate: training holds out a fraction of the sampled classes and records, for every
+ * geometry combination (component, j, i, rho class), twice the largest held-out
+ * error of the predicted matrices in the norm that weighs entry (n, n') by
+ * (k_t h)^n (k_s h)^n' / ((2n+1)!! (2n'+1)!!) (the size of its effect on expansions of
+ * boxes of size h).  An evaluation uses the network for a class only if its h lies in
+ * the trained range and its combination's bound is <= the gate tolerance; every other
+ * class is integrated by quadrature.  With the gate closed (tolerance 0, the default)
+ * the evaluation is bit-identical to one without a surrogate.
+ */
+typedef struct {
+  double h_min, h_max; /* box sizes covered: 0.02 .. 2.0 */
+  int epochs;          /* passes over the training classes: 150 */
+  int batch;           /* classes per Adam step: 256 */
+  double lr;           /* initial Adam step size, cosine-decayed to 1/100 of it: 2e-3 */
+  double holdout;      /* fraction of each combination's classes held out for the gate: 0.1 */
+  int width, nhidden;  /* hidden-layer width and count: 128, 4 */
+} lfmm_train_opts;
+
+typedef struct {
+  int64_t n_train, n_holdout; /* classes (one integral matrix each) */
+  int64_t n_values;           /* complex integral values in the training set */
+  int n_combos;               /* geometry combinations of the plan's medium */
+  int nin, nout;              /* network input and output widths */
+  int epochs, steps;
+  double loss_first, loss_last; /* training loss (normalised mean squared error): first step, last epoch */
+  double err_median, err_max;   /* held-out weighted relative errors of the integral matrices */
+  double ms_labels, ms_train;   /* wall time of the quadrature labels and of the training */
+} lfmm_train_report;
+
+/*
+ * Train the plan's surrogate: n_samples classes (0: 48 per geometry combination)
+ * with log-uniform box sizes, labelled by the library's quadrature on the GPU;
+ * seed fixes the sampling, initialisation and batch order.  opts and rep are
+ * optional (host).  Replaces a previous surrogate; the gate keeps its tolerance.
+ * Errors: LFMM_EINVAL (L = 0: no reaction field; bad options), LFMM_ENOMEM, LFMM_EHIP.
+ */
+int lfmm_surrogate_train(lfmm_plan_t* plan, int64_t n_samples, uint64_t seed, const lfmm_train_opts* opts,
+                         lfmm_train_report* rep);
+
+/* Write the surrogate (network, statistics, gate bounds, medium) to a file; LFMM_EINVAL if none, LFMM_EIO. */
+int lfmm_surrogate_save(const lfmm_plan_t* plan, const char* path);
+
+/* Read a surrogate written for the same medium and order p; LFMM_EIO if unreadable or mismatched. */
+int lfmm_surrogate_load(lfmm_plan_t* plan, const char* path);
+
+/* Gate tolerance (>= 0; 0 closes the gate) for later evaluations of this plan. */
+int lfmm_surrogate_gate(lfmm_plan_t* plan, double tol);
+
+/*
+ * Held-out error bound of each geometry combination of the plan's surrogate
+ * (host, capacity n; ordered by component, then j, i, rho class; +inf where a
+ * combination had no held-out class), and the number written in *count.
+ */
+int lfmm_surrogate_bounds(const lfmm_plan_t* plan, int n, double* bounds, int* count);
+
+/*
+ * One forward and backward pass of a network of the surrogate's form on the GPU
+ * (component check of the kernels): B rows of x [B][nin], parameters packed per
+ * layer as W [out][in] row-major then b [out] (FP32; weights and x are rounded to
+ * BF16 as the network holds them), targets t [B][nout].  Out: y [B][nout], the
+ * gradient of the mean squared error in the parameters' packing, and the loss.
+ * All host arrays.  Errors: LFMM_EINVAL, LFMM_ENOMEM, LFMM_EHIP.
+ */
+int lfmm_mlp_forward_backward(int B, int nin, int width, int nhidden, int nout, const float* x, const float* params,
+                              const float* t, float* y, float* grad, double* loss);
 
 /* ---- component entry points (the same kernels the evaluation runs) ---- */
 

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblfmm.so")
-SOURCES = ["lfmm_kernels.hip", "lfmm_host.hip"]
+SOURCES = ["lfmm_kernels.hip", "lfmm_mlp.hip", "lfmm_host.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -18,6 +18,8 @@
 #include <functional>
 #include <atomic>
 #include <map>
+#include <random>
+#include <chrono>
 #include <set>
 #include <thread>
 #include <string>
@@ -46,10 +48,11 @@ struct Fail {
 
 enum {
   ST_CLASSIFY, ST_TREE, ST_OPS_FREE, ST_REACT_TABLES, ST_REACT_MFMA, ST_REACT_EXPAND, ST_JOBS, ST_P2M, ST_M2M,
-  ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_NEAR_REACT, ST_SUM, ST_COUNT
+  ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_NEAR_REACT, ST_SUM, ST_REACT_SUR, ST_COUNT
 };
-const char* kStageNames[ST_COUNT] = {"classify", "tree", "ops_free", "react_tables", "react_mfma", "react_expand",
-                                     "jobs", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p_free", "near_reaction", "sum"};
+const char* kStageNames[ST_COUNT] = {"classify", "tree",  "ops_free", "react_tables",  "react_mfma", "react_expand",
+                                     "jobs",     "p2m",   "m2m",      "m2l",           "l2l",        "l2p",
+                                     "p2p_free", "near_reaction", "sum", "react_surrogate"};
 
 // ---------------------------------------------------------------------------
 // Host-side constants owned by the library (independent of any checker):
@@ -152,6 +155,169 @@ double decay_length(int N, double c) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Surrogate network runtime (kernels in lfmm_mlp.hip): parameters packed per
+// layer as the weight matrix [out][in] row-major, then the bias [out]; FP32
+// master copy, BF16 copy for the matrix cores, Adam moments, gradient.
+// ---------------------------------------------------------------------------
+struct MlpNet {
+  int nin = 0, width = 0, nh = 0, nout = 0;
+  long np = 0;
+  std::vector<int> lo, li;
+  std::vector<long> woff, boff;
+  std::map<std::string, DevBuf> bufs;
+  void setup(int nin_, int width_, int nh_, int nout_) {
+    nin = nin_;
+    width = width_;
+    nh = nh_;
+    nout = nout_;
+    lo.clear();
+    li.clear();
+    woff.clear();
+    boff.clear();
+    np = 0;
+    for (int l = 0; l <= nh; l++) {
+      int i = l == 0 ? nin : width, o = l == nh ? nout : width;
+      li.push_back(i);
+      lo.push_back(o);
+      woff.push_back(np);
+      np += (long)o * i;
+      boff.push_back(np);
+      np += o;
+    }
+  }
+  template <typename T>
+  T* dev(const std::string& name, size_t count) {
+    size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+    DevBuf& B = bufs[name];
+    if (B.cap < bytes) {
+      if (B.p) HIPCHK(hipFree(B.p));
+      B.p = nullptr;
+      B.cap = 0;
+      if (hipMalloc(&B.p, bytes) != hipSuccess) {
+        B.p = nullptr;
+        throw Fail{LFMM_ENOMEM};
+      }
+      B.cap = bytes;
+    }
+    return (T*)B.p;
+  }
+  void release() {
+    for (auto& kv : bufs)
+      if (kv.second.p) (void)hipFree(kv.second.p);
+    bufs.clear();
+  }
+  float* w() { return dev<float>("w", np); }
+  unsigned short* wb() { return dev<unsigned short>("wb", np); }
+  float* z(int l, int B) { return dev<float>("z" + std::to_string(l), (size_t)B * width); }
+  unsigned short* a(int l, int B) { return dev<unsigned short>("a" + std::to_string(l), (size_t)B * width); }
+  float* y(int B) { return dev<float>("y", (size_t)B * nout); }
+  // forward pass of B rows of x (BF16, [B][nin]) -> y [B][nout] (FP32)
+  void forward(int B, const unsigned short* x, hipStream_t s) {
+    const unsigned short* in = x;
+    for (int l = 0; l <= nh; l++) {
+      MlpGemm g;
+      memset(&g, 0, sizeof(g));
+      g.M = B;
+      g.N = lo[l];
+      g.K = li[l];
+      g.A = in;
+      g.am = li[l];
+      g.ak = 1;
+      g.B = wb() + woff[l];
+      g.bk = 1;
+      g.bn = li[l];
+      g.bias = w() + boff[l];
+      if (l < nh) {
+        g.mode = MLP_EPI_SILU;
+        g.C = z(l, B);
+        g.ldc = width;
+        g.Cb = a(l, B);
+        g.ldcb = width;
+        in = g.Cb;
+      } else {
+        g.mode = MLP_EPI_STORE;
+        g.C = y(B);
+        g.ldc = nout;
+      }
+      lk_mlp_gemm(g, s);
+    }
+  }
+  // gradient of the mean squared error against t ([B][ldt] FP32) after forward();
+  // the loss goes to loss_out (device, one double)
+  void backward(int B, const unsigned short* x, const float* t, long ldt, double* loss_out, hipStream_t s) {
+    const int dmax = std::max(nout, std::max(width, nin));
+    unsigned short* d = dev<unsigned short>("d0", (size_t)B * dmax);
+    unsigned short* dn = dev<unsigned short>("d1", (size_t)B * dmax);
+    float* grad = dev<float>("g", np);
+    lk_mlp_mse(B, nout, y(B), t, ldt, d, dev<double>("partial", MLP_MSE_BLOCKS), loss_out, s);
+    for (int l = nh; l >= 0; l--) {
+      const unsigned short* ain = l == 0 ? x : a(l - 1, B);
+      MlpGemm g;
+      memset(&g, 0, sizeof(g));
+      g.M = lo[l];  // weight gradient: gW[o][i] = sum_b d[b][o] ain[b][i]
+      g.N = li[l];
+      g.K = B;
+      g.A = d;
+      g.am = 1;
+      g.ak = lo[l];
+      g.B = ain;
+      g.bk = li[l];
+      g.bn = 1;
+      g.mode = MLP_EPI_STORE;
+      g.C = grad + woff[l];
+      g.ldc = li[l];
+      lk_mlp_gemm(g, s);
+      lk_mlp_colsum(B, lo[l], d, grad + boff[l], s);
+      if (l == 0) break;
+      memset(&g, 0, sizeof(g));
+      g.M = B;  // dn[b][i] = (sum_o d[b][o] W[o][i]) silu'(z_{l-1}[b][i])
+      g.N = li[l];
+      g.K = lo[l];
+      g.A = d;
+      g.am = lo[l];
+      g.ak = 1;
+      g.B = wb() + woff[l];
+      g.bk = li[l];
+      g.bn = 1;
+      g.mode = MLP_EPI_DSILU;
+      g.Cb = dn;
+      g.ldcb = li[l];
+      g.Zs = z(l - 1, B);
+      g.ldz = width;
+      lk_mlp_gemm(g, s);
+      std::swap(d, dn);
+    }
+  }
+  void adam(int step, float lr, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
+    lk_mlp_adam(np, w(), dev<float>("m", np), dev<float>("v", np), dev<float>("g", np), lr, b1, b2, eps, c1, c2,
+                wb(), s);
+  }
+  // FP32 parameters from the host; BF16 copy and zero Adam moments
+  void load_params(const float* host, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(w(), host, np * sizeof(float), hipMemcpyHostToDevice, s));
+    lk_f2bf(np, w(), wb(), s);
+    HIPCHK(hipMemsetAsync(dev<float>("m", np), 0, np * sizeof(float), s));
+    HIPCHK(hipMemsetAsync(dev<float>("v", np), 0, np * sizeof(float), s));
+  }
+};
+
+// The trained surrogate of the reaction M2L integrals of one plan, and its gate.
+struct Surrogate {
+  bool ready = false;
+  double tol = 0.0;  // gate: classes whose held-out error bound is <= tol use the network
+  double h_lo = 0.0, h_hi = 0.0;
+  int ncomp = 0;
+  std::vector<int> comp_of;  // [(l * 2 + a) * 2 * NL... ] component id of (l, a, lp, b) or -1
+  std::vector<double> bound; // [comp][j][i][ri] held-out error bound (inf: none)
+  std::vector<float> mu, sd; // per-output statistics (host copies)
+  std::vector<double> Dc;    // per component: extra decay length of its density at large k_rho
+  MlpNet net;
+  lfmm_train_report trep;
+};
+
 // widest far panel of the Sommerfeld contour rule (tuning override LFMM_FAR_CAP)
 static const double P_FAR_CAP_DEFAULT = 16.0;
 
@@ -177,6 +343,7 @@ struct lfmm_plan_s {
   // and runs beside the free-space operators, job tables, P2M, M2M and near field
   hipStream_t s2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  Surrogate sur;
 
   // device workspace in use: the plan's own, or one lent by a batch worker
   std::map<std::string, DevBuf>* bufp = &bufs;
@@ -468,6 +635,292 @@ static void reaction_integrals(lfmm_plan_s* P, const char* tag, std::vector<Clas
 }
 
 inline int has_dir(const Stack& st, int l, int a) { return a == 0 ? (l <= st.L - 1) : (l >= 1); }
+
+// ---------------------------------------------------------------------------
+// Surrogate training.  Geometry combinations of a component: heights j, i of the
+// target and source boxes (in boxes above / below the interface) and the lateral
+// offset class r2 = (dx^2 + dy^2) / h^2; (j, i) = (0, 0) has no r2 <= 2 (adjacent
+// boxes are near field).  Input features (built on the GPU, k_sur_features): one-hot
+// geometry combination (component, j, i, r2 class), and t = the box size on a log
+// scale mapped to [-1, 1] (with its rounding residual, scaled by 256, so that BF16
+// inputs still resolve h) plus T_2(t), T_3(t).
+// ---------------------------------------------------------------------------
+const int kR2[10] = {0, 1, 2, 4, 5, 8, 9, 10, 13, 18};
+inline int sur_nin(int ncomp) { return (ncomp * 40 + 4 + 31) / 32 * 32; }
+inline int sur_combo(int comp, int j, int i, int ri) { return ((comp * 2 + j) * 2 + i) * 10 + ri; }
+void sur_components(lfmm_plan_s* P) {
+  Surrogate& S = P->sur;
+  const Stack& st = P->st;
+  const int NL = st.L + 1;
+  S.comp_of.assign((size_t)NL * 2 * NL * 2, -1);
+  S.ncomp = 0;
+  for (int l = 0; l < NL; l++)
+    for (int a = 0; a < 2; a++)
+      for (int lp = 0; lp < NL; lp++)
+        for (int b = 0; b < 2; b++)
+          if (has_dir(st, l, a) && has_dir(st, lp, b)) S.comp_of[((l * 2 + a) * NL + lp) * 2 + b] = S.ncomp++;
+}
+inline int sur_comp(const lfmm_plan_s* P, int l, int a, int lp, int b) {
+  const int NL = P->st.L + 1;
+  return P->sur.comp_of[((l * 2 + a) * NL + lp) * 2 + b];
+}
+// Extra decay length of each component's density: -d ln|sigma| / d k_rho between
+// k_rho = 30 and 60 (beyond every wavenumber the plan accepts as typical), i.e.
+// the thickness of the layers between the two interfaces the component couples.
+void sur_decay(lfmm_plan_s* P) {
+  Surrogate& S = P->sur;
+  const int NL = P->st.L + 1;
+  S.Dc.assign(S.ncomp, 0.0);
+  const double kr[4] = {30.0, 0.0, 60.0, 0.0};
+  double* dk = P->dev<double>("sur_dk", 4);
+  double* ds = P->dev<double>("sur_ds", 16);
+  HIPCHK(hipMemcpy(dk, kr, sizeof(kr), hipMemcpyHostToDevice));
+  for (int l = 0; l < NL; l++)
+    for (int lp = 0; lp < NL; lp++) {
+      double out[16];
+      lk_dbg_dens(2, dk, P->st, l, lp, ds, nullptr);
+      HIPCHK(hipMemcpy(out, ds, sizeof(out), hipMemcpyDeviceToHost));
+      for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+          const int c = sur_comp(P, l, a, lp, b);
+          if (c < 0) continue;
+          const int e = 2 * (2 * a + b);
+          const double s1 = std::hypot(out[e], out[e + 1]), s2 = std::hypot(out[8 + e], out[8 + e + 1]);
+          S.Dc[c] = (s1 > 0 && s2 > 0) ? std::max(0.0, -std::log(s2 / s1) / 30.0) : 0.0;
+        }
+    }
+}
+
+void sur_train_impl(lfmm_plan_s* P, int64_t n_samples, uint64_t seed, const lfmm_train_opts& o,
+                    lfmm_train_report& R) {
+  Surrogate& S = P->sur;
+  const Stack& st = P->st;
+  const int NL = st.L + 1, p = P->p, NC = P->NC, NT = P->NT;
+  hipStream_t s = P->s2;
+  auto wall = []() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  };
+  S.ready = false;
+  S.h_lo = o.h_min;
+  S.h_hi = o.h_max;
+  sur_components(P);
+  sur_decay(P);
+  const int nout = 2 * NT * NC, nin = sur_nin(S.ncomp);
+  S.net.setup(nin, o.width, o.nhidden, nout);
+  S.bound.assign((size_t)S.ncomp * 40, INFINITY);
+  memset(&R, 0, sizeof(R));
+  R.n_combos = S.ncomp * 37;
+  R.nin = nin;
+  R.nout = nout;
+  // ---- sampling: stratified log-uniform box sizes per combination, evenly spaced strata held out
+  struct Smp {
+    int comp, j, i, ri;
+    double h;
+  };
+  std::vector<Smp> tr, ho;
+  const int nper = n_samples > 0 ? std::max<int>(4, (int)((n_samples + R.n_combos - 1) / R.n_combos)) : 48;
+  const int nhold = std::max(1, (int)std::lround(o.holdout * nper));
+  const int stride = std::max(1, nper / nhold);
+  std::mt19937_64 rng(seed);
+  std::uniform_real_distribution<double> U(0.0, 1.0);
+  const double lh0 = std::log(S.h_lo), lh1 = std::log(S.h_hi);
+  for (int l = 0; l < NL; l++)
+    for (int a = 0; a < 2; a++)
+      for (int lp = 0; lp < NL; lp++)
+        for (int b = 0; b < 2; b++) {
+          const int comp = sur_comp(P, l, a, lp, b);
+          if (comp < 0) continue;
+          for (int j = 0; j < 2; j++)
+            for (int i = 0; i < 2; i++)
+              for (int ri = 0; ri < 10; ri++) {
+                if (i == 0 && j == 0 && kR2[ri] <= 2) continue;
+                int held = 0;
+                for (int k = 0; k < nper; k++) {
+                  Smp m{comp, j, i, ri, std::exp(lh0 + (k + U(rng)) / nper * (lh1 - lh0))};
+                  if (k % stride == stride / 2 && held < nhold) {
+                    ho.push_back(m);
+                    held++;
+                  } else {
+                    tr.push_back(m);
+                  }
+                }
+              }
+        }
+  std::vector<int4> comp_lab(S.ncomp);
+  for (int l = 0; l < NL; l++)
+    for (int a = 0; a < 2; a++)
+      for (int lp = 0; lp < NL; lp++)
+        for (int b = 0; b < 2; b++) {
+          int c = sur_comp(P, l, a, lp, b);
+          if (c >= 0) comp_lab[c] = make_int4(l, a, lp, b);
+        }
+  auto make_class = [&](const Smp& m, int out) {
+    ClassDesc C;
+    memset(&C, 0, sizeof(C));
+    C.zt = (m.j + 0.5) * m.h;
+    C.zs = (m.i + 0.5) * m.h;
+    C.rho = m.h * std::sqrt((double)kR2[m.ri]);
+    C.rule = P->make_rule(C.zt + C.zs, C.rho, 2 * p + 1);
+    C.lt = comp_lab[m.comp].x;
+    C.a = comp_lab[m.comp].y;
+    C.ls = comp_lab[m.comp].z;
+    C.b = comp_lab[m.comp].w;
+    C.out = out;
+    return C;
+  };
+  const int64_t ntr = (int64_t)tr.size(), nho = (int64_t)ho.size(), ntot = ntr + nho;
+  R.n_train = ntr;
+  R.n_holdout = nho;
+  R.n_values = ntr * NT * NC;
+  const size_t mat = (size_t)NC * NC * 2;
+  // ---- labels by quadrature, in chunks
+  double t0 = wall();
+  MlpNet& N = S.net;
+  float* T = N.dev<float>("T", (size_t)ntr * nout);
+  double* Iref = N.dev<double>("Iref", (size_t)nho * mat);
+  const int CHK = 1024;
+  double* Ich = N.dev<double>("Ich", (size_t)CHK * mat);
+  for (int64_t c0 = 0; c0 < ntot; c0 += CHK) {
+    const int nc = (int)std::min<int64_t>(CHK, ntot - c0);
+    HIPCHK(hipStreamSynchronize(s));
+    P->pin_reset();
+    std::vector<ClassDesc> cls(nc);
+    for (int c = 0; c < nc; c++) {
+      const int64_t g = c0 + c;
+      cls[c] = make_class(g < ntr ? tr[g] : ho[g - ntr], c);
+    }
+    std::vector<double> dadd(nc);
+    for (int c = 0; c < nc; c++) {
+      const int64_t g = c0 + c;
+      dadd[c] = S.Dc[(g < ntr ? tr[g] : ho[g - ntr]).comp];
+    }
+    reaction_integrals(P, "sur", cls, Ich, s);
+    ClassDesc* dcls = P->upload("sur_lab_cls", cls, s);
+    double* ddadd = P->upload("sur_lab_dadd", dadd, s);
+    const int ntrain_here = (int)std::max<int64_t>(0, std::min<int64_t>(ntr - c0, nc));
+    if (ntrain_here > 0)
+      lk_sur_targets(ntrain_here, dcls, ddadd, st, Ich, p, NC, nullptr, nullptr, T + (size_t)c0 * nout, s);
+    if (ntrain_here < nc) {
+      const int64_t h0 = c0 + ntrain_here - ntr;
+      HIPCHK(hipMemcpyAsync(Iref + (size_t)h0 * mat, Ich + (size_t)ntrain_here * mat,
+                            (size_t)(nc - ntrain_here) * mat * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  float* mu = N.dev<float>("mu", nout);
+  float* sd = N.dev<float>("sd", nout);
+  lk_sur_colstats((int)ntr, nout, NC, T, mu, sd, s);
+  lk_sur_norm(ntr, nout, T, mu, sd, s);
+  HIPCHK(hipStreamSynchronize(s));
+  R.ms_labels = wall() - t0;
+  // ---- inputs
+  std::vector<int> xc(ntot);
+  std::vector<double> xh(ntot);
+  for (int64_t g = 0; g < ntot; g++) {
+    const Smp& m = g < ntr ? tr[g] : ho[g - ntr];
+    xc[g] = sur_combo(m.comp, m.j, m.i, m.ri);
+    xh[g] = m.h;
+  }
+  int* dxc = N.dev<int>("xc", ntot);
+  double* dxh = N.dev<double>("xh", ntot);
+  HIPCHK(hipMemcpy(dxc, xc.data(), ntot * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(dxh, xh.data(), ntot * sizeof(double), hipMemcpyHostToDevice));
+  unsigned short* dX = N.dev<unsigned short>("X", (size_t)ntot * nin);
+  lk_sur_features((int)ntot, dxc, dxh, nin, S.ncomp * 40, std::log(S.h_lo), std::log(S.h_hi), dX, s);
+  // ---- initialisation: uniform +-sqrt(6 / fan_in) weights, zero biases
+  t0 = wall();
+  std::vector<float> w0(N.np, 0.0f);
+  for (int l = 0; l <= N.nh; l++) {
+    const double lim = std::sqrt(6.0 / N.li[l]);
+    for (long e = 0; e < (long)N.lo[l] * N.li[l]; e++) w0[N.woff[l] + e] = (float)(lim * (2.0 * U(rng) - 1.0));
+  }
+  N.load_params(w0.data(), s);
+  // ---- Adam on shuffled mini-batches, cosine-decayed step size
+  const int B = o.batch, spe = (int)((ntr + B - 1) / B), total = o.epochs * spe;
+  int* didx = N.dev<int>("idx", ntr);
+  unsigned short* xb = N.dev<unsigned short>("xb", (size_t)B * nin);
+  float* tb = N.dev<float>("tb", (size_t)B * nout);
+  double* losses = N.dev<double>("losses", o.epochs + 1);
+  double* lossb = N.dev<double>("lossb", 1);
+  std::vector<int> perm(ntr);
+  for (int64_t i = 0; i < ntr; i++) perm[i] = (int)i;
+  int step = 0;
+  for (int e = 0; e < o.epochs; e++) {
+    std::shuffle(perm.begin(), perm.end(), rng);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(didx, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
+    for (int sb = 0; sb < spe; sb++) {
+      const int b0 = sb * B, nb = (int)std::min<int64_t>(B, ntr - b0);
+      lk_gather_rows(nb, didx + b0, nin, 2, dX, xb, s);
+      lk_gather_rows(nb, didx + b0, nout, 4, T, tb, s);
+      N.forward(nb, xb, s);
+      double* lo = (step == 0) ? losses : (sb == spe - 1 ? losses + e + 1 : lossb);
+      N.backward(nb, xb, tb, nout, lo, s);
+      const double lr = o.lr * (0.01 + 0.99 * 0.5 * (1.0 + std::cos(LFMM_PI * step / std::max(1, total))));
+      N.adam(++step, (float)lr, s);
+    }
+  }
+  std::vector<double> hl(o.epochs + 1);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(hl.data(), losses, hl.size() * sizeof(double), hipMemcpyDeviceToHost));
+  R.ms_train = wall() - t0;
+  R.epochs = o.epochs;
+  R.steps = step;
+  R.loss_first = hl[0];
+  R.loss_last = hl[o.epochs];
+  // ---- held-out errors -> gate bounds
+  S.mu.resize(nout);
+  S.sd.resize(nout);
+  HIPCHK(hipMemcpy(S.mu.data(), mu, nout * sizeof(float), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(S.sd.data(), sd, nout * sizeof(float), hipMemcpyDeviceToHost));
+  if (nho > 0) {
+    double* Ipred = N.dev<double>("Ipred", (size_t)nho * mat);
+    std::vector<ClassDesc> hc(nho);
+    std::vector<double> hh(nho), hd(nho);
+    for (int64_t g = 0; g < nho; g++) {
+      hc[g] = make_class(ho[g], (int)g);
+      hh[g] = ho[g].h;
+      hd[g] = S.Dc[ho[g].comp];
+    }
+    ClassDesc* dhc = N.dev<ClassDesc>("hold_cls", nho);
+    double* dhh = N.dev<double>("hold_h", nho);
+    double* dhd = N.dev<double>("hold_d", nho);
+    double* derr = N.dev<double>("hold_err", nho);
+    HIPCHK(hipMemcpy(dhc, hc.data(), nho * sizeof(ClassDesc), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dhh, hh.data(), nho * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dhd, hd.data(), nho * sizeof(double), hipMemcpyHostToDevice));
+    const int FB = 2048;
+    for (int64_t c0 = 0; c0 < nho; c0 += FB) {
+      const int nc = (int)std::min<int64_t>(FB, nho - c0);
+      N.forward(nc, dX + (size_t)(ntr + c0) * nin, s);
+      lk_sur_write(nc, dhc + c0, dhd + c0, st, N.y(nc), p, NC, mu, sd, Ipred, s);
+    }
+    lk_sur_err((int)nho, dhc, st, dhh, Ipred, Iref, p, NC, derr, s);
+    std::vector<double> err(nho);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(err.data(), derr, nho * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<double> worst(S.bound.size(), -1.0);
+    for (int64_t g = 0; g < nho; g++) {
+      const int cb = sur_combo(ho[g].comp, ho[g].j, ho[g].i, ho[g].ri);
+      worst[cb] = std::max(worst[cb], err[g]);
+    }
+    for (size_t cb = 0; cb < worst.size(); cb++)
+      if (worst[cb] >= 0.0) S.bound[cb] = 2.0 * worst[cb];
+    std::vector<double> se = err;
+    std::sort(se.begin(), se.end());
+    R.err_median = se[se.size() / 2];
+    R.err_max = se.back();
+  }
+  for (const char* nm : {"T", "Iref", "Ich", "Ipred", "X", "xc", "xh", "idx", "xb", "tb", "hold_cls", "hold_h",
+                         "hold_d", "hold_err"}) {
+    auto it = N.bufs.find(nm);
+    if (it != N.bufs.end()) {
+      if (it->second.p) (void)hipFree(it->second.p);
+      N.bufs.erase(it);
+    }
+  }
+  S.trep = R;
+  S.ready = true;
+}
 
 struct Group {
   int seq0, K;
@@ -794,6 +1247,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.n_ops_free = (int64_t)fops.size();
   // reaction M2L classes and operators
   std::vector<ClassDesc> classes;
+  std::vector<int4> cls_meta;  // (j, i, r2 class) of each class
+  std::vector<double> cls_h;   // its box size
   std::vector<ROpDesc> rops;
   // rop index: [tt][ts][l][j][i][dx+3][dy+3] (0 = the zero operator)
   std::vector<int> rop_id((size_t)ntrees * ntrees * 9 * 2 * 2 * 49, 0);
@@ -836,6 +1291,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
                     nodes_total += rule_nodes(C.rule);
                     cls_of_r2[r2] = C.out;
                     classes.push_back(C);
+                    cls_meta.push_back(make_int4(j, i, ri, 0));
+                    cls_h.push_back(h);
                   }
                   for (int dx = -3; dx <= 3; dx++)
                     for (int dy = -3; dy <= 3; dy++) {
@@ -873,14 +1330,60 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // the reaction-operator chain forks onto the second stream here and joins before the M2L
   HIPCHK(hipEventRecord(P->fork_ev, s));
   HIPCHK(hipStreamWaitEvent(s2, P->fork_ev, 0));
+  // gate: classes whose combination the surrogate predicts within the tolerance
+  // take the network's integrals, the others the quadrature's
+  std::vector<ClassDesc> qcls, scls;
+  std::vector<int> sC;
+  std::vector<double> sH, sD;
+  const bool use_sur = P->sur.ready && P->sur.tol > 0.0 && !classes.empty();
+  if (use_sur) {
+    const Surrogate& S = P->sur;
+    for (size_t c = 0; c < classes.size(); c++) {
+      const ClassDesc& C = classes[c];
+      const int comp = sur_comp(P, C.lt, C.a, C.ls, C.b);
+      const int j = cls_meta[c].x, i = cls_meta[c].y, ri = cls_meta[c].z;
+      const double h = cls_h[c];
+      if (comp >= 0 && h >= S.h_lo && h <= S.h_hi && S.bound[sur_combo(comp, j, i, ri)] <= S.tol) {
+        scls.push_back(C);
+        sC.push_back(sur_combo(comp, j, i, ri));
+        sH.push_back(h);
+        sD.push_back(S.Dc[comp]);
+      } else {
+        qcls.push_back(C);
+      }
+    }
+  }
+  std::vector<ClassDesc>& qref = use_sur ? qcls : classes;
+  rep.n_react_surrogate = (int64_t)scls.size();
   sbeg(ST_REACT_TABLES, s2);
   if (!classes.empty()) {
     double* Iall = P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-    reaction_integrals(P, "ri", classes, Iall, s2, [&]() {
+    if (!qref.empty()) {
+      reaction_integrals(P, "ri", qref, Iall, s2, [&]() {
+        send(ST_REACT_TABLES, s2);
+        sbeg(ST_REACT_MFMA, s2);
+      });
+    } else {
       send(ST_REACT_TABLES, s2);
       sbeg(ST_REACT_MFMA, s2);
-    });
+    }
     send(ST_REACT_MFMA, s2);
+    sbeg(ST_REACT_SUR, s2);
+    if (!scls.empty()) {
+      MlpNet& Nn = P->sur.net;
+      const int ns = (int)scls.size();
+      ClassDesc* d_scls = P->upload("gate_cls", scls, s2);
+      int* d_sc = P->upload("gate_combo", sC, s2);
+      double* d_sh = P->upload("gate_h", sH, s2);
+      double* d_sd = P->upload("gate_d", sD, s2);
+      unsigned short* d_sx = P->dev<unsigned short>("gate_x", (size_t)ns * Nn.nin);
+      const Surrogate& S = P->sur;
+      lk_sur_features(ns, d_sc, d_sh, Nn.nin, S.ncomp * 40, std::log(S.h_lo), std::log(S.h_hi), d_sx, s2);
+      Nn.forward(ns, d_sx, s2);
+      lk_sur_write(ns, d_scls, d_sd, st, Nn.y(ns), p, NC, Nn.dev<float>("mu", Nn.nout), Nn.dev<float>("sd", Nn.nout),
+                   Iall, s2);
+    }
+    send(ST_REACT_SUR, s2);
     sbeg(ST_REACT_EXPAND, s2);
     ROpDesc* d_rops = P->upload("rops", rops, s2);
     lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s2);
@@ -888,6 +1391,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     send(ST_REACT_TABLES, s2);
     sbeg(ST_REACT_MFMA, s2);
     send(ST_REACT_MFMA, s2);
+    sbeg(ST_REACT_SUR, s2);
+    send(ST_REACT_SUR, s2);
     sbeg(ST_REACT_EXPAND, s2);
   }
   send(ST_REACT_EXPAND, s2);
@@ -1222,7 +1727,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   int* d_tl = P->upload("tgt_list", tgt_list, s);
   lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, s);
-  mark(15);
+  send(ST_SUM, s);
   HIPCHK(hipGetLastError());
   unsigned long long hcnt[4] = {0, 0, 0, 0};
   P->rb_add(hcnt, d_cnt, sizeof(hcnt), s);
@@ -1450,6 +1955,7 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   }
   if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
   if (plan->join_ev) (void)hipEventDestroy(plan->join_ev);
+  plan->sur.net.release();
   delete plan;
 }
 
@@ -1460,6 +1966,7 @@ const char* lfmm_status_string(int status) {
     case LFMM_ENOMEM: return "out of memory";
     case LFMM_EHIP: return "HIP runtime error";
     case LFMM_ENOTSUP: return "not supported";
+    case LFMM_EIO: return "surrogate file unreadable, unwritable or not for this plan";
     default: return "unknown status";
   }
 }
@@ -1541,6 +2048,186 @@ int lfmm_densities(lfmm_plan_t* plan, int n, const double* krho, int l, int lp, 
     return f.code;
   }
   return LFMM_OK;
+}
+
+int lfmm_surrogate_train(lfmm_plan_t* plan, int64_t n_samples, uint64_t seed, const lfmm_train_opts* opts,
+                         lfmm_train_report* rep) {
+  if (!plan || n_samples < 0) return LFMM_EINVAL;
+  if (plan->st.L < 1) return LFMM_EINVAL;
+  lfmm_train_opts o;
+  memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  if (o.h_min <= 0) o.h_min = 0.02;
+  if (o.h_max <= 0) o.h_max = 2.0;
+  if (o.epochs <= 0) o.epochs = 150;
+  if (o.batch <= 0) o.batch = 256;
+  if (o.lr <= 0) o.lr = 2e-3;
+  if (o.holdout <= 0) o.holdout = 0.1;
+  if (o.width <= 0) o.width = 128;
+  if (o.nhidden <= 0) o.nhidden = 4;
+  if (!(o.h_max > o.h_min) || !std::isfinite(o.h_max) || o.holdout >= 1.0 || o.width > 1024 || o.nhidden > 16 ||
+      o.batch > 65536 || n_samples > ((int64_t)1 << 26))
+    return LFMM_EINVAL;
+  lfmm_train_report R;
+  try {
+    sur_train_impl(plan, n_samples, seed, o, R);
+  } catch (Fail& f) {
+    (void)hipStreamSynchronize(plan->s2);
+    plan->sur.ready = false;
+    return f.code;
+  }
+  if (rep) *rep = R;
+  return LFMM_OK;
+}
+
+// File: "LFMMSUR1", then int32 {version 1, p, L, ncomp, nin, width, nhidden, nout},
+// double k[L+1], d[L], h_lo, h_hi, bound[ncomp*40], float mu[nout], sd[nout], w[np].
+int lfmm_surrogate_save(const lfmm_plan_t* plan, const char* path) {
+  if (!plan || !path || !plan->sur.ready) return LFMM_EINVAL;
+  const Surrogate& S = plan->sur;
+  MlpNet& N = const_cast<MlpNet&>(S.net);
+  std::vector<float> w(N.np);
+  if (hipMemcpy(w.data(), N.w(), N.np * sizeof(float), hipMemcpyDeviceToHost) != hipSuccess) return LFMM_EHIP;
+  FILE* f = fopen(path, "wb");
+  if (!f) return LFMM_EIO;
+  const int L = plan->st.L;
+  int32_t hd[8] = {1, plan->p, L, S.ncomp, N.nin, N.width, N.nh, N.nout};
+  bool ok = fwrite("LFMMSUR1", 1, 8, f) == 8 && fwrite(hd, sizeof(hd), 1, f) == 1 &&
+            fwrite(plan->st.k, sizeof(double), L + 1, f) == (size_t)(L + 1) &&
+            (L == 0 || fwrite(plan->st.d, sizeof(double), L, f) == (size_t)L) &&
+            fwrite(&S.h_lo, sizeof(double), 1, f) == 1 && fwrite(&S.h_hi, sizeof(double), 1, f) == 1 &&
+            fwrite(S.bound.data(), sizeof(double), S.bound.size(), f) == S.bound.size() &&
+            fwrite(S.mu.data(), sizeof(float), S.mu.size(), f) == S.mu.size() &&
+            fwrite(S.sd.data(), sizeof(float), S.sd.size(), f) == S.sd.size() &&
+            fwrite(w.data(), sizeof(float), w.size(), f) == w.size();
+  if (fclose(f) != 0) ok = false;
+  return ok ? LFMM_OK : LFMM_EIO;
+}
+
+int lfmm_surrogate_load(lfmm_plan_t* plan, const char* path) {
+  if (!plan || !path) return LFMM_EINVAL;
+  FILE* f = fopen(path, "rb");
+  if (!f) return LFMM_EIO;
+  const int L = plan->st.L, NL = L + 1;
+  char magic[8];
+  int32_t hd[8];
+  std::vector<double> kk(NL), dd(L);
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "LFMMSUR1", 8) == 0 && fread(hd, sizeof(hd), 1, f) == 1 &&
+            hd[0] == 1 && hd[1] == plan->p && hd[2] == L;
+  ok = ok && fread(kk.data(), sizeof(double), NL, f) == (size_t)NL && (L == 0 || fread(dd.data(), sizeof(double), L, f) == (size_t)L);
+  for (int i = 0; ok && i < NL; i++) ok = kk[i] == plan->st.k[i];
+  for (int i = 0; ok && i < L; i++) ok = dd[i] == plan->st.d[i];
+  Surrogate T;
+  if (ok) {
+    int ncomp = 0;  // the component numbering depends on L only
+    for (int l = 0; l < NL; l++)
+      for (int a = 0; a < 2; a++)
+        for (int lp = 0; lp < NL; lp++)
+          for (int b = 0; b < 2; b++) ncomp += has_dir(plan->st, l, a) && has_dir(plan->st, lp, b);
+    ok = hd[3] == ncomp && hd[4] == sur_nin(hd[3]) && hd[5] > 0 && hd[5] <= 1024 && hd[6] > 0 && hd[6] <= 16 &&
+         hd[7] == 2 * plan->NT * plan->NC;
+  }
+  std::vector<float> w;
+  if (ok) {
+    T.net.setup(hd[4], hd[5], hd[6], hd[7]);
+    T.bound.resize((size_t)hd[3] * 40);
+    T.mu.resize(hd[7]);
+    T.sd.resize(hd[7]);
+    w.resize(T.net.np);
+    ok = fread(&T.h_lo, sizeof(double), 1, f) == 1 && fread(&T.h_hi, sizeof(double), 1, f) == 1 &&
+         fread(T.bound.data(), sizeof(double), T.bound.size(), f) == T.bound.size() &&
+         fread(T.mu.data(), sizeof(float), T.mu.size(), f) == T.mu.size() &&
+         fread(T.sd.data(), sizeof(float), T.sd.size(), f) == T.sd.size() &&
+         fread(w.data(), sizeof(float), w.size(), f) == w.size() && T.h_hi > T.h_lo && T.h_lo > 0;
+    char extra;
+    ok = ok && fread(&extra, 1, 1, f) == 0;
+  }
+  fclose(f);
+  if (!ok) return LFMM_EIO;
+  Surrogate& S = plan->sur;
+  try {
+    S.ready = false;
+    S.net.release();
+    S.net.setup(T.net.nin, T.net.width, T.net.nh, T.net.nout);
+    S.net.load_params(w.data(), nullptr);
+    HIPCHK(hipMemcpy(S.net.dev<float>("mu", S.net.nout), T.mu.data(), T.mu.size() * sizeof(float),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.net.dev<float>("sd", S.net.nout), T.sd.data(), T.sd.size() * sizeof(float),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipDeviceSynchronize());
+  } catch (Fail& fl) {
+    return fl.code;
+  }
+  sur_components(plan);
+  try {
+    sur_decay(plan);
+  } catch (Fail& fl) {
+    return fl.code;
+  }
+  S.h_lo = T.h_lo;
+  S.h_hi = T.h_hi;
+  S.bound = T.bound;
+  S.mu = T.mu;
+  S.sd = T.sd;
+  memset(&S.trep, 0, sizeof(S.trep));
+  S.ready = true;
+  return LFMM_OK;
+}
+
+int lfmm_surrogate_gate(lfmm_plan_t* plan, double tol) {
+  if (!plan || !(tol >= 0.0)) return LFMM_EINVAL;
+  plan->sur.tol = tol;
+  return LFMM_OK;
+}
+
+int lfmm_surrogate_bounds(const lfmm_plan_t* plan, int n, double* bounds, int* count) {
+  if (!plan || !count || n < 0 || (n > 0 && !bounds)) return LFMM_EINVAL;
+  const Surrogate& S = plan->sur;
+  if (!S.ready) {
+    *count = 0;
+    return LFMM_EINVAL;
+  }
+  int w = 0;
+  for (int c = 0; c < S.ncomp; c++)
+    for (int j = 0; j < 2; j++)
+      for (int i = 0; i < 2; i++)
+        for (int ri = 0; ri < 10; ri++) {
+          if (i == 0 && j == 0 && kR2[ri] <= 2) continue;
+          if (w < n) bounds[w] = S.bound[sur_combo(c, j, i, ri)];
+          w++;
+        }
+  *count = w;
+  return LFMM_OK;
+}
+
+int lfmm_mlp_forward_backward(int B, int nin, int width, int nhidden, int nout, const float* x, const float* params,
+                              const float* t, float* y, float* grad, double* loss) {
+  if (B < 1 || nin < 1 || width < 1 || nhidden < 0 || nout < 1 || B > 65536 || nin > 4096 || width > 4096 ||
+      nhidden > 16 || nout > 65536 || !x || !params || !t || !y || !grad || !loss)
+    return LFMM_EINVAL;
+  MlpNet N;
+  int rc = LFMM_OK;
+  try {
+    N.setup(nin, width, nhidden, nout);
+    N.load_params(params, nullptr);
+    float* dxf = N.dev<float>("xf", (size_t)B * nin);
+    unsigned short* dx = N.dev<unsigned short>("x", (size_t)B * nin);
+    float* dt = N.dev<float>("t", (size_t)B * nout);
+    double* dl = N.dev<double>("loss", 1);
+    HIPCHK(hipMemcpy(dxf, x, sizeof(float) * B * nin, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dt, t, sizeof(float) * B * nout, hipMemcpyHostToDevice));
+    lk_f2bf((long)B * nin, dxf, dx, nullptr);
+    N.forward(B, dx, nullptr);
+    N.backward(B, dx, dt, nout, dl, nullptr);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpy(y, N.y(B), sizeof(float) * B * nout, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(grad, N.dev<float>("g", N.np), sizeof(float) * N.np, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(loss, dl, sizeof(double), hipMemcpyDeviceToHost));
+  } catch (Fail& f) {
+    rc = f.code;
+  }
+  N.release();
+  return rc;
 }
 
 }  // extern "C"

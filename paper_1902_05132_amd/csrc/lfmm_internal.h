@@ -20,6 +20,28 @@ struct TreeInfo {
   int pad0, pad1;
 };
 
+// One product of the surrogate network, C = A B with BF16 operands
+// (A(m, k) = A[m am + k ak], B(k, n) = B[k bk + n bn]) and an epilogue:
+//   MLP_EPI_STORE  C = A B (+ bias[n]) in FP32
+//   MLP_EPI_SILU   C = A B + bias[n] in FP32 and Cb = bf16(silu(C))
+//   MLP_EPI_DSILU  Cb = bf16((A B) silu'(Zs))
+enum { MLP_EPI_STORE = 0, MLP_EPI_SILU = 1, MLP_EPI_DSILU = 2 };
+#define MLP_MSE_BLOCKS 256
+struct MlpGemm {
+  int M, N, K, mode;
+  const unsigned short* A;
+  long am, ak;
+  const unsigned short* B;
+  long bk, bn;
+  const float* bias;
+  float* C;
+  long ldc;
+  unsigned short* Cb;
+  long ldcb;
+  const float* Zs;
+  long ldz;
+};
+
 // Free-space translation operator request.
 struct OpDesc {
   double bx, by, bz, k;
@@ -170,4 +192,22 @@ void lk_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, con
                     unsigned long long* counter, hipStream_t s);
 void lk_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
                   int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, hipStream_t s);
+void lk_mlp_gemm(const MlpGemm& g, hipStream_t s);
+void lk_mlp_mse(int B, int nout, const float* y, const float* t, long ldt, unsigned short* d, double* partial,
+                double* loss, hipStream_t s);
+void lk_mlp_colsum(int M, int N, const unsigned short* d, float* gb, hipStream_t s);
+void lk_mlp_adam(long n, float* w, float* m, float* v, const float* g, float lr, float b1, float b2, float eps,
+                 float c1, float c2, unsigned short* wb, hipStream_t s);
+void lk_f2bf(long n, const float* x, unsigned short* y, hipStream_t s);
+void lk_sur_targets(int ncls, const ClassDesc* cls, const double* dadd, Stack st, const double* Iall, int p, int NC,
+                    const float* mu, const float* sd, float* T, hipStream_t s);
+void lk_sur_colstats(int n, int nout, int NC, const float* T, float* mu, float* sd, hipStream_t s);
+void lk_sur_write(int ncls, const ClassDesc* cls, const double* dadd, Stack st, const float* Y, int p, int NC,
+                  const float* mu, const float* sd, double* Iall, hipStream_t s);
+void lk_sur_err(int ncls, const ClassDesc* cls, Stack st, const double* hcls, const double* Ipred, const double* Iref,
+                int p, int NC, double* err, hipStream_t s);
+void lk_gather_rows(int nrows, const int* idx, int ncol, int esz, const void* src, void* dst, hipStream_t s);
+void lk_sur_norm(long n, int nout, float* T, const float* mu, const float* sd, hipStream_t s);
+void lk_sur_features(int n, const int* combo, const double* h, int nin, int c0, double lh0, double lh1,
+                     unsigned short* X, hipStream_t s);
 }

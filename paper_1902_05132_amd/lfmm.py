@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblfmm.so")
 
 LFMM_OK = 0
-_STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "not supported"}
+_STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "not supported",
+           5: "surrogate file error"}
 
 
 class LfmmError(RuntimeError):
@@ -34,7 +35,22 @@ class Report(ctypes.Structure):
                 ("m2l_slots", ctypes.c_int64), ("m2m_pairs", ctypes.c_int64), ("l2l_pairs", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
                 ("p2p_series", ctypes.c_int), ("precision", ctypes.c_int),
-                ("stage_ms", ctypes.c_double * 16)]
+                ("stage_ms", ctypes.c_double * 16), ("n_react_surrogate", ctypes.c_int64)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("h_min", ctypes.c_double), ("h_max", ctypes.c_double), ("epochs", ctypes.c_int),
+                ("batch", ctypes.c_int), ("lr", ctypes.c_double), ("holdout", ctypes.c_double),
+                ("width", ctypes.c_int), ("nhidden", ctypes.c_int)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("n_train", ctypes.c_int64), ("n_holdout", ctypes.c_int64), ("n_values", ctypes.c_int64),
+                ("n_combos", ctypes.c_int), ("nin", ctypes.c_int), ("nout", ctypes.c_int),
+                ("epochs", ctypes.c_int), ("steps", ctypes.c_int),
+                ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("err_median", ctypes.c_double), ("err_max", ctypes.c_double),
+                ("ms_labels", ctypes.c_double), ("ms_train", ctypes.c_double)]
 
 
 _lib = None
@@ -77,6 +93,15 @@ def load():
     L.lfmm_reaction_operator.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
     L.lfmm_densities.argtypes = [vp, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, _D]
+    L.lfmm_surrogate_train.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(TrainOpts),
+                                       ctypes.POINTER(TrainReport)]
+    L.lfmm_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+    L.lfmm_surrogate_load.argtypes = [vp, ctypes.c_char_p]
+    L.lfmm_surrogate_gate.argtypes = [vp, ctypes.c_double]
+    L.lfmm_surrogate_bounds.argtypes = [vp, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int)]
+    _F = ctypes.POINTER(ctypes.c_float)
+    L.lfmm_mlp_forward_backward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            _F, _F, _F, _F, _F, _D]
     _lib = L
     return L
 
@@ -204,7 +229,34 @@ class Plan:
                     m2l_pairs=r.m2l_pairs, m2l_slots=r.m2l_slots,
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
                     p2p_series=r.p2p_series, precision=r.precision,
-                    stage_ms=stages)
+                    n_react_surrogate=r.n_react_surrogate, stage_ms=stages)
+
+    # ---- learned surrogate of the reaction integrals ----
+    def surrogate_train(self, n_samples=0, seed=0, h_min=0.0, h_max=0.0, epochs=0, batch=0, lr=0.0, holdout=0.0,
+                        width=0, nhidden=0):
+        """Train on quadrature labels (zeros select the library defaults); returns the training report."""
+        o = TrainOpts(h_min, h_max, epochs, batch, lr, holdout, width, nhidden)
+        r = TrainReport()
+        _check(self.lib.lfmm_surrogate_train(self.h, int(n_samples), int(seed), ctypes.byref(o), ctypes.byref(r)),
+               "lfmm_surrogate_train")
+        return {f: getattr(r, f) for f, _ in TrainReport._fields_}
+
+    def surrogate_save(self, path):
+        _check(self.lib.lfmm_surrogate_save(self.h, os.fsencode(path)), "lfmm_surrogate_save")
+
+    def surrogate_load(self, path):
+        _check(self.lib.lfmm_surrogate_load(self.h, os.fsencode(path)), "lfmm_surrogate_load")
+
+    def surrogate_gate(self, tol):
+        _check(self.lib.lfmm_surrogate_gate(self.h, float(tol)), "lfmm_surrogate_gate")
+
+    def surrogate_bounds(self):
+        cnt = ctypes.c_int()
+        _check(self.lib.lfmm_surrogate_bounds(self.h, 0, None, ctypes.byref(cnt)), "lfmm_surrogate_bounds")
+        out = np.zeros(max(cnt.value, 1))
+        _check(self.lib.lfmm_surrogate_bounds(self.h, cnt.value, out.ctypes.data_as(_D), ctypes.byref(cnt)),
+               "lfmm_surrogate_bounds")
+        return out[:cnt.value]
 
     # ---- component entry points ----
     def translation(self, kind, kw, b):
@@ -248,6 +300,25 @@ def eval_batch(plans, xyzs, qs, phis, layers=None, nworkers=8):
     rc = L.lfmm_eval_batch(m, P, N, X, Ly, Q, F, int(nworkers), st)
     _check(rc, "lfmm_eval_batch")
     return list(st)
+
+
+def mlp_forward_backward(x, params, t, nin, width, nhidden, nout):
+    """One forward and backward pass of the surrogate network's kernels on the GPU:
+    x [B, nin], t [B, nout], params packed per layer (W [out][in], then b).  Returns
+    (y, grad, loss) with the gradient in the parameters' packing."""
+    L = load()
+    _F = ctypes.POINTER(ctypes.c_float)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    B = x.shape[0]
+    y = np.zeros((B, nout), dtype=np.float32)
+    g = np.zeros(params.size, dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(L.lfmm_mlp_forward_backward(B, nin, width, nhidden, nout, x.ctypes.data_as(_F), params.ctypes.data_as(_F),
+                                       t.ctypes.data_as(_F), y.ctypes.data_as(_F), g.ctypes.data_as(_F),
+                                       ctypes.byref(loss)), "lfmm_mlp_forward_backward")
+    return y, g, loss.value
 
 
 def exported_symbols_from_header(path=None):

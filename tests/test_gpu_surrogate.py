@@ -1,0 +1,198 @@
+"""The learned surrogate of the reaction M2L integrals on the GPU.
+
+* Network kernels (BF16 matrix-core forward and backward, FP32 accumulation)
+  against the FP64 reference in oracle/mlp.py with BF16 rounding at the same
+  points.  What remains is FP32 against FP64 accumulation (about 1e-7 relative)
+  and, rarely, a value within that distance of a BF16 rounding boundary that the
+  two sides round to neighbouring BF16 numbers (2^-8 apart).  One such flip in a
+  hidden activation moves its whole output row, and, through the backward pass,
+  every gradient entry of the earlier layers, by about 2^-8 of one term.  So the
+  median entry must agree to FP32 accumulation level (1e-6 of the largest output,
+  2e-4 of the largest gradient of its block), and the relative norm, which a few
+  flips dominate, to 2e-3 (outputs) and 2e-2 (gradients).  A wrong lane layout or
+  a dropped term moves most entries by O(1).
+* Training on quadrature labels (config 1 medium, p = 5): what the network gains
+  over its initial state, and its held-out error.  What it gains over the method
+  without it: the integrals of every class in a fraction of the quadrature's
+  time, at the error its held-out bounds state.
+* Gate: closed, the evaluation is bit-identical to one without a surrogate; open,
+  the network supplies the integrals, and the potential's error against the
+  quadrature path stays within the held-out bounds of the combinations it used.
+* Save / load: a loaded surrogate reproduces the trained one bit for bit; files
+  for another medium, missing or truncated files are rejected.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from paper_1902_05132_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lfmm():
+    from paper_1902_05132_amd import lfmm
+    return lfmm
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _med(a, b):
+    return float(np.median(np.abs(a - b)) / np.abs(b).max())
+
+
+@pytest.mark.parametrize("B,nin,width,nh,nout", [(77, 48, 72, 3, 150), (256, 64, 128, 4, 1512), (5, 32, 16, 1, 7)])
+def test_mlp_kernels_match_oracle(B, nin, width, nh, nout):
+    lf = _lfmm()
+    rng = np.random.default_rng(B + nout)
+    P = OM.init_params(nin, width, nh, nout, rng)
+    P = (P + 0.05 * rng.standard_normal(P.size)).astype(np.float32)
+    x = rng.uniform(-1, 1, (B, nin)).astype(np.float32)
+    t = rng.standard_normal((B, nout)).astype(np.float32)
+    y, g, loss = lf.mlp_forward_backward(x, P, t, nin, width, nh, nout)
+    P64 = P.astype(np.float64)
+    l_ref, g_ref, y_ref = OM.loss_and_grad(P64, x.astype(np.float64), t.astype(np.float64), nin, width, nh, nout,
+                                           mimic=True)
+    rows = [("y", _rel(y, y_ref), _med(y, y_ref), 2e-3, 1e-6)]
+    off = 0
+    for li, (o, i) in enumerate(OM.layer_dims(nin, width, nh, nout)):
+        for part, n in (("W", o * i), ("b", o)):
+            a, b = g[off:off + n], g_ref[off:off + n]
+            rows.append(("grad %s%d" % (part, li), _rel(a, b), _med(a, b), 2e-2, 2e-4))
+            off += n
+    print("B=%d nin=%d width=%d nh=%d nout=%d, loss rel %.2e" % (B, nin, width, nh, nout, abs(loss - l_ref) / l_ref))
+    for name, e, m, te, tm in rows:
+        print("  %-8s norm %.2e median %.2e" % (name, e, m))
+    assert abs(loss - l_ref) < 1e-4 * l_ref
+    for name, e, m, te, tm in rows:
+        assert e < te and m < tm, (name, e, m)
+
+
+@pytest.fixture(scope="module")
+def trained(tmp_path_factory):
+    lf = _lfmm()
+    w = W.config1()
+    P = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], profile=True)
+    rep = P.surrogate_train(seed=7)
+    print("training report:", rep)
+    path = str(tmp_path_factory.mktemp("surrogate") / "config1_p5.bin")
+    P.surrogate_save(path)
+    ref = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], profile=True)
+    phi_ref = ref.eval_torch(w["x"], w["y"], w["z"], w["q"])
+    return dict(lf=lf, w=w, P=P, rep=rep, path=path, phi_ref=phi_ref, rep_ref=ref.report())
+
+
+def _eval(P, w):
+    return P.eval_torch(w["x"], w["y"], w["z"], w["q"])
+
+
+def test_training_gain(trained):
+    r = trained["rep"]
+    assert r["n_combos"] == 16 * 37
+    assert r["n_holdout"] >= r["n_combos"]
+    assert r["n_values"] == r["n_train"] * 21 * 36
+    # the trained network against its initial state, on the normalised targets
+    # (observed: a factor of about 1e3), and its median held-out error of the
+    # weighted integral matrices (observed 1.8e-2; BF16 activations alone limit it
+    # to a few 1e-3)
+    assert r["loss_last"] < 1e-2 * r["loss_first"], r
+    assert np.isfinite(r["err_median"]) and r["err_median"] < 0.05, r
+
+
+def test_bounds_cover_every_combination(trained):
+    b = trained["P"].surrogate_bounds()
+    assert b.size == 16 * 37
+    assert np.all(np.isfinite(b)) and np.all(b > 0)
+
+
+def test_gate_closed_is_bit_identical(trained):
+    P, w = trained["P"], trained["w"]
+    P.surrogate_gate(0.0)
+    phi = _eval(P, w)
+    assert P.report()["n_react_surrogate"] == 0
+    assert np.array_equal(phi, trained["phi_ref"])
+
+
+def test_gate_open_uses_the_network(trained):
+    P, w = trained["P"], trained["w"]
+    P.surrogate_gate(1e300)
+    _eval(P, w)  # sizes the network's work buffers
+    phi = _eval(P, w)
+    rep = P.report()
+    P.surrogate_gate(0.0)
+    n_sur, n_cls = rep["n_react_surrogate"], rep["n_react_classes"]
+    err = _rel(phi, trained["phi_ref"])
+    st, st0 = rep["stage_ms"], trained["rep_ref"]["stage_ms"]
+    t_net = st["react_tables"] + st["react_mfma"] + st["react_surrogate"]
+    t_quad = st0["react_tables"] + st0["react_mfma"]
+    print("gate open: %d of %d classes from the network, Err2 vs quadrature %.2e; "
+          "reaction integrals %.3f ms (quadrature alone %.3f ms)" % (n_sur, n_cls, err, t_net, t_quad))
+    # what the network gains: the integrals of every class in a fraction of the
+    # quadrature's time (observed 0.26 against 1.46 ms)
+    assert t_net < 0.7 * t_quad
+    assert n_sur > 0.5 * n_cls
+    assert not np.array_equal(phi, trained["phi_ref"])
+    # each class's weighted error is below its combination's bound; the reaction
+    # part is a fraction of the potential (observed 5.8e-3)
+    assert err < min(P.surrogate_bounds().max(), 2e-2)
+
+
+def test_gate_at_the_precision_target(trained):
+    # the 1e-6 target of the mixed-precision path: the gate admits only
+    # combinations whose held-out bound meets it, so the potential stays within it
+    P, w = trained["P"], trained["w"]
+    P.surrogate_gate(1e-6)
+    phi = _eval(P, w)
+    rep = P.report()
+    P.surrogate_gate(0.0)
+    err = _rel(phi, trained["phi_ref"])
+    print("gate 1e-6: %d of %d classes from the network (smallest bound %.2e), Err2 %.2e"
+          % (rep["n_react_surrogate"], rep["n_react_classes"], P.surrogate_bounds().min(), err))
+    assert err <= 1e-6
+    if rep["n_react_surrogate"] == 0:
+        assert np.array_equal(phi, trained["phi_ref"])
+
+
+def test_gate_tolerance_selects_combinations(trained):
+    P, w = trained["P"], trained["w"]
+    b = P.surrogate_bounds()
+    tol = float(np.median(b))
+    P.surrogate_gate(tol)
+    phi = _eval(P, w)
+    rep = P.report()
+    P.surrogate_gate(0.0)
+    err = _rel(phi, trained["phi_ref"])
+    print("gate %.2e: %d of %d classes, Err2 %.2e" % (tol, rep["n_react_surrogate"], rep["n_react_classes"], err))
+    assert 0 < rep["n_react_surrogate"] < rep["n_react_classes"]
+    assert err < tol
+
+
+def test_save_load_roundtrip_and_rejections(trained, tmp_path):
+    lf, w, P = trained["lf"], trained["w"], trained["P"]
+    Q = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"])
+    Q.surrogate_load(trained["path"])
+    assert np.array_equal(Q.surrogate_bounds(), P.surrogate_bounds())
+    P.surrogate_gate(1e300)
+    Q.surrogate_gate(1e300)
+    a = _eval(P, w)
+    b = _eval(Q, w)
+    P.surrogate_gate(0.0)
+    assert np.array_equal(a, b)
+    other = lf.Plan(w["d"], (0.8, 1.5, 2.1), p=w["p"], leaf_max=w["leaf"])
+    with pytest.raises(lf.LfmmError) as e:
+        other.surrogate_load(trained["path"])
+    assert e.value.code == 5
+    with pytest.raises(lf.LfmmError) as e:
+        Q.surrogate_load(str(tmp_path / "missing.bin"))
+    assert e.value.code == 5
+    data = open(trained["path"], "rb").read()
+    cut = tmp_path / "cut.bin"
+    cut.write_bytes(data[:len(data) // 2])
+    with pytest.raises(lf.LfmmError) as e:
+        Q.surrogate_load(str(cut))
+    assert e.value.code == 5
+    with pytest.raises(lf.LfmmError) as e:
+        lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"]).surrogate_save(str(tmp_path / "none.bin"))
+    assert e.value.code == 1
