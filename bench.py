@@ -107,6 +107,53 @@ def cpu_fmm_sample(p, leaf, n=12288, seed=2):
             "sample": "whole evaluation of N=%d (same medium, p=%d, leaf<=%d); %.1f s" % (n, p, leaf, dt)}
 
 
+def surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch):
+    """The learned surrogate of the reaction M2L integrals on the bench workload
+    (mixed precision): trained once on quadrature labels (not timed, as a table
+    would be built once per medium), then timed with the gate at the 1e-6 target
+    and with the gate open, each against the plain FP64 path."""
+    n = len(w["x"])
+    plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=1)
+    t0 = time.perf_counter()
+    tr = plan.surrogate_train(seed=4)
+    t_train = time.perf_counter() - t0
+    log("bench: surrogate trained in %.1f s: %d classes (%d held out), held-out weighted error median %.2e, max %.2e"
+        % (t_train, tr["n_train"], tr["n_holdout"], tr["err_median"], tr["err_max"]))
+    res = {"train": {"classes": tr["n_train"], "held_out": tr["n_holdout"], "values": tr["n_values"],
+                     "seconds": t_train, "ms_labels": tr["ms_labels"], "ms_train": tr["ms_train"],
+                     "loss_first": tr["loss_first"], "loss_last": tr["loss_last"],
+                     "held_out_err_median": tr["err_median"], "held_out_err_max": tr["err_max"],
+                     "smallest_gate_bound": float(plan.surrogate_bounds().min())}}
+    phi = torch.empty(n, dtype=torch.complex128, device=xyz.device)
+    for name, tol in (("gate_1e-6", TOL_MIXED), ("gate_open", 1e300)):
+        plan.surrogate_gate(tol)
+        for i in range(args.warmup):
+            plan.eval_device(xyz, q, phi, stream=stream)
+        torch.cuda.synchronize()
+        acc = {}
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.eval_device(xyz, q, phi, stream=stream)
+            rep = plan.report()
+            for kname, v in rep["stage_ms"].items():
+                acc[kname] = acc.get(kname, 0.0) + v
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        d = phi - plain["phi"]
+        err2 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(plain["phi"]))
+        errmax = float(d.abs().max() / plain["phi"].abs().max())
+        st = {k: v / args.steps for k, v in acc.items()}
+        res[name] = {"gate_tol": tol, "classes_from_network": rep["n_react_surrogate"],
+                     "classes": rep["n_react_classes"], "ms_per_step": ms, "value": n / (ms / 1000.0),
+                     "speedup_vs_plain_fp64": plain["ms"] / ms, "rel_err_vs_fp64": {"err2": err2, "errmax": errmax},
+                     "reaction_integrals_ms": st["react_tables"] + st["react_mfma"] + st["react_surrogate"]}
+        log("bench: surrogate %s: %d of %d classes from the network, %.3f ms/step, Err2 %.2e, Errmax %.2e, "
+            "reaction integrals %.3f ms" % (name, rep["n_react_surrogate"], rep["n_react_classes"], ms, err2, errmax,
+                                              res[name]["reaction_integrals_ms"]))
+    plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +164,7 @@ def main():
     ap.add_argument("--leaf", type=int, default=256)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--scaling", action="store_true",
                     help="also time N = 2^17 .. 2^21 of the same workload (both precisions), to show O(N) cost")
@@ -210,6 +258,8 @@ def main():
            "stages_ms": head["stages"], "roofline": roofline, "rooflines": head["rooflines"],
            "plain_fp64": {"value": plain["value"], "ms_per_step": plain["ms"], "dtype": "f64",
                           "stages_ms": plain["stages"], "rooflines": plain["rooflines"]}}
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch)
     if args.scaling:
         rows = []
         for n2 in (1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21):
