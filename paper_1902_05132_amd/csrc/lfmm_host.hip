@@ -339,10 +339,11 @@ struct lfmm_plan_s {
   lfmm_report rep;
   hipEvent_t evb[ST_COUNT], eve[ST_COUNT];  // begin / end of each stage (profiling)
   bool ev_ok = false;
-  // second stream for the reaction-operator chain, which depends only on the trees
-  // and runs beside the free-space operators, job tables, P2M, M2M and near field
+  // second stream for the operator generation (free-space operators, then the
+  // reaction chain), which depends only on the trees and runs beside the job
+  // tables, P2M and near field of the main stream
   hipStream_t s2 = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr, ops_ev = nullptr;
   Surrogate sur;
 
   // device workspace in use: the plan's own, or one lent by a batch worker
@@ -545,6 +546,7 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     HIPCHK(hipStreamCreateWithFlags(&P->s2, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->ops_ev, hipEventDisableTiming));
   } catch (Fail& f) {
     lfmm_destroy(P);
     return f.code;
@@ -555,10 +557,23 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
 
 // Reaction integral matrices of the given classes into Iall (class c at c.out):
 // node tables per rule group (classes with the same quadrature rule and rho),
-// F per class, then the MFMA node sum.
-static void reaction_integrals(lfmm_plan_s* P, const char* tag, std::vector<ClassDesc>& classes, double* Iall,
-                               hipStream_t s, const std::function<void()>& after_tables = nullptr) {
-  if (classes.empty()) return;
+// F per class, then the MFMA node sum.  reaction_prep does the host bookkeeping
+// and the uploads (on stream up), reaction_launch the kernels (on stream s), so
+// that an evaluation can upload everything on its main stream before it forks
+// the kernels onto the second one (copies of both streams share one DMA queue:
+// an upload queued on the second stream behind its kernels would hold up every
+// later upload of the main stream).
+struct RIPrep {
+  ClassDesc* cls = nullptr;
+  RGDesc* rgs = nullptr;
+  SCDesc* scs = nullptr;
+  int* mem = nullptr;
+  double *J = nullptr, *Pt = nullptr, *F = nullptr;
+  int nrg = 0, ncls = 0, nsc = 0, nwg = 0, Ntot = 0, maxnn = 0;
+};
+static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDesc>& classes, hipStream_t up) {
+  RIPrep R;
+  if (classes.empty()) return R;
   const int p = P->p, Q = 2 * p, NT = P->NT, NL = P->st.L + 1;
   std::map<std::tuple<double, double, double, double, int, int, double>, int> key_rg;
   std::vector<RGDesc> rgs;
@@ -621,17 +636,33 @@ static void reaction_integrals(lfmm_plan_s* P, const char* tag, std::vector<Clas
     }
   }
   std::string t(tag);
-  ClassDesc* d_cls = P->upload((t + "_cls").c_str(), classes, s);
-  RGDesc* d_rgs = P->upload((t + "_rgs").c_str(), rgs, s);
-  SCDesc* d_scs = P->upload((t + "_scs").c_str(), scs, s);
-  int* d_mem = P->upload((t + "_mem").c_str(), members, s);
-  double* J = P->dev<double>((t + "_J").c_str(), (size_t)Ntot * (Q + 1) * 2);
-  double* Pt = P->dev<double>((t + "_P").c_str(), (size_t)NL * Ntot * NT * 2);
-  double* F = P->dev<double>((t + "_F").c_str(), (size_t)Ftot * 2);
-  lk_react_tables((int)rgs.size(), d_rgs, Ntot, P->st, p, J, Pt, s);
-  lk_react_F((int)classes.size(), d_cls, maxnn, P->st, F, s);
+  R.cls = P->upload((t + "_cls").c_str(), classes, up);
+  R.rgs = P->upload((t + "_rgs").c_str(), rgs, up);
+  R.scs = P->upload((t + "_scs").c_str(), scs, up);
+  R.mem = P->upload((t + "_mem").c_str(), members, up);
+  R.J = P->dev<double>((t + "_J").c_str(), (size_t)Ntot * (Q + 1) * 2);
+  R.Pt = P->dev<double>((t + "_P").c_str(), (size_t)NL * Ntot * NT * 2);
+  R.F = P->dev<double>((t + "_F").c_str(), (size_t)Ftot * 2);
+  R.nrg = (int)rgs.size();
+  R.ncls = (int)classes.size();
+  R.nsc = (int)scs.size();
+  R.nwg = nwg;
+  R.Ntot = Ntot;
+  R.maxnn = maxnn;
+  return R;
+}
+static void reaction_launch(lfmm_plan_s* P, const RIPrep& R, double* Iall, hipStream_t s,
+                            const std::function<void()>& after_tables = nullptr) {
+  if (!R.ncls) return;
+  lk_react_tables(R.nrg, R.rgs, R.Ntot, P->st, P->p, R.J, R.Pt, s);
+  lk_react_F(R.ncls, R.cls, R.maxnn, P->st, R.F, s);
   if (after_tables) after_tables();
-  lk_react_mfma(nwg, (int)scs.size(), d_scs, d_mem, d_cls, p, Ntot, J, Pt, F, Iall, P->NC, s);
+  lk_react_mfma(R.nwg, R.nsc, R.scs, R.mem, R.cls, P->p, R.Ntot, R.J, R.Pt, R.F, Iall, P->NC, s);
+}
+static void reaction_integrals(lfmm_plan_s* P, const char* tag, std::vector<ClassDesc>& classes, double* Iall,
+                               hipStream_t s) {
+  RIPrep R = reaction_prep(P, tag, classes, s);
+  reaction_launch(P, R, Iall, s);
 }
 
 inline int has_dir(const Stack& st, int l, int a) { return a == 0 ? (l <= st.L - 1) : (l >= 1); }
@@ -1193,7 +1224,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   double* pz = P->dev<double>("pz", ntp);
   double* pq = P->dev<double>("pq", 2 * (size_t)ntp);
   lk_gather(ntp, sg, d_trees, ntrees, perm, d_lstart, x, y, z, q, st, px, py, pz, pq, s);
-  mark(2);
+  send(ST_TREE, s);
+  sbeg(ST_JOBS, s);  // host operator and job tables, then the job kernels
   // ---------------- operators
   // expansion scale exponents of the mixed-precision M2L: c = 2^e, e = round(log2(1/(k h))) per (tree, level)
   std::vector<int> hse((size_t)ntrees * 9, 0);
@@ -1327,9 +1359,6 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     opse.resize(2 * (size_t)nops, 0);
     d_opsc = P->upload("op_scale", opse, s);
   }
-  // the reaction-operator chain forks onto the second stream here and joins before the M2L
-  HIPCHK(hipEventRecord(P->fork_ev, s));
-  HIPCHK(hipStreamWaitEvent(s2, P->fork_ev, 0));
   // gate: classes whose combination the surrogate predicts within the tolerance
   // take the network's integrals, the others the quadrature's
   std::vector<ClassDesc> qcls, scls;
@@ -1355,11 +1384,33 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   std::vector<ClassDesc>& qref = use_sur ? qcls : classes;
   rep.n_react_surrogate = (int64_t)scls.size();
+  // everything the second stream reads is uploaded here, on the main stream, before the fork
+  OpDesc* d_fops = P->upload("fops", fops, s);
+  RIPrep rip = reaction_prep(P, "ri", qref, s);
+  ROpDesc* d_rops = classes.empty() ? nullptr : P->upload("rops", rops, s);
+  ClassDesc* d_gcls = nullptr;
+  int* d_gcombo = nullptr;
+  double *d_gh = nullptr, *d_gd = nullptr;
+  if (!scls.empty()) {
+    d_gcls = P->upload("gate_cls", scls, s);
+    d_gcombo = P->upload("gate_combo", sC, s);
+    d_gh = P->upload("gate_h", sH, s);
+    d_gd = P->upload("gate_d", sD, s);
+  }
+  double* Iall = classes.empty() ? nullptr : P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
+  // the operator generation forks onto the second stream here: free-space
+  // operators first (the main stream waits for them before the M2M), then the
+  // reaction chain (joined before the M2L)
+  HIPCHK(hipEventRecord(P->fork_ev, s));
+  HIPCHK(hipStreamWaitEvent(s2, P->fork_ev, 0));
+  sbeg(ST_OPS_FREE, s2);
+  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
+  send(ST_OPS_FREE, s2);
+  HIPCHK(hipEventRecord(P->ops_ev, s2));
   sbeg(ST_REACT_TABLES, s2);
   if (!classes.empty()) {
-    double* Iall = P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
     if (!qref.empty()) {
-      reaction_integrals(P, "ri", qref, Iall, s2, [&]() {
+      reaction_launch(P, rip, Iall, s2, [&]() {
         send(ST_REACT_TABLES, s2);
         sbeg(ST_REACT_MFMA, s2);
       });
@@ -1372,20 +1423,15 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     if (!scls.empty()) {
       MlpNet& Nn = P->sur.net;
       const int ns = (int)scls.size();
-      ClassDesc* d_scls = P->upload("gate_cls", scls, s2);
-      int* d_sc = P->upload("gate_combo", sC, s2);
-      double* d_sh = P->upload("gate_h", sH, s2);
-      double* d_sd = P->upload("gate_d", sD, s2);
       unsigned short* d_sx = P->dev<unsigned short>("gate_x", (size_t)ns * Nn.nin);
       const Surrogate& S = P->sur;
-      lk_sur_features(ns, d_sc, d_sh, Nn.nin, S.ncomp * 40, std::log(S.h_lo), std::log(S.h_hi), d_sx, s2);
+      lk_sur_features(ns, d_gcombo, d_gh, Nn.nin, S.ncomp * 40, std::log(S.h_lo), std::log(S.h_hi), d_sx, s2);
       Nn.forward(ns, d_sx, s2);
-      lk_sur_write(ns, d_scls, d_sd, st, Nn.y(ns), p, NC, Nn.dev<float>("mu", Nn.nout), Nn.dev<float>("sd", Nn.nout),
+      lk_sur_write(ns, d_gcls, d_gd, st, Nn.y(ns), p, NC, Nn.dev<float>("mu", Nn.nout), Nn.dev<float>("sd", Nn.nout),
                    Iall, s2);
     }
     send(ST_REACT_SUR, s2);
     sbeg(ST_REACT_EXPAND, s2);
-    ROpDesc* d_rops = P->upload("rops", rops, s2);
     lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s2);
   } else {
     send(ST_REACT_TABLES, s2);
@@ -1397,11 +1443,6 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   send(ST_REACT_EXPAND, s2);
   HIPCHK(hipEventRecord(P->join_ev, s2));
-  // free-space operators on the main stream
-  OpDesc* d_fops = P->upload("fops", fops, s);
-  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s);
-  send(ST_OPS_FREE, s);
-  sbeg(ST_JOBS, s);
   // ---------------- GEMM jobs
   // group tables (host): M2M groups per (tree, parent level), level-major descending;
   // L2L groups per (tree, level, class) level-major ascending; M2L groups per (tree, level, class)
@@ -1593,12 +1634,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     lk_p2m((int)seg_row0.size(), d_r0, d_pf, ptot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, px, py,
            pz, pq, p, NCK, M, s);
   }
-  mark(8);
-  for (int lp = Dmax - 1; lp >= 2; lp--)
-    if (bc_m2m[lp] > 0)
-      lk_gemm(0, P->NRT, 1, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
-              NCK, NC, s);
-  send(ST_M2M, s);
+  send(ST_P2M, s);
   double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
   lk_zero(phi_tp, 2 * (size_t)ntp, s);
   // ---------------- free-space near field (its stage brackets the kernel alone)
@@ -1628,7 +1664,15 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     }
     send(ST_P2P, s);
   }
-  // the reaction operators are needed from here on
+  // the free-space operators are needed from here on
+  HIPCHK(hipStreamWaitEvent(s, P->ops_ev, 0));
+  sbeg(ST_M2M, s);
+  for (int lp = Dmax - 1; lp >= 2; lp--)
+    if (bc_m2m[lp] > 0)
+      lk_gemm(0, P->NRT, 1, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
+              NCK, NC, s);
+  send(ST_M2M, s);
+  // and the reaction operators from here on
   HIPCHK(hipStreamWaitEvent(s, P->join_ev, 0));
   sbeg(ST_M2L, s);
   // ---------------- M2L (every level, free and reaction)
@@ -1955,6 +1999,7 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   }
   if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
   if (plan->join_ev) (void)hipEventDestroy(plan->join_ev);
+  if (plan->ops_ev) (void)hipEventDestroy(plan->ops_ev);
   plan->sur.net.release();
   delete plan;
 }
