@@ -212,14 +212,17 @@ def main():
         stages = {kname: v / args.steps for kname, v in stage_acc.items()}
         bits = 32 if precision else 64
         sfx = "32" if precision else ""
-        cands = [dict(kernel="k_m2l_gemm" + sfx, stage="m2l", bound="mfma", bits=bits,
+        # main: the kernel has the GPU to itself on the main stream; second: it runs on
+        # the operator stream beside the main stream's P2M and near field, so its
+        # event-timed duration includes sharing the GPU and understates its own rate
+        cands = [dict(kernel="k_m2l_gemm" + sfx, stage="m2l", bound="mfma", bits=bits, stream="main",
                       flops=8.0 * nc * nc * rep["m2l_pairs"],
                       what="M2L, batched complex %s GEMM" % ("FP32 MFMA" if precision else "FP64 MFMA")),
-                 dict(kernel="k_react_mfma", stage="react_mfma", bound="mfma", bits=64,
+                 dict(kernel="k_react_mfma", stage="react_mfma", bound="mfma", bits=64, stream="second",
                       flops=8.0 * nt * nc * rep["n_react_nodes"],
-                      what="reaction M2L integrals, node sums on FP64 MFMA")]
+                      what="reaction M2L integrals, node sums on FP64 MFMA (overlapped with the main stream)")]
         if rep.get("p2p_series"):
-            cands.append(dict(kernel="k_p2p_free" + sfx, stage="p2p_free", bound="alu", bits=bits,
+            cands.append(dict(kernel="k_p2p_free" + sfx, stage="p2p_free", bound="alu", bits=bits, stream="main",
                               flops=float(P2P_FLOPS_PER_PAIR[bits]) * rep["p2p_pairs"],
                               what="free-space near field, %s vector ALU" % ("FP32" if precision else "FP64")))
         rooflines = []
@@ -227,7 +230,8 @@ def main():
             t = stages[c["stage"]] / 1000.0
             ach = c["flops"] / t / 1e12 if t > 0 else 0.0
             peak = PEAK[(c["bound"], c["bits"])]
-            rooflines.append({"kernel": c["kernel"], "what": c["what"], "bound": c["bound"], "achieved": ach,
+            rooflines.append({"kernel": c["kernel"], "what": c["what"], "stream": c["stream"], "bound": c["bound"],
+                              "achieved": ach,
                               "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
                               "traffic": profiled_traffic(c["kernel"], n, args.p, args.leaf, args.seed),
                               "algorithmic_flops_per_launch": c["flops"], "launch_ms": stages[c["stage"]]})
@@ -246,7 +250,8 @@ def main():
     ok = err2 <= TOL_MIXED and errmax <= TOL_MIXED
     head = mixed if ok else plain
     log("bench: mixed vs FP64: Err2 %.3e, Errmax %.3e -> headline %s" % (err2, errmax, "mixed" if ok else "FP64"))
-    roofline = max(head["rooflines"], key=lambda r: r["launch_ms"])
+    # the dominant kernel: the longest one that has the GPU to itself
+    roofline = max((r for r in head["rooflines"] if r["stream"] == "main"), key=lambda r: r["launch_ms"])
     out = {"metric": METRIC, "value": head["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "strong",
            "vs_baseline": None, "dtype": "f32+f64" if ok else "f64", "data": "synthetic",
