@@ -10,6 +10,7 @@
 
 #define LFMM_PI 3.14159265358979323846
 #define LFMM_DMAX 8
+#define LFMM_PMAX 10  // largest expansion order a plan accepts
 #define LFMM_MAXL 16
 
 struct cd {

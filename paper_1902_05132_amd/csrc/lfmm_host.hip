@@ -478,7 +478,7 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
               lfmm_plan_t** out) {
   if (!out) return LFMM_EINVAL;
   *out = nullptr;
-  if (L < 0 || L > LFMM_MAXL || p < 1 || p > 10 || leaf_max < 1) return LFMM_EINVAL;
+  if (L < 0 || L > LFMM_MAXL || p < 1 || p > LFMM_PMAX || leaf_max < 1) return LFMM_EINVAL;
   if (L > 0 && !d) return LFMM_EINVAL;
   if (!k) return LFMM_EINVAL;
   for (int i = 0; i <= L; i++)

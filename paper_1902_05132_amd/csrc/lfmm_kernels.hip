@@ -455,6 +455,23 @@ __device__ __forceinline__ void decode_nm(int r, int* n, int* m) {
   *n = nn;
   *m = r - nn * nn - nn;
 }
+// (n, m) of every index idx(n, m) < NC, in LDS (one entry per thread, then a barrier)
+#define NM_TAB 128
+__device__ __forceinline__ void fill_nm(int NC, int2* tab) {
+  for (int r = threadIdx.x; r < NC; r += blockDim.x) {
+    int n, m;
+    decode_nm(r, &n, &m);
+    tab[r] = make_int2(n, m);
+  }
+}
+// Entry e of an operator in the packed MFMA operand order: 16 x 4 tiles, row tile
+// major, and within a tile lane = (row & 15) | ((col & 3) << 4); packed_pos of the
+// result is 2 e, so consecutive threads store consecutive elements.
+__device__ __forceinline__ void packed_rc(int e, int NKS, int* row, int* col) {
+  const int tile = e >> 6, lane = e & 63;
+  *row = (tile / NKS) * 16 + (lane & 15);
+  *col = (tile % NKS) * 4 + (lane >> 4);
+}
 
 // Free-space translation operators (Section 2.1 addition theorems):
 //   Op[(n,m),(nu,mu)] = 4 pi i^{n-nu} sum_q i^q z_q(k|b|) conj(Y_q^{m-mu}(b^)) G(nu,mu; q,m-mu; n)
@@ -465,8 +482,10 @@ __device__ __forceinline__ void decode_nm(int r, int* n, int* m) {
 __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
                                                  const double* gaunt, float* ops32, const int2* opse) {
   __shared__ cd zq[64];
-  __shared__ cd Yq[64 * 64];
+  __shared__ cd Yq[(2 * LFMM_PMAX + 1) * (2 * LFMM_PMAX + 1)];  // idx(q, s), q <= 2p
+  __shared__ int2 nmt[NM_TAB];
   OpDesc D = descs[blockIdx.x];
+  fill_nm(NC, nmt);
   int Q = 2 * p;
   double bb = sqrt(D.bx * D.bx + D.by * D.by + D.bz * D.bz);
   __shared__ double jj[64];
@@ -523,12 +542,11 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   int P1 = p + 1;
   for (int e = threadIdx.x; e < NR * NK; e += 256) {
-    int row = e / NK, col = e % NK;
+    int row, col;
+    packed_rc(e, NKS, &row, &col);
     cd val = mk(0, 0);
     if (row < NC && col < NC) {
-      int n, mm, nu, mu;
-      decode_nm(row, &n, &mm);
-      decode_nm(col, &nu, &mu);
+      const int n = nmt[row].x, mm = nmt[row].y, nu = nmt[col].x, mu = nmt[col].y;
       int s = mm - mu;
       const double* g = gaunt + ((size_t)row * NC + col) * P1;
       int q0 = abs(n - nu);
@@ -547,13 +565,10 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
         val = mk(ldexp(val.x, sh), ldexp(val.y, sh));
       }
     }
-    size_t pp = packed_pos(row, col, NKS);
     if (f32) {
-      out32[pp] = (float)val.x;
-      out32[pp + 1] = (float)val.y;
+      ((float2*)out32)[e] = make_float2((float)val.x, (float)val.y);
     } else {
-      out[pp] = val.x;
-      out[pp + 1] = val.y;
+      ((double2*)out)[e] = make_double2(val.x, val.y);
     }
   }
 }
@@ -826,7 +841,9 @@ extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* me
 __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const double* Iall, double* ops, int opsz,
                                                       int p, int NC, int NKS, float* ops32, const int2* opse) {
   __shared__ cd ph[64];  // i^q e^{i q phi}, q = -2p..2p
+  __shared__ int2 nmt[NM_TAB];
   ROpDesc R = rops[blockIdx.x];
+  fill_nm(NC, nmt);
   const double phi = atan2(R.dy, R.dx);
   const int Q = 2 * p;
   if ((int)threadIdx.x <= 2 * Q) {
@@ -843,12 +860,11 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   double pre = 4.0 * LFMM_PI / R.kt;
   for (int e = threadIdx.x; e < NR * NK; e += 256) {
-    int row = e / NK, col = e % NK;
+    int row, col;
+    packed_rc(e, NKS, &row, &col);
     cd val = mk(0, 0);
     if (row < NC && col < NC) {
-      int n, m, n2, m2;
-      decode_nm(row, &n, &m);
-      decode_nm(col, &n2, &m2);
+      const int n = nmt[row].x, m = nmt[row].y, n2 = nmt[col].x, m2 = nmt[col].y;
       cd iv = mk(I[2 * ((size_t)row * NC + col)], I[2 * ((size_t)row * NC + col) + 1]);
       val = pre * (ipow(n - n2) * (ph[m2 - m + Q] * iv));
       if (out32) {
@@ -856,13 +872,10 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
         val = mk(ldexp(val.x, sh), ldexp(val.y, sh));
       }
     }
-    size_t pp = packed_pos(row, col, NKS);
     if (out32) {
-      out32[pp] = (float)val.x;
-      out32[pp + 1] = (float)val.y;
+      ((float2*)out32)[e] = make_float2((float)val.x, (float)val.y);
     } else {
-      out[pp] = val.x;
-      out[pp + 1] = val.y;
+      ((double2*)out)[e] = make_double2(val.x, val.y);
     }
   }
 }
