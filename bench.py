@@ -157,8 +157,8 @@ def surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=256)

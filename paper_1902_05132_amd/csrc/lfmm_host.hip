@@ -344,6 +344,9 @@ struct lfmm_plan_s {
   // tables, P2M and near field of the main stream
   hipStream_t s2 = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr, ops_ev = nullptr;
+  // third stream for the GEMM job tables, beside the main stream's P2M and near field
+  hipStream_t s3 = nullptr;
+  hipEvent_t jobs_ev = nullptr;
   Surrogate sur;
 
   // device workspace in use: the plan's own, or one lent by a batch worker
@@ -547,6 +550,8 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     HIPCHK(hipEventCreateWithFlags(&P->fork_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&P->join_ev, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&P->ops_ev, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&P->s3, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&P->jobs_ev, hipEventDisableTiming));
   } catch (Fail& f) {
     lfmm_destroy(P);
     return f.code;
@@ -1225,7 +1230,69 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   double* pq = P->dev<double>("pq", 2 * (size_t)ntp);
   lk_gather(ntp, sg, d_trees, ntrees, perm, d_lstart, x, y, z, q, st, px, py, pz, pq, s);
   send(ST_TREE, s);
-  sbeg(ST_JOBS, s);  // host operator and job tables, then the job kernels
+  // the operator stream (and the job stream) may start from here: everything the
+  // operator stream reads is uploaded on it ahead of its kernels (copies of all
+  // streams share one DMA queue, so an upload queued behind its kernels would hold
+  // up the other streams' later ones)
+  unsigned long long* d_cnt = P->dev<unsigned long long>("pair_counts", 4);
+  HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * 4, s));
+  HIPCHK(hipEventRecord(P->fork_ev, s));
+  HIPCHK(hipStreamWaitEvent(s2, P->fork_ev, 0));
+  const bool m2l32 = P->prec && (P->prec_parts & 2), p2p32 = P->prec && (P->prec_parts & 1);
+  // ---------------- P2M and the free-space near field need the trees only: they go
+  // first and keep the GPU busy while the host builds the operator and job tables
+  double* M = P->dev<double>("M", (size_t)NR * NCK * 2);
+  double* Lx = P->dev<double>("L", (size_t)NR * NCK * 2);
+  lk_zero(M, (size_t)NR * NCK * 2, s);
+  lk_zero(Lx, (size_t)NR * NCK * 2, s);
+  // leaf segments of trees with a far field
+  std::vector<int> seg_row0, seg_prefix;
+  int ptot = 0;
+  for (int t = 0; t < ntrees; t++) {
+    const TreeInfo& T = trees[t];
+    if ((T.kind == 0 || T.kind == 2) && T.depth >= 2) {
+      seg_row0.push_back(first_row(t, T.depth));
+      seg_prefix.push_back(ptot);
+      ptot += nbox(t, T.depth);
+    }
+  }
+  sbeg(ST_P2M, s);
+  if (ptot) {
+    int* d_r0 = P->upload("p2m_r0", seg_row0, s);
+    int* d_pf = P->upload("p2m_pf", seg_prefix, s);
+    lk_p2m((int)seg_row0.size(), d_r0, d_pf, ptot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, px, py,
+           pz, pq, p, NCK, M, s);
+  }
+  send(ST_P2M, s);
+  double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
+  lk_zero(phi_tp, 2 * (size_t)ntp, s);
+  // ---------------- free-space near field (its stage brackets the kernel alone)
+  {
+    std::vector<int> r0, pf;
+    int tot = 0;
+    double krmax = 0.0;  // bound on k r over adjacent leaves: the diagonal of two boxes side by side
+    for (int t = 0; t < ntrees; t++) {
+      const TreeInfo& T = trees[t];
+      if (T.kind != 0) continue;
+      r0.push_back(first_row(t, T.depth));
+      pf.push_back(tot);
+      tot += nbox(t, T.depth);
+      double h = T.S / (double)(1 << T.depth);
+      krmax = std::max(krmax, T.k * 2.0 * h * std::sqrt(3.0));
+    }
+    if (tot) {
+      int* d_r0 = P->upload("p2p_r0", r0, s);
+      int* d_pf = P->upload("p2p_pf", pf, s);
+      rep.p2p_series = krmax <= 1.0 ? 1 : 0;
+      sbeg(ST_P2P, s);
+      lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
+                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, rep.p2p_series, P->p2p_ta, P->p2p_ch, p2p32 ? 1 : 0,
+                  d_cnt + 3, s);
+    } else {
+      sbeg(ST_P2P, s);
+    }
+    send(ST_P2P, s);
+  }
   // ---------------- operators
   // expansion scale exponents of the mixed-precision M2L: c = 2^e, e = round(log2(1/(k h))) per (tree, level)
   std::vector<int> hse((size_t)ntrees * 9, 0);
@@ -1348,16 +1415,13 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.n_react_nodes = nodes_total;
   rep.n_ops_react = (int64_t)rops.size();
   double* ops = P->dev<double>("ops", (size_t)nops * opsz);
-  lk_zero(ops, opsz, s);
   float* ops32 = nullptr;
   int* d_opsc = nullptr;
   int* d_sc = P->upload("exp_scale", hse, s);
-  const bool m2l32 = P->prec && (P->prec_parts & 2), p2p32 = P->prec && (P->prec_parts & 1);
   if (m2l32) {
     ops32 = P->dev<float>("ops32", (size_t)nops * opsz);
-    lk_zero((double*)ops32, opsz / 2, s);
     opse.resize(2 * (size_t)nops, 0);
-    d_opsc = P->upload("op_scale", opse, s);
+    d_opsc = P->upload("op_scale", opse, s2);
   }
   // gate: classes whose combination the surrogate predicts within the tolerance
   // take the network's integrals, the others the quadrature's
@@ -1384,25 +1448,23 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   std::vector<ClassDesc>& qref = use_sur ? qcls : classes;
   rep.n_react_surrogate = (int64_t)scls.size();
-  // everything the second stream reads is uploaded here, on the main stream, before the fork
-  OpDesc* d_fops = P->upload("fops", fops, s);
-  RIPrep rip = reaction_prep(P, "ri", qref, s);
-  ROpDesc* d_rops = classes.empty() ? nullptr : P->upload("rops", rops, s);
+  // the operator stream: its uploads, then free-space operators (the main stream
+  // waits for them before the M2M), then the reaction chain (joined before the M2L)
+  OpDesc* d_fops = P->upload("fops", fops, s2);
+  RIPrep rip = reaction_prep(P, "ri", qref, s2);
+  ROpDesc* d_rops = classes.empty() ? nullptr : P->upload("rops", rops, s2);
   ClassDesc* d_gcls = nullptr;
   int* d_gcombo = nullptr;
   double *d_gh = nullptr, *d_gd = nullptr;
   if (!scls.empty()) {
-    d_gcls = P->upload("gate_cls", scls, s);
-    d_gcombo = P->upload("gate_combo", sC, s);
-    d_gh = P->upload("gate_h", sH, s);
-    d_gd = P->upload("gate_d", sD, s);
+    d_gcls = P->upload("gate_cls", scls, s2);
+    d_gcombo = P->upload("gate_combo", sC, s2);
+    d_gh = P->upload("gate_h", sH, s2);
+    d_gd = P->upload("gate_d", sD, s2);
   }
   double* Iall = classes.empty() ? nullptr : P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-  // the operator generation forks onto the second stream here: free-space
-  // operators first (the main stream waits for them before the M2M), then the
-  // reaction chain (joined before the M2L)
-  HIPCHK(hipEventRecord(P->fork_ev, s));
-  HIPCHK(hipStreamWaitEvent(s2, P->fork_ev, 0));
+  lk_zero(ops, opsz, s2);  // operator 0: the zero operator
+  if (m2l32) lk_zero((double*)ops32, opsz / 2, s2);
   sbeg(ST_OPS_FREE, s2);
   lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
   send(ST_OPS_FREE, s2);
@@ -1443,7 +1505,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   send(ST_REACT_EXPAND, s2);
   HIPCHK(hipEventRecord(P->join_ev, s2));
-  // ---------------- GEMM jobs
+  // ---------------- GEMM jobs, on a third stream (they need the trees only, and
+  // their count readbacks then wait for the job kernels alone, not for the near field)
+  hipStream_t sj = P->s3;
+  HIPCHK(hipStreamWaitEvent(sj, P->fork_ev, 0));
+  sbeg(ST_JOBS, sj);
   // group tables (host): M2M groups per (tree, parent level), level-major descending;
   // L2L groups per (tree, level, class) level-major ascending; M2L groups per (tree, level, class)
   std::vector<int> gb_m2m(ntrees * 9, -1), gb_l2l(ntrees * 9, -1), gb_m2l(ntrees * 9, -1);
@@ -1545,17 +1611,17 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     J.sgid = P->dev<int>((t + "_sgid").c_str(), NR + 1);
     J.srowid = P->dev<int>((t + "_srow").c_str(), NR + 1);
     J.cnt = P->dev<int>((t + "_cnt").c_str(), ngroups + 1);
-    int* d_gb = P->upload((t + "_gb").c_str(), gbase, s);
-    lk_group_ids(NR, 0, mode, box_code, box_tree, box_level, d_trees, d_gb, 9, J.gid, J.rowid, s);
+    int* d_gb = P->upload((t + "_gb").c_str(), gbase, sj);
+    lk_group_ids(NR, 0, mode, box_code, box_tree, box_level, d_trees, d_gb, 9, J.gid, J.rowid, sj);
     size_t tbb = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, sj));
     void* tt = P->dev<char>((t + "_tmp").c_str(), tbb);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tt, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, s));
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tt, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, sj));
     // histogram of valid group ids
     size_t tbh = 0;
-    HIPCHK(hipcub::DeviceHistogram::HistogramEven(nullptr, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, s));
+    HIPCHK(hipcub::DeviceHistogram::HistogramEven(nullptr, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, sj));
     void* th = P->dev<char>((t + "_htmp").c_str(), tbh);
-    HIPCHK(hipcub::DeviceHistogram::HistogramEven(th, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, s));
+    HIPCHK(hipcub::DeviceHistogram::HistogramEven(th, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, sj));
   };
   JobDev J_m2m{}, J_l2l{}, J_m2l{};
   int ng_m2m = (int)g_m2m.size(), ng_l2l = (int)g_l2l.size(), ng_m2l = (int)g_m2l.size();
@@ -1563,10 +1629,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   if (ng_l2l) job_prep("l2l", 1, gb_l2l, ng_l2l, J_l2l);
   if (ng_m2l) job_prep("m2l", 2, gb_m2l, ng_m2l, J_m2l);
   std::vector<int> c_m2m(ng_m2m + 1), c_l2l(ng_l2l + 1), c_m2l(ng_m2l + 1);
-  if (ng_m2m) P->rb_add(c_m2m.data(), J_m2m.cnt, sizeof(int) * ng_m2m, s);
-  if (ng_l2l) P->rb_add(c_l2l.data(), J_l2l.cnt, sizeof(int) * ng_l2l, s);
-  if (ng_m2l) P->rb_add(c_m2l.data(), J_m2l.cnt, sizeof(int) * ng_m2l, s);
-  P->rb_flush(s);
+  if (ng_m2m) P->rb_add(c_m2m.data(), J_m2m.cnt, sizeof(int) * ng_m2m, sj);
+  if (ng_l2l) P->rb_add(c_l2l.data(), J_l2l.cnt, sizeof(int) * ng_l2l, sj);
+  if (ng_m2l) P->rb_add(c_m2l.data(), J_m2l.cnt, sizeof(int) * ng_m2l, sj);
+  P->rb_flush(sj);
   c_m2m.resize(ng_m2m);
   c_l2l.resize(ng_l2l);
   c_m2l.resize(ng_m2l);
@@ -1587,83 +1653,31 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* sr_m2m = P->dev<int>("sr_m2m", (size_t)ne_m2m * 8 + 1);
   int* sr_l2l = P->dev<int>("sr_l2l", (size_t)ne_l2l + 1);
   int* sr_m2l = P->dev<int>("sr_m2l", (size_t)ne_m2l * kmax_m2l + 1);
-  if (ne_m2m) lk_src_m2m(ne_m2m, J_m2m.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_m2m, s);
-  if (ne_l2l) lk_src_l2l(ne_l2l, J_l2l.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_l2l, s);
+  if (ne_m2m) lk_src_m2m(ne_m2m, J_m2m.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_m2m, sj);
+  if (ne_l2l) lk_src_l2l(ne_l2l, J_l2l.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_l2l, sj);
   std::vector<int> gseq0(ng_m2l), gK(ng_m2l);
   for (int g = 0; g < ng_m2l; g++) {
     gseq0[g] = g_m2l[g].seq0;
     gK[g] = g_m2l[g].K;
   }
-  int* d_gseq0 = P->upload("m2l_gseq0", gseq0, s);
-  int* d_gK = P->upload("m2l_gK", gK, s);
-  Tmpl* d_tmpl = P->upload("m2l_tmpl", tmpl_m2l, s);
+  int* d_gseq0 = P->upload("m2l_gseq0", gseq0, sj);
+  int* d_gK = P->upload("m2l_gK", gK, sj);
+  Tmpl* d_tmpl = P->upload("m2l_tmpl", tmpl_m2l, sj);
   if (ne_m2l)
     lk_src_m2l(ne_m2l, J_m2l.srowid, J_m2l.sgid, d_gseq0, d_gK, d_tmpl, kmax_m2l, box_code, box_level, d_lvl_off,
-               d_grid_off, 9, grid, nullptr, sr_m2l, s);
-  unsigned long long* d_cnt = P->dev<unsigned long long>("pair_counts", 4);
-  HIPCHK(hipMemsetAsync(d_cnt, 0, sizeof(unsigned long long) * 4, s));
-  if (ne_m2l) lk_count_valid(ne_m2l, J_m2l.sgid, d_gK, 0, sr_m2l, kmax_m2l, d_cnt + 0, s);
-  if (ne_m2m) lk_count_valid(ne_m2m, nullptr, nullptr, 8, sr_m2m, 8, d_cnt + 1, s);
-  if (ne_l2l) lk_count_valid(ne_l2l, nullptr, nullptr, 1, sr_l2l, 1, d_cnt + 2, s);
-  GBlock* d_bm2m = P->upload("b_m2m", b_m2m, s);
-  GBlock* d_bl2l = P->upload("b_l2l", b_l2l, s);
-  GBlock* d_bm2l = P->upload("b_m2l", b_m2l, s);
-  int* d_sq_m2m = P->upload("sq_m2m", seq_m2m, s);
-  int* d_sq_l2l = P->upload("sq_l2l", seq_l2l, s);
-  int* d_sq_m2l = P->upload("sq_m2l", seq_m2l, s);
-  mark(7);
-  // ---------------- upward pass
-  double* M = P->dev<double>("M", (size_t)NR * NCK * 2);
-  double* Lx = P->dev<double>("L", (size_t)NR * NCK * 2);
-  lk_zero(M, (size_t)NR * NCK * 2, s);
-  lk_zero(Lx, (size_t)NR * NCK * 2, s);
-  // leaf segments of trees with a far field
-  std::vector<int> seg_row0, seg_prefix;
-  int ptot = 0;
-  for (int t = 0; t < ntrees; t++) {
-    const TreeInfo& T = trees[t];
-    if ((T.kind == 0 || T.kind == 2) && T.depth >= 2) {
-      seg_row0.push_back(first_row(t, T.depth));
-      seg_prefix.push_back(ptot);
-      ptot += nbox(t, T.depth);
-    }
-  }
-  if (ptot) {
-    int* d_r0 = P->upload("p2m_r0", seg_row0, s);
-    int* d_pf = P->upload("p2m_pf", seg_prefix, s);
-    lk_p2m((int)seg_row0.size(), d_r0, d_pf, ptot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, px, py,
-           pz, pq, p, NCK, M, s);
-  }
-  send(ST_P2M, s);
-  double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
-  lk_zero(phi_tp, 2 * (size_t)ntp, s);
-  // ---------------- free-space near field (its stage brackets the kernel alone)
-  {
-    std::vector<int> r0, pf;
-    int tot = 0;
-    double krmax = 0.0;  // bound on k r over adjacent leaves: the diagonal of two boxes side by side
-    for (int t = 0; t < ntrees; t++) {
-      const TreeInfo& T = trees[t];
-      if (T.kind != 0) continue;
-      r0.push_back(first_row(t, T.depth));
-      pf.push_back(tot);
-      tot += nbox(t, T.depth);
-      double h = T.S / (double)(1 << T.depth);
-      krmax = std::max(krmax, T.k * 2.0 * h * std::sqrt(3.0));
-    }
-    if (tot) {
-      int* d_r0 = P->upload("p2p_r0", r0, s);
-      int* d_pf = P->upload("p2p_pf", pf, s);
-      rep.p2p_series = krmax <= 1.0 ? 1 : 0;
-      sbeg(ST_P2P, s);
-      lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
-                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, rep.p2p_series, P->p2p_ta, P->p2p_ch, p2p32 ? 1 : 0,
-                  d_cnt + 3, s);
-    } else {
-      sbeg(ST_P2P, s);
-    }
-    send(ST_P2P, s);
-  }
+               d_grid_off, 9, grid, nullptr, sr_m2l, sj);
+  if (ne_m2l) lk_count_valid(ne_m2l, J_m2l.sgid, d_gK, 0, sr_m2l, kmax_m2l, d_cnt + 0, sj);
+  if (ne_m2m) lk_count_valid(ne_m2m, nullptr, nullptr, 8, sr_m2m, 8, d_cnt + 1, sj);
+  if (ne_l2l) lk_count_valid(ne_l2l, nullptr, nullptr, 1, sr_l2l, 1, d_cnt + 2, sj);
+  GBlock* d_bm2m = P->upload("b_m2m", b_m2m, sj);
+  GBlock* d_bl2l = P->upload("b_l2l", b_l2l, sj);
+  GBlock* d_bm2l = P->upload("b_m2l", b_m2l, sj);
+  int* d_sq_m2m = P->upload("sq_m2m", seq_m2m, sj);
+  int* d_sq_l2l = P->upload("sq_l2l", seq_l2l, sj);
+  int* d_sq_m2l = P->upload("sq_m2l", seq_m2l, sj);
+  send(ST_JOBS, sj);
+  HIPCHK(hipEventRecord(P->jobs_ev, sj));
+  HIPCHK(hipStreamWaitEvent(s, P->jobs_ev, 0));
   // the free-space operators are needed from here on
   HIPCHK(hipStreamWaitEvent(s, P->ops_ev, 0));
   sbeg(ST_M2M, s);
@@ -1772,6 +1786,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* d_tl = P->upload("tgt_list", tgt_list, s);
   lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, s);
   send(ST_SUM, s);
+  // every stream has joined the main one by now: the staging arena's last use is
+  // complete once the main stream gets here
+  if (P->pin_pending) HIPCHK(hipEventRecord(P->pin_ev, s));
   HIPCHK(hipGetLastError());
   unsigned long long hcnt[4] = {0, 0, 0, 0};
   P->rb_add(hcnt, d_cnt, sizeof(hcnt), s);
@@ -1806,6 +1823,7 @@ int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int3
     // drain what this call queued before its staging buffers are reused
     (void)hipStreamSynchronize((hipStream_t)stream);
     (void)hipStreamSynchronize(plan->s2);
+    if (plan->s3) (void)hipStreamSynchronize(plan->s3);
     plan->rb_list.clear();
     plan->rb_used = 0;
     return f.code;
@@ -1834,6 +1852,7 @@ int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* la
   } catch (Fail& f) {
     (void)hipStreamSynchronize(nullptr);
     (void)hipStreamSynchronize(plan->s2);
+    if (plan->s3) (void)hipStreamSynchronize(plan->s3);
     plan->rb_list.clear();
     plan->rb_used = 0;
     return f.code;
@@ -1882,6 +1901,7 @@ int lfmm_eval_targets_device(lfmm_plan_t* plan, int64_t n_src, const double* src
     (void)hipStreamSynchronize((hipStream_t)stream);
     if (plan) {
       (void)hipStreamSynchronize(plan->s2);
+      if (plan->s3) (void)hipStreamSynchronize(plan->s3);
       plan->rb_list.clear();
       plan->rb_used = 0;
     }
@@ -1920,6 +1940,7 @@ int lfmm_eval_targets(lfmm_plan_t* plan, int64_t n_src, const double* src_xyz, c
   } catch (Fail& f) {
     (void)hipStreamSynchronize(nullptr);
     (void)hipStreamSynchronize(plan->s2);
+    if (plan->s3) (void)hipStreamSynchronize(plan->s3);
     plan->rb_list.clear();
     plan->rb_used = 0;
     return f.code;
@@ -2000,6 +2021,11 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   if (plan->fork_ev) (void)hipEventDestroy(plan->fork_ev);
   if (plan->join_ev) (void)hipEventDestroy(plan->join_ev);
   if (plan->ops_ev) (void)hipEventDestroy(plan->ops_ev);
+  if (plan->s3) {
+    (void)hipStreamSynchronize(plan->s3);
+    (void)hipStreamDestroy(plan->s3);
+  }
+  if (plan->jobs_ev) (void)hipEventDestroy(plan->jobs_ev);
   plan->sur.net.release();
   delete plan;
 }
@@ -2118,6 +2144,7 @@ int lfmm_surrogate_train(lfmm_plan_t* plan, int64_t n_samples, uint64_t seed, co
     sur_train_impl(plan, n_samples, seed, o, R);
   } catch (Fail& f) {
     (void)hipStreamSynchronize(plan->s2);
+    if (plan->s3) (void)hipStreamSynchronize(plan->s3);
     plan->sur.ready = false;
     return f.code;
   }
