@@ -1179,16 +1179,14 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* scan_all = P->dev<int>("scan_all", (size_t)nlev * ntp);
   int* tb = P->dev<int>("tb", ntrees * 18);
   HIPCHK(hipMemsetAsync(tb, 0, sizeof(int) * ntrees * 18, s));
+  // box flags of every level, one scan over all levels (global box rows), box ranges
+  if ((size_t)nlev * ntp >= ((size_t)1 << 31)) throw Fail{LFMM_ENOTSUP};
   size_t tb3 = 0;
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb3, flags_all, scan_all, ntp, s));
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb3, flags_all, scan_all, nlev * ntp, s));
   tmp = P->dev<char>("cubtmp3", tb3);
-  for (int l = 0; l < nlev; l++) {
-    int* fl = flags_all + (size_t)l * ntp;
-    int* sc = scan_all + (size_t)l * ntp;
-    lk_box_flags(ntp, l, skeys, d_trees, fl, s);
-    HIPCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb3, fl, sc, ntp, s));
-    lk_tree_box_range(ntrees, l, ntp, d_trees, fl, sc, tb, s);
-  }
+  lk_box_flags_all(ntp, nlev, skeys, d_trees, flags_all, s);
+  HIPCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb3, flags_all, scan_all, nlev * ntp, s));
+  lk_tree_box_range_all(ntrees, nlev, ntp, d_trees, flags_all, scan_all, tb, s);
   std::vector<int> htb(ntrees * 18);
   P->rb_add(htb.data(), tb, sizeof(int) * ntrees * 18, s);
   P->rb_flush(s);
@@ -1205,9 +1203,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* box_tree = P->dev<int>("box_tree", NR + 1);
   int* box_level = P->dev<int>("box_level", NR + 1);
   int* box_cnt = P->dev<int>("box_cnt", NR + 1);
-  for (int l = 0; l < nlev; l++)
-    lk_box_fill(ntp, l, skeys, flags_all + (size_t)l * ntp, scan_all + (size_t)l * ntp, lvl_off[l], d_trees,
-                box_start, box_code, box_tree, box_level, box_cnt, s);
+  lk_box_fill_all(ntp, nlev, skeys, flags_all, scan_all, d_trees, box_start, box_code, box_tree, box_level, box_cnt,
+                  s);
   int* d_lvl_off = P->upload("lvl_off", lvl_off, s);
   int* leafrow = P->dev<int>("leafrow", ntp);
   lk_point_leaf(ntp, skeys, d_trees, flags_all, scan_all, d_lvl_off, leafrow, s);
@@ -1222,7 +1219,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* grid = P->dev<int>("grid", (size_t)gtot);
   lk_fill_int(grid, (size_t)gtot, -1, s);
   long long* d_grid_off = P->upload("grid_off", grid_off, s);
-  for (int l = 0; l < nlev; l++) lk_grid_fill(lvl_count[l], lvl_off[l], l, box_code, box_tree, d_grid_off, 9, grid, s);
+  lk_grid_fill_all(NR, box_code, box_tree, box_level, d_grid_off, grid, s);
   // particle data in sorted order, frame coordinates
   double* px = P->dev<double>("px", ntp);
   double* py = P->dev<double>("py", ntp);

@@ -128,16 +128,8 @@ void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm,
                     hipStream_t s);
 void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab,
                   hipStream_t s);
-void lk_box_flags(int ntp, int level, const unsigned* skeys, const TreeInfo* trees, int* flags, hipStream_t s);
-void lk_box_fill(int ntp, int level, const unsigned* skeys, const int* flags, const int* scan, int lvl_off,
-                 const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level, int* box_cnt,
-                 hipStream_t s);
 void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all, const int* scan_all,
                    const int* lvl_off, int* leafrow, hipStream_t s);
-void lk_tree_box_range(int ntrees, int level, int ntp, const TreeInfo* trees, const int* flags, const int* scan,
-                       int* tb, hipStream_t s);
-void lk_grid_fill(int nrows_level, int row0, int level, const int* box_code, const int* box_tree,
-                  const long long* grid_off, int nlev1, int* grid, hipStream_t s);
 void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm, const int* layer_start,
                const double* x, const double* y, const double* z, const double* q, Stack st, double* px,
                double* py, double* pz, double* pq, hipStream_t s);
@@ -210,4 +202,12 @@ void lk_gather_rows(int nrows, const int* idx, int ncol, int esz, const void* sr
 void lk_sur_norm(long n, int nout, float* T, const float* mu, const float* sd, hipStream_t s);
 void lk_sur_features(int n, const int* combo, const double* h, int nin, int c0, double lh0, double lh1,
                      unsigned short* X, hipStream_t s);
+void lk_box_flags_all(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* flags_all, hipStream_t s);
+void lk_tree_box_range_all(int ntrees, int nlev, int ntp, const TreeInfo* trees, const int* flags_all,
+                           const int* scan_all, int* tb, hipStream_t s);
+void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_all, const int* scan_all,
+                     const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level, int* box_cnt,
+                     hipStream_t s);
+void lk_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
+                      const long long* grid_off, int* grid, hipStream_t s);
 }

@@ -327,43 +327,6 @@ extern "C" void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const T
 }
 
 // run-start flags of the level-l boxes (only for trees of depth >= l)
-__global__ void k_box_flags(int ntp, int level, const unsigned* skeys, const TreeInfo* trees, int* flags) {
-  int s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= ntp) return;
-  unsigned key = skeys[s];
-  int t = key >> 24;
-  int sh = 3 * (8 - level);
-  int f = 0;
-  if (level <= trees[t].depth) f = (s == 0 || (skeys[s - 1] >> sh) != (key >> sh)) ? 1 : 0;
-  flags[s] = f;
-}
-extern "C" void lk_box_flags(int ntp, int level, const unsigned* skeys, const TreeInfo* trees, int* flags, hipStream_t s) {
-  if (ntp) k_box_flags<<<nblk(ntp, 256), 256, 0, s>>>(ntp, level, skeys, trees, flags);
-}
-
-__global__ void k_box_fill(int ntp, int level, const unsigned* skeys, const int* flags, const int* scan, int lvl_off,
-                           const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
-                           int* box_cnt) {
-  int s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= ntp || !flags[s]) return;
-  unsigned key = skeys[s];
-  int t = key >> 24;
-  int sh = 3 * (8 - level);
-  int R = lvl_off + scan[s];
-  box_start[R] = s;
-  box_code[R] = (int)((key & 0xFFFFFFu) >> sh);
-  box_tree[R] = t;
-  box_level[R] = level;
-  box_cnt[R] = run_end(skeys, s, trees[t].pt_off + trees[t].npts, sh) - s;
-}
-extern "C" void lk_box_fill(int ntp, int level, const unsigned* skeys, const int* flags, const int* scan, int lvl_off,
-                             const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
-                             int* box_cnt, hipStream_t s) {
-  if (ntp)
-    k_box_fill<<<nblk(ntp, 256), 256, 0, s>>>(ntp, level, skeys, flags, scan, lvl_off, trees, box_start, box_code,
-                                              box_tree, box_level, box_cnt);
-}
-
 // leaf row of every sorted point (flags/scans of all levels stored level-major)
 __global__ void k_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all,
                              const int* scan_all, const int* lvl_off, int* leafrow) {
@@ -372,47 +335,89 @@ __global__ void k_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* tre
   int t = skeys[s] >> 24;
   int D = trees[t].depth;
   size_t o = (size_t)D * ntp + s;
-  leafrow[s] = lvl_off[D] + scan_all[o] + flags_all[o] - 1;
+  (void)lvl_off;  // the level-major scan already holds global rows
+  leafrow[s] = scan_all[o] + flags_all[o] - 1;
 }
 extern "C" void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all,
                                const int* scan_all, const int* lvl_off, int* leafrow, hipStream_t s) {
   if (ntp) k_point_leaf<<<nblk(ntp, 256), 256, 0, s>>>(ntp, skeys, trees, flags_all, scan_all, lvl_off, leafrow);
 }
 
+
+// All levels at once.  flags_all[l][s] = 1 where sorted point s opens a box of
+// level l (of its tree, if the tree reaches level l); one exclusive scan over the
+// level-major array then numbers the boxes of all levels: scan_all[l][s] is the
+// global row of that box (the rows of level l start at scan_all[l][0]).
+__global__ void k_box_flags_all(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* flags_all) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp) return;
+  const unsigned key = skeys[s];
+  const unsigned prev = s > 0 ? skeys[s - 1] : 0u;
+  const int D = trees[key >> 24].depth;
+  for (int l = 0; l < nlev; l++) {
+    const int sh = 3 * (8 - l);
+    flags_all[(size_t)l * ntp + s] = (l <= D && (s == 0 || (prev >> sh) != (key >> sh))) ? 1 : 0;
+  }
+}
+extern "C" void lk_box_flags_all(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* flags_all,
+                                 hipStream_t s) {
+  if (ntp) k_box_flags_all<<<nblk(ntp, 256), 256, 0, s>>>(ntp, nlev, skeys, trees, flags_all);
+}
 // per (tree, level): first box (level-local) and number of boxes
-__global__ void k_tree_box_range(int ntrees, int level, int ntp, const TreeInfo* trees, const int* flags,
-                                 const int* scan, int* tb) {
-  int t = threadIdx.x;
-  if (t >= ntrees) return;
-  TreeInfo T = trees[t];
+__global__ void k_tree_box_range_all(int ntrees, int nlev, int ntp, const TreeInfo* trees, const int* flags_all,
+                                     const int* scan_all, int* tb) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= ntrees * nlev) return;
+  const int t = i / nlev, level = i % nlev;
+  const TreeInfo T = trees[t];
+  const size_t o = (size_t)level * ntp;
   int first = 0, cnt = 0;
   if (T.npts > 0 && level <= T.depth) {
-    first = scan[T.pt_off];
-    int last = T.pt_off + T.npts - 1;
-    cnt = scan[last] + flags[last] - first;
+    first = scan_all[o + T.pt_off] - scan_all[o];
+    const int last = T.pt_off + T.npts - 1;
+    cnt = scan_all[o + last] + flags_all[o + last] - scan_all[o + T.pt_off];
   }
   tb[(t * 9 + level) * 2] = first;
   tb[(t * 9 + level) * 2 + 1] = cnt;
 }
-extern "C" void lk_tree_box_range(int ntrees, int level, int ntp, const TreeInfo* trees, const int* flags,
-                                  const int* scan, int* tb, hipStream_t s) {
-  k_tree_box_range<<<1, 256, 0, s>>>(ntrees, level, ntp, trees, flags, scan, tb);
+extern "C" void lk_tree_box_range_all(int ntrees, int nlev, int ntp, const TreeInfo* trees, const int* flags_all,
+                                      const int* scan_all, int* tb, hipStream_t s) {
+  if (ntrees * nlev) k_tree_box_range_all<<<nblk(ntrees * nlev, 256), 256, 0, s>>>(ntrees, nlev, ntp, trees, flags_all, scan_all, tb);
 }
-
-__global__ void k_grid_fill(int nrows, int row0, int level, const int* box_code, const int* box_tree,
-                            const long long* grid_off, int* grid) {
-  int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= nrows) return;
-  int R = row0 + r;
-  int t = box_tree[R];
-  long long go = grid_off[t * 9 + level];
+__global__ void k_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_all, const int* scan_all,
+                               const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
+                               int* box_cnt) {
+  const int s = blockIdx.x * 256 + threadIdx.x, level = blockIdx.y;
+  if (s >= ntp || level >= nlev) return;
+  const size_t o = (size_t)level * ntp + s;
+  if (!flags_all[o]) return;
+  const unsigned key = skeys[s];
+  const int t = key >> 24, sh = 3 * (8 - level);
+  const int R = scan_all[o];
+  box_start[R] = s;
+  box_code[R] = (int)((key & 0xFFFFFFu) >> sh);
+  box_tree[R] = t;
+  box_level[R] = level;
+  box_cnt[R] = run_end(skeys, s, trees[t].pt_off + trees[t].npts, sh) - s;
+}
+extern "C" void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_all, const int* scan_all,
+                                const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
+                                int* box_cnt, hipStream_t s) {
+  if (ntp && nlev)
+    k_box_fill_all<<<dim3(nblk(ntp, 256), nlev), 256, 0, s>>>(ntp, nlev, skeys, flags_all, scan_all, trees, box_start,
+                                                               box_code, box_tree, box_level, box_cnt);
+}
+__global__ void k_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
+                                const long long* grid_off, int* grid) {
+  const int R = blockIdx.x * 256 + threadIdx.x;
+  if (R >= nrows) return;
+  const long long go = grid_off[box_tree[R] * 9 + box_level[R]];
   if (go < 0) return;
   grid[go + box_code[R]] = R;
 }
-extern "C" void lk_grid_fill(int nrows_level, int row0, int level, const int* box_code, const int* box_tree,
-                             const long long* grid_off, int nlev1, int* grid, hipStream_t s) {
-  (void)nlev1;
-  if (nrows_level) k_grid_fill<<<nblk(nrows_level, 256), 256, 0, s>>>(nrows_level, row0, level, box_code, box_tree, grid_off, grid);
+extern "C" void lk_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
+                                 const long long* grid_off, int* grid, hipStream_t s) {
+  if (nrows) k_grid_fill_all<<<nblk(nrows, 256), 256, 0, s>>>(nrows, box_code, box_tree, box_level, grid_off, grid);
 }
 
 __global__ void k_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm,
