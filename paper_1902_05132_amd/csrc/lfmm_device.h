@@ -387,8 +387,12 @@ struct Stack {
 
 // LL > 0: the stack has exactly LL interfaces (arrays stay in registers);
 // LL = 0: any L <= LFMM_MAXL.
+// With one != nullptr, *one also receives sig[asel][bsel], chosen among register
+// values (a caller that indexes sig with runtime values would keep the array in
+// memory, which the compiler places in LDS).
 template <int LL>
-__device__ __forceinline__ void dev_densities_t(const Stack& st, cd kr, int l, int lp, cd sig[2][2]) {
+__device__ __forceinline__ void dev_densities_t(const Stack& st, cd kr, int l, int lp, cd sig[2][2], int asel = 0,
+                                                int bsel = 0, cd* one = nullptr) {
   constexpr int NL = (LL > 0) ? LL : LFMM_MAXL;
   const int L = (LL > 0) ? LL : st.L;
   cd kz[NL + 1], a[NL + 1], E[NL + 1], Rd[NL + 1], Ru[NL + 1];
@@ -475,6 +479,7 @@ __device__ __forceinline__ void dev_densities_t(const Stack& st, cd kr, int l, i
     }
     sig[0][b] = (l <= L - 1) ? Ul : mk(0, 0);
     sig[1][b] = (l >= 1) ? Dl : mk(0, 0);
+    if (one && b == bsel) *one = asel == 0 ? ((l <= L - 1) ? Ul : mk(0, 0)) : ((l >= 1) ? Dl : mk(0, 0));
   }
 }
 

@@ -630,10 +630,14 @@ __global__ __launch_bounds__(256) void k_react_F(const ClassDesc* cls, Stack st,
   double kt = st.k[C.lt], ks = st.k[C.ls];
   cd kr2 = kr * kr;
   cd kzt = csqrtd(mk(kt * kt, 0) - kr2), kzs = csqrtd(mk(ks * ks, 0) - kr2);
-  cd sig[2][2];
-  dev_densities_t<LL>(st, kr, C.lt, C.ls, sig);
+  // the one density this class needs, as a register value: reading sig with the
+  // class's runtime (a, b) would keep the array in memory, which the compiler
+  // places in LDS (16 KB per workgroup), so that the kernel could not share CUs
+  // with the near field
+  cd sig[2][2], sab = mk(0, 0);
+  dev_densities_t<LL>(st, kr, C.lt, C.ls, sig, C.a, C.b, &sab);
   cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
-  Ftab[C.f_off + node] = w * kr * ex * sig[C.a][C.b] / kzt;
+  Ftab[C.f_off + node] = w * kr * ex * sab / kzt;
 }
 // The node sum on the FP64 matrix cores.  For a fixed order m the block
 //   I_g[(n, m), (n', m')] = sum_c (F_{g,c} Phat_n^m(t_c)) (s J_{|q|}(k_c rho) Phat_{n'}^{|m'|}(s_c))
