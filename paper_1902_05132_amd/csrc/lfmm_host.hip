@@ -1617,6 +1617,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, sj));
     void* tt = P->dev<char>((t + "_tmp").c_str(), tbb);
     HIPCHK(hipcub::DeviceRadixSort::SortPairs(tt, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, sj));
+    if (mode == 2) lk_m2l_key_to_group(NR, J.sgid, sj);
     // histogram of valid group ids
     size_t tbh = 0;
     HIPCHK(hipcub::DeviceHistogram::HistogramEven(nullptr, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, sj));
@@ -1627,6 +1628,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int ng_m2m = (int)g_m2m.size(), ng_l2l = (int)g_l2l.size(), ng_m2l = (int)g_m2l.size();
   if (ng_m2m) job_prep("m2m", 0, gb_m2m, ng_m2m, J_m2m);
   if (ng_l2l) job_prep("l2l", 1, gb_l2l, ng_l2l, J_l2l);
+  if ((int64_t)ng_m2l * M2L_BCLS >= 0x7fffffff) throw Fail{LFMM_ENOTSUP};
   if (ng_m2l) job_prep("m2l", 2, gb_m2l, ng_m2l, J_m2l);
   std::vector<int> c_m2m(ng_m2m + 1), c_l2l(ng_l2l + 1), c_m2l(ng_m2l + 1);
   if (ng_m2m) P->rb_add(c_m2m.data(), J_m2m.cnt, sizeof(int) * ng_m2m, sj);

@@ -3,6 +3,7 @@
 #include "lfmm_device.h"
 
 #define LFMM_NSTAT 12  // per-layer statistics gathered by the classification kernel
+#define M2L_BCLS 4096  // boundary classes of M2L targets (16 per axis) in the job sort key
 
 // One octree of the evaluation: a free-space tree of one layer, a reaction
 // target tree (layer l, direction a) or a reaction polarisation-source tree
@@ -210,4 +211,5 @@ void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_
                      hipStream_t s);
 void lk_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
                       const long long* grid_off, int* grid, hipStream_t s);
+void lk_m2l_key_to_group(int n, int* key, hipStream_t s);
 }

@@ -1506,18 +1506,32 @@ __global__ void k_group_ids(int nrows, int row0, int mode, const int* box_code, 
     if (mode == 0) g = gb;
     else if (mode == 1) g = gb + (int)(code & 7u);
     else {
+      // M2L: the group, then (sort key only) the box's boundary class, so that
+      // targets with the same missing interaction offsets share GEMM tiles and a
+      // tile skips every operator none of its targets has
       TreeInfo T = trees[t];
-      if (T.kind == 0) g = gb + (int)(code & 7u);
-      else {
-        int ix, iy, iz;
-        demorton3(code, l, &ix, &iy, &iz);
+      int ix, iy, iz;
+      demorton3(code, l, &ix, &iy, &iz);
+      const int n = 1 << l;
+      auto axis = [n](int x) { return min(x, 3) * 4 + min(n - 1 - x, 3); };
+      if (T.kind == 0) {
+        g = (gb + (int)(code & 7u)) * M2L_BCLS + (axis(ix) * 16 + axis(iy)) * 16 + axis(iz);
+      } else {
         int j = iz - (1 << (l - 1));
-        if (j == 0 || j == 1) g = gb + j * 4 + (((ix & 1) << 1) | (iy & 1));
+        if (j == 0 || j == 1) g = (gb + j * 4 + (((ix & 1) << 1) | (iy & 1))) * M2L_BCLS + (axis(ix) * 16 + axis(iy)) * 16;
       }
     }
   }
   gid[r] = g;
   rowid[r] = R;
+}
+// sorted M2L sort keys back to group ids
+__global__ void k_m2l_key_to_group(int n, int* key) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n && key[i] != 0x7fffffff) key[i] /= M2L_BCLS;
+}
+extern "C" void lk_m2l_key_to_group(int n, int* key, hipStream_t s) {
+  if (n) k_m2l_key_to_group<<<nblk(n, 256), 256, 0, s>>>(n, key);
 }
 extern "C" void lk_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree,
                              const int* box_level, const TreeInfo* trees, const int* gbase, int nlev1, int* gid,
