@@ -263,6 +263,25 @@ def main():
            "stages_ms": head["stages"], "roofline": roofline, "rooflines": head["rooflines"],
            "plain_fp64": {"value": plain["value"], "ms_per_step": plain["ms"], "dtype": "f64",
                           "stages_ms": plain["stages"], "rooflines": plain["rooflines"]}}
+    # warm: the same input again with operator reuse (every step after the first keeps
+    # the operators); context beside the cold headline, never the headline
+    wplan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=1, reuse_operators=True)
+    wphi = torch.empty(n, dtype=torch.complex128, device=dev)
+    for i in range(args.warmup):
+        wplan.eval_device(xyz, q, wphi, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        wplan.eval_device(xyz, q, wphi, stream=stream)
+    torch.cuda.synchronize()
+    wms = (time.perf_counter() - t0) * 1000.0 / args.steps
+    reused = wplan.report()["ops_reused"]
+    wplan.close()
+    same = bool(torch.equal(wphi, mixed["phi"]))
+    log("bench: warm operators (reused: %d): %.3f ms/step, identical to the cold mixed result: %s" % (reused, wms, same))
+    out["warm_operators"] = {"ms_per_step": wms, "value": n / (wms / 1000.0), "ops_reused": reused,
+                             "identical_to_cold": same,
+                             "what": "mixed path, operators of the previous evaluation kept (same trees)"}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch)
     if args.scaling:

@@ -53,6 +53,13 @@ typedef struct {
                        on FP32 matrix cores (operators and multipole expansions rescaled per
                        level), with the Bessel/Legendre recurrences, the Sommerfeld quadrature,
                        the local-expansion accumulation and the final sums in FP64: 0 */
+  int physical;     /* 0: potentials in the paper's normalisation Phi (eq. (totalinteraction): the
+                       free part is sum Q_j h0(k_l r), h0(x) = e^{ix}/(ix)); 1: physical potentials,
+                       Phi times i k_l / (4 pi) (free part sum Q_j e^{i k_l r} / (4 pi r)): 0 */
+  int reuse_operators; /* 1: an evaluation whose trees, classes, precision and surrogate gate are the
+                          same as the previous successful one's keeps that evaluation's free-space and
+                          reaction operators instead of generating them again ("warm"); not in
+                          lfmm_eval_batch, whose workers lend their workspaces: 0 */
 } lfmm_options;
 
 typedef struct lfmm_plan_s lfmm_plan_t;
@@ -78,6 +85,7 @@ typedef struct {
   double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
   int64_t n_react_surrogate; /* reaction classes whose integrals came from the surrogate (gate hits);
                                 the other n_react_classes - n_react_surrogate used the quadrature */
+  int ops_reused;            /* 1: the operators of the previous evaluation were kept (reuse_operators) */
 } lfmm_report;
 
 /*

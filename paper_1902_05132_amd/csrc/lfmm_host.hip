@@ -327,6 +327,9 @@ struct lfmm_plan_s {
   double b, min_gap;
   int max_depth, profile;
   int prec;      // 0: FP64; 1: mixed (FP32 near field and FP32-MFMA M2L)
+  int physical = 0;  // 1: return physical potentials instead of the paper's normalisation
+  int reuse_ops = 0;  // 1: keep the operators of the last evaluation when its trees are the same
+  std::string last_opsig;  // what those operators were generated from
   int prec_parts;  // which stages the mixed path runs in FP32: 1 near field, 2 M2L (both by default)
   int gemm_ks;   // M2L GEMM: waves sharing a 16-target tile (0 = chosen from the tile count)
   int p2p_ta;    // near field: targets per wave step (64 / p2p_ta sources)
@@ -533,6 +536,16 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
       return LFMM_EINVAL;
     }
     P->prec = opt->precision;
+    if (opt->physical < 0 || opt->physical > 1) {
+      delete P;
+      return LFMM_EINVAL;
+    }
+    P->physical = opt->physical;
+    if (opt->reuse_operators < 0 || opt->reuse_operators > 1) {
+      delete P;
+      return LFMM_EINVAL;
+    }
+    P->reuse_ops = opt->reuse_operators;
   }
   memset(&P->rep, 0, sizeof(P->rep));
   try {
@@ -997,6 +1010,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.precision = P->prec;
   if (n == 0) return LFMM_OK;
   P->pin_reset();
+  std::string prev_opsig;  // signature of the operators in the buffer (cleared until this evaluation succeeds)
+  prev_opsig.swap(P->last_opsig);
   const Stack& st = P->st;
   const int L = st.L, NL = L + 1, p = P->p, NC = P->NC, NCK = P->NCK, NKS = P->NKS, opsz = P->opsz;
   const double* x = xyz;
@@ -1416,60 +1431,86 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   std::vector<ClassDesc>& qref = use_sur ? qcls : classes;
   rep.n_react_surrogate = (int64_t)scls.size();
-  // the operator stream: its uploads, then free-space operators (the main stream
-  // waits for them before the M2M), then the reaction chain (joined before the M2L)
-  OpDesc* d_fops = P->upload("fops", fops, s2);
-  RIPrep rip = reaction_prep(P, "ri", qref, s2);
-  ROpDesc* d_rops = classes.empty() ? nullptr : P->upload("rops", rops, s2);
-  ClassDesc* d_gcls = nullptr;
-  int* d_gcombo = nullptr;
-  double *d_gh = nullptr, *d_gd = nullptr;
-  if (!scls.empty()) {
-    d_gcls = P->upload("gate_cls", scls, s2);
-    d_gcombo = P->upload("gate_combo", sC, s2);
-    d_gh = P->upload("gate_h", sH, s2);
-    d_gd = P->upload("gate_d", sD, s2);
+  // operators of the previous evaluation are kept when the plan asks for it and
+  // everything they are generated from is the same (trees, classes, precision,
+  // surrogate gate, buffers); a failed evaluation leaves no signature behind
+  std::string opsig;
+  {
+    auto app = [&](const void* q, size_t nb) { opsig.append((const char*)q, nb); };
+    app(fops.data(), fops.size() * sizeof(OpDesc));
+    app(classes.data(), classes.size() * sizeof(ClassDesc));
+    app(rops.data(), rops.size() * sizeof(ROpDesc));
+    app(opse.data(), opse.size() * sizeof(int));
+    const int fl[4] = {P->prec, P->prec_parts, (int)scls.size(), P->physical};
+    app(fl, sizeof(fl));
+    app(&P->sur.tol, sizeof(double));
+    app(&ops, sizeof(ops));
+    app(&ops32, sizeof(ops32));
   }
-  double* Iall = classes.empty() ? nullptr : P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-  lk_zero(ops, opsz, s2);  // operator 0: the zero operator
-  if (m2l32) lk_zero((double*)ops32, opsz / 2, s2);
-  sbeg(ST_OPS_FREE, s2);
-  lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
-  send(ST_OPS_FREE, s2);
-  HIPCHK(hipEventRecord(P->ops_ev, s2));
-  sbeg(ST_REACT_TABLES, s2);
-  if (!classes.empty()) {
-    if (!qref.empty()) {
-      reaction_launch(P, rip, Iall, s2, [&]() {
+  const bool reuse = P->reuse_ops && P->bufp == &P->bufs && !prev_opsig.empty() && opsig == prev_opsig;
+  rep.ops_reused = reuse ? 1 : 0;
+  if (reuse) {
+    for (int st_i : {ST_OPS_FREE, ST_REACT_TABLES, ST_REACT_MFMA, ST_REACT_SUR, ST_REACT_EXPAND}) {
+      sbeg(st_i, s2);
+      send(st_i, s2);
+    }
+    HIPCHK(hipEventRecord(P->ops_ev, s2));
+  } else {
+    // the operator stream: its uploads, then free-space operators (the main stream
+    // waits for them before the M2M), then the reaction chain (joined before the M2L)
+    OpDesc* d_fops = P->upload("fops", fops, s2);
+    RIPrep rip = reaction_prep(P, "ri", qref, s2);
+    ROpDesc* d_rops = classes.empty() ? nullptr : P->upload("rops", rops, s2);
+    ClassDesc* d_gcls = nullptr;
+    int* d_gcombo = nullptr;
+    double *d_gh = nullptr, *d_gd = nullptr;
+    if (!scls.empty()) {
+      d_gcls = P->upload("gate_cls", scls, s2);
+      d_gcombo = P->upload("gate_combo", sC, s2);
+      d_gh = P->upload("gate_h", sH, s2);
+      d_gd = P->upload("gate_d", sD, s2);
+    }
+    double* Iall = classes.empty() ? nullptr : P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
+    lk_zero(ops, opsz, s2);  // operator 0: the zero operator
+    if (m2l32) lk_zero((double*)ops32, opsz / 2, s2);
+    sbeg(ST_OPS_FREE, s2);
+    lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
+    send(ST_OPS_FREE, s2);
+    HIPCHK(hipEventRecord(P->ops_ev, s2));
+    sbeg(ST_REACT_TABLES, s2);
+    if (!classes.empty()) {
+      if (!qref.empty()) {
+        reaction_launch(P, rip, Iall, s2, [&]() {
+          send(ST_REACT_TABLES, s2);
+          sbeg(ST_REACT_MFMA, s2);
+        });
+      } else {
         send(ST_REACT_TABLES, s2);
         sbeg(ST_REACT_MFMA, s2);
-      });
+      }
+      send(ST_REACT_MFMA, s2);
+      sbeg(ST_REACT_SUR, s2);
+      if (!scls.empty()) {
+        MlpNet& Nn = P->sur.net;
+        const int ns = (int)scls.size();
+        unsigned short* d_sx = P->dev<unsigned short>("gate_x", (size_t)ns * Nn.nin);
+        const Surrogate& S = P->sur;
+        lk_sur_features(ns, d_gcombo, d_gh, Nn.nin, S.ncomp * 40, std::log(S.h_lo), std::log(S.h_hi), d_sx, s2);
+        Nn.forward(ns, d_sx, s2);
+        lk_sur_write(ns, d_gcls, d_gd, st, Nn.y(ns), p, NC, Nn.dev<float>("mu", Nn.nout), Nn.dev<float>("sd", Nn.nout),
+                     Iall, s2);
+      }
+      send(ST_REACT_SUR, s2);
+      sbeg(ST_REACT_EXPAND, s2);
+      lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s2);
     } else {
       send(ST_REACT_TABLES, s2);
       sbeg(ST_REACT_MFMA, s2);
+      send(ST_REACT_MFMA, s2);
+      sbeg(ST_REACT_SUR, s2);
+      send(ST_REACT_SUR, s2);
+      sbeg(ST_REACT_EXPAND, s2);
     }
-    send(ST_REACT_MFMA, s2);
-    sbeg(ST_REACT_SUR, s2);
-    if (!scls.empty()) {
-      MlpNet& Nn = P->sur.net;
-      const int ns = (int)scls.size();
-      unsigned short* d_sx = P->dev<unsigned short>("gate_x", (size_t)ns * Nn.nin);
-      const Surrogate& S = P->sur;
-      lk_sur_features(ns, d_gcombo, d_gh, Nn.nin, S.ncomp * 40, std::log(S.h_lo), std::log(S.h_hi), d_sx, s2);
-      Nn.forward(ns, d_sx, s2);
-      lk_sur_write(ns, d_gcls, d_gd, st, Nn.y(ns), p, NC, Nn.dev<float>("mu", Nn.nout), Nn.dev<float>("sd", Nn.nout),
-                   Iall, s2);
-    }
-    send(ST_REACT_SUR, s2);
-    sbeg(ST_REACT_EXPAND, s2);
-    lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s2);
-  } else {
-    send(ST_REACT_TABLES, s2);
-    sbeg(ST_REACT_MFMA, s2);
-    send(ST_REACT_MFMA, s2);
-    sbeg(ST_REACT_SUR, s2);
-    send(ST_REACT_SUR, s2);
-    sbeg(ST_REACT_EXPAND, s2);
   }
   send(ST_REACT_EXPAND, s2);
   HIPCHK(hipEventRecord(P->join_ev, s2));
@@ -1786,7 +1827,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     tgt_list[l * max_tt + 2] = tgt_tree[2 * l + 1];
   }
   int* d_tl = P->upload("tgt_list", tgt_list, s);
-  lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, s);
+  lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, st, P->physical, s);
   send(ST_SUM, s);
   // every stream has joined the main one by now: the staging arena's last use is
   // complete once the main stream gets here
@@ -1805,6 +1846,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       if (hipEventElapsedTime(&ms, P->evb[i], P->eve[i]) == hipSuccess) rep.stage_ms[i] = ms;
     }
   }
+  P->last_opsig.swap(opsig);
   return LFMM_OK;
 }
 

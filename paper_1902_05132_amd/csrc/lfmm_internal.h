@@ -184,7 +184,8 @@ void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps,
 void lk_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, const int* srow, int stride,
                     unsigned long long* counter, hipStream_t s);
 void lk_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
-                  int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, hipStream_t s);
+                  int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, Stack st, int phys,
+                  hipStream_t s);
 void lk_mlp_gemm(const MlpGemm& g, hipStream_t s);
 void lk_mlp_mse(int B, int nout, const float* y, const float* t, long ldt, unsigned short* d, double* partial,
                 double* loss, hipStream_t s);

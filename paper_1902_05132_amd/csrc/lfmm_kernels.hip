@@ -2073,8 +2073,11 @@ extern "C" void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFC
 // ---------------------------------------------------------------------------
 // Final sum over the trees in which particle i is a target (eq. (totalinteraction))
 // ---------------------------------------------------------------------------
+// phys: return the physical potential, the sum times i k_l / (4 pi) (the paper's
+// Phi normalisation divides the physical potential by it)
 __global__ void k_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
-                            int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi) {
+                            int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, Stack st,
+                            int phys) {
   int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   int l = layer[i];
@@ -2089,10 +2092,19 @@ __global__ void k_final_sum(int n, const int* layer, const int* inv_perm, const 
       sy += phi_tp[2 * g + 1];
     }
   }
+  if (phys && l >= 0) {
+    const double c = st.k[l] / (4.0 * LFMM_PI);
+    const double rx = -sy * c, ry = sx * c;
+    sx = rx;
+    sy = ry;
+  }
   phi[2 * i] = sx;
   phi[2 * i + 1] = sy;
 }
 extern "C" void lk_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
-                             int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, hipStream_t s) {
-  if (n) k_final_sum<<<nblk(n, 256), 256, 0, s>>>(n, layer, inv_perm, layer_start, tgt_trees, max_tt, trees, phi_tp, phi);
+                             int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, Stack st, int phys,
+                             hipStream_t s) {
+  if (n)
+    k_final_sum<<<nblk(n, 256), 256, 0, s>>>(n, layer, inv_perm, layer_start, tgt_trees, max_tt, trees, phi_tp, phi,
+                                             st, phys);
 }

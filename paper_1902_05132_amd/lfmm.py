@@ -25,7 +25,8 @@ class LfmmError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("contour_b", ctypes.c_double), ("max_depth", ctypes.c_int), ("min_gap", ctypes.c_double),
-                ("profile", ctypes.c_int), ("precision", ctypes.c_int)]
+                ("profile", ctypes.c_int), ("precision", ctypes.c_int), ("physical", ctypes.c_int),
+                ("reuse_operators", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -35,7 +36,7 @@ class Report(ctypes.Structure):
                 ("m2l_slots", ctypes.c_int64), ("m2m_pairs", ctypes.c_int64), ("l2l_pairs", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
                 ("p2p_series", ctypes.c_int), ("precision", ctypes.c_int),
-                ("stage_ms", ctypes.c_double * 16), ("n_react_surrogate", ctypes.c_int64)]
+                ("stage_ms", ctypes.c_double * 16), ("n_react_surrogate", ctypes.c_int64), ("ops_reused", ctypes.c_int)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -118,14 +119,18 @@ def _f64(a):
 class Plan:
     """lfmm_plan wrapper: d (L interfaces, decreasing), k (L+1 wavenumbers), order p, leaf size."""
 
-    def __init__(self, d, k, p, leaf_max, contour_b=0.5, max_depth=8, min_gap=1e-9, profile=False, precision=0):
-        """precision 0: FP64 throughout; 1: mixed (FP32 near field and FP32-MFMA M2L)."""
+    def __init__(self, d, k, p, leaf_max, contour_b=0.5, max_depth=8, min_gap=1e-9, profile=False, precision=0,
+                 physical=False, reuse_operators=False):
+        """precision 0: FP64 throughout; 1: mixed (FP32 near field and FP32-MFMA M2L).
+        physical: return physical potentials (Phi times i k_l / (4 pi)) instead of Phi.
+        reuse_operators: keep the previous evaluation's operators when its trees are the same."""
         self.lib = load()
         self.d = _f64(d)
         self.k = _f64(k)
         self.p = int(p)
         self.L = len(self.d)
-        opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0, int(precision))
+        opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0, int(precision), 1 if physical else 0,
+                      1 if reuse_operators else 0)
         h = ctypes.c_void_p()
         dptr = self.d.ctypes.data_as(_D) if self.L else None
         _check(self.lib.lfmm_plan(self.L, dptr, self.k.ctypes.data_as(_D), self.p, int(leaf_max),
@@ -229,7 +234,7 @@ class Plan:
                     m2l_pairs=r.m2l_pairs, m2l_slots=r.m2l_slots,
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
                     p2p_series=r.p2p_series, precision=r.precision,
-                    n_react_surrogate=r.n_react_surrogate, stage_ms=stages)
+                    n_react_surrogate=r.n_react_surrogate, ops_reused=r.ops_reused, stage_ms=stages)
 
     # ---- learned surrogate of the reaction integrals ----
     def surrogate_train(self, n_samples=0, seed=0, h_min=0.0, h_max=0.0, epochs=0, batch=0, lr=0.0, holdout=0.0,

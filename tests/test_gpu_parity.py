@@ -298,3 +298,46 @@ def test_five_layer_clustered():
     w = W.config5(n=5000, p=5, leaf=64)
     phi, ref, rep = _check_fmm(w, p=5, leaf=64)
     assert rep["reaction_depth"] >= 5
+
+
+def test_physical_normalisation():
+    lf = _lfmm()
+    # one homogeneous layer, two particles: the physical potential is the closed form
+    k = 1.3
+    x, y, z = np.array([0.1, 0.4]), np.array([-0.2, 0.3]), np.array([0.0, 0.25])
+    q = np.array([1.0 + 0.5j, -0.3 + 2.0j])
+    P = lf.Plan([], [k], p=4, leaf_max=8, physical=True)
+    phi = P.eval_torch(x, y, z, q)
+    r = np.sqrt((x[0] - x[1]) ** 2 + (y[0] - y[1]) ** 2 + (z[0] - z[1]) ** 2)
+    g = np.exp(1j * k * r) / (4 * np.pi * r)
+    assert np.allclose(phi, [q[1] * g, q[0] * g], rtol=1e-14, atol=0)
+    # three layers: Phi times i k_l / (4 pi), layer by layer
+    w = W.small_three_layer(n_per_layer=80, seed=5)
+    a = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"]).eval_torch(w["x"], w["y"], w["z"], w["q"])
+    b = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], physical=True).eval_torch(w["x"], w["y"], w["z"], w["q"])
+    kl = np.asarray(w["k"])[w["layer"]]
+    assert np.allclose(b, a * 1j * kl / (4 * np.pi), rtol=1e-15, atol=0)
+
+
+def test_operator_reuse_on_unchanged_trees():
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=300, seed=11)
+    for prec in (0, 1):
+        P = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], precision=prec, reuse_operators=True)
+        a = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
+        assert P.report()["ops_reused"] == 0
+        b = P.eval_torch(w["x"], w["y"], w["z"], 2.0 * w["q"])  # same trees, other charges
+        assert P.report()["ops_reused"] == 1
+        assert np.array_equal(b, 2.0 * a) or np.allclose(b, 2.0 * a, rtol=1e-14, atol=0)
+        # moved particles: whatever the plan reuses must give the result of a fresh plan
+        # (operators depend only on the trees' box sizes, so a shift inside the same
+        # roots may keep them)
+        fresh_plan = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], precision=prec)
+        x2 = w["x"] * 0.9
+        c = P.eval_torch(x2, w["y"], w["z"], w["q"])
+        assert np.array_equal(c, fresh_plan.eval_torch(x2, w["y"], w["z"], w["q"]))
+        # stretched laterally: larger roots, so the operators are generated again
+        x3, y3 = w["x"] * 1.3, w["y"] * 1.3
+        d = P.eval_torch(x3, y3, w["z"], w["q"])
+        assert P.report()["ops_reused"] == 0
+        assert np.array_equal(d, fresh_plan.eval_torch(x3, y3, w["z"], w["q"]))
