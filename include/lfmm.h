@@ -170,6 +170,27 @@ void lfmm_destroy(lfmm_plan_t* plan);
 /* Text of a status code. */
 const char* lfmm_status_string(int status);
 
+/* ---- tile-shape autotuning ---- */
+typedef struct {
+  int gemm_ks;          /* chosen M2L K-split (waves sharing a 16-target tile's operator sequence) */
+  int p2p_ta, p2p_ch;   /* chosen near-field tile shape (FP64 series path: targets per wave step,
+                           sources per LDS tile); the mixed path has one shape */
+  int trials;           /* evaluations timed */
+  double ms_default, ms_best; /* time per evaluation with the default and the chosen shapes */
+} lfmm_tune_report;
+
+/*
+ * Time whole evaluations of the given particles (device buffers, as lfmm_eval_device,
+ * on the given stream) over the tile shapes the library carries -- M2L K-split 1, 2, 4;
+ * for FP64 plans the near-field shapes (4, 8, 16 targets per wave step x 128, 256, 512
+ * sources per tile) -- one coordinate at a time, and keep the fastest for later
+ * evaluations of this plan.  phi receives the last evaluation's potentials.  The shapes
+ * change only the summation order, so results agree to rounding.  rep is optional (host).
+ * Errors: as lfmm_eval_device.
+ */
+int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi,
+                  void* stream, lfmm_tune_report* rep);
+
 /* ---- learned surrogate of the reaction M2L integrals ----
  *
  * The integral matrices I[(n,m),(n',m')] of the reaction M2L operators (Section 3.5,

@@ -2346,4 +2346,75 @@ int lfmm_mlp_forward_backward(int B, int nin, int width, int nhidden, int nout, 
   return rc;
 }
 
+int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi,
+                  void* stream, lfmm_tune_report* rep) {
+  if (!plan) return LFMM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  lfmm_tune_report R;
+  memset(&R, 0, sizeof(R));
+  auto timed = [&](double* ms) -> int {
+    int rc = eval_impl(plan, n, xyz, layer, q, phi, s);  // warm-up (sizes buffers)
+    if (rc != LFMM_OK) return rc;
+    double best = 1e300;
+    for (int r = 0; r < 2; r++) {
+      if (hipStreamSynchronize(s) != hipSuccess) return LFMM_EHIP;
+      auto t0 = std::chrono::steady_clock::now();
+      rc = eval_impl(plan, n, xyz, layer, q, phi, s);
+      if (rc != LFMM_OK) return rc;
+      if (hipStreamSynchronize(s) != hipSuccess) return LFMM_EHIP;
+      best = std::min(best, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+    R.trials += 3;
+    *ms = best;
+    return LFMM_OK;
+  };
+  const int ks0 = plan->gemm_ks, ta0 = plan->p2p_ta, ch0 = plan->p2p_ch;
+  double best;
+  int rc = timed(&best);
+  if (rc != LFMM_OK) return rc;
+  R.ms_default = best;
+  int bks = ks0, bta = ta0, bch = ch0;
+  for (int ks : {1, 2, 4}) {
+    if (ks == ks0) continue;
+    plan->gemm_ks = ks;
+    double ms;
+    if ((rc = timed(&ms)) != LFMM_OK) break;
+    if (ms < best) {
+      best = ms;
+      bks = ks;
+    }
+  }
+  plan->gemm_ks = bks;
+  if (rc == LFMM_OK && plan->prec == 0) {
+    const int shapes[][2] = {{4, 256}, {16, 256}, {8, 128}, {8, 512}, {4, 128}, {16, 512}};
+    for (auto& sh : shapes) {
+      if (sh[0] == ta0 && sh[1] == ch0) continue;
+      plan->p2p_ta = sh[0];
+      plan->p2p_ch = sh[1];
+      double ms;
+      if ((rc = timed(&ms)) != LFMM_OK) break;
+      if (ms < best) {
+        best = ms;
+        bta = sh[0];
+        bch = sh[1];
+      }
+    }
+  }
+  plan->p2p_ta = bta;
+  plan->p2p_ch = bch;
+  if (rc != LFMM_OK) {  // keep the defaults after a failure
+    plan->gemm_ks = ks0;
+    plan->p2p_ta = ta0;
+    plan->p2p_ch = ch0;
+    return rc;
+  }
+  if ((rc = eval_impl(plan, n, xyz, layer, q, phi, s)) != LFMM_OK) return rc;
+  R.gemm_ks = plan->gemm_ks > 0 ? plan->gemm_ks : 4;
+  R.p2p_ta = plan->p2p_ta;
+  R.p2p_ch = plan->p2p_ch;
+  R.ms_best = best;
+  if (rep) *rep = R;
+  return LFMM_OK;
+}
+
 }  // extern "C"

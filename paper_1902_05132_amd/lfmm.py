@@ -39,6 +39,11 @@ class Report(ctypes.Structure):
                 ("stage_ms", ctypes.c_double * 16), ("n_react_surrogate", ctypes.c_int64), ("ops_reused", ctypes.c_int)]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [("gemm_ks", ctypes.c_int), ("p2p_ta", ctypes.c_int), ("p2p_ch", ctypes.c_int),
+                ("trials", ctypes.c_int), ("ms_default", ctypes.c_double), ("ms_best", ctypes.c_double)]
+
+
 class TrainOpts(ctypes.Structure):
     _fields_ = [("h_min", ctypes.c_double), ("h_max", ctypes.c_double), ("epochs", ctypes.c_int),
                 ("batch", ctypes.c_int), ("lr", ctypes.c_double), ("holdout", ctypes.c_double),
@@ -94,6 +99,7 @@ def load():
     L.lfmm_reaction_operator.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
     L.lfmm_densities.argtypes = [vp, ctypes.c_int, _D, ctypes.c_int, ctypes.c_int, _D]
+    L.lfmm_autotune.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, ctypes.POINTER(TuneReport)]
     L.lfmm_surrogate_train.argtypes = [vp, ctypes.c_int64, ctypes.c_uint64, ctypes.POINTER(TrainOpts),
                                        ctypes.POINTER(TrainReport)]
     L.lfmm_surrogate_save.argtypes = [vp, ctypes.c_char_p]
@@ -235,6 +241,16 @@ class Plan:
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
                     p2p_series=r.p2p_series, precision=r.precision,
                     n_react_surrogate=r.n_react_surrogate, ops_reused=r.ops_reused, stage_ms=stages)
+
+    def autotune(self, xyz, q, phi, layer=None, stream=None):
+        """lfmm_autotune on torch device tensors (as eval_device); returns the tuning report."""
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        r = TuneReport()
+        lp = layer.data_ptr() if layer is not None else None
+        _check(self.lib.lfmm_autotune(self.h, xyz.shape[1], xyz.data_ptr(), lp, q.data_ptr(), phi.data_ptr(),
+                                      ctypes.c_void_p(s.cuda_stream), ctypes.byref(r)), "lfmm_autotune")
+        return {f: getattr(r, f) for f, _ in TuneReport._fields_}
 
     # ---- learned surrogate of the reaction integrals ----
     def surrogate_train(self, n_samples=0, seed=0, h_min=0.0, h_max=0.0, epochs=0, batch=0, lr=0.0, holdout=0.0,

@@ -341,3 +341,24 @@ def test_operator_reuse_on_unchanged_trees():
         d = P.eval_torch(x3, y3, w["z"], w["q"])
         assert P.report()["ops_reused"] == 0
         assert np.array_equal(d, fresh_plan.eval_torch(x3, y3, w["z"], w["q"]))
+
+
+def test_autotune_keeps_results():
+    import torch
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=400, seed=13)
+    dev = torch.device("cuda")
+    xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+    q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+    for prec in (0, 1):
+        ref = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], precision=prec).eval_torch(
+            w["x"], w["y"], w["z"], w["q"])
+        P = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], precision=prec)
+        phi = torch.empty_like(q)
+        r = P.autotune(xyz, q, phi)
+        torch.cuda.synchronize()
+        assert r["gemm_ks"] in (1, 2, 4) and r["trials"] >= 3 and r["ms_best"] <= r["ms_default"]
+        after = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
+        # a different tile shape changes the summation order only
+        assert rel(after, ref) < (1e-13 if prec == 0 else 1e-6)
+        assert rel(phi.cpu().numpy(), ref) < (1e-13 if prec == 0 else 1e-6)
