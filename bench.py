@@ -33,6 +33,7 @@ PEAK = {("mfma", 64): 78.6, ("mfma", 32): 157.3, ("alu", 64): 78.6, ("alu", 32):
 # -(kr)^2 (1), series (6 + 6 fma), -cos(kr)/(kr) (2), complex multiply-add (8) = 50.
 P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}
 TOL_MIXED = 1e-6  # the mixed path is the headline only if it stays this close to the FP64 path
+TABLE_H = (0.03, 1.0)  # box sizes the tables cover (every level of the bench workload's trees)
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_05132_amd", "csrc", "lfmm_kernels.hip")
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "m2l_p2p_react_kernels_hbm_counters_3layer_N1M_p8_leaf256.txt")
 
@@ -154,6 +155,56 @@ def surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch):
     return res
 
 
+def tables_leg(args, w, xyz, q, stream, plain, lfmm, torch):
+    """Pre-computed tables of the reaction M2L integrals on the bench workload: built
+    once per medium by the quadrature (not timed, reported), then timed with the gate
+    open in both precisions, each against the plain FP64 path."""
+    n = len(w["x"])
+    res = {}
+    phi = torch.empty(n, dtype=torch.complex128, device=xyz.device)
+    for precision in (0, 1):
+        plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision)
+        t0 = time.perf_counter()
+        tr = plan.tables_build(h_min=TABLE_H[0], h_max=TABLE_H[1])
+        t_build = time.perf_counter() - t0
+        if precision == 0:
+            log("bench: tables built in %.2f s: %d combinations x %d panels x %d nodes, %.2f GB, "
+                "validation error median %.2e, max %.2e" % (t_build, tr["n_combos"], tr["npanel"], tr["nnode"],
+                                                            tr["bytes"] / 1e9, tr["err_median"], tr["err_max"]))
+            res["build"] = {"seconds": t_build, "ms_quadrature": tr["ms_build"], "ms_validate": tr["ms_validate"],
+                            "h_range": list(TABLE_H), "combinations": tr["n_combos"], "panels": tr["npanel"],
+                            "nodes": tr["nnode"], "bytes": tr["bytes"], "validation_err_median": tr["err_median"],
+                            "validation_err_max": tr["err_max"], "largest_bound": float(plan.tables_bounds().max())}
+        plan.tables_gate(1e300)
+        for i in range(args.warmup):
+            plan.eval_device(xyz, q, phi, stream=stream)
+        torch.cuda.synchronize()
+        acc = {}
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            plan.eval_device(xyz, q, phi, stream=stream)
+            rep = plan.report()
+            for kname, v in rep["stage_ms"].items():
+                acc[kname] = acc.get(kname, 0.0) + v
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        plan.close()
+        d = phi - plain["phi"]
+        err2 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(plain["phi"]))
+        errmax = float(d.abs().max() / plain["phi"].abs().max())
+        st = {k: v / args.steps for k, v in acc.items()}
+        name = "fp64" if precision == 0 else "mixed"
+        res[name] = {"classes_from_tables": rep["n_react_table"], "classes": rep["n_react_classes"],
+                     "ms_per_step": ms, "value": n / (ms / 1000.0), "speedup_vs_plain_fp64": plain["ms"] / ms,
+                     "rel_err_vs_fp64": {"err2": err2, "errmax": errmax},
+                     "reaction_integrals_ms": st["react_tables"] + st["react_mfma"] + st["react_table"],
+                     "stages_ms": st}
+        log("bench: tables %s: %d of %d classes from the tables, %.3f ms/step, Err2 %.2e, Errmax %.2e, "
+            "reaction integrals %.3f ms" % (name, rep["n_react_table"], rep["n_react_classes"], ms, err2, errmax,
+                                              res[name]["reaction_integrals_ms"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +216,7 @@ def main():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
+    ap.add_argument("--no-tables", action="store_true", help="skip the pre-computed-tables leg")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--scaling", action="store_true",
                     help="also time N = 2^17 .. 2^21 of the same workload (both precisions), to show O(N) cost")
@@ -282,6 +334,8 @@ def main():
     out["warm_operators"] = {"ms_per_step": wms, "value": n / (wms / 1000.0), "ops_reused": reused,
                              "identical_to_cold": same,
                              "what": "mixed path, operators of the previous evaluation kept (same trees)"}
+    if not args.no_tables:
+        out["tables"] = tables_leg(args, w, xyz, q, stream, plain, lfmm, torch)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch)
     if args.scaling:

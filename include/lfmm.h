@@ -40,7 +40,7 @@ typedef enum {
   LFMM_ENOMEM = 2,  /* device or host allocation failed */
   LFMM_EHIP = 3,    /* a HIP runtime call failed */
   LFMM_ENOTSUP = 4, /* the configuration is outside what this build supports */
-  LFMM_EIO = 5      /* a surrogate file could not be read or written, or does not match the plan */
+  LFMM_EIO = 5      /* a surrogate or table file could not be read or written, or does not match the plan */
 } lfmm_status;
 
 /* Plan options; pass NULL for the defaults shown. */
@@ -82,10 +82,11 @@ typedef struct {
   int64_t nf_react_pairs;  /* near-field reaction pairs */
   int p2p_series;          /* 1: near field used the series form of h0 (k r <= 1 on every pair) */
   int precision;           /* the plan's precision option */
-  double stage_ms[16];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
+  double stage_ms[24];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
   int64_t n_react_surrogate; /* reaction classes whose integrals came from the surrogate (gate hits);
                                 the other n_react_classes - n_react_surrogate used the quadrature */
   int ops_reused;            /* 1: the operators of the previous evaluation were kept (reuse_operators) */
+  int64_t n_react_table;     /* reaction classes whose integrals came from the pre-computed tables */
 } lfmm_report;
 
 /*
@@ -260,6 +261,61 @@ int lfmm_surrogate_gate(lfmm_plan_t* plan, double tol);
  * combination had no held-out class), and the number written in *count.
  */
 int lfmm_surrogate_bounds(const lfmm_plan_t* plan, int n, double* bounds, int* count);
+
+/* ---- pre-computed tables of the reaction M2L integrals ----
+ *
+ * The paper's alternative to integrating every class at run time (Section 3.5:
+ * tables of the integrals on a grid, polynomial interpolation in the FMM), in the
+ * form a uniform tree needs: a class is a geometry combination (as for the
+ * surrogate) at a box size h, so the paper's tables over (rho, z, z') reduce along
+ * the tree's geometry to one table in h per combination.  Each holds the
+ * normalised matrix (the m >= 0 rows) at Chebyshev points of the second kind on
+ * equal panels of u = ln h + alpha h, alpha = 4 max_l k_l, built by the library's
+ * quadrature on the GPU, and is interpolated by the barycentric formula (FP64,
+ * in HBM).  Bound of a combination: twice the largest error, in the surrogate's
+ * norm, at validation points halfway (in angle) between nodes against the
+ * quadrature.  Gate: a class uses the tables if its h lies in the tabulated range
+ * and its combination's bound is <= the gate tolerance; the tables take precedence
+ * over the surrogate; a closed gate (0, the default) leaves evaluations
+ * bit-identical to ones without tables.
+ */
+typedef struct {
+  double h_min, h_max; /* box sizes covered: 0.02 .. 2.0 */
+  int nnode;           /* Chebyshev points per panel: 16 (2 .. 32) */
+  double du;           /* largest panel width in u: 1.5 */
+  int nval;            /* validation points per panel: 4 (at most nnode - 1) */
+} lfmm_table_opts;
+
+typedef struct {
+  int n_combos, npanel, nnode;
+  int64_t n_slots;            /* tabulated matrices (combinations x panels x nodes) */
+  int64_t n_validation;       /* validation classes */
+  int64_t bytes;              /* device memory of the tables */
+  double err_median, err_max; /* validation errors (weighted relative, as the bounds) */
+  double ms_build, ms_validate;
+} lfmm_table_report;
+
+/*
+ * Build the plan's tables (opts and rep optional, host).  Replaces previous tables;
+ * the gate keeps its tolerance.  Errors: LFMM_EINVAL (L = 0; bad options, more than
+ * 4096 panels), LFMM_ENOMEM, LFMM_EHIP.
+ */
+int lfmm_tables_build(lfmm_plan_t* plan, const lfmm_table_opts* opts, lfmm_table_report* rep);
+
+/* Gate tolerance (>= 0; 0 closes the gate) for later evaluations of this plan. */
+int lfmm_tables_gate(lfmm_plan_t* plan, double tol);
+
+/* Validated bound of each geometry combination (ordered as lfmm_surrogate_bounds). */
+int lfmm_tables_bounds(const lfmm_plan_t* plan, int n, double* bounds, int* count);
+
+/* Free the tables' device memory (the gate then has nothing to select). */
+int lfmm_tables_release(lfmm_plan_t* plan);
+
+/* Write the tables (layout, bounds, medium, values) to a file; LFMM_EINVAL if none, LFMM_EIO. */
+int lfmm_tables_save(const lfmm_plan_t* plan, const char* path);
+
+/* Read tables written for the same medium and order p; LFMM_EIO if unreadable or mismatched. */
+int lfmm_tables_load(lfmm_plan_t* plan, const char* path);
 
 /*
  * One forward and backward pass of a network of the surrogate's form on the GPU

@@ -48,11 +48,11 @@ struct Fail {
 
 enum {
   ST_CLASSIFY, ST_TREE, ST_OPS_FREE, ST_REACT_TABLES, ST_REACT_MFMA, ST_REACT_EXPAND, ST_JOBS, ST_P2M, ST_M2M,
-  ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_NEAR_REACT, ST_SUM, ST_REACT_SUR, ST_COUNT
+  ST_M2L, ST_L2L, ST_L2P, ST_P2P, ST_NEAR_REACT, ST_SUM, ST_REACT_SUR, ST_REACT_TAB, ST_COUNT
 };
 const char* kStageNames[ST_COUNT] = {"classify", "tree",  "ops_free", "react_tables",  "react_mfma", "react_expand",
                                      "jobs",     "p2m",   "m2m",      "m2l",           "l2l",        "l2p",
-                                     "p2p_free", "near_reaction", "sum", "react_surrogate"};
+                                     "p2p_free", "near_reaction", "sum", "react_surrogate", "react_table"};
 
 // ---------------------------------------------------------------------------
 // Host-side constants owned by the library (independent of any checker):
@@ -316,6 +316,29 @@ struct Surrogate {
   std::vector<double> Dc;    // per component: extra decay length of its density at large k_rho
   MlpNet net;
   lfmm_train_report trep;
+  int version = 0;  // changes whenever the network does
+};
+
+// Pre-computed tables of the reaction M2L integrals of one plan, and their gate.
+// For every geometry combination the normalised integral matrix is tabulated as a
+// function of u = ln h + alpha h (alpha = 4 max_l k_l: logarithmic in h where the
+// matrices vary as powers of h, linear where they oscillate with h) on npanel equal
+// panels of Chebyshev points of the second kind (nnode per panel).
+struct OpTables {
+  bool ready = false;
+  double tol = 0.0;  // gate: classes whose validated bound is <= tol use the tables
+  double h_lo = 0.0, h_hi = 0.0, alpha = 0.0, u0 = 0.0, du = 0.0;
+  int npanel = 0, nnode = 0, ndense = 0, version = 0;
+  std::vector<int> dense;     // [comp][j][i][ri] -> dense combination index, -1 where none
+  std::vector<double> bound;  // [comp][j][i][ri] validated error bound (inf: none)
+  DevBuf tab;                 // [dense][panel][node] normalised matrices (NT x NC complex FP64)
+  lfmm_table_report rep;
+  void release() {
+    if (tab.p) (void)hipFree(tab.p);
+    tab.p = nullptr;
+    tab.cap = 0;
+    ready = false;
+  }
 };
 
 // widest far panel of the Sommerfeld contour rule (tuning override LFMM_FAR_CAP)
@@ -351,6 +374,7 @@ struct lfmm_plan_s {
   hipStream_t s3 = nullptr;
   hipEvent_t jobs_ev = nullptr;
   Surrogate sur;
+  OpTables tab;
 
   // device workspace in use: the plan's own, or one lent by a batch worker
   std::map<std::string, DevBuf>* bufp = &bufs;
@@ -968,7 +992,226 @@ void sur_train_impl(lfmm_plan_s* P, int64_t n_samples, uint64_t seed, const lfmm
     }
   }
   S.trep = R;
+  S.version++;
   S.ready = true;
+}
+
+// ---------------------------------------------------------------------------
+// Pre-computed tables of the reaction M2L integrals (the tabulation of Section
+// 3.5 and the table form of Algorithm 1, restricted to what a uniform tree asks
+// for).  Every reaction class of an evaluation is a geometry combination (component,
+// j, i, lateral class) at a box size h, its centres at heights (j + 1/2) h and
+// (i + 1/2) h and lateral distance sqrt(r2) h: the paper's tables over (rho, z, z')
+// are, along that curve, one table in h per combination.  Entries are normalised as
+// the surrogate's targets (I / env) and interpolated in u = ln h + alpha h by the
+// barycentric formula on Chebyshev points of the second kind.  Bounds: the largest
+// weighted relative error (the surrogate's norm) over validation classes halfway
+// (in angle) between nodes, against the quadrature, times two.
+// ---------------------------------------------------------------------------
+static std::vector<int4> component_labels(lfmm_plan_s* P) {
+  const int NL = P->st.L + 1;
+  std::vector<int4> lab(P->sur.ncomp);
+  for (int l = 0; l < NL; l++)
+    for (int a = 0; a < 2; a++)
+      for (int lp = 0; lp < NL; lp++)
+        for (int b = 0; b < 2; b++) {
+          const int c = sur_comp(P, l, a, lp, b);
+          if (c >= 0) lab[c] = make_int4(l, a, lp, b);
+        }
+  return lab;
+}
+static ClassDesc combo_class(lfmm_plan_s* P, const int4& lab, int j, int i, int ri, double h, int out) {
+  ClassDesc C;
+  memset(&C, 0, sizeof(C));
+  C.zt = (j + 0.5) * h;
+  C.zs = (i + 0.5) * h;
+  C.rho = h * std::sqrt((double)kR2[ri]);
+  C.rule = P->make_rule(C.zt + C.zs, C.rho, 2 * P->p + 1);
+  C.lt = lab.x;
+  C.a = lab.y;
+  C.ls = lab.z;
+  C.b = lab.w;
+  C.out = out;
+  return C;
+}
+inline double tab_u(const OpTables& T, double h) { return std::log(h) + T.alpha * h; }
+// h of u: Newton on f(t) = t + alpha e^t - u (increasing, convex) from t = u, where
+// f >= 0, so the iterates decrease monotonically to the root
+static double tab_h(const OpTables& T, double u) {
+  double t = u;
+  for (int it = 0; it < 400; it++) {
+    const double e = T.alpha * std::exp(t), f = t + e - u, dt = f / (1.0 + e);
+    t -= dt;
+    if (std::fabs(dt) <= 1e-15 * std::max(1.0, std::fabs(t))) break;
+  }
+  return std::exp(t);
+}
+inline double tab_node_x(int n, int j) { return std::cos(LFMM_PI * j / (n - 1)); }
+// panel of h and the barycentric weights of its nodes (w[0..n-1], summing to 1);
+// Chebyshev points of the second kind have the weights (-1)^j, halved at both ends
+static int tab_weights(const OpTables& T, double h, double* w) {
+  const int n = T.nnode;
+  const double u = tab_u(T, h);
+  int k = (int)std::floor((u - T.u0) / T.du);
+  k = std::min(std::max(k, 0), T.npanel - 1);
+  const double x = std::min(1.0, std::max(-1.0, 2.0 * (u - (T.u0 + k * T.du)) / T.du - 1.0));
+  double sum = 0.0;
+  for (int j = 0; j < n; j++) {
+    const double xj = tab_node_x(n, j);
+    if (x == xj) {
+      for (int i = 0; i < n; i++) w[i] = i == j ? 1.0 : 0.0;
+      return k;
+    }
+    w[j] = ((j & 1) ? -1.0 : 1.0) * ((j == 0 || j == n - 1) ? 0.5 : 1.0) / (x - xj);
+    sum += w[j];
+  }
+  for (int j = 0; j < n; j++) w[j] /= sum;
+  return k;
+}
+// node j of panel k -> x = cos(pi j / (n - 1)) -> u = u_k + (x + 1) du / 2
+static double tab_node_h(const OpTables& T, int k, double x) {
+  return tab_h(T, T.u0 + k * T.du + 0.5 * (x + 1.0) * T.du);
+}
+
+void tab_build_impl(lfmm_plan_s* P, const lfmm_table_opts& o, lfmm_table_report& R) {
+  OpTables& T = P->tab;
+  const Stack& st = P->st;
+  const int p = P->p, NC = P->NC, NT = P->NT;
+  hipStream_t s = P->s2;
+  auto wall = []() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  };
+  T.release();
+  sur_components(P);
+  sur_decay(P);
+  const int ncomp = P->sur.ncomp;
+  const std::vector<int4> lab = component_labels(P);
+  T.h_lo = o.h_min;
+  T.h_hi = o.h_max;
+  T.alpha = 4.0 * P->kmax;
+  T.nnode = o.nnode;
+  T.u0 = tab_u(T, T.h_lo);
+  const double u1 = tab_u(T, T.h_hi);
+  T.npanel = std::max(1, (int)std::ceil((u1 - T.u0) / o.du - 1e-9));
+  T.du = (u1 - T.u0) / T.npanel;
+  T.dense.assign((size_t)ncomp * 40, -1);
+  T.bound.assign((size_t)ncomp * 40, INFINITY);
+  struct Cmb {
+    int comp, j, i, ri;
+  };
+  std::vector<Cmb> cmbs;
+  for (int c = 0; c < ncomp; c++)
+    for (int j = 0; j < 2; j++)
+      for (int i = 0; i < 2; i++)
+        for (int ri = 0; ri < 10; ri++) {
+          if (i == 0 && j == 0 && kR2[ri] <= 2) continue;
+          T.dense[sur_combo(c, j, i, ri)] = (int)cmbs.size();
+          cmbs.push_back(Cmb{c, j, i, ri});
+        }
+  T.ndense = (int)cmbs.size();
+  const size_t nh = (size_t)NT * NC, mat = (size_t)NC * NC * 2;
+  const int64_t nslot = (int64_t)T.ndense * T.npanel * T.nnode;
+  memset(&R, 0, sizeof(R));
+  R.n_combos = T.ndense;
+  R.npanel = T.npanel;
+  R.nnode = T.nnode;
+  R.n_slots = nslot;
+  R.bytes = nslot * (int64_t)nh * 16;
+  if (hipMalloc(&T.tab.p, (size_t)R.bytes) != hipSuccess) {
+    T.tab.p = nullptr;
+    throw Fail{LFMM_ENOMEM};
+  }
+  T.tab.cap = (size_t)R.bytes;
+  double* tab = (double*)T.tab.p;
+  const int CHK = 1024;
+  double* Ich = P->dev<double>("tab_Ich", (size_t)CHK * mat);
+  // ---- nodes: quadrature, normalised into their slots
+  double t0 = wall();
+  for (int64_t g0 = 0; g0 < nslot; g0 += CHK) {
+    const int nc = (int)std::min<int64_t>(CHK, nslot - g0);
+    HIPCHK(hipStreamSynchronize(s));
+    P->pin_reset();
+    std::vector<ClassDesc> cls(nc);
+    std::vector<double> dadd(nc);
+    std::vector<int> slot(nc);
+    for (int c = 0; c < nc; c++) {
+      const int64_t g = g0 + c;
+      const int jn = (int)(g % T.nnode), k = (int)((g / T.nnode) % T.npanel), d = (int)(g / ((int64_t)T.nnode * T.npanel));
+      const Cmb& m = cmbs[d];
+      cls[c] = combo_class(P, lab[m.comp], m.j, m.i, m.ri, tab_node_h(T, k, tab_node_x(T.nnode, jn)), c);
+      dadd[c] = P->sur.Dc[m.comp];
+      slot[c] = (int)g;
+    }
+    reaction_integrals(P, "tab", cls, Ich, s);
+    ClassDesc* dcls = P->upload("tab_cls", cls, s);
+    double* dd = P->upload("tab_dadd", dadd, s);
+    int* ds = P->upload("tab_slot", slot, s);
+    lk_tab_store(nc, dcls, dd, ds, st, Ich, p, NC, tab, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  R.ms_build = wall() - t0;
+  // ---- validation halfway (in angle) between nodes, spread over each panel
+  t0 = wall();
+  const int nval = std::min(o.nval, T.nnode - 1);
+  const int64_t nv = (int64_t)T.ndense * T.npanel * nval;
+  R.n_validation = nv;
+  std::vector<double> worst(T.bound.size(), -1.0), all;
+  double* Ipred = P->dev<double>("tab_Ipred", (size_t)CHK * mat);
+  double* derr = P->dev<double>("tab_err", CHK);
+  for (int64_t g0 = 0; g0 < nv; g0 += CHK) {
+    const int nc = (int)std::min<int64_t>(CHK, nv - g0);
+    HIPCHK(hipStreamSynchronize(s));
+    P->pin_reset();
+    std::vector<ClassDesc> cls(nc);
+    std::vector<double> dadd(nc), hv(nc), w((size_t)nc * T.nnode);
+    std::vector<int> slot0(nc), cb(nc);
+    for (int c = 0; c < nc; c++) {
+      const int64_t g = g0 + c;
+      const int v = (int)(g % nval), k = (int)((g / nval) % T.npanel), d = (int)(g / ((int64_t)nval * T.npanel));
+      const int jv = nval > 1 ? (int)std::lround((double)v * (T.nnode - 2) / (nval - 1)) : (T.nnode - 2) / 2;
+      const double x = std::cos(LFMM_PI * (jv + 0.5) / (T.nnode - 1));
+      const Cmb& m = cmbs[d];
+      hv[c] = tab_node_h(T, k, x);
+      cls[c] = combo_class(P, lab[m.comp], m.j, m.i, m.ri, hv[c], c);
+      dadd[c] = P->sur.Dc[m.comp];
+      const int kk = tab_weights(T, hv[c], &w[(size_t)c * T.nnode]);
+      slot0[c] = (d * T.npanel + kk) * T.nnode;
+      cb[c] = sur_combo(m.comp, m.j, m.i, m.ri);
+    }
+    reaction_integrals(P, "tab", cls, Ich, s);
+    ClassDesc* dcls = P->upload("tab_cls", cls, s);
+    double* dd = P->upload("tab_dadd", dadd, s);
+    int* ds = P->upload("tab_slot", slot0, s);
+    double* dw = P->upload("tab_w", w, s);
+    double* dh = P->upload("tab_h", hv, s);
+    lk_tab_interp(nc, dcls, dd, ds, dw, T.nnode, st, tab, p, NC, Ipred, s);
+    lk_sur_err(nc, dcls, st, dh, Ipred, Ich, p, NC, derr, s);
+    std::vector<double> err(nc);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(err.data(), derr, nc * sizeof(double), hipMemcpyDeviceToHost));
+    for (int c = 0; c < nc; c++) {
+      worst[cb[c]] = std::max(worst[cb[c]], err[c]);
+      all.push_back(err[c]);
+    }
+  }
+  for (size_t c = 0; c < worst.size(); c++)
+    if (worst[c] >= 0.0) T.bound[c] = 2.0 * worst[c];
+  if (!all.empty()) {
+    std::sort(all.begin(), all.end());
+    R.err_median = all[all.size() / 2];
+    R.err_max = all.back();
+  }
+  R.ms_validate = wall() - t0;
+  for (const char* nm : {"tab_Ich", "tab_Ipred", "tab_err"}) {
+    auto it = P->bufs.find(nm);
+    if (it != P->bufs.end()) {
+      if (it->second.p) (void)hipFree(it->second.p);
+      P->bufs.erase(it);
+    }
+  }
+  T.rep = R;
+  T.version++;
+  T.ready = true;
 }
 
 struct Group {
@@ -1406,22 +1649,32 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     opse.resize(2 * (size_t)nops, 0);
     d_opsc = P->upload("op_scale", opse, s2);
   }
-  // gate: classes whose combination the surrogate predicts within the tolerance
-  // take the network's integrals, the others the quadrature's
-  std::vector<ClassDesc> qcls, scls;
-  std::vector<int> sC;
-  std::vector<double> sH, sD;
+  // gates: classes whose combination the pre-computed tables, else the surrogate,
+  // give within its tolerance take those integrals, the others the quadrature's
+  std::vector<ClassDesc> qcls, scls, tcls;
+  std::vector<int> sC, tSlot;
+  std::vector<double> sH, sD, tW, tD;
   const bool use_sur = P->sur.ready && P->sur.tol > 0.0 && !classes.empty();
-  if (use_sur) {
+  const bool use_tab = P->tab.ready && P->tab.tol > 0.0 && !classes.empty();
+  if (use_sur || use_tab) {
     const Surrogate& S = P->sur;
+    const OpTables& T = P->tab;
     for (size_t c = 0; c < classes.size(); c++) {
       const ClassDesc& C = classes[c];
       const int comp = sur_comp(P, C.lt, C.a, C.ls, C.b);
       const int j = cls_meta[c].x, i = cls_meta[c].y, ri = cls_meta[c].z;
       const double h = cls_h[c];
-      if (comp >= 0 && h >= S.h_lo && h <= S.h_hi && S.bound[sur_combo(comp, j, i, ri)] <= S.tol) {
+      const int cb = comp >= 0 ? sur_combo(comp, j, i, ri) : -1;
+      if (use_tab && cb >= 0 && h >= T.h_lo && h <= T.h_hi && T.dense[cb] >= 0 && T.bound[cb] <= T.tol) {
+        tcls.push_back(C);
+        const size_t w0 = tW.size();
+        tW.resize(w0 + T.nnode);
+        const int k = tab_weights(T, h, &tW[w0]);
+        tSlot.push_back((T.dense[cb] * T.npanel + k) * T.nnode);
+        tD.push_back(S.Dc[comp]);
+      } else if (use_sur && cb >= 0 && h >= S.h_lo && h <= S.h_hi && S.bound[cb] <= S.tol) {
         scls.push_back(C);
-        sC.push_back(sur_combo(comp, j, i, ri));
+        sC.push_back(cb);
         sH.push_back(h);
         sD.push_back(S.Dc[comp]);
       } else {
@@ -1429,8 +1682,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       }
     }
   }
-  std::vector<ClassDesc>& qref = use_sur ? qcls : classes;
+  std::vector<ClassDesc>& qref = (use_sur || use_tab) ? qcls : classes;
   rep.n_react_surrogate = (int64_t)scls.size();
+  rep.n_react_table = (int64_t)tcls.size();
   // operators of the previous evaluation are kept when the plan asks for it and
   // everything they are generated from is the same (trees, classes, precision,
   // surrogate gate, buffers); a failed evaluation leaves no signature behind
@@ -1441,16 +1695,18 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     app(classes.data(), classes.size() * sizeof(ClassDesc));
     app(rops.data(), rops.size() * sizeof(ROpDesc));
     app(opse.data(), opse.size() * sizeof(int));
-    const int fl[4] = {P->prec, P->prec_parts, (int)scls.size(), P->physical};
+    const int fl[7] = {P->prec, P->prec_parts, (int)scls.size(), P->physical, (int)tcls.size(), P->sur.version,
+                       P->tab.version};
     app(fl, sizeof(fl));
     app(&P->sur.tol, sizeof(double));
+    app(&P->tab.tol, sizeof(double));
     app(&ops, sizeof(ops));
     app(&ops32, sizeof(ops32));
   }
   const bool reuse = P->reuse_ops && P->bufp == &P->bufs && !prev_opsig.empty() && opsig == prev_opsig;
   rep.ops_reused = reuse ? 1 : 0;
   if (reuse) {
-    for (int st_i : {ST_OPS_FREE, ST_REACT_TABLES, ST_REACT_MFMA, ST_REACT_SUR, ST_REACT_EXPAND}) {
+    for (int st_i : {ST_OPS_FREE, ST_REACT_TABLES, ST_REACT_MFMA, ST_REACT_SUR, ST_REACT_TAB, ST_REACT_EXPAND}) {
       sbeg(st_i, s2);
       send(st_i, s2);
     }
@@ -1469,6 +1725,15 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       d_gcombo = P->upload("gate_combo", sC, s2);
       d_gh = P->upload("gate_h", sH, s2);
       d_gd = P->upload("gate_d", sD, s2);
+    }
+    ClassDesc* d_tcls = nullptr;
+    int* d_tslot = nullptr;
+    double *d_tw = nullptr, *d_td = nullptr;
+    if (!tcls.empty()) {
+      d_tcls = P->upload("tab_gcls", tcls, s2);
+      d_tslot = P->upload("tab_gslot", tSlot, s2);
+      d_tw = P->upload("tab_gw", tW, s2);
+      d_td = P->upload("tab_gd", tD, s2);
     }
     double* Iall = classes.empty() ? nullptr : P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
     lk_zero(ops, opsz, s2);  // operator 0: the zero operator
@@ -1501,6 +1766,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
                      Iall, s2);
       }
       send(ST_REACT_SUR, s2);
+      sbeg(ST_REACT_TAB, s2);
+      if (!tcls.empty())
+        lk_tab_interp((int)tcls.size(), d_tcls, d_td, d_tslot, d_tw, P->tab.nnode, st, (const double*)P->tab.tab.p, p,
+                      NC, Iall, s2);
+      send(ST_REACT_TAB, s2);
       sbeg(ST_REACT_EXPAND, s2);
       lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s2);
     } else {
@@ -1509,6 +1779,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       send(ST_REACT_MFMA, s2);
       sbeg(ST_REACT_SUR, s2);
       send(ST_REACT_SUR, s2);
+      sbeg(ST_REACT_TAB, s2);
+      send(ST_REACT_TAB, s2);
       sbeg(ST_REACT_EXPAND, s2);
     }
   }
@@ -2071,6 +2343,7 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   }
   if (plan->jobs_ev) (void)hipEventDestroy(plan->jobs_ev);
   plan->sur.net.release();
+  plan->tab.release();
   delete plan;
 }
 
@@ -2286,6 +2559,7 @@ int lfmm_surrogate_load(lfmm_plan_t* plan, const char* path) {
   S.mu = T.mu;
   S.sd = T.sd;
   memset(&S.trep, 0, sizeof(S.trep));
+  S.version++;
   S.ready = true;
   return LFMM_OK;
 }
@@ -2313,6 +2587,181 @@ int lfmm_surrogate_bounds(const lfmm_plan_t* plan, int n, double* bounds, int* c
           w++;
         }
   *count = w;
+  return LFMM_OK;
+}
+
+int lfmm_tables_build(lfmm_plan_t* plan, const lfmm_table_opts* opts, lfmm_table_report* rep) {
+  if (!plan) return LFMM_EINVAL;
+  if (plan->st.L < 1) return LFMM_EINVAL;
+  lfmm_table_opts o;
+  memset(&o, 0, sizeof(o));
+  if (opts) o = *opts;
+  if (o.h_min <= 0) o.h_min = 0.02;
+  if (o.h_max <= 0) o.h_max = 2.0;
+  if (o.nnode <= 0) o.nnode = 16;
+  if (o.du <= 0) o.du = 1.5;
+  if (o.nval <= 0) o.nval = 4;
+  if (!(o.h_max > o.h_min) || !std::isfinite(o.h_max) || o.nnode < 2 || o.nnode > 32 || o.nval > 32 ||
+      !std::isfinite(o.du))
+    return LFMM_EINVAL;
+  OpTables& T = plan->tab;
+  T.alpha = 4.0 * plan->kmax;
+  const double span = (std::log(o.h_max) + T.alpha * o.h_max) - (std::log(o.h_min) + T.alpha * o.h_min);
+  if (span / o.du > 4096) return LFMM_EINVAL;
+  lfmm_table_report R;
+  try {
+    tab_build_impl(plan, o, R);
+  } catch (Fail& f) {
+    (void)hipStreamSynchronize(plan->s2);
+    T.release();
+    return f.code;
+  }
+  if (rep) *rep = R;
+  return LFMM_OK;
+}
+
+int lfmm_tables_gate(lfmm_plan_t* plan, double tol) {
+  if (!plan || !(tol >= 0.0)) return LFMM_EINVAL;
+  plan->tab.tol = tol;
+  return LFMM_OK;
+}
+
+int lfmm_tables_bounds(const lfmm_plan_t* plan, int n, double* bounds, int* count) {
+  if (!plan || !count || n < 0 || (n > 0 && !bounds)) return LFMM_EINVAL;
+  const OpTables& T = plan->tab;
+  if (!T.ready) {
+    *count = 0;
+    return LFMM_EINVAL;
+  }
+  int w = 0;
+  for (size_t c = 0; c < T.bound.size(); c++)
+    if (T.dense[c] >= 0) {
+      if (w < n) bounds[w] = T.bound[c];
+      w++;
+    }
+  *count = w;
+  return LFMM_OK;
+}
+
+int lfmm_tables_release(lfmm_plan_t* plan) {
+  if (!plan) return LFMM_EINVAL;
+  (void)hipStreamSynchronize(plan->s2);
+  (void)hipDeviceSynchronize();
+  plan->tab.release();
+  plan->tab.version++;
+  return LFMM_OK;
+}
+
+// File: "LFMMTAB1", then int32 {version 1, p, L, ncomp, npanel, nnode, NT * NC, ndense},
+// double k[L+1], d[L], h_lo, h_hi, alpha, u0, du, bound[ncomp*40], then the table
+// (ndense * npanel * nnode matrices of NT * NC complex FP64).
+static const size_t TAB_IO_CHUNK = (size_t)64 << 20;
+int lfmm_tables_save(const lfmm_plan_t* plan, const char* path) {
+  if (!plan || !path || !plan->tab.ready) return LFMM_EINVAL;
+  const OpTables& T = plan->tab;
+  FILE* f = fopen(path, "wb");
+  if (!f) return LFMM_EIO;
+  const int L = plan->st.L;
+  const int32_t hd[8] = {1, plan->p, L, plan->sur.ncomp, T.npanel, T.nnode, plan->NT * plan->NC, T.ndense};
+  const double geo[5] = {T.h_lo, T.h_hi, T.alpha, T.u0, T.du};
+  bool ok = fwrite("LFMMTAB1", 1, 8, f) == 8 && fwrite(hd, sizeof(hd), 1, f) == 1 &&
+            fwrite(plan->st.k, sizeof(double), L + 1, f) == (size_t)(L + 1) &&
+            (L == 0 || fwrite(plan->st.d, sizeof(double), L, f) == (size_t)L) && fwrite(geo, sizeof(geo), 1, f) == 1 &&
+            fwrite(T.bound.data(), sizeof(double), T.bound.size(), f) == T.bound.size();
+  std::vector<char> buf;
+  for (size_t off = 0; ok && off < T.tab.cap; off += TAB_IO_CHUNK) {
+    const size_t nb = std::min(TAB_IO_CHUNK, T.tab.cap - off);
+    buf.resize(nb);
+    ok = hipMemcpy(buf.data(), (const char*)T.tab.p + off, nb, hipMemcpyDeviceToHost) == hipSuccess &&
+         fwrite(buf.data(), 1, nb, f) == nb;
+  }
+  if (fclose(f) != 0) ok = false;
+  return ok ? LFMM_OK : LFMM_EIO;
+}
+
+int lfmm_tables_load(lfmm_plan_t* plan, const char* path) {
+  if (!plan || !path) return LFMM_EINVAL;
+  if (plan->st.L < 1) return LFMM_EINVAL;
+  FILE* f = fopen(path, "rb");
+  if (!f) return LFMM_EIO;
+  const int L = plan->st.L, NL = L + 1;
+  char magic[8];
+  int32_t hd[8];
+  double geo[5];
+  std::vector<double> kk(NL), dd(L);
+  sur_components(plan);
+  const int ncomp = plan->sur.ncomp;
+  int ndense = 0;
+  for (int c = 0; c < ncomp; c++)
+    for (int j = 0; j < 2; j++)
+      for (int i = 0; i < 2; i++)
+        for (int ri = 0; ri < 10; ri++) ndense += !(i == 0 && j == 0 && kR2[ri] <= 2);
+  bool ok = fread(magic, 1, 8, f) == 8 && memcmp(magic, "LFMMTAB1", 8) == 0 && fread(hd, sizeof(hd), 1, f) == 1 &&
+            hd[0] == 1 && hd[1] == plan->p && hd[2] == L && hd[3] == ncomp && hd[4] >= 1 && hd[4] <= 4096 &&
+            hd[5] >= 2 && hd[5] <= 32 && hd[6] == plan->NT * plan->NC && hd[7] == ndense;
+  ok = ok && fread(kk.data(), sizeof(double), NL, f) == (size_t)NL && fread(dd.data(), sizeof(double), L, f) == (size_t)L &&
+       fread(geo, sizeof(geo), 1, f) == 1;
+  for (int i = 0; ok && i < NL; i++) ok = kk[i] == plan->st.k[i];
+  for (int i = 0; ok && i < L; i++) ok = dd[i] == plan->st.d[i];
+  ok = ok && geo[1] > geo[0] && geo[0] > 0 && geo[4] > 0 && geo[2] == 4.0 * plan->kmax;
+  std::vector<double> bound((size_t)ncomp * 40);
+  ok = ok && fread(bound.data(), sizeof(double), bound.size(), f) == bound.size();
+  if (!ok) {
+    fclose(f);
+    return LFMM_EIO;
+  }
+  OpTables& T = plan->tab;
+  (void)hipStreamSynchronize(plan->s2);
+  (void)hipDeviceSynchronize();
+  T.release();
+  const size_t bytes = (size_t)hd[7] * hd[4] * hd[5] * hd[6] * 16;
+  if (hipMalloc(&T.tab.p, bytes) != hipSuccess) {
+    T.tab.p = nullptr;
+    fclose(f);
+    return LFMM_ENOMEM;
+  }
+  T.tab.cap = bytes;
+  std::vector<char> buf;
+  for (size_t off = 0; ok && off < bytes; off += TAB_IO_CHUNK) {
+    const size_t nb = std::min(TAB_IO_CHUNK, bytes - off);
+    buf.resize(nb);
+    ok = fread(buf.data(), 1, nb, f) == nb &&
+         hipMemcpy((char*)T.tab.p + off, buf.data(), nb, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  char extra;
+  ok = ok && fread(&extra, 1, 1, f) == 0;
+  fclose(f);
+  if (ok) {
+    try {
+      sur_decay(plan);
+    } catch (Fail& fl) {
+      T.release();
+      return fl.code;
+    }
+  }
+  if (!ok) {
+    T.release();
+    return LFMM_EIO;
+  }
+  T.h_lo = geo[0];
+  T.h_hi = geo[1];
+  T.alpha = geo[2];
+  T.u0 = geo[3];
+  T.du = geo[4];
+  T.npanel = hd[4];
+  T.nnode = hd[5];
+  T.ndense = hd[7];
+  T.bound = bound;
+  T.dense.assign((size_t)ncomp * 40, -1);
+  int dn = 0;
+  for (int c = 0; c < ncomp; c++)
+    for (int j = 0; j < 2; j++)
+      for (int i = 0; i < 2; i++)
+        for (int ri = 0; ri < 10; ri++)
+          if (!(i == 0 && j == 0 && kR2[ri] <= 2)) T.dense[sur_combo(c, j, i, ri)] = dn++;
+  memset(&T.rep, 0, sizeof(T.rep));
+  T.version++;
+  T.ready = true;
   return LFMM_OK;
 }
 

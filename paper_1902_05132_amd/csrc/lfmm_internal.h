@@ -213,4 +213,8 @@ void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_
 void lk_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
                       const long long* grid_off, int* grid, hipStream_t s);
 void lk_m2l_key_to_group(int n, int* key, hipStream_t s);
+void lk_tab_store(int ncls, const ClassDesc* cls, const double* dadd, const int* slot, Stack st, const double* Iall,
+                  int p, int NC, double* tab, hipStream_t s);
+void lk_tab_interp(int ncls, const ClassDesc* cls, const double* dadd, const int* slot0, const double* w, int nnode,
+                   Stack st, const double* tab, int p, int NC, double* Iall, hipStream_t s);
 }

@@ -414,3 +414,74 @@ extern "C" void lk_sur_features(int n, const int* combo, const double* h, int ni
   const long tot = (long)n * nin;
   if (tot > 0) k_sur_features<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(n, combo, h, nin, c0, lh0, lh1, X);
 }
+
+// ---------------------------------------------------------------------------
+// Pre-computed tables of the reaction M2L integrals (the paper's tabulation of
+// Section 3.5, in the form a uniform tree needs): for every geometry combination
+// the normalised matrix I / env (as above) as a function of t = log h, on panels
+// in t with Chebyshev points of the second kind; an evaluation interpolates it
+// (barycentric formula, weights from the host) and multiplies env back.
+// Table layout: [slot][entry] complex FP64, slot = (combo * npanel + panel) *
+// nnode + node, entry = tix(n, m) NC + idx(n', m').
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tab_store(const ClassDesc* cls, const double* dadd, const int* slot, Stack st,
+                                                   const double* Iall, int p, int NC, double* tab) {
+  const ClassDesc C = cls[blockIdx.y];
+  const int NT = (p + 1) * (p + 2) / 2, nh = NT * NC;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nh) return;
+  const int r = e / NC, c = e % NC;
+  int n, m, n2, m2;
+  sur_row_nm(r, &n, &m);
+  sur_col_nm(c, &n2, &m2);
+  const double env = sur_env(C, dadd[blockIdx.y], st.k[C.lt], st.k[C.ls], n, n2);
+  const double* I = Iall + (size_t)C.out * NC * NC * 2 + 2 * ((size_t)cidx(n, m) * NC + c);
+  double* o = tab + ((size_t)slot[blockIdx.y] * nh + e) * 2;
+  o[0] = I[0] / env;
+  o[1] = I[1] / env;
+}
+extern "C" void lk_tab_store(int ncls, const ClassDesc* cls, const double* dadd, const int* slot, Stack st,
+                             const double* Iall, int p, int NC, double* tab, hipStream_t s) {
+  const int nh = (p + 1) * (p + 2) / 2 * NC;
+  if (ncls > 0) k_tab_store<<<dim3((nh + 255) / 256, ncls), 256, 0, s>>>(cls, dadd, slot, st, Iall, p, NC, tab);
+}
+// Interpolated matrices of the classes into Iall (both the m and the -m rows):
+// class c uses the nnode table slots from slot0[c] on with weights w[c][j] (they sum to 1).
+__global__ __launch_bounds__(256) void k_tab_interp(const ClassDesc* cls, const double* dadd, const int* slot0,
+                                                    const double* w, int nnode, Stack st, const double* tab, int p,
+                                                    int NC, double* Iall) {
+  const ClassDesc C = cls[blockIdx.y];
+  const int NT = (p + 1) * (p + 2) / 2, nh = NT * NC;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nh) return;
+  const int r = e / NC, c = e % NC;
+  int n, m, n2, m2;
+  sur_row_nm(r, &n, &m);
+  sur_col_nm(c, &n2, &m2);
+  const double* wc = w + (size_t)blockIdx.y * nnode;
+  const double* t = tab + ((size_t)slot0[blockIdx.y] * nh + e) * 2;
+  double vr = 0.0, vi = 0.0;
+  for (int j = 0; j < nnode; j++) {
+    const double wj = wc[j];
+    vr += wj * t[(size_t)j * nh * 2];
+    vi += wj * t[(size_t)j * nh * 2 + 1];
+  }
+  const double env = sur_env(C, dadd[blockIdx.y], st.k[C.lt], st.k[C.ls], n, n2);
+  vr *= env;
+  vi *= env;
+  double* out = Iall + (size_t)C.out * NC * NC * 2;
+  const size_t o1 = (size_t)cidx(n, m) * NC + c;
+  out[2 * o1] = vr;
+  out[2 * o1 + 1] = vi;
+  if (m > 0) {
+    const size_t o2 = (size_t)cidx(n, -m) * NC + cidx(n2, -m2);
+    out[2 * o2] = vr;
+    out[2 * o2 + 1] = vi;
+  }
+}
+extern "C" void lk_tab_interp(int ncls, const ClassDesc* cls, const double* dadd, const int* slot0, const double* w,
+                              int nnode, Stack st, const double* tab, int p, int NC, double* Iall, hipStream_t s) {
+  const int nh = (p + 1) * (p + 2) / 2 * NC;
+  if (ncls > 0)
+    k_tab_interp<<<dim3((nh + 255) / 256, ncls), 256, 0, s>>>(cls, dadd, slot0, w, nnode, st, tab, p, NC, Iall);
+}

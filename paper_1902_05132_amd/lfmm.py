@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblfmm.so")
 
 LFMM_OK = 0
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "not supported",
-           5: "surrogate file error"}
+           5: "surrogate or table file error"}
 
 
 class LfmmError(RuntimeError):
@@ -36,7 +36,8 @@ class Report(ctypes.Structure):
                 ("m2l_slots", ctypes.c_int64), ("m2m_pairs", ctypes.c_int64), ("l2l_pairs", ctypes.c_int64),
                 ("p2p_pairs", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
                 ("p2p_series", ctypes.c_int), ("precision", ctypes.c_int),
-                ("stage_ms", ctypes.c_double * 16), ("n_react_surrogate", ctypes.c_int64), ("ops_reused", ctypes.c_int)]
+                ("stage_ms", ctypes.c_double * 24), ("n_react_surrogate", ctypes.c_int64), ("ops_reused", ctypes.c_int),
+                ("n_react_table", ctypes.c_int64)]
 
 
 class TuneReport(ctypes.Structure):
@@ -57,6 +58,18 @@ class TrainReport(ctypes.Structure):
                 ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
                 ("err_median", ctypes.c_double), ("err_max", ctypes.c_double),
                 ("ms_labels", ctypes.c_double), ("ms_train", ctypes.c_double)]
+
+
+class TableOpts(ctypes.Structure):
+    _fields_ = [("h_min", ctypes.c_double), ("h_max", ctypes.c_double), ("nnode", ctypes.c_int),
+                ("du", ctypes.c_double), ("nval", ctypes.c_int)]
+
+
+class TableReport(ctypes.Structure):
+    _fields_ = [("n_combos", ctypes.c_int), ("npanel", ctypes.c_int), ("nnode", ctypes.c_int),
+                ("n_slots", ctypes.c_int64), ("n_validation", ctypes.c_int64), ("bytes", ctypes.c_int64),
+                ("err_median", ctypes.c_double), ("err_max", ctypes.c_double),
+                ("ms_build", ctypes.c_double), ("ms_validate", ctypes.c_double)]
 
 
 _lib = None
@@ -106,6 +119,12 @@ def load():
     L.lfmm_surrogate_load.argtypes = [vp, ctypes.c_char_p]
     L.lfmm_surrogate_gate.argtypes = [vp, ctypes.c_double]
     L.lfmm_surrogate_bounds.argtypes = [vp, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int)]
+    L.lfmm_tables_build.argtypes = [vp, ctypes.POINTER(TableOpts), ctypes.POINTER(TableReport)]
+    L.lfmm_tables_gate.argtypes = [vp, ctypes.c_double]
+    L.lfmm_tables_bounds.argtypes = [vp, ctypes.c_int, _D, ctypes.POINTER(ctypes.c_int)]
+    L.lfmm_tables_release.argtypes = [vp]
+    L.lfmm_tables_save.argtypes = [vp, ctypes.c_char_p]
+    L.lfmm_tables_load.argtypes = [vp, ctypes.c_char_p]
     _F = ctypes.POINTER(ctypes.c_float)
     L.lfmm_mlp_forward_backward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                             _F, _F, _F, _F, _F, _D]
@@ -240,7 +259,8 @@ class Plan:
                     m2l_pairs=r.m2l_pairs, m2l_slots=r.m2l_slots,
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
                     p2p_series=r.p2p_series, precision=r.precision,
-                    n_react_surrogate=r.n_react_surrogate, ops_reused=r.ops_reused, stage_ms=stages)
+                    n_react_surrogate=r.n_react_surrogate, ops_reused=r.ops_reused,
+                    n_react_table=r.n_react_table, stage_ms=stages)
 
     def autotune(self, xyz, q, phi, layer=None, stream=None):
         """lfmm_autotune on torch device tensors (as eval_device); returns the tuning report."""
@@ -278,6 +298,34 @@ class Plan:
         _check(self.lib.lfmm_surrogate_bounds(self.h, cnt.value, out.ctypes.data_as(_D), ctypes.byref(cnt)),
                "lfmm_surrogate_bounds")
         return out[:cnt.value]
+
+    # ---- pre-computed tables of the reaction integrals ----
+    def tables_build(self, h_min=0.0, h_max=0.0, nnode=0, du=0.0, nval=0):
+        """Tabulate by quadrature and validate (zeros select the library defaults); returns the report."""
+        o = TableOpts(h_min, h_max, nnode, du, nval)
+        r = TableReport()
+        _check(self.lib.lfmm_tables_build(self.h, ctypes.byref(o), ctypes.byref(r)), "lfmm_tables_build")
+        return {f: getattr(r, f) for f, _ in TableReport._fields_}
+
+    def tables_gate(self, tol):
+        _check(self.lib.lfmm_tables_gate(self.h, float(tol)), "lfmm_tables_gate")
+
+    def tables_bounds(self):
+        cnt = ctypes.c_int()
+        _check(self.lib.lfmm_tables_bounds(self.h, 0, None, ctypes.byref(cnt)), "lfmm_tables_bounds")
+        out = np.zeros(max(cnt.value, 1))
+        _check(self.lib.lfmm_tables_bounds(self.h, cnt.value, out.ctypes.data_as(_D), ctypes.byref(cnt)),
+               "lfmm_tables_bounds")
+        return out[:cnt.value]
+
+    def tables_release(self):
+        _check(self.lib.lfmm_tables_release(self.h), "lfmm_tables_release")
+
+    def tables_save(self, path):
+        _check(self.lib.lfmm_tables_save(self.h, os.fsencode(path)), "lfmm_tables_save")
+
+    def tables_load(self, path):
+        _check(self.lib.lfmm_tables_load(self.h, os.fsencode(path)), "lfmm_tables_load")
 
     # ---- component entry points ----
     def translation(self, kind, kw, b):
