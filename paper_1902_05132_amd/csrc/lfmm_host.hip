@@ -579,7 +579,6 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     std::vector<double> G = gaunt_table(p);
     HIPCHK(hipMalloc(&P->d_gaunt, G.size() * sizeof(double)));
     HIPCHK(hipMemcpy(P->d_gaunt, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
-    // 4 x 4 tiles of the reaction integral matrices over the half m > 0 or (m = 0, m' >= 0)
     P->ev_ok = true;
     for (int i = 0; i < ST_COUNT; i++)
       if (hipEventCreate(&P->evb[i]) != hipSuccess || hipEventCreate(&P->eve[i]) != hipSuccess) P->ev_ok = false;
@@ -610,7 +609,7 @@ struct RIPrep {
   RGDesc* rgs = nullptr;
   SCDesc* scs = nullptr;
   int* mem = nullptr;
-  double *J = nullptr, *Pt = nullptr, *F = nullptr;
+  double *J = nullptr, *Pt = nullptr, *F = nullptr, *Lt = nullptr;
   int nrg = 0, ncls = 0, nsc = 0, nwg = 0, Ntot = 0, maxnn = 0;
 };
 static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDesc>& classes, hipStream_t up) {
@@ -685,6 +684,9 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
   R.J = P->dev<double>((t + "_J").c_str(), (size_t)Ntot * (Q + 1) * 2);
   R.Pt = P->dev<double>((t + "_P").c_str(), (size_t)NL * Ntot * NT * 2);
   R.F = P->dev<double>((t + "_F").c_str(), (size_t)Ftot * 2);
+  // stacks deeper than the specialised density kernels: the layer recursions once
+  // per node (6 quantities per layer), shared by every class on that node
+  if (P->st.L > 4) R.Lt = P->dev<double>((t + "_Lt").c_str(), (size_t)6 * NL * Ntot * 2);
   R.nrg = (int)rgs.size();
   R.ncls = (int)classes.size();
   R.nsc = (int)scs.size();
@@ -696,8 +698,8 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
 static void reaction_launch(lfmm_plan_s* P, const RIPrep& R, double* Iall, hipStream_t s,
                             const std::function<void()>& after_tables = nullptr) {
   if (!R.ncls) return;
-  lk_react_tables(R.nrg, R.rgs, R.Ntot, P->st, P->p, R.J, R.Pt, s);
-  lk_react_F(R.ncls, R.cls, R.maxnn, P->st, R.F, s);
+  lk_react_tables(R.nrg, R.rgs, R.Ntot, P->st, P->p, R.J, R.Pt, R.Lt, s);
+  lk_react_F(R.ncls, R.cls, R.maxnn, P->st, R.Ntot, R.Lt, R.F, s);
   if (after_tables) after_tables();
   lk_react_mfma(R.nwg, R.nsc, R.scs, R.mem, R.cls, P->p, R.Ntot, R.J, R.Pt, R.F, Iall, P->NC, s);
 }

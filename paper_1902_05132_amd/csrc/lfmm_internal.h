@@ -136,9 +136,12 @@ void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const 
                double* py, double* pz, double* pq, hipStream_t s);
 void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS, const double* gaunt,
                 float* ops32, const int* opse, hipStream_t s);
+// Ltab != nullptr (stacks with more than four interfaces): per-node layer tables,
+// 6 (L + 1) Ntot complex, from which k_react_F assembles the densities.
 void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, int p, double* Jtab, double* Ptab,
-                     hipStream_t s);
-void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, double* Ftab, hipStream_t s);
+                     double* Ltab, hipStream_t s);
+void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, int Ntot, const double* Ltab, double* Ftab,
+                hipStream_t s);
 void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p, int Ntot,
                    const double* Jtab, const double* Ptab, const double* Ftab, double* Iout, int NC, hipStream_t s);
 void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p, int NC,

@@ -596,11 +596,69 @@ extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz,
 //   k_react_F:      F = w k_rho e^{...} sigma_ab / kz_t per class and node;
 //   k_react_mfma:   the node sum as FP64 MFMA products (below).
 // ---------------------------------------------------------------------------
+// Per-node layer quantities of the density recursion (stacks with more than four
+// interfaces, whose densities k_react_F then assembles from them): for every layer
+// m, kz_m, the phase E_m over the layer, the generalised reflections Rd_m (looking
+// down at d_m) and Ru_m (looking up at d_{m-1}), and the generalised transmissions
+// Tu_m (from layer m up into m-1) and Td_m (from m down into m+1), the same
+// expressions as dev_densities_t.  Layout: Ltab[(field * (L + 1) + m) * Ntot + node],
+// fields LT_KZ, LT_E, LT_RD, LT_RU, LT_TU, LT_TD (zero where a quantity does not exist).
+enum { LT_KZ, LT_E, LT_RD, LT_RU, LT_TU, LT_TD, LT_NF };
+__device__ void layer_tables_node(const Stack& st, cd kr, int Ntot, int g, cd* Lt) {
+  const int L = st.L, NLm = L + 1;
+  auto at = [&](int f, int m) -> cd& { return Lt[((size_t)f * NLm + m) * Ntot + g]; };
+  const cd kr2 = kr * kr, zero = mk(0, 0), one = mk(1, 0);
+  auto kzf = [&](int m) { return csqrtd(mk(st.k[m] * st.k[m], 0) - kr2); };
+  auto Ef = [&](int m, cd kz) {
+    return (m >= 1 && m <= L - 1) ? cexpd(cmul_i(kz * (st.d[m - 1] - st.d[m]))) : zero;
+  };
+  for (int m = 0; m <= L; m++) {
+    const cd kz = kzf(m);
+    at(LT_KZ, m) = kz;
+    at(LT_E, m) = Ef(m, kz);
+  }
+  // looking down: m = L-1 .. 0 from the layer below
+  at(LT_RD, L) = zero;
+  at(LT_TD, L) = zero;
+  {
+    cd kzn = kzf(L), an = st.k[L] * kzn, Rdn = zero, En = zero;
+    for (int m = L - 1; m >= 0; m--) {
+      const cd kz = kzf(m), a = st.k[m] * kz;
+      const cd r = (a - an) / (a + an);
+      const cd rho = (m + 1 <= L - 1) ? Rdn * En * En : zero;
+      const cd Rd = (r + rho) / (one + r * rho);
+      at(LT_RD, m) = Rd;
+      at(LT_TD, m) = (kzn / kz) * (one + r) / (one + r * rho);
+      kzn = kz;
+      an = a;
+      Rdn = Rd;
+      En = Ef(m, kz);
+    }
+  }
+  // looking up: m = 1 .. L from the layer above
+  at(LT_RU, 0) = zero;
+  at(LT_TU, 0) = zero;
+  {
+    cd kzp = kzf(0), ap = st.k[0] * kzp, Rup = zero, Ep = zero;
+    for (int m = 1; m <= L; m++) {
+      const cd kz = kzf(m), a = st.k[m] * kz;
+      const cd r = (a - ap) / (a + ap);
+      const cd rho = (m - 1 >= 1) ? Rup * Ep * Ep : zero;
+      const cd Ru = (r + rho) / (one + r * rho);
+      at(LT_RU, m) = Ru;
+      at(LT_TU, m) = (kzp / kz) * (one + r) / (one + r * rho);
+      kzp = kz;
+      ap = a;
+      Rup = Ru;
+      Ep = Ef(m, kz);
+    }
+  }
+}
 __global__ __launch_bounds__(256) void k_react_tables(const RGDesc* rgs, int nrg, int Ntot, Stack st, int p,
-                                                      cd* Jtab, cd* Ptab) {
+                                                      cd* Jtab, cd* Ptab, cd* Ltab) {
   const int NL = st.L + 1, Q = 2 * p, NT = (p + 1) * (p + 2) / 2;
   long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (t >= (long long)(NL + 1) * Ntot) return;
+  if (t >= (long long)(NL + (Ltab ? 2 : 1)) * Ntot) return;
   int kind = (int)(t / Ntot), g = (int)(t % Ntot);
   int lo = 0, hi = nrg - 1;  // rule group holding global node g
   while (lo < hi) {
@@ -613,6 +671,8 @@ __global__ __launch_bounds__(256) void k_react_tables(const RGDesc* rgs, int nrg
   rule_node(R.rule, g - R.off, c_glx, c_glw, &kr, &w);
   if (kind == 0) {
     dev_besselJ(Q, kr * R.rho, Jtab + (size_t)g * (Q + 1), 1);
+  } else if (kind == NL + 1) {
+    layer_tables_node(st, kr, Ntot, g, Ltab);
   } else {
     int l = kind - 1;
     double kl = st.k[l];
@@ -636,6 +696,48 @@ __global__ __launch_bounds__(256) void k_react_F(const ClassDesc* cls, Stack st,
   // with the near field
   cd sig[2][2], sab = mk(0, 0);
   dev_densities_t<LL>(st, kr, C.lt, C.ls, sig, C.a, C.b, &sab);
+  cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
+  Ftab[C.f_off + node] = w * kr * ex * sab / kzt;
+}
+// k_react_F for stacks with more than four interfaces: the density of the class's
+// component from the per-node layer tables (closure in the source layer, then the
+// generalised transmissions to the target layer), the same steps as
+// dev_densities_t without repeating the recursions for every class of a node.
+__global__ __launch_bounds__(256) void k_react_F_lt(const ClassDesc* cls, Stack st, int Ntot, const cd* Lt,
+                                                    cd* Ftab) {
+  const ClassDesc C = cls[blockIdx.y];
+  int node = blockIdx.x * 256 + threadIdx.x;
+  if (node >= rule_nodes(C.rule)) return;
+  cd kr, w;
+  rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
+  const int L = st.L, NLm = L + 1, g = C.rg_off + node, l = C.lt, lp = C.ls;
+  auto at = [&](int f, int m) { return Lt[((size_t)f * NLm + m) * Ntot + g]; };
+  const cd zero = mk(0, 0), one = mk(1, 0);
+  const cd kzt = at(LT_KZ, l), kzs = at(LT_KZ, lp);
+  const cd Rb = (lp <= L - 1) ? at(LT_RD, lp) : zero, Rt = (lp >= 1) ? at(LT_RU, lp) : zero;
+  const cd Ep = (lp >= 1 && lp <= L - 1) ? at(LT_E, lp) : zero;
+  const cd Delta = one - Rb * Rt * Ep * Ep;
+  const cd Xb = (C.b == 0) ? one : zero, Xt = (C.b == 1) ? one : zero;
+  const cd U = Rb * (Xb + Ep * Rt * Xt) / Delta, D = Rt * (Xt + Ep * Rb * Xb) / Delta;
+  cd Ul = U, Dl = D;
+  if (l < lp) {
+    cd Um = Xt + ((lp <= L - 1) ? Ep * U : zero);
+    for (int m = lp; m > l; m--) {
+      Um = at(LT_TU, m) * Um;
+      if (m - 1 > l) Um = at(LT_E, m - 1) * Um;
+    }
+    Ul = Um;
+    Dl = (l >= 1) ? at(LT_RU, l) * at(LT_E, l) * Ul : zero;
+  } else if (l > lp) {
+    cd Dm = Xb + ((lp >= 1) ? Ep * D : zero);
+    for (int m = lp; m < l; m++) {
+      Dm = at(LT_TD, m) * Dm;
+      if (m + 1 < l) Dm = at(LT_E, m + 1) * Dm;
+    }
+    Dl = Dm;
+    Ul = (l <= L - 1) ? at(LT_RD, l) * at(LT_E, l) * Dl : zero;
+  }
+  const cd sab = (C.a == 0) ? ((l <= L - 1) ? Ul : zero) : ((l >= 1) ? Dl : zero);
   cd ex = cexpd(cmul_i(kzt * C.zt + kzs * C.zs));
   Ftab[C.f_off + node] = w * kr * ex * sab / kzt;
 }
@@ -807,13 +909,20 @@ __global__ __launch_bounds__(512) void k_react_mfma(const SCDesc* scs, int nsc, 
   }
 }
 extern "C" void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, int p, double* Jtab, double* Ptab,
-                                hipStream_t s) {
-  long long nt = (long long)(st.L + 2) * Ntot;
-  if (nrg && nt) k_react_tables<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(rgs, nrg, Ntot, st, p, (cd*)Jtab, (cd*)Ptab);
+                                double* Ltab, hipStream_t s) {
+  long long nt = (long long)(st.L + (Ltab ? 3 : 2)) * Ntot;
+  if (nrg && nt)
+    k_react_tables<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(rgs, nrg, Ntot, st, p, (cd*)Jtab, (cd*)Ptab,
+                                                                (cd*)Ltab);
 }
-extern "C" void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, double* Ftab, hipStream_t s) {
+extern "C" void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, int Ntot, const double* Ltab,
+                           double* Ftab, hipStream_t s) {
   if (!ncls || !maxnn) return;
   dim3 g((maxnn + 255) / 256, ncls);
+  if (Ltab) {
+    k_react_F_lt<<<g, 256, 0, s>>>(cls, st, Ntot, (const cd*)Ltab, (cd*)Ftab);
+    return;
+  }
   switch (st.L) {
     case 1: k_react_F<1><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
     case 2: k_react_F<2><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;

@@ -139,3 +139,19 @@ def config5(n=16777216, seed=5, clusters=8, sigma=0.05, gap=0.05, p=10, leaf=64)
     return dict(d=d, k=np.array(FIVE_LAYER_K), x=np.concatenate(xs), y=np.concatenate(ys), z=np.concatenate(zs),
                 layer=np.concatenate(ls), q=q.astype(np.complex128), p=p, leaf=leaf,
                 name="5-layer Gaussian clusters, N=%d, p=%d, leaf<=%d" % (nt, p, leaf))
+
+
+# Ten interfaces, eleven layers 0.6 thick (the paper expects L of about 10 in
+# practice, Section 5); wavenumbers rising with depth.
+TEN_LAYER_D = tuple(-0.6 * i for i in range(10))
+TEN_LAYER_K = tuple(0.5 + 0.25 * i for i in range(11))
+TEN_LAYER_CENTERS = (0.3,) + tuple(-0.3 - 0.6 * i for i in range(9)) + (-5.7,)
+
+
+def ten_layer(n=1048576, seed=10, p=8, leaf=256, side=0.3):
+    """Ten-interface stack: N split evenly over the eleven layers, one cube of side
+    `side` in each, centred in the layer (top and bottom: 0.3 from their interface),
+    so every particle is at least (0.6 - side) / 2 from an interface."""
+    w = layered_cubes(TEN_LAYER_D, TEN_LAYER_K, split_even(n, 11), TEN_LAYER_CENTERS, side=side, seed=seed)
+    w.update(p=p, leaf=leaf, name="10-interface cubes, N=%d, p=%d, leaf<=%d" % (n, p, leaf))
+    return w

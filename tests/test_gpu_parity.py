@@ -207,6 +207,12 @@ def test_five_layer_fmm():
     _check_fmm(w, p=4, leaf=10)
 
 
+def test_ten_interface_fmm():
+    """Ten interfaces, eleven layers: 400 reaction components, against the oracle's FMM."""
+    w = W.ten_layer(n=330, seed=31, p=4, leaf=10)
+    _check_fmm(w, p=4, leaf=10)
+
+
 def test_separate_targets():
     """Targets apart from the sources (every layer, one on a source position):
     against the oracle's FMM on the union with zero target charges (same trees,
