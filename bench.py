@@ -34,6 +34,7 @@ PEAK = {("mfma", 64): 78.6, ("mfma", 32): 157.3, ("alu", 64): 78.6, ("alu", 32):
 P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}
 TOL_MIXED = 1e-6  # the mixed path is the headline only if it stays this close to the FP64 path
 TABLE_H = (0.03, 1.0)  # box sizes the tables cover (every level of the bench workload's trees)
+TEN_TABLE_H = (0.025, 0.25)  # the same for the ten-interface workload
 KERNEL_SRC = os.path.join(ROOT, "paper_1902_05132_amd", "csrc", "lfmm_kernels.hip")
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "m2l_p2p_react_kernels_hbm_counters_3layer_N1M_p8_leaf256.txt")
 
@@ -205,6 +206,53 @@ def tables_leg(args, w, xyz, q, stream, plain, lfmm, torch):
     return res
 
 
+def ten_interface_leg(args, lfmm, W, torch, dev, stream):
+    """Layer-count scaling: the ten-interface stack (400 reaction components) at the
+    bench size, both precisions, with the reaction integrals by quadrature and from
+    pre-computed tables (built once, reported, not timed)."""
+    w = W.ten_layer(n=args.n, seed=args.seed, p=args.p, leaf=args.leaf)
+    n = len(w["x"])
+    xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+    q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+    phi = torch.empty_like(q)
+    res = {"workload": w["name"]}
+    ref = None
+    for source in ("quadrature", "tables"):
+        for precision in (0, 1):
+            plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision)
+            if source == "tables":
+                t0 = time.perf_counter()
+                tr = plan.tables_build(h_min=TEN_TABLE_H[0], h_max=TEN_TABLE_H[1])
+                res["tables_build"] = {"seconds": time.perf_counter() - t0, "bytes": tr["bytes"],
+                                       "combinations": tr["n_combos"], "validation_err_max": tr["err_max"],
+                                       "h_range": list(TEN_TABLE_H)}
+                plan.tables_gate(1e300)
+            for i in range(args.warmup):
+                plan.eval_device(xyz, q, phi, stream=stream)
+            torch.cuda.synchronize()
+            acc = {}
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                plan.eval_device(xyz, q, phi, stream=stream)
+                rep = plan.report()
+                for kname, v in rep["stage_ms"].items():
+                    acc[kname] = acc.get(kname, 0.0) + v
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+            plan.close()
+            if ref is None:
+                ref = phi.clone()
+            err2 = float(torch.linalg.vector_norm(phi - ref) / torch.linalg.vector_norm(ref))
+            name = "%s_%s" % (source, "fp64" if precision == 0 else "mixed")
+            res[name] = {"ms_per_step": ms, "value": n / (ms / 1000.0), "err2_vs_fp64_quadrature": err2,
+                         "classes": rep["n_react_classes"], "class_nodes": rep["n_react_nodes"],
+                         "reaction_operators": rep["n_ops_react"],
+                         "stages_ms": {k: v / args.steps for k, v in acc.items()}}
+            log("bench: ten interfaces, %s %s: %.3f ms/step, Err2 vs FP64 quadrature %.2e"
+                % (source, "FP64" if precision == 0 else "mixed", ms, err2))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--no-tables", action="store_true", help="skip the pre-computed-tables leg")
+    ap.add_argument("--ten-interface", action="store_true",
+                    help="also time the ten-interface workload (needs about 60 GB of device memory)")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
     ap.add_argument("--scaling", action="store_true",
                     help="also time N = 2^17 .. 2^21 of the same workload (both precisions), to show O(N) cost")
@@ -338,6 +388,8 @@ def main():
         out["tables"] = tables_leg(args, w, xyz, q, stream, plain, lfmm, torch)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch)
+    if args.ten_interface:
+        out["ten_interface"] = ten_interface_leg(args, lfmm, W, torch, dev, stream)
     if args.scaling:
         rows = []
         for n2 in (1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21):

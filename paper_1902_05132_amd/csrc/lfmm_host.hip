@@ -375,6 +375,8 @@ struct lfmm_plan_s {
   hipEvent_t jobs_ev = nullptr;
   Surrogate sur;
   OpTables tab;
+  std::vector<int> rop_idx;       // reaction operator of each (trees, level, heights, offset) key
+  std::vector<size_t> rop_dirty;  // keys the last evaluation set
 
   // device workspace in use: the plan's own, or one lent by a batch worker
   std::map<std::string, DevBuf>* bufp = &bufs;
@@ -1577,8 +1579,16 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   std::vector<int4> cls_meta;  // (j, i, r2 class) of each class
   std::vector<double> cls_h;   // its box size
   std::vector<ROpDesc> rops;
-  // rop index: [tt][ts][l][j][i][dx+3][dy+3] (0 = the zero operator)
-  std::vector<int> rop_id((size_t)ntrees * ntrees * 9 * 2 * 2 * 49, 0);
+  // rop index: [tt][ts][l][j][i][dx+3][dy+3] (0 = the zero operator); kept by the
+  // plan, and only the entries the previous evaluation wrote are cleared
+  const size_t nrop_keys = (size_t)ntrees * ntrees * 9 * 2 * 2 * 49;
+  if (P->rop_idx.size() < nrop_keys) {
+    P->rop_idx.assign(nrop_keys, 0);
+    P->rop_dirty.clear();
+  }
+  for (size_t k : P->rop_dirty) P->rop_idx[k] = 0;
+  P->rop_dirty.clear();
+  std::vector<int>& rop_id = P->rop_idx;
   auto rkey = [&](int tt, int ts, int l, int j, int i, int dx, int dy) {
     return (((((size_t)tt * ntrees + ts) * 9 + l) * 2 + j) * 2 + i) * 49 + (size_t)(dx + 3) * 7 + (dy + 3);
   };
@@ -1632,6 +1642,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
                       set_opsc(nops, scl(tt, lv), scl(ts, lv));
                       R.op = nops++;
                       rop_id[rkey(tt, ts, lv, j, i, dx, dy)] = R.op;
+                      P->rop_dirty.push_back(rkey(tt, ts, lv, j, i, dx, dy));
                       rops.push_back(R);
                     }
                 }
@@ -1691,7 +1702,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // everything they are generated from is the same (trees, classes, precision,
   // surrogate gate, buffers); a failed evaluation leaves no signature behind
   std::string opsig;
-  {
+  if (P->reuse_ops) {
     auto app = [&](const void* q, size_t nb) { opsig.append((const char*)q, nb); };
     app(fops.data(), fops.size() * sizeof(OpDesc));
     app(classes.data(), classes.size() * sizeof(ClassDesc));
