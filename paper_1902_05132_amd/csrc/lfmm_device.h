@@ -495,9 +495,11 @@ __device__ __forceinline__ void dev_densities(const Stack& st, cd kr, int l, int
 // ---------------------------------------------------------------------------
 #define LFMM_NGL 16
 #define LFMM_NP1 2
+// Far panels: the first kg grow geometrically from width hf by the factor g (panel
+// k is hf g^k wide), the rest are wmax wide; kg = 0 gives equal panels of width hf.
 struct Rule {
-  double b, T0, hn, hf;
-  int nnear, nfar;
+  double b, T0, hn, hf, g, wmax;
+  int nnear, nfar, kg, pad;
 };
 __host__ __device__ __forceinline__ int rule_nodes(const Rule& r) { return (LFMM_NP1 + r.nnear + r.nfar) * LFMM_NGL; }
 
@@ -515,9 +517,18 @@ __device__ __forceinline__ void rule_node(const Rule& r, int i, const double* gl
   if (pnl < r.nnear) {
     h = r.hn;
     t0 = pnl * h;
-  } else {
+  } else if (r.kg == 0) {
     h = r.hf;
     t0 = r.T0 + (pnl - r.nnear) * h;
+  } else {
+    const int k = pnl - r.nnear, kk = k < r.kg ? k : r.kg;
+    double gk = 1.0, sum = 0.0;  // g^kk and 1 + g + ... + g^(kk-1)
+    for (int j = 0; j < kk; j++) {
+      sum += gk;
+      gk *= r.g;
+    }
+    t0 = r.T0 + r.hf * sum + (k - kk) * r.wmax;
+    h = k < r.kg ? r.hf * gk : r.wmax;
   }
   *kr = mk(t0 + 0.5 * h * (1.0 + x), -r.b);
   *w = mk(0.5 * h * ww, 0.0);

@@ -359,6 +359,7 @@ struct lfmm_plan_s {
   int p2p_ch;    // near field: sources per LDS tile
   double kmax;
   double far_cap = P_FAR_CAP_DEFAULT;
+  double far_grow = 1.5;  // growth of the far panels beyond the cap (1: none; tuning override LFMM_FAR_GROW)
   double* d_gaunt = nullptr;
   std::map<std::string, DevBuf> bufs;
   std::vector<char> hbuf;
@@ -487,6 +488,7 @@ struct lfmm_plan_s {
   }
   Rule make_rule(double dz, double rho, int npow) const {
     Rule r;
+    memset(&r, 0, sizeof(r));
     r.b = b;
     r.T0 = 0.5 * std::ceil(2.0 * (kmax + 2.0));
     r.hn = 0.5;
@@ -495,11 +497,35 @@ struct lfmm_plan_s {
     double tfar = U / dz;
     // far panels: a few decay lengths of e^{-t dz} wide, at most a fraction of the
     // oscillation period 2 pi / rho of J_q(t rho)
-    double hf = 8.0 / dz;
-    if (rho > 0.0) hf = std::min(hf, 7.0 / rho);
-    hf = std::min(hf, far_cap);
+    double wlim = 8.0 / dz;
+    if (rho > 0.0) wlim = std::min(wlim, 7.0 / rho);
+    double hf = std::min(wlim, far_cap);
+    r.g = 1.0;
+    if (far_grow > 1.0 && wlim > hf * (1.0 + 1e-12)) {
+      // the cap holds near T0, where the densities' faster-decaying terms (multiple
+      // reflections, e^{-2 t d}) still matter; beyond, only the polynomial and the
+      // exponential remain, and the panels widen geometrically up to wlim
+      r.hf = hf;
+      r.g = far_grow;
+      r.wmax = wlim;
+      double w = hf;
+      while (w < wlim && r.kg < 64) {
+        r.kg++;
+        w *= far_grow;
+      }
+      double t = r.T0, wk = hf;
+      int k = 0;
+      while (t < tfar && k < 100000) {
+        t += (k < r.kg) ? wk : wlim;
+        if (k < r.kg) wk *= far_grow;
+        k++;
+      }
+      r.nfar = std::max(1, k);
+      return r;
+    }
     r.nfar = std::max(1, (int)std::ceil(tfar / hf));
     r.hf = tfar / r.nfar;
+    r.wmax = r.hf;
     return r;
   }
 };
@@ -545,6 +571,7 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     if (v == 1 || v == 2 || v == 4) P->gemm_ks = v;
   }
   if (const char* e = getenv("LFMM_FAR_CAP")) P->far_cap = atof(e);
+  if (const char* e = getenv("LFMM_FAR_GROW")) P->far_grow = atof(e);
   P->b = 0.5;
   P->min_gap = 1e-9;
   P->max_depth = 8;
@@ -618,11 +645,12 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
   RIPrep R;
   if (classes.empty()) return R;
   const int p = P->p, Q = 2 * p, NT = P->NT, NL = P->st.L + 1;
-  std::map<std::tuple<double, double, double, double, int, int, double>, int> key_rg;
+  std::map<std::tuple<double, double, double, double, int, int, double, double, int>, int> key_rg;
   std::vector<RGDesc> rgs;
   int Ntot = 0, Ftot = 0, maxnn = 0;
   for (auto& C : classes) {
-    auto key = std::make_tuple(C.rule.b, C.rule.T0, C.rule.hn, C.rule.hf, C.rule.nnear, C.rule.nfar, C.rho);
+    auto key = std::make_tuple(C.rule.b, C.rule.T0, C.rule.hn, C.rule.hf, C.rule.nnear, C.rule.nfar, C.rho,
+                               C.rule.wmax, C.rule.kg);
     auto it = key_rg.find(key);
     int nn = rule_nodes(C.rule);
     if (it == key_rg.end()) {
