@@ -35,7 +35,8 @@ P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}
 TOL_MIXED = 1e-6  # the mixed path is the headline only if it stays this close to the FP64 path
 TABLE_H = (0.03, 1.0)  # box sizes the tables cover (every level of the bench workload's trees)
 TEN_TABLE_H = (0.025, 0.25)  # the same for the ten-interface workload
-KERNEL_SRC = os.path.join(ROOT, "paper_1902_05132_amd", "csrc", "lfmm_kernels.hip")
+# the kernels' sources: the counter profile is stale once their bytes change
+KERNEL_SRC = [os.path.join(ROOT, "paper_1902_05132_amd", "csrc", f) for f in ("lfmm_kernels.hip", "lfmm_device.h")]
 COUNTER_PROFILE = os.path.join(ROOT, "profiles", "m2l_p2p_react_kernels_hbm_counters_3layer_N1M_p8_leaf256.txt")
 
 
@@ -48,7 +49,7 @@ def profiled_traffic(kernel, n, p, leaf, seed):
     when the profile is for another workload or the kernels changed since."""
     if not os.path.exists(COUNTER_PROFILE):
         return None
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SRC)).hexdigest()
     cfg, src, traffic = {}, None, {}
     for line in open(COUNTER_PROFILE):
         if line.startswith("config "):
