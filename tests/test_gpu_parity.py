@@ -207,6 +207,15 @@ def test_five_layer_fmm():
     _check_fmm(w, p=4, leaf=10)
 
 
+def test_five_interface_fmm():
+    """Five interfaces, the shallowest stack whose densities come from the per-node
+    layer tables (uneven counts per layer), against the oracle's FMM."""
+    d = tuple(-0.6 * i for i in range(5))
+    k = tuple(0.6 + 0.4 * i for i in range(6))
+    w = W.layered_cubes(d, k, [30, 25, 30, 25, 30, 35], (0.3, -0.3, -0.9, -1.5, -2.1, -2.7), side=0.3, seed=41)
+    _check_fmm(w, p=4, leaf=10)
+
+
 def test_ten_interface_fmm():
     """Ten interfaces, eleven layers: 400 reaction components, against the oracle's FMM."""
     w = W.ten_layer(n=330, seed=31, p=4, leaf=10)
