@@ -1997,7 +1997,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // M2L: four waves share each 16-target tile and split its operator sequence
   // (fastest on both shallow and deep trees)
   int ks_m2l = P->gemm_ks > 0 ? P->gemm_ks : 4;
-  build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9, 64);
+  // M2M: the waves of a 16-target tile split each parent's eight child operators
+  // (a level's parents alone give too few 64-target blocks to fill the GPU)
+  static const int ks_m2m = getenv("LFMM_M2M_KS") ? atoi(getenv("LFMM_M2M_KS")) : 4;  // tuning override
+  build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9, 64 / ks_m2m);
   build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9, 64);
   build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1, 64 / ks_m2l);
   int ne_m2m = ng_m2m ? gs_m2m[ng_m2m] : 0, ne_l2l = ng_l2l ? gs_l2l[ng_l2l] : 0,
@@ -2039,7 +2042,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   sbeg(ST_M2M, s);
   for (int lp = Dmax - 1; lp >= 2; lp--)
     if (bc_m2m[lp] > 0)
-      lk_gemm(0, P->NRT, 1, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
+      lk_gemm(0, P->NRT, ks_m2m, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
               NCK, NC, s);
   send(ST_M2M, s);
   // and the reaction operators from here on
