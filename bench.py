@@ -275,7 +275,7 @@ def main():
                     help="also run one 512 MiB device copy (calibrates hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; multi-GPU runs are not part of it (got --gpus %d)"
+        print("bench.py: measures one GPU; runs on several GPUs are not supported (got --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 

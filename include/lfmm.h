@@ -39,7 +39,7 @@ typedef enum {
                        layer id inconsistent with z, particle closer than min_gap to an interface) */
   LFMM_ENOMEM = 2,  /* device or host allocation failed */
   LFMM_EHIP = 3,    /* a HIP runtime call failed */
-  LFMM_ENOTSUP = 4, /* the configuration is outside what this build supports */
+  LFMM_ENOTSUP = 4, /* the configuration is outside what the library supports */
   LFMM_EIO = 5      /* a surrogate or table file could not be read or written, or does not match the plan */
 } lfmm_status;
 
@@ -203,7 +203,7 @@ int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t
  * maps this geometry to the whole matrix (the m >= 0 rows), normalised by the
  * low-frequency size of each entry and per-output statistics.  It stands where the
  * paper uses pre-computed interpolation tables; the quadrature stays the fallback
- * and the judge of every value.  Its weights and activations are BF16 on the matrix
+ * and the reference for every value.  Its weights and activations are BF16 on the matrix
  * cores with FP32 accumulation; the FP32 master weights are trained on the GPU by
  * the library's own forward and backward kernels (mean squared error, Adam).
  *

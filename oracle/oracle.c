@@ -994,8 +994,8 @@ void orc_reaction_me_basis(int L, const double *d, const double *k, int l, int a
 /* Plain FMM (Section 3.4 Algorithm 1 for each reaction component; the classic */
 /* FMM for each free-space component)                                         */
 /* ------------------------------------------------------------------------- */
-/* Tree rule (the paper builds "an adaptive tree by bisection"; this build uses a
- * uniform-depth octree):
+/* Tree rule (the paper builds its trees adaptively, by bisection; the library and
+ * this oracle use uniform-depth octrees):
  *  - free tree of layer l: root = bounding cube of the layer's particles
  *    (centre = bounding-box midpoint, side S = largest extent, S = 1 if zero);
  *  - all reaction trees share one root: x,y as the bounding box of all particles,
