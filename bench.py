@@ -102,7 +102,7 @@ def cpu_fmm_sample(p, leaf, n=12288, seed=2):
     import oracle
     from paper_1902_05132_amd import workloads as W
 
-    w = W.config2(n=n, seed=seed, p=p, leaf=leaf)
+    w = W.three_layer_cubes(n=n, seed=seed, p=p, leaf=leaf)
     t0 = time.perf_counter()
     oracle.fmm(w["d"], w["k"], p, leaf, w["x"], w["y"], w["z"], w["layer"], w["q"])
     dt = time.perf_counter() - t0
@@ -284,7 +284,7 @@ def main():
     from paper_1902_05132_amd import lfmm
     from paper_1902_05132_amd import workloads as W
 
-    w = W.config2(n=args.n, seed=args.seed, p=args.p, leaf=args.leaf)
+    w = W.three_layer_cubes(n=args.n, seed=args.seed, p=args.p, leaf=args.leaf)
     n = len(w["x"])
     log("bench: workload %s" % w["name"])
     dev = torch.device("cuda:0")
@@ -394,7 +394,7 @@ def main():
     if args.scaling:
         rows = []
         for n2 in (1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21):
-            ws = W.config2(n=n2, seed=args.seed, p=args.p, leaf=args.leaf)
+            ws = W.three_layer_cubes(n=n2, seed=args.seed, p=args.p, leaf=args.leaf)
             xs = torch.tensor(np.stack([ws["x"], ws["y"], ws["z"]]), dtype=torch.float64, device=dev).contiguous()
             qq = torch.tensor(ws["q"], dtype=torch.complex128, device=dev)
             ph = torch.empty_like(qq)

@@ -48,14 +48,14 @@ def layered_cubes(d, k, counts, centers, side=1.0, seed=0, shuffle=False):
                 layer=layer, q=q.astype(np.complex128))
 
 
-def config1(seed=1):
+def three_layer_3k(seed=1):
     """Plain FP64 case: 3 layers, 1000 uniform particles per unit cube, p = 5, leaf <= 50."""
     w = layered_cubes(THREE_LAYER_D, THREE_LAYER_K, [1000, 1000, 1000], THREE_LAYER_CENTERS, seed=seed)
     w.update(p=5, leaf=50, name="3-layer cubes, N=3000, p=5, leaf<=50")
     return w
 
 
-def config2(n=1048576, seed=2, p=8, leaf=256):
+def three_layer_cubes(n=1048576, seed=2, p=8, leaf=256):
     """N = 1,048,576 split evenly over the three unit cubes (each 0.1 clear of the
     interfaces), p = 8.  The leaf bound 256 gives depth-4 layer trees (about 85
     particles per leaf), the fastest of the depths this workload allows."""
@@ -72,7 +72,7 @@ def small_three_layer(n_per_layer=100, seed=0, p=4, leaf=16, shuffle=False):
     return w
 
 
-def config3(seed=3, nprob=256, nmin=2048, nmax=65536, p=6, leaf=64):
+def batch_three_layer(seed=3, nprob=256, nmin=2048, nmax=65536, p=6, leaf=64):
     """Batching case: independent three-layer problems, interfaces at 0 and -g with
     g uniform on [1.0, 2.0], k per layer uniform on [0.5, 2.5], N log-uniform on
     [nmin, nmax] split evenly over the layers; uniform particles in the top cube
@@ -102,7 +102,7 @@ FIVE_LAYER_D = (0.0, -0.6, -1.2, -1.8)
 FIVE_LAYER_K = (0.5, 1.2, 2.0, 2.8, 3.0)
 
 
-def config5(n=16777216, seed=5, clusters=8, sigma=0.05, gap=0.05, p=10, leaf=64):
+def five_layer_clusters(n=16777216, seed=5, clusters=8, sigma=0.05, gap=0.05, p=10, leaf=64):
     """Five-layer medium, N split evenly over the layers (remainder to the top); in
     each layer a mixture of `clusters` Gaussian clusters (standard deviation sigma)
     with centres uniform in x, y in [-0.5, 0.5] and z in the layer's admissible band

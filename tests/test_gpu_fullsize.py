@@ -24,7 +24,7 @@ def full():
     import torch
     from paper_1902_05132_amd import lfmm
 
-    w = W.config2()
+    w = W.three_layer_cubes()
     dev = torch.device("cuda:0")
     xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
     q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)

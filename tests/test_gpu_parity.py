@@ -105,9 +105,9 @@ def test_fmm_three_layer_ragged():
     _check_fmm(w, p=5, leaf=9)
 
 
-def test_fmm_config1_full():
+def test_fmm_three_layer_3k_full():
     """Config 1: 3 x 1000 particles, p = 5, leaf <= 50; every target against the oracle FMM."""
-    w = W.config1()
+    w = W.three_layer_3k()
     phi, ref, rep = _check_fmm(w, p=w["p"], leaf=w["leaf"])
     # and against the exact sum on a sample: the FMM truncation error at p = 5
     tg = np.arange(0, len(w["x"]), 97)
@@ -252,7 +252,7 @@ def test_batch_matches_single_and_oracle():
     the smallest problem matches the oracle's FMM (same trees, 1e-10)."""
     import torch
     lf = _lfmm()
-    probs = W.config3(seed=5, nprob=12, nmin=1500, nmax=6000)
+    probs = W.batch_three_layer(seed=5, nprob=12, nmin=1500, nmax=6000)
     dev = torch.device("cuda")
     plans, xyzs, qs, phis, singles = [], [], [], [], []
     for w in probs:
@@ -310,7 +310,7 @@ def test_reaction_near_field_only():
 def test_five_layer_clustered():
     """The five-layer Gaussian-cluster workload (its recipe, N = 5000, p = 5):
     clustered particles 0.05 from the interfaces give uneven, deeper trees."""
-    w = W.config5(n=5000, p=5, leaf=64)
+    w = W.five_layer_clusters(n=5000, p=5, leaf=64)
     phi, ref, rep = _check_fmm(w, p=5, leaf=64)
     assert rep["reaction_depth"] >= 5
 

@@ -28,8 +28,8 @@ def _both(w, p, leaf):
     return e2, emax
 
 
-def test_mixed_precision_config1():
-    w = W.config1()
+def test_mixed_precision_three_layer_3k():
+    w = W.three_layer_3k()
     e2, emax = _both(w, w["p"], w["leaf"])
     print("config 1 mixed vs FP64: Err2 %.2e Errmax %.2e" % (e2, emax))
     assert e2 < TOL_MIXED and emax < TOL_MIXED

@@ -73,11 +73,11 @@ def test_mlp_kernels_match_oracle(B, nin, width, nh, nout):
 @pytest.fixture(scope="module")
 def trained(tmp_path_factory):
     lf = _lfmm()
-    w = W.config1()
+    w = W.three_layer_3k()
     P = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], profile=True)
     rep = P.surrogate_train(seed=7)
     print("training report:", rep)
-    path = str(tmp_path_factory.mktemp("surrogate") / "config1_p5.bin")
+    path = str(tmp_path_factory.mktemp("surrogate") / "three_layer_3k_p5.bin")
     P.surrogate_save(path)
     ref = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], profile=True)
     phi_ref = ref.eval_torch(w["x"], w["y"], w["z"], w["q"])

@@ -43,7 +43,7 @@ def _eval(P, w):
 @pytest.fixture(scope="module")
 def built():
     lf = _lfmm()
-    w = W.config1()
+    w = W.three_layer_3k()
     P = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], profile=True)
     rep = P.tables_build(h_min=H_RANGE[0], h_max=H_RANGE[1])
     print("table report:", rep)
