@@ -33,6 +33,7 @@ PEAK = {("mfma", 64): 78.6, ("mfma", 32): 157.3, ("alu", 64): 78.6, ("alu", 32):
 # -(kr)^2 (1), series (6 + 6 fma), -cos(kr)/(kr) (2), complex multiply-add (8) = 50.
 P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}
 TOL_MIXED = 1e-6  # the mixed path is the headline only if it stays this close to the FP64 path
+MIXED_QUAD_TOL = 1e-10
 TABLE_H = (0.03, 1.0)  # box sizes the tables cover (every level of the bench workload's trees)
 TEN_TABLE_H = (0.025, 0.25)  # the same for the ten-interface workload
 # the kernels' sources: the counter profile is stale once their bytes change
@@ -116,7 +117,8 @@ def surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch):
     would be built once per medium), then timed with the gate at the 1e-6 target
     and with the gate open, each against the plain FP64 path."""
     n = len(w["x"])
-    plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=1)
+    plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=1,
+                     quad_tol=args.mixed_quad_tol)
     t0 = time.perf_counter()
     tr = plan.surrogate_train(seed=4)
     t_train = time.perf_counter() - t0
@@ -165,7 +167,8 @@ def tables_leg(args, w, xyz, q, stream, plain, lfmm, torch):
     res = {}
     phi = torch.empty(n, dtype=torch.complex128, device=xyz.device)
     for precision in (0, 1):
-        plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision)
+        plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision,
+                         quad_tol=args.mixed_quad_tol if precision else 0.0)
         t0 = time.perf_counter()
         tr = plan.tables_build(h_min=TABLE_H[0], h_max=TABLE_H[1])
         t_build = time.perf_counter() - t0
@@ -220,7 +223,8 @@ def ten_interface_leg(args, lfmm, W, torch, dev, stream):
     ref = None
     for source in ("quadrature", "tables"):
         for precision in (0, 1):
-            plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision)
+            plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision,
+                             quad_tol=args.mixed_quad_tol if precision else 0.0)
             if source == "tables":
                 t0 = time.perf_counter()
                 tr = plan.tables_build(h_min=TEN_TABLE_H[0], h_max=TEN_TABLE_H[1])
@@ -257,8 +261,8 @@ def ten_interface_leg(args, lfmm, W, torch, dev, stream):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1048576)
     ap.add_argument("--p", type=int, default=8)
     ap.add_argument("--leaf", type=int, default=256)
@@ -266,6 +270,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--no-tables", action="store_true", help="skip the pre-computed-tables leg")
+    # the mixed path's contour ends where the integrands' envelope has fallen to 1e-10
+    # (its error, about 5e-13, is four orders below the FP32 parts' 1.75e-7); the FP64
+    # path keeps the library default e^-40
+    ap.add_argument("--mixed-quad-tol", type=float, default=MIXED_QUAD_TOL,
+                    help="contour truncation of the mixed path (0: the library default)")
     ap.add_argument("--ten-interface", action="store_true",
                     help="also time the ten-interface workload (needs about 60 GB of device memory)")
     ap.add_argument("--stages", action="store_true", help="print per-stage times to stderr")
@@ -296,7 +305,8 @@ def main():
 
     def run(precision):
         phi = torch.empty(n, dtype=torch.complex128, device=dev)
-        plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision)
+        plan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=precision,
+                         quad_tol=args.mixed_quad_tol if precision else 0.0)
         for i in range(args.warmup):
             plan.eval_device(xyz, q, phi, stream=stream)
             torch.cuda.synchronize()
@@ -360,7 +370,8 @@ def main():
            "vs_baseline": None, "dtype": "f32+f64" if ok else "f64", "data": "synthetic",
            "config": {"workload": w["name"], "N": n, "p": args.p, "leaf": args.leaf, "layers": 3,
                       "interfaces": list(map(float, w["d"])), "k": list(map(float, w["k"])),
-                      "precision": "mixed: FP32 near field and FP32-MFMA M2L, FP64 elsewhere" if ok else "FP64"},
+                      "precision": ("mixed: FP32 near field and FP32-MFMA M2L, FP64 elsewhere; Sommerfeld contour "
+                                    "truncated at %.0e (FP64 path: e^-40)" % args.mixed_quad_tol) if ok else "FP64"},
            "rel_err_vs_fp64": {"err2": err2, "errmax": errmax, "tol": TOL_MIXED},
            "speedup_vs_plain_fp64": plain["ms"] / mixed["ms"],
            "stages_ms": head["stages"], "roofline": roofline, "rooflines": head["rooflines"],
@@ -368,7 +379,8 @@ def main():
                           "stages_ms": plain["stages"], "rooflines": plain["rooflines"]}}
     # warm: the same input again with operator reuse (every step after the first keeps
     # the operators); context beside the cold headline, never the headline
-    wplan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=1, reuse_operators=True)
+    wplan = lfmm.Plan(w["d"], w["k"], p=args.p, leaf_max=args.leaf, profile=True, precision=1, reuse_operators=True,
+                      quad_tol=args.mixed_quad_tol)
     wphi = torch.empty(n, dtype=torch.complex128, device=dev)
     for i in range(args.warmup):
         wplan.eval_device(xyz, q, wphi, stream=stream)

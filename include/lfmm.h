@@ -60,6 +60,9 @@ typedef struct {
                           same as the previous successful one's keeps that evaluation's free-space and
                           reaction operators instead of generating them again ("warm"); not in
                           lfmm_eval_batch, whose workers lend their workspaces: 0 */
+  double quad_tol;     /* truncation of the Sommerfeld contour (Section 3.5): the far panels end where
+                          the envelope t^N e^{-t dz} of a class's integrands has fallen to quad_tol
+                          times its largest value (N = 2p + 1); in (0, 1), or 0 for e^{-40} (4e-18) */
 } lfmm_options;
 
 typedef struct lfmm_plan_s lfmm_plan_t;

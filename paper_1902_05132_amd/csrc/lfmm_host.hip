@@ -359,6 +359,7 @@ struct lfmm_plan_s {
   int p2p_ch;    // near field: sources per LDS tile
   double kmax;
   double far_cap = P_FAR_CAP_DEFAULT;
+  double quad_c = 40.0;  // the contour ends where the integrands' envelope has fallen by e^{-quad_c}
   double far_grow = 1.5;  // growth of the far panels beyond the cap (1: none; tuning override LFMM_FAR_GROW)
   double* d_gaunt = nullptr;
   std::map<std::string, DevBuf> bufs;
@@ -482,7 +483,7 @@ struct lfmm_plan_s {
   double decay_cached(int npow) const {
     auto it = decay_memo.find(npow);
     if (it != decay_memo.end()) return it->second;
-    double U = decay_length(npow, 40.0);
+    double U = decay_length(npow, quad_c);
     decay_memo[npow] = U;
     return U;
   }
@@ -599,6 +600,11 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
       return LFMM_EINVAL;
     }
     P->reuse_ops = opt->reuse_operators;
+    if (opt->quad_tol < 0 || opt->quad_tol >= 1 || std::isnan(opt->quad_tol)) {
+      delete P;
+      return LFMM_EINVAL;
+    }
+    if (opt->quad_tol > 0) P->quad_c = -std::log(opt->quad_tol);
   }
   memset(&P->rep, 0, sizeof(P->rep));
   try {

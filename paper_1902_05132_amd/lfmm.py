@@ -26,7 +26,7 @@ class LfmmError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("contour_b", ctypes.c_double), ("max_depth", ctypes.c_int), ("min_gap", ctypes.c_double),
                 ("profile", ctypes.c_int), ("precision", ctypes.c_int), ("physical", ctypes.c_int),
-                ("reuse_operators", ctypes.c_int)]
+                ("reuse_operators", ctypes.c_int), ("quad_tol", ctypes.c_double)]
 
 
 class Report(ctypes.Structure):
@@ -145,17 +145,18 @@ class Plan:
     """lfmm_plan wrapper: d (L interfaces, decreasing), k (L+1 wavenumbers), order p, leaf size."""
 
     def __init__(self, d, k, p, leaf_max, contour_b=0.5, max_depth=8, min_gap=1e-9, profile=False, precision=0,
-                 physical=False, reuse_operators=False):
+                 physical=False, reuse_operators=False, quad_tol=0.0):
         """precision 0: FP64 throughout; 1: mixed (FP32 near field and FP32-MFMA M2L).
         physical: return physical potentials (Phi times i k_l / (4 pi)) instead of Phi.
-        reuse_operators: keep the previous evaluation's operators when its trees are the same."""
+        reuse_operators: keep the previous evaluation's operators when its trees are the same.
+        quad_tol: truncation of the Sommerfeld contour (0: the default e^-40)."""
         self.lib = load()
         self.d = _f64(d)
         self.k = _f64(k)
         self.p = int(p)
         self.L = len(self.d)
         opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0, int(precision), 1 if physical else 0,
-                      1 if reuse_operators else 0)
+                      1 if reuse_operators else 0, float(quad_tol))
         h = ctypes.c_void_p()
         dptr = self.d.ctypes.data_as(_D) if self.L else None
         _check(self.lib.lfmm_plan(self.L, dptr, self.k.ctypes.data_as(_D), self.p, int(leaf_max),

@@ -358,6 +358,29 @@ def test_operator_reuse_on_unchanged_trees():
         assert np.array_equal(d, fresh_plan.eval_torch(x3, y3, w["z"], w["q"]))
 
 
+def test_quadrature_tolerance_option():
+    """quad_tol ends the Sommerfeld contour earlier: fewer nodes, and a potential that
+    moves by at most a small multiple of the tolerance from the default contour's;
+    values outside (0, 1) are rejected."""
+    lf = _lfmm()
+    w = W.three_layer_3k()
+    a = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"])
+    pa = a.eval_torch(w["x"], w["y"], w["z"], w["q"])
+    na = a.report()["n_react_nodes"]
+    for tol in (1e-6, 1e-10):
+        b = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], quad_tol=tol)
+        pb = b.eval_torch(w["x"], w["y"], w["z"], w["q"])
+        nb = b.report()["n_react_nodes"]
+        e = float(np.linalg.norm(pb - pa) / np.linalg.norm(pa))
+        print("quad_tol %.0e: %d of %d class-nodes, Err2 vs the default contour %.2e" % (tol, nb, na, e))
+        assert nb < na
+        assert e < 10 * tol
+    for bad in (-1.0, 1.0, 1.5):
+        with pytest.raises(lf.LfmmError) as ex:
+            lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], quad_tol=bad)
+        assert ex.value.code == 1
+
+
 def test_autotune_keeps_results():
     import torch
     lf = _lfmm()

@@ -14,10 +14,10 @@ pytestmark = pytest.mark.gpu
 TOL_MIXED = 1e-6
 
 
-def _both(w, p, leaf):
+def _both(w, p, leaf, quad_tol=0.0):
     from paper_1902_05132_amd import lfmm
     a = lfmm.Plan(w["d"], w["k"], p=p, leaf_max=leaf)
-    b = lfmm.Plan(w["d"], w["k"], p=p, leaf_max=leaf, precision=1)
+    b = lfmm.Plan(w["d"], w["k"], p=p, leaf_max=leaf, precision=1, quad_tol=quad_tol)
     phi64 = a.eval_torch(w["x"], w["y"], w["z"], w["q"])
     phi32 = b.eval_torch(w["x"], w["y"], w["z"], w["q"])
     ra, rb = a.report(), b.report()
@@ -31,7 +31,16 @@ def _both(w, p, leaf):
 def test_mixed_precision_three_layer_3k():
     w = W.three_layer_3k()
     e2, emax = _both(w, w["p"], w["leaf"])
-    print("config 1 mixed vs FP64: Err2 %.2e Errmax %.2e" % (e2, emax))
+    print("three layers, N = 3000, mixed vs FP64: Err2 %.2e Errmax %.2e" % (e2, emax))
+    assert e2 < TOL_MIXED and emax < TOL_MIXED
+
+
+def test_mixed_precision_with_truncated_contour():
+    """The benchmark's mixed setting: FP32 parts and the Sommerfeld contour truncated at
+    1e-10, against the FP64 path with the default contour."""
+    w = W.three_layer_3k()
+    e2, emax = _both(w, w["p"], w["leaf"], quad_tol=1e-10)
+    print("mixed, contour at 1e-10, vs FP64: Err2 %.2e Errmax %.2e" % (e2, emax))
     assert e2 < TOL_MIXED and emax < TOL_MIXED
 
 
