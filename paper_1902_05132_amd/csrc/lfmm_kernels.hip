@@ -1116,9 +1116,15 @@ __global__ __launch_bounds__(128) void k_p2m(int nseg, const int* seg_row0, cons
       }
     }
     __syncthreads();
-    if (tid < P1 && (half == 0 || tid > 0)) {
-      const int mm = tid;
-      for (int n = mm; n <= P; n++) {
+    // one thread per output (m, n >= m): the stripes are summed in a fixed order
+    if (tid < P1 * (P1 + 1) / 2) {
+      int mm = 0, r = tid;
+      while (r >= P1 - mm) {
+        r -= P1 - mm;
+        mm++;
+      }
+      const int n = mm + r;
+      if (half == 0 || mm > 0) {
         double sx = 0.0, sy = 0.0;
         for (int k = 0; k < NSTR; k++) {
           sx += red[((k * P1 + mm) * P1 + n) * 2];
