@@ -1426,7 +1426,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   HIPCHK(hipMemsetAsync(occ, 0, sizeof(int) * ntrees * 9, s));
   HIPCHK(hipMemsetAsync(slab, 0, sizeof(int) * ntrees * 18, s));
   if (ntrees > 96) throw Fail{LFMM_ENOTSUP};  // at most 5 L + 1 trees: never for L <= 16
-  lk_occupancy(ntp, ntrees, skeys, d_trees, occ, slab, s);
+  lk_occupancy(ntp, ntrees, skeys, d_trees, P->leaf_max, occ, slab, s);
   std::vector<int> hocc(ntrees * 9), hslab(ntrees * 18);
   P->rb_add(hocc.data(), occ, sizeof(int) * ntrees * 9, s);
   P->rb_add(hslab.data(), slab, sizeof(int) * ntrees * 18, s);

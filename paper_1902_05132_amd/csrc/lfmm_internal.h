@@ -127,8 +127,8 @@ void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s);
 void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
                     const double* x, const double* y, const double* z, Stack st, unsigned* keys, int* vals,
                     hipStream_t s);
-void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab,
-                  hipStream_t s);
+void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int leaf_max, int* occ,
+                  int* slab, hipStream_t s);
 void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all, const int* scan_all,
                    const int* lvl_off, int* leafrow, hipStream_t s);
 void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm, const int* layer_start,

@@ -282,14 +282,16 @@ __device__ __forceinline__ int run_end(const unsigned* keys, int s, int hi, int 
   return a;
 }
 
-// occupancy[t*9 + l] = fullest cell of tree t at level l; slab flags of reaction trees.
+// occupancy[t*9 + l] = fullest cell of tree t at level l, capped at leaf_max + 1 (the
+// depth rule asks only whether it exceeds leaf_max: one probe leaf_max points ahead
+// of a cell's first point answers that); slab flags of reaction trees.
 // A workgroup scans a contiguous segment of the sorted keys and keeps its maxima
 // and flags in LDS (the keys are sorted by tree, so a segment touches few
 // trees); one flush per workgroup then updates the global tables.
 #define OCC_SEG 8192
 #define OCC_TMAX 96
 __global__ __launch_bounds__(256) void k_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees,
-                                                   int* occ, int* slab) {
+                                                   int leaf_max, int* occ, int* slab) {
   __shared__ int s_occ[OCC_TMAX * 9], s_slab[OCC_TMAX * 18];
   for (int i = threadIdx.x; i < ntrees * 9; i += 256) s_occ[i] = 0;
   for (int i = threadIdx.x; i < ntrees * 18; i += 256) s_slab[i] = 0;
@@ -305,7 +307,7 @@ __global__ __launch_bounds__(256) void k_occupancy(int ntp, int ntrees, const un
     for (int l = 0; l <= 8; l++) {
       int sh = 3 * (8 - l);
       if (s == pt0 || (skeys[s - 1] >> sh) != (key >> sh)) {  // first point of its cell
-        int v = run_end(skeys, s, hi, sh) - s;
+        const int v = (leaf_max < hi - s && (skeys[s + leaf_max] >> sh) == (key >> sh)) ? leaf_max + 1 : 1;
         atomicMax(&s_occ[t * 9 + l], v);
         if (l >= 1 && T.kind != 0) {
           int izl = iz >> (8 - l), half = 1 << (l - 1);
@@ -321,9 +323,9 @@ __global__ __launch_bounds__(256) void k_occupancy(int ntp, int ntrees, const un
   for (int i = threadIdx.x; i < ntrees * 18; i += 256)
     if (s_slab[i]) slab[i] = 1;
 }
-extern "C" void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int* occ, int* slab,
-                             hipStream_t s) {
-  if (ntp) k_occupancy<<<(ntp + OCC_SEG - 1) / OCC_SEG, 256, 0, s>>>(ntp, ntrees, skeys, trees, occ, slab);
+extern "C" void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int leaf_max,
+                             int* occ, int* slab, hipStream_t s) {
+  if (ntp) k_occupancy<<<(ntp + OCC_SEG - 1) / OCC_SEG, 256, 0, s>>>(ntp, ntrees, skeys, trees, leaf_max, occ, slab);
 }
 
 // run-start flags of the level-l boxes (only for trees of depth >= l)
