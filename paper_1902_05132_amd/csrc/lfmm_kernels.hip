@@ -1176,16 +1176,22 @@ __global__ __launch_bounds__(256) void k_l2p(int nseg, const int* seg_s0, const 
   double r = sqrt(dx * dx + dy * dy + dz * dz);
   double jn[P + 1];
   dev_sph_j_t<P>(T.k * r, jn);
-  double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? sqrt(dx * dx + dy * dy) / r : 0.0;
-  double ph = atan2(dy, dx);
+  const double rho = sqrt(dx * dx + dy * dy);
+  double ct = r > 0 ? dz / r : 1.0, st = r > 0 ? rho / r : 0.0;
+  // e^{i m phi} by repeated multiplication with e^{i phi} = (dx + i dy) / rho
+  const double cp = rho > 0 ? dx / rho : 1.0, sp = rho > 0 ? dy / rho : 0.0;
+  double cs = 1.0, sn = 0.0;
   const double* L = Lc + (size_t)R * NCK * 2;
   cd acc = mk(0, 0);
   double pmm = 0.28209479177387814347;
 #pragma unroll 1
   for (int m = 0; m <= P; m++) {
-    if (m > 0) pmm *= c_ld[m] * st;
-    double sn, cs;
-    sincos(m * ph, &sn, &cs);
+    if (m > 0) {
+      pmm *= c_ld[m] * st;
+      const double t = cs * cp - sn * sp;
+      sn = sn * cp + cs * sp;
+      cs = t;
+    }
     double cm = (m & 1) ? -1.0 : 1.0;
     double p0 = 0.0, p1 = pmm;
 #pragma unroll
