@@ -121,6 +121,31 @@ def test_box_sizes_between_nodes(built):
     assert _rel2(phi, ref) < TOL_FMM and _relmax(phi, ref) < TOL_FMM
 
 
+def test_partial_range_mixes_tables_and_quadrature(built):
+    """Tables covering only some of the box sizes: the other classes fall back to the
+    quadrature in the same evaluation, and the result still matches the oracle."""
+    lf, w = built["lf"], built["w"]
+    Q = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"])
+    Q.tables_build(h_min=0.1, h_max=0.3)
+    Q.tables_gate(1e300)
+    phi = _eval(Q, w)
+    rep = Q.report()
+    assert 0 < rep["n_react_table"] < rep["n_react_classes"], rep
+    ref = _oracle_fmm(w)
+    print("partial range: %d of %d classes from the tables, Err2 vs oracle FMM %.2e"
+          % (rep["n_react_table"], rep["n_react_classes"], _rel2(phi, ref)))
+    assert _rel2(phi, built["phi_ref"]) <= max(Q.tables_bounds().max(), 1e-14)
+    assert _rel2(phi, ref) < TOL_FMM and _relmax(phi, ref) < TOL_FMM
+
+
+def test_tables_need_a_layered_medium(built):
+    lf, w = built["lf"], built["w"]
+    H = lf.Plan([], [w["k"][0]], p=4, leaf_max=16)
+    with pytest.raises(lf.LfmmError) as e:
+        H.tables_build()
+    assert e.value.code == 1
+
+
 def test_tables_take_precedence_over_surrogate(built):
     P, w = built["P"], built["w"]
     P.surrogate_train(seed=3, epochs=2)
