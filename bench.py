@@ -412,7 +412,8 @@ def main():
             ph = torch.empty_like(qq)
             row = {"N": n2}
             for prec in (0, 1):
-                pl = lfmm.Plan(ws["d"], ws["k"], p=args.p, leaf_max=args.leaf, precision=prec)
+                pl = lfmm.Plan(ws["d"], ws["k"], p=args.p, leaf_max=args.leaf, precision=prec,
+                               quad_tol=args.mixed_quad_tol if prec else 0.0)
                 for i in range(args.warmup):
                     pl.eval_device(xs, qq, ph, stream=stream)
                 torch.cuda.synchronize()
