@@ -2029,9 +2029,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* d_gK = P->upload("m2l_gK", gK, sj);
   Tmpl* d_tmpl = P->upload("m2l_tmpl", tmpl_m2l, sj);
   if (ne_m2l)
-    lk_src_m2l(ne_m2l, J_m2l.srowid, J_m2l.sgid, d_gseq0, d_gK, d_tmpl, kmax_m2l, box_code, box_level, d_lvl_off,
-               d_grid_off, 9, grid, nullptr, sr_m2l, sj);
-  if (ne_m2l) lk_count_valid(ne_m2l, J_m2l.sgid, d_gK, 0, sr_m2l, kmax_m2l, d_cnt + 0, sj);
+    lk_src_m2l(ne_m2l, J_m2l.srowid, J_m2l.sgid, d_gseq0, d_gK, d_tmpl, kmax_m2l, box_code, box_level, d_grid_off,
+               grid, sr_m2l, d_cnt + 0, sj);
   if (ne_m2m) lk_count_valid(ne_m2m, nullptr, nullptr, 8, sr_m2m, 8, d_cnt + 1, sj);
   if (ne_l2l) lk_count_valid(ne_l2l, nullptr, nullptr, 1, sr_l2l, 1, d_cnt + 2, sj);
   GBlock* d_bm2m = P->upload("b_m2m", b_m2m, sj);

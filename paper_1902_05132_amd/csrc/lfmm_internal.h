@@ -158,9 +158,10 @@ void lk_gemm(int m2l, int nrt, int ks, int nblocks, const GBlock* blocks, const 
              int NCK, int NC, hipStream_t s);
 void lk_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree, const int* box_level,
                   const TreeInfo* trees, const int* gbase, int nlev1, int* gid, int* rowid, hipStream_t s);
+// also adds the number of slots with a source present to *npairs
 void lk_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
-                const Tmpl* tmpl, int stride, const int* box_code, const int* box_level, const int* lvl_off,
-                const long long* grid_off, int nlev1, const int* grid, int* seq_out, int* srow, hipStream_t s);
+                const Tmpl* tmpl, int stride, const int* box_code, const int* box_level, const long long* grid_off,
+                const int* grid, int* srow, unsigned long long* npairs, hipStream_t s);
 void lk_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
                 const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
                 hipStream_t s);

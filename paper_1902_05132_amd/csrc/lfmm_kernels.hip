@@ -1674,29 +1674,37 @@ __device__ __forceinline__ int grid_get(const long long* grid_off, const int* gr
 
 // M2L sources from interaction templates (free: offsets within the same tree;
 // reaction: absolute source depth in a polarisation-source tree)
+// Also counts the products with a source present (a wave sum, one atomic per wave).
 __global__ void k_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
                           const Tmpl* tmpl, int stride, const int* box_code, const int* box_level,
-                          const long long* grid_off, const int* grid, int* srow) {
+                          const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs) {
   int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nent) return;
-  int g = egrp[e];
-  int R = trow[e];
-  int l = box_level[R];
-  int ix, iy, iz;
-  demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
-  int s0 = grp_seq0[g], K = grp_K[g];
-  for (int kk = 0; kk < K; kk++) {
-    Tmpl T = tmpl[s0 + kk];
-    int sz = T.zabs ? T.dz : iz - T.dz;
-    srow[(size_t)e * stride + kk] = grid_get(grid_off, grid, T.stree, l, ix - T.dx, iy - T.dy, sz);
+  int cnt = 0;
+  if (e < nent) {
+    int g = egrp[e];
+    int R = trow[e];
+    int l = box_level[R];
+    int ix, iy, iz;
+    demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
+    int s0 = grp_seq0[g], K = grp_K[g];
+    for (int kk = 0; kk < K; kk++) {
+      Tmpl T = tmpl[s0 + kk];
+      int sz = T.zabs ? T.dz : iz - T.dz;
+      const int sr = grid_get(grid_off, grid, T.stree, l, ix - T.dx, iy - T.dy, sz);
+      srow[(size_t)e * stride + kk] = sr;
+      cnt += sr >= 0;
+    }
   }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(npairs, (unsigned long long)cnt);
 }
 extern "C" void lk_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
-                           const Tmpl* tmpl, int stride, const int* box_code, const int* box_level, const int* lvl_off,
-                           const long long* grid_off, int nlev1, const int* grid, int* seq_out, int* srow,
+                           const Tmpl* tmpl, int stride, const int* box_code, const int* box_level,
+                           const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs,
                            hipStream_t s) {
-  (void)lvl_off; (void)nlev1; (void)seq_out;
-  if (nent) k_src_m2l<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, egrp, grp_seq0, grp_K, tmpl, stride, box_code, box_level, grid_off, grid, srow);
+  if (nent) k_src_m2l<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, egrp, grp_seq0, grp_K, tmpl, stride, box_code,
+                                                      box_level, grid_off, grid, srow, npairs);
 }
 
 // number of (target, source) products with a source present
