@@ -1414,7 +1414,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   unsigned* skeys = P->dev<unsigned>("skeys", ntp);
   int* vals = P->dev<int>("vals", ntp);
   int* sg = P->dev<int>("sg", ntp);
-  lk_tree_points(ntp, ntrees, d_trees, perm, d_lstart, x, y, z, st, keys, vals, s);
+  double* rec = P->dev<double>("tp_rec", 5 * (size_t)ntp);
+  lk_tree_points(ntp, ntrees, d_trees, perm, d_lstart, x, y, z, q, st, keys, vals, rec, s);
   int tbits = 1;
   while ((1 << tbits) < ntrees) tbits++;
   size_t tb2 = 0;
@@ -1521,7 +1522,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   double* py = P->dev<double>("py", ntp);
   double* pz = P->dev<double>("pz", ntp);
   double* pq = P->dev<double>("pq", 2 * (size_t)ntp);
-  lk_gather(ntp, sg, d_trees, ntrees, perm, d_lstart, x, y, z, q, st, px, py, pz, pq, s);
+  lk_gather(ntp, sg, rec, px, py, pz, pq, s);
   send(ST_TREE, s);
   // the operator stream (and the job stream) may start from here: everything the
   // operator stream reads is uploaded on it ahead of its kernels (copies of all

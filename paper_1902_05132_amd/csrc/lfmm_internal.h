@@ -125,15 +125,14 @@ void lk_classify(int n, const double* x, const double* y, const double* z, const
 void lk_reduce_stats(int nblocks, int nl, const double* partial, double* stats, hipStream_t s);
 void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s);
 void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
-                    const double* x, const double* y, const double* z, Stack st, unsigned* keys, int* vals,
-                    hipStream_t s);
+                    const double* x, const double* y, const double* z, const double* q, Stack st, unsigned* keys,
+                    int* vals, double* rec, hipStream_t s);
 void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int leaf_max, int* occ,
                   int* slab, hipStream_t s);
 void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all, const int* scan_all,
                    const int* lvl_off, int* leafrow, hipStream_t s);
-void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm, const int* layer_start,
-               const double* x, const double* y, const double* z, const double* q, Stack st, double* px,
-               double* py, double* pz, double* pq, hipStream_t s);
+void lk_gather(int ntp, const int* sg, const double* rec, double* px, double* py, double* pz, double* pq,
+               hipStream_t s);
 void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS, const double* gaunt,
                 float* ops32, const int* opse, hipStream_t s);
 // Ltab != nullptr (stacks with more than four interfaces): per-node layer tables,

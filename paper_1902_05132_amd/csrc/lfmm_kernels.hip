@@ -239,9 +239,12 @@ extern "C" void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s)
 // ---------------------------------------------------------------------------
 // Tree points: keys = (tree << 24) | Morton code of the depth-8 cell
 // ---------------------------------------------------------------------------
+// Each tree point also gets its record (frame x, y, z, Re q, Im q) here, in tree
+// point order: the gather into sorted order then reads one 40-byte record per
+// point instead of following the layer permutation into five separate arrays.
 __global__ void k_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
-                              const double* x, const double* y, const double* z, Stack st, unsigned* keys,
-                              int* vals) {
+                              const double* x, const double* y, const double* z, const double* q, Stack st,
+                              unsigned* keys, int* vals, double* rec) {
   int g = blockIdx.x * 256 + threadIdx.x;
   if (g >= ntp) return;
   int t = tree_of(trees, ntrees, g);
@@ -255,11 +258,19 @@ __global__ void k_tree_points(int ntp, int ntrees, const TreeInfo* trees, const 
   else iz = 127 - half_cell(-fz, T.S);
   keys[g] = ((unsigned)t << 24) | morton3(ix, iy, iz);
   vals[g] = g;
+  double* r = rec + 5 * (size_t)g;
+  r[0] = fx;
+  r[1] = fy;
+  r[2] = fz;
+  r[3] = q[2 * i];
+  r[4] = q[2 * i + 1];
 }
 extern "C" void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
-                               const double* x, const double* y, const double* z, Stack st, unsigned* keys, int* vals,
-                               hipStream_t s) {
-  if (ntp) k_tree_points<<<nblk(ntp, 256), 256, 0, s>>>(ntp, ntrees, trees, perm, layer_start, x, y, z, st, keys, vals);
+                               const double* x, const double* y, const double* z, const double* q, Stack st,
+                               unsigned* keys, int* vals, double* rec, hipStream_t s) {
+  if (ntp)
+    k_tree_points<<<nblk(ntp, 256), 256, 0, s>>>(ntp, ntrees, trees, perm, layer_start, x, y, z, q, st, keys, vals,
+                                                 rec);
 }
 
 // end (exclusive) of the run of keys sharing key >> sh, starting at s, within [s, hi):
@@ -422,28 +433,21 @@ extern "C" void lk_grid_fill_all(int nrows, const int* box_code, const int* box_
   if (nrows) k_grid_fill_all<<<nblk(nrows, 256), 256, 0, s>>>(nrows, box_code, box_tree, box_level, grid_off, grid);
 }
 
-__global__ void k_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm,
-                         const int* layer_start, const double* x, const double* y, const double* z, const double* q,
-                         Stack st, double* px, double* py, double* pz, double* pq) {
+// tree point records into Morton-sorted order, split into coordinate and charge arrays
+__global__ void k_gather(int ntp, const int* sg, const double* rec, double* px, double* py, double* pz, double* pq) {
   int s = blockIdx.x * 256 + threadIdx.x;
   if (s >= ntp) return;
-  int g = sg[s];
-  int t = tree_of(trees, ntrees, g);
-  TreeInfo T = trees[t];
-  int i = perm[layer_start[T.layer] + (g - T.pt_off)];
-  double fx, fy, fz;
-  frame_xyz(T, st, x[i], y[i], z[i], &fx, &fy, &fz);
+  const double* r = rec + 5 * (size_t)sg[s];
+  double fx = r[0], fy = r[1], fz = r[2], qr = r[3], qi = r[4];
   px[s] = fx;
   py[s] = fy;
   pz[s] = fz;
-  pq[2 * s] = q[2 * i];
-  pq[2 * s + 1] = q[2 * i + 1];
+  pq[2 * s] = qr;
+  pq[2 * s + 1] = qi;
 }
-extern "C" void lk_gather(int ntp, const int* sg, const TreeInfo* trees, int ntrees, const int* perm,
-                          const int* layer_start, const double* x, const double* y, const double* z, const double* q,
-                          Stack st, double* px, double* py, double* pz, double* pq, hipStream_t s) {
-  if (ntp)
-    k_gather<<<nblk(ntp, 256), 256, 0, s>>>(ntp, sg, trees, ntrees, perm, layer_start, x, y, z, q, st, px, py, pz, pq);
+extern "C" void lk_gather(int ntp, const int* sg, const double* rec, double* px, double* py, double* pz, double* pq,
+                          hipStream_t s) {
+  if (ntp) k_gather<<<nblk(ntp, 256), 256, 0, s>>>(ntp, sg, rec, px, py, pz, pq);
 }
 
 // ---------------------------------------------------------------------------
