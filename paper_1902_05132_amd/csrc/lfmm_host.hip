@@ -645,7 +645,7 @@ struct RIPrep {
   SCDesc* scs = nullptr;
   int* mem = nullptr;
   double *J = nullptr, *Pt = nullptr, *F = nullptr, *Lt = nullptr;
-  int nrg = 0, ncls = 0, nsc = 0, nwg = 0, Ntot = 0, maxnn = 0;
+  int nrg = 0, ncls = 0, nsc = 0, nwg = 0, Ntot = 0, Ftot = 0;
 };
 static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDesc>& classes, hipStream_t up) {
   RIPrep R;
@@ -653,7 +653,7 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
   const int p = P->p, Q = 2 * p, NT = P->NT, NL = P->st.L + 1;
   std::map<std::tuple<double, double, double, double, int, int, double, double, int>, int> key_rg;
   std::vector<RGDesc> rgs;
-  int Ntot = 0, Ftot = 0, maxnn = 0;
+  int Ntot = 0, Ftot = 0;
   for (auto& C : classes) {
     auto key = std::make_tuple(C.rule.b, C.rule.T0, C.rule.hn, C.rule.hf, C.rule.nnear, C.rule.nfar, C.rho,
                                C.rule.wmax, C.rule.kg);
@@ -673,7 +673,6 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
     C.rg_off = rgs[it->second].off;
     C.f_off = Ftot;
     Ftot += nn;
-    maxnn = std::max(maxnn, nn);
   }
   // stacks: classes with the same rule group and source layer, at most SC_GMAX
   // of them and three target layers each
@@ -728,14 +727,14 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
   R.nsc = (int)scs.size();
   R.nwg = nwg;
   R.Ntot = Ntot;
-  R.maxnn = maxnn;
+  R.Ftot = Ftot;
   return R;
 }
 static void reaction_launch(lfmm_plan_s* P, const RIPrep& R, double* Iall, hipStream_t s,
                             const std::function<void()>& after_tables = nullptr) {
   if (!R.ncls) return;
   lk_react_tables(R.nrg, R.rgs, R.Ntot, P->st, P->p, R.J, R.Pt, R.Lt, s);
-  lk_react_F(R.ncls, R.cls, R.maxnn, P->st, R.Ntot, R.Lt, R.F, s);
+  lk_react_F(R.ncls, R.cls, R.Ftot, P->st, R.Ntot, R.Lt, R.F, s);
   if (after_tables) after_tables();
   lk_react_mfma(R.nwg, R.nsc, R.scs, R.mem, R.cls, P->p, R.Ntot, R.J, R.Pt, R.F, Iall, P->NC, s);
 }

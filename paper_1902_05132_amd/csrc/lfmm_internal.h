@@ -139,7 +139,7 @@ void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int
 // 6 (L + 1) Ntot complex, from which k_react_F assembles the densities.
 void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, int p, double* Jtab, double* Ptab,
                      double* Ltab, hipStream_t s);
-void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, int Ntot, const double* Ltab, double* Ftab,
+void lk_react_F(int ncls, const ClassDesc* cls, int Ftot, Stack st, int Ntot, const double* Ltab, double* Ftab,
                 hipStream_t s);
 void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p, int Ntot,
                    const double* Jtab, const double* Ptab, const double* Ftab, double* Iout, int NC, hipStream_t s);

@@ -686,11 +686,23 @@ __global__ __launch_bounds__(256) void k_react_tables(const RGDesc* rgs, int nrg
     dev_legendre_c(p, kz / kl, kr / kl, Ptab + ((size_t)l * Ntot + g) * NT, 1);
   }
 }
+// The F values of all classes are one array (class c's nodes from cls[c].f_off on,
+// in class order): one thread per entry, its class by bisection on f_off.
+__device__ __forceinline__ int class_of_entry(const ClassDesc* cls, int ncls, int f) {
+  int lo = 0, hi = ncls - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (cls[mid].f_off <= f) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 template <int LL>
-__global__ __launch_bounds__(256) void k_react_F(const ClassDesc* cls, Stack st, cd* Ftab) {
-  const ClassDesc C = cls[blockIdx.y];
-  int node = blockIdx.x * 256 + threadIdx.x;
-  if (node >= rule_nodes(C.rule)) return;
+__global__ __launch_bounds__(256) void k_react_F(const ClassDesc* cls, int ncls, int Ftot, Stack st, cd* Ftab) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= Ftot) return;
+  const ClassDesc C = cls[class_of_entry(cls, ncls, f)];
+  const int node = f - C.f_off;
   cd kr, w;
   rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
   double kt = st.k[C.lt], ks = st.k[C.ls];
@@ -709,11 +721,12 @@ __global__ __launch_bounds__(256) void k_react_F(const ClassDesc* cls, Stack st,
 // component from the per-node layer tables (closure in the source layer, then the
 // generalised transmissions to the target layer), the same steps as
 // dev_densities_t without repeating the recursions for every class of a node.
-__global__ __launch_bounds__(256) void k_react_F_lt(const ClassDesc* cls, Stack st, int Ntot, const cd* Lt,
-                                                    cd* Ftab) {
-  const ClassDesc C = cls[blockIdx.y];
-  int node = blockIdx.x * 256 + threadIdx.x;
-  if (node >= rule_nodes(C.rule)) return;
+__global__ __launch_bounds__(256) void k_react_F_lt(const ClassDesc* cls, int ncls, int Ftot, Stack st, int Ntot,
+                                                    const cd* Lt, cd* Ftab) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  if (f >= Ftot) return;
+  const ClassDesc C = cls[class_of_entry(cls, ncls, f)];
+  const int node = f - C.f_off;
   cd kr, w;
   rule_node(C.rule, node, c_glx, c_glw, &kr, &w);
   const int L = st.L, NLm = L + 1, g = C.rg_off + node, l = C.lt, lp = C.ls;
@@ -921,20 +934,20 @@ extern "C" void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, 
     k_react_tables<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(rgs, nrg, Ntot, st, p, (cd*)Jtab, (cd*)Ptab,
                                                                 (cd*)Ltab);
 }
-extern "C" void lk_react_F(int ncls, const ClassDesc* cls, int maxnn, Stack st, int Ntot, const double* Ltab,
+extern "C" void lk_react_F(int ncls, const ClassDesc* cls, int Ftot, Stack st, int Ntot, const double* Ltab,
                            double* Ftab, hipStream_t s) {
-  if (!ncls || !maxnn) return;
-  dim3 g((maxnn + 255) / 256, ncls);
+  if (!ncls || !Ftot) return;
+  const unsigned g = (unsigned)((Ftot + 255) / 256);
   if (Ltab) {
-    k_react_F_lt<<<g, 256, 0, s>>>(cls, st, Ntot, (const cd*)Ltab, (cd*)Ftab);
+    k_react_F_lt<<<g, 256, 0, s>>>(cls, ncls, Ftot, st, Ntot, (const cd*)Ltab, (cd*)Ftab);
     return;
   }
   switch (st.L) {
-    case 1: k_react_F<1><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
-    case 2: k_react_F<2><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
-    case 3: k_react_F<3><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
-    case 4: k_react_F<4><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
-    default: k_react_F<0><<<g, 256, 0, s>>>(cls, st, (cd*)Ftab); break;
+    case 1: k_react_F<1><<<g, 256, 0, s>>>(cls, ncls, Ftot, st, (cd*)Ftab); break;
+    case 2: k_react_F<2><<<g, 256, 0, s>>>(cls, ncls, Ftot, st, (cd*)Ftab); break;
+    case 3: k_react_F<3><<<g, 256, 0, s>>>(cls, ncls, Ftot, st, (cd*)Ftab); break;
+    case 4: k_react_F<4><<<g, 256, 0, s>>>(cls, ncls, Ftot, st, (cd*)Ftab); break;
+    default: k_react_F<0><<<g, 256, 0, s>>>(cls, ncls, Ftot, st, (cd*)Ftab); break;
   }
 }
 template <int UPW, int CH>
