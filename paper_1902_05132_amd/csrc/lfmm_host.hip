@@ -2018,8 +2018,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* sr_m2m = P->dev<int>("sr_m2m", (size_t)ne_m2m * 8 + 1);
   int* sr_l2l = P->dev<int>("sr_l2l", (size_t)ne_l2l + 1);
   int* sr_m2l = P->dev<int>("sr_m2l", (size_t)ne_m2l * kmax_m2l + 1);
-  if (ne_m2m) lk_src_m2m(ne_m2m, J_m2m.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_m2m, sj);
-  if (ne_l2l) lk_src_l2l(ne_l2l, J_l2l.srowid, box_code, box_tree, box_level, d_lvl_off, d_grid_off, 9, grid, sr_l2l, sj);
+  if (ne_m2m) lk_src_m2m(ne_m2m, J_m2m.srowid, box_code, box_tree, box_level, d_grid_off, grid, sr_m2m, d_cnt + 1, sj);
+  if (ne_l2l) lk_src_l2l(ne_l2l, J_l2l.srowid, box_code, box_tree, box_level, d_grid_off, grid, sr_l2l, d_cnt + 2, sj);
   std::vector<int> gseq0(ng_m2l), gK(ng_m2l);
   for (int g = 0; g < ng_m2l; g++) {
     gseq0[g] = g_m2l[g].seq0;
@@ -2031,8 +2031,6 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   if (ne_m2l)
     lk_src_m2l(ne_m2l, J_m2l.srowid, J_m2l.sgid, d_gseq0, d_gK, d_tmpl, kmax_m2l, box_code, box_level, d_grid_off,
                grid, sr_m2l, d_cnt + 0, sj);
-  if (ne_m2m) lk_count_valid(ne_m2m, nullptr, nullptr, 8, sr_m2m, 8, d_cnt + 1, sj);
-  if (ne_l2l) lk_count_valid(ne_l2l, nullptr, nullptr, 1, sr_l2l, 1, d_cnt + 2, sj);
   GBlock* d_bm2m = P->upload("b_m2m", b_m2m, sj);
   GBlock* d_bl2l = P->upload("b_l2l", b_l2l, sj);
   GBlock* d_bm2l = P->upload("b_m2l", b_m2l, sj);

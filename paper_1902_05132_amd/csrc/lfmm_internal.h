@@ -162,11 +162,9 @@ void lk_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0,
                 const Tmpl* tmpl, int stride, const int* box_code, const int* box_level, const long long* grid_off,
                 const int* grid, int* srow, unsigned long long* npairs, hipStream_t s);
 void lk_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
-                const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
-                hipStream_t s);
+                const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs, hipStream_t s);
 void lk_src_l2l(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
-                const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
-                hipStream_t s);
+                const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs, hipStream_t s);
 void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
                  const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
                  const TreeInfo* trees, const long long* grid_off, const int* grid, const double* px,
@@ -184,8 +182,6 @@ void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps,
                  const int* grid, const double* px, const double* py, const double* pz, const double* pq,
                  const int* sg, const double* nkr, const double* nfac, const double* nkzt, const double* nkzs,
                  double* phi_tp, hipStream_t s);
-void lk_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, const int* srow, int stride,
-                    unsigned long long* counter, hipStream_t s);
 void lk_final_sum(int n, const int* layer, const int* inv_perm, const int* layer_start, const int* tgt_trees,
                   int max_tt, const TreeInfo* trees, const double* phi_tp, double* phi, Stack st, int phys,
                   hipStream_t s);

@@ -1689,6 +1689,13 @@ __device__ __forceinline__ int grid_get(const long long* grid_off, const int* gr
   return grid[go + morton3(ix, iy, iz)];
 }
 
+// adds the wave's per-lane counts to *npairs (a wave sum, one atomic per wave); every
+// lane of the wave calls it
+__device__ __forceinline__ void count_wave(int cnt, unsigned long long* npairs) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
+  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(npairs, (unsigned long long)cnt);
+}
 // M2L sources from interaction templates (free: offsets within the same tree;
 // reaction: absolute source depth in a polarisation-source tree)
 // Also counts the products with a source present (a wave sum, one atomic per wave).
@@ -1712,9 +1719,7 @@ __global__ void k_src_m2l(int nent, const int* trow, const int* egrp, const int*
       cnt += sr >= 0;
     }
   }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) cnt += __shfl_xor(cnt, m, 64);
-  if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(npairs, (unsigned long long)cnt);
+  count_wave(cnt, npairs);
 }
 extern "C" void lk_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
                            const Tmpl* tmpl, int stride, const int* box_code, const int* box_level,
@@ -1725,53 +1730,52 @@ extern "C" void lk_src_m2l(int nent, const int* trow, const int* egrp, const int
 }
 
 // number of (target, source) products with a source present
-__global__ void k_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, const int* srow, int stride,
-                              unsigned long long* counter) {
-  int e = blockIdx.x * 256 + threadIdx.x;
-  unsigned long long c = 0;
-  if (e < nent) {
-    int K = egrp ? grp_K[egrp[e]] : fixedK;
-    for (int kk = 0; kk < K; kk++) c += (srow[(size_t)e * stride + kk] >= 0) ? 1ull : 0ull;
-  }
-  if (c) atomicAdd(counter, c);
-}
-extern "C" void lk_count_valid(int nent, const int* egrp, const int* grp_K, int fixedK, const int* srow, int stride,
-                               unsigned long long* counter, hipStream_t s) {
-  if (nent) k_count_valid<<<nblk(nent, 256), 256, 0, s>>>(nent, egrp, grp_K, fixedK, srow, stride, counter);
-}
-
+// M2M and L2L sources of each target row; each kernel also counts the products with
+// a source present
 __global__ void k_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
-                          const long long* grid_off, const int* grid, int* srow) {
+                          const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs) {
   int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nent) return;
-  int R = trow[e];
-  int t = box_tree[R], l = box_level[R] + 1;
-  unsigned code = (unsigned)box_code[R];
-  long long go = grid_off[t * 9 + l];
-  for (int ch = 0; ch < 8; ch++) srow[(size_t)e * 8 + ch] = (go < 0) ? -1 : grid[go + code * 8 + ch];
+  int cnt = 0;
+  if (e < nent) {
+    int R = trow[e];
+    int t = box_tree[R], l = box_level[R] + 1;
+    unsigned code = (unsigned)box_code[R];
+    long long go = grid_off[t * 9 + l];
+    for (int ch = 0; ch < 8; ch++) {
+      const int sr = (go < 0) ? -1 : grid[go + code * 8 + ch];
+      srow[(size_t)e * 8 + ch] = sr;
+      cnt += sr >= 0;
+    }
+  }
+  count_wave(cnt, npairs);
 }
 extern "C" void lk_src_m2m(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
-                           const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
+                           const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs,
                            hipStream_t s) {
-  (void)lvl_off; (void)nlev1;
-  if (nent) k_src_m2m<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, box_code, box_tree, box_level, grid_off, grid, srow);
+  if (nent)
+    k_src_m2m<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, box_code, box_tree, box_level, grid_off, grid, srow, npairs);
 }
 
 __global__ void k_src_l2l(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
-                          const long long* grid_off, const int* grid, int* srow) {
+                          const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs) {
   int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= nent) return;
-  int R = trow[e];
-  int t = box_tree[R], l = box_level[R];
-  unsigned code = (unsigned)box_code[R];
-  long long go = grid_off[t * 9 + (l - 1)];
-  srow[e] = (go < 0) ? -1 : grid[go + (code >> 3)];
+  int cnt = 0;
+  if (e < nent) {
+    int R = trow[e];
+    int t = box_tree[R], l = box_level[R];
+    unsigned code = (unsigned)box_code[R];
+    long long go = grid_off[t * 9 + (l - 1)];
+    const int sr = (go < 0) ? -1 : grid[go + (code >> 3)];
+    srow[e] = sr;
+    cnt = sr >= 0;
+  }
+  count_wave(cnt, npairs);
 }
 extern "C" void lk_src_l2l(int nent, const int* trow, const int* box_code, const int* box_tree, const int* box_level,
-                           const int* lvl_off, const long long* grid_off, int nlev1, const int* grid, int* srow,
+                           const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs,
                            hipStream_t s) {
-  (void)lvl_off; (void)nlev1;
-  if (nent) k_src_l2l<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, box_code, box_tree, box_level, grid_off, grid, srow);
+  if (nent)
+    k_src_l2l<<<nblk(nent, 256), 256, 0, s>>>(nent, trow, box_code, box_tree, box_level, grid_off, grid, srow, npairs);
 }
 
 // ---------------------------------------------------------------------------

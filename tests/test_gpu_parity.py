@@ -149,6 +149,48 @@ def test_free_space_fmm_single_layer():
     _check_fmm(w, p=6, leaf=20)
 
 
+def _m2l_list_count(level):
+    """Interaction-list entries at one level of a full uniform tree: pairs of cells
+    whose parents are adjacent (or equal) and which are not adjacent themselves,
+    counted by brute force over the grid."""
+    n = 1 << level
+    c = np.arange(n)
+    total = 0
+    for ix in range(n):
+        ax = (np.abs(c // 2 - ix // 2) <= 1)
+        nx = (np.abs(c - ix) <= 1)
+        for iy in range(n):
+            ay = (np.abs(c // 2 - iy // 2) <= 1)
+            ny = (np.abs(c - iy) <= 1)
+            for iz in range(n):
+                az = (np.abs(c // 2 - iz // 2) <= 1)
+                nz = (np.abs(c - iz) <= 1)
+                par = ax[:, None, None] & ay[None, :, None] & az[None, None, :]
+                adj = nx[:, None, None] & ny[None, :, None] & nz[None, None, :]
+                total += int(np.count_nonzero(par & ~adj))
+    return total
+
+
+def test_translation_pair_counts_full_tree():
+    """Homogeneous medium, 20,000 uniform particles, leaf <= 100: the depth rule gives
+    depth 3 (level 2 holds about 312 particles per cell, level 3 about 39) and every
+    level-3 cell is occupied (a Poisson(39) cell is empty with probability e^-39).
+    The tree is then the full octree: 585 boxes, one M2M and one L2L per level-3
+    box, and the M2L products of the full interaction lists at levels 2 and 3."""
+    lf = _lfmm()
+    rng = np.random.default_rng(17)
+    n = 20000
+    x, y, z = rng.random(n), rng.random(n), rng.random(n)
+    q = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    P = lf.Plan((), (1.1,), p=4, leaf_max=100)
+    P.eval_torch(x, y, z, q)
+    rep = P.report()
+    assert rep["free_depth"][0] == 3
+    assert rep["n_boxes"] == 1 + 8 + 64 + 512
+    assert rep["m2m_pairs"] == 512 and rep["l2l_pairs"] == 512
+    assert rep["m2l_pairs"] == _m2l_list_count(2) + _m2l_list_count(3)
+
+
 def test_empty_and_single_particle():
     lf = _lfmm()
     d, k = W.THREE_LAYER_D, W.THREE_LAYER_K
