@@ -1038,18 +1038,24 @@ __device__ __forceinline__ int seg_find(const int* prefix, int nseg, int x) {
 
 // One workgroup of 128 threads per leaf.  The per-particle quantities (j_n(k r),
 // the angles and the charge) are computed once per particle into LDS; then thread
-// (m, stripe) runs the Legendre recurrence in n for order m over its stripe of the
-// particles and accumulates M_{n,m} and M_{n,-m}; the stripes are summed through
-// LDS in a fixed order.
+// (m, sign, stripe) runs the Legendre recurrence in n for order m over its stripe of
+// the particles and accumulates M_{n,m} (sign 0) or M_{n,-m} (sign 1); the stripes
+// are summed through LDS in a fixed order.  One sign per thread halves the
+// accumulators a thread holds, and the stripe sums reuse the staging arrays' LDS
+// (they start after the last particle chunk is consumed): four waves share a SIMD.
 template <int P>
-__global__ __launch_bounds__(128) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix,
                                              const int* box_start, const int* box_cnt, const int* box_code,
                                              const int* box_tree, const int* box_level, const TreeInfo* trees,
                                              const double* px, const double* py, const double* pz, const double* pq,
                                              int NCK, double* M) {
-  constexpr int P1 = P + 1, NSTR = 128 / P1;
-  __shared__ double s_ct[128], s_st[128], s_cp[128], s_sp[128], s_qr[128], s_qi[128], s_j[P1][128];
-  __shared__ double red[NSTR * P1 * P1 * 2];
+  constexpr int P1 = P + 1, NSTR = 128 / (2 * P1);
+  constexpr int NSTAGE = (6 + P1) * 128, NRED = 2 * NSTR * P1 * P1 * 2;
+  __shared__ double smem[NSTAGE > NRED ? NSTAGE : NRED];
+  double *s_ct = smem, *s_st = smem + 128, *s_cp = smem + 256, *s_sp = smem + 384, *s_qr = smem + 512,
+         *s_qi = smem + 640;
+  double(*s_j)[128] = reinterpret_cast<double(*)[128]>(smem + 768);
+  double* red = smem;  // [sign][stripe][m][n] (re, im)
   const int tid = threadIdx.x;
   const int li = blockIdx.x;
   const int sgm = seg_find(seg_prefix, nseg, li);
@@ -1058,15 +1064,14 @@ __global__ __launch_bounds__(128) void k_p2m(int nseg, const int* seg_row0, cons
   double c[3];
   box_center(T, (unsigned)box_code[R], box_level[R], c);
   const int s0 = box_start[R], nt = box_cnt[R];
-  const int m = tid % P1, str = tid / P1;
-  const bool active = str < NSTR;
-  const double cm = (m & 1) ? -1.0 : 1.0;
-  cd accp[P1], accn[P1];
+  const int m = tid % P1, sgn = (tid / P1) & 1, str = tid / (2 * P1);
+  // M_{n,0} needs one sign only
+  const bool active = str < NSTR && !(sgn && m == 0);
+  // conj(Y_n^m) = Phat e^{-i m phi};  conj(Y_n^{-m}) = (-1)^m Phat e^{+i m phi}
+  const double cm = sgn ? ((m & 1) ? -1.0 : 1.0) : 1.0, ss = sgn ? 1.0 : -1.0;
+  cd acc[P1];
 #pragma unroll
-  for (int n = 0; n <= P; n++) {
-    accp[n] = mk(0, 0);
-    accn[n] = mk(0, 0);
-  }
+  for (int n = 0; n <= P; n++) acc[n] = mk(0, 0);
   for (int c0 = 0; c0 < nt; c0 += 128) {
     const int nc = nt - c0 < 128 ? nt - c0 : 128;
     __syncthreads();
@@ -1098,8 +1103,7 @@ __global__ __launch_bounds__(128) void k_p2m(int nseg, const int* seg_row0, cons
           sn = sn * cp + cs * sp;
           cs = t;
         }
-        const cd q = mk(s_qr[i], s_qi[i]);
-        const cd qp = q * mk(cs, -sn), qn = cm * (q * mk(cs, sn));
+        const cd qx = cm * (mk(s_qr[i], s_qi[i]) * mk(cs, ss * sn));
         double pmm = 0.28209479177387814347;
         for (int mm = 1; mm <= m; mm++) pmm *= c_ld[mm] * st;
         double p0 = 0.0, p1 = 0.0;
@@ -1115,44 +1119,43 @@ __global__ __launch_bounds__(128) void k_p2m(int nseg, const int* seg_row0, cons
             p0 = p1;
             p1 = val;
           }
-          const double base = s_j[n][i] * val;
-          // conj(Y_n^m) = Phat e^{-i m phi};  conj(Y_n^{-m}) = (-1)^m Phat e^{+i m phi}
-          accp[n] = accp[n] + base * qp;
-          accn[n] = accn[n] + base * qn;
+          acc[n] = acc[n] + (s_j[n][i] * val) * qx;
         }
       }
     }
   }
-  double* Mr = M + (size_t)R * NCK * 2;
-  for (int half = 0; half < 2; half++) {
-    __syncthreads();
-    if (active) {
+  __syncthreads();
+  if (str < NSTR) {
 #pragma unroll
-      for (int n = 0; n <= P; n++) {
-        const cd v = half ? accn[n] : accp[n];
-        red[((str * P1 + m) * P1 + n) * 2] = v.x;
-        red[((str * P1 + m) * P1 + n) * 2 + 1] = v.y;
-      }
+    for (int n = 0; n <= P; n++) {
+      const size_t o = (((size_t)(sgn * NSTR + str) * P1 + m) * P1 + n) * 2;
+      red[o] = acc[n].x;
+      red[o + 1] = acc[n].y;
     }
-    __syncthreads();
-    // one thread per output (m, n >= m): the stripes are summed in a fixed order
-    if (tid < P1 * (P1 + 1) / 2) {
-      int mm = 0, r = tid;
-      while (r >= P1 - mm) {
-        r -= P1 - mm;
-        mm++;
+  }
+  __syncthreads();
+  // one thread per output (sign, m, n >= m; no sign 1 for m = 0): the stripes are
+  // summed in a fixed order
+  double* Mr = M + (size_t)R * NCK * 2;
+  constexpr int NOUT = P1 * (P1 + 1) / 2;
+  if (tid < 2 * NOUT) {
+    const int half = tid / NOUT;
+    int mm = 0, r = tid % NOUT;
+    while (r >= P1 - mm) {
+      r -= P1 - mm;
+      mm++;
+    }
+    const int n = mm + r;
+    if (half == 0 || mm > 0) {
+      double sx = 0.0, sy = 0.0;
+      for (int k = 0; k < NSTR; k++) {
+        const size_t o = (((size_t)(half * NSTR + k) * P1 + mm) * P1 + n) * 2;
+        sx += red[o];
+        sy += red[o + 1];
       }
-      const int n = mm + r;
-      if (half == 0 || mm > 0) {
-        double sx = 0.0, sy = 0.0;
-        for (int k = 0; k < NSTR; k++) {
-          sx += red[((k * P1 + mm) * P1 + n) * 2];
-          sy += red[((k * P1 + mm) * P1 + n) * 2 + 1];
-        }
-        const int o = cidx(n, half ? -mm : mm);
-        Mr[2 * o] = sx;
-        Mr[2 * o + 1] = sy;
-      }
+      const int oc = cidx(n, half ? -mm : mm);
+      Mr[2 * oc] = sx;
+      Mr[2 * oc + 1] = sy;
     }
   }
 }
