@@ -1393,18 +1393,21 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     ntp += T.npts;
   }
   rep.n_trees = ntrees;
-  // ---------------- layer sort
-  int* iota = P->dev<int>("iota", n);
+  // ---------------- stable partition of the particles by layer
   int* perm = P->dev<int>("perm", n);
-  int* lsorted = P->dev<int>("lsorted", n);
   int* inv_perm = P->dev<int>("inv_perm", n);
-  lk_iota(n, iota, s);
-  int lbits = 1;
-  while ((1 << lbits) <= L) lbits++;
-  size_t tb1 = 0;
-  HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb1, layer, lsorted, iota, perm, n, 0, lbits, s));
-  void* tmp = P->dev<char>("cubtmp1", tb1);
-  HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb1, layer, lsorted, iota, perm, n, 0, lbits, s));
+  const int nbl = (n + 255) / 256;
+  int* lcnt = P->dev<int>("layer_cnt", (size_t)NL * nbl + 1);
+  int* loff = P->dev<int>("layer_off", (size_t)NL * nbl + 1);
+  void* tmp = nullptr;
+  if (n) {
+    lk_layer_count(n, NL, layer, lcnt, s);
+    size_t tb1 = 0;
+    HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb1, lcnt, loff, NL * nbl, s));
+    tmp = P->dev<char>("cubtmp1", tb1);
+    HIPCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb1, lcnt, loff, NL * nbl, s));
+    lk_layer_scatter(n, NL, layer, loff, perm, s);
+  }
   lk_inverse_perm(n, perm, inv_perm, s);
   int* d_lstart = P->upload("layer_start", layer_start, s);
   TreeInfo* d_trees = P->upload("trees", trees, s);

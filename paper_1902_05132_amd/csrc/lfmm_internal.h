@@ -118,7 +118,10 @@ extern "C" {
 void lk_set_gl(const double* x, const double* w);
 void lk_zero(double* p, size_t n, hipStream_t s);
 void lk_fill_int(int* p, size_t n, int v, hipStream_t s);
-void lk_iota(int n, int* a, hipStream_t s);
+// stable partition by layer: per-block counts cnt[l * nb + b] (nb = ceil(n / 256)),
+// then, with off = their exclusive scan, perm[slot] = particle
+void lk_layer_count(int n, int NL, const int* layer, int* cnt, hipStream_t s);
+void lk_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm, hipStream_t s);
 void lk_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out, hipStream_t s);
 void lk_classify(int n, const double* x, const double* y, const double* z, const int* lin, int* lout, Stack st,
                  double* partial, int nblocks, hipStream_t s);

@@ -205,12 +205,51 @@ extern "C" void lk_reduce_stats(int nblocks, int nl, const double* partial, doub
   k_reduce_stats<<<nl * NSTAT, 64, 0, s>>>(nblocks, nl, partial, stats);
 }
 
-__global__ void k_iota(int n, int* a) {
-  int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) a[i] = i;
+// ---------------------------------------------------------------------------
+// Stable partition of the particles by layer (a counting sort: at most LFMM_MAXL + 1
+// layers).  Block b holds particles [256 b, 256 b + 256).  k_layer_count writes each
+// layer's count per block, cnt[l * nb + b]; an exclusive scan of that layer-major
+// array gives every (layer, block) its first output slot; k_layer_scatter puts each
+// particle at that slot plus its rank among the block's earlier particles of its
+// layer (wave ballots, then the earlier waves' counts).  Layers are in [0, NL).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_layer_count(int n, int NL, const int* layer, int* cnt) {
+  __shared__ int wc[4][LFMM_MAXL + 1];
+  const int i = blockIdx.x * 256 + threadIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int my = i < n ? layer[i] : -1;
+  for (int l = 0; l < NL; l++) {
+    const unsigned long long m = __ballot(my == l);
+    if (lane == 0) wc[wave][l] = __popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < NL) {
+    const int l = threadIdx.x;
+    cnt[(size_t)l * gridDim.x + blockIdx.x] = wc[0][l] + wc[1][l] + wc[2][l] + wc[3][l];
+  }
 }
-extern "C" void lk_iota(int n, int* a, hipStream_t s) {
-  if (n) k_iota<<<nblk(n, 256), 256, 0, s>>>(n, a);
+__global__ __launch_bounds__(256) void k_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm) {
+  __shared__ int wc[4][LFMM_MAXL + 1];
+  const int i = blockIdx.x * 256 + threadIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int my = i < n ? layer[i] : -1;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int rank = 0;
+  for (int l = 0; l < NL; l++) {
+    const unsigned long long m = __ballot(my == l);
+    if (my == l) rank = __popcll(m & below);
+    if (lane == 0) wc[wave][l] = __popcll(m);
+  }
+  __syncthreads();
+  if (i < n) {
+    int pos = off[(size_t)my * gridDim.x + blockIdx.x] + rank;
+    for (int w = 0; w < wave; w++) pos += wc[w][my];
+    perm[pos] = i;
+  }
+}
+extern "C" void lk_layer_count(int n, int NL, const int* layer, int* cnt, hipStream_t s) {
+  if (n) k_layer_count<<<nblk(n, 256), 256, 0, s>>>(n, NL, layer, cnt);
+}
+extern "C" void lk_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm, hipStream_t s) {
+  if (n) k_layer_scatter<<<nblk(n, 256), 256, 0, s>>>(n, NL, layer, off, perm);
 }
 
 __global__ void k_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out) {
