@@ -1992,9 +1992,12 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
 // target leaf's first particle are formed in FP64 and kept as FP32 hi + lo pairs,
 // so a pair difference (hi - hi) + (lo - lo) is accurate to FP32 rounding of the
 // difference itself, also for the closest pairs; pairs are evaluated and
-// partially summed in FP32 (seven-term series of sin(x)/x and cos(x), truncation
-// below 1e-11 for u <= 1; v_rsq_f32), and each target's sum is accumulated in FP64.
-template <bool POLY, int TA, int CH>
+// partially summed in FP32, and each target's sum is accumulated in FP64.  NS: the
+// number of terms of the series of sin(x)/x and cos(x), x = k r (v_rsq_f32 for 1/r):
+// 7 where x <= 1 on every pair (truncation below 1e-11), 5 where x <= 1/2 (the next
+// terms, x^10/11! and x^10/10!, are below 2.5e-11 and 2.7e-10, 3.1e-10 of cos x);
+// 0 takes sincosf.
+template <int NS, int TA, int CH>
 __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row0, const int* seg_prefix,
                                                     const int* box_start, const int* box_cnt, const int* box_code,
                                                     const int* box_tree, const int* box_level, const TreeInfo* trees,
@@ -2086,20 +2089,27 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
           float r2s = ok ? r2 : 1.f;
           float y = __builtin_amdgcn_rsqf(r2s);
           float hr, hi;
-          if (POLY) {
+          if constexpr (NS > 0) {
             constexpr float s1 = (float)inv_fact(3), s2 = (float)inv_fact(5), s3 = (float)inv_fact(7),
                             s4 = (float)inv_fact(9), s5 = (float)inv_fact(11), s6 = (float)inv_fact(13);
             constexpr float c1 = (float)inv_fact(2), c2 = (float)inv_fact(4), c3 = (float)inv_fact(6),
                             c4 = (float)inv_fact(8), c5 = (float)inv_fact(10), c6 = (float)inv_fact(12);
+            static_assert(NS == 5 || NS == 7, "series of 5 or 7 terms");
             float v = -k2 * r2s;
-            float ps = fmaf(s6, v, s5);
-            ps = fmaf(ps, v, s4);
+            float ps, pc;
+            if constexpr (NS == 7) {
+              ps = fmaf(s6, v, s5);
+              ps = fmaf(ps, v, s4);
+              pc = fmaf(c6, v, c5);
+              pc = fmaf(pc, v, c4);
+            } else {
+              ps = s4;
+              pc = c4;
+            }
             ps = fmaf(ps, v, s3);
             ps = fmaf(ps, v, s2);
             ps = fmaf(ps, v, s1);
             ps = fmaf(ps, v, 1.f);
-            float pc = fmaf(c6, v, c5);
-            pc = fmaf(pc, v, c4);
             pc = fmaf(pc, v, c3);
             pc = fmaf(pc, v, c2);
             pc = fmaf(pc, v, c1);
@@ -2147,14 +2157,14 @@ extern "C" void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix
                             int poly, int ta, int ch, int f32, unsigned long long* npairs, hipStream_t s) {
   if (!total) return;
   if (f32) {
-    if (poly)
-      k_p2p_free32<true, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
-                                                       box_tree, box_level, trees, grid_off, grid, px, py, pz, pq,
-                                                       sg, phi_tp, npairs);
-    else
-      k_p2p_free32<false, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
-                                                        box_tree, box_level, trees, grid_off, grid, px, py, pz, pq,
-                                                        sg, phi_tp, npairs);
+#define P2P32(NS)                                                                                               \
+  k_p2p_free32<NS, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,      \
+                                                 box_tree, box_level, trees, grid_off, grid, px, py, pz, pq, sg, \
+                                                 phi_tp, npairs)
+    if (poly == 2) P2P32(5);
+    else if (poly) P2P32(7);
+    else P2P32(0);
+#undef P2P32
     return;
   }
 #define P2P_CASE(PO, T, C)                                                                                      \

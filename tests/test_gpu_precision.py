@@ -60,3 +60,28 @@ def test_mixed_precision_near_field_library_path():
     e2, emax = _both(w, 6, 400)
     print("sincos path mixed vs FP64: Err2 %.2e Errmax %.2e" % (e2, emax))
     assert e2 < TOL_MIXED
+
+
+@pytest.mark.parametrize("side,k,form", [(0.05, 2.0, 2), (0.1, 2.0, 1), (1.0, 2.0, 0)])
+def test_mixed_near_field_forms_against_oracle(side, k, form):
+    """One medium, every particle in one leaf: the FP32 near field alone against the
+    oracle's direct sum, in each form of h0.  The host bounds k r by 2 k side sqrt(3):
+    0.35 <= 1/2 at side 0.05 (five-term series), 0.69 <= 1 at side 0.1 (seven terms),
+    6.9 at side 1 (sincosf)."""
+    import oracle as O
+    from paper_1902_05132_amd import lfmm
+    n = 700
+    rng = np.random.default_rng(41)
+    pts = np.array([0.2, -0.1, 0.3]) + side * (rng.random((n, 3)) - 0.5)
+    x, y, z = pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy()
+    q = rng.uniform(-1, 1, n) + 1j * rng.uniform(-1, 1, n)
+    P = lfmm.Plan((), (k,), p=4, leaf_max=1000, precision=1)
+    phi = P.eval_torch(x, y, z, q)
+    rep = P.report()
+    assert rep["free_depth"][0] == 0 and rep["p2p_pairs"] == n * (n - 1)
+    assert rep["p2p_series"] == form
+    ref = O.direct((), (k,), x, y, z, np.zeros(n, np.int32), q, np.arange(n))
+    e2 = np.linalg.norm(phi - ref) / np.linalg.norm(ref)
+    emax = np.max(np.abs(phi - ref)) / np.max(np.abs(ref))
+    print("form %d: Err2 %.2e Errmax %.2e vs the oracle's direct sum" % (form, e2, emax))
+    assert e2 < TOL_MIXED and emax < TOL_MIXED
