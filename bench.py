@@ -31,8 +31,8 @@ PEAK = {("mfma", 64): 78.6, ("mfma", 32): 157.3, ("alu", 64): 78.6, ("alu", 32):
 # reciprocal square root with two Newton steps (10), -(kr)^2 (1), sin(x)/x and cos(x) series (9 + 10 fma),
 # -cos(kr)/(kr) (2), complex multiply-add (8) = 67.  FP32: hi/lo differences (9), r^2 (5), rsqrt (1),
 # -(kr)^2 (1), series (6 + 6 fma), -cos(kr)/(kr) (2), complex multiply-add (8) = 50.
-P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}  # series forms; the FP32 five-term series (k r <= 1/2): 42
-P2P32_SHORT_FLOPS_PER_PAIR = 42
+P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}  # series forms for k r <= 1
+P2P_SHORT_FLOPS_PER_PAIR = {64: 55, 32: 42}  # the shorter series for k r <= 1/2
 TOL_MIXED = 1e-6  # the mixed path is the headline only if it stays this close to the FP64 path
 MIXED_QUAD_TOL = 1e-10
 TABLE_H = (0.03, 1.0)  # box sizes the tables cover (every level of the bench workload's trees)
@@ -337,7 +337,7 @@ def main():
                       what="reaction M2L integrals, node sums on FP64 MFMA (overlapped with the main stream)")]
         if rep.get("p2p_series"):
             cands.append(dict(kernel="k_p2p_free" + sfx, stage="p2p_free", bound="alu", bits=bits, stream="main",
-                              flops=float(P2P32_SHORT_FLOPS_PER_PAIR if rep["p2p_series"] == 2 else P2P_FLOPS_PER_PAIR[bits])
+                              flops=float((P2P_SHORT_FLOPS_PER_PAIR if rep["p2p_series"] == 2 else P2P_FLOPS_PER_PAIR)[bits])
                               * rep["p2p_pairs"],
                               what="free-space near field, %s vector ALU" % ("FP32" if precision else "FP64")))
         rooflines = []

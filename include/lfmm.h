@@ -83,8 +83,8 @@ typedef struct {
   int64_t l2l_pairs;       /* (child, parent) L2L products */
   int64_t p2p_pairs;       /* free-space near-field (target, source) pairs evaluated */
   int64_t nf_react_pairs;  /* near-field reaction pairs */
-  int p2p_series;          /* near field's form of h0: 1 the series (k r <= 1 on every pair), 2 the FP32
-                              near field's five-term series (k r <= 1/2), 0 the library sin and cos */
+  int p2p_series;          /* near field's form of h0: 1 the series (k r <= 1 on every pair), 2 the shorter
+                              series (k r <= 1/2), 0 the library sin and cos */
   int precision;           /* the plan's precision option */
   double stage_ms[24];     /* per-stage device time when profiling is on (see lfmm_stage_name) */
   int64_t n_react_surrogate; /* reaction classes whose integrals came from the surrogate (gate hits);

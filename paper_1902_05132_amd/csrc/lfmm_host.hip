@@ -1858,9 +1858,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     if (tot) {
       int* d_r0 = P->upload("p2p_r0", r0, s);
       int* d_pf = P->upload("p2p_pf", pf, s);
-      // the series form where k r <= 1 on every pair; the FP32 kernel's shorter
-      // series where k r <= 1/2
-      rep.p2p_series = (p2p32 && krmax <= 0.5) ? 2 : (krmax <= 1.0 ? 1 : 0);
+      // the series form where k r <= 1 on every pair, shorter series where k r <= 1/2
+      rep.p2p_series = krmax <= 0.5 ? 2 : (krmax <= 1.0 ? 1 : 0);
       const int series = rep.p2p_series;
       sbeg(ST_P2P, s);
       lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,

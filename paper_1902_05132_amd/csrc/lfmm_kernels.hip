@@ -1843,28 +1843,38 @@ __device__ __forceinline__ double rsqrt_nr(double r2) {
   y = y * fma(-hh, y * y, 1.5);
   return y;
 }
-// h0(k r) for r^2 = r2 > 0 (hr + i hi); k2 = k^2, invk = 1/k
-template <bool POLY>
+// h0(k r) for r^2 = r2 > 0 (hr + i hi); k2 = k^2, invk = 1/k.  FORM 1: series of
+// sin(x)/x (10 terms) and cos(x) (11 terms) for x = k r <= 1; FORM 2: 7 and 8 terms
+// for x <= 1/2 (the first dropped terms, x^14/15! and x^16/16!, are below 4.9e-17 and
+// 8.3e-19 relative); FORM 0: sincos.
+template <int FORM>
 __device__ __forceinline__ void h0_pair(double r2, double k, double k2, double invk, double& hr, double& hi) {
   double y = rsqrt_nr(r2);
-  if (POLY) {
+  if constexpr (FORM > 0) {
     constexpr double s1 = inv_fact(3), s2 = inv_fact(5), s3 = inv_fact(7), s4 = inv_fact(9), s5 = inv_fact(11),
                      s6 = inv_fact(13), s7 = inv_fact(15), s8 = inv_fact(17), s9 = inv_fact(19);
     constexpr double c1 = inv_fact(2), c2 = inv_fact(4), c3 = inv_fact(6), c4 = inv_fact(8), c5 = inv_fact(10),
                      c6 = inv_fact(12), c7 = inv_fact(14), c8 = inv_fact(16), c9 = inv_fact(18), c10 = inv_fact(20);
+    static_assert(FORM == 1 || FORM == 2, "series forms 1 and 2");
     double v = -k2 * r2;  // -(kr)^2
-    double ps = fma(s9, v, s8);
-    ps = fma(ps, v, s7);
-    ps = fma(ps, v, s6);
+    double ps, pc;
+    if constexpr (FORM == 1) {
+      ps = fma(s9, v, s8);
+      ps = fma(ps, v, s7);
+      ps = fma(ps, v, s6);
+      pc = fma(c10, v, c9);
+      pc = fma(pc, v, c8);
+      pc = fma(pc, v, c7);
+    } else {
+      ps = s6;
+      pc = c7;
+    }
     ps = fma(ps, v, s5);
     ps = fma(ps, v, s4);
     ps = fma(ps, v, s3);
     ps = fma(ps, v, s2);
     ps = fma(ps, v, s1);
     ps = fma(ps, v, 1.0);
-    double pc = fma(c10, v, c9);
-    pc = fma(pc, v, c8);
-    pc = fma(pc, v, c7);
     pc = fma(pc, v, c6);
     pc = fma(pc, v, c5);
     pc = fma(pc, v, c4);
@@ -1884,7 +1894,7 @@ __device__ __forceinline__ void h0_pair(double r2, double k, double k2, double i
   }
 }
 #define P2P_TMAX 256
-template <bool POLY, int TA, int CH>
+template <int FORM, int TA, int CH>
 __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix,
                                                   const int* box_start, const int* box_cnt, const int* box_code,
                                                   const int* box_tree, const int* box_level, const TreeInfo* trees,
@@ -1961,7 +1971,7 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
           double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
           bool ok = r2 > 0.0;  // the target itself (and coincident points) contribute nothing
           double hr, hi;
-          h0_pair<POLY>(ok ? r2 : 1.0, k, k2, invk, hr, hi);
+          h0_pair<FORM>(ok ? r2 : 1.0, k, k2, invk, hr, hi);
           hr = ok ? hr : 0.0;
           hi = ok ? hi : 0.0;
           double qr = s_qr[j], qi = s_qi[j];
@@ -2167,27 +2177,34 @@ extern "C" void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix
 #undef P2P32
     return;
   }
-#define P2P_CASE(PO, T, C)                                                                                      \
-  if ((poly != 0) == PO && ta == T && ch == C) {                                                                \
-    k_p2p_free<PO, T, C><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,        \
+#define P2P_CASE(FO, T, C)                                                                                      \
+  if (poly == FO && ta == T && ch == C) {                                                                       \
+    k_p2p_free<FO, T, C><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,        \
                                               box_tree, box_level, trees, grid_off, grid, px, py, pz, pq, sg,   \
                                               phi_tp, npairs);                                                  \
     return;                                                                                                     \
   }
-  P2P_CASE(true, 4, 128) P2P_CASE(true, 8, 128) P2P_CASE(true, 16, 128)
-  P2P_CASE(true, 4, 256) P2P_CASE(true, 8, 256) P2P_CASE(true, 16, 256)
-  P2P_CASE(true, 4, 512) P2P_CASE(true, 8, 512) P2P_CASE(true, 16, 512)
-  P2P_CASE(false, 4, 256) P2P_CASE(false, 8, 256) P2P_CASE(false, 16, 256)
+  P2P_CASE(1, 4, 128) P2P_CASE(1, 8, 128) P2P_CASE(1, 16, 128)
+  P2P_CASE(1, 4, 256) P2P_CASE(1, 8, 256) P2P_CASE(1, 16, 256)
+  P2P_CASE(1, 4, 512) P2P_CASE(1, 8, 512) P2P_CASE(1, 16, 512)
+  P2P_CASE(2, 4, 128) P2P_CASE(2, 8, 128) P2P_CASE(2, 16, 128)
+  P2P_CASE(2, 4, 256) P2P_CASE(2, 8, 256) P2P_CASE(2, 16, 256)
+  P2P_CASE(2, 4, 512) P2P_CASE(2, 8, 512) P2P_CASE(2, 16, 512)
+  P2P_CASE(0, 4, 256) P2P_CASE(0, 8, 256) P2P_CASE(0, 16, 256)
 #undef P2P_CASE
   // any other request falls back to the general-purpose shape
-  if (poly)
-    k_p2p_free<true, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
-                                                   box_tree, box_level, trees, grid_off, grid, px, py, pz, pq, sg,
-                                                   phi_tp, npairs);
+  if (poly == 2)
+    k_p2p_free<2, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code, box_tree,
+                                                box_level, trees, grid_off, grid, px, py, pz, pq, sg, phi_tp,
+                                                npairs);
+  else if (poly)
+    k_p2p_free<1, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code, box_tree,
+                                                box_level, trees, grid_off, grid, px, py, pz, pq, sg, phi_tp,
+                                                npairs);
   else
-    k_p2p_free<false, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code,
-                                                    box_tree, box_level, trees, grid_off, grid, px, py, pz, pq, sg,
-                                                    phi_tp, npairs);
+    k_p2p_free<0, 8, 256><<<total, 256, 0, s>>>(nseg, seg_row0, seg_prefix, box_start, box_cnt, box_code, box_tree,
+                                                box_level, trees, grid_off, grid, px, py, pz, pq, sg, phi_tp,
+                                                npairs);
 }
 
 // ---------------------------------------------------------------------------

@@ -122,18 +122,19 @@ def _cube(n, side, centre, seed):
     return pts[:, 0].copy(), pts[:, 1].copy(), pts[:, 2].copy(), q
 
 
-@pytest.mark.parametrize("side,k", [(0.1, 2.0), (1.0, 2.0), (0.05, 9.0)])
-def test_near_field_only_free_space(side, k):
+@pytest.mark.parametrize("side,k,form", [(0.05, 2.0, 2), (0.1, 2.0, 1), (1.0, 2.0, 0), (0.05, 9.0, 0)])
+def test_near_field_only_free_space(side, k, form):
     """One medium, every particle in one leaf: the result is the plain pair sum.
-    Side 0.1 with k = 2 bounds k r by 2 k side sqrt(3) = 0.69 <= 1 and takes the
-    series path for sin(x)/x and cos(x); side 1 with k = 2 (6.9) and side 0.05
-    with k = 9 (1.56) exceed the bound and take the library sincos path."""
+    The host bounds k r by 2 k side sqrt(3): side 0.05 with k = 2 (0.35 <= 1/2)
+    takes the shorter series for sin(x)/x and cos(x), side 0.1 with k = 2 (0.69 <= 1)
+    the full series; side 1 with k = 2 (6.9) and side 0.05 with k = 9 (1.56) exceed
+    the bound and take the library sincos path."""
     lf = _lfmm()
     x, y, z, q = _cube(700, side, np.array([0.2, -0.1, 0.3]), seed=21)
     P = lf.Plan((), (k,), p=4, leaf_max=1000)
     phi = P.eval_torch(x, y, z, q)
     rep = P.report()
-    assert rep["free_depth"][0] == 0
+    assert rep["free_depth"][0] == 0 and rep["p2p_series"] == form
     assert rep["p2p_pairs"] == 700 * 699
     ref = O.direct((), (k,), x, y, z, np.zeros(700, np.int32), q, np.arange(700))
     assert rel(phi, ref) < 1e-12, rel(phi, ref)
