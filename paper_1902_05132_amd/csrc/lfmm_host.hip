@@ -2170,7 +2170,12 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       if (hipEventElapsedTime(&ms, P->evb[i], P->eve[i]) == hipSuccess) rep.stage_ms[i] = ms;
     }
   }
-  P->last_opsig.swap(opsig);
+  // operators generated into a lent workspace (a batch worker's) are gone once the
+  // worker frees it, and a later allocation may reuse its addresses: keep no
+  // signature then, so that the next evaluation on the plan's own workspace
+  // generates its operators again
+  if (P->bufp == &P->bufs) P->last_opsig.swap(opsig);
+  else P->last_opsig.clear();
   return LFMM_OK;
 }
 

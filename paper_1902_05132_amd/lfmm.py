@@ -141,6 +141,34 @@ def _f64(a):
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+def _dev_arg(t, name, dtype, numel, device=None):
+    """Check a torch tensor handed to the library by address: on the GPU, contiguous,
+    of the given dtype and with at least `numel` elements (and on `device` if given).
+    A wrong argument would otherwise become an out-of-bounds device access."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise LfmmError(1, "%s: a torch tensor is required" % name)
+    if not t.is_cuda:
+        raise LfmmError(1, "%s: must be on the GPU" % name)
+    if t.dtype != dtype:
+        raise LfmmError(1, "%s: dtype %s, expected %s" % (name, t.dtype, dtype))
+    if not t.is_contiguous():
+        raise LfmmError(1, "%s: must be contiguous" % name)
+    if t.numel() < numel:
+        raise LfmmError(1, "%s: %d elements, at least %d needed" % (name, t.numel(), numel))
+    if device is not None and t.device != device:
+        raise LfmmError(1, "%s: on %s, the other arguments are on %s" % (name, t.device, device))
+    return t.data_ptr()
+
+
+def _xyz_arg(xyz, name):
+    import torch
+    if not isinstance(xyz, torch.Tensor) or xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise LfmmError(1, "%s: a (3, n) tensor is required" % name)
+    n = int(xyz.shape[1])
+    return n, _dev_arg(xyz, name, torch.float64, 3 * n)
+
+
 class Plan:
     """lfmm_plan wrapper: d (L interfaces, decreasing), k (L+1 wavenumbers), order p, leaf size."""
 
@@ -178,13 +206,13 @@ class Plan:
     def eval_device(self, xyz, q, phi, layer=None, stream=None):
         """xyz: float64 (3, n) contiguous; q, phi: complex128 (n,) contiguous; layer: int32 (n,) or None."""
         import torch
-        n = xyz.shape[1]
-        assert xyz.dtype == torch.float64 and xyz.is_contiguous() and xyz.is_cuda
-        assert q.dtype == torch.complex128 and q.is_contiguous() and phi.dtype == torch.complex128
+        n, xp = _xyz_arg(xyz, "xyz")
+        qp = _dev_arg(q, "q", torch.complex128, n, xyz.device)
+        fp = _dev_arg(phi, "phi", torch.complex128, n, xyz.device)
+        lp = _dev_arg(layer, "layer", torch.int32, n, xyz.device) if layer is not None else None
         s = stream if stream is not None else torch.cuda.current_stream()
-        lp = layer.data_ptr() if layer is not None else None
-        _check(self.lib.lfmm_eval_device(self.h, n, xyz.data_ptr(), lp, q.data_ptr(), phi.data_ptr(),
-                                         ctypes.c_void_p(s.cuda_stream)), "lfmm_eval_device")
+        _check(self.lib.lfmm_eval_device(self.h, n, xp, lp, qp, fp, ctypes.c_void_p(s.cuda_stream)),
+               "lfmm_eval_device")
         return phi
 
     def eval_torch(self, x, y, z, q, layer=None):
@@ -202,11 +230,19 @@ class Plan:
         """Phi at separate targets.  src_xyz (3, ns), tgt_xyz (3, nt) float64 contiguous on the
         GPU; q (ns,), phi (nt,) complex128; layer ids int32 or None (both or neither)."""
         import torch
+        ns, sp = _xyz_arg(src_xyz, "src_xyz")
+        nt, tp = _xyz_arg(tgt_xyz, "tgt_xyz")
+        dev = src_xyz.device
+        if tgt_xyz.device != dev:
+            raise LfmmError(1, "tgt_xyz: on %s, the sources are on %s" % (tgt_xyz.device, dev))
+        qp = _dev_arg(q, "q", torch.complex128, ns, dev)
+        fp = _dev_arg(phi, "phi", torch.complex128, nt, dev)
+        if (src_layer is None) != (tgt_layer is None):
+            raise LfmmError(1, "src_layer and tgt_layer: give both or neither")
+        sl = _dev_arg(src_layer, "src_layer", torch.int32, ns, dev) if src_layer is not None else None
+        tl = _dev_arg(tgt_layer, "tgt_layer", torch.int32, nt, dev) if tgt_layer is not None else None
         s = stream if stream is not None else torch.cuda.current_stream()
-        sl = src_layer.data_ptr() if src_layer is not None else None
-        tl = tgt_layer.data_ptr() if tgt_layer is not None else None
-        _check(self.lib.lfmm_eval_targets_device(self.h, src_xyz.shape[1], src_xyz.data_ptr(), sl, q.data_ptr(),
-                                                 tgt_xyz.shape[1], tgt_xyz.data_ptr(), tl, phi.data_ptr(),
+        _check(self.lib.lfmm_eval_targets_device(self.h, ns, sp, sl, qp, nt, tp, tl, fp,
                                                  ctypes.c_void_p(s.cuda_stream)), "lfmm_eval_targets_device")
         return phi
 
@@ -266,11 +302,14 @@ class Plan:
     def autotune(self, xyz, q, phi, layer=None, stream=None):
         """lfmm_autotune on torch device tensors (as eval_device); returns the tuning report."""
         import torch
+        n, xp = _xyz_arg(xyz, "xyz")
+        qp = _dev_arg(q, "q", torch.complex128, n, xyz.device)
+        fp = _dev_arg(phi, "phi", torch.complex128, n, xyz.device)
+        lp = _dev_arg(layer, "layer", torch.int32, n, xyz.device) if layer is not None else None
         s = stream if stream is not None else torch.cuda.current_stream()
         r = TuneReport()
-        lp = layer.data_ptr() if layer is not None else None
-        _check(self.lib.lfmm_autotune(self.h, xyz.shape[1], xyz.data_ptr(), lp, q.data_ptr(), phi.data_ptr(),
-                                      ctypes.c_void_p(s.cuda_stream), ctypes.byref(r)), "lfmm_autotune")
+        _check(self.lib.lfmm_autotune(self.h, n, xp, lp, qp, fp, ctypes.c_void_p(s.cuda_stream), ctypes.byref(r)),
+               "lfmm_autotune")
         return {f: getattr(r, f) for f, _ in TuneReport._fields_}
 
     # ---- learned surrogate of the reaction integrals ----
@@ -357,15 +396,28 @@ def eval_batch(plans, xyzs, qs, phis, layers=None, nworkers=8):
     """lfmm_eval_batch over torch device tensors: plans[i] with xyzs[i] (3, n_i) float64,
     qs[i] / phis[i] (n_i,) complex128 (all contiguous, on the GPU).  Returns the
     per-problem status codes; raises on failure."""
-    L = load()
+    import torch
     m = len(plans)
+    if not (len(xyzs) == len(qs) == len(phis) == m) or (layers is not None and len(layers) != m):
+        raise LfmmError(1, "eval_batch: one plan, xyz, q and phi (and layer) per problem")
+    ns, xp, qp, fp, lp = [], [], [], [], []
+    for i in range(m):
+        n, p = _xyz_arg(xyzs[i], "xyzs[%d]" % i)
+        dev = xyzs[i].device
+        ns.append(n)
+        xp.append(p)
+        qp.append(_dev_arg(qs[i], "qs[%d]" % i, torch.complex128, n, dev))
+        fp.append(_dev_arg(phis[i], "phis[%d]" % i, torch.complex128, n, dev))
+        if layers is not None:
+            lp.append(_dev_arg(layers[i], "layers[%d]" % i, torch.int32, n, dev))
+    L = load()
     vp = ctypes.c_void_p
     P = (vp * m)(*[pl.h.value for pl in plans])
-    N = (ctypes.c_int64 * m)(*[x.shape[1] for x in xyzs])
-    X = (vp * m)(*[x.data_ptr() for x in xyzs])
-    Q = (vp * m)(*[x.data_ptr() for x in qs])
-    F = (vp * m)(*[x.data_ptr() for x in phis])
-    Ly = (vp * m)(*[x.data_ptr() for x in layers]) if layers is not None else None
+    N = (ctypes.c_int64 * m)(*ns)
+    X = (vp * m)(*xp)
+    Q = (vp * m)(*qp)
+    F = (vp * m)(*fp)
+    Ly = (vp * m)(*lp) if layers is not None else None
     st = (ctypes.c_int * m)()
     rc = L.lfmm_eval_batch(m, P, N, X, Ly, Q, F, int(nworkers), st)
     _check(rc, "lfmm_eval_batch")

@@ -68,3 +68,49 @@ def test_binding_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for f, _ in cls._fields_:
             assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_device_entry_points_reject_bad_tensors():
+    """The binding checks every tensor it hands to the library by address (device,
+    dtype, contiguity, length, same device) before any library call, so a host or
+    undersized tensor raises instead of becoming an out-of-bounds device access."""
+    import torch
+    P = lfmm.Plan.__new__(lfmm.Plan)  # no library call: the checks come first
+    P.h = None
+    n = 5
+    xyz = torch.zeros(3, n, dtype=torch.float64)
+    q = torch.zeros(n, dtype=torch.complex128)
+    phi = torch.zeros(n, dtype=torch.complex128)
+    with pytest.raises(lfmm.LfmmError) as e:
+        P.eval_device(xyz, q, phi)
+    assert e.value.code == 1 and "GPU" in str(e.value)
+    with pytest.raises(lfmm.LfmmError):
+        P.eval_device(torch.zeros(2, n, dtype=torch.float64), q, phi)
+    with pytest.raises(lfmm.LfmmError):
+        P.eval_targets_device(xyz, q, xyz, phi)
+    with pytest.raises(lfmm.LfmmError):
+        P.autotune(xyz, q, phi)
+    with pytest.raises(lfmm.LfmmError):
+        lfmm.eval_batch([P], [xyz], [q], [phi])
+    with pytest.raises(lfmm.LfmmError):
+        lfmm.eval_batch([P, P], [xyz], [q], [phi])
+
+
+def test_argument_checks_on_tensor_properties(monkeypatch):
+    """dtype, contiguity, length and device mismatches, with the GPU check passed by
+    a stand-in (no GPU here)."""
+    import torch
+    monkeypatch.setattr(torch.Tensor, "is_cuda", property(lambda self: True))
+    n = 6
+    good = torch.zeros(n, dtype=torch.complex128)
+    assert lfmm._dev_arg(good, "q", torch.complex128, n) == good.data_ptr()
+    with pytest.raises(lfmm.LfmmError, match="dtype"):
+        lfmm._dev_arg(torch.zeros(n, dtype=torch.float64), "q", torch.complex128, n)
+    with pytest.raises(lfmm.LfmmError, match="elements"):
+        lfmm._dev_arg(torch.zeros(n - 1, dtype=torch.complex128), "phi", torch.complex128, n)
+    with pytest.raises(lfmm.LfmmError, match="contiguous"):
+        lfmm._dev_arg(torch.zeros(2 * n, dtype=torch.complex128)[::2], "q", torch.complex128, n)
+    with pytest.raises(lfmm.LfmmError, match="dtype"):
+        lfmm._dev_arg(torch.zeros(n, dtype=torch.int64), "layer", torch.int32, n)
+    with pytest.raises(lfmm.LfmmError, match="on"):
+        lfmm._dev_arg(good, "q", torch.complex128, n, torch.device("meta"))
