@@ -91,6 +91,8 @@ typedef struct {
                                 the other n_react_classes - n_react_surrogate used the quadrature */
   int ops_reused;            /* 1: the operators of the previous evaluation were kept (reuse_operators) */
   int64_t n_react_table;     /* reaction classes whose integrals came from the pre-computed tables */
+  int64_t workspace_bytes;   /* device workspace the evaluation used (its buffers' capacities; for
+                                lfmm_eval_device_noalloc, the part of the static scratch it took) */
 } lfmm_report;
 
 /*
@@ -122,6 +124,30 @@ int lfmm_plan(int L, const double* d, const double* k, int p, int leaf_max, cons
  */
 int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q,
                      double* phi, void* stream);
+
+/*
+ * lfmm_eval_device_noalloc -- lfmm_eval_device without any allocation: for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The evaluation's whole device workspace is
+ * taken from a static device array of LFMM_NOALLOC_BYTES that the library holds
+ * on every device it runs on until the process ends; no device or pinned host
+ * memory is allocated (host bookkeeping uses ordinary heap memory).  Arguments,
+ * layout and results are those of lfmm_eval_device, and the potentials are
+ * bit-identical to its own.  The call is synchronous: it returns after every
+ * stream it used has finished.
+ *   - must be called with the plan's device current (else LFMM_EINVAL);
+ *   - LFMM_ENOMEM if the evaluation needs more workspace than LFMM_NOALLOC_BYTES
+ *     (lfmm_report.workspace_bytes of an ordinary evaluation of the same problem
+ *     tells how much it needs); nothing is allocated instead, and phi is then
+ *     undefined;
+ *   - the operators of an earlier evaluation are never kept (reuse_operators does
+ *     not apply);
+ *   - every call on one device shares that device's scratch: calls that overlap in
+ *     time on one device (from several threads or plans) race and must not be made.
+ */
+#define LFMM_NOALLOC_BYTES ((size_t)512 << 20)
+int lfmm_eval_device_noalloc(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q,
+                             double* phi, void* stream);
 
 /* lfmm_eval -- the same with host buffers (copied to and from the device). */
 int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi);

@@ -18,6 +18,7 @@
 #include <functional>
 #include <atomic>
 #include <map>
+#include <mutex>
 #include <random>
 #include <chrono>
 #include <set>
@@ -36,6 +37,15 @@ struct DevBuf {
   size_t cap = 0;
 };
 
+// Workspace of an allocation-free evaluation: consecutive 256-byte aligned pieces
+// of a region the caller did not have to allocate (the library's static device
+// scratch).  take() throws LFMM_ENOMEM when the region is exhausted.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  void* take(size_t bytes);
+};
+
 #define HIPCHK(x)                       \
   do {                                  \
     hipError_t _e = (x);                \
@@ -45,6 +55,13 @@ struct DevBuf {
 struct Fail {
   int code;
 };
+
+void* Arena::take(size_t bytes) {
+  const size_t off = (used + 255) & ~(size_t)255;
+  if (off > cap || bytes > cap - off) throw Fail{LFMM_ENOMEM};
+  used = off + bytes;
+  return base + off;
+}
 
 enum {
   ST_CLASSIFY, ST_TREE, ST_OPS_FREE, ST_REACT_TABLES, ST_REACT_MFMA, ST_REACT_EXPAND, ST_JOBS, ST_P2M, ST_M2M,
@@ -166,6 +183,10 @@ struct MlpNet {
   std::vector<int> lo, li;
   std::vector<long> woff, boff;
   std::map<std::string, DevBuf> bufs;
+  // during an allocation-free evaluation: pieces of the arena for buffers that
+  // would otherwise have to grow (forward-pass activations of more rows)
+  Arena* arena = nullptr;
+  std::map<std::string, DevBuf> abufs;
   void setup(int nin_, int width_, int nh_, int nout_) {
     nin = nin_;
     width = width_;
@@ -190,6 +211,14 @@ struct MlpNet {
   T* dev(const std::string& name, size_t count) {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
     DevBuf& B = bufs[name];
+    if (B.cap < bytes && arena) {
+      DevBuf& A = abufs[name];
+      if (A.cap < bytes) {
+        A.p = arena->take(bytes);
+        A.cap = bytes;
+      }
+      return (T*)A.p;
+    }
     if (B.cap < bytes) {
       if (B.p) HIPCHK(hipFree(B.p));
       B.p = nullptr;
@@ -382,10 +411,21 @@ struct lfmm_plan_s {
 
   // device workspace in use: the plan's own, or one lent by a batch worker
   std::map<std::string, DevBuf>* bufp = &bufs;
+  // allocation-free evaluation: every workspace buffer is a piece of this arena
+  // (bufp then points at a map of such pieces, which nobody frees)
+  Arena* arena = nullptr;
+  int device = 0;  // the device the plan's streams belong to
   template <typename T>
   T* dev(const char* name, size_t count) {
     size_t bytes = std::max<size_t>(count * sizeof(T), 256);
     DevBuf& B = (*bufp)[name];
+    if (arena) {
+      if (B.cap < bytes) {
+        B.p = arena->take(bytes);
+        B.cap = bytes;
+      }
+      return (T*)B.p;
+    }
     if (B.cap < bytes) {
       if (B.p) HIPCHK(hipFree(B.p));
       B.p = nullptr;
@@ -413,7 +453,7 @@ struct lfmm_plan_s {
       HIPCHK(hipEventSynchronize(pin_ev));
       pin_pending = false;
     }
-    if (pin_need > pin_cap) {
+    if (pin_need > pin_cap && !arena) {
       if (pin) (void)hipHostFree(pin);
       pin = nullptr;
       pin_cap = 0;
@@ -435,7 +475,6 @@ struct lfmm_plan_s {
     if (pin && off + bytes <= pin_cap) {
       memcpy(pin + off, v.data(), bytes);
       HIPCHK(hipMemcpyAsync(d, pin + off, bytes, hipMemcpyHostToDevice, s));
-      if (!pin_ev) HIPCHK(hipEventCreateWithFlags(&pin_ev, hipEventDisableTiming));
       HIPCHK(hipEventRecord(pin_ev, s));
       pin_pending = true;
     } else {
@@ -450,8 +489,14 @@ struct lfmm_plan_s {
   size_t rb_cap = 0, rb_used = 0;
   hipEvent_t rb_ev = nullptr;
   std::vector<std::pair<void*, std::pair<size_t, size_t>>> rb_list;  // (host dst, (offset, bytes))
+  std::vector<std::pair<void*, std::pair<const void*, size_t>>> rb_direct;  // (host dst, (device src, bytes))
   void rb_add(void* dst, const void* src, size_t bytes, hipStream_t s) {
     size_t off = (rb_used + 255) & ~(size_t)255;
+    if (arena && off + bytes > rb_cap) {
+      // no pinned buffer may be allocated now: copy this one at the flush
+      rb_direct.push_back({dst, {src, bytes}});
+      return;
+    }
     if (off + bytes > rb_cap) {
       rb_flush(s);  // empties the buffer (and waits for what it holds)
       off = 0;
@@ -469,7 +514,6 @@ struct lfmm_plan_s {
     rb_used = off + bytes;
   }
   void rb_flush(hipStream_t s) {
-    if (!rb_ev) HIPCHK(hipEventCreateWithFlags(&rb_ev, hipEventDisableTiming));
     HIPCHK(hipEventRecord(rb_ev, s));
     hipError_t e;
     while ((e = hipEventQuery(rb_ev)) == hipErrorNotReady) {
@@ -478,6 +522,8 @@ struct lfmm_plan_s {
     for (auto& d : rb_list) memcpy(d.first, rb + d.second.first, d.second.second);
     rb_list.clear();
     rb_used = 0;
+    for (auto& d : rb_direct) HIPCHK(hipMemcpy(d.first, d.second.first, d.second.second, hipMemcpyDeviceToHost));
+    rb_direct.clear();
   }
   mutable std::map<int, double> decay_memo;
   double decay_cached(int npow) const {
@@ -623,6 +669,13 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     HIPCHK(hipEventCreateWithFlags(&P->ops_ev, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&P->s3, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&P->jobs_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->pin_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&P->rb_ev, hipEventDisableTiming));
+    // the readback buffer exists before the first evaluation, so that an
+    // allocation-free evaluation finds one
+    if (hipHostMalloc((void**)&P->rb, (size_t)1 << 20, hipHostMallocDefault) != hipSuccess) throw Fail{LFMM_ENOMEM};
+    P->rb_cap = (size_t)1 << 20;
+    HIPCHK(hipGetDevice(&P->device));
   } catch (Fail& f) {
     lfmm_destroy(P);
     return f.code;
@@ -2176,6 +2229,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // generates its operators again
   if (P->bufp == &P->bufs) P->last_opsig.swap(opsig);
   else P->last_opsig.clear();
+  if (P->arena) {
+    rep.workspace_bytes = (int64_t)P->arena->used;
+  } else {
+    for (auto& kv : *P->bufp) rep.workspace_bytes += (int64_t)kv.second.cap;
+  }
   return LFMM_OK;
 }
 
@@ -2198,6 +2256,7 @@ int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int3
     (void)hipStreamSynchronize(plan->s2);
     if (plan->s3) (void)hipStreamSynchronize(plan->s3);
     plan->rb_list.clear();
+    plan->rb_direct.clear();
     plan->rb_used = 0;
     return f.code;
   }
@@ -2227,6 +2286,7 @@ int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* la
     (void)hipStreamSynchronize(plan->s2);
     if (plan->s3) (void)hipStreamSynchronize(plan->s3);
     plan->rb_list.clear();
+    plan->rb_direct.clear();
     plan->rb_used = 0;
     return f.code;
   }
@@ -2276,6 +2336,7 @@ int lfmm_eval_targets_device(lfmm_plan_t* plan, int64_t n_src, const double* src
       (void)hipStreamSynchronize(plan->s2);
       if (plan->s3) (void)hipStreamSynchronize(plan->s3);
       plan->rb_list.clear();
+      plan->rb_direct.clear();
       plan->rb_used = 0;
     }
     return f.code;
@@ -2315,6 +2376,7 @@ int lfmm_eval_targets(lfmm_plan_t* plan, int64_t n_src, const double* src_xyz, c
     (void)hipStreamSynchronize(plan->s2);
     if (plan->s3) (void)hipStreamSynchronize(plan->s3);
     plan->rb_list.clear();
+    plan->rb_direct.clear();
     plan->rb_used = 0;
     return f.code;
   }
@@ -2362,6 +2424,56 @@ int lfmm_eval_batch(int nprob, lfmm_plan_t* const* plans, const int64_t* n, cons
     if (status) status[i] = st[i];
     if (rc == LFMM_OK && st[i] != LFMM_OK) rc = st[i];
   }
+  return rc;
+}
+
+// ---- allocation-free evaluation ----
+// The library's static device scratch: every device that loads the library holds
+// one copy of it until the process ends.  In host code the array's name is only a
+// stand-in; its device address on each device comes from hipGetSymbolAddress,
+// called once per device with that device current, and only that address is used.
+static __device__ __align__(256) char scratch[LFMM_NOALLOC_BYTES];
+#define LFMM_NOALLOC_MAXDEV 64
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[LFMM_NOALLOC_MAXDEV] = {};
+
+static int scratch_of_device(int dev, char** out) {
+  if (dev < 0 || dev >= LFMM_NOALLOC_MAXDEV) return LFMM_ENOTSUP;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LFMM_EHIP;
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LFMM_OK;
+}
+
+int lfmm_eval_device_noalloc(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q,
+                             double* phi, void* stream) {
+  if (!plan) return LFMM_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LFMM_EHIP;
+  if (dev != plan->device) return LFMM_EINVAL;  // the plan's streams live on another device
+  char* base = nullptr;
+  int rc = scratch_of_device(dev, &base);
+  if (rc != LFMM_OK) return rc;
+  Arena A;
+  A.base = base;
+  A.cap = (size_t)LFMM_NOALLOC_BYTES;
+  std::map<std::string, DevBuf> pieces;  // names -> pieces of the scratch; never freed
+  plan->arena = &A;
+  plan->bufp = &pieces;
+  plan->sur.net.arena = &A;
+  rc = lfmm_eval_device(plan, n, xyz, layer, q, phi, stream);
+  // the next call on this device reuses the scratch: nothing of this one may still run
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && rc == LFMM_OK) rc = LFMM_EHIP;
+  if (hipStreamSynchronize(plan->s2) != hipSuccess && rc == LFMM_OK) rc = LFMM_EHIP;
+  if (plan->s3 && hipStreamSynchronize(plan->s3) != hipSuccess && rc == LFMM_OK) rc = LFMM_EHIP;
+  plan->arena = nullptr;
+  plan->bufp = &plan->bufs;
+  plan->sur.net.arena = nullptr;
+  plan->sur.net.abufs.clear();
   return rc;
 }
 

@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblfmm.so")
 
 LFMM_OK = 0
+NOALLOC_BYTES = 512 << 20  # LFMM_NOALLOC_BYTES of include/lfmm.h
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "not supported",
            5: "surrogate or table file error"}
 
@@ -37,7 +38,7 @@ class Report(ctypes.Structure):
                 ("p2p_pairs", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
                 ("p2p_series", ctypes.c_int), ("precision", ctypes.c_int),
                 ("stage_ms", ctypes.c_double * 24), ("n_react_surrogate", ctypes.c_int64), ("ops_reused", ctypes.c_int),
-                ("n_react_table", ctypes.c_int64)]
+                ("n_react_table", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
 
 
 class TuneReport(ctypes.Structure):
@@ -95,6 +96,7 @@ def load():
     L.lfmm_plan.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options),
                             ctypes.POINTER(vp)]
     L.lfmm_eval_device.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    L.lfmm_eval_device_noalloc.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
     L.lfmm_eval.argtypes = [vp, ctypes.c_int64, _D, ctypes.c_void_p, _D, _D]
     L.lfmm_eval_targets_device.argtypes = [vp, ctypes.c_int64, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp]
     L.lfmm_eval_targets.argtypes = [vp, ctypes.c_int64, _D, vp, _D, ctypes.c_int64, _D, vp, _D]
@@ -215,6 +217,19 @@ class Plan:
                "lfmm_eval_device")
         return phi
 
+    def eval_device_noalloc(self, xyz, q, phi, layer=None, stream=None):
+        """lfmm_eval_device_noalloc: as eval_device, with the workspace taken from the
+        library's static device scratch (no allocation); synchronous."""
+        import torch
+        n, xp = _xyz_arg(xyz, "xyz")
+        qp = _dev_arg(q, "q", torch.complex128, n, xyz.device)
+        fp = _dev_arg(phi, "phi", torch.complex128, n, xyz.device)
+        lp = _dev_arg(layer, "layer", torch.int32, n, xyz.device) if layer is not None else None
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(self.lib.lfmm_eval_device_noalloc(self.h, n, xp, lp, qp, fp, ctypes.c_void_p(s.cuda_stream)),
+               "lfmm_eval_device_noalloc")
+        return phi
+
     def eval_torch(self, x, y, z, q, layer=None):
         import torch
         dev = torch.device("cuda")
@@ -297,7 +312,7 @@ class Plan:
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
                     p2p_series=r.p2p_series, precision=r.precision,
                     n_react_surrogate=r.n_react_surrogate, ops_reused=r.ops_reused,
-                    n_react_table=r.n_react_table, stage_ms=stages)
+                    n_react_table=r.n_react_table, workspace_bytes=r.workspace_bytes, stage_ms=stages)
 
     def autotune(self, xyz, q, phi, layer=None, stream=None):
         """lfmm_autotune on torch device tensors (as eval_device); returns the tuning report."""

@@ -1,0 +1,61 @@
+"""The allocation-free entry point (lfmm_eval_device_noalloc) against lfmm_eval_device:
+two calls in a row, the second with a smaller input, each bit-identical to the
+ordinary evaluation of the same particles; a problem whose workspace exceeds the
+static scratch is rejected with LFMM_ENOMEM and leaves the plan usable."""
+import numpy as np
+import pytest
+
+from paper_1902_05132_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(w):
+    import torch
+    dev = torch.device("cuda:0")
+    xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+    q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+    return xyz, q
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_noalloc_matches_eval_device_twice(prec):
+    import torch
+    from paper_1902_05132_amd import lfmm
+    big = W.small_three_layer(n_per_layer=400, seed=61, p=4, leaf=16)
+    small = W.small_three_layer(n_per_layer=90, seed=62, p=4, leaf=16)
+    ref_plan = lfmm.Plan(big["d"], big["k"], p=4, leaf_max=16, precision=prec)
+    na_plan = lfmm.Plan(big["d"], big["k"], p=4, leaf_max=16, precision=prec)
+    for w in (big, small):
+        xyz, q = _dev(w)
+        ref = torch.empty_like(q)
+        ref_plan.eval_device(xyz, q, ref)
+        torch.cuda.synchronize()
+        need = ref_plan.report()["workspace_bytes"]
+        out = torch.full_like(q, complex(np.nan, np.nan))
+        na_plan.eval_device_noalloc(xyz, q, out)
+        rep = na_plan.report()
+        print("n=%d: workspace %.1f MB (ordinary evaluation %.1f MB), scratch %.0f MB" % (
+            len(w["x"]), rep["workspace_bytes"] / 1e6, need / 1e6, lfmm.NOALLOC_BYTES / 1e6))
+        assert 0 < rep["workspace_bytes"] <= lfmm.NOALLOC_BYTES
+        assert torch.equal(out, ref)
+
+
+def test_noalloc_rejects_oversized_workspace_and_recovers():
+    import torch
+    from paper_1902_05132_amd import lfmm
+    w = W.three_layer_cubes(n=98304, seed=63, p=8, leaf=64)
+    P = lfmm.Plan(w["d"], w["k"], p=8, leaf_max=64)
+    xyz, q = _dev(w)
+    out = torch.empty_like(q)
+    with pytest.raises(lfmm.LfmmError) as e:
+        P.eval_device_noalloc(xyz, q, out)
+    assert e.value.code == 2
+    s = W.small_three_layer(n_per_layer=50, seed=64, p=8, leaf=16)
+    xs, qs = _dev(s)
+    a, b = torch.empty_like(qs), torch.empty_like(qs)
+    P2 = lfmm.Plan(s["d"], s["k"], p=8, leaf_max=16)
+    P.eval_device(xs, qs, a)
+    P2.eval_device(xs, qs, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
