@@ -33,6 +33,17 @@ PEAK = {("mfma", 64): 78.6, ("mfma", 32): 157.3, ("alu", 64): 78.6, ("alu", 32):
 # -(kr)^2 (1), series (6 + 6 fma), -cos(kr)/(kr) (2), complex multiply-add (8) = 50.
 P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}  # series forms for k r <= 1
 P2P_SHORT_FLOPS_PER_PAIR = {64: 55, 32: 42}  # the shorter series for k r <= 1/2
+# what one near-field pair needs by the method's own count: differences, r^2, k r, the complex
+# multiply-add (about 20 flops) and sqrt, reciprocal, sin, cos (one operation each)
+P2P_ALG_OPS_PER_PAIR = 24
+# P2M / L2P work per point: (p+1)^2 complex multiply-adds plus the Phat and j_n recurrences, about
+# 18 (p+1)^2 flops; bytes the method must move: P2M reads x, y, z, q (40 B) per point and writes
+# (p+1)^2 complex (16 B each) per leaf; L2P reads x, y, z (24 B) per target, (p+1)^2 complex per leaf
+# and writes one complex potential (16 B) per target
+HBM_PEAK_GBS = 8000.0
+# distinct Sommerfeld integrals per reaction class (the reduced form of the M2L integrals:
+# (|m - m'|, |m| + |m'| + 2 s) pairs times the four (mu, nu) families) at the orders the bench runs
+REDUCED_INTEGRALS = {4: 111, 5: 159, 6: 215, 8: 351, 10: 519}
 TOL_MIXED = 1e-6  # the mixed path is the headline only if it stays this close to the FP64 path
 MIXED_QUAD_TOL = 1e-10
 TABLE_H = (0.03, 1.0)  # box sizes the tables cover (every level of the bench workload's trees)
@@ -329,27 +340,54 @@ def main():
         # main: the kernel has the GPU to itself on the main stream; second: it runs on
         # the operator stream beside the main stream's P2M and near field, so its
         # event-timed duration includes sharing the GPU and understates its own rate
-        cands = [dict(kernel="k_m2l_gemm" + sfx, stage="m2l", bound="mfma", bits=bits, stream="main",
-                      flops=8.0 * nc * nc * rep["m2l_pairs"],
+        cands = [dict(kernel="k_m2l_gemm" + ("32" if precision else "64"), stage="m2l", bound="mfma", bits=bits,
+                      stream="main", flops=8.0 * nc * nc * rep["m2l_pairs"],
                       what="M2L, batched complex %s GEMM" % ("FP32 MFMA" if precision else "FP64 MFMA")),
                  dict(kernel="k_react_mfma", stage="react_mfma", bound="mfma", bits=64, stream="second",
                       flops=8.0 * nt * nc * rep["n_react_nodes"],
+                      reduced=(8.0 * REDUCED_INTEGRALS[args.p] * rep["n_react_nodes"]
+                               if args.p in REDUCED_INTEGRALS else None),
                       what="reaction M2L integrals, node sums on FP64 MFMA (overlapped with the main stream)")]
         if rep.get("p2p_series"):
             cands.append(dict(kernel="k_p2p_free" + sfx, stage="p2p_free", bound="alu", bits=bits, stream="main",
-                              flops=float((P2P_SHORT_FLOPS_PER_PAIR if rep["p2p_series"] == 2 else P2P_FLOPS_PER_PAIR)[bits])
-                              * rep["p2p_pairs"],
+                              flops=float(P2P_ALG_OPS_PER_PAIR) * rep["p2p_pairs"],
+                              impl=float((P2P_SHORT_FLOPS_PER_PAIR if rep["p2p_series"] == 2
+                                          else P2P_FLOPS_PER_PAIR)[bits]) * rep["p2p_pairs"],
                               what="free-space near field, %s vector ALU" % ("FP32" if precision else "FP64")))
         rooflines = []
         for c in cands:
             t = stages[c["stage"]] / 1000.0
             ach = c["flops"] / t / 1e12 if t > 0 else 0.0
             peak = PEAK[(c["bound"], c["bits"])]
-            rooflines.append({"kernel": c["kernel"], "what": c["what"], "stream": c["stream"], "bound": c["bound"],
-                              "achieved": ach,
-                              "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                              "traffic": profiled_traffic(c["kernel"], n, args.p, args.leaf, args.seed),
-                              "algorithmic_flops_per_launch": c["flops"], "launch_ms": stages[c["stage"]]})
+            r = {"kernel": c["kernel"], "what": c["what"], "stream": c["stream"], "bound": c["bound"],
+                 "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                 "traffic": profiled_traffic(c["kernel"], n, args.p, args.leaf, args.seed),
+                 "algorithmic_flops_per_launch": c["flops"], "launch_ms": stages[c["stage"]]}
+            if c.get("impl"):
+                # the operations the kernel's series form of h0 executes per pair
+                r["achieved_impl"] = c["impl"] / t / 1e12 if t > 0 else 0.0
+                r["frac_impl"] = r["achieved_impl"] / peak
+            if c.get("reduced"):
+                # the reduced form needs only the distinct integrals of a class per node
+                r["achieved_reduced"] = c["reduced"] / t / 1e12 if t > 0 else 0.0
+                r["frac_reduced"] = r["achieved_reduced"] / peak
+            rooflines.append(r)
+        # P2M and L2P against HBM (with their recurrence work on the vector ALU beside)
+        for kname, stage, pts, leaves, bpp, bpl in (
+                ("k_p2m<%d>" % args.p, "p2m", rep["p2m_points"], rep["p2m_leaves"], 40, 16 * nc),
+                ("k_l2p<%d>" % args.p, "l2p", rep["l2p_points"], rep["l2p_leaves"], 24 + 16, 16 * nc)):
+            t = stages[stage] / 1000.0
+            if t <= 0 or pts <= 0:
+                continue
+            nbytes = float(bpp * pts + bpl * leaves)
+            gbs = nbytes / t / 1e9
+            alu = 18.0 * nc * pts / t / 1e12
+            rooflines.append({"kernel": kname, "what": "%s, FP64 recurrences and sums" % stage.upper(),
+                              "stream": "main", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                              "algorithmic_bytes_per_launch": nbytes, "launch_ms": stages[stage],
+                              "alu_achieved": alu, "alu_peak": PEAK[("alu", 64)],
+                              "alu_frac": alu / PEAK[("alu", 64)]})
         log("bench: precision %d: %d steps, %.3f ms/step, %.4g evals/s" % (precision, args.steps, ms, n / ms * 1e3))
         if args.stages:
             for kname, v in stages.items():

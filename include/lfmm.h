@@ -93,6 +93,8 @@ typedef struct {
   int64_t n_react_table;     /* reaction classes whose integrals came from the pre-computed tables */
   int64_t workspace_bytes;   /* device workspace the evaluation used (its buffers' capacities; for
                                 lfmm_eval_device_noalloc, the part of the static scratch it took) */
+  int64_t p2m_points, p2m_leaves; /* points (particles and polarisation images) and leaves of the P2M */
+  int64_t l2p_points, l2p_leaves; /* targets and leaves of the L2P */
 } lfmm_report;
 
 /*

@@ -383,7 +383,7 @@ struct lfmm_plan_s {
   int reuse_ops = 0;  // 1: keep the operators of the last evaluation when its trees are the same
   std::string last_opsig;  // what those operators were generated from
   int prec_parts;  // which stages the mixed path runs in FP32: 1 near field, 2 M2L (both by default)
-  int gemm_ks;   // M2L GEMM: waves sharing a 16-target tile (0 = chosen from the tile count)
+  int gemm_ks;   // M2L GEMM: waves sharing a 16-target tile (0: 4)
   int p2p_ta;    // near field: targets per wave step (64 / p2p_ta sources)
   int p2p_ch;    // near field: sources per LDS tile
   double kmax;
@@ -1603,8 +1603,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       seg_row0.push_back(first_row(t, T.depth));
       seg_prefix.push_back(ptot);
       ptot += nbox(t, T.depth);
+      rep.p2m_points += T.npts;
     }
   }
+  rep.p2m_leaves = ptot;
   sbeg(ST_P2M, s);
   if (ptot) {
     int* d_r0 = P->upload("p2m_r0", seg_row0, s);
@@ -2060,7 +2062,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   std::vector<int> gs_m2m, gs_l2l, gs_m2l, bf_m2m, bc_m2m, bf_l2l, bc_l2l, bf_m2l, bc_m2l;
   // M2L: four waves share each 16-target tile and split its operator sequence
   // (fastest on both shallow and deep trees)
-  int ks_m2l = P->gemm_ks > 0 ? P->gemm_ks : 4;
+  const int ks_m2l = P->gemm_ks > 0 ? P->gemm_ks : 4;
   // M2M: the waves of a 16-target tile split each parent's eight child operators
   // (a level's parents alone give too few 64-target blocks to fill the GPU)
   static const int ks_m2m = getenv("LFMM_M2M_KS") ? atoi(getenv("LFMM_M2M_KS")) : 4;  // tuning override
@@ -2090,8 +2092,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     lk_src_m2l(ne_m2l, J_m2l.srowid, J_m2l.sgid, d_gseq0, d_gK, d_tmpl, kmax_m2l, box_code, box_level, d_grid_off,
                grid, sr_m2l, d_cnt + 0, sj);
   GBlock* d_bm2m = P->upload("b_m2m", b_m2m, sj);
-  GBlock* d_bl2l = P->upload("b_l2l", b_l2l, sj);
   GBlock* d_bm2l = P->upload("b_m2l", b_m2l, sj);
+  GBlock* d_bl2l = P->upload("b_l2l", b_l2l, sj);
   int* d_sq_m2m = P->upload("sq_m2m", seq_m2m, sj);
   int* d_sq_l2l = P->upload("sq_l2l", seq_l2l, sj);
   int* d_sq_m2l = P->upload("sq_m2l", seq_m2l, sj);
@@ -2103,7 +2105,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   sbeg(ST_M2M, s);
   for (int lp = Dmax - 1; lp >= 2; lp--)
     if (bc_m2m[lp] > 0)
-      lk_gemm(0, P->NRT, ks_m2m, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
+      lk_gemm(P->NRT, ks_m2m, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
               NCK, NC, s);
   send(ST_M2M, s);
   // and the reaction operators from here on
@@ -2116,16 +2118,17 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     float* M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
     lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, s);
     sbeg(ST_M2L, s);
-    lk_gemm32(P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops32, opsz, NKS,
-              M32, Lx, NCK, NC, box_tree, box_level, d_sc, s);
-  } else if (!b_m2l.empty())
-    lk_gemm(1, P->NRT, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
-            Lx, NCK, NC, s);
+    lk_gemm32(NC, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops32, opsz, NKS, M32,
+              Lx, NCK, box_tree, box_level, d_sc, s);
+  } else if (!b_m2l.empty()) {
+    lk_m2l_gemm64(NC, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
+                  Lx, NCK, s);
+  }
   mark(10);
   // ---------------- downward pass
   for (int l = 3; l <= Dmax; l++)
     if (bc_l2l[l] > 0)
-      lk_gemm(0, P->NRT, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx,
+      lk_gemm(P->NRT, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx,
               NCK, NC, s);
   mark(11);
   {
@@ -2137,8 +2140,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
         s0.push_back(T.pt_off);
         pf.push_back(tot);
         tot += T.npts;
+        rep.l2p_leaves += nbox(t, T.depth);
       }
     }
+    rep.l2p_points = tot;
     if (tot) {
       int* d_s0 = P->upload("l2p_s0", s0, s);
       int* d_pf = P->upload("l2p_pf", pf, s);
@@ -2528,10 +2533,16 @@ const char* lfmm_status_string(int status) {
   }
 }
 
-static void unpack_op(const std::vector<double>& pk, int NC, int NKS, double* out) {
+// Operator from its packed form: the shift GEMM's row-tile-major tiles, or (m2l)
+// the M2L GEMMs' k-step-major layout with its last-row entries.
+static void unpack_op(const std::vector<double>& pk, int NC, int NKS, bool m2l, double* out) {
+  const int NRT = m2l_nrt(NC), XR = m2l_xr(NC), SZ = NRT * 64 + 4 * XR;
   for (int r = 0; r < NC; r++)
     for (int c = 0; c < NC; c++) {
-      size_t pp = ((size_t)((r >> 4) * NKS + (c >> 2)) << 7) + 2 * (size_t)((r & 15) | ((c & 3) << 4));
+      size_t pp;
+      if (!m2l) pp = ((size_t)((r >> 4) * NKS + (c >> 2)) << 7) + 2 * (size_t)((r & 15) | ((c & 3) << 4));
+      else if (r < NRT * 16) pp = 2 * ((size_t)(c >> 2) * SZ + (r >> 4) * 64 + (r & 15) + 16 * (c & 3));
+      else pp = 2 * ((size_t)(c >> 2) * SZ + NRT * 64 + (c & 3));
       out[2 * ((size_t)r * NC + c)] = pk[pp];
       out[2 * ((size_t)r * NC + c) + 1] = pk[pp + 1];
     }
@@ -2548,7 +2559,7 @@ int lfmm_translation(lfmm_plan_t* plan, int kind, double kw, const double* b, do
     lk_transop(1, dd, ops, plan->opsz, plan->p, plan->NC, plan->NKS, plan->d_gaunt, nullptr, nullptr, nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
-    unpack_op(pk, plan->NC, plan->NKS, out);
+    unpack_op(pk, plan->NC, plan->NKS, kind == 1, out);
   } catch (Fail& f) {
     return f.code;
   }
@@ -2584,7 +2595,7 @@ int lfmm_reaction_operator(lfmm_plan_t* plan, int l, int a, int lp, int b, doubl
     lk_react_expand(1, dr, I, ops, plan->opsz, plan->p, NC, plan->NKS, nullptr, nullptr, nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
-    unpack_op(pk, NC, plan->NKS, out);
+    unpack_op(pk, NC, plan->NKS, true, out);
   } catch (Fail& f) {
     return f.code;
   }
@@ -2986,7 +2997,8 @@ int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t
     *ms = best;
     return LFMM_OK;
   };
-  const int ks0 = plan->gemm_ks, ta0 = plan->p2p_ta, ch0 = plan->p2p_ch;
+  const int ks0 = plan->gemm_ks > 0 ? plan->gemm_ks : 4, ta0 = plan->p2p_ta, ch0 = plan->p2p_ch;
+  plan->gemm_ks = ks0;
   double best;
   int rc = timed(&best);
   if (rc != LFMM_OK) return rc;
@@ -3027,7 +3039,7 @@ int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t
     return rc;
   }
   if ((rc = eval_impl(plan, n, xyz, layer, q, phi, s)) != LFMM_OK) return rc;
-  R.gemm_ks = plan->gemm_ks > 0 ? plan->gemm_ks : 4;
+  R.gemm_ks = plan->gemm_ks;
   R.p2p_ta = plan->p2p_ta;
   R.p2p_ch = plan->p2p_ch;
   R.ms_best = best;

@@ -106,6 +106,14 @@ struct GBlock {
   int K;      // number of operators in the group
 };
 
+// M2L operators (FP64, and FP32 in the mixed path) are stored k-step by k-step (4
+// source coefficients each): the NRT full tiles of 16 rows in MFMA A-operand lane
+// order (lane = row % 16 + 16 (col % 4)), then, when (p+1)^2 = 16 NRT + 1, the 4
+// values of the last row, which the GEMM accumulates on the vector ALU instead of
+// in a sixteen-row tile that would hold one useful row.  (M2M and L2L operators keep
+// the row-tile-major layout of the shift GEMM.)
+__host__ __device__ inline int m2l_nrt(int NC) { return (NC % 16 == 1) ? NC / 16 : (NC + 15) / 16; }
+__host__ __device__ inline int m2l_xr(int NC) { return (NC % 16 == 1) ? 1 : 0; }
 // Near-field reaction pair table for one (target tree, source tree) component.
 struct NFComp {
   int node0, nnodes;  // node range in the node tables
@@ -155,9 +163,9 @@ void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, con
 void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int total, const int* leafrow, const int* box_code,
             const int* box_tree, const int* box_level, const TreeInfo* trees, const double* px, const double* py,
             const double* pz, const int* sg, int p, int NCK, const double* Lc, double* phi_tp, hipStream_t s);
-void lk_gemm(int m2l, int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
-             const int* srow, int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D,
-             int NCK, int NC, hipStream_t s);
+void lk_gemm(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
+             int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D, int NCK, int NC,
+             hipStream_t s);
 void lk_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree, const int* box_level,
                   const TreeInfo* trees, const int* gbase, int nlev1, int* gid, int* rowid, hipStream_t s);
 // also adds the number of slots with a source present to *npairs
@@ -175,9 +183,14 @@ void lk_p2p_free(int nseg, const int* seg_row0, const int* seg_prefix, int total
                  int ta, int ch, int f32, unsigned long long* npairs, hipStream_t s);
 void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box_level, const int* se,
                  const double* M, float* M32, hipStream_t s);
-void lk_gemm32(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
-               int srow_stride, const float* ops, int opsz, int NKS, const float* S, double* D, int NCK, int NC,
+// M2L GEMMs: blocks of 16 x (4 / ks) targets, ks waves splitting each tile's operator
+// sequence; srow_stride is the longest sequence
+void lk_gemm32(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
+               int srow_stride, const float* ops, int opsz, int NKS, const float* S, double* D, int NCK,
                const int* box_tree, const int* box_level, const int* se, hipStream_t s);
+void lk_m2l_gemm64(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
+                   int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D, int NCK,
+                   hipStream_t s);
 void lk_nf_nodes(int nnodes, Rule rule, Stack st, int lt, int ls, int a, int b, double* nkr, double* nfac,
                  double* nkzt, double* nkzs, hipStream_t s);
 void lk_nf_react(int nleaf, int row0, int ttree, int ncomp, const NFComp* comps, const int* box_start,

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
+#include <type_traits>
 
 #include "lfmm_internal.h"
 
@@ -523,6 +524,19 @@ __device__ __forceinline__ void packed_rc(int e, int NKS, int* row, int* col) {
   *col = (tile % NKS) * 4 + (lane >> 4);
 }
 
+// Entry e of an operator in the FP32 M2L layout (k-step major; see m2l32_nrt):
+// k-step e / SZ, then within it the NRT tiles in lane order and the last row.
+__device__ __forceinline__ void m2l_packed_rc(int e, int NRT, int XR, int* row, int* col) {
+  const int SZ = NRT * 64 + 4 * XR, ks = e / SZ, r = e - ks * SZ;
+  if (r < NRT * 64) {
+    *row = (r >> 6) * 16 + (r & 15);
+    *col = ks * 4 + ((r & 63) >> 4);
+  } else {
+    *row = NRT * 16;
+    *col = ks * 4 + (r - NRT * 64);
+  }
+}
+
 // Free-space translation operators (Section 2.1 addition theorems):
 //   Op[(n,m),(nu,mu)] = 4 pi i^{n-nu} sum_q i^q z_q(k|b|) conj(Y_q^{m-mu}(b^)) G(nu,mu; q,m-mu; n)
 // G tabulated per (row, col, j), q = |n - nu| + 2 j.  One workgroup per operator.
@@ -591,9 +605,13 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
   const int2 se = f32 ? opse[D.op] : make_int2(0, 0);
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   int P1 = p + 1;
-  for (int e = threadIdx.x; e < NR * NK; e += 256) {
+  const int nrtl = m2l_nrt(NC), xrl = m2l_xr(NC);
+  const bool m2l_lay = D.kind == 1;
+  const int ntot = m2l_lay ? NKS * (nrtl * 64 + 4 * xrl) : NR * NK;
+  for (int e = threadIdx.x; e < ntot; e += 256) {
     int row, col;
-    packed_rc(e, NKS, &row, &col);
+    if (m2l_lay) m2l_packed_rc(e, nrtl, xrl, &row, &col);
+    else packed_rc(e, NKS, &row, &col);
     cd val = mk(0, 0);
     if (row < NC && col < NC) {
       const int n = nmt[row].x, mm = nmt[row].y, nu = nmt[col].x, mu = nmt[col].y;
@@ -1033,11 +1051,12 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
   double* out = ops + (size_t)R.op * opsz;
   float* out32 = ops32 ? ops32 + (size_t)R.op * opsz : nullptr;
   const int2 se = ops32 ? opse[R.op] : make_int2(0, 0);
-  int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   double pre = 4.0 * LFMM_PI / R.kt;
-  for (int e = threadIdx.x; e < NR * NK; e += 256) {
+  const int nrtl = m2l_nrt(NC), xrl = m2l_xr(NC);
+  const int ntot = NKS * (nrtl * 64 + 4 * xrl);
+  for (int e = threadIdx.x; e < ntot; e += 256) {
     int row, col;
-    packed_rc(e, NKS, &row, &col);
+    m2l_packed_rc(e, nrtl, xrl, &row, &col);
     cd val = mk(0, 0);
     if (row < NC && col < NC) {
       const int n = nmt[row].x, m = nmt[row].y, n2 = nmt[col].x, m2 = nmt[col].y;
@@ -1173,13 +1192,14 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
   }
   __syncthreads();
-  // one thread per output (sign, m, n >= m; no sign 1 for m = 0): the stripes are
-  // summed in a fixed order
+  // one thread per output (sign, m, n >= m; no sign 1 for m = 0; 2 NOUT exceeds the
+  // block at P = 10, so the threads stride over the outputs): the stripes are summed
+  // in a fixed order
   double* Mr = M + (size_t)R * NCK * 2;
   constexpr int NOUT = P1 * (P1 + 1) / 2;
-  if (tid < 2 * NOUT) {
-    const int half = tid / NOUT;
-    int mm = 0, r = tid % NOUT;
+  for (int o = tid; o < 2 * NOUT; o += 128) {
+    const int half = o / NOUT;
+    int mm = 0, r = o % NOUT;
     while (r >= P1 - mm) {
       r -= P1 - mm;
       mm++;
@@ -1437,15 +1457,6 @@ __device__ __forceinline__ void gemm_body(const GBlock* blocks, const int* seq, 
       }
     }
 }
-// M2L (free-space and reaction operators): its own kernel name so that traces
-// time it apart from the shift GEMMs
-template <int NRT, int KS>
-__global__ __launch_bounds__(256) void k_m2l_gemm(const GBlock* blocks, const int* seq, const int* trow,
-                                                  const int* srow, int srow_stride, const double* __restrict__ ops,
-                                                  int opsz, int NKS, const double2* __restrict__ S, double2* D,
-                                                  int NCK, int NC) {
-  gemm_body<NRT, KS>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S, D, NCK, NC);
-}
 // M2M and L2L
 template <int NRT, int KS>
 __global__ __launch_bounds__(256) void k_shift_gemm(const GBlock* blocks, const int* seq, const int* trow,
@@ -1454,21 +1465,17 @@ __global__ __launch_bounds__(256) void k_shift_gemm(const GBlock* blocks, const 
                                                     int NCK, int NC) {
   gemm_body<NRT, KS>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S, D, NCK, NC);
 }
-extern "C" void lk_gemm(int m2l, int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+extern "C" void lk_gemm(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
                         const int* srow, int srow_stride, const double* ops, int opsz, int NKS, const double* S,
                         double* D, int NCK, int NC, hipStream_t s) {
   if (!nblocks) return;
   const double2* S2 = (const double2*)S;
   double2* D2 = (double2*)D;
-#define GEMM_CASE(N, K)                                                                                          \
-  if (nrt == N && ks == K) {                                                                                     \
-    if (m2l)                                                                                                     \
-      k_m2l_gemm<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, \
-                                               NC);                                                              \
-    else                                                                                                         \
-      k_shift_gemm<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2,   \
-                                                 NCK, NC);                                                       \
-    return;                                                                                                      \
+#define GEMM_CASE(N, K)                                                                                        \
+  if (nrt == N && ks == K) {                                                                                   \
+    k_shift_gemm<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, \
+                                               NC);                                                            \
+    return;                                                                                                    \
   }
   GEMM_CASE(1, 1) GEMM_CASE(2, 1) GEMM_CASE(3, 1) GEMM_CASE(4, 1) GEMM_CASE(5, 1) GEMM_CASE(6, 1) GEMM_CASE(7, 1)
   GEMM_CASE(8, 1) GEMM_CASE(1, 2) GEMM_CASE(2, 2) GEMM_CASE(3, 2) GEMM_CASE(4, 2) GEMM_CASE(5, 2) GEMM_CASE(6, 2)
@@ -1510,164 +1517,326 @@ extern "C" void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, con
   if (n) k_m_to_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(nrows, NCK, NC, box_tree, box_level, se,
                                                                 (const double2*)M, (float2*)M32);
 }
-template <int NRT, int KS>
-__global__ __launch_bounds__(256) void k_m2l_gemm32(const GBlock* blocks, const int* seq, const int* trow,
-                                                    const int* srow, int srow_stride, const float* __restrict__ ops,
-                                                    int opsz, int NKS, const float2* __restrict__ S, double2* D,
-                                                    int NCK, int NC, const int* box_tree, const int* box_level,
-                                                    const int* se) {
-  GBlock bd = blocks[xcd_block(blockIdx.x, gridDim.x)];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = lane & 15, kr = lane >> 4;
+// M2L on the matrix cores (FP32 in the mixed path, FP64 otherwise).  A wave owns
+// 16 targets of one group (the B columns: source expansions gathered by row) and
+// every row of the output; the KS waves of a workgroup take every KS-th operator of
+// the group's sequence and add their partial sums through LDS at the end, in a
+// fixed order.  Before the loop each wave lists the operators for which at least
+// one of its targets has a source (the others would only multiply zeros), with the
+// source rows, in LDS; the loop then runs over the (operator, k-step) steps of that
+// list with the operands of the next PF steps in flight in registers.  Operators
+// are stored k-step major (see m2l_nrt), so one step's operand is NRT contiguous
+// 512-byte (FP32) or 1 KB (FP64) tiles.  The complex product takes three real
+// MFMAs (Gauss's method: P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi),
+// re = P1 - P2, im = P3 - P1 - P2) where the registers allow, four otherwise; a
+// last row that would be alone in its sixteen-row tile (XR) is summed on the
+// vector ALU.  The FP32 kernel moves each operator's sums into FP64 accumulators
+// when the operator is done.
+template <typename R>
+struct M2LT {
+  typedef typename std::conditional<sizeof(R) == 4, float2, double2>::type C2;
+  typedef typename std::conditional<sizeof(R) == 4, v4f, v4d>::type V4;
+};
+__device__ __forceinline__ v4f mfma16(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// lst: this wave's lists in LDS: lmax operator ids, then lmax x 16 source rows (one
+// per target column).  Every load of the main loop is unconditional (addresses
+// clamped, absent sources zeroed by a flag where the value is used), so that the
+// compiler can keep PF steps of loads in flight instead of waiting for all of them.
+template <typename R, int NRT, int XR, int KS, int PF, bool G3>
+__device__ __forceinline__ void m2l_body(const GBlock& bd, const int* seq, const int* srow, int srow_stride,
+                                         const typename M2LT<R>::C2* __restrict__ ops, size_t opstride, int NKS,
+                                         const typename M2LT<R>::C2* __restrict__ S, int NCK, v4d (&dre)[NRT],
+                                         v4d (&dim)[NRT], double& dxre, double& dxim, int* lst, int lmax) {
+  typedef typename M2LT<R>::C2 C2;
+  typedef typename M2LT<R>::V4 V4;
+  constexpr bool F32 = sizeof(R) == 4;
+  constexpr int SZ = NRT * 64 + 4 * XR;
+  constexpr int NA = NRT + XR;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, kr = lane >> 4;
   const int cg = wave / KS, kw = wave % KS;
   const int tt = cg * 16 + col;
   const bool tv = tt < bd.nt;
-  const int ee = bd.e0 + (tv ? tt : 0);
-  const int* my_srow = srow + (size_t)ee * srow_stride;
-  v4f accr[NRT], acci[NRT];
-  v4d dr[NRT], di[NRT];  // FP64 sums of the per-operator FP32 partial sums
-#pragma unroll
-  for (int i = 0; i < NRT; i++) {
-    accr[i] = (v4f){0, 0, 0, 0};
-    acci[i] = (v4f){0, 0, 0, 0};
-    dr[i] = (v4d){0, 0, 0, 0};
-    di[i] = (v4d){0, 0, 0, 0};
-  }
-  const float2* A2 = (const float2*)ops;
-  const size_t opstride = (size_t)(opsz >> 1);
-  int kk = kw, sr = -1;
-  while (kk < bd.K) {
-    sr = tv ? my_srow[kk] : -1;
-    if (__ballot(sr >= 0)) break;
-    kk += KS;
-  }
-  if (kk < bd.K) {
-    const float2* A = A2 + (size_t)seq[bd.seq0 + kk] * opstride;
-    const float2* B = S + (size_t)(sr >= 0 ? sr : 0) * NCK + kr;
-    bool bv = sr >= 0;
-    float2 a_cur[NRT], b_cur;
-#pragma unroll
-    for (int rt = 0; rt < NRT; rt++) a_cur[rt] = A[((size_t)(rt * NKS) << 6) + lane];
-    b_cur = bv ? B[0] : make_float2(0.f, 0.f);
-    while (true) {
-      int kn = kk + KS, srn = -1, opn = 0;
-      if (kn < bd.K) {
-        srn = tv ? my_srow[kn] : -1;
-        opn = seq[bd.seq0 + kn];
-      }
-      for (int ks = 0; ks < NKS; ks++) {
-        float2 a_nxt[NRT], b_nxt;
-        if (ks + 1 < NKS) {
-#pragma unroll
-          for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS + ks + 1) << 6) + lane];
-          b_nxt = bv ? B[(ks + 1) * 4] : make_float2(0.f, 0.f);
-        } else {
-          while (kn < bd.K && !__ballot(srn >= 0)) {
-            kn += KS;
-            if (kn < bd.K) {
-              srn = tv ? my_srow[kn] : -1;
-              opn = seq[bd.seq0 + kn];
-            }
-          }
-          if (kn < bd.K) {
-            A = A2 + (size_t)opn * opstride;
-            B = S + (size_t)(srn >= 0 ? srn : 0) * NCK + kr;
-            bv = srn >= 0;
-#pragma unroll
-            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS) << 6) + lane];
-            b_nxt = bv ? B[0] : make_float2(0.f, 0.f);
-          } else {
-#pragma unroll
-            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = a_cur[rt];
-            b_nxt = b_cur;
-          }
-        }
-#pragma unroll
-        for (int rt = 0; rt < NRT; rt++) {
-          accr[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[rt].x, b_cur.x, accr[rt], 0, 0, 0);
-          acci[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[rt].x, b_cur.y, acci[rt], 0, 0, 0);
-          accr[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a_cur[rt].y, b_cur.y, accr[rt], 0, 0, 0);
-          acci[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[rt].y, b_cur.x, acci[rt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int rt = 0; rt < NRT; rt++) a_cur[rt] = a_nxt[rt];
-        b_cur = b_nxt;
-      }
-      // one operator done: move its partial sums to FP64
-#pragma unroll
-      for (int rt = 0; rt < NRT; rt++) {
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-          dr[rt][r] += (double)accr[rt][r];
-          di[rt][r] += (double)acci[rt][r];
-        }
-        accr[rt] = (v4f){0, 0, 0, 0};
-        acci[rt] = (v4f){0, 0, 0, 0};
-      }
-      if (kn >= bd.K) break;
-      kk = kn;
+  const int* my_srow = srow + (size_t)(bd.e0 + (tv ? tt : 0)) * srow_stride;
+  int* lop = lst;
+  int* lsr = lst + lmax;
+  // this wave's operators with a source for at least one of its targets, with the
+  // source row of each target column
+  int nv = 0;
+  for (int k = kw; k < bd.K; k += KS) {
+    const int sr = tv ? my_srow[k] : -1;
+    if (__ballot(sr >= 0)) {
+      if (lane == 0) lop[nv] = seq[bd.seq0 + k];
+      if (kr == 0) lsr[nv * 16 + col] = sr;
+      nv++;
     }
   }
+  if (nv == 0) return;
+  __builtin_amdgcn_wave_barrier();
+  const int T = nv * NKS;
+  int ak = 0, aks = 0, ls = 0;  // next step to load: operator ak of the list, k-step aks; its index ls
+  auto load = [&](C2 (&a)[NA], C2& b, bool& bv) {
+    const int akc = ak < nv ? ak : nv - 1;  // past the end: a valid address, the value unused
+    const C2* A = ops + (size_t)lop[akc] * opstride + (size_t)aks * SZ;
+#pragma unroll
+    for (int rt = 0; rt < NRT; rt++) a[rt] = A[rt * 64 + lane];
+    if constexpr (XR) a[NRT] = A[NRT * 64 + kr];
+    const int sr = lsr[akc * 16 + col];
+    bv = sr >= 0 && ls < T;
+    b = S[(size_t)(sr >= 0 ? sr : 0) * NCK + 4 * aks + kr];
+    ls++;
+    aks++;
+    ak += aks == NKS;
+    aks = aks == NKS ? 0 : aks;
+  };
+  V4 p1[NRT], p2[NRT], p3[NRT];
+#pragma unroll
+  for (int rt = 0; rt < NRT; rt++) {
+    p1[rt] = V4{0, 0, 0, 0};
+    p2[rt] = V4{0, 0, 0, 0};
+    p3[rt] = V4{0, 0, 0, 0};
+  }
+  R xre = 0, xim = 0;
+  C2 af[PF][NA], bf[PF];
+  bool bv[PF];
+#pragma unroll
+  for (int u = 0; u < PF; u++) load(af[u], bf[u], bv[u]);
+  int cks = 0;
+  auto flush = [&]() {
+#pragma unroll
+    for (int rt = 0; rt < NRT; rt++) {
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const double q1 = (double)p1[rt][r], q3 = (double)p3[rt][r];
+        if constexpr (G3) {
+          const double q2 = (double)p2[rt][r];
+          dre[rt][r] += q1 - q2;
+          dim[rt][r] += q3 - q1 - q2;
+        } else {
+          dre[rt][r] += q1;
+          dim[rt][r] += q3;
+        }
+      }
+      p1[rt] = V4{0, 0, 0, 0};
+      p2[rt] = V4{0, 0, 0, 0};
+      p3[rt] = V4{0, 0, 0, 0};
+    }
+    if constexpr (XR) {
+      dxre += (double)xre;
+      dxim += (double)xim;
+      xre = 0;
+      xim = 0;
+    }
+  };
+  auto step = [&](C2 (&a)[NA], C2& b_, bool& bv_) {
+    const C2 b = bv_ ? b_ : C2{0, 0};
+    if constexpr (G3) {
+      const R bs = b.x + b.y;
+#pragma unroll
+      for (int rt = 0; rt < NRT; rt++) {
+        p1[rt] = mfma16(a[rt].x, b.x, p1[rt]);
+        p2[rt] = mfma16(a[rt].y, b.y, p2[rt]);
+        p3[rt] = mfma16(a[rt].x + a[rt].y, bs, p3[rt]);
+      }
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < NRT; rt++) {
+        p1[rt] = mfma16(a[rt].x, b.x, p1[rt]);
+        p3[rt] = mfma16(a[rt].x, b.y, p3[rt]);
+        p1[rt] = mfma16(-a[rt].y, b.y, p1[rt]);
+        p3[rt] = mfma16(a[rt].y, b.x, p3[rt]);
+      }
+    }
+    if constexpr (XR) {
+      xre += a[NRT].x * b.x - a[NRT].y * b.y;
+      xim += a[NRT].x * b.y + a[NRT].y * b.x;
+    }
+    load(a, b_, bv_);  // the step PF ahead into the registers just used
+    // FP32: one operator done -> its sums into FP64 (FP64 keeps accumulating)
+    if (++cks == NKS) {
+      cks = 0;
+      if constexpr (F32) flush();
+    }
+    // keep the scheduler from moving the loads of this step down to their uses
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // steps past T (up to the next multiple of UN) multiply zeros; the loop body runs
+  // UN = 4 PF steps, since the compiler's wait at the top of the loop drains every
+  // load in flight: once per 4 PF steps instead of once per PF
+  constexpr int UN = 4 * PF;
+  for (int i = 0; i < T; i += UN) {
+#pragma unroll
+    for (int u = 0; u < UN; u++) step(af[u % PF], bf[u % PF], bv[u % PF]);
+  }
+  flush();
+  if constexpr (XR) {
+    // the four k-lanes of a target hold partial sums of the last row
+    dxre += __shfl_xor(dxre, 16);
+    dxim += __shfl_xor(dxim, 16);
+    dxre += __shfl_xor(dxre, 32);
+    dxim += __shfl_xor(dxim, 32);
+  }
+}
+// Partial sums of the KS waves of a 16-target tile through LDS (fixed order), then
+// the rows of wave kw = 0 added to the local expansions (rows of FP32 results
+// unscaled by the level's power of two first).
+template <int NRT, int XR, int KS>
+__device__ __forceinline__ void m2l_store(const GBlock& bd, const int* trow, double2* D, int NCK, int NC, bool f32row,
+                                          int e_t_or_0, const int* box_tree, const int* box_level, const int* se,
+                                          v4d (&dre)[NRT], v4d (&dim)[NRT], double& dxre, double& dxim) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, kr = lane >> 4;
+  const int cg = wave / KS, kw = wave % KS;
   if constexpr (KS > 1) {
     __shared__ double red[4][8][64];
 #pragma unroll
-    for (int rt = 0; rt < NRT; rt++) {
+    for (int rt = 0; rt < NRT + XR; rt++) {
       if (kw > 0) {
+        if (rt < NRT) {
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-          red[wave][r][lane] = dr[rt][r];
-          red[wave][4 + r][lane] = di[rt][r];
+          for (int r = 0; r < 4; r++) {
+            red[wave][r][lane] = dre[rt < NRT ? rt : 0][r];
+            red[wave][4 + r][lane] = dim[rt < NRT ? rt : 0][r];
+          }
+        } else {
+          red[wave][0][lane] = dxre;
+          red[wave][4][lane] = dxim;
         }
       }
       __syncthreads();
       if (kw == 0) {
-        for (int w = 1; w < KS; w++)
+        for (int w = 1; w < KS; w++) {
+          if (rt < NRT) {
 #pragma unroll
-          for (int r = 0; r < 4; r++) {
-            dr[rt][r] += red[wave + w][r][lane];
-            di[rt][r] += red[wave + w][4 + r][lane];
+            for (int r = 0; r < 4; r++) {
+              dre[rt < NRT ? rt : 0][r] += red[wave + w][r][lane];
+              dim[rt < NRT ? rt : 0][r] += red[wave + w][4 + r][lane];
+            }
+          } else {
+            dxre += red[wave + w][0][lane];
+            dxim += red[wave + w][4][lane];
           }
+        }
       }
       __syncthreads();
     }
   }
-  if (kw != 0 || !tv) return;
-  const int tr = trow[ee];
-  const int e_t = se[box_tree[tr] * 9 + box_level[tr]];
+  const int tt = cg * 16 + col;
+  if (kw != 0 || tt >= bd.nt) return;
+  const int tr = trow[bd.e0 + tt];
+  const int e_t = f32row ? se[box_tree[tr] * 9 + box_level[tr]] : 0;
   double2* Dr = D + (size_t)tr * NCK;
+  auto put = [&](int row, double vr, double vi) {
+    if (f32row) {
+      int n = (int)sqrt((double)row);
+      while (n * n > row) n--;
+      vr = ldexp(vr, e_t * n);
+      vi = ldexp(vi, e_t * n);
+    }
+    double2 v = Dr[row];
+    v.x += vr;
+    v.y += vi;
+    Dr[row] = v;
+  };
 #pragma unroll
   for (int rt = 0; rt < NRT; rt++)
 #pragma unroll
     for (int r = 0; r < 4; r++) {
-      int row = rt * 16 + 4 * kr + r;
-      if (row < NC) {
-        int n = (int)sqrt((double)row);
-        while (n * n > row) n--;
-        double2 v = Dr[row];
-        v.x += ldexp(dr[rt][r], e_t * n);
-        v.y += ldexp(di[rt][r], e_t * n);
-        Dr[row] = v;
-      }
+      // D layouts: FP32 element r of lane l = row 4 (l/16) + r; FP64: row l/16 + 4 r
+      const int row = rt * 16 + (f32row ? 4 * kr + r : kr + 4 * r);
+      if (row < NC) put(row, dre[rt][r], dim[rt][r]);
     }
+  if constexpr (XR) {
+    if (kr == 0) put(NRT * 16, dxre, dxim);
+  }
 }
-extern "C" void lk_gemm32(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+template <int NRT, int XR, int KS>
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_m2l_gemm32(const GBlock* blocks, const int* seq, const int* trow,
+                                                       const int* srow, int srow_stride,
+                                                       const float2* __restrict__ ops, int opstride2, int NKS,
+                                                       const float2* __restrict__ S, double2* D, int NCK, int NC,
+                                                       const int* box_tree, const int* box_level, const int* se,
+                                                       int lmax) {
+  extern __shared__ int m2l_lists[];  // per wave: lmax operator ids, then lmax x 16 source rows
+  const GBlock bd = blocks[xcd_block(blockIdx.x, gridDim.x)];
+  v4d dre[NRT], dim[NRT];
+#pragma unroll
+  for (int rt = 0; rt < NRT; rt++) {
+    dre[rt] = (v4d){0, 0, 0, 0};
+    dim[rt] = (v4d){0, 0, 0, 0};
+  }
+  double dxre = 0.0, dxim = 0.0;
+  const int wave = threadIdx.x >> 6;
+  m2l_body<float, NRT, XR, KS, (NRT <= 6 ? 3 : 2), (NRT <= 6)>(bd, seq, srow, srow_stride, ops, (size_t)opstride2, NKS, S, NCK, dre,
+                                               dim, dxre, dxim, m2l_lists + 17 * lmax * wave, lmax);
+  m2l_store<NRT, XR, KS>(bd, trow, D, NCK, NC, true, 0, box_tree, box_level, se, dre, dim, dxre, dxim);
+}
+// (two waves per SIMD is the target: at a higher one the scheduler would sink the
+// prefetch loads to their uses to free registers)
+template <int NRT, int XR, int KS>
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_m2l_gemm64(const GBlock* blocks, const int* seq, const int* trow,
+                                                       const int* srow, int srow_stride,
+                                                       const double2* __restrict__ ops, int opstride2, int NKS,
+                                                       const double2* __restrict__ S, double2* D, int NCK, int NC,
+                                                       int lmax) {
+  extern __shared__ int m2l_lists[];  // per wave: lmax operator ids, then lmax x 16 source rows
+  const GBlock bd = blocks[xcd_block(blockIdx.x, gridDim.x)];
+  v4d dre[NRT], dim[NRT];
+#pragma unroll
+  for (int rt = 0; rt < NRT; rt++) {
+    dre[rt] = (v4d){0, 0, 0, 0};
+    dim[rt] = (v4d){0, 0, 0, 0};
+  }
+  double dxre = 0.0, dxim = 0.0;
+  const int wave = threadIdx.x >> 6;
+  m2l_body<double, NRT, XR, KS, 2, (NRT <= 5)>(bd, seq, srow, srow_stride, ops, (size_t)opstride2, NKS, S, NCK, dre,
+                                                dim, dxre, dxim, m2l_lists + 17 * lmax * wave, lmax);
+  m2l_store<NRT, XR, KS>(bd, trow, D, NCK, NC, false, 0, nullptr, nullptr, nullptr, dre, dim, dxre, dxim);
+}
+extern "C" void lk_gemm32(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
                           const int* srow, int srow_stride, const float* ops, int opsz, int NKS, const float* S,
-                          double* D, int NCK, int NC, const int* box_tree, const int* box_level, const int* se,
+                          double* D, int NCK, const int* box_tree, const int* box_level, const int* se,
                           hipStream_t s) {
   if (!nblocks) return;
-  const float2* S2 = (const float2*)S;
-  double2* D2 = (double2*)D;
-#define GEMM32_CASE(N, K)                                                                                     \
-  if (nrt == N && ks == K) {                                                                                  \
-    k_m2l_gemm32<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2,  \
-                                               NCK, NC, box_tree, box_level, se);                             \
+  const int lmax = (srow_stride + ks - 1) / ks;  // a wave lists at most ceil(K / ks) operators
+  const size_t lds = sizeof(int) * 17 * (size_t)lmax * 4;
+  const int nrt = m2l_nrt(NC), xr = m2l_xr(NC);
+  const float2* o2 = (const float2*)ops;
+  const int os2 = opsz / 2;  // operator stride in float2 (opsz floats per operator)
+#define GEMM32_CASE(N, X, K)                                                                                        \
+  if (nrt == N && xr == X && ks == K) {                                                                             \
+    k_m2l_gemm32<N, X, K><<<nblocks, 256, lds, s>>>(blocks, seq, trow, srow, srow_stride, o2, os2, NKS,             \
+                                                    (const float2*)S, (double2*)D, NCK, NC, box_tree, box_level, se, \
+                                                    lmax);                                                          \
+    return;                                                                                                         \
+  }
+#define GEMM32_KS(N, X) GEMM32_CASE(N, X, 1) GEMM32_CASE(N, X, 2) GEMM32_CASE(N, X, 4)
+  GEMM32_KS(1, 0) GEMM32_KS(2, 0) GEMM32_KS(3, 1) GEMM32_KS(3, 0) GEMM32_KS(4, 0) GEMM32_KS(5, 1) GEMM32_KS(7, 0)
+  GEMM32_KS(8, 0)
+#undef GEMM32_KS
+#undef GEMM32_CASE
+}
+extern "C" void lk_m2l_gemm64(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+                              const int* srow, int srow_stride, const double* ops, int opsz, int NKS,
+                              const double* S, double* D, int NCK, hipStream_t s) {
+  if (!nblocks) return;
+  const int lmax = (srow_stride + ks - 1) / ks;  // a wave lists at most ceil(K / ks) operators
+  const size_t lds = sizeof(int) * 17 * (size_t)lmax * 4;
+  const int nrt = m2l_nrt(NC), xr = m2l_xr(NC);
+  const double2* o2 = (const double2*)ops;
+  const int os2 = opsz / 2;  // operator stride in double2 (opsz doubles per operator)
+#define GEMM64_CASE(N, X, K)                                                                                  \
+  if (nrt == N && xr == X && ks == K) {                                                                       \
+    k_m2l_gemm64<N, X, K><<<nblocks, 256, lds, s>>>(blocks, seq, trow, srow, srow_stride, o2, os2, NKS,       \
+                                                    (const double2*)S, (double2*)D, NCK, NC, lmax);           \
     return;                                                                                                   \
   }
-  GEMM32_CASE(1, 1) GEMM32_CASE(2, 1) GEMM32_CASE(3, 1) GEMM32_CASE(4, 1) GEMM32_CASE(5, 1) GEMM32_CASE(6, 1)
-  GEMM32_CASE(7, 1) GEMM32_CASE(8, 1) GEMM32_CASE(1, 2) GEMM32_CASE(2, 2) GEMM32_CASE(3, 2) GEMM32_CASE(4, 2)
-  GEMM32_CASE(5, 2) GEMM32_CASE(6, 2) GEMM32_CASE(7, 2) GEMM32_CASE(8, 2) GEMM32_CASE(1, 4) GEMM32_CASE(2, 4)
-  GEMM32_CASE(3, 4) GEMM32_CASE(4, 4) GEMM32_CASE(5, 4) GEMM32_CASE(6, 4) GEMM32_CASE(7, 4) GEMM32_CASE(8, 4)
-#undef GEMM32_CASE
+#define GEMM64_KS(N, X) GEMM64_CASE(N, X, 1) GEMM64_CASE(N, X, 2) GEMM64_CASE(N, X, 4)
+  GEMM64_KS(1, 0) GEMM64_KS(2, 0) GEMM64_KS(3, 1) GEMM64_KS(3, 0) GEMM64_KS(4, 0) GEMM64_KS(5, 1) GEMM64_KS(7, 0)
+  GEMM64_KS(8, 0)
+#undef GEMM64_KS
+#undef GEMM64_CASE
 }
 
 // ---------------------------------------------------------------------------

@@ -38,7 +38,9 @@ class Report(ctypes.Structure):
                 ("p2p_pairs", ctypes.c_int64), ("nf_react_pairs", ctypes.c_int64),
                 ("p2p_series", ctypes.c_int), ("precision", ctypes.c_int),
                 ("stage_ms", ctypes.c_double * 24), ("n_react_surrogate", ctypes.c_int64), ("ops_reused", ctypes.c_int),
-                ("n_react_table", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64)]
+                ("n_react_table", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("p2m_points", ctypes.c_int64), ("p2m_leaves", ctypes.c_int64),
+                ("l2p_points", ctypes.c_int64), ("l2p_leaves", ctypes.c_int64)]
 
 
 class TuneReport(ctypes.Structure):
@@ -312,7 +314,9 @@ class Plan:
                     m2m_pairs=r.m2m_pairs, l2l_pairs=r.l2l_pairs, p2p_pairs=r.p2p_pairs, nf_react_pairs=r.nf_react_pairs,
                     p2p_series=r.p2p_series, precision=r.precision,
                     n_react_surrogate=r.n_react_surrogate, ops_reused=r.ops_reused,
-                    n_react_table=r.n_react_table, workspace_bytes=r.workspace_bytes, stage_ms=stages)
+                    n_react_table=r.n_react_table, workspace_bytes=r.workspace_bytes,
+                    p2m_points=r.p2m_points, p2m_leaves=r.p2m_leaves, l2p_points=r.l2p_points,
+                    l2p_leaves=r.l2p_leaves, stage_ms=stages)
 
     def autotune(self, xyz, q, phi, layer=None, stream=None):
         """lfmm_autotune on torch device tensors (as eval_device); returns the tuning report."""

@@ -95,3 +95,46 @@ def test_full_size_mixed_precision(full):
     emax = np.max(np.abs(a - b)) / np.max(np.abs(b))
     print("full size mixed vs FP64: Err2 %.2e Errmax %.2e" % (e2, emax))
     assert e2 < 1e-6 and emax < 1e-6
+
+
+def test_full_size_layer_against_closed_form_32_targets():
+    """One layer of the benchmark workload (the 349,526 particles of the top unit
+    cube, k = 0.8) as a homogeneous medium: the same depth-4 tree as in the
+    layered run, with P2M and L2P at order 8, the near-field tiles of the leaf bound
+    256 and the M2L GEMM over its whole interaction lists.  32 seeded targets
+    against the closed-form direct sum (exact and cheap here, unlike the layered
+    sum, whose per-pair Sommerfeld quadrature costs about 0.2 ms per pair on a CPU
+    core).  The error must be the order-8 truncation and must shrink at order 10;
+    the mixed path must stay within 1e-6 of the FP64 path at the same targets."""
+    import torch
+    from paper_1902_05132_amd import lfmm
+
+    w = W.three_layer_cubes()
+    sel = w["layer"] == 0
+    x, y, z, q = w["x"][sel], w["y"][sel], w["z"][sel], w["q"][sel]
+    k = float(w["k"][0])
+    dev = torch.device("cuda:0")
+    xyz = torch.tensor(np.stack([x, y, z]), dtype=torch.float64, device=dev).contiguous()
+    qt = torch.tensor(q, dtype=torch.complex128, device=dev)
+    rng = np.random.default_rng(123)
+    tg = np.sort(rng.choice(len(x), 32, replace=False))
+    R = np.sqrt((x[tg, None] - x[None]) ** 2 + (y[tg, None] - y[None]) ** 2 + (z[tg, None] - z[None]) ** 2)
+    R[np.arange(32), tg] = 1.0
+    H = np.exp(1j * k * R) / (1j * k * R)
+    H[np.arange(32), tg] = 0.0
+    ex = H @ q
+    out = {}
+    for p, prec in ((8, 0), (10, 0), (8, 1)):
+        P = lfmm.Plan((), (k,), p=p, leaf_max=256, precision=prec)
+        phi = torch.empty_like(qt)
+        P.eval_device(xyz, qt, phi)
+        torch.cuda.synchronize()
+        assert P.report()["free_depth"][0] == 4
+        out[(p, prec)] = phi.cpu().numpy()[tg]
+    e8 = np.linalg.norm(out[(8, 0)] - ex) / np.linalg.norm(ex)
+    e10 = np.linalg.norm(out[(10, 0)] - ex) / np.linalg.norm(ex)
+    emix = np.linalg.norm(out[(8, 1)] - out[(8, 0)]) / np.linalg.norm(out[(8, 0)])
+    print("one full-size layer, 32 targets: Err2 p=8 %.2e, p=10 %.2e; mixed vs FP64 %.2e" % (e8, e10, emix))
+    assert e8 < 1e-4, e8
+    assert e10 < 0.5 * e8, (e10, e8)
+    assert emix < 1e-6, emix
