@@ -8,7 +8,6 @@
 // the component sum.  The host only does bookkeeping on counts read back at a
 // few synchronisation points.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -1452,13 +1451,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   const int nbl = (n + 255) / 256;
   int* lcnt = P->dev<int>("layer_cnt", (size_t)NL * nbl + 1);
   int* loff = P->dev<int>("layer_off", (size_t)NL * nbl + 1);
-  void* tmp = nullptr;
   if (n) {
     lk_layer_count(n, NL, layer, lcnt, s);
-    size_t tb1 = 0;
-    HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb1, lcnt, loff, NL * nbl, s));
-    tmp = P->dev<char>("cubtmp1", tb1);
-    HIPCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb1, lcnt, loff, NL * nbl, s));
+    int* ts1 = P->dev<int>("scan_ts1", lk_scan_tsum_size((long long)NL * nbl));
+    lk_scan_excl(lcnt, (long long)NL * nbl, loff, ts1, s);
     lk_layer_scatter(n, NL, layer, loff, perm, s);
   }
   lk_inverse_perm(n, perm, inv_perm, s);
@@ -1473,10 +1469,12 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   lk_tree_points(ntp, ntrees, d_trees, perm, d_lstart, x, y, z, q, st, keys, vals, rec, s);
   int tbits = 1;
   while ((1 << tbits) < ntrees) tbits++;
-  size_t tb2 = 0;
-  HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb2, keys, skeys, vals, sg, ntp, 0, 24 + tbits, s));
-  tmp = P->dev<char>("cubtmp2", tb2);
-  HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb2, keys, skeys, vals, sg, ntp, 0, 24 + tbits, s));
+  {
+    unsigned* ktmp = P->dev<unsigned>("keys_tmp", ntp);
+    int* vtmp = P->dev<int>("vals_tmp", ntp);
+    int* rsw = P->dev<int>("rs_scratch", (size_t)lk_radix_sort_scratch(ntp));
+    lk_radix_sort_pairs(keys, vals, skeys, sg, ktmp, vtmp, ntp, 24 + tbits, 0xffffffffu, rsw, s);
+  }
   int* occ = P->dev<int>("occ", ntrees * 9);
   int* slab = P->dev<int>("slab", ntrees * 18);
   HIPCHK(hipMemsetAsync(occ, 0, sizeof(int) * ntrees * 9, s));
@@ -1533,11 +1531,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   HIPCHK(hipMemsetAsync(tb, 0, sizeof(int) * ntrees * 18, s));
   // box flags of every level, one scan over all levels (global box rows), box ranges
   if ((size_t)nlev * ntp >= ((size_t)1 << 31)) throw Fail{LFMM_ENOTSUP};
-  size_t tb3 = 0;
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, tb3, flags_all, scan_all, nlev * ntp, s));
-  tmp = P->dev<char>("cubtmp3", tb3);
+  int* ts3 = P->dev<int>("scan_ts3", lk_scan_tsum_size((long long)nlev * ntp));
   lk_box_flags_all(ntp, nlev, skeys, d_trees, flags_all, s);
-  HIPCHK(hipcub::DeviceScan::ExclusiveSum(tmp, tb3, flags_all, scan_all, nlev * ntp, s));
+  lk_scan_excl(flags_all, (long long)nlev * ntp, scan_all, ts3, s);
   lk_tree_box_range_all(ntrees, nlev, ntp, d_trees, flags_all, scan_all, tb, s);
   std::vector<int> htb(ntrees * 18);
   P->rb_add(htb.data(), tb, sizeof(int) * ntrees * 18, s);
@@ -2033,16 +2029,20 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     J.cnt = P->dev<int>((t + "_cnt").c_str(), ngroups + 1);
     int* d_gb = P->upload((t + "_gb").c_str(), gbase, sj);
     lk_group_ids(NR, 0, mode, box_code, box_tree, box_level, d_trees, d_gb, 9, J.gid, J.rowid, sj);
-    size_t tbb = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, sj));
-    void* tt = P->dev<char>((t + "_tmp").c_str(), tbb);
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tt, tbb, J.gid, J.sgid, J.rowid, J.srowid, NR, 0, 32, sj));
+    // sort keys: group ids (M2L: group * M2L_BCLS + boundary class); rows in no group
+    // carry 0x7fffffff and sort as the largest key
+    const long long kend = mode == 2 ? (long long)ngroups * M2L_BCLS : (long long)ngroups;
+    int nbits = 1;
+    while ((1LL << nbits) <= kend) nbits++;
+    unsigned* kt = P->dev<unsigned>((t + "_ktmp").c_str(), NR + 1);
+    int* vt = P->dev<int>((t + "_vtmp").c_str(), NR + 1);
+    int* rsw = P->dev<int>((t + "_rs").c_str(), (size_t)lk_radix_sort_scratch(NR));
+    lk_radix_sort_pairs((const unsigned*)J.gid, J.rowid, (unsigned*)J.sgid, J.srowid, kt, vt, NR, nbits,
+                        (unsigned)((1LL << nbits) - 1), rsw, sj);
     if (mode == 2) lk_m2l_key_to_group(NR, J.sgid, sj);
-    // histogram of valid group ids
-    size_t tbh = 0;
-    HIPCHK(hipcub::DeviceHistogram::HistogramEven(nullptr, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, sj));
-    void* th = P->dev<char>((t + "_htmp").c_str(), tbh);
-    HIPCHK(hipcub::DeviceHistogram::HistogramEven(th, tbh, J.sgid, J.cnt, ngroups + 1, 0, ngroups, NR, sj));
+    // sizes of the groups
+    lk_fill_int(J.cnt, ngroups + 1, 0, sj);
+    lk_hist_ids(J.sgid, NR, ngroups, J.cnt, sj);
   };
   JobDev J_m2m{}, J_l2l{}, J_m2l{};
   int ng_m2m = (int)g_m2m.size(), ng_l2l = (int)g_l2l.size(), ng_m2l = (int)g_m2l.size();

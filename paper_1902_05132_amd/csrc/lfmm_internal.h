@@ -228,6 +228,16 @@ void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_
 void lk_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
                       const long long* grid_off, int* grid, hipStream_t s);
 void lk_m2l_key_to_group(int n, int* key, hipStream_t s);
+// exclusive prefix sum of n ints (out may equal in); tsum: lk_scan_tsum_size(n) ints
+void lk_scan_excl(const int* in, long long n, int* out, int* tsum, hipStream_t s);
+int lk_scan_tsum_size(long long n);
+// stable radix sort of (key, value) pairs on the low nbits bits of min(key, kcap);
+// scratch: lk_radix_sort_scratch(n) ints
+long long lk_radix_sort_scratch(int n);
+void lk_radix_sort_pairs(const unsigned* kin, const int* vin, unsigned* kout, int* vout, unsigned* ktmp, int* vtmp,
+                         int n, int nbits, unsigned kcap, int* scratch, hipStream_t s);
+// group sizes of ids in [0, ng), added to cnt
+void lk_hist_ids(const int* ids, int n, int ng, int* cnt, hipStream_t s);
 void lk_tab_store(int ncls, const ClassDesc* cls, const double* dadd, const int* slot, Stack st, const double* Iall,
                   int p, int NC, double* tab, hipStream_t s);
 void lk_tab_interp(int ncls, const ClassDesc* cls, const double* dadd, const int* slot0, const double* w, int nnode,

@@ -1840,6 +1840,239 @@ extern "C" void lk_m2l_gemm64(int NC, int ks, int nblocks, const GBlock* blocks,
 }
 
 // ---------------------------------------------------------------------------
+// Device-wide exclusive prefix sum of int32 values in three passes over tiles of
+// SCAN_TILE: the sum of every tile, an exclusive scan of the tile sums in one
+// workgroup, then every tile scanned again from its offset.  out may equal in.
+// ---------------------------------------------------------------------------
+#define SCAN_TILE 4096
+__device__ __forceinline__ int block_excl_scan256(int v, int* sh, int* total) {
+  // Hillis-Steele scan of one value per thread of a 256-thread block
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  *total = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+__global__ __launch_bounds__(256) void k_scan_tiles(const int* in, long long n, int* tsum) {
+  __shared__ int sh[256];
+  const long long base = (long long)blockIdx.x * SCAN_TILE + threadIdx.x;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < 16; k++)
+    if (base + 256 * k < n) s += in[base + 256 * k];
+  int tot;
+  block_excl_scan256(s, sh, &tot);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(256) void k_scan_sums(int* tsum, int nt) {
+  __shared__ int sh[256];
+  int carry = 0;
+  for (int c = 0; c < nt; c += 256) {
+    const int i = c + threadIdx.x;
+    const int v = i < nt ? tsum[i] : 0;
+    int tot;
+    const int ex = block_excl_scan256(v, sh, &tot);
+    if (i < nt) tsum[i] = carry + ex;
+    carry += tot;
+  }
+}
+__global__ __launch_bounds__(256) void k_scan_apply(const int* in, long long n, const int* toff, int* out) {
+  // the tile in 16 rounds of 256 consecutive values: a shuffle scan in each wave,
+  // the waves' totals in wave order, the rounds in order
+  __shared__ int wt[4];
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  int carry = toff[blockIdx.x];
+  for (int r = 0; r < 16; r++) {
+    const long long g = (long long)blockIdx.x * SCAN_TILE + r * 256 + t;
+    const int v = g < n ? in[g] : 0;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int y = __shfl_up(x, d);
+      if (lane >= d) x += y;
+    }
+    if (lane == 63) wt[wave] = x;
+    __syncthreads();
+    int wpre = 0;
+    for (int w = 0; w < wave; w++) wpre += wt[w];
+    const int rtot = wt[0] + wt[1] + wt[2] + wt[3];
+    if (g < n) out[g] = carry + wpre + x - v;
+    carry += rtot;
+    __syncthreads();
+  }
+}
+extern "C" void lk_scan_excl(const int* in, long long n, int* out, int* tsum, hipStream_t s) {
+  if (n <= 0) return;
+  const int nt = (int)((n + SCAN_TILE - 1) / SCAN_TILE);
+  k_scan_tiles<<<nt, 256, 0, s>>>(in, n, tsum);
+  k_scan_sums<<<1, 256, 0, s>>>(tsum, nt);
+  k_scan_apply<<<nt, 256, 0, s>>>(in, n, tsum, out);
+}
+extern "C" int lk_scan_tsum_size(long long n) { return (int)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of (u32 key, int32 value) pairs, 8 key bits per pass.
+// Per pass: digit counts of every tile of RS_TILE pairs (digit-major), one
+// exclusive scan of the counts (each digit's tiles in order), then a stable
+// scatter.  A tile is taken in rounds of 256 consecutive pairs; within a wave the
+// pairs with the same digit are found by eight ballots and ranked by lane, and the
+// waves' counts are added in wave order, the rounds in order.  The scatter first
+// places the tile's pairs in LDS in digit order, then writes each digit's run to
+// its consecutive global positions.  Keys above kcap sort as kcap (a sentinel of
+// the caller) but keep their value.
+// ---------------------------------------------------------------------------
+#define RS_TILE 4096
+#define RS_ROUNDS (RS_TILE / 256)
+__device__ __forceinline__ unsigned rs_digit(unsigned key, unsigned kcap, int shift) {
+  return ((key < kcap ? key : kcap) >> shift) & 255u;
+}
+// lanes of the wave whose valid pair has digit d (d < 256)
+__device__ __forceinline__ unsigned long long rs_same(unsigned d, bool valid) {
+  unsigned long long same = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; b++) {
+    const unsigned long long m = __ballot((d >> b) & 1u);
+    same &= ((d >> b) & 1u) ? m : ~m;
+  }
+  return same;
+}
+__global__ __launch_bounds__(256) void k_rs_count(const unsigned* keys, int n, unsigned kcap, int shift, int* cnt,
+                                                  int nb) {
+  __shared__ int h[256];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  h[tid] = 0;
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; r++) {
+    const long long g = base + r * 256 + tid;
+    const bool valid = g < n;
+    const unsigned d = rs_digit(valid ? keys[g] : 0u, kcap, shift);
+    const unsigned long long same = rs_same(d, valid);
+    if (valid && (same & below) == 0) atomicAdd(&h[d], __popcll(same));
+  }
+  __syncthreads();
+  cnt[(size_t)tid * nb + blockIdx.x] = h[tid];
+}
+__global__ __launch_bounds__(256) void k_rs_scatter(const unsigned* kin, const int* vin, int n, unsigned kcap,
+                                                    int shift, const int* cnt, const int* off, int nb,
+                                                    unsigned* kout, int* vout) {
+  __shared__ unsigned sk[RS_TILE];
+  __shared__ int sv[RS_TILE];
+  __shared__ int lstart[256], run[256], goff[256], sh[256];
+  __shared__ int wcnt[4][256];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  // where each digit's pairs start in the tile's digit order, and globally
+  int tot;
+  const int mine = cnt[(size_t)tid * nb + blockIdx.x];
+  const int ls = block_excl_scan256(mine, sh, &tot);
+  lstart[tid] = ls;
+  run[tid] = ls;
+  goff[tid] = off[(size_t)tid * nb + blockIdx.x];
+  const long long base = (long long)blockIdx.x * RS_TILE;
+  for (int r = 0; r < RS_ROUNDS; r++) {
+    for (int w = 0; w < 4; w++) wcnt[w][tid] = 0;
+    __syncthreads();
+    const long long g = base + r * 256 + tid;
+    const bool valid = g < n;
+    const unsigned key = valid ? kin[g] : 0u;
+    const int val = valid ? vin[g] : 0;
+    const unsigned d = rs_digit(key, kcap, shift);
+    const unsigned long long same = rs_same(d, valid);
+    const int rank = __popcll(same & below);
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(same);
+    __syncthreads();
+    if (valid) {
+      int pos = run[d] + rank;
+      for (int w = 0; w < wave; w++) pos += wcnt[w][d];
+      sk[pos] = key;
+      sv[pos] = val;
+    }
+    __syncthreads();
+    run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+  }
+  __syncthreads();
+  const int nt = (int)(n - base < RS_TILE ? n - base : RS_TILE);
+  for (int i = tid; i < nt; i += 256) {
+    const unsigned key = sk[i];
+    const unsigned d = rs_digit(key, kcap, shift);
+    const int gp = goff[d] + (i - lstart[d]);
+    kout[gp] = key;
+    vout[gp] = sv[i];
+  }
+}
+// Scratch (ints) the sort needs for n pairs: the counts, their offsets and the scan's tile sums.
+extern "C" long long lk_radix_sort_scratch(int n) {
+  const int nb = (n + RS_TILE - 1) / RS_TILE;
+  return 2LL * 256 * nb + lk_scan_tsum_size(256LL * nb);
+}
+// Sorts kin/vin (left unchanged) into kout/vout, with ktmp/vtmp (all n long) between passes.
+extern "C" void lk_radix_sort_pairs(const unsigned* kin, const int* vin, unsigned* kout, int* vout, unsigned* ktmp,
+                                    int* vtmp, int n, int nbits, unsigned kcap, int* scratch, hipStream_t s) {
+  if (n <= 0) return;
+  const int nb = (n + RS_TILE - 1) / RS_TILE;
+  const int passes = nbits <= 0 ? 1 : (nbits + 7) / 8;
+  int* cnt = scratch;
+  int* off = scratch + 256LL * nb;
+  int* tsum = off + 256LL * nb;
+  const unsigned* ks = kin;
+  const int* vs = vin;
+  for (int pss = 0; pss < passes; pss++) {
+    const bool to_out = ((passes - 1 - pss) & 1) == 0;
+    unsigned* kd = to_out ? kout : ktmp;
+    int* vd = to_out ? vout : vtmp;
+    k_rs_count<<<nb, 256, 0, s>>>(ks, n, kcap, 8 * pss, cnt, nb);
+    lk_scan_excl(cnt, 256LL * nb, off, tsum, s);
+    k_rs_scatter<<<nb, 256, 0, s>>>(ks, vs, n, kcap, 8 * pss, cnt, off, nb, kd, vd);
+    ks = kd;
+    vs = vd;
+  }
+}
+// Sizes of groups of sorted ids in [0, ng) (ids outside are skipped): one LDS
+// histogram per workgroup, added to cnt (zeroed by the caller).
+__global__ __launch_bounds__(256) void k_hist_ids(const int* ids, int n, int ng, int* cnt) {
+  extern __shared__ int hh[];
+  for (int g = threadIdx.x; g < ng; g += 256) hh[g] = 0;
+  __syncthreads();
+  // lanes with equal ids (runs, as the ids are sorted) are counted together: one
+  // atomic per distinct id in a wave
+  const int lane = threadIdx.x & 63;
+  for (int i0 = blockIdx.x * 4096; i0 < n && i0 < (blockIdx.x + 1) * 4096; i0 += 256) {
+    const int i = i0 + threadIdx.x;
+    const int g = i < n ? ids[i] : -1;
+    bool todo = g >= 0 && g < ng;
+    while (__ballot(todo)) {
+      const int lead = __ffsll((long long)__ballot(todo)) - 1;
+      const int gl = __shfl(g, lead);
+      const unsigned long long same = __ballot(todo && g == gl);
+      if (lane == lead) atomicAdd(&hh[gl], __popcll(same));
+      if (g == gl) todo = false;
+    }
+  }
+  __syncthreads();
+  for (int g = threadIdx.x; g < ng; g += 256)
+    if (hh[g]) atomicAdd(&cnt[g], hh[g]);
+}
+__global__ __launch_bounds__(256) void k_hist_ids_global(const int* ids, int n, int ng, int* cnt) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n && ids[i] >= 0 && ids[i] < ng) atomicAdd(&cnt[ids[i]], 1);
+}
+extern "C" void lk_hist_ids(const int* ids, int n, int ng, int* cnt, hipStream_t s) {
+  if (n <= 0 || ng <= 0) return;
+  if (ng <= 16384) k_hist_ids<<<(n + 4095) / 4096, 256, sizeof(int) * (size_t)ng, s>>>(ids, n, ng, cnt);
+  else k_hist_ids_global<<<(n + 255) / 256, 256, 0, s>>>(ids, n, ng, cnt);
+}
+
+// ---------------------------------------------------------------------------
 // GEMM job construction: group ids per target box, then source rows.
 // mode 0: M2M targets (parents), mode 1: L2L targets, mode 2: M2L targets.
 // gbase[t*9 + l] = first group id of (tree, level) or -1.
