@@ -40,7 +40,9 @@ typedef enum {
   LFMM_ENOMEM = 2,  /* device or host allocation failed */
   LFMM_EHIP = 3,    /* a HIP runtime call failed */
   LFMM_ENOTSUP = 4, /* the configuration is outside what the library supports */
-  LFMM_EIO = 5      /* a surrogate or table file could not be read or written, or does not match the plan */
+  LFMM_EIO = 5,     /* a surrogate or table file could not be read or written, or does not match the plan */
+  LFMM_ENOCONV = 6  /* the Sommerfeld quadrature of a reaction class (Section 3.5) would need more contour
+                       nodes than the plan's budget (quad_max_nodes) to reach its truncation tolerance */
 } lfmm_status;
 
 /* Plan options; pass NULL for the defaults shown. */
@@ -63,6 +65,10 @@ typedef struct {
   double quad_tol;     /* truncation of the Sommerfeld contour (Section 3.5): the far panels end where
                           the envelope t^N e^{-t dz} of a class's integrands has fallen to quad_tol
                           times its largest value (N = 2p + 1); in (0, 1), or 0 for e^{-40} (4e-18) */
+  int64_t quad_max_nodes; /* the most contour nodes one reaction class (or one near-field reaction
+                          component) may take.  The far panels' count grows as 1/dz when the target and
+                          source boxes' images approach each other (dz = z_t + z_s -> 0); a class that
+                          needs more fails the evaluation with LFMM_ENOCONV: 0 for 2^20 */
 } lfmm_options;
 
 typedef struct lfmm_plan_s lfmm_plan_t;
@@ -202,6 +208,16 @@ void lfmm_destroy(lfmm_plan_t* plan);
 
 /* Text of a status code. */
 const char* lfmm_status_string(int status);
+
+/* Contour nodes of the Sommerfeld quadrature (Section 3.5: the deformed contour, then panels of
+ * the real axis truncated where the integrand envelope t^{2p+1} e^{-t dz} has decayed to quad_tol,
+ * widened up to the J_q(t rho) oscillation limit) that a plan with these arguments uses for one
+ * reaction class at vertical image distance dz = z_t + z_s > 0 and horizontal distance rho >= 0.
+ * Arguments as lfmm_plan; no device is touched, so it serves for budgeting on any host.
+ * *nodes receives the count; LFMM_ENOCONV when it exceeds opt->quad_max_nodes (*nodes then still
+ * holds the count, or 0 beyond 2^30), LFMM_EINVAL for invalid arguments. */
+int lfmm_quad_nodes(int L, const double* d, const double* k, int p, const lfmm_options* opt, double dz,
+                    double rho, int64_t* nodes);
 
 /* ---- tile-shape autotuning ---- */
 typedef struct {

@@ -389,6 +389,7 @@ struct lfmm_plan_s {
   double far_cap = P_FAR_CAP_DEFAULT;
   double quad_c = 40.0;  // the contour ends where the integrands' envelope has fallen by e^{-quad_c}
   double far_grow = 1.5;  // growth of the far panels beyond the cap (1: none; tuning override LFMM_FAR_GROW)
+  int64_t quad_max_nodes = (int64_t)1 << 20;  // contour nodes one class may take (more: LFMM_ENOCONV)
   double* d_gaunt = nullptr;
   std::map<std::string, DevBuf> bufs;
   std::vector<char> hbuf;
@@ -559,17 +560,27 @@ struct lfmm_plan_s {
         r.kg++;
         w *= far_grow;
       }
+      // panels the budget leaves for the far part (LFMM_NP1 + nnear are taken)
+      const int64_t kbud = quad_max_nodes / LFMM_NGL - LFMM_NP1 - r.nnear;
       double t = r.T0, wk = hf;
-      int k = 0;
-      while (t < tfar && k < 100000) {
-        t += (k < r.kg) ? wk : wlim;
-        if (k < r.kg) wk *= far_grow;
+      int64_t k = 0;
+      while (t < tfar && k < r.kg) {  // the growing panels
+        t += wk;
+        wk *= far_grow;
         k++;
       }
-      r.nfar = std::max(1, k);
+      if (t < tfar) {  // then panels of width wlim up to tfar
+        const double more = std::ceil((tfar - t) / wlim);
+        if (!(more <= (double)kbud)) throw Fail{LFMM_ENOCONV};
+        k += (int64_t)more;
+      }
+      if (k > kbud) throw Fail{LFMM_ENOCONV};
+      r.nfar = std::max<int>(1, (int)k);
       return r;
     }
-    r.nfar = std::max(1, (int)std::ceil(tfar / hf));
+    const double nf = std::ceil(tfar / hf);
+    if (!(nf <= (double)(quad_max_nodes / LFMM_NGL - LFMM_NP1 - r.nnear))) throw Fail{LFMM_ENOCONV};
+    r.nfar = std::max(1, (int)nf);
     r.hf = tfar / r.nfar;
     r.wmax = r.hf;
     return r;
@@ -578,10 +589,9 @@ struct lfmm_plan_s {
 
 namespace {
 
-int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, const lfmm_options* opt,
-              lfmm_plan_t** out) {
-  if (!out) return LFMM_EINVAL;
-  *out = nullptr;
+// The plan's parameters from the arguments of lfmm_plan, on the host only.
+int plan_params(int L, const double* d, const double* k, int p, int leaf_max, const lfmm_options* opt,
+                lfmm_plan_s* P) {
   if (L < 0 || L > LFMM_MAXL || p < 1 || p > LFMM_PMAX || leaf_max < 1) return LFMM_EINVAL;
   if (L > 0 && !d) return LFMM_EINVAL;
   if (!k) return LFMM_EINVAL;
@@ -591,7 +601,6 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     if (!std::isfinite(d[i])) return LFMM_EINVAL;
     if (i > 0 && !(d[i] < d[i - 1])) return LFMM_EINVAL;
   }
-  lfmm_plan_s* P = new lfmm_plan_s();
   P->st.L = L;
   for (int i = 0; i < LFMM_MAXL; i++) P->st.d[i] = (i < L) ? d[i] : 0.0;
   P->kmax = 0;
@@ -631,25 +640,35 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     if (opt->min_gap > 0) P->min_gap = opt->min_gap;
     P->profile = opt->profile;
     if (opt->precision < 0 || opt->precision > 1) {
-      delete P;
       return LFMM_EINVAL;
     }
     P->prec = opt->precision;
     if (opt->physical < 0 || opt->physical > 1) {
-      delete P;
       return LFMM_EINVAL;
     }
     P->physical = opt->physical;
     if (opt->reuse_operators < 0 || opt->reuse_operators > 1) {
-      delete P;
       return LFMM_EINVAL;
     }
     P->reuse_ops = opt->reuse_operators;
     if (opt->quad_tol < 0 || opt->quad_tol >= 1 || std::isnan(opt->quad_tol)) {
-      delete P;
       return LFMM_EINVAL;
     }
     if (opt->quad_tol > 0) P->quad_c = -std::log(opt->quad_tol);
+    if (opt->quad_max_nodes < 0) return LFMM_EINVAL;
+    if (opt->quad_max_nodes > 0) P->quad_max_nodes = opt->quad_max_nodes;
+  }
+  return LFMM_OK;
+}
+
+int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, const lfmm_options* opt,
+              lfmm_plan_t** out) {
+  if (!out) return LFMM_EINVAL;
+  *out = nullptr;
+  lfmm_plan_s* P = new lfmm_plan_s();
+  if (int rc = plan_params(L, d, k, p, leaf_max, opt, P)) {
+    delete P;
+    return rc;
   }
   memset(&P->rep, 0, sizeof(P->rep));
   try {
@@ -2251,6 +2270,25 @@ int lfmm_plan(int L, const double* d, const double* k, int p, int leaf_max, cons
   return plan_impl(L, d, k, p, leaf_max, opt, out);
 }
 
+int lfmm_quad_nodes(int L, const double* d, const double* k, int p, const lfmm_options* opt, double dz,
+                    double rho, int64_t* nodes) {
+  if (!nodes) return LFMM_EINVAL;
+  *nodes = 0;
+  if (!(dz > 0) || !std::isfinite(dz) || !(rho >= 0) || !std::isfinite(rho)) return LFMM_EINVAL;
+  lfmm_plan_s P;
+  if (int rc = plan_params(L, d, k, p, 1, opt, &P)) return rc;
+  // the count the rule would reach with an unlimited budget, reported beside LFMM_ENOCONV
+  const int64_t budget = P.quad_max_nodes;
+  P.quad_max_nodes = (int64_t)1 << 30;
+  try {
+    Rule r = P.make_rule(dz, rho, 2 * p + 1);
+    *nodes = ((int64_t)LFMM_NP1 + r.nnear + r.nfar) * LFMM_NGL;
+  } catch (Fail& f) {
+    return f.code;
+  }
+  return *nodes > budget ? LFMM_ENOCONV : LFMM_OK;
+}
+
 int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q,
                      double* phi, void* stream) {
   try {
@@ -2529,6 +2567,7 @@ const char* lfmm_status_string(int status) {
     case LFMM_EHIP: return "HIP runtime error";
     case LFMM_ENOTSUP: return "not supported";
     case LFMM_EIO: return "surrogate file unreadable, unwritable or not for this plan";
+    case LFMM_ENOCONV: return "Sommerfeld quadrature needs more contour nodes than the plan allows";
     default: return "unknown status";
   }
 }

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(HERE, "liblfmm.so")
 LFMM_OK = 0
 NOALLOC_BYTES = 512 << 20  # LFMM_NOALLOC_BYTES of include/lfmm.h
 _STATUS = {0: "ok", 1: "invalid argument", 2: "out of memory", 3: "HIP runtime error", 4: "not supported",
-           5: "surrogate or table file error"}
+           5: "surrogate or table file error", 6: "Sommerfeld quadrature over its node budget"}
+LFMM_ENOCONV = 6
 
 
 class LfmmError(RuntimeError):
@@ -27,7 +28,8 @@ class LfmmError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("contour_b", ctypes.c_double), ("max_depth", ctypes.c_int), ("min_gap", ctypes.c_double),
                 ("profile", ctypes.c_int), ("precision", ctypes.c_int), ("physical", ctypes.c_int),
-                ("reuse_operators", ctypes.c_int), ("quad_tol", ctypes.c_double)]
+                ("reuse_operators", ctypes.c_int), ("quad_tol", ctypes.c_double),
+                ("quad_max_nodes", ctypes.c_int64)]
 
 
 class Report(ctypes.Structure):
@@ -112,6 +114,8 @@ def load():
     L.lfmm_destroy.restype = None
     L.lfmm_status_string.argtypes = [ctypes.c_int]
     L.lfmm_status_string.restype = ctypes.c_char_p
+    L.lfmm_quad_nodes.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, ctypes.POINTER(Options), ctypes.c_double,
+                                  ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
     L.lfmm_translation.argtypes = [vp, ctypes.c_int, ctypes.c_double, _D, _D]
     L.lfmm_reaction_operator.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, _D]
@@ -173,22 +177,39 @@ def _xyz_arg(xyz, name):
     return n, _dev_arg(xyz, name, torch.float64, 3 * n)
 
 
+def quad_nodes(d, k, p, dz, rho, contour_b=0.5, quad_tol=0.0, quad_max_nodes=0):
+    """lfmm_quad_nodes: contour nodes of one reaction class at image distance dz and
+    horizontal distance rho, for the medium (d, k) and order p.  Host only (no device).
+    Returns (status, nodes): status 0, or LFMM_ENOCONV over quad_max_nodes."""
+    lib = load()
+    d = _f64(d)
+    k = _f64(k)
+    opt = Options(contour_b, 8, 1e-9, 0, 0, 0, 0, float(quad_tol), int(quad_max_nodes))
+    out = ctypes.c_int64(0)
+    rc = lib.lfmm_quad_nodes(len(d), d.ctypes.data_as(_D) if len(d) else None, k.ctypes.data_as(_D), int(p),
+                             ctypes.byref(opt), float(dz), float(rho), ctypes.byref(out))
+    if rc not in (LFMM_OK, LFMM_ENOCONV):
+        raise LfmmError(rc, "lfmm_quad_nodes")
+    return rc, int(out.value)
+
+
 class Plan:
     """lfmm_plan wrapper: d (L interfaces, decreasing), k (L+1 wavenumbers), order p, leaf size."""
 
     def __init__(self, d, k, p, leaf_max, contour_b=0.5, max_depth=8, min_gap=1e-9, profile=False, precision=0,
-                 physical=False, reuse_operators=False, quad_tol=0.0):
+                 physical=False, reuse_operators=False, quad_tol=0.0, quad_max_nodes=0):
         """precision 0: FP64 throughout; 1: mixed (FP32 near field and FP32-MFMA M2L).
         physical: return physical potentials (Phi times i k_l / (4 pi)) instead of Phi.
         reuse_operators: keep the previous evaluation's operators when its trees are the same.
-        quad_tol: truncation of the Sommerfeld contour (0: the default e^-40)."""
+        quad_tol: truncation of the Sommerfeld contour (0: the default e^-40).
+        quad_max_nodes: contour nodes one reaction class may take (0: 2^20); more is LFMM_ENOCONV."""
         self.lib = load()
         self.d = _f64(d)
         self.k = _f64(k)
         self.p = int(p)
         self.L = len(self.d)
         opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0, int(precision), 1 if physical else 0,
-                      1 if reuse_operators else 0, float(quad_tol))
+                      1 if reuse_operators else 0, float(quad_tol), int(quad_max_nodes))
         h = ctypes.c_void_p()
         dptr = self.d.ctypes.data_as(_D) if self.L else None
         _check(self.lib.lfmm_plan(self.L, dptr, self.k.ctypes.data_as(_D), self.p, int(leaf_max),

@@ -483,6 +483,22 @@ def test_quadrature_tolerance_option():
         assert ex.value.code == 1
 
 
+def test_quadrature_node_budget():
+    """A plan whose node budget is below what the workload's reaction classes need fails
+    the evaluation with LFMM_ENOCONV (no output claimed); the same plan parameters with
+    the default budget evaluate, and the budget equal to the largest class's count passes."""
+    lf = _lfmm()
+    w = W.three_layer_3k()
+    a = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"])
+    pa = a.eval_torch(w["x"], w["y"], w["z"], w["q"])
+    b = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], quad_max_nodes=64)
+    with pytest.raises(lf.LfmmError) as ex:
+        b.eval_torch(w["x"], w["y"], w["z"], w["q"])
+    assert ex.value.code == lf.LFMM_ENOCONV
+    c = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], quad_max_nodes=1 << 16)
+    assert np.array_equal(c.eval_torch(w["x"], w["y"], w["z"], w["q"]), pa)
+
+
 def test_autotune_keeps_results():
     import torch
     lf = _lfmm()

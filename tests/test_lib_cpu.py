@@ -26,6 +26,7 @@ def test_status_strings():
     lib = lfmm.load()
     assert lib.lfmm_status_string(0) == b"ok"
     assert lib.lfmm_status_string(1) == b"invalid argument"
+    assert b"contour nodes" in lib.lfmm_status_string(6)
     assert lib.lfmm_stage_name(0) == b"classify"
     assert lib.lfmm_stage_name(99) is None
 
@@ -114,3 +115,37 @@ def test_argument_checks_on_tensor_properties(monkeypatch):
         lfmm._dev_arg(torch.zeros(n, dtype=torch.int64), "layer", torch.int32, n)
     with pytest.raises(lfmm.LfmmError, match="on"):
         lfmm._dev_arg(good, "q", torch.complex128, n, torch.device("meta"))
+
+
+_D3 = [0.0, -1.2]
+_K3 = [0.8, 1.5, 2.0]
+
+
+@pytest.mark.skipif(not os.path.exists(lfmm.LIB_PATH), reason="liblfmm.so not built")
+def test_quadrature_node_budget_host_forced():
+    """The contour's node count (Section 3.5: far panels up to where t^(2p+1) e^(-t dz)
+    has decayed, at most 7/rho wide) grows as 1/dz once dz is small; a class over the
+    plan's budget is LFMM_ENOCONV, exactly beyond the count, and needs no device."""
+    rc, n1 = lfmm.quad_nodes(_D3, _K3, 8, dz=0.5, rho=0.3)
+    assert rc == 0 and n1 > 0 and n1 % 16 == 0
+    # smaller image distance: a longer contour
+    rc, n2 = lfmm.quad_nodes(_D3, _K3, 8, dz=0.05, rho=0.3)
+    assert rc == 0 and n2 > n1
+    # deep in the 1/dz regime the panel count doubles when dz halves
+    _, na = lfmm.quad_nodes(_D3, _K3, 8, dz=1e-4, rho=1.0)
+    _, nb = lfmm.quad_nodes(_D3, _K3, 8, dz=5e-5, rho=1.0)
+    assert abs(nb / na - 2.0) < 0.01
+    # the budget: the count itself passes, one node less fails and still reports the count
+    assert lfmm.quad_nodes(_D3, _K3, 8, dz=0.05, rho=0.3, quad_max_nodes=n2) == (0, n2)
+    assert lfmm.quad_nodes(_D3, _K3, 8, dz=0.05, rho=0.3, quad_max_nodes=n2 - 1) == (lfmm.LFMM_ENOCONV, n2)
+    # the default budget (2^20 nodes) refuses a class almost on the interface images
+    rc, n = lfmm.quad_nodes(_D3, _K3, 8, dz=1e-9, rho=1.0)
+    assert rc == lfmm.LFMM_ENOCONV and (n == 0 or n > (1 << 20))
+    # a looser truncation tolerance shortens the contour
+    _, nt = lfmm.quad_nodes(_D3, _K3, 8, dz=0.05, rho=0.3, quad_tol=1e-6)
+    assert nt < n2
+    for bad in (dict(dz=0.0, rho=0.3), dict(dz=0.1, rho=-1.0), dict(dz=float("nan"), rho=0.3),
+                dict(dz=0.1, rho=0.3, quad_max_nodes=-5)):
+        with pytest.raises(lfmm.LfmmError) as ex:
+            lfmm.quad_nodes(_D3, _K3, 8, **bad)
+        assert ex.value.code == 1
