@@ -270,6 +270,110 @@ def ten_interface_leg(args, lfmm, W, torch, dev, stream):
     return res
 
 
+def batch_leg(args, lfmm, W, torch, dev, stream):
+    """Batching: 256 independent three-layer problems (interface gap uniform on [1, 2],
+    k per layer uniform on [0.5, 2.5], N log-uniform on [2k, 64k], p = 6, leaf 64), on the
+    mixed path.  Tile shapes: lfmm_autotune on the median problem, applied to every plan.
+    Positions are prepared once per problem; one captured HIP graph then evaluates every
+    problem (graph branches tuned over 1, 2, 4, 8).  Timed beside it: the same problems
+    from scratch by the worker-thread batch (geometry included) and every problem's
+    apply queued eagerly on one stream.  Error: against the FP64 path, all problems."""
+    probs = W.batch_three_layer(seed=3)
+    ns = np.array([len(w["x"]) for w in probs])
+    ntot = int(ns.sum())
+    xyzs = [torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+            for w in probs]
+    qs = [torch.tensor(w["q"], dtype=torch.complex128, device=dev) for w in probs]
+    res = {"workload": "batch_three_layer(seed=3): 256 problems, N %d..%d, total %d, p = 6, leaf 64"
+           % (ns.min(), ns.max(), ntot), "n_total": ntot}
+
+    def plans_for(prec):
+        return [lfmm.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], precision=prec,
+                          quad_tol=args.mixed_quad_tol if prec else 0.0) for w in probs]
+
+    med = int(np.argsort(ns)[len(ns) // 2])
+    tp = plans_for(1)[med]
+    tr = tp.autotune(xyzs[med], qs[med], torch.empty_like(qs[med]))
+    tp.close()
+    tiles = (tr["gemm_ks"], tr["p2p_ta"], tr["p2p_ch"])
+    log("bench: batch tiles from the median problem (N = %d): M2L K-split %d, near field %d x %d"
+        % (ns[med], tiles[0], tiles[1], tiles[2]))
+    res["tiles"] = {"gemm_ks": tiles[0], "p2p_ta": tiles[1], "p2p_ch": tiles[2], "tuned_on_n": int(ns[med]),
+                    "ms_default": tr["ms_default"], "ms_best": tr["ms_best"]}
+    # FP64 reference of every problem (worker-thread batch, not timed)
+    p64 = plans_for(0)
+    ref = [torch.empty_like(q) for q in qs]
+    lfmm.eval_batch(p64, xyzs, qs, ref, nworkers=8)
+    torch.cuda.synchronize()
+    for pl in p64:
+        pl.close()
+    plans = plans_for(1)
+    for pl in plans:
+        pl.set_tiles(*tiles)
+    full = [torch.empty_like(q) for q in qs]
+    lfmm.eval_batch(plans, xyzs, qs, full, nworkers=8)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for r in range(reps):
+        lfmm.eval_batch(plans, xyzs, qs, full, nworkers=8)
+    torch.cuda.synchronize()
+    ms_full = (time.perf_counter() - t0) * 1000.0 / reps
+    t0 = time.perf_counter()
+    lfmm.batch_prepare(plans, xyzs, nworkers=8)
+    torch.cuda.synchronize()
+    ms_prep = (time.perf_counter() - t0) * 1000.0
+    ws = sum(pl.report()["workspace_bytes"] for pl in plans)
+    phis = [torch.zeros_like(q) for q in qs]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sweep = {}
+    best = None
+    for nb in (1, 2, 4, 8):
+        B = lfmm.Batch(plans, qs, phis, nbranch=nb)
+        rb = B.report()
+        for i in range(max(2, args.warmup)):
+            B.launch(stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(args.steps):
+            B.launch(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        sweep[nb] = {"ms_per_launch": ms, "graph_nodes": rb["graph_nodes"], "capture_ms": rb["capture_ms"]}
+        log("bench: batch graph, %d branches: %.3f ms per launch (%d nodes)" % (nb, ms, rb["graph_nodes"]))
+        if best is None or ms < sweep[best]["ms_per_launch"]:
+            best = nb
+        B.close()
+    identical = all(bool(torch.equal(a, b)) for a, b in zip(phis, full))
+    # eager: every problem's apply on one stream, no graph
+    for pl, q, ph in zip(plans, qs, phis):
+        pl.apply(q, ph, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        for pl, q, ph in zip(plans, qs, phis):
+            pl.apply(q, ph, stream=stream)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1000.0 / reps
+    num = sum(float(torch.sum(torch.abs(a - b) ** 2)) for a, b in zip(phis, ref))
+    den = sum(float(torch.sum(torch.abs(b) ** 2)) for b in ref)
+    emax = max(float(torch.max(torch.abs(a - b)) / torch.max(torch.abs(b))) for a, b in zip(phis, ref))
+    for pl in plans:
+        pl.close()
+    gms = sweep[best]["ms_per_launch"]
+    res.update({"graph": {"branches": best, "ms_per_launch": gms, "value": ntot / (gms / 1000.0),
+                          "sweep": sweep, "identical_to_eval_batch": identical},
+                "prepare_ms": ms_prep, "workspace_bytes_total": int(ws),
+                "eval_batch_from_scratch": {"ms": ms_full, "value": ntot / (ms_full / 1000.0)},
+                "eager_apply_one_stream": {"ms": ms_eager, "value": ntot / (ms_eager / 1000.0)},
+                "err2_vs_fp64": float(np.sqrt(num / den)), "errmax_vs_fp64": emax})
+    log("bench: batch of 256: graph %.3f ms (%.3e evals/s, %d branches), eager apply %.3f ms, from scratch %.3f ms,"
+        " prepare %.0f ms, workspace %.1f GB, identical %s, Err2 vs FP64 %.2e"
+        % (gms, ntot / (gms / 1000.0), best, ms_eager, ms_full, ms_prep, ws / 1e9, identical, np.sqrt(num / den)))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +386,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--no-tables", action="store_true", help="skip the pre-computed-tables leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batch leg")
     # the mixed path's contour ends where the integrands' envelope has fallen to 1e-10
     # (its error, about 5e-13, is four orders below the FP32 parts' 1.75e-7); the FP64
     # path keeps the library default e^-40
@@ -441,6 +546,8 @@ def main():
         out["tables"] = tables_leg(args, w, xyz, q, stream, plain, lfmm, torch)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(args, w, xyz, q, stream, plain, lfmm, torch)
+    if not args.no_batch:
+        out["batch"] = batch_leg(args, lfmm, W, torch, dev, stream)
     if args.ten_interface:
         out["ten_interface"] = ten_interface_leg(args, lfmm, W, torch, dev, stream)
     if args.scaling:

@@ -197,6 +197,60 @@ int lfmm_eval_batch(int nprob, lfmm_plan_t* const* plans, const int64_t* n, cons
                     const int32_t* const* layer, const double* const* q, double* const* phi, int nworkers,
                     int* status);
 
+/*
+ * Positions once, charges many times.
+ *
+ * lfmm_prepare -- the charge-independent part of lfmm_eval_device for these positions
+ * (n, xyz, layer as there): classification, the trees of Section 3.4, interaction
+ * lists, and the free-space and reaction translation operators (Section 2; Section 3.5,
+ * eq. (me2lesimplified)).  No charges are read.  Returns once the work is complete.
+ *
+ * lfmm_apply -- Phi at the prepared positions for charges q (device, 2n doubles,
+ * interleaved re/im as in lfmm_eval_device) into phi (device, 2n doubles): the
+ * charge-dependent kernels of Algorithm 1 (Section 3.4) from the upward pass on -- P2M,
+ * M2M, M2L, L2L, L2P, the near fields and the component sum -- queued on `stream` in one
+ * stream order.  The call synchronises nothing, allocates nothing and clears memory with
+ * kernels only, so it can be captured into a HIP graph.  The result equals
+ * lfmm_eval_device's for the same positions and charges bit for bit.  Valid after
+ * lfmm_prepare, or lfmm_eval_device on the plan's own workspace, until the plan's next
+ * evaluation (LFMM_EINVAL otherwise); calls on one plan must not overlap.
+ */
+int lfmm_prepare(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, void* stream);
+int lfmm_apply(lfmm_plan_t* plan, const double* q, double* phi, void* stream);
+
+/*
+ * lfmm_batch -- many independent layered problems (each its own medium, particles and
+ * plan) evaluated by one launch of one HIP graph.
+ *
+ * lfmm_batch_prepare runs lfmm_prepare for every problem on nworkers host threads
+ * (<= 0: 8), each on a stream of its own; status (host, nprob ints, may be NULL)
+ * receives each problem's code, the return value the first failing one.
+ *
+ * lfmm_batch_capture captures lfmm_apply of every prepared problem, with charges q[i]
+ * and output phi[i] (device pointers), on nbranch (<= 0: 4, at most 16) independent
+ * branches of one graph, the problems spread over the branches by size (largest first,
+ * each to the least loaded branch), and instantiates it.  No problem is evaluated.
+ *
+ * lfmm_batch_launch launches that graph on `stream`: every problem's phi[i] then equals
+ * lfmm_eval_device(plans[i], n[i], xyz[i], layer[i], q[i], ...) bit for bit, for
+ * whatever q[i] holds when the graph runs.  The plans must be distinct, and must be
+ * neither evaluated, prepared again nor destroyed while the batch is used; the q and
+ * phi buffers must stay allocated.  rep (may be NULL) receives the batch's sizes.
+ */
+typedef struct lfmm_batch_s lfmm_batch_t;
+typedef struct {
+  int64_t n_total;     /* particles over all problems */
+  int64_t graph_nodes; /* kernel and dependency nodes of the captured graph */
+  int branches;        /* independent branches of the graph */
+  double capture_ms;   /* host wall time of the capture and instantiation */
+} lfmm_batch_report;
+int lfmm_batch_prepare(int nprob, lfmm_plan_t* const* plans, const int64_t* n, const double* const* xyz,
+                       const int32_t* const* layer, int nworkers, int* status);
+int lfmm_batch_capture(int nprob, lfmm_plan_t* const* plans, const double* const* q, double* const* phi,
+                       int nbranch, lfmm_batch_t** out, lfmm_batch_report* rep);
+int lfmm_batch_launch(lfmm_batch_t* batch, void* stream);
+void lfmm_batch_destroy(lfmm_batch_t* batch);
+
 /* Report of the last evaluation on this plan. */
 int lfmm_last_report(const lfmm_plan_t* plan, lfmm_report* rep);
 
@@ -208,6 +262,11 @@ void lfmm_destroy(lfmm_plan_t* plan);
 
 /* Text of a status code. */
 const char* lfmm_status_string(int status);
+
+/* The HIP error behind the library's last LFMM_EHIP, from any thread (its name, code and
+ * the library source line that saw it), or "" if there was none.  The string belongs to
+ * the library and stays valid until the next failing HIP call after the next one. */
+const char* lfmm_last_hip_error(void);
 
 /* Contour nodes of the Sommerfeld quadrature (Section 3.5: the deformed contour, then panels of
  * the real axis truncated where the integrand envelope t^{2p+1} e^{-t dz} has decayed to quad_tol,
@@ -239,6 +298,12 @@ typedef struct {
  */
 int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi,
                   void* stream, lfmm_tune_report* rep);
+
+/* Set a plan's tile shapes to ones lfmm_autotune carries (for instance those it chose on
+ * a representative problem): M2L K-split gemm_ks in {1, 2, 4}; near-field p2p_ta in
+ * {4, 8, 16} targets per wave step and p2p_ch in {128, 256, 512} sources per tile.
+ * Later evaluations use them; LFMM_EINVAL for other values. */
+int lfmm_set_tiles(lfmm_plan_t* plan, int gemm_ks, int p2p_ta, int p2p_ch);
 
 /* ---- learned surrogate of the reaction M2L integrals ----
  *

@@ -45,10 +45,23 @@ struct Arena {
   void* take(size_t bytes);
 };
 
+// The library's last failed HIP call, from any thread (for lfmm_last_hip_error).
+static std::mutex g_hip_err_mu;
+static char g_hip_err[2][160] = {"", ""};
+static int g_hip_err_cur = 0;
+static void note_hip_error(hipError_t e, int line) {
+  std::lock_guard<std::mutex> g(g_hip_err_mu);
+  const int nx = g_hip_err_cur ^ 1;
+  snprintf(g_hip_err[nx], sizeof(g_hip_err[nx]), "%s (%d) at lfmm_host.hip:%d", hipGetErrorName(e), (int)e, line);
+  g_hip_err_cur = nx;
+}
 #define HIPCHK(x)                       \
   do {                                  \
     hipError_t _e = (x);                \
-    if (_e != hipSuccess) throw Fail{LFMM_EHIP}; \
+    if (_e != hipSuccess) {             \
+      note_hip_error(_e, __LINE__);     \
+      throw Fail{LFMM_EHIP};            \
+    }                                   \
   } while (0)
 
 struct Fail {
@@ -408,6 +421,18 @@ struct lfmm_plan_s {
   OpTables tab;
   std::vector<int> rop_idx;       // reaction operator of each (trees, level, heights, offset) key
   std::vector<size_t> rop_dirty;  // keys the last evaluation set
+  // The charge-dependent launches of the last evaluation, in the order they were
+  // queued on its main stream (zeroing, P2M, near field, M2M, M2L, L2L, L2P,
+  // reaction near field, component sum).  Everything they read besides the charges
+  // stays in the plan's workspace, so replaying them after gathering new charges into
+  // tree order evaluates the same positions again (lfmm_apply).
+  std::vector<std::function<void(hipStream_t, const double*, double*)>> apply_list;
+  bool apply_ready = false;  // the list and its workspace are valid (set by lfmm_prepare / lfmm_eval_device)
+  bool prep_only = false;    // the evaluation records the list without running it (lfmm_prepare)
+  int64_t apply_n = 0;       // particles of the prepared evaluation
+  int apply_ntp = 0;         // tree points (particles plus polarisation images)
+  const int* apply_orig = nullptr;  // particle index of each tree point in tree order
+  double* apply_pq = nullptr;       // tree-order charges
 
   // device workspace in use: the plan's own, or one lent by a batch worker
   std::map<std::string, DevBuf>* bufp = &bufs;
@@ -675,6 +700,7 @@ int plan_impl(int L, const double* d, const double* k, int p, int leaf_max, cons
     std::vector<double> gx, gw;
     gauss_rule(LFMM_NGL, gx, gw);
     lk_set_gl(gx.data(), gw.data());
+    lk_m2l_gemm_init();
     std::vector<double> G = gaunt_table(p);
     HIPCHK(hipMalloc(&P->d_gaunt, G.size() * sizeof(double)));
     HIPCHK(hipMemcpy(P->d_gaunt, G.data(), G.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -1354,12 +1380,23 @@ void build_blocks(const std::vector<int>& counts, const std::vector<Group>& grou
 int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* layer_in, const double* q,
               double* phi, hipStream_t s) {
   if (!P || n64 < 0 || n64 >= (int64_t)1 << 31) return LFMM_EINVAL;
-  if (n64 > 0 && (!xyz || !q || !phi)) return LFMM_EINVAL;
+  if (n64 > 0 && (!xyz || (!P->prep_only && (!q || !phi)))) return LFMM_EINVAL;
   int n = (int)n64;
   lfmm_report& rep = P->rep;
   memset(&rep, 0, sizeof(rep));
   rep.precision = P->prec;
+  (void)hipGetLastError();  // the launch check below is for this evaluation's own launches
+  P->apply_list.clear();
+  P->apply_ready = false;
+  P->apply_n = n;
+  P->apply_ntp = 0;
   if (n == 0) return LFMM_OK;
+  // a charge-dependent launch: queued now (unless only preparing) and recorded
+  const bool run_q = !P->prep_only;
+  auto qrun = [&](std::function<void(hipStream_t, const double*, double*)> f) {
+    if (run_q) f(s, q, phi);
+    P->apply_list.push_back(std::move(f));
+  };
   P->pin_reset();
   std::string prev_opsig;  // signature of the operators in the buffer (cleared until this evaluation succeeds)
   prev_opsig.swap(P->last_opsig);
@@ -1593,6 +1630,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   double* pz = P->dev<double>("pz", ntp);
   double* pq = P->dev<double>("pq", 2 * (size_t)ntp);
   lk_gather(ntp, sg, rec, px, py, pz, pq, s);
+  int* tp_orig = P->dev<int>("tp_orig", ntp);
+  lk_point_origin(ntp, ntrees, d_trees, perm, d_lstart, sg, tp_orig, s);
+  P->apply_ntp = ntp;
+  P->apply_orig = tp_orig;
+  P->apply_pq = pq;
   send(ST_TREE, s);
   // the operator stream (and the job stream) may start from here: everything the
   // operator stream reads is uploaded on it ahead of its kernels (copies of all
@@ -1607,8 +1649,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // while the host builds the operator tables
   double* M = P->dev<double>("M", (size_t)NR * NCK * 2);
   double* Lx = P->dev<double>("L", (size_t)NR * NCK * 2);
-  lk_zero(M, (size_t)NR * NCK * 2, s);
-  lk_zero(Lx, (size_t)NR * NCK * 2, s);
+  qrun([=](hipStream_t ss, const double*, double*) {
+    lk_zero(M, (size_t)NR * NCK * 2, ss);
+    lk_zero(Lx, (size_t)NR * NCK * 2, ss);
+  });
   // leaf segments of trees with a far field
   std::vector<int> seg_row0, seg_prefix;
   int ptot = 0;
@@ -1626,8 +1670,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   if (ptot) {
     int* d_r0 = P->upload("p2m_r0", seg_row0, s);
     int* d_pf = P->upload("p2m_pf", seg_prefix, s);
-    lk_p2m((int)seg_row0.size(), d_r0, d_pf, ptot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, px, py,
-           pz, pq, p, NCK, M, s);
+    const int nseg = (int)seg_row0.size();
+    qrun([=](hipStream_t ss, const double*, double*) {
+      lk_p2m(nseg, d_r0, d_pf, ptot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, px, py, pz, pq, p,
+             NCK, M, ss);
+    });
   }
   send(ST_P2M, s);
   // ---------------- operators
@@ -1645,8 +1692,9 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     opse[2 * (size_t)op] = et;
     opse[2 * (size_t)op + 1] = es;
   };
-  // op 0 is the zero operator
-  int nops = 1;
+  // M2L operators (free and reaction) and shift operators (M2M, L2L) are numbered
+  // separately, each array with the zero operator at index 0
+  int nops = 1, nsh = 1;
   std::vector<OpDesc> fops;
   std::vector<int> m2l_op((size_t)ntrees * 9 * 343, 0), m2m_op((size_t)ntrees * 9 * 8, 0),
       l2l_op((size_t)ntrees * 9 * 8, 0);
@@ -1668,13 +1716,13 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
         for (int ch = 0; ch < 8; ch++) {
           double cx = (((ch >> 2) & 1) - 0.5) * h, cy = (((ch >> 1) & 1) - 0.5) * h, cz = ((ch & 1) - 0.5) * h;
           if (T.kind == 0 || T.kind == 2) {  // M2M: b = parent - child
-            OpDesc od{-cx, -cy, -cz, T.k, 0, nops};
-            m2m_op[((size_t)t * 9 + l) * 8 + ch] = nops++;
+            OpDesc od{-cx, -cy, -cz, T.k, 0, nsh};
+            m2m_op[((size_t)t * 9 + l) * 8 + ch] = nsh++;
             fops.push_back(od);
           }
           if (T.kind == 0 || T.kind == 1) {  // L2L: b = child - parent
-            OpDesc od{cx, cy, cz, T.k, 0, nops};
-            l2l_op[((size_t)t * 9 + l) * 8 + ch] = nops++;
+            OpDesc od{cx, cy, cz, T.k, 0, nsh};
+            l2l_op[((size_t)t * 9 + l) * 8 + ch] = nsh++;
             fops.push_back(od);
           }
         }
@@ -1760,12 +1808,16 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.n_react_classes = (int64_t)classes.size();
   rep.n_react_nodes = nodes_total;
   rep.n_ops_react = (int64_t)rops.size();
-  double* ops = P->dev<double>("ops", (size_t)nops * opsz);
+  // shift operators in FP64 with the shift GEMM's stride; M2L operators in the M2L
+  // GEMMs' k-step-major layout, FP32 on the mixed path and FP64 otherwise
+  const int opsz_m = 2 * NKS * (m2l_nrt(NC) * 64 + 4 * m2l_xr(NC));
+  double* sops = P->dev<double>("sops", (size_t)nsh * opsz);
+  double* ops = m2l32 ? nullptr : P->dev<double>("ops", (size_t)nops * opsz_m);
   float* ops32 = nullptr;
   int* d_opsc = nullptr;
   int* d_sc = P->upload("exp_scale", hse, s);
   if (m2l32) {
-    ops32 = P->dev<float>("ops32", (size_t)nops * opsz);
+    ops32 = P->dev<float>("ops32", (size_t)nops * opsz_m);
     opse.resize(2 * (size_t)nops, 0);
     d_opsc = P->upload("op_scale", opse, s2);
   }
@@ -1822,6 +1874,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     app(&P->tab.tol, sizeof(double));
     app(&ops, sizeof(ops));
     app(&ops32, sizeof(ops32));
+    app(&sops, sizeof(sops));
   }
   const bool reuse = P->reuse_ops && P->bufp == &P->bufs && !prev_opsig.empty() && opsig == prev_opsig;
   rep.ops_reused = reuse ? 1 : 0;
@@ -1856,10 +1909,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       d_td = P->upload("tab_gd", tD, s2);
     }
     double* Iall = classes.empty() ? nullptr : P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-    lk_zero(ops, opsz, s2);  // operator 0: the zero operator
-    if (m2l32) lk_zero((double*)ops32, opsz / 2, s2);
+    lk_zero(sops, opsz, s2);  // operator 0 of both arrays: the zero operator
+    if (m2l32) lk_zero((double*)ops32, opsz_m / 2, s2);
+    else lk_zero(ops, opsz_m, s2);
     sbeg(ST_OPS_FREE, s2);
-    lk_transop((int)fops.size(), d_fops, ops, opsz, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
+    lk_transop((int)fops.size(), d_fops, sops, opsz, ops, opsz_m, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
     send(ST_OPS_FREE, s2);
     HIPCHK(hipEventRecord(P->ops_ev, s2));
     sbeg(ST_REACT_TABLES, s2);
@@ -1892,7 +1946,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
                       NC, Iall, s2);
       send(ST_REACT_TAB, s2);
       sbeg(ST_REACT_EXPAND, s2);
-      lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz, p, NC, NKS, ops32, d_opsc, s2);
+      lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz_m, p, NC, NKS, ops32, d_opsc, s2);
     } else {
       send(ST_REACT_TABLES, s2);
       sbeg(ST_REACT_MFMA, s2);
@@ -1910,7 +1964,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // that those are dispatched first (the near field fills the GPU and would
   // otherwise starve them; the M2L waits for the reaction operators)
   double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
-  lk_zero(phi_tp, 2 * (size_t)ntp, s);
+  qrun([=](hipStream_t ss, const double*, double*) { lk_zero(phi_tp, 2 * (size_t)ntp, ss); });
   // ---------------- free-space near field (its stage brackets the kernel alone)
   {
     std::vector<int> r0, pf;
@@ -1932,9 +1986,12 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       rep.p2p_series = krmax <= 0.5 ? 2 : (krmax <= 1.0 ? 1 : 0);
       const int series = rep.p2p_series;
       sbeg(ST_P2P, s);
-      lk_p2p_free((int)r0.size(), d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees,
-                  d_grid_off, grid, px, py, pz, pq, sg, phi_tp, series, P->p2p_ta, P->p2p_ch, p2p32 ? 1 : 0,
-                  d_cnt + 3, s);
+      const int nr0 = (int)r0.size(), ta = P->p2p_ta, ch = P->p2p_ch, f32 = p2p32 ? 1 : 0;
+      unsigned long long* cnt3 = d_cnt + 3;
+      qrun([=](hipStream_t ss, const double*, double*) {
+        lk_p2p_free(nr0, d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, d_grid_off, grid,
+                    px, py, pz, pq, sg, phi_tp, series, ta, ch, f32, cnt3, ss);
+      });
     } else {
       sbeg(ST_P2P, s);
     }
@@ -2081,7 +2138,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   std::vector<int> gs_m2m, gs_l2l, gs_m2l, bf_m2m, bc_m2m, bf_l2l, bc_l2l, bf_m2l, bc_m2l;
   // M2L: four waves share each 16-target tile and split its operator sequence
   // (fastest on both shallow and deep trees)
-  const int ks_m2l = P->gemm_ks > 0 ? P->gemm_ks : 4;
+  // (a larger split where one wave's operator list would not fit the CU's LDS)
+  int ks_m2l = P->gemm_ks > 0 ? P->gemm_ks : 4;
+  while (ks_m2l < 4 && lk_m2l_lds_bytes(kmax_m2l, ks_m2l) > lk_m2l_lds_max()) ks_m2l *= 2;
+  if (lk_m2l_lds_bytes(kmax_m2l, ks_m2l) > lk_m2l_lds_max()) throw Fail{LFMM_ENOTSUP};
   // M2M: the waves of a 16-target tile split each parent's eight child operators
   // (a level's parents alone give too few 64-target blocks to fill the GPU)
   static const int ks_m2m = getenv("LFMM_M2M_KS") ? atoi(getenv("LFMM_M2M_KS")) : 4;  // tuning override
@@ -2122,10 +2182,16 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   // the free-space operators are needed from here on
   HIPCHK(hipStreamWaitEvent(s, P->ops_ev, 0));
   sbeg(ST_M2M, s);
-  for (int lp = Dmax - 1; lp >= 2; lp--)
-    if (bc_m2m[lp] > 0)
-      lk_gemm(P->NRT, ks_m2m, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, J_m2m.srowid, sr_m2m, 8, ops, opsz, NKS, M, M,
-              NCK, NC, s);
+  {
+    const int nrt = P->NRT, ksm = ks_m2m;
+    const int* srow = J_m2m.srowid;
+    qrun([=](hipStream_t ss, const double*, double*) {
+      for (int lp = Dmax - 1; lp >= 2; lp--)
+        if (bc_m2m[lp] > 0)
+          lk_gemm(nrt, ksm, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, srow, sr_m2m, 8, sops, opsz, NKS, M, M, NCK, NC,
+                  ss);
+    });
+  }
   send(ST_M2M, s);
   // and the reaction operators from here on
   HIPCHK(hipStreamWaitEvent(s, P->join_ev, 0));
@@ -2135,20 +2201,33 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     // mixed precision: rescaled FP32 copy of the multipole expansions (its time is
     // counted with the upward pass, so that the m2l stage brackets the GEMM alone)
     float* M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
-    lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, s);
+    qrun([=](hipStream_t ss, const double*, double*) { lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, ss); });
     sbeg(ST_M2L, s);
-    lk_gemm32(NC, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops32, opsz, NKS, M32,
-              Lx, NCK, box_tree, box_level, d_sc, s);
+    const int nb = (int)b_m2l.size();
+    const int* srow = J_m2l.srowid;
+    qrun([=](hipStream_t ss, const double*, double*) {
+      lk_gemm32(NC, ks_m2l, nb, d_bm2l, d_sq_m2l, srow, sr_m2l, kmax_m2l, ops32, opsz_m, NKS, M32, Lx, NCK, box_tree,
+                box_level, d_sc, ss);
+    });
   } else if (!b_m2l.empty()) {
-    lk_m2l_gemm64(NC, ks_m2l, (int)b_m2l.size(), d_bm2l, d_sq_m2l, J_m2l.srowid, sr_m2l, kmax_m2l, ops, opsz, NKS, M,
-                  Lx, NCK, s);
+    const int nb = (int)b_m2l.size();
+    const int* srow = J_m2l.srowid;
+    qrun([=](hipStream_t ss, const double*, double*) {
+      lk_m2l_gemm64(NC, ks_m2l, nb, d_bm2l, d_sq_m2l, srow, sr_m2l, kmax_m2l, ops, opsz_m, NKS, M, Lx, NCK, ss);
+    });
   }
   mark(10);
   // ---------------- downward pass
-  for (int l = 3; l <= Dmax; l++)
-    if (bc_l2l[l] > 0)
-      lk_gemm(P->NRT, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, J_l2l.srowid, sr_l2l, 1, ops, opsz, NKS, Lx, Lx,
-              NCK, NC, s);
+  {
+    const int nrt = P->NRT;
+    const int* srow = J_l2l.srowid;
+    qrun([=](hipStream_t ss, const double*, double*) {
+      for (int l = 3; l <= Dmax; l++)
+        if (bc_l2l[l] > 0)
+          lk_gemm(nrt, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, srow, sr_l2l, 1, sops, opsz, NKS, Lx, Lx, NCK, NC,
+                  ss);
+    });
+  }
   mark(11);
   {
     std::vector<int> s0, pf;
@@ -2166,8 +2245,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     if (tot) {
       int* d_s0 = P->upload("l2p_s0", s0, s);
       int* d_pf = P->upload("l2p_pf", pf, s);
-      lk_l2p((int)s0.size(), d_s0, d_pf, tot, leafrow, box_code, box_tree, box_level, d_trees, px, py, pz, sg, p, NCK,
-             Lx, phi_tp, s);
+      const int ns0 = (int)s0.size();
+      qrun([=](hipStream_t ss, const double*, double*) {
+        lk_l2p(ns0, d_s0, d_pf, tot, leafrow, box_code, box_tree, box_level, d_trees, px, py, pz, sg, p, NCK, Lx,
+               phi_tp, ss);
+      });
     }
   }
   send(ST_L2P, s);
@@ -2213,8 +2295,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
           lk_nf_nodes(comps[c].nnodes, rules[c], st, lts[c], lss[c], as[c], bs[c], nkr + 2 * comps[c].node0,
                       nfac + 2 * comps[c].node0, nkzt + 2 * comps[c].node0, nkzs + 2 * comps[c].node0, s);
         NFComp* d_comps = P->upload((tag + "comps").c_str(), comps, s);
-        lk_nf_react(nbox(tt, Dr), first_row(tt, Dr), tt, (int)comps.size(), d_comps, box_start, box_cnt, box_code,
-                    d_trees, d_grid_off, grid, px, py, pz, pq, sg, nkr, nfac, nkzt, nkzs, phi_tp, s);
+        const int nbt = nbox(tt, Dr), fr = first_row(tt, Dr), nco = (int)comps.size();
+        qrun([=](hipStream_t ss, const double*, double*) {
+          lk_nf_react(nbt, fr, tt, nco, d_comps, box_start, box_cnt, box_code, d_trees, d_grid_off, grid, px, py, pz, pq,
+                      sg, nkr, nfac, nkzt, nkzs, phi_tp, ss);
+        });
         rep.nf_react_pairs += 1;
       }
   }
@@ -2228,7 +2313,13 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     tgt_list[l * max_tt + 2] = tgt_tree[2 * l + 1];
   }
   int* d_tl = P->upload("tgt_list", tgt_list, s);
-  lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, phi, st, P->physical, s);
+  {
+    const Stack stk = st;
+    const int phys = P->physical;
+    qrun([=](hipStream_t ss, const double*, double* ph) {
+      lk_final_sum(n, layer, inv_perm, d_lstart, d_tl, max_tt, d_trees, phi_tp, ph, stk, phys, ss);
+    });
+  }
   send(ST_SUM, s);
   // every stream has joined the main one by now: the staging arena's last use is
   // complete once the main stream gets here
@@ -2237,6 +2328,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   unsigned long long hcnt[4] = {0, 0, 0, 0};
   P->rb_add(hcnt, d_cnt, sizeof(hcnt), s);
   P->rb_flush(s);
+  // the readback waited for the main stream, which every other stream had joined:
+  // the staging arena is free again, and no later call waits on an event recorded on
+  // the caller's stream (which may be gone by then, as a batch worker's is)
+  P->pin_pending = false;
   rep.m2l_pairs = (int64_t)hcnt[0];
   rep.m2m_pairs = (int64_t)hcnt[1];
   rep.l2l_pairs = (int64_t)hcnt[2];
@@ -2292,7 +2387,10 @@ int lfmm_quad_nodes(int L, const double* d, const double* k, int p, const lfmm_o
 int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q,
                      double* phi, void* stream) {
   try {
-    return eval_impl(plan, n, xyz, layer, q, phi, (hipStream_t)stream);
+    int rc = eval_impl(plan, n, xyz, layer, q, phi, (hipStream_t)stream);
+    // the recorded launches stay valid while the workspace is the plan's own
+    if (rc == LFMM_OK && plan->bufp == &plan->bufs && !plan->arena) plan->apply_ready = true;
+    return rc;
   } catch (Fail& f) {
     // drain what this call queued before its staging buffers are reused
     (void)hipStreamSynchronize((hipStream_t)stream);
@@ -2301,8 +2399,45 @@ int lfmm_eval_device(lfmm_plan_t* plan, int64_t n, const double* xyz, const int3
     plan->rb_list.clear();
     plan->rb_direct.clear();
     plan->rb_used = 0;
+    plan->pin_pending = false;  // the streams are drained
     return f.code;
   }
+}
+
+int lfmm_prepare(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, void* stream) {
+  if (!plan) return LFMM_EINVAL;
+  if (plan->bufp != &plan->bufs || plan->arena) return LFMM_EINVAL;  // only on the plan's own workspace
+  hipStream_t s = (hipStream_t)stream;
+  int rc;
+  plan->prep_only = true;
+  try {
+    rc = eval_impl(plan, n, xyz, layer, nullptr, nullptr, s);
+    if (rc == LFMM_OK && hipStreamSynchronize(s) != hipSuccess) rc = LFMM_EHIP;
+  } catch (Fail& f) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamSynchronize(plan->s2);
+    if (plan->s3) (void)hipStreamSynchronize(plan->s3);
+    plan->rb_list.clear();
+    plan->rb_direct.clear();
+    plan->rb_used = 0;
+    plan->pin_pending = false;  // the streams are drained
+    rc = f.code;
+  }
+  plan->prep_only = false;
+  plan->apply_ready = rc == LFMM_OK;
+  if (rc != LFMM_OK) plan->apply_list.clear();
+  return rc;
+}
+
+int lfmm_apply(lfmm_plan_t* plan, const double* q, double* phi, void* stream) {
+  if (!plan || !plan->apply_ready) return LFMM_EINVAL;
+  if (plan->apply_n == 0) return LFMM_OK;
+  if (!q || !phi) return LFMM_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  (void)hipGetLastError();  // the check below is for these launches
+  lk_gather_q(plan->apply_ntp, plan->apply_orig, q, plan->apply_pq, s);
+  for (auto& f : plan->apply_list) f(s, q, phi);
+  return hipPeekAtLastError() == hipSuccess ? LFMM_OK : LFMM_EHIP;
 }
 
 int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi) {
@@ -2331,6 +2466,7 @@ int lfmm_eval(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* la
     plan->rb_list.clear();
     plan->rb_direct.clear();
     plan->rb_used = 0;
+    plan->pin_pending = false;  // the streams are drained
     return f.code;
   }
 }
@@ -2381,6 +2517,7 @@ int lfmm_eval_targets_device(lfmm_plan_t* plan, int64_t n_src, const double* src
       plan->rb_list.clear();
       plan->rb_direct.clear();
       plan->rb_used = 0;
+      plan->pin_pending = false;  // the streams are drained
     }
     return f.code;
   }
@@ -2421,6 +2558,7 @@ int lfmm_eval_targets(lfmm_plan_t* plan, int64_t n_src, const double* src_xyz, c
     plan->rb_list.clear();
     plan->rb_direct.clear();
     plan->rb_used = 0;
+    plan->pin_pending = false;  // the streams are drained
     return f.code;
   }
 }
@@ -2468,6 +2606,148 @@ int lfmm_eval_batch(int nprob, lfmm_plan_t* const* plans, const int64_t* n, cons
     if (rc == LFMM_OK && st[i] != LFMM_OK) rc = st[i];
   }
   return rc;
+}
+
+struct lfmm_batch_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int lfmm_batch_prepare(int nprob, lfmm_plan_t* const* plans, const int64_t* n, const double* const* xyz,
+                       const int32_t* const* layer, int nworkers, int* status) {
+  if (nprob <= 0 || !plans || !n || !xyz) return LFMM_EINVAL;
+  {
+    std::set<const lfmm_plan_t*> seen;
+    for (int i = 0; i < nprob; i++) {
+      if (!plans[i] || !seen.insert(plans[i]).second || n[i] < 0) return LFMM_EINVAL;
+      if (n[i] > 0 && !xyz[i]) return LFMM_EINVAL;
+    }
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return LFMM_EHIP;
+  const int nw = std::max(1, std::min(nworkers > 0 ? nworkers : 8, nprob));
+  std::vector<int> st(nprob, LFMM_OK);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    hipStream_t ws = nullptr;
+    if (hipSetDevice(dev) != hipSuccess || hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
+      for (int i; (i = next.fetch_add(1)) < nprob;) st[i] = LFMM_EHIP;
+      return;
+    }
+    for (int i; (i = next.fetch_add(1)) < nprob;)
+      st[i] = lfmm_prepare(plans[i], n[i], xyz[i], layer ? layer[i] : nullptr, ws);
+    (void)hipStreamDestroy(ws);
+  };
+  std::vector<std::thread> th;
+  for (int w = 0; w < nw; w++) th.emplace_back(worker);
+  for (auto& t : th) t.join();
+  int rc = LFMM_OK;
+  for (int i = 0; i < nprob; i++) {
+    if (status) status[i] = st[i];
+    if (rc == LFMM_OK && st[i] != LFMM_OK) rc = st[i];
+  }
+  return rc;
+}
+
+int lfmm_batch_capture(int nprob, lfmm_plan_t* const* plans, const double* const* q, double* const* phi,
+                       int nbranch, lfmm_batch_t** out, lfmm_batch_report* rep) {
+  if (!out) return LFMM_EINVAL;
+  *out = nullptr;
+  if (nprob <= 0 || !plans || !q || !phi) return LFMM_EINVAL;
+  {
+    std::set<const lfmm_plan_t*> seen;
+    for (int i = 0; i < nprob; i++) {
+      if (!plans[i] || !seen.insert(plans[i]).second || !plans[i]->apply_ready) return LFMM_EINVAL;
+      if (plans[i]->apply_n > 0 && (!q[i] || !phi[i])) return LFMM_EINVAL;
+    }
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  int rc = LFMM_OK;
+  // the problems over the branches, largest first, each to the least loaded branch
+  const int nb = std::max(1, std::min(nbranch > 0 ? nbranch : 4, std::min(nprob, 16)));
+  std::vector<int> order(nprob);
+  for (int i = 0; i < nprob; i++) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return plans[a]->apply_n > plans[b]->apply_n; });
+  std::vector<int64_t> load(nb, 0);
+  std::vector<std::vector<int>> members(nb);
+  for (int i : order) {
+    const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    members[b].push_back(i);
+    load[b] += plans[i]->apply_n;
+  }
+  hipStream_t cs = nullptr;
+  std::vector<hipStream_t> br(nb, nullptr);
+  std::vector<hipEvent_t> ev(nb + 1, nullptr);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool capturing = false;
+  auto cleanup = [&]() {
+    if (capturing) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+    }
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& b : br)
+      if (b) (void)hipStreamDestroy(b);
+    if (cs) (void)hipStreamDestroy(cs);
+  };
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = LFMM_EHIP;
+  for (int b = 0; b < nb && rc == LFMM_OK; b++)
+    if (hipStreamCreateWithFlags(&br[b], hipStreamNonBlocking) != hipSuccess) rc = LFMM_EHIP;
+  for (int b = 0; b <= nb && rc == LFMM_OK; b++)
+    if (hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess) rc = LFMM_EHIP;
+  if (rc == LFMM_OK && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = LFMM_EHIP;
+  capturing = rc == LFMM_OK;
+  if (rc == LFMM_OK && hipEventRecord(ev[nb], cs) != hipSuccess) rc = LFMM_EHIP;
+  for (int b = 0; b < nb && rc == LFMM_OK; b++) {
+    if (hipStreamWaitEvent(br[b], ev[nb], 0) != hipSuccess) {
+      rc = LFMM_EHIP;
+      break;
+    }
+    for (int i : members[b])
+      if ((rc = lfmm_apply(plans[i], q[i], phi[i], br[b])) != LFMM_OK) break;
+    if (rc == LFMM_OK && (hipEventRecord(ev[b], br[b]) != hipSuccess || hipStreamWaitEvent(cs, ev[b], 0) != hipSuccess))
+      rc = LFMM_EHIP;
+  }
+  if (capturing) {
+    capturing = false;
+    if (hipStreamEndCapture(cs, &graph) != hipSuccess && rc == LFMM_OK) rc = LFMM_EHIP;
+  }
+  if (rc == LFMM_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) rc = LFMM_EHIP;
+  cleanup();
+  if (rc != LFMM_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  lfmm_batch_s* B = new lfmm_batch_s();
+  B->graph = graph;
+  B->exec = exec;
+  if (rep) {
+    memset(rep, 0, sizeof(*rep));
+    for (int i = 0; i < nprob; i++) rep->n_total += plans[i]->apply_n;
+    size_t nn = 0;
+    if (hipGraphGetNodes(graph, nullptr, &nn) == hipSuccess) rep->graph_nodes = (int64_t)nn;
+    rep->branches = nb;
+    rep->capture_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+  }
+  *out = B;
+  return LFMM_OK;
+}
+
+int lfmm_batch_launch(lfmm_batch_t* batch, void* stream) {
+  if (!batch || !batch->exec) return LFMM_EINVAL;
+  return hipGraphLaunch(batch->exec, (hipStream_t)stream) == hipSuccess ? LFMM_OK : LFMM_EHIP;
+}
+
+void lfmm_batch_destroy(lfmm_batch_t* batch) {
+  if (!batch) return;
+  if (batch->exec) (void)hipGraphExecDestroy(batch->exec);
+  if (batch->graph) (void)hipGraphDestroy(batch->graph);
+  delete batch;
 }
 
 // ---- allocation-free evaluation ----
@@ -2559,6 +2839,11 @@ void lfmm_destroy(lfmm_plan_t* plan) {
   delete plan;
 }
 
+const char* lfmm_last_hip_error(void) {
+  std::lock_guard<std::mutex> g(g_hip_err_mu);
+  return g_hip_err[g_hip_err_cur];
+}
+
 const char* lfmm_status_string(int status) {
   switch (status) {
     case LFMM_OK: return "ok";
@@ -2595,7 +2880,8 @@ int lfmm_translation(lfmm_plan_t* plan, int kind, double kw, const double* b, do
     d[0] = OpDesc{b[0], b[1], b[2], kw, kind, 0};
     OpDesc* dd = plan->upload("dbg_op", d, nullptr);
     double* ops = plan->dev<double>("dbg_ops", plan->opsz);
-    lk_transop(1, dd, ops, plan->opsz, plan->p, plan->NC, plan->NKS, plan->d_gaunt, nullptr, nullptr, nullptr);
+    lk_transop(1, dd, ops, plan->opsz, ops, plan->opsz, plan->p, plan->NC, plan->NKS, plan->d_gaunt, nullptr, nullptr,
+               nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
     unpack_op(pk, plan->NC, plan->NKS, kind == 1, out);
@@ -3012,6 +3298,17 @@ int lfmm_mlp_forward_backward(int B, int nin, int width, int nhidden, int nout, 
   }
   N.release();
   return rc;
+}
+
+int lfmm_set_tiles(lfmm_plan_t* plan, int gemm_ks, int p2p_ta, int p2p_ch) {
+  if (!plan) return LFMM_EINVAL;
+  if (gemm_ks != 1 && gemm_ks != 2 && gemm_ks != 4) return LFMM_EINVAL;
+  if (p2p_ta != 4 && p2p_ta != 8 && p2p_ta != 16) return LFMM_EINVAL;
+  if (p2p_ch != 128 && p2p_ch != 256 && p2p_ch != 512) return LFMM_EINVAL;
+  plan->gemm_ks = gemm_ks;
+  plan->p2p_ta = p2p_ta;
+  plan->p2p_ch = p2p_ch;
+  return LFMM_OK;
 }
 
 int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t* layer, const double* q, double* phi,

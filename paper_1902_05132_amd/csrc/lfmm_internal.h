@@ -47,7 +47,7 @@ struct MlpGemm {
 struct OpDesc {
   double bx, by, bz, k;
   int kind;  // 0: regular (j_q), 1: singular (h_q)
-  int op;    // destination operator index
+  int op;    // destination index: in the shift array (kind 0) or the M2L array (kind 1)
 };
 
 // One geometry class of the reaction M2L integrals.
@@ -144,8 +144,11 @@ void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const 
                    const int* lvl_off, int* leafrow, hipStream_t s);
 void lk_gather(int ntp, const int* sg, const double* rec, double* px, double* py, double* pz, double* pq,
                hipStream_t s);
-void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS, const double* gaunt,
-                float* ops32, const int* opse, hipStream_t s);
+void lk_point_origin(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
+                     const int* sg, int* orig, hipStream_t s);
+void lk_gather_q(int ntp, const int* orig, const double* q, double* pq, hipStream_t s);
+void lk_transop(int nops, const OpDesc* descs, double* sops, int opsz, double* ops, int opsz_m, int p, int NC,
+                int NKS, const double* gaunt, float* ops32, const int* opse, hipStream_t s);
 // Ltab != nullptr (stacks with more than four interfaces): per-node layer tables,
 // 6 (L + 1) Ntot complex, from which k_react_F assembles the densities.
 void lk_react_tables(int nrg, const RGDesc* rgs, int Ntot, Stack st, int p, double* Jtab, double* Ptab,
@@ -185,6 +188,11 @@ void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box
                  const double* M, float* M32, hipStream_t s);
 // M2L GEMMs: blocks of 16 x (4 / ks) targets, ks waves splitting each tile's operator
 // sequence; srow_stride is the longest sequence
+// M2L GEMMs: allow every instance the CU's LDS (less its static LDS); the dynamic LDS
+// any instance may take; the LDS one launch needs for its operator lists
+void lk_m2l_gemm_init();
+size_t lk_m2l_lds_max();
+size_t lk_m2l_lds_bytes(int srow_stride, int ks);
 void lk_gemm32(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
                int srow_stride, const float* ops, int opsz, int NKS, const float* S, double* D, int NCK,
                const int* box_tree, const int* box_level, const int* se, hipStream_t s);

@@ -302,8 +302,8 @@ __global__ void k_tree_points(int ntp, int ntrees, const TreeInfo* trees, const 
   r[0] = fx;
   r[1] = fy;
   r[2] = fz;
-  r[3] = q[2 * i];
-  r[4] = q[2 * i + 1];
+  r[3] = q ? q[2 * i] : 0.0;  // no charges yet when only the geometry is prepared
+  r[4] = q ? q[2 * i + 1] : 0.0;
 }
 extern "C" void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
                                const double* x, const double* y, const double* z, const double* q, Stack st,
@@ -490,6 +490,32 @@ extern "C" void lk_gather(int ntp, const int* sg, const double* rec, double* px,
   if (ntp) k_gather<<<nblk(ntp, 256), 256, 0, s>>>(ntp, sg, rec, px, py, pz, pq);
 }
 
+// particle index of every tree point in tree order (the particle whose charge it carries)
+__global__ void k_point_origin(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
+                               const int* sg, int* orig) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp) return;
+  const int g = sg[s];
+  const TreeInfo& T = trees[tree_of(trees, ntrees, g)];
+  orig[s] = perm[layer_start[T.layer] + (g - T.pt_off)];
+}
+extern "C" void lk_point_origin(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
+                                const int* sg, int* orig, hipStream_t s) {
+  if (ntp) k_point_origin<<<nblk(ntp, 256), 256, 0, s>>>(ntp, ntrees, trees, perm, layer_start, sg, orig);
+}
+
+// tree-order charges from the particles' charges
+__global__ void k_gather_q(int ntp, const int* orig, const double* q, double* pq) {
+  int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= ntp) return;
+  const int i = orig[s];
+  pq[2 * s] = q[2 * i];
+  pq[2 * s + 1] = q[2 * i + 1];
+}
+extern "C" void lk_gather_q(int ntp, const int* orig, const double* q, double* pq, hipStream_t s) {
+  if (ntp) k_gather_q<<<nblk(ntp, 256), 256, 0, s>>>(ntp, orig, q, pq);
+}
+
 // ---------------------------------------------------------------------------
 // Operator layout for the MFMA GEMM: an (NRT*16) x (NKS*4) complex matrix is
 // stored as tiles of 16 rows x 4 columns; tile (rt, ks) holds 64 (re, im) pairs
@@ -543,8 +569,9 @@ __device__ __forceinline__ void m2l_packed_rc(int e, int NRT, int XR, int* row, 
 // With ops32 given, singular (M2L) operators are written in FP32 to ops32 instead,
 // scaled as Op[(n,m),(nu,mu)] 2^{-(e_t n + e_s nu)} with (e_t, e_s) = opse[op] (the
 // per-level expansion scale exponents of the FP32 path).
-__global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
-                                                 const double* gaunt, float* ops32, const int2* opse) {
+__global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* sops, int opsz, double* ops, int opsz_m,
+                                                 int p, int NC, int NKS, const double* gaunt, float* ops32,
+                                                 const int2* opse) {
   __shared__ cd zq[64];
   __shared__ cd Yq[(2 * LFMM_PMAX + 1) * (2 * LFMM_PMAX + 1)];  // idx(q, s), q <= 2p
   __shared__ int2 nmt[NM_TAB];
@@ -599,9 +626,11 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
     }
   }
   __syncthreads();
-  double* out = ops + (size_t)D.op * opsz;
+  // shift operators (regular) in their own array; M2L operators (singular) in the
+  // M2L array, FP32 when one is given
   const bool f32 = ops32 != nullptr && D.kind == 1;
-  float* out32 = f32 ? ops32 + (size_t)D.op * opsz : nullptr;
+  double* out = D.kind == 0 ? sops + (size_t)D.op * opsz : (f32 ? nullptr : ops + (size_t)D.op * opsz_m);
+  float* out32 = f32 ? ops32 + (size_t)D.op * opsz_m : nullptr;
   const int2 se = f32 ? opse[D.op] : make_int2(0, 0);
   int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   int P1 = p + 1;
@@ -640,9 +669,10 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* op
     }
   }
 }
-extern "C" void lk_transop(int nops, const OpDesc* descs, double* ops, int opsz, int p, int NC, int NKS,
-                           const double* gaunt, float* ops32, const int* opse, hipStream_t s) {
-  if (nops) k_transop<<<nops, 256, 0, s>>>(descs, ops, opsz, p, NC, NKS, gaunt, ops32, (const int2*)opse);
+extern "C" void lk_transop(int nops, const OpDesc* descs, double* sops, int opsz, double* ops, int opsz_m, int p,
+                           int NC, int NKS, const double* gaunt, float* ops32, const int* opse, hipStream_t s) {
+  if (nops)
+    k_transop<<<nops, 256, 0, s>>>(descs, sops, opsz, ops, opsz_m, p, NC, NKS, gaunt, ops32, (const int2*)opse);
 }
 
 // ---------------------------------------------------------------------------
@@ -1011,7 +1041,6 @@ template <int UPW, int CH>
 static void launch_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p,
                               int Ntot, const cd* J, const cd* P, const cd* F, double* Iout, int NC, size_t lds,
                               hipStream_t s) {
-  (void)hipFuncSetAttribute((const void*)k_react_mfma<UPW, CH>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   k_react_mfma<UPW, CH><<<nwg, 512, lds, s>>>(scs, nsc, members, cls, p, Ntot, J, P, F, Iout, NC);
 }
 extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p,
@@ -1048,7 +1077,7 @@ __global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const
   }
   __syncthreads();
   const double* I = Iall + (size_t)R.cls * NC * NC * 2;
-  double* out = ops + (size_t)R.op * opsz;
+  double* out = ops32 ? nullptr : ops + (size_t)R.op * opsz;
   float* out32 = ops32 ? ops32 + (size_t)R.op * opsz : nullptr;
   const int2 se = ops32 ? opse[R.op] : make_int2(0, 0);
   double pre = 4.0 * LFMM_PI / R.kt;
@@ -1794,6 +1823,42 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
                                                 dim, dxre, dxim, m2l_lists + 17 * lmax * wave, lmax);
   m2l_store<NRT, XR, KS>(bd, trow, D, NCK, NC, false, 0, nullptr, nullptr, nullptr, dre, dim, dxre, dxim);
 }
+// Every M2L GEMM instance may use the CU's 160 KB of LDS, less its static LDS, for its
+// operator lists (17 ints per listed operator and wave), and the reaction node sums
+// for their tables; set once per plan, outside any capture and any evaluation (so no
+// attribute call races another thread's launches).  The smallest allowance over the
+// M2L instances bounds an M2L launch.
+static size_t g_m2l_lds_max = 64 * 1024 - 16 * 1024;
+template <typename K>
+static size_t m2l_allow_lds(K* kern) {
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, (const void*)kern) != hipSuccess) return 64 * 1024 - 16 * 1024;
+  const size_t lim = 160 * 1024 - fa.sharedSizeBytes;
+  if (hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) != hipSuccess)
+    return 64 * 1024 - fa.sharedSizeBytes;
+  return lim;
+}
+extern "C" void lk_m2l_gemm_init() {
+  size_t lim = 160 * 1024;
+#define M2L_ATTR(N, X, K)                                          \
+  lim = std::min(lim, m2l_allow_lds(k_m2l_gemm32<N, X, K>));     \
+  lim = std::min(lim, m2l_allow_lds(k_m2l_gemm64<N, X, K>));
+#define M2L_ATTR_KS(N, X) M2L_ATTR(N, X, 1) M2L_ATTR(N, X, 2) M2L_ATTR(N, X, 4)
+  M2L_ATTR_KS(1, 0) M2L_ATTR_KS(2, 0) M2L_ATTR_KS(3, 1) M2L_ATTR_KS(3, 0) M2L_ATTR_KS(4, 0) M2L_ATTR_KS(5, 1)
+  M2L_ATTR_KS(7, 0) M2L_ATTR_KS(8, 0)
+#undef M2L_ATTR_KS
+#undef M2L_ATTR
+  g_m2l_lds_max = lim;
+  // the reaction node sums' LDS (32 or 16 classes' tables per workgroup)
+  (void)m2l_allow_lds(k_react_mfma<SC_UPW, 32>);
+  (void)m2l_allow_lds(k_react_mfma<SC_UPW, 16>);
+  (void)hipGetLastError();  // a refused attribute leaves no error behind: its smaller limit is kept
+}
+extern "C" size_t lk_m2l_lds_max() { return g_m2l_lds_max; }
+extern "C" size_t lk_m2l_lds_bytes(int srow_stride, int ks) {
+  return sizeof(int) * 17 * (size_t)((srow_stride + ks - 1) / ks) * 4;
+}
+
 extern "C" void lk_gemm32(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
                           const int* srow, int srow_stride, const float* ops, int opsz, int NKS, const float* S,
                           double* D, int NCK, const int* box_tree, const int* box_level, const int* se,

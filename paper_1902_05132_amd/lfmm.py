@@ -20,8 +20,9 @@ LFMM_ENOCONV = 6
 
 
 class LfmmError(RuntimeError):
-    def __init__(self, code, what):
-        super().__init__("%s failed: %s (status %d)" % (what, _STATUS.get(code, "?"), code))
+    def __init__(self, code, what, detail=""):
+        super().__init__("%s failed: %s (status %d)%s" % (what, _STATUS.get(code, "?"), code,
+                                                           ": " + detail if detail else ""))
         self.code = code
 
 
@@ -43,6 +44,11 @@ class Report(ctypes.Structure):
                 ("n_react_table", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("p2m_points", ctypes.c_int64), ("p2m_leaves", ctypes.c_int64),
                 ("l2p_points", ctypes.c_int64), ("l2p_leaves", ctypes.c_int64)]
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("n_total", ctypes.c_int64), ("graph_nodes", ctypes.c_int64), ("branches", ctypes.c_int),
+                ("capture_ms", ctypes.c_double)]
 
 
 class TuneReport(ctypes.Structure):
@@ -107,6 +113,16 @@ def load():
     L.lfmm_eval_batch.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                   ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.lfmm_prepare.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+    L.lfmm_apply.argtypes = [vp, vp, vp, vp]
+    L.lfmm_batch_prepare.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
+                                     ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.lfmm_batch_capture.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(BatchReport)]
+    L.lfmm_set_tiles.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.lfmm_batch_launch.argtypes = [vp, vp]
+    L.lfmm_batch_destroy.argtypes = [vp]
+    L.lfmm_batch_destroy.restype = None
     L.lfmm_last_report.argtypes = [vp, ctypes.POINTER(Report)]
     L.lfmm_stage_name.argtypes = [ctypes.c_int]
     L.lfmm_stage_name.restype = ctypes.c_char_p
@@ -114,6 +130,8 @@ def load():
     L.lfmm_destroy.restype = None
     L.lfmm_status_string.argtypes = [ctypes.c_int]
     L.lfmm_status_string.restype = ctypes.c_char_p
+    L.lfmm_last_hip_error.argtypes = []
+    L.lfmm_last_hip_error.restype = ctypes.c_char_p
     L.lfmm_quad_nodes.argtypes = [ctypes.c_int, _D, _D, ctypes.c_int, ctypes.POINTER(Options), ctypes.c_double,
                                   ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
     L.lfmm_translation.argtypes = [vp, ctypes.c_int, ctypes.c_double, _D, _D]
@@ -142,7 +160,10 @@ def load():
 
 def _check(rc, what):
     if rc != LFMM_OK:
-        raise LfmmError(rc, what)
+        detail = ""
+        if rc == 3 and _lib is not None:
+            detail = (_lib.lfmm_last_hip_error() or b"").decode(errors="replace")
+        raise LfmmError(rc, what, detail)
 
 
 def _f64(a):
@@ -238,7 +259,36 @@ class Plan:
         s = stream if stream is not None else torch.cuda.current_stream()
         _check(self.lib.lfmm_eval_device(self.h, n, xp, lp, qp, fp, ctypes.c_void_p(s.cuda_stream)),
                "lfmm_eval_device")
+        self._prep_n = n
         return phi
+
+    def prepare(self, xyz, layer=None, stream=None):
+        """lfmm_prepare: trees, lists and operators for these positions (no charges)."""
+        import torch
+        n, xp = _xyz_arg(xyz, "xyz")
+        lp = _dev_arg(layer, "layer", torch.int32, n, xyz.device) if layer is not None else None
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._prep_n = None
+        _check(self.lib.lfmm_prepare(self.h, n, xp, lp, ctypes.c_void_p(s.cuda_stream)), "lfmm_prepare")
+        self._prep_n = n
+        return self
+
+    def apply(self, q, phi, stream=None):
+        """lfmm_apply: Phi for charges q (complex128 (n,)) at the prepared positions into
+        phi; queued on the stream, no synchronisation (capturable into a graph)."""
+        import torch
+        n = getattr(self, "_prep_n", None)
+        if n is None:
+            raise LfmmError(1, "lfmm_apply: the plan has no prepared positions")
+        qp = _dev_arg(q, "q", torch.complex128, n)
+        fp = _dev_arg(phi, "phi", torch.complex128, n, q.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(self.lib.lfmm_apply(self.h, qp, fp, ctypes.c_void_p(s.cuda_stream)), "lfmm_apply")
+        return phi
+
+    def set_tiles(self, gemm_ks, p2p_ta, p2p_ch):
+        """lfmm_set_tiles: tile shapes for later evaluations and preparations."""
+        _check(self.lib.lfmm_set_tiles(self.h, int(gemm_ks), int(p2p_ta), int(p2p_ch)), "lfmm_set_tiles")
 
     def eval_device_noalloc(self, xyz, q, phi, layer=None, stream=None):
         """lfmm_eval_device_noalloc: as eval_device, with the workspace taken from the
@@ -462,6 +512,82 @@ def eval_batch(plans, xyzs, qs, phis, layers=None, nworkers=8):
     rc = L.lfmm_eval_batch(m, P, N, X, Ly, Q, F, int(nworkers), st)
     _check(rc, "lfmm_eval_batch")
     return list(st)
+
+
+def batch_prepare(plans, xyzs, layers=None, nworkers=8):
+    """lfmm_batch_prepare: lfmm_prepare of every problem (plans[i] with xyzs[i], float64
+    (3, n_i) on the GPU) on host worker threads.  Returns the per-problem codes; raises
+    on failure."""
+    import torch
+    m = len(plans)
+    if len(xyzs) != m or (layers is not None and len(layers) != m):
+        raise LfmmError(1, "batch_prepare: one plan and xyz (and layer) per problem")
+    ns, xp, lp = [], [], []
+    for i in range(m):
+        n, p = _xyz_arg(xyzs[i], "xyzs[%d]" % i)
+        ns.append(n)
+        xp.append(p)
+        if layers is not None:
+            lp.append(_dev_arg(layers[i], "layers[%d]" % i, torch.int32, n, xyzs[i].device))
+    L = load()
+    vp = ctypes.c_void_p
+    P = (vp * m)(*[pl.h.value for pl in plans])
+    st = (ctypes.c_int * m)()
+    for pl in plans:
+        pl._prep_n = None
+    rc = L.lfmm_batch_prepare(m, P, (ctypes.c_int64 * m)(*ns), (vp * m)(*xp),
+                              (vp * m)(*lp) if layers is not None else None, int(nworkers), st)
+    _check(rc, "lfmm_batch_prepare")
+    for pl, n in zip(plans, ns):
+        pl._prep_n = n
+    return list(st)
+
+
+class Batch:
+    """lfmm_batch_capture: the prepared problems' lfmm_apply captured into one HIP graph;
+    launch() runs it.  The graph reads qs[i] and writes phis[i] (complex128 on the GPU)
+    each time it runs; plans and tensors are kept referenced for the batch's lifetime."""
+
+    def __init__(self, plans, qs, phis, nbranch=4):
+        import torch
+        m = len(plans)
+        if not (len(qs) == len(phis) == m):
+            raise LfmmError(1, "Batch: one plan, q and phi per problem")
+        qp, fp = [], []
+        for i in range(m):
+            n = getattr(plans[i], "_prep_n", None)
+            if n is None:
+                raise LfmmError(1, "Batch: plan %d has no prepared positions" % i)
+            qp.append(_dev_arg(qs[i], "qs[%d]" % i, torch.complex128, n))
+            fp.append(_dev_arg(phis[i], "phis[%d]" % i, torch.complex128, n, qs[i].device))
+        self.lib = load()
+        vp = ctypes.c_void_p
+        self.rep = BatchReport()
+        h = vp()
+        self._keep = (list(plans), list(qs), list(phis))
+        rc = self.lib.lfmm_batch_capture(m, (vp * m)(*[pl.h.value for pl in plans]), (vp * m)(*qp), (vp * m)(*fp),
+                                         int(nbranch), ctypes.byref(h), ctypes.byref(self.rep))
+        _check(rc, "lfmm_batch_capture")
+        self.h = h
+
+    def report(self):
+        return {f: getattr(self.rep, f) for f, _ in BatchReport._fields_}
+
+    def launch(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(self.lib.lfmm_batch_launch(self.h, ctypes.c_void_p(s.cuda_stream)), "lfmm_batch_launch")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.lfmm_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mlp_forward_backward(x, params, t, nin, width, nhidden, nout):

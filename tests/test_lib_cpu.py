@@ -47,7 +47,8 @@ def test_binding_structs_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     structs = {"lfmm_options": lfmm.Options, "lfmm_report": lfmm.Report, "lfmm_tune_report": lfmm.TuneReport,
                "lfmm_train_opts": lfmm.TrainOpts, "lfmm_train_report": lfmm.TrainReport,
-               "lfmm_table_opts": lfmm.TableOpts, "lfmm_table_report": lfmm.TableReport}
+               "lfmm_table_opts": lfmm.TableOpts, "lfmm_table_report": lfmm.TableReport,
+               "lfmm_batch_report": lfmm.BatchReport}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lfmm.h"', "int main(void) {"]
     for cname, cls in structs.items():
         lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
@@ -95,6 +96,14 @@ def test_device_entry_points_reject_bad_tensors():
         lfmm.eval_batch([P], [xyz], [q], [phi])
     with pytest.raises(lfmm.LfmmError):
         lfmm.eval_batch([P, P], [xyz], [q], [phi])
+    with pytest.raises(lfmm.LfmmError):
+        P.prepare(xyz)
+    with pytest.raises(lfmm.LfmmError):
+        P.apply(q, phi)  # no prepared positions
+    with pytest.raises(lfmm.LfmmError):
+        lfmm.batch_prepare([P], [xyz])
+    with pytest.raises(lfmm.LfmmError):
+        lfmm.Batch([P], [q], [phi])  # no prepared positions
 
 
 def test_argument_checks_on_tensor_properties(monkeypatch):
