@@ -374,6 +374,48 @@ def batch_leg(args, lfmm, W, torch, dev, stream):
     return res
 
 
+def config5_leg(args, lfmm, W, torch, dev, stream):
+    """Clustered inputs at full size (config 5): 16,777,216 particles in Gaussian
+    clusters over the five-layer medium, p = 10, leaf <= 64 (uniform trees at their
+    depth cap of 8), both precisions, the mixed path's error against the FP64 path."""
+    w = W.five_layer_clusters(n=args.config5_n)
+    n = len(w["x"])
+    xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+    q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+    res = {"workload": w["name"]}
+    ref = None
+    steps = max(1, min(args.steps, 3))
+    for precision in (0, 1):
+        plan = lfmm.Plan(w["d"], w["k"], p=10, leaf_max=64, precision=precision,
+                         quad_tol=args.mixed_quad_tol if precision else 0.0)
+        phi = torch.empty_like(q)
+        plan.eval_device(xyz, q, phi, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            plan.eval_device(xyz, q, phi, stream=stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / steps
+        rep = plan.report()
+        plan.close()
+        name = "fp64" if precision == 0 else "mixed"
+        res[name] = {"ms_per_step": ms, "value": n / (ms / 1000.0), "free_depth": rep["free_depth"],
+                     "reaction_depth": rep["reaction_depth"], "boxes": rep["n_boxes"],
+                     "m2l_pairs": rep["m2l_pairs"], "p2p_pairs": rep["p2p_pairs"],
+                     "react_classes": rep["n_react_classes"], "workspace_bytes": rep["workspace_bytes"]}
+        if ref is None:
+            ref = phi
+        else:
+            d = phi - ref
+            res[name]["err2_vs_fp64"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(ref))
+            res[name]["errmax_vs_fp64"] = float(d.abs().max() / ref.abs().max())
+        log("bench: config 5 %s: %.1f ms/step, %.3e evals/s, depths %s/%d, %d boxes, workspace %.1f GB%s"
+            % (name, ms, n / (ms / 1000.0), rep["free_depth"], rep["reaction_depth"], rep["n_boxes"],
+               rep["workspace_bytes"] / 1e9,
+               (", Err2 vs FP64 %.2e" % res[name]["err2_vs_fp64"]) if precision else ""))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,6 +429,9 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--no-tables", action="store_true", help="skip the pre-computed-tables leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batch leg")
+    ap.add_argument("--config5", action="store_true",
+                    help="also time the clustered five-layer workload at full size (about 80 GB of device memory)")
+    ap.add_argument("--config5-n", type=int, default=16777216, help="particles of the --config5 leg")
     # the mixed path's contour ends where the integrands' envelope has fallen to 1e-10
     # (its error, about 5e-13, is four orders below the FP32 parts' 1.75e-7); the FP64
     # path keeps the library default e^-40
@@ -550,6 +595,8 @@ def main():
         out["batch"] = batch_leg(args, lfmm, W, torch, dev, stream)
     if args.ten_interface:
         out["ten_interface"] = ten_interface_leg(args, lfmm, W, torch, dev, stream)
+    if args.config5:
+        out["config5"] = config5_leg(args, lfmm, W, torch, dev, stream)
     if args.scaling:
         rows = []
         for n2 in (1 << 17, 1 << 18, 1 << 19, 1 << 20, 1 << 21):

@@ -138,3 +138,58 @@ def test_full_size_layer_against_closed_form_32_targets():
     assert e8 < 1e-4, e8
     assert e10 < 0.5 * e8, (e10, e8)
     assert emix < 1e-6, emix
+
+
+def test_config5_full_size():
+    """Config 5 at full size: 16,777,216 particles in Gaussian clusters (8 per layer,
+    sigma 0.05) over the five-layer medium, p = 10, leaf <= 64.  The trees reach the
+    depth cap of 8, where the cluster cores still hold a few hundred particles per
+    leaf.  The whole layered evaluation in both precisions: finite, and the mixed path
+    within 1e-6 of the FP64 path over every particle.  The free-space part of the top
+    layer (its particles as a homogeneous medium, k = 0.5, the same depth-8 tree) at 32
+    seeded targets against the closed-form direct sum: the order-10 truncation."""
+    import torch
+    from paper_1902_05132_amd import lfmm
+
+    w = W.five_layer_clusters()
+    dev = torch.device("cuda:0")
+    xyz = torch.tensor(np.stack([w["x"], w["y"], w["z"]]), dtype=torch.float64, device=dev).contiguous()
+    q = torch.tensor(w["q"], dtype=torch.complex128, device=dev)
+    res = {}
+    for prec in (0, 1):
+        P = lfmm.Plan(w["d"], w["k"], p=10, leaf_max=64, precision=prec, quad_tol=1e-10 if prec else 0.0)
+        phi = torch.empty_like(q)
+        P.eval_device(xyz, q, phi)
+        torch.cuda.synchronize()
+        rep = P.report()
+        assert rep["free_depth"] == [8, 8, 8, 8, 8] and rep["reaction_depth"] == 8, rep["free_depth"]
+        res[prec] = phi
+        P.close()
+    assert bool(torch.isfinite(torch.view_as_real(res[0])).all())
+    d = res[1] - res[0]
+    e2 = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(res[0]))
+    emax = float(d.abs().max() / res[0].abs().max())
+    del d
+    print("config 5 full size: mixed vs FP64 Err2 %.2e, Errmax %.2e" % (e2, emax))
+    assert e2 < 1e-6 and emax < 1e-6, (e2, emax)
+    del res, xyz, q
+    torch.cuda.empty_cache()
+    sel = w["layer"] == 0
+    x, y, z, qq = w["x"][sel], w["y"][sel], w["z"][sel], w["q"][sel]
+    k = float(w["k"][0])
+    xyz = torch.tensor(np.stack([x, y, z]), dtype=torch.float64, device=dev).contiguous()
+    qt = torch.tensor(qq, dtype=torch.complex128, device=dev)
+    P = lfmm.Plan((), (k,), p=10, leaf_max=64)
+    phi = torch.empty_like(qt)
+    P.eval_device(xyz, qt, phi)
+    torch.cuda.synchronize()
+    assert P.report()["free_depth"][0] == 8
+    rng = np.random.default_rng(321)
+    tg = np.sort(rng.choice(len(x), 32, replace=False))
+    ex = O.direct((), (k,), x, y, z, np.zeros(len(x), np.int32), qq, tg)
+    got = phi.cpu().numpy()[tg]
+    e = np.linalg.norm(got - ex) / np.linalg.norm(ex)
+    print("config 5 full size, top layer's free part at 32 targets: Err2 %.2e, max rel %.2e"
+          % (e, np.max(np.abs(got - ex) / np.abs(ex))))
+    assert e < 1e-5, e
+    P.close()

@@ -417,6 +417,23 @@ def test_five_layer_clustered():
     assert rep["reaction_depth"] >= 5
 
 
+def test_five_layer_clusters_p10():
+    """Config 5's recipe at N = 24,000 (seed 11), p = 10, leaf <= 64: clusters 0.05 from
+    the interfaces (reaction trees six levels deep), every reaction component of the
+    five layers, the order-10 kernels.  FP64 against the oracle's FMM at 1e-10 (depths
+    equal); the mixed path within 1e-6 of the FP64 path."""
+    lf = _lfmm()
+    w = W.five_layer_clusters(n=24000, seed=11, p=10, leaf=64)
+    phi, ref, rep = _check_fmm(w, p=10, leaf=64)
+    assert rep["reaction_depth"] >= 6
+    pm = lf.Plan(w["d"], w["k"], p=10, leaf_max=64, precision=1, quad_tol=1e-10).eval_torch(
+        w["x"], w["y"], w["z"], w["q"])
+    e2 = np.linalg.norm(pm - phi) / np.linalg.norm(phi)
+    emax = np.max(np.abs(pm - phi)) / np.max(np.abs(phi))
+    print("five-layer clusters, p = 10: mixed vs FP64 Err2 %.2e, Errmax %.2e" % (e2, emax))
+    assert e2 < 1e-6 and emax < 1e-6, (e2, emax)
+
+
 def test_physical_normalisation():
     lf = _lfmm()
     # one homogeneous layer, two particles: the physical potential is the closed form
