@@ -27,12 +27,13 @@ METRIC = "potential evals/sec at N=1M, rel-err≤1e-6 vs FP64; surrogate/FP32 vs
 # MI355X peaks (TFLOP/s): dense MFMA FP64 78.6, FP32 157.3; vector ALU 256 CU x 4 SIMD x 16 lanes x
 # 2 (fma) x 2.4 GHz = 78.6 (FP64), twice that for FP32
 PEAK = {("mfma", 64): 78.6, ("mfma", 32): 157.3, ("alu", 64): 78.6, ("alu", 32): 157.3}
-# operations of one near-field pair in the series form of h0 (k r <= 1).  FP64: 3 differences, r^2 (5),
-# reciprocal square root with two Newton steps (10), -(kr)^2 (1), sin(x)/x and cos(x) series (9 + 10 fma),
-# -cos(kr)/(kr) (2), complex multiply-add (8) = 67.  FP32: hi/lo differences (9), r^2 (5), rsqrt (1),
-# -(kr)^2 (1), series (6 + 6 fma), -cos(kr)/(kr) (2), complex multiply-add (8) = 50.
-P2P_FLOPS_PER_PAIR = {64: 67, 32: 50}  # series forms for k r <= 1
-P2P_SHORT_FLOPS_PER_PAIR = {64: 55, 32: 42}  # the shorter series for k r <= 1/2
+# operations of one near-field pair in the series form of h0 (k r <= 1), coordinates in units of 1/k.
+# FP64: 3 differences, (kr)^2 (5), reciprocal square root with two Newton steps (10), sin(x)/x and
+# cos(x) series (9 + 10 fma), -cos(kr)/(kr) (1), complex multiply-add (8) = 65.  FP32: hi/lo
+# differences (9), (kr)^2 (5), rsqrt (1), series (6 + 6 fma), -cos(kr)/(kr) (1), complex
+# multiply-add (8) = 48.
+P2P_FLOPS_PER_PAIR = {64: 65, 32: 48}  # series forms for k r <= 1
+P2P_SHORT_FLOPS_PER_PAIR = {64: 53, 32: 40}  # the shorter series for k r <= 1/2 (6 + 7 and 4 + 4 fma)
 # what one near-field pair needs by the method's own count: differences, r^2, k r, the complex
 # multiply-add (about 20 flops) and sqrt, reciprocal, sin, cos (one operation each)
 P2P_ALG_OPS_PER_PAIR = 24

@@ -2310,54 +2310,51 @@ __device__ __forceinline__ double rsqrt_nr(double r2) {
   y = y * fma(-hh, y * y, 1.5);
   return y;
 }
-// h0(k r) for r^2 = r2 > 0 (hr + i hi); k2 = k^2, invk = 1/k.  FORM 1: series of
-// sin(x)/x (10 terms) and cos(x) (11 terms) for x = k r <= 1; FORM 2: 7 and 8 terms
-// for x <= 1/2 (the first dropped terms, x^14/15! and x^16/16!, are below 4.9e-17 and
-// 8.3e-19 relative); FORM 0: sincos.
+// h0(x) = sin(x)/x - i cos(x)/x for x = k r, from u = x^2 > 0 and y = 1/x (hr + i hi).
+// FORM 1: series of sin(x)/x (10 terms) and cos(x) (11 terms) for x <= 1; FORM 2: 7 and
+// 8 terms for x <= 1/2 (the first dropped terms, x^14/15! and x^16/16!, are below 4.9e-17
+// and 8.3e-19 relative); FORM 0: sincos.  The series' signs are in their coefficients.
 template <int FORM>
-__device__ __forceinline__ void h0_pair(double r2, double k, double k2, double invk, double& hr, double& hi) {
-  double y = rsqrt_nr(r2);
+__device__ __forceinline__ void h0_pair(double u, double y, double& hr, double& hi) {
   if constexpr (FORM > 0) {
-    constexpr double s1 = inv_fact(3), s2 = inv_fact(5), s3 = inv_fact(7), s4 = inv_fact(9), s5 = inv_fact(11),
-                     s6 = inv_fact(13), s7 = inv_fact(15), s8 = inv_fact(17), s9 = inv_fact(19);
-    constexpr double c1 = inv_fact(2), c2 = inv_fact(4), c3 = inv_fact(6), c4 = inv_fact(8), c5 = inv_fact(10),
-                     c6 = inv_fact(12), c7 = inv_fact(14), c8 = inv_fact(16), c9 = inv_fact(18), c10 = inv_fact(20);
+    constexpr double s1 = -inv_fact(3), s2 = inv_fact(5), s3 = -inv_fact(7), s4 = inv_fact(9), s5 = -inv_fact(11),
+                     s6 = inv_fact(13), s7 = -inv_fact(15), s8 = inv_fact(17), s9 = -inv_fact(19);
+    constexpr double c1 = -inv_fact(2), c2 = inv_fact(4), c3 = -inv_fact(6), c4 = inv_fact(8), c5 = -inv_fact(10),
+                     c6 = inv_fact(12), c7 = -inv_fact(14), c8 = inv_fact(16), c9 = -inv_fact(18),
+                     c10 = inv_fact(20);
     static_assert(FORM == 1 || FORM == 2, "series forms 1 and 2");
-    double v = -k2 * r2;  // -(kr)^2
     double ps, pc;
     if constexpr (FORM == 1) {
-      ps = fma(s9, v, s8);
-      ps = fma(ps, v, s7);
-      ps = fma(ps, v, s6);
-      pc = fma(c10, v, c9);
-      pc = fma(pc, v, c8);
-      pc = fma(pc, v, c7);
+      ps = fma(s9, u, s8);
+      ps = fma(ps, u, s7);
+      ps = fma(ps, u, s6);
+      pc = fma(c10, u, c9);
+      pc = fma(pc, u, c8);
+      pc = fma(pc, u, c7);
     } else {
       ps = s6;
       pc = c7;
     }
-    ps = fma(ps, v, s5);
-    ps = fma(ps, v, s4);
-    ps = fma(ps, v, s3);
-    ps = fma(ps, v, s2);
-    ps = fma(ps, v, s1);
-    ps = fma(ps, v, 1.0);
-    pc = fma(pc, v, c6);
-    pc = fma(pc, v, c5);
-    pc = fma(pc, v, c4);
-    pc = fma(pc, v, c3);
-    pc = fma(pc, v, c2);
-    pc = fma(pc, v, c1);
-    pc = fma(pc, v, 1.0);
-    hr = ps;                // sin(kr)/(kr)
-    hi = -pc * (y * invk);  // -cos(kr)/(kr)
+    ps = fma(ps, u, s5);
+    ps = fma(ps, u, s4);
+    ps = fma(ps, u, s3);
+    ps = fma(ps, u, s2);
+    ps = fma(ps, u, s1);
+    ps = fma(ps, u, 1.0);
+    pc = fma(pc, u, c6);
+    pc = fma(pc, u, c5);
+    pc = fma(pc, u, c4);
+    pc = fma(pc, u, c3);
+    pc = fma(pc, u, c2);
+    pc = fma(pc, u, c1);
+    pc = fma(pc, u, 1.0);
+    hr = ps;       // sin(x)/x
+    hi = -pc * y;  // -cos(x)/x
   } else {
-    double kr = k * (r2 * y);
     double sn, cs;
-    sincos(kr, &sn, &cs);
-    double ikr = y * invk;
-    hr = sn * ikr;
-    hi = -cs * ikr;
+    sincos(u * y, &sn, &cs);
+    hr = sn * y;
+    hi = -cs * y;
   }
 }
 #define P2P_TMAX 256
@@ -2369,7 +2366,9 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
                                                   const double* py, const double* pz, const double* pq, const int* sg,
                                                   double* phi_tp, unsigned long long* npairs) {
   constexpr int TB = 64 / TA;
-  __shared__ double s_x[CH], s_y[CH], s_z[CH], s_qr[CH], s_qi[CH];
+  // one record per source (k x, k y, k z, Re q, Im q): the five reads of a pair share
+  // one address register, their offsets folded into the instructions
+  __shared__ double s_src[5 * CH];
   __shared__ double t_x[P2P_TMAX], t_y[P2P_TMAX], t_z[P2P_TMAX], acc_r[P2P_TMAX], acc_i[P2P_TMAX];
   __shared__ int nb_start[27], nb_pre[28];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -2396,14 +2395,13 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
   }
   __syncthreads();
   const int total = nb_pre[27];
-  const double k2 = k * k, invk = 1.0 / k;
   for (int c0 = 0; c0 < nt; c0 += P2P_TMAX) {
     const int ntp = nt - c0 < P2P_TMAX ? nt - c0 : P2P_TMAX;
     const int ntb = (ntp + TA - 1) / TA;
-    if (tid < ntp) {
-      t_x[tid] = px[s0 + c0 + tid];
-      t_y[tid] = py[s0 + c0 + tid];
-      t_z[tid] = pz[s0 + c0 + tid];
+    if (tid < ntp) {  // coordinates in units of 1/k: r^2 is then (k r)^2
+      t_x[tid] = k * px[s0 + c0 + tid];
+      t_y[tid] = k * py[s0 + c0 + tid];
+      t_z[tid] = k * pz[s0 + c0 + tid];
       acc_r[tid] = 0.0;
       acc_i[tid] = 0.0;
     }
@@ -2419,11 +2417,12 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
           else hi = mid - 1;
         }
         int ss = nb_start[lo] + (g - nb_pre[lo]);
-        s_x[f] = px[ss];
-        s_y[f] = py[ss];
-        s_z[f] = pz[ss];
-        s_qr[f] = pq[2 * ss];
-        s_qi[f] = pq[2 * ss + 1];
+        double* rec = s_src + 5 * f;
+        rec[0] = k * px[ss];
+        rec[1] = k * py[ss];
+        rec[2] = k * pz[ss];
+        rec[3] = pq[2 * ss];
+        rec[4] = pq[2 * ss + 1];
       }
       __syncthreads();
       for (int tb = wave; tb < ntb; tb += 4) {
@@ -2434,14 +2433,16 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
         double ax = 0.0, ay = 0.0;
 #pragma unroll 2
         for (int j = b; j < nch; j += TB) {
-          double dx = x0 - s_x[j], dy = y0 - s_y[j], dz = z0 - s_z[j];
-          double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-          bool ok = r2 > 0.0;  // the target itself (and coincident points) contribute nothing
+          const double* rec = s_src + 5 * j;
+          double dx = x0 - rec[0], dy = y0 - rec[1], dz = z0 - rec[2];
+          double u = fma(dx, dx, fma(dy, dy, dz * dz));  // (k r)^2
+          bool ok = u > 0.0;  // the target itself (and coincident points) contribute nothing
+          const double us = ok ? u : 1.0;  // (a select of the input keeps the loop free of branches)
           double hr, hi;
-          h0_pair<FORM>(ok ? r2 : 1.0, k, k2, invk, hr, hi);
+          h0_pair<FORM>(us, rsqrt_nr(us), hr, hi);  // 1 / (k r) from the refined rsq
           hr = ok ? hr : 0.0;
           hi = ok ? hi : 0.0;
-          double qr = s_qr[j], qi = s_qi[j];
+          double qr = rec[3], qi = rec[4];
           ax = fma(qr, hr, fma(-qi, hi, ax));
           ay = fma(qr, hi, fma(qi, hr, ay));
         }
@@ -2466,14 +2467,16 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
   }
 }
 // FP32 variant of the near field (mixed precision).  Coordinates relative to the
-// target leaf's first particle are formed in FP64 and kept as FP32 hi + lo pairs,
-// so a pair difference (hi - hi) + (lo - lo) is accurate to FP32 rounding of the
-// difference itself, also for the closest pairs; pairs are evaluated and
-// partially summed in FP32, and each target's sum is accumulated in FP64.  NS: the
-// number of terms of the series of sin(x)/x and cos(x), x = k r (v_rsq_f32 for 1/r):
-// 7 where x <= 1 on every pair (truncation below 1e-11), 5 where x <= 1/2 (the next
-// terms, x^10/11! and x^10/10!, are below 2.5e-11 and 2.7e-10, 3.1e-10 of cos x);
-// 0 takes sincosf.
+// target leaf's first particle, scaled by k, are formed in FP64 and kept as FP32 hi + lo
+// pairs, so a pair difference (hi - hi) + (lo - lo) is accurate to FP32 rounding of the
+// difference itself, also for the closest pairs; pairs are evaluated and partially
+// summed in FP32, and each target's sum is accumulated in FP64.  With coordinates in
+// units of 1/k, r2 is (k r)^2 and the reciprocal square root gives 1/(k r) directly.
+// A source is one 32-byte LDS record (x, y, z, xl | yl, zl, Re q, Im q): two 16-byte
+// reads at offsets the compiler folds into the instruction.  NS: the number of terms of
+// the series of sin(x)/x and cos(x), x = k r (v_rsq_f32 for 1/x): 7 where x <= 1 on
+// every pair (truncation below 1e-11), 5 where x <= 1/2 (the next terms, x^10/11! and
+// x^10/10!, are below 2.5e-11 and 2.7e-10, 3.1e-10 of cos x); 0 takes sincosf.
 template <int NS, int TA, int CH>
 __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row0, const int* seg_prefix,
                                                     const int* box_start, const int* box_cnt, const int* box_code,
@@ -2482,7 +2485,7 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
                                                     const double* py, const double* pz, const double* pq,
                                                     const int* sg, double* phi_tp, unsigned long long* npairs) {
   constexpr int TB = 64 / TA;
-  __shared__ float s_x[CH], s_y[CH], s_z[CH], s_xl[CH], s_yl[CH], s_zl[CH], s_qr[CH], s_qi[CH];
+  __shared__ float4 s_src[2 * CH];  // per source: (x, y, z, xl), (yl, zl, qr, qi)
   __shared__ float t_x[P2P_TMAX], t_y[P2P_TMAX], t_z[P2P_TMAX], t_xl[P2P_TMAX], t_yl[P2P_TMAX], t_zl[P2P_TMAX];
   __shared__ double acc_r[P2P_TMAX], acc_i[P2P_TMAX];
   __shared__ int nb_start[27], nb_pre[28];
@@ -2512,12 +2515,11 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
   if (nt == 0) return;
   const int total = nb_pre[27];
   const double xr = px[s0], yr = py[s0], zr = pz[s0];
-  const float kf = (float)k, k2 = (float)(k * k), invk = (float)(1.0 / k);
   for (int c0 = 0; c0 < nt; c0 += P2P_TMAX) {
     const int ntp = nt - c0 < P2P_TMAX ? nt - c0 : P2P_TMAX;
     const int ntb = (ntp + TA - 1) / TA;
     if (tid < ntp) {
-      double ux = px[s0 + c0 + tid] - xr, uy = py[s0 + c0 + tid] - yr, uz = pz[s0 + c0 + tid] - zr;
+      double ux = k * (px[s0 + c0 + tid] - xr), uy = k * (py[s0 + c0 + tid] - yr), uz = k * (pz[s0 + c0 + tid] - zr);
       t_x[tid] = (float)ux;
       t_y[tid] = (float)uy;
       t_z[tid] = (float)uz;
@@ -2539,16 +2541,11 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
           else hi = mid - 1;
         }
         int ss = nb_start[lo] + (g - nb_pre[lo]);
-        double ux = px[ss] - xr, uy = py[ss] - yr, uz = pz[ss] - zr;
+        double ux = k * (px[ss] - xr), uy = k * (py[ss] - yr), uz = k * (pz[ss] - zr);
         float hx = (float)ux, hy = (float)uy, hz = (float)uz;
-        s_x[f] = hx;
-        s_y[f] = hy;
-        s_z[f] = hz;
-        s_xl[f] = (float)(ux - (double)hx);
-        s_yl[f] = (float)(uy - (double)hy);
-        s_zl[f] = (float)(uz - (double)hz);
-        s_qr[f] = (float)pq[2 * ss];
-        s_qi[f] = (float)pq[2 * ss + 1];
+        s_src[2 * f] = make_float4(hx, hy, hz, (float)(ux - (double)hx));
+        s_src[2 * f + 1] = make_float4((float)(uy - (double)hy), (float)(uz - (double)hz), (float)pq[2 * ss],
+                                       (float)pq[2 * ss + 1]);
       }
       __syncthreads();
       for (int tb = wave; tb < ntb; tb += 4) {
@@ -2557,53 +2554,49 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
         const int tr = tv ? ti : 0;
         const float x0 = t_x[tr], y0 = t_y[tr], z0 = t_z[tr], x0l = t_xl[tr], y0l = t_yl[tr], z0l = t_zl[tr];
         float ax = 0.f, ay = 0.f;
-#pragma unroll 2
+#pragma unroll 4
         for (int j = b; j < nch; j += TB) {
-          float dx = (x0 - s_x[j]) + (x0l - s_xl[j]), dy = (y0 - s_y[j]) + (y0l - s_yl[j]),
-                dz = (z0 - s_z[j]) + (z0l - s_zl[j]);
-          float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-          bool ok = r2 > 0.f;
-          float r2s = ok ? r2 : 1.f;
-          float y = __builtin_amdgcn_rsqf(r2s);
+          const float4 A = s_src[2 * j], B = s_src[2 * j + 1];
+          float dx = (x0 - A.x) + (x0l - A.w), dy = (y0 - A.y) + (y0l - B.x), dz = (z0 - A.z) + (z0l - B.y);
+          float u = fmaf(dx, dx, fmaf(dy, dy, dz * dz));  // (k r)^2
+          const bool ok = u > 0.f;                        // coincident points contribute nothing
+          const float y = ok ? __builtin_amdgcn_rsqf(u) : 0.f;  // 1 / (k r)
           float hr, hi;
           if constexpr (NS > 0) {
-            constexpr float s1 = (float)inv_fact(3), s2 = (float)inv_fact(5), s3 = (float)inv_fact(7),
-                            s4 = (float)inv_fact(9), s5 = (float)inv_fact(11), s6 = (float)inv_fact(13);
-            constexpr float c1 = (float)inv_fact(2), c2 = (float)inv_fact(4), c3 = (float)inv_fact(6),
-                            c4 = (float)inv_fact(8), c5 = (float)inv_fact(10), c6 = (float)inv_fact(12);
+            // sin(x)/x and cos(x) as polynomials in u = x^2, the signs in the coefficients
+            constexpr float s1 = (float)-inv_fact(3), s2 = (float)inv_fact(5), s3 = (float)-inv_fact(7),
+                            s4 = (float)inv_fact(9), s5 = (float)-inv_fact(11), s6 = (float)inv_fact(13);
+            constexpr float c1 = (float)-inv_fact(2), c2 = (float)inv_fact(4), c3 = (float)-inv_fact(6),
+                            c4 = (float)inv_fact(8), c5 = (float)-inv_fact(10), c6 = (float)inv_fact(12);
             static_assert(NS == 5 || NS == 7, "series of 5 or 7 terms");
-            float v = -k2 * r2s;
             float ps, pc;
             if constexpr (NS == 7) {
-              ps = fmaf(s6, v, s5);
-              ps = fmaf(ps, v, s4);
-              pc = fmaf(c6, v, c5);
-              pc = fmaf(pc, v, c4);
+              ps = fmaf(s6, u, s5);
+              ps = fmaf(ps, u, s4);
+              pc = fmaf(c6, u, c5);
+              pc = fmaf(pc, u, c4);
             } else {
               ps = s4;
               pc = c4;
             }
-            ps = fmaf(ps, v, s3);
-            ps = fmaf(ps, v, s2);
-            ps = fmaf(ps, v, s1);
-            ps = fmaf(ps, v, 1.f);
-            pc = fmaf(pc, v, c3);
-            pc = fmaf(pc, v, c2);
-            pc = fmaf(pc, v, c1);
-            pc = fmaf(pc, v, 1.f);
-            hr = ps;
-            hi = -pc * (y * invk);
+            ps = fmaf(ps, u, s3);
+            ps = fmaf(ps, u, s2);
+            ps = fmaf(ps, u, s1);
+            ps = fmaf(ps, u, 1.f);
+            pc = fmaf(pc, u, c3);
+            pc = fmaf(pc, u, c2);
+            pc = fmaf(pc, u, c1);
+            pc = fmaf(pc, u, 1.f);
+            hr = ok ? ps : 0.f;
+            hi = -pc * y;
           } else {
-            float kr = kf * (r2s * y);
+            const float kr = u * y;
             float sn, cs;
             sincosf(kr, &sn, &cs);
-            float ikr = y * invk;
-            hr = sn * ikr;
-            hi = -cs * ikr;
+            hr = sn * y;
+            hi = -cs * y;
           }
-          hr = ok ? hr : 0.f;
-          hi = ok ? hi : 0.f;
-          float qr = s_qr[j], qi = s_qi[j];
+          const float qr = B.z, qi = B.w;
           ax = fmaf(qr, hr, fmaf(-qi, hi, ax));
           ay = fmaf(qr, hi, fmaf(qi, hr, ay));
         }
