@@ -1808,10 +1808,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   rep.n_react_classes = (int64_t)classes.size();
   rep.n_react_nodes = nodes_total;
   rep.n_ops_react = (int64_t)rops.size();
-  // shift operators in FP64 with the shift GEMM's stride; M2L operators in the M2L
-  // GEMMs' k-step-major layout, FP32 on the mixed path and FP64 otherwise
+  // every operator in the GEMMs' k-step-major layout: shift operators in FP64, M2L
+  // operators in FP32 on the mixed path and FP64 otherwise
   const int opsz_m = 2 * NKS * (m2l_nrt(NC) * 64 + 4 * m2l_xr(NC));
-  double* sops = P->dev<double>("sops", (size_t)nsh * opsz);
+  double* sops = P->dev<double>("sops", (size_t)nsh * opsz_m);
   double* ops = m2l32 ? nullptr : P->dev<double>("ops", (size_t)nops * opsz_m);
   float* ops32 = nullptr;
   int* d_opsc = nullptr;
@@ -1909,11 +1909,11 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
       d_td = P->upload("tab_gd", tD, s2);
     }
     double* Iall = classes.empty() ? nullptr : P->dev<double>("Iall", classes.size() * (size_t)NC * NC * 2);
-    lk_zero(sops, opsz, s2);  // operator 0 of both arrays: the zero operator
+    lk_zero(sops, opsz_m, s2);  // operator 0 of both arrays: the zero operator
     if (m2l32) lk_zero((double*)ops32, opsz_m / 2, s2);
     else lk_zero(ops, opsz_m, s2);
     sbeg(ST_OPS_FREE, s2);
-    lk_transop((int)fops.size(), d_fops, sops, opsz, ops, opsz_m, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
+    lk_transop((int)fops.size(), d_fops, sops, opsz_m, ops, opsz_m, p, NC, NKS, P->d_gaunt, ops32, d_opsc, s2);
     send(ST_OPS_FREE, s2);
     HIPCHK(hipEventRecord(P->ops_ev, s2));
     sbeg(ST_REACT_TABLES, s2);
@@ -2144,7 +2144,10 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   if (lk_m2l_lds_bytes(kmax_m2l, ks_m2l) > lk_m2l_lds_max()) throw Fail{LFMM_ENOTSUP};
   // M2M: the waves of a 16-target tile split each parent's eight child operators
   // (a level's parents alone give too few 64-target blocks to fill the GPU)
-  static const int ks_m2m = getenv("LFMM_M2M_KS") ? atoi(getenv("LFMM_M2M_KS")) : 4;  // tuning override
+  static const int ks_m2m = [] {  // tuning override: 1, 2 or 4
+    const int v = getenv("LFMM_M2M_KS") ? atoi(getenv("LFMM_M2M_KS")) : 4;
+    return (v == 1 || v == 2) ? v : 4;
+  }();
   build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9, 64 / ks_m2m);
   build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9, 64);
   build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1, 64 / ks_m2l);
@@ -2183,13 +2186,13 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   HIPCHK(hipStreamWaitEvent(s, P->ops_ev, 0));
   sbeg(ST_M2M, s);
   {
-    const int nrt = P->NRT, ksm = ks_m2m;
+    const int ksm = ks_m2m;
     const int* srow = J_m2m.srowid;
     qrun([=](hipStream_t ss, const double*, double*) {
       for (int lp = Dmax - 1; lp >= 2; lp--)
         if (bc_m2m[lp] > 0)
-          lk_gemm(nrt, ksm, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, srow, sr_m2m, 8, sops, opsz, NKS, M, M, NCK, NC,
-                  ss);
+          lk_m2l_gemm64(NC, ksm, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, srow, sr_m2m, 8, sops, opsz_m, NKS, M, M,
+                        NCK, ss);
     });
   }
   send(ST_M2M, s);
@@ -2219,13 +2222,12 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   mark(10);
   // ---------------- downward pass
   {
-    const int nrt = P->NRT;
     const int* srow = J_l2l.srowid;
     qrun([=](hipStream_t ss, const double*, double*) {
       for (int l = 3; l <= Dmax; l++)
         if (bc_l2l[l] > 0)
-          lk_gemm(nrt, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, srow, sr_l2l, 1, sops, opsz, NKS, Lx, Lx, NCK, NC,
-                  ss);
+          lk_m2l_gemm64(NC, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, srow, sr_l2l, 1, sops, opsz_m, NKS, Lx, Lx,
+                        NCK, ss);
     });
   }
   mark(11);
@@ -2857,15 +2859,13 @@ const char* lfmm_status_string(int status) {
   }
 }
 
-// Operator from its packed form: the shift GEMM's row-tile-major tiles, or (m2l)
-// the M2L GEMMs' k-step-major layout with its last-row entries.
-static void unpack_op(const std::vector<double>& pk, int NC, int NKS, bool m2l, double* out) {
+// Operator from its packed form: the GEMMs' k-step-major layout with its last-row entries.
+static void unpack_op(const std::vector<double>& pk, int NC, int NKS, double* out) {
   const int NRT = m2l_nrt(NC), XR = m2l_xr(NC), SZ = NRT * 64 + 4 * XR;
   for (int r = 0; r < NC; r++)
     for (int c = 0; c < NC; c++) {
       size_t pp;
-      if (!m2l) pp = ((size_t)((r >> 4) * NKS + (c >> 2)) << 7) + 2 * (size_t)((r & 15) | ((c & 3) << 4));
-      else if (r < NRT * 16) pp = 2 * ((size_t)(c >> 2) * SZ + (r >> 4) * 64 + (r & 15) + 16 * (c & 3));
+      if (r < NRT * 16) pp = 2 * ((size_t)(c >> 2) * SZ + (r >> 4) * 64 + (r & 15) + 16 * (c & 3));
       else pp = 2 * ((size_t)(c >> 2) * SZ + NRT * 64 + (c & 3));
       out[2 * ((size_t)r * NC + c)] = pk[pp];
       out[2 * ((size_t)r * NC + c) + 1] = pk[pp + 1];
@@ -2884,7 +2884,7 @@ int lfmm_translation(lfmm_plan_t* plan, int kind, double kw, const double* b, do
                nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
-    unpack_op(pk, plan->NC, plan->NKS, kind == 1, out);
+    unpack_op(pk, plan->NC, plan->NKS, out);
   } catch (Fail& f) {
     return f.code;
   }
@@ -2920,7 +2920,7 @@ int lfmm_reaction_operator(lfmm_plan_t* plan, int l, int a, int lp, int b, doubl
     lk_react_expand(1, dr, I, ops, plan->opsz, plan->p, NC, plan->NKS, nullptr, nullptr, nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
-    unpack_op(pk, NC, plan->NKS, true, out);
+    unpack_op(pk, NC, plan->NKS, out);
   } catch (Fail& f) {
     return f.code;
   }

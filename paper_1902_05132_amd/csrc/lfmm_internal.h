@@ -166,9 +166,6 @@ void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, con
 void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int total, const int* leafrow, const int* box_code,
             const int* box_tree, const int* box_level, const TreeInfo* trees, const double* px, const double* py,
             const double* pz, const int* sg, int p, int NCK, const double* Lc, double* phi_tp, hipStream_t s);
-void lk_gemm(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow, const int* srow,
-             int srow_stride, const double* ops, int opsz, int NKS, const double* S, double* D, int NCK, int NC,
-             hipStream_t s);
 void lk_group_ids(int nrows, int row0, int mode, const int* box_code, const int* box_tree, const int* box_level,
                   const TreeInfo* trees, const int* gbase, int nlev1, int* gid, int* rowid, hipStream_t s);
 // also adds the number of slots with a source present to *npairs

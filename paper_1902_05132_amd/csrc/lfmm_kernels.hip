@@ -541,15 +541,6 @@ __device__ __forceinline__ void fill_nm(int NC, int2* tab) {
     tab[r] = make_int2(n, m);
   }
 }
-// Entry e of an operator in the packed MFMA operand order: 16 x 4 tiles, row tile
-// major, and within a tile lane = (row & 15) | ((col & 3) << 4); packed_pos of the
-// result is 2 e, so consecutive threads store consecutive elements.
-__device__ __forceinline__ void packed_rc(int e, int NKS, int* row, int* col) {
-  const int tile = e >> 6, lane = e & 63;
-  *row = (tile / NKS) * 16 + (lane & 15);
-  *col = (tile % NKS) * 4 + (lane >> 4);
-}
-
 // Entry e of an operator in the FP32 M2L layout (k-step major; see m2l32_nrt):
 // k-step e / SZ, then within it the NRT tiles in lane order and the last row.
 __device__ __forceinline__ void m2l_packed_rc(int e, int NRT, int XR, int* row, int* col) {
@@ -627,20 +618,17 @@ __global__ __launch_bounds__(256) void k_transop(const OpDesc* descs, double* so
   }
   __syncthreads();
   // shift operators (regular) in their own array; M2L operators (singular) in the
-  // M2L array, FP32 when one is given
+  // M2L array, FP32 when one is given; both in the GEMMs' k-step-major layout
   const bool f32 = ops32 != nullptr && D.kind == 1;
   double* out = D.kind == 0 ? sops + (size_t)D.op * opsz : (f32 ? nullptr : ops + (size_t)D.op * opsz_m);
   float* out32 = f32 ? ops32 + (size_t)D.op * opsz_m : nullptr;
   const int2 se = f32 ? opse[D.op] : make_int2(0, 0);
-  int NR = ((NC + 15) / 16) * 16, NK = NKS * 4;
   int P1 = p + 1;
   const int nrtl = m2l_nrt(NC), xrl = m2l_xr(NC);
-  const bool m2l_lay = D.kind == 1;
-  const int ntot = m2l_lay ? NKS * (nrtl * 64 + 4 * xrl) : NR * NK;
+  const int ntot = NKS * (nrtl * 64 + 4 * xrl);
   for (int e = threadIdx.x; e < ntot; e += 256) {
     int row, col;
-    if (m2l_lay) m2l_packed_rc(e, nrtl, xrl, &row, &col);
-    else packed_rc(e, NKS, &row, &col);
+    m2l_packed_rc(e, nrtl, xrl, &row, &col);
     cd val = mk(0, 0);
     if (row < NC && col < NC) {
       const int n = nmt[row].x, mm = nmt[row].y, nu = nmt[col].x, mu = nmt[col].y;
@@ -1342,19 +1330,6 @@ extern "C" void lk_l2p(int nseg, const int* seg_s0, const int* seg_prefix, int t
 }
 
 // ---------------------------------------------------------------------------
-// Batched complex GEMM on FP64 MFMA (v_mfma_f64_16x16x4f64):
-//   D[trow(e)] += sum_k Op[seq(k)] * S[srow(e, k)]
-// for every target e of a block; one block = the targets of one group that share
-// the operator sequence.  A wave owns a tile of 16 targets (MFMA columns) and all
-// NRT row tiles; complex products use four real MFMAs.  KS waves share a target
-// tile and split its operator sequence (wave kw takes k = kw, kw + KS, ...); their
-// partial sums are combined through LDS in a fixed order, so a level with few
-// targets still spreads over the whole chip.  The operands of the next MFMA step
-// (including the first step of the next operator) are loaded while the current
-// step runs.
-// f64 16x16x4 lane layout: A lane l = (row l%16, k l/16); B lane l = (k l/16,
-// col l%16); D lane l element r = (row l/16 + 4r, col l%16).
-// ---------------------------------------------------------------------------
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own L2):
 // map the dispatch index so that consecutive logical blocks -- which share their
 // group's operator sequence -- run on the same XCD and reuse its L2.
@@ -1362,157 +1337,6 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + (x < r ? x : r) + (b >> 3);
 }
-template <int NRT, int KS>
-__device__ __forceinline__ void gemm_body(const GBlock* blocks, const int* seq, const int* trow, const int* srow,
-                                          int srow_stride, const double* __restrict__ ops, int opsz, int NKS,
-                                          const double2* __restrict__ S, double2* D, int NCK, int NC) {
-  GBlock bd = blocks[xcd_block(blockIdx.x, gridDim.x)];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int col = lane & 15, kr = lane >> 4;
-  const int cg = wave / KS, kw = wave % KS;
-  const int tt = cg * 16 + col;
-  const bool tv = tt < bd.nt;
-  const int ee = bd.e0 + (tv ? tt : 0);
-  const int* my_srow = srow + (size_t)ee * srow_stride;
-  v4d accr[NRT], acci[NRT];
-#pragma unroll
-  for (int i = 0; i < NRT; i++) {
-    accr[i] = (v4d){0, 0, 0, 0};
-    acci[i] = (v4d){0, 0, 0, 0};
-  }
-  const double2* A2 = (const double2*)ops;
-  const size_t opstride = (size_t)(opsz >> 1);
-  // first operator with a source for at least one target of the tile
-  int kk = kw, sr = -1;
-  while (kk < bd.K) {
-    sr = tv ? my_srow[kk] : -1;
-    if (__ballot(sr >= 0)) break;
-    kk += KS;
-  }
-  if (kk < bd.K) {
-    const double2* A = A2 + (size_t)seq[bd.seq0 + kk] * opstride;
-    const double2* B = S + (size_t)(sr >= 0 ? sr : 0) * NCK + kr;
-    bool bv = sr >= 0;
-    double2 a_cur[NRT], b_cur;
-#pragma unroll
-    for (int rt = 0; rt < NRT; rt++) a_cur[rt] = A[((size_t)(rt * NKS) << 6) + lane];
-    b_cur = bv ? B[0] : make_double2(0.0, 0.0);
-    while (true) {
-      // look-ahead of the next operator (its source row and operator index)
-      int kn = kk + KS, srn = -1, opn = 0;
-      if (kn < bd.K) {
-        srn = tv ? my_srow[kn] : -1;
-        opn = seq[bd.seq0 + kn];
-      }
-      for (int ks = 0; ks < NKS; ks++) {
-        double2 a_nxt[NRT], b_nxt;
-        if (ks + 1 < NKS) {
-#pragma unroll
-          for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS + ks + 1) << 6) + lane];
-          b_nxt = bv ? B[(ks + 1) * 4] : make_double2(0.0, 0.0);
-        } else {
-          // skip operators with no source for the whole tile
-          while (kn < bd.K && !__ballot(srn >= 0)) {
-            kn += KS;
-            if (kn < bd.K) {
-              srn = tv ? my_srow[kn] : -1;
-              opn = seq[bd.seq0 + kn];
-            }
-          }
-          if (kn < bd.K) {
-            A = A2 + (size_t)opn * opstride;
-            B = S + (size_t)(srn >= 0 ? srn : 0) * NCK + kr;
-            bv = srn >= 0;
-#pragma unroll
-            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = A[((size_t)(rt * NKS) << 6) + lane];
-            b_nxt = bv ? B[0] : make_double2(0.0, 0.0);
-          } else {
-#pragma unroll
-            for (int rt = 0; rt < NRT; rt++) a_nxt[rt] = a_cur[rt];
-            b_nxt = b_cur;
-          }
-        }
-#pragma unroll
-        for (int rt = 0; rt < NRT; rt++) {
-          accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur.x, accr[rt], 0, 0, 0);
-          acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].x, b_cur.y, acci[rt], 0, 0, 0);
-          accr[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_cur[rt].y, b_cur.y, accr[rt], 0, 0, 0);
-          acci[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[rt].y, b_cur.x, acci[rt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int rt = 0; rt < NRT; rt++) a_cur[rt] = a_nxt[rt];
-        b_cur = b_nxt;
-      }
-      if (kn >= bd.K) break;
-      kk = kn;
-    }
-  }
-  if constexpr (KS > 1) {
-    // partial sums of waves kw > 0 go through LDS, one row tile at a time
-    __shared__ double red[4][8][64];
-#pragma unroll
-    for (int rt = 0; rt < NRT; rt++) {
-      if (kw > 0) {
-#pragma unroll
-        for (int r = 0; r < 4; r++) {
-          red[wave][r][lane] = accr[rt][r];
-          red[wave][4 + r][lane] = acci[rt][r];
-        }
-      }
-      __syncthreads();
-      if (kw == 0) {
-        for (int w = 1; w < KS; w++)
-#pragma unroll
-          for (int r = 0; r < 4; r++) {
-            accr[rt][r] += red[wave + w][r][lane];
-            acci[rt][r] += red[wave + w][4 + r][lane];
-          }
-      }
-      __syncthreads();
-    }
-  }
-  if (kw != 0 || !tv) return;
-  double2* Dr = D + (size_t)trow[ee] * NCK;
-#pragma unroll
-  for (int rt = 0; rt < NRT; rt++)
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-      int row = rt * 16 + kr + 4 * r;
-      if (row < NC) {
-        double2 v = Dr[row];
-        v.x += accr[rt][r];
-        v.y += acci[rt][r];
-        Dr[row] = v;
-      }
-    }
-}
-// M2M and L2L
-template <int NRT, int KS>
-__global__ __launch_bounds__(256) void k_shift_gemm(const GBlock* blocks, const int* seq, const int* trow,
-                                                    const int* srow, int srow_stride, const double* __restrict__ ops,
-                                                    int opsz, int NKS, const double2* __restrict__ S, double2* D,
-                                                    int NCK, int NC) {
-  gemm_body<NRT, KS>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S, D, NCK, NC);
-}
-extern "C" void lk_gemm(int nrt, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
-                        const int* srow, int srow_stride, const double* ops, int opsz, int NKS, const double* S,
-                        double* D, int NCK, int NC, hipStream_t s) {
-  if (!nblocks) return;
-  const double2* S2 = (const double2*)S;
-  double2* D2 = (double2*)D;
-#define GEMM_CASE(N, K)                                                                                        \
-  if (nrt == N && ks == K) {                                                                                   \
-    k_shift_gemm<N, K><<<nblocks, 256, 0, s>>>(blocks, seq, trow, srow, srow_stride, ops, opsz, NKS, S2, D2, NCK, \
-                                               NC);                                                            \
-    return;                                                                                                    \
-  }
-  GEMM_CASE(1, 1) GEMM_CASE(2, 1) GEMM_CASE(3, 1) GEMM_CASE(4, 1) GEMM_CASE(5, 1) GEMM_CASE(6, 1) GEMM_CASE(7, 1)
-  GEMM_CASE(8, 1) GEMM_CASE(1, 2) GEMM_CASE(2, 2) GEMM_CASE(3, 2) GEMM_CASE(4, 2) GEMM_CASE(5, 2) GEMM_CASE(6, 2)
-  GEMM_CASE(7, 2) GEMM_CASE(8, 2) GEMM_CASE(1, 4) GEMM_CASE(2, 4) GEMM_CASE(3, 4) GEMM_CASE(4, 4) GEMM_CASE(5, 4)
-  GEMM_CASE(6, 4) GEMM_CASE(7, 4) GEMM_CASE(8, 4)
-#undef GEMM_CASE
-}
-
 // ---------------------------------------------------------------------------
 // FP32 path of the M2L (mixed precision).  Expansions of a box at level l of a
 // tree with wavenumber k are rescaled by powers c^n of c = 2^e, e = round(log2(1/(k h_l)))
