@@ -2191,7 +2191,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     qrun([=](hipStream_t ss, const double*, double*) {
       for (int lp = Dmax - 1; lp >= 2; lp--)
         if (bc_m2m[lp] > 0)
-          lk_m2l_gemm64(NC, ksm, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, srow, sr_m2m, 8, sops, opsz_m, NKS, M, M,
+          lk_shift_gemm64(NC, ksm, bc_m2m[lp], d_bm2m + bf_m2m[lp], d_sq_m2m, srow, sr_m2m, 8, sops, opsz_m, NKS, M, M,
                         NCK, ss);
     });
   }
@@ -2226,7 +2226,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     qrun([=](hipStream_t ss, const double*, double*) {
       for (int l = 3; l <= Dmax; l++)
         if (bc_l2l[l] > 0)
-          lk_m2l_gemm64(NC, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, srow, sr_l2l, 1, sops, opsz_m, NKS, Lx, Lx,
+          lk_shift_gemm64(NC, 1, bc_l2l[l], d_bl2l + bf_l2l[l], d_sq_l2l, srow, sr_l2l, 1, sops, opsz_m, NKS, Lx, Lx,
                         NCK, ss);
     });
   }

@@ -187,6 +187,10 @@ void lk_m_to_f32(int nrows, int NCK, int NC, const int* box_tree, const int* box
 // sequence; srow_stride is the longest sequence
 // M2L GEMMs: allow every instance the CU's LDS (less its static LDS); the dynamic LDS
 // any instance may take; the LDS one launch needs for its operator lists
+// M2M and L2L on the same GEMM design (shift operators in the M2L layout, FP64)
+void lk_shift_gemm64(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+                     const int* srow, int srow_stride, const double* ops, int opsz, int NKS, const double* S,
+                     double* D, int NCK, hipStream_t s);
 void lk_m2l_gemm_init();
 size_t lk_m2l_lds_max();
 size_t lk_m2l_lds_bytes(int srow_stride, int ks);

@@ -1647,6 +1647,48 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
                                                 dim, dxre, dxim, m2l_lists + 17 * lmax * wave, lmax);
   m2l_store<NRT, XR, KS>(bd, trow, D, NCK, NC, false, 0, nullptr, nullptr, nullptr, dre, dim, dxre, dxim);
 }
+// M2M and L2L: the same GEMM over the 8 (M2M) or 1 (L2L) shift operators of a
+// target's level; a kernel of its own so that profiles tell it from the M2L.
+template <int NRT, int XR, int KS>
+__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_shift_gemm64(
+    const GBlock* blocks, const int* seq, const int* trow, const int* srow, int srow_stride,
+    const double2* __restrict__ ops, int opstride2, int NKS, const double2* __restrict__ S, double2* D, int NCK,
+    int NC, int lmax) {
+  extern __shared__ int m2l_lists[];
+  const GBlock bd = blocks[xcd_block(blockIdx.x, gridDim.x)];
+  v4d dre[NRT], dim[NRT];
+#pragma unroll
+  for (int rt = 0; rt < NRT; rt++) {
+    dre[rt] = (v4d){0, 0, 0, 0};
+    dim[rt] = (v4d){0, 0, 0, 0};
+  }
+  double dxre = 0.0, dxim = 0.0;
+  const int wave = threadIdx.x >> 6;
+  m2l_body<double, NRT, XR, KS, 2, (NRT <= 5)>(bd, seq, srow, srow_stride, ops, (size_t)opstride2, NKS, S, NCK, dre,
+                                                dim, dxre, dxim, m2l_lists + 17 * lmax * wave, lmax);
+  m2l_store<NRT, XR, KS>(bd, trow, D, NCK, NC, false, 0, nullptr, nullptr, nullptr, dre, dim, dxre, dxim);
+}
+extern "C" void lk_shift_gemm64(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
+                                const int* srow, int srow_stride, const double* ops, int opsz, int NKS,
+                                const double* S, double* D, int NCK, hipStream_t s) {
+  if (!nblocks) return;
+  const int lmax = (srow_stride + ks - 1) / ks;
+  const size_t lds = sizeof(int) * 17 * (size_t)lmax * 4;
+  const int nrt = m2l_nrt(NC), xr = m2l_xr(NC);
+  const double2* o2 = (const double2*)ops;
+  const int os2 = opsz / 2;
+#define SHIFT_CASE(N, X, K)                                                                                     \
+  if (nrt == N && xr == X && ks == K) {                                                                         \
+    k_shift_gemm64<N, X, K><<<nblocks, 256, lds, s>>>(blocks, seq, trow, srow, srow_stride, o2, os2, NKS,       \
+                                                      (const double2*)S, (double2*)D, NCK, NC, lmax);           \
+    return;                                                                                                     \
+  }
+#define SHIFT_KS(N, X) SHIFT_CASE(N, X, 1) SHIFT_CASE(N, X, 2) SHIFT_CASE(N, X, 4)
+  SHIFT_KS(1, 0) SHIFT_KS(2, 0) SHIFT_KS(3, 1) SHIFT_KS(3, 0) SHIFT_KS(4, 0) SHIFT_KS(5, 1) SHIFT_KS(7, 0)
+  SHIFT_KS(8, 0)
+#undef SHIFT_KS
+#undef SHIFT_CASE
+}
 // Every M2L GEMM instance may use the CU's 160 KB of LDS, less its static LDS, for its
 // operator lists (17 ints per listed operator and wave), and the reaction node sums
 // for their tables; set once per plan, outside any capture and any evaluation (so no
