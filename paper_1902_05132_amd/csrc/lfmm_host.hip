@@ -1889,7 +1889,26 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     // waits for them before the M2M), then the reaction chain (joined before the M2L)
     OpDesc* d_fops = P->upload("fops", fops, s2);
     RIPrep rip = reaction_prep(P, "ri", qref, s2);
-    ROpDesc* d_rops = classes.empty() ? nullptr : P->upload("rops", rops, s2);
+    // reaction operators grouped by class (counting sort, stable): one expansion
+    // workgroup per class
+    std::vector<ROpDesc> rops_c(rops.size());
+    std::vector<int> rgrp;
+    if (!classes.empty()) {
+      std::vector<int> ccnt(classes.size() + 1, 0);
+      for (const ROpDesc& R : rops) ccnt[R.cls + 1]++;
+      for (size_t c = 0; c < classes.size(); c++) {
+        if (ccnt[c + 1] > 8) throw Fail{LFMM_ENOTSUP};  // (a class has at most 8 lateral offsets)
+        if (ccnt[c + 1] > 0) {
+          rgrp.push_back(ccnt[c]);
+          rgrp.push_back(ccnt[c + 1]);
+        }
+        ccnt[c + 1] += ccnt[c];
+      }
+      std::vector<int> pos(ccnt.begin(), ccnt.end() - 1);
+      for (const ROpDesc& R : rops) rops_c[pos[R.cls]++] = R;
+    }
+    ROpDesc* d_rops = classes.empty() ? nullptr : P->upload("rops", rops_c, s2);
+    int* d_rgrp = rgrp.empty() ? nullptr : P->upload("rop_groups", rgrp, s2);
     ClassDesc* d_gcls = nullptr;
     int* d_gcombo = nullptr;
     double *d_gh = nullptr, *d_gd = nullptr;
@@ -1946,7 +1965,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
                       NC, Iall, s2);
       send(ST_REACT_TAB, s2);
       sbeg(ST_REACT_EXPAND, s2);
-      lk_react_expand((int)rops.size(), d_rops, Iall, ops, opsz_m, p, NC, NKS, ops32, d_opsc, s2);
+      lk_react_expand((int)rgrp.size() / 2, d_rgrp, d_rops, Iall, ops, opsz_m, p, NC, NKS, ops32, d_opsc, s2);
     } else {
       send(ST_REACT_TABLES, s2);
       sbeg(ST_REACT_MFMA, s2);
@@ -2917,7 +2936,9 @@ int lfmm_reaction_operator(lfmm_plan_t* plan, int l, int a, int lp, int b, doubl
     r[0] = ROpDesc{dx, dy, st.k[l], 0, 0};
     ROpDesc* dr = plan->upload("dbg_rop", r, nullptr);
     double* ops = plan->dev<double>("dbg_ops", plan->opsz);
-    lk_react_expand(1, dr, I, ops, plan->opsz, plan->p, NC, plan->NKS, nullptr, nullptr, nullptr);
+    std::vector<int> g1 = {0, 1};
+    int* dg = plan->upload("dbg_rgrp", g1, nullptr);
+    lk_react_expand(1, dg, dr, I, ops, plan->opsz, plan->p, NC, plan->NKS, nullptr, nullptr, nullptr);
     std::vector<double> pk(plan->opsz);
     HIPCHK(hipMemcpy(pk.data(), ops, sizeof(double) * plan->opsz, hipMemcpyDeviceToHost));
     unpack_op(pk, NC, plan->NKS, out);

@@ -157,8 +157,9 @@ void lk_react_F(int ncls, const ClassDesc* cls, int Ftot, Stack st, int Ntot, co
                 hipStream_t s);
 void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p, int Ntot,
                    const double* Jtab, const double* Ptab, const double* Ftab, double* Iout, int NC, hipStream_t s);
-void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p, int NC,
-                     int NKS, float* ops32, const int* opse, hipStream_t s);
+// grp: (first, count) per class over rops sorted by class, at most 8 operators a class
+void lk_react_expand(int ngrp, const int* grp, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p,
+                     int NC, int NKS, float* ops32, const int* opse, hipStream_t s);
 void lk_p2m(int nseg, const int* seg_row0, const int* seg_prefix, int total, const int* box_start,
             const int* box_cnt, const int* box_code, const int* box_tree, const int* box_level,
             const TreeInfo* trees, const double* px, const double* py, const double* pz, const double* pq, int p,

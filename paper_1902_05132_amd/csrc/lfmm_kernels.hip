@@ -1049,51 +1049,63 @@ extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* me
 
 // T[(n,m),(n',m')] = (4 pi/k_t) i^n (-i)^{n'} i^q e^{i q phi} I[(n,m),(n',m')], q = m' - m,
 // phi = arg of the lateral offset target - source.  One workgroup per operator.
-__global__ __launch_bounds__(256) void k_react_expand(const ROpDesc* rops, const double* Iall, double* ops, int opsz,
-                                                      int p, int NC, int NKS, float* ops32, const int2* opse) {
-  __shared__ cd ph[64];  // i^q e^{i q phi}, q = -2p..2p
+// One workgroup per class: the class's integral matrix is read once and written out as
+// each of its operators (at most eight lateral offsets share a class), which differ
+// only in the phases e^{i q phi}; operators of one class share k_t and the FP32 scale
+// exponents.  grp[g] = (first operator in rops, count).
+#define RX_MAXOPS 8
+__global__ __launch_bounds__(256) void k_react_expand(const int2* grp, const ROpDesc* rops, const double* Iall,
+                                                      double* ops, int opsz, int p, int NC, int NKS, float* ops32,
+                                                      const int2* opse) {
+  __shared__ cd ph[RX_MAXOPS][64];  // i^q e^{i q phi} of each operator, q = -2p..2p
+  __shared__ int s_op[RX_MAXOPS];
   __shared__ int2 nmt[NM_TAB];
-  ROpDesc R = rops[blockIdx.x];
+  const int2 G = grp[blockIdx.x];
+  const int nop = G.y;
   fill_nm(NC, nmt);
-  const double phi = atan2(R.dy, R.dx);
   const int Q = 2 * p;
-  if ((int)threadIdx.x <= 2 * Q) {
-    int q = (int)threadIdx.x - Q;
+  for (int t = threadIdx.x; t < nop * (2 * Q + 1); t += 256) {
+    const int o = t / (2 * Q + 1), q = t % (2 * Q + 1) - Q;
+    const ROpDesc R = rops[G.x + o];
     double sn, cs;
-    sincos(q * phi, &sn, &cs);
-    ph[threadIdx.x] = ipow(q) * mk(cs, sn);
+    sincos(q * atan2(R.dy, R.dx), &sn, &cs);
+    ph[o][q + Q] = ipow(q) * mk(cs, sn);
+    if (q == -Q) s_op[o] = R.op;
   }
   __syncthreads();
-  const double* I = Iall + (size_t)R.cls * NC * NC * 2;
-  double* out = ops32 ? nullptr : ops + (size_t)R.op * opsz;
-  float* out32 = ops32 ? ops32 + (size_t)R.op * opsz : nullptr;
-  const int2 se = ops32 ? opse[R.op] : make_int2(0, 0);
-  double pre = 4.0 * LFMM_PI / R.kt;
+  const ROpDesc R0 = rops[G.x];
+  const double* I = Iall + (size_t)R0.cls * NC * NC * 2;
+  const int2 se = ops32 ? opse[R0.op] : make_int2(0, 0);
+  const double pre = 4.0 * LFMM_PI / R0.kt;
   const int nrtl = m2l_nrt(NC), xrl = m2l_xr(NC);
   const int ntot = NKS * (nrtl * 64 + 4 * xrl);
   for (int e = threadIdx.x; e < ntot; e += 256) {
     int row, col;
     m2l_packed_rc(e, nrtl, xrl, &row, &col);
-    cd val = mk(0, 0);
-    if (row < NC && col < NC) {
+    const bool in = row < NC && col < NC;
+    cd base = mk(0, 0);
+    int q = 0;
+    if (in) {
       const int n = nmt[row].x, m = nmt[row].y, n2 = nmt[col].x, m2 = nmt[col].y;
-      cd iv = mk(I[2 * ((size_t)row * NC + col)], I[2 * ((size_t)row * NC + col) + 1]);
-      val = pre * (ipow(n - n2) * (ph[m2 - m + Q] * iv));
-      if (out32) {
-        int sh = -(se.x * n + se.y * n2);
-        val = mk(ldexp(val.x, sh), ldexp(val.y, sh));
+      base = pre * (ipow(n - n2) * mk(I[2 * ((size_t)row * NC + col)], I[2 * ((size_t)row * NC + col) + 1]));
+      if (ops32) {
+        const int sh = -(se.x * n + se.y * n2);
+        base = mk(ldexp(base.x, sh), ldexp(base.y, sh));
       }
+      q = m2 - m + Q;
     }
-    if (out32) {
-      ((float2*)out32)[e] = make_float2((float)val.x, (float)val.y);
-    } else {
-      ((double2*)out)[e] = make_double2(val.x, val.y);
+    for (int o = 0; o < nop; o++) {
+      const cd val = in ? ph[o][q] * base : mk(0, 0);
+      if (ops32) ((float2*)(ops32 + (size_t)s_op[o] * opsz))[e] = make_float2((float)val.x, (float)val.y);
+      else ((double2*)(ops + (size_t)s_op[o] * opsz))[e] = make_double2(val.x, val.y);
     }
   }
 }
-extern "C" void lk_react_expand(int nops, const ROpDesc* rops, const double* Iall, double* ops, int opsz, int p,
-                                int NC, int NKS, float* ops32, const int* opse, hipStream_t s) {
-  if (nops) k_react_expand<<<nops, 256, 0, s>>>(rops, Iall, ops, opsz, p, NC, NKS, ops32, (const int2*)opse);
+extern "C" void lk_react_expand(int ngrp, const int* grp, const ROpDesc* rops, const double* Iall, double* ops,
+                                int opsz, int p, int NC, int NKS, float* ops32, const int* opse, hipStream_t s) {
+  if (ngrp)
+    k_react_expand<<<ngrp, 256, 0, s>>>((const int2*)grp, rops, Iall, ops, opsz, p, NC, NKS, ops32,
+                                        (const int2*)opse);
 }
 
 // ---------------------------------------------------------------------------
