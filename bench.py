@@ -512,7 +512,7 @@ def main():
             peak = PEAK[(c["bound"], c["bits"])]
             r = {"kernel": c["kernel"], "what": c["what"], "stream": c["stream"], "bound": c["bound"],
                  "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                 "traffic": profiled_traffic(c["kernel"], n, args.p, args.leaf, args.seed),
+                 "traffic": profiled_traffic(c["kernel"].split("<")[0], n, args.p, args.leaf, args.seed),
                  "algorithmic_flops_per_launch": c["flops"], "launch_ms": stages[c["stage"]]}
             if c.get("impl"):
                 # the operations the kernel's series form of h0 executes per pair
