@@ -104,7 +104,10 @@ typedef struct {
 } lfmm_report;
 
 /*
- * lfmm_plan -- fix the layered medium and the FMM parameters.
+ * lfmm_plan -- fix the layered medium and the FMM parameters: the stack of Section 3.1
+ * (interfaces z = d_l, layer l between d_l and d_{l-1}, wavenumber k_l in layer l), the
+ * truncation order p of the expansions of Sections 2 and 3.3 and the leaf bound of the
+ * trees of Section 3.4.
  *   L        number of interfaces (0 <= L <= 16; L = 0 is free space)
  *   d        host array of L interface heights, strictly decreasing (copied)
  *   k        host array of L+1 wavenumbers, each > 0 (copied)
@@ -118,7 +121,11 @@ int lfmm_plan(int L, const double* d, const double* k, int p, int leaf_max, cons
               lfmm_plan_t** out);
 
 /*
- * lfmm_eval_device -- Phi at every particle (targets = sources), device memory.
+ * lfmm_eval_device -- Phi at every particle (targets = sources), device memory: the total
+ * interaction of Section 3.4 eq. (totalinteraction) -- the free-space sum within each
+ * layer plus the four reaction components of every layer pair (Section 3.1 eq.
+ * (greenfuncomponent)) -- by Algorithm 1 (Section 3.4) on the polarisation sources of
+ * Section 3.3 eq. (eqpolarizedsource).
  *   n        number of particles (0 <= n < 2^31)
  *   xyz      device, 3*n doubles, structure of arrays: x[0..n), y[0..n), z[0..n)
  *   layer    device, n int32 layer ids or NULL (then derived from z); when given,
