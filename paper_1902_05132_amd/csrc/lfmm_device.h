@@ -157,11 +157,14 @@ __device__ __forceinline__ void dev_sph_j_t(double x, double (&j)[P + 1]) {
     }
     return;
   }
+  // one reciprocal for the whole recurrence: the backward recurrence is stable, so the
+  // extra rounding of (2n+1) * (1/x) against (2n+1) / x stays at the last digit
+  const double ix = 1.0 / x;
   int N = P + 24 + (int)x;
   fp1 = 0.0;
   f = 1e-200;
   for (int n = N; n >= P + 2; n--) {  // f_{n-1} from f_n, f_{n+1}; nothing stored yet
-    double fm = (2.0 * n + 1.0) / x * f - fp1;
+    double fm = (2.0 * n + 1.0) * ix * f - fp1;
     fp1 = f;
     f = fm;
     if (fabs(f) > 1e200) {
@@ -172,14 +175,14 @@ __device__ __forceinline__ void dev_sph_j_t(double x, double (&j)[P + 1]) {
   // f = f_{P+1}, fp1 = f_{P+2}
 #pragma unroll
   for (int n = P + 1; n >= 1; n--) {
-    double fm = (2.0 * n + 1.0) / x * f - fp1;
+    double fm = (2.0 * n + 1.0) * ix * f - fp1;
     fp1 = f;
     f = fm;
     j[n - 1] = f;
   }
   double s, c;
   sincos(x, &s, &c);
-  double j0 = s / x, j1 = s / (x * x) - c / x;
+  double j0 = s * ix, j1 = (s * ix - c) * ix;
   double sc = (fabs(j0) >= fabs(j1)) ? j0 / j[0] : j1 / j[1];
 #pragma unroll
   for (int n = 0; n <= P; n++) j[n] *= sc;

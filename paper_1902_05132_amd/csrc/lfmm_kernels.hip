@@ -1123,26 +1123,36 @@ __device__ __forceinline__ int seg_find(const int* prefix, int nseg, int x) {
   return lo;
 }
 
-// One workgroup of 128 threads per leaf.  The per-particle quantities (j_n(k r),
-// the angles and the charge) are computed once per particle into LDS; then thread
-// (m, sign, stripe) runs the Legendre recurrence in n for order m over its stripe of
-// the particles and accumulates M_{n,m} (sign 0) or M_{n,-m} (sign 1); the stripes
-// are summed through LDS in a fixed order.  One sign per thread halves the
-// accumulators a thread holds, and the stripe sums reuse the staging arrays' LDS
-// (they start after the last particle chunk is consumed): four waves share a SIMD.
+// One workgroup of 128 threads per leaf, the particles taken in chunks of 64.  Per
+// chunk the first wave computes 4 pi j_n(k r), cos(theta) and the charge of each
+// particle, the second wave Phat_m^m(theta) e^{i m phi} for every order m (the
+// diagonal start of the Legendre recurrence and the azimuthal factor), all into LDS.
+// Then thread (m, stripe) runs the recurrence in n for order m, normalised to start at
+// 1, over its stripe of the chunk and accumulates both M_{n,m} and M_{n,-m}, which share
+// every recurrence value; the stripes are summed through LDS in a fixed order, one sign
+// at a time.  The two signs' accumulators need three waves per SIMD's registers.
 template <int P>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix,
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3))) void k_p2m(int nseg, const int* seg_row0, const int* seg_prefix,
                                              const int* box_start, const int* box_cnt, const int* box_code,
                                              const int* box_tree, const int* box_level, const TreeInfo* trees,
                                              const double* px, const double* py, const double* pz, const double* pq,
                                              int NCK, double* M) {
-  constexpr int P1 = P + 1, NSTR = 128 / (2 * P1);
-  constexpr int NSTAGE = (6 + P1) * 128, NRED = 2 * NSTR * P1 * P1 * 2;
-  __shared__ double smem[NSTAGE > NRED ? NSTAGE : NRED];
-  double *s_ct = smem, *s_st = smem + 128, *s_cp = smem + 256, *s_sp = smem + 384, *s_qr = smem + 512,
-         *s_qi = smem + 640;
-  double(*s_j)[128] = reinterpret_cast<double(*)[128]>(smem + 768);
-  double* red = smem;  // [sign][stripe][m][n] (re, im)
+  constexpr int P1 = P + 1, NSTR = 128 / P1, CH = 64, ES = CH + 1;
+  constexpr int NTRI = P1 * (P1 + 1) / 2;  // (m, n >= m) pairs of one sign
+  // staging: cos(theta), charge, j_n rows, then the Phat_m^m e^{i m phi} rows (padded by
+  // one entry so that the orders of one particle fall in different banks)
+  constexpr int NSTAGE = 3 * CH + P1 * CH + 2 * P1 * ES, NRED = NSTR * NTRI * 2;
+  __shared__ __align__(16) double smem[NSTAGE > NRED ? NSTAGE : NRED];
+  // recurrence coefficients (a_n^m, b_n^m) at n P1 + m.  On and below the diagonal they
+  // are set to (0, -1): started from p_{-2} = p_{-1} = 1 the steps n <= m then give 1,
+  // the normalised start of order m, with no branch (the values below the diagonal are
+  // accumulated but never stored); b vanishes one above the diagonal
+  __shared__ double2 s_ab[P1 * P1];
+  double* s_ct = smem;
+  double2* s_q = reinterpret_cast<double2*>(smem + CH);
+  double(*s_j)[CH] = reinterpret_cast<double(*)[CH]>(smem + 3 * CH);
+  double2(*s_e)[ES] = reinterpret_cast<double2(*)[ES]>(smem + 3 * CH + P1 * CH);
+  double* red = smem;  // [stripe][(m, n >= m)] (re, im), one sign at a time
   const int tid = threadIdx.x;
   const int li = blockIdx.x;
   const int sgm = seg_find(seg_prefix, nseg, li);
@@ -1151,99 +1161,109 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void k
   double c[3];
   box_center(T, (unsigned)box_code[R], box_level[R], c);
   const int s0 = box_start[R], nt = box_cnt[R];
-  const int m = tid % P1, sgn = (tid / P1) & 1, str = tid / (2 * P1);
-  // M_{n,0} needs one sign only
-  const bool active = str < NSTR && !(sgn && m == 0);
-  // conj(Y_n^m) = Phat e^{-i m phi};  conj(Y_n^{-m}) = (-1)^m Phat e^{+i m phi}
-  const double cm = sgn ? ((m & 1) ? -1.0 : 1.0) : 1.0, ss = sgn ? 1.0 : -1.0;
-  cd acc[P1];
+  for (int o = tid; o < P1 * P1; o += 128) {
+    const int n = o / P1, mm = o % P1;
+    s_ab[o] = n <= mm ? make_double2(0.0, -1.0) : make_double2(c_la[n * 16 + mm], c_lb[n * 16 + mm]);
+  }
+  const int m = tid % P1, str = tid / P1;
+  const bool active = str < NSTR;
+  const double cm = (m & 1) ? -1.0 : 1.0;
+  cd accp[P1], accn[P1];
 #pragma unroll
-  for (int n = 0; n <= P; n++) acc[n] = mk(0, 0);
-  for (int c0 = 0; c0 < nt; c0 += 128) {
-    const int nc = nt - c0 < 128 ? nt - c0 : 128;
+  for (int n = 0; n <= P; n++) {
+    accp[n] = mk(0, 0);
+    accn[n] = mk(0, 0);
+  }
+  for (int c0 = 0; c0 < nt; c0 += CH) {
+    const int nc = nt - c0 < CH ? nt - c0 : CH;
+    const int pl = tid & (CH - 1);
     __syncthreads();
-    if (tid < nc) {
-      const int i = s0 + c0 + tid;
-      double dx = px[i] - c[0], dy = py[i] - c[1], dz = pz[i] - c[2];
-      double rho = sqrt(dx * dx + dy * dy), r = sqrt(rho * rho + dz * dz);
-      double jn[P1];
-      dev_sph_j_t<P>(T.k * r, jn);
+    if (pl < nc) {
+      const int i = s0 + c0 + pl;
+      const double dx = px[i] - c[0], dy = py[i] - c[1], dz = pz[i] - c[2];
+      const double rho = sqrt(dx * dx + dy * dy), r = sqrt(rho * rho + dz * dz);
+      if (tid < CH) {
+        double jn[P1];
+        dev_sph_j_t<P>(T.k * r, jn);
 #pragma unroll
-      for (int n = 0; n <= P; n++) s_j[n][tid] = 4.0 * LFMM_PI * jn[n];
-      s_ct[tid] = r > 0 ? dz / r : 1.0;
-      s_st[tid] = r > 0 ? rho / r : 0.0;
-      s_cp[tid] = rho > 0 ? dx / rho : 1.0;
-      s_sp[tid] = rho > 0 ? dy / rho : 0.0;
-      s_qr[tid] = pq[2 * i];
-      s_qi[tid] = pq[2 * i + 1];
+        for (int n = 0; n <= P; n++) s_j[n][pl] = 4.0 * LFMM_PI * jn[n];
+        s_ct[pl] = r > 0 ? dz / r : 1.0;
+        s_q[pl] = make_double2(pq[2 * i], pq[2 * i + 1]);
+      } else {
+        const double st = r > 0 ? rho / r : 0.0;
+        // e^{i m phi} by repeated multiplication with e^{i phi} = (dx + i dy) / rho
+        const double cp = rho > 0 ? dx / rho : 1.0, sp = rho > 0 ? dy / rho : 0.0;
+        double pmm = 0.28209479177387814347, cs = 1.0, sn = 0.0;
+        s_e[0][pl] = make_double2(pmm, 0.0);
+#pragma unroll
+        for (int mm = 1; mm <= P; mm++) {
+          pmm *= c_ld[mm] * st;
+          const double t = cs * cp - sn * sp;
+          sn = sn * cp + cs * sp;
+          cs = t;
+          s_e[mm][pl] = make_double2(pmm * cs, pmm * sn);
+        }
+      }
     }
     __syncthreads();
     if (active) {
+      // the second particle of an iteration past the end of the chunk is a zero-weight
+      // copy of the first
 #pragma unroll 1
       for (int i = str; i < nc; i += NSTR) {
-        const double ct = s_ct[i], st = s_st[i];
-        // e^{i m phi} by repeated multiplication
-        double cs = 1.0, sn = 0.0;
-        const double cp = s_cp[i], sp = s_sp[i];
-        for (int k = 0; k < m; k++) {
-          double t = cs * cp - sn * sp;
-          sn = sn * cp + cs * sp;
-          cs = t;
-        }
-        const cd qx = cm * (mk(s_qr[i], s_qi[i]) * mk(cs, ss * sn));
-        double pmm = 0.28209479177387814347;
-        for (int mm = 1; mm <= m; mm++) pmm *= c_ld[mm] * st;
-        double p0 = 0.0, p1 = 0.0;
+        const double ct = s_ct[i];
+        const double2 e = s_e[m][i], q = s_q[i];
+        const cd qp = mk(q.x, q.y) * mk(e.x, -e.y), qn = cm * (mk(q.x, q.y) * mk(e.x, e.y));
+        double p0 = 1.0, p1 = 1.0;
 #pragma unroll
         for (int n = 0; n <= P; n++) {
-          if (n < m) continue;
-          double val;
-          if (n == m) {
-            val = pmm;
-            p1 = pmm;
-          } else {
-            val = c_la[n * 16 + m] * ct * p1 - c_lb[n * 16 + m] * p0;
-            p0 = p1;
-            p1 = val;
-          }
-          acc[n] = acc[n] + (s_j[n][i] * val) * qx;
+          const double2 ab = s_ab[n * P1 + m];
+          const double val = ab.x * ct * p1 - ab.y * p0;
+          p0 = p1;
+          p1 = val;
+          const double u = s_j[n][i] * val;
+          accp[n] = accp[n] + u * qp;
+          accn[n] = accn[n] + u * qn;
         }
       }
     }
   }
-  __syncthreads();
-  if (str < NSTR) {
-#pragma unroll
-    for (int n = 0; n <= P; n++) {
-      const size_t o = (((size_t)(sgn * NSTR + str) * P1 + m) * P1 + n) * 2;
-      red[o] = acc[n].x;
-      red[o + 1] = acc[n].y;
-    }
-  }
-  __syncthreads();
-  // one thread per output (sign, m, n >= m; no sign 1 for m = 0; 2 NOUT exceeds the
-  // block at P = 10, so the threads stride over the outputs): the stripes are summed
-  // in a fixed order
+  // (m, n) at m P1 - m (m - 1) / 2 + (n - m) within one stripe's block
+  const int tri = m * P1 - m * (m - 1) / 2 - m;
   double* Mr = M + (size_t)R * NCK * 2;
-  constexpr int NOUT = P1 * (P1 + 1) / 2;
-  for (int o = tid; o < 2 * NOUT; o += 128) {
-    const int half = o / NOUT;
-    int mm = 0, r = o % NOUT;
-    while (r >= P1 - mm) {
-      r -= P1 - mm;
-      mm++;
-    }
-    const int n = mm + r;
-    if (half == 0 || mm > 0) {
-      double sx = 0.0, sy = 0.0;
-      for (int k = 0; k < NSTR; k++) {
-        const size_t o = (((size_t)(half * NSTR + k) * P1 + mm) * P1 + n) * 2;
-        sx += red[o];
-        sy += red[o + 1];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int n = 0; n <= P; n++) {
+        if (n < m) continue;
+        const cd a = h ? accn[n] : accp[n];
+        const size_t o = ((size_t)str * NTRI + tri + n) * 2;
+        red[o] = a.x;
+        red[o + 1] = a.y;
       }
-      const int oc = cidx(n, half ? -mm : mm);
-      Mr[2 * oc] = sx;
-      Mr[2 * oc + 1] = sy;
+    }
+    __syncthreads();
+    // one thread per output (m, n >= m; no sign 1 for m = 0): the stripes are summed in
+    // a fixed order
+    for (int o = tid; o < NTRI; o += 128) {
+      int mm = 0, r = o;
+      while (r >= P1 - mm) {
+        r -= P1 - mm;
+        mm++;
+      }
+      const int n = mm + r;
+      if (h == 0 || mm > 0) {
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < NSTR; k++) {
+          sx += red[((size_t)k * NTRI + o) * 2];
+          sy += red[((size_t)k * NTRI + o) * 2 + 1];
+        }
+        const int oc = cidx(n, h ? -mm : mm);
+        Mr[2 * oc] = sx;
+        Mr[2 * oc + 1] = sy;
+      }
     }
   }
 }
