@@ -64,7 +64,8 @@ struct ClassDesc {
 // A stack of reaction classes contracted together: same quadrature rule group
 // and source layer, at most SC_GMAX classes and three target layers.
 #define SC_GMAX 16
-#define SC_UPW 6  // MFMA units per wave
+#define SC_UPW 5     // MFMA units per wave
+#define SC_G3 true  // complex products in Gauss's three-product form
 struct SCDesc {
   int rg_off, nn, ls, G;
   int mem0;   // first member in the member list

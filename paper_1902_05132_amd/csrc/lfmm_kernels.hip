@@ -843,12 +843,12 @@ __global__ __launch_bounds__(256) void k_react_F_lt(const ClassDesc* cls, int nc
 // classes sharing both (a stack of G <= 16 classes, with at most three target
 // layers) are contracted together: for each m the left-hand rows (g, n) of all
 // G classes are packed into 16-row tiles, and the products run as 16x16x4
-// complex MFMA steps (four real MFMAs each) against column tiles (n', m') in NC
-// order.  The (m, row tile, column tile) units of a stack are spread over the
+// complex MFMA steps (three real MFMAs each in Gauss's form, four otherwise)
+// against column tiles (n', m') in NC order.  The (m, row tile, column tile) units of a stack are spread over the
 // eight waves of one or more workgroups (UPW units per wave); the node tables of
 // a chunk of CH nodes are staged in LDS.  Entries with -m, -m' equal those with
 // m, m' and are written too.
-template <int UPW, int CH>
+template <int UPW, int CH, bool G3>
 __global__ __launch_bounds__(512) void k_react_mfma(const SCDesc* scs, int nsc, const int* members,
                                                     const ClassDesc* cls, int p, int Ntot, const cd* Jtab,
                                                     const cd* Ptab, const cd* Ftab, double* Iout, int NC) {
@@ -930,11 +930,14 @@ __global__ __launch_bounds__(512) void k_react_mfma(const SCDesc* scs, int nsc, 
       sgn[i] = (double)sg;
     }
   }
-  v4d accr[UPW], acci[UPW];
+  // Gauss's form (G3): P1 = Ar Br, P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi) in accr, accg,
+  // acci; re = P1 - P2, im = P3 - P1 - P2.  Otherwise four real products.
+  v4d accr[UPW], acci[UPW], accg[G3 ? UPW : 1];
 #pragma unroll
   for (int i = 0; i < UPW; i++) {
     accr[i] = (v4d){0, 0, 0, 0};
     acci[i] = (v4d){0, 0, 0, 0};
+    if constexpr (G3) accg[i] = (v4d){0, 0, 0, 0};
   }
   const int nn = S.nn;
   const cd* Jg = Jtab + (size_t)S.rg_off * (Q + 1);
@@ -969,10 +972,16 @@ __global__ __launch_bounds__(512) void k_react_mfma(const SCDesc* scs, int nsc, 
           ai = x.y;
         }
         cd y = sgn[i] * (FJ[c * (Q + 1) + jq[i]] * PS[c * NT + psi[i]]);
-        accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.x, accr[i], 0, 0, 0);
-        acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.y, acci[i], 0, 0, 0);
-        accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, y.y, accr[i], 0, 0, 0);
-        acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, y.x, acci[i], 0, 0, 0);
+        if constexpr (G3) {
+          accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.x, accr[i], 0, 0, 0);
+          accg[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, y.y, accg[i], 0, 0, 0);
+          acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, y.x + y.y, acci[i], 0, 0, 0);
+        } else {
+          accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.x, accr[i], 0, 0, 0);
+          acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, y.y, acci[i], 0, 0, 0);
+          accr[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, y.y, accr[i], 0, 0, 0);
+          acci[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, y.x, acci[i], 0, 0, 0);
+        }
       }
     }
   }
@@ -991,13 +1000,18 @@ __global__ __launch_bounds__(512) void k_react_mfma(const SCDesc* scs, int nsc, 
       if (row >= G * Rm) continue;
       int g = row / Rm, n = m + row % Rm;
       double* out = Iout + (size_t)s_out[g] * NC * NC * 2;
+      double vr = accr[i][r], vi = acci[i][r];
+      if constexpr (G3) {
+        vi = vi - vr - accg[i][r];
+        vr = vr - accg[i][r];
+      }
       size_t o1 = (size_t)cidx(n, m) * NC + j;
-      out[2 * o1] = accr[i][r];
-      out[2 * o1 + 1] = acci[i][r];
+      out[2 * o1] = vr;
+      out[2 * o1 + 1] = vi;
       if (m > 0) {
         size_t o2 = (size_t)cidx(n, -m) * NC + cidx(n2, -m2);
-        out[2 * o2] = accr[i][r];
-        out[2 * o2 + 1] = acci[i][r];
+        out[2 * o2] = vr;
+        out[2 * o2 + 1] = vi;
       }
     }
   }
@@ -1029,7 +1043,7 @@ template <int UPW, int CH>
 static void launch_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p,
                               int Ntot, const cd* J, const cd* P, const cd* F, double* Iout, int NC, size_t lds,
                               hipStream_t s) {
-  k_react_mfma<UPW, CH><<<nwg, 512, lds, s>>>(scs, nsc, members, cls, p, Ntot, J, P, F, Iout, NC);
+  k_react_mfma<UPW, CH, SC_G3><<<nwg, 512, lds, s>>>(scs, nsc, members, cls, p, Ntot, J, P, F, Iout, NC);
 }
 extern "C" void lk_react_mfma(int nwg, int nsc, const SCDesc* scs, const int* members, const ClassDesc* cls, int p,
                               int Ntot, const double* Jtab, const double* Ptab, const double* Ftab, double* Iout,
@@ -1748,8 +1762,8 @@ extern "C" void lk_m2l_gemm_init() {
 #undef M2L_ATTR
   g_m2l_lds_max = lim;
   // the reaction node sums' LDS (32 or 16 classes' tables per workgroup)
-  (void)m2l_allow_lds(k_react_mfma<SC_UPW, 32>);
-  (void)m2l_allow_lds(k_react_mfma<SC_UPW, 16>);
+  (void)m2l_allow_lds(k_react_mfma<SC_UPW, 32, SC_G3>);
+  (void)m2l_allow_lds(k_react_mfma<SC_UPW, 16, SC_G3>);
   (void)hipGetLastError();  // a refused attribute leaves no error behind: its smaller limit is kept
 }
 extern "C" size_t lk_m2l_lds_max() { return g_m2l_lds_max; }
