@@ -2120,9 +2120,13 @@ __device__ __forceinline__ void count_wave(int cnt, unsigned long long* npairs) 
 // M2L sources from interaction templates (free: offsets within the same tree;
 // reaction: absolute source depth in a polarisation-source tree)
 // Also counts the products with a source present (a wave sum, one atomic per wave).
-__global__ void k_src_m2l(int nent, const int* trow, const int* egrp, const int* grp_seq0, const int* grp_K,
-                          const Tmpl* tmpl, int stride, const int* box_code, const int* box_level,
-                          const long long* grid_off, const int* grid, int* srow, unsigned long long* npairs) {
+// (restrict: the table written never aliases the lookups, so the loads of several
+// template entries can be in flight at once)
+__global__ void k_src_m2l(int nent, const int* __restrict__ trow, const int* __restrict__ egrp,
+                          const int* __restrict__ grp_seq0, const int* __restrict__ grp_K,
+                          const Tmpl* __restrict__ tmpl, int stride, const int* __restrict__ box_code,
+                          const int* __restrict__ box_level, const long long* __restrict__ grid_off,
+                          const int* __restrict__ grid, int* __restrict__ srow, unsigned long long* npairs) {
   int e = blockIdx.x * 256 + threadIdx.x;
   int cnt = 0;
   if (e < nent) {
@@ -2132,10 +2136,17 @@ __global__ void k_src_m2l(int nent, const int* trow, const int* egrp, const int*
     int ix, iy, iz;
     demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
     int s0 = grp_seq0[g], K = grp_K[g];
+    const unsigned n = 1u << l;
+#pragma unroll 4
     for (int kk = 0; kk < K; kk++) {
-      Tmpl T = tmpl[s0 + kk];
-      int sz = T.zabs ? T.dz : iz - T.dz;
-      const int sr = grid_get(grid_off, grid, T.stree, l, ix - T.dx, iy - T.dy, sz);
+      const Tmpl T = tmpl[s0 + kk];
+      const int x = ix - T.dx, y = iy - T.dy, z = T.zabs ? T.dz : iz - T.dz;
+      // the lookup of grid_get without branches (an empty cell or a cell outside the
+      // grid reads entry 0, which always exists, and is then discarded)
+      const long long go = grid_off[T.stree * 9 + l];
+      const bool ok = (unsigned)x < n && (unsigned)y < n && (unsigned)z < n && go >= 0;
+      const int v = grid[ok ? go + morton3(x, y, z) : 0];
+      const int sr = ok ? v : -1;
       srow[(size_t)e * stride + kk] = sr;
       cnt += sr >= 0;
     }
