@@ -1677,6 +1677,42 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     });
   }
   send(ST_P2M, s);
+  // the free-space near field, right after the P2M: the main stream is then busy while
+  // the host builds the operator tables
+  double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
+  qrun([=](hipStream_t ss, const double*, double*) { lk_zero(phi_tp, 2 * (size_t)ntp, ss); });
+  // ---------------- free-space near field (its stage brackets the kernel alone)
+  {
+    std::vector<int> r0, pf;
+    int tot = 0;
+    double krmax = 0.0;  // bound on k r over adjacent leaves: the diagonal of two boxes side by side
+    for (int t = 0; t < ntrees; t++) {
+      const TreeInfo& T = trees[t];
+      if (T.kind != 0) continue;
+      r0.push_back(first_row(t, T.depth));
+      pf.push_back(tot);
+      tot += nbox(t, T.depth);
+      double h = T.S / (double)(1 << T.depth);
+      krmax = std::max(krmax, T.k * 2.0 * h * std::sqrt(3.0));
+    }
+    if (tot) {
+      int* d_r0 = P->upload("p2p_r0", r0, s);
+      int* d_pf = P->upload("p2p_pf", pf, s);
+      // the series form where k r <= 1 on every pair, shorter series where k r <= 1/2
+      rep.p2p_series = krmax <= 0.5 ? 2 : (krmax <= 1.0 ? 1 : 0);
+      const int series = rep.p2p_series;
+      sbeg(ST_P2P, s);
+      const int nr0 = (int)r0.size(), ta = P->p2p_ta, ch = P->p2p_ch, f32 = p2p32 ? 1 : 0;
+      unsigned long long* cnt3 = d_cnt + 3;
+      qrun([=](hipStream_t ss, const double*, double*) {
+        lk_p2p_free(nr0, d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, d_grid_off, grid,
+                    px, py, pz, pq, sg, phi_tp, series, ta, ch, f32, cnt3, ss);
+      });
+    } else {
+      sbeg(ST_P2P, s);
+    }
+    send(ST_P2P, s);
+  }
   // ---------------- operators
   // expansion scale exponents of the mixed-precision M2L: c = 2^e, e = round(log2(1/(k h))) per (tree, level)
   std::vector<int> hse((size_t)ntrees * 9, 0);
@@ -1979,43 +2015,6 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }
   send(ST_REACT_EXPAND, s2);
   HIPCHK(hipEventRecord(P->join_ev, s2));
-  // the free-space near field: launched after the operator stream's kernels so
-  // that those are dispatched first (the near field fills the GPU and would
-  // otherwise starve them; the M2L waits for the reaction operators)
-  double* phi_tp = P->dev<double>("phi_tp", 2 * (size_t)ntp);
-  qrun([=](hipStream_t ss, const double*, double*) { lk_zero(phi_tp, 2 * (size_t)ntp, ss); });
-  // ---------------- free-space near field (its stage brackets the kernel alone)
-  {
-    std::vector<int> r0, pf;
-    int tot = 0;
-    double krmax = 0.0;  // bound on k r over adjacent leaves: the diagonal of two boxes side by side
-    for (int t = 0; t < ntrees; t++) {
-      const TreeInfo& T = trees[t];
-      if (T.kind != 0) continue;
-      r0.push_back(first_row(t, T.depth));
-      pf.push_back(tot);
-      tot += nbox(t, T.depth);
-      double h = T.S / (double)(1 << T.depth);
-      krmax = std::max(krmax, T.k * 2.0 * h * std::sqrt(3.0));
-    }
-    if (tot) {
-      int* d_r0 = P->upload("p2p_r0", r0, s);
-      int* d_pf = P->upload("p2p_pf", pf, s);
-      // the series form where k r <= 1 on every pair, shorter series where k r <= 1/2
-      rep.p2p_series = krmax <= 0.5 ? 2 : (krmax <= 1.0 ? 1 : 0);
-      const int series = rep.p2p_series;
-      sbeg(ST_P2P, s);
-      const int nr0 = (int)r0.size(), ta = P->p2p_ta, ch = P->p2p_ch, f32 = p2p32 ? 1 : 0;
-      unsigned long long* cnt3 = d_cnt + 3;
-      qrun([=](hipStream_t ss, const double*, double*) {
-        lk_p2p_free(nr0, d_r0, d_pf, tot, box_start, box_cnt, box_code, box_tree, box_level, d_trees, d_grid_off, grid,
-                    px, py, pz, pq, sg, phi_tp, series, ta, ch, f32, cnt3, ss);
-      });
-    } else {
-      sbeg(ST_P2P, s);
-    }
-    send(ST_P2P, s);
-  }
   // ---------------- GEMM jobs, on a third stream (they need the trees only, and
   // their count readbacks then wait for the job kernels alone, not for the near field)
   hipStream_t sj = P->s3;
