@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -24,6 +25,7 @@
 #include <thread>
 #include <string>
 #include <tuple>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/lfmm.h"
@@ -748,12 +750,33 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
   RIPrep R;
   if (classes.empty()) return R;
   const int p = P->p, Q = 2 * p, NT = P->NT, NL = P->st.L + 1;
-  std::map<std::tuple<double, double, double, double, int, int, double, double, int>, int> key_rg;
+  // rule groups in order of first appearance (a hash map: this bookkeeping runs while
+  // the GPU waits for the operator stream's first kernels)
+  typedef std::tuple<double, double, double, double, int, int, double, double, int> RGKey;
+  struct RGKeyHash {
+    size_t operator()(const RGKey& k) const {
+      size_t h = 1469598103934665603ull;
+      auto mix = [&h](size_t v) { h = (h ^ v) * 1099511628211ull; };
+      const std::hash<double> hd;
+      mix(hd(std::get<0>(k)));
+      mix(hd(std::get<1>(k)));
+      mix(hd(std::get<2>(k)));
+      mix(hd(std::get<3>(k)));
+      mix((size_t)std::get<4>(k));
+      mix((size_t)std::get<5>(k));
+      mix(hd(std::get<6>(k)));
+      mix(hd(std::get<7>(k)));
+      mix((size_t)std::get<8>(k));
+      return h;
+    }
+  };
+  std::unordered_map<RGKey, int, RGKeyHash> key_rg;
+  key_rg.reserve(classes.size());
   std::vector<RGDesc> rgs;
   int Ntot = 0, Ftot = 0;
   for (auto& C : classes) {
-    auto key = std::make_tuple(C.rule.b, C.rule.T0, C.rule.hn, C.rule.hf, C.rule.nnear, C.rule.nfar, C.rho,
-                               C.rule.wmax, C.rule.kg);
+    const RGKey key(C.rule.b, C.rule.T0, C.rule.hn, C.rule.hf, C.rule.nnear, C.rule.nfar, C.rho, C.rule.wmax,
+                    C.rule.kg);
     auto it = key_rg.find(key);
     int nn = rule_nodes(C.rule);
     if (it == key_rg.end()) {
@@ -773,21 +796,26 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
   }
   // stacks: classes with the same rule group and source layer, at most SC_GMAX
   // of them and three target layers each
+  // (rule group, source layer) in ascending order, each with its classes by target
+  // layer and then by index: one sort of (rg_off, ls, lt, class) entries
   const int NTILE = (P->NC + 15) / 16;
-  std::map<std::pair<int, int>, std::vector<int>> by_rg_ls;
-  for (int c = 0; c < (int)classes.size(); c++) by_rg_ls[{classes[c].rg_off, classes[c].ls}].push_back(c);
+  std::vector<std::array<int, 4>> ord(classes.size());
+  for (int c = 0; c < (int)classes.size(); c++) ord[c] = {classes[c].rg_off, classes[c].ls, classes[c].lt, c};
+  std::sort(ord.begin(), ord.end());
   std::vector<SCDesc> scs;
   std::vector<int> members;
   int nwg = 0;
-  for (auto& kv : by_rg_ls) {
-    std::vector<int>& mem = kv.second;
-    std::stable_sort(mem.begin(), mem.end(), [&](int a, int b) { return classes[a].lt < classes[b].lt; });
+  std::vector<int> mem;
+  for (size_t o0 = 0; o0 < ord.size();) {
+    size_t o1 = o0;
+    mem.clear();
+    while (o1 < ord.size() && ord[o1][0] == ord[o0][0] && ord[o1][1] == ord[o0][1]) mem.push_back(ord[o1++][3]);
     size_t i = 0;
     while (i < mem.size()) {
       SCDesc S;
       memset(&S, 0, sizeof(S));
-      S.rg_off = kv.first.first;
-      S.ls = kv.first.second;
+      S.rg_off = ord[o0][0];
+      S.ls = ord[o0][1];
       S.nn = rule_nodes(classes[mem[i]].rule);
       S.mem0 = (int)members.size();
       while (i < mem.size() && S.G < SC_GMAX) {
@@ -807,6 +835,7 @@ static RIPrep reaction_prep(lfmm_plan_s* P, const char* tag, std::vector<ClassDe
       nwg += (S.NU + 8 * SC_UPW - 1) / (8 * SC_UPW);
       scs.push_back(S);
     }
+    o0 = o1;
   }
   std::string t(tag);
   R.cls = P->upload((t + "_cls").c_str(), classes, up);
