@@ -535,7 +535,8 @@ def main():
             alu = 18.0 * nc * pts / t / 1e12
             rooflines.append({"kernel": kname, "what": "%s, FP64 recurrences and sums" % stage.upper(),
                               "stream": "main", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                              "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                              "traffic": profiled_traffic(kname.split("<")[0], n, args.p, args.leaf, args.seed),
                               "algorithmic_bytes_per_launch": nbytes, "launch_ms": stages[stage],
                               "alu_achieved": alu, "alu_peak": PEAK[("alu", 64)],
                               "alu_frac": alu / PEAK[("alu", 64)]})
