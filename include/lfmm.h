@@ -101,6 +101,7 @@ typedef struct {
                                 lfmm_eval_device_noalloc, the part of the static scratch it took) */
   int64_t p2m_points, p2m_leaves; /* points (particles and polarisation images) and leaves of the P2M */
   int64_t l2p_points, l2p_leaves; /* targets and leaves of the L2P */
+  int m2l_ks;                     /* M2L K-split the evaluation used (waves sharing a 16-target tile) */
 } lfmm_report;
 
 /*
@@ -296,7 +297,7 @@ typedef struct {
 
 /*
  * Time whole evaluations of the given particles (device buffers, as lfmm_eval_device,
- * on the given stream) over the tile shapes the library carries -- M2L K-split 1, 2, 4;
+ * on the given stream) over the tile shapes the library carries -- M2L K-split 1, 2, 4, 8;
  * for FP64 plans the near-field shapes (4, 8, 16 targets per wave step x 128, 256, 512
  * sources per tile) -- one coordinate at a time, and keep the fastest for later
  * evaluations of this plan.  phi receives the last evaluation's potentials.  The shapes
@@ -307,7 +308,7 @@ int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t
                   void* stream, lfmm_tune_report* rep);
 
 /* Set a plan's tile shapes to ones lfmm_autotune carries (for instance those it chose on
- * a representative problem): M2L K-split gemm_ks in {1, 2, 4}; near-field p2p_ta in
+ * a representative problem): M2L K-split gemm_ks in {1, 2, 4, 8}; near-field p2p_ta in
  * {4, 8, 16} targets per wave step and p2p_ch in {128, 256, 512} sources per tile.
  * Later evaluations use them; LFMM_EINVAL for other values. */
 int lfmm_set_tiles(lfmm_plan_t* plan, int gemm_ks, int p2p_ta, int p2p_ch);

@@ -397,7 +397,7 @@ struct lfmm_plan_s {
   int reuse_ops = 0;  // 1: keep the operators of the last evaluation when its trees are the same
   std::string last_opsig;  // what those operators were generated from
   int prec_parts;  // which stages the mixed path runs in FP32: 1 near field, 2 M2L (both by default)
-  int gemm_ks;   // M2L GEMM: waves sharing a 16-target tile (0: 4)
+  int gemm_ks;   // M2L GEMM: waves sharing a 16-target tile, 1, 2, 4 or 8 (0: 4)
   int p2p_ta;    // near field: targets per wave step (64 / p2p_ta sources)
   int p2p_ch;    // near field: sources per LDS tile
   double kmax;
@@ -650,7 +650,7 @@ int plan_params(int L, const double* d, const double* k, int p, int leaf_max, co
   if (const char* e = getenv("LFMM_P2P_CH")) P->p2p_ch = atoi(e);
   if (const char* e = getenv("LFMM_GEMM_KS")) {  // tile-shape override for tuning runs
     int v = atoi(e);
-    if (v == 1 || v == 2 || v == 4) P->gemm_ks = v;
+    if (v == 1 || v == 2 || v == 4 || v == 8) P->gemm_ks = v;
   }
   if (const char* e = getenv("LFMM_FAR_CAP")) P->far_cap = atof(e);
   if (const char* e = getenv("LFMM_FAR_GROW")) P->far_grow = atof(e);
@@ -2184,11 +2184,19 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   std::vector<GBlock> b_m2m, b_l2l, b_m2l;
   std::vector<int> gs_m2m, gs_l2l, gs_m2l, bf_m2m, bc_m2m, bf_l2l, bc_l2l, bf_m2l, bc_m2l;
   // M2L: four waves share each 16-target tile and split its operator sequence
-  // (fastest on both shallow and deep trees)
+  // (fastest on both shallow and deep trees); eight, in workgroups of 512 threads,
+  // where the 16-target tiles are too few to fill the GPU twice over, so that the
+  // longest lists (reaction tiles of several hundred operators) end sooner
   // (a larger split where one wave's operator list would not fit the CU's LDS)
-  int ks_m2l = P->gemm_ks > 0 ? P->gemm_ks : 4;
+  int ks_m2l = P->gemm_ks;
+  if (ks_m2l <= 0) {
+    int64_t tiles = 0;
+    for (int g = 0; g < ng_m2l; g++) tiles += (c_m2l[g] + 15) / 16;
+    ks_m2l = tiles <= 2 * 256 ? 8 : 4;
+  }
   while (ks_m2l < 4 && lk_m2l_lds_bytes(kmax_m2l, ks_m2l) > lk_m2l_lds_max()) ks_m2l *= 2;
   if (lk_m2l_lds_bytes(kmax_m2l, ks_m2l) > lk_m2l_lds_max()) throw Fail{LFMM_ENOTSUP};
+  rep.m2l_ks = ks_m2l;
   // M2M: the waves of a 16-target tile split each parent's eight child operators
   // (a level's parents alone give too few 64-target blocks to fill the GPU)
   static const int ks_m2m = [] {  // tuning override: 1, 2 or 4
@@ -2197,7 +2205,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   }();
   build_blocks(c_m2m, g_m2m, b_m2m, gs_m2m, bf_m2m, bc_m2m, lv_m2m, 9, 64 / ks_m2m);
   build_blocks(c_l2l, g_l2l, b_l2l, gs_l2l, bf_l2l, bc_l2l, lv_l2l, 9, 64);
-  build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1, 64 / ks_m2l);
+  // (a 16-target tile per workgroup of four waves at K-split 4, of eight at 8)
+  build_blocks(c_m2l, g_m2l, b_m2l, gs_m2l, bf_m2l, bc_m2l, {}, 1, ks_m2l == 8 ? 16 : 64 / ks_m2l);
   int ne_m2m = ng_m2m ? gs_m2m[ng_m2m] : 0, ne_l2l = ng_l2l ? gs_l2l[ng_l2l] : 0,
       ne_m2l = ng_m2l ? gs_m2l[ng_m2l] : 0;
   int64_t m2l_slots = 0;
@@ -3351,7 +3360,7 @@ int lfmm_mlp_forward_backward(int B, int nin, int width, int nhidden, int nout, 
 
 int lfmm_set_tiles(lfmm_plan_t* plan, int gemm_ks, int p2p_ta, int p2p_ch) {
   if (!plan) return LFMM_EINVAL;
-  if (gemm_ks != 1 && gemm_ks != 2 && gemm_ks != 4) return LFMM_EINVAL;
+  if (gemm_ks != 1 && gemm_ks != 2 && gemm_ks != 4 && gemm_ks != 8) return LFMM_EINVAL;
   if (p2p_ta != 4 && p2p_ta != 8 && p2p_ta != 16) return LFMM_EINVAL;
   if (p2p_ch != 128 && p2p_ch != 256 && p2p_ch != 512) return LFMM_EINVAL;
   plan->gemm_ks = gemm_ks;
@@ -3389,7 +3398,7 @@ int lfmm_autotune(lfmm_plan_t* plan, int64_t n, const double* xyz, const int32_t
   if (rc != LFMM_OK) return rc;
   R.ms_default = best;
   int bks = ks0, bta = ta0, bch = ch0;
-  for (int ks : {1, 2, 4}) {
+  for (int ks : {1, 2, 4, 8}) {
     if (ks == ks0) continue;
     plan->gemm_ks = ks;
     double ms;

@@ -1588,7 +1588,7 @@ __device__ __forceinline__ void m2l_store(const GBlock& bd, const int* trow, dou
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, col = lane & 15, kr = lane >> 4;
   const int cg = wave / KS, kw = wave % KS;
   if constexpr (KS > 1) {
-    __shared__ double red[4][8][64];
+    __shared__ double red[KS > 4 ? KS : 4][8][64];
 #pragma unroll
     for (int rt = 0; rt < NRT + XR; rt++) {
       if (kw > 0) {
@@ -1651,7 +1651,7 @@ __device__ __forceinline__ void m2l_store(const GBlock& bd, const int* trow, dou
   }
 }
 template <int NRT, int XR, int KS>
-__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_m2l_gemm32(const GBlock* blocks, const int* seq, const int* trow,
+__global__ __launch_bounds__(KS == 8 ? 512 : 256, KS == 8 ? 1 : 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_m2l_gemm32(const GBlock* blocks, const int* seq, const int* trow,
                                                        const int* srow, int srow_stride,
                                                        const float2* __restrict__ ops, int opstride2, int NKS,
                                                        const float2* __restrict__ S, double2* D, int NCK, int NC,
@@ -1674,7 +1674,7 @@ __global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) 
 // (two waves per SIMD is the target: at a higher one the scheduler would sink the
 // prefetch loads to their uses to free registers)
 template <int NRT, int XR, int KS>
-__global__ __launch_bounds__(256, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_m2l_gemm64(const GBlock* blocks, const int* seq, const int* trow,
+__global__ __launch_bounds__(KS == 8 ? 512 : 256, KS == 8 ? 1 : 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_m2l_gemm64(const GBlock* blocks, const int* seq, const int* trow,
                                                        const int* srow, int srow_stride,
                                                        const double2* __restrict__ ops, int opstride2, int NKS,
                                                        const double2* __restrict__ S, double2* D, int NCK, int NC,
@@ -1755,7 +1755,7 @@ extern "C" void lk_m2l_gemm_init() {
 #define M2L_ATTR(N, X, K)                                          \
   lim = std::min(lim, m2l_allow_lds(k_m2l_gemm32<N, X, K>));     \
   lim = std::min(lim, m2l_allow_lds(k_m2l_gemm64<N, X, K>));
-#define M2L_ATTR_KS(N, X) M2L_ATTR(N, X, 1) M2L_ATTR(N, X, 2) M2L_ATTR(N, X, 4)
+#define M2L_ATTR_KS(N, X) M2L_ATTR(N, X, 1) M2L_ATTR(N, X, 2) M2L_ATTR(N, X, 4) M2L_ATTR(N, X, 8)
   M2L_ATTR_KS(1, 0) M2L_ATTR_KS(2, 0) M2L_ATTR_KS(3, 1) M2L_ATTR_KS(3, 0) M2L_ATTR_KS(4, 0) M2L_ATTR_KS(5, 1)
   M2L_ATTR_KS(7, 0) M2L_ATTR_KS(8, 0)
 #undef M2L_ATTR_KS
@@ -1768,7 +1768,7 @@ extern "C" void lk_m2l_gemm_init() {
 }
 extern "C" size_t lk_m2l_lds_max() { return g_m2l_lds_max; }
 extern "C" size_t lk_m2l_lds_bytes(int srow_stride, int ks) {
-  return sizeof(int) * 17 * (size_t)((srow_stride + ks - 1) / ks) * 4;
+  return sizeof(int) * 17 * (size_t)((srow_stride + ks - 1) / ks) * (ks == 8 ? 8 : 4);  // every wave's lists
 }
 
 extern "C" void lk_gemm32(int NC, int ks, int nblocks, const GBlock* blocks, const int* seq, const int* trow,
@@ -1777,18 +1777,18 @@ extern "C" void lk_gemm32(int NC, int ks, int nblocks, const GBlock* blocks, con
                           hipStream_t s) {
   if (!nblocks) return;
   const int lmax = (srow_stride + ks - 1) / ks;  // a wave lists at most ceil(K / ks) operators
-  const size_t lds = sizeof(int) * 17 * (size_t)lmax * 4;
+  const size_t lds = sizeof(int) * 17 * (size_t)lmax * (ks == 8 ? 8 : 4);  // every wave's lists
   const int nrt = m2l_nrt(NC), xr = m2l_xr(NC);
   const float2* o2 = (const float2*)ops;
   const int os2 = opsz / 2;  // operator stride in float2 (opsz floats per operator)
 #define GEMM32_CASE(N, X, K)                                                                                        \
   if (nrt == N && xr == X && ks == K) {                                                                             \
-    k_m2l_gemm32<N, X, K><<<nblocks, 256, lds, s>>>(blocks, seq, trow, srow, srow_stride, o2, os2, NKS,             \
+    k_m2l_gemm32<N, X, K><<<nblocks, K == 8 ? 512 : 256, lds, s>>>(blocks, seq, trow, srow, srow_stride, o2, os2, NKS,             \
                                                     (const float2*)S, (double2*)D, NCK, NC, box_tree, box_level, se, \
                                                     lmax);                                                          \
     return;                                                                                                         \
   }
-#define GEMM32_KS(N, X) GEMM32_CASE(N, X, 1) GEMM32_CASE(N, X, 2) GEMM32_CASE(N, X, 4)
+#define GEMM32_KS(N, X) GEMM32_CASE(N, X, 1) GEMM32_CASE(N, X, 2) GEMM32_CASE(N, X, 4) GEMM32_CASE(N, X, 8)
   GEMM32_KS(1, 0) GEMM32_KS(2, 0) GEMM32_KS(3, 1) GEMM32_KS(3, 0) GEMM32_KS(4, 0) GEMM32_KS(5, 1) GEMM32_KS(7, 0)
   GEMM32_KS(8, 0)
 #undef GEMM32_KS
@@ -1799,17 +1799,17 @@ extern "C" void lk_m2l_gemm64(int NC, int ks, int nblocks, const GBlock* blocks,
                               const double* S, double* D, int NCK, hipStream_t s) {
   if (!nblocks) return;
   const int lmax = (srow_stride + ks - 1) / ks;  // a wave lists at most ceil(K / ks) operators
-  const size_t lds = sizeof(int) * 17 * (size_t)lmax * 4;
+  const size_t lds = sizeof(int) * 17 * (size_t)lmax * (ks == 8 ? 8 : 4);  // every wave's lists
   const int nrt = m2l_nrt(NC), xr = m2l_xr(NC);
   const double2* o2 = (const double2*)ops;
   const int os2 = opsz / 2;  // operator stride in double2 (opsz doubles per operator)
 #define GEMM64_CASE(N, X, K)                                                                                  \
   if (nrt == N && xr == X && ks == K) {                                                                       \
-    k_m2l_gemm64<N, X, K><<<nblocks, 256, lds, s>>>(blocks, seq, trow, srow, srow_stride, o2, os2, NKS,       \
+    k_m2l_gemm64<N, X, K><<<nblocks, K == 8 ? 512 : 256, lds, s>>>(blocks, seq, trow, srow, srow_stride, o2, os2, NKS,       \
                                                     (const double2*)S, (double2*)D, NCK, NC, lmax);           \
     return;                                                                                                   \
   }
-#define GEMM64_KS(N, X) GEMM64_CASE(N, X, 1) GEMM64_CASE(N, X, 2) GEMM64_CASE(N, X, 4)
+#define GEMM64_KS(N, X) GEMM64_CASE(N, X, 1) GEMM64_CASE(N, X, 2) GEMM64_CASE(N, X, 4) GEMM64_CASE(N, X, 8)
   GEMM64_KS(1, 0) GEMM64_KS(2, 0) GEMM64_KS(3, 1) GEMM64_KS(3, 0) GEMM64_KS(4, 0) GEMM64_KS(5, 1) GEMM64_KS(7, 0)
   GEMM64_KS(8, 0)
 #undef GEMM64_KS

@@ -43,7 +43,7 @@ class Report(ctypes.Structure):
                 ("stage_ms", ctypes.c_double * 24), ("n_react_surrogate", ctypes.c_int64), ("ops_reused", ctypes.c_int),
                 ("n_react_table", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("p2m_points", ctypes.c_int64), ("p2m_leaves", ctypes.c_int64),
-                ("l2p_points", ctypes.c_int64), ("l2p_leaves", ctypes.c_int64)]
+                ("l2p_points", ctypes.c_int64), ("l2p_leaves", ctypes.c_int64), ("m2l_ks", ctypes.c_int)]
 
 
 class BatchReport(ctypes.Structure):
@@ -387,7 +387,7 @@ class Plan:
                     n_react_surrogate=r.n_react_surrogate, ops_reused=r.ops_reused,
                     n_react_table=r.n_react_table, workspace_bytes=r.workspace_bytes,
                     p2m_points=r.p2m_points, p2m_leaves=r.p2m_leaves, l2p_points=r.l2p_points,
-                    l2p_leaves=r.l2p_leaves, stage_ms=stages)
+                    l2p_leaves=r.l2p_leaves, m2l_ks=r.m2l_ks, stage_ms=stages)
 
     def autotune(self, xyz, q, phi, layer=None, stream=None):
         """lfmm_autotune on torch device tensors (as eval_device); returns the tuning report."""

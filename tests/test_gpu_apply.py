@@ -166,20 +166,23 @@ def test_batch_graph_matches_single_and_oracle():
 def test_m2l_split_one_on_long_operator_lists(precision):
     """M2L K-split 1 on a problem whose reaction groups list the most operators (every
     source slab occupied, reaction depth 6): one wave holds a target tile's whole list
-    in LDS (above 64 KB).  Same potentials as split 4 up to summation order."""
+    in LDS (above 64 KB).  K-split 8 there: eight waves of a 512-thread workgroup share
+    each tile's list.  Same potentials as split 4 up to summation order."""
     import torch
     lf = _lfmm()
     probs = W.batch_three_layer(seed=3)
     w = probs[int(np.argmin([len(v["x"]) for v in probs]))]
     xyz, q = _dev(w)
     out = {}
-    for ks in (1, 4):
+    for ks in (1, 4, 8):
         P = lf.Plan(w["d"], w["k"], p=w["p"], leaf_max=w["leaf"], precision=precision)
         P.set_tiles(ks, 8, 256)
         out[ks] = P.eval_device(xyz, q, torch.empty_like(q))
         torch.cuda.synchronize()
-    a, b = out[1].cpu().numpy(), out[4].cpu().numpy()
-    assert rel(a, b) < (1e-13 if precision == 0 else 1e-6), rel(a, b)
+    b = out[4].cpu().numpy()
+    for ks in (1, 8):
+        a = out[ks].cpu().numpy()
+        assert rel(a, b) < (1e-13 if precision == 0 else 1e-6), (ks, rel(a, b))
 
 
 def test_repeated_batches_on_worker_streams():

@@ -183,6 +183,7 @@ def test_fmm_every_order(p):
     w = W.small_three_layer(n_per_layer=150, seed=13)
     _, ref, rep = _check_fmm(w, p=p, leaf=10)
     assert rep["free_depth"][:3] == [2, 2, 2]  # free-space M2L too, not only the reaction part
+    assert rep["m2l_ks"] == 8  # few tiles: eight waves share each tile's operators
     P = _lfmm().Plan(w["d"], w["k"], p=p, leaf_max=10, precision=1, quad_tol=1e-10)
     phi = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
     e = np.linalg.norm(phi - ref) / np.linalg.norm(ref)
@@ -546,7 +547,7 @@ def test_autotune_keeps_results():
         phi = torch.empty_like(q)
         r = P.autotune(xyz, q, phi)
         torch.cuda.synchronize()
-        assert r["gemm_ks"] in (1, 2, 4) and r["trials"] >= 3 and r["ms_best"] <= r["ms_default"]
+        assert r["gemm_ks"] in (1, 2, 4, 8) and r["trials"] >= 3 and r["ms_best"] <= r["ms_default"]
         after = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
         # a different tile shape changes the summation order only
         assert rel(after, ref) < (1e-13 if prec == 0 else 1e-6)
