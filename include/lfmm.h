@@ -50,7 +50,8 @@ typedef struct {
   double contour_b; /* depth of the deformed Sommerfeld contour (Section 3.5, b): 0.5 */
   int max_depth;    /* largest octree depth, <= 8: 8 */
   double min_gap;   /* smallest allowed particle-to-interface distance: 1e-9 */
-  int profile;      /* 1: record per-stage times (adds stream events): 0 */
+  int profile;      /* 1: record per-stage times (adds stream events); 2: only the M2L, near field,
+                       node sums, P2M and L2P stages: 0 */
   int precision;    /* 0: FP64 throughout.  1: mixed precision -- near field in FP32 and the M2L
                        on FP32 matrix cores (operators and multipole expansions rescaled per
                        level), with the Bessel/Legendre recurrences, the Sommerfeld quadrature,

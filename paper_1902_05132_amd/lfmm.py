@@ -229,7 +229,7 @@ class Plan:
         self.k = _f64(k)
         self.p = int(p)
         self.L = len(self.d)
-        opt = Options(contour_b, max_depth, min_gap, 1 if profile else 0, int(precision), 1 if physical else 0,
+        opt = Options(contour_b, max_depth, min_gap, int(profile), int(precision), 1 if physical else 0,
                       1 if reuse_operators else 0, float(quad_tol), int(quad_max_nodes))
         h = ctypes.c_void_p()
         dptr = self.d.ctypes.data_as(_D) if self.L else None
