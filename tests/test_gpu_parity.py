@@ -191,6 +191,27 @@ def test_fmm_every_order(p):
     assert e < 1e-6 and emax < 1e-6, (e, emax)
 
 
+def test_stage_events_levels():
+    """Stage times: every stage at profile 1, only the roofline stages (M2L, near field,
+    node sums, P2M, L2P) at profile 2, none at 0; the potentials are the same bits."""
+    lf = _lfmm()
+    w = W.small_three_layer(n_per_layer=150, seed=13)
+    out = {}
+    for level in (0, 1, 2):
+        P = lf.Plan(w["d"], w["k"], p=5, leaf_max=10, profile=level)
+        out[level] = P.eval_torch(w["x"], w["y"], w["z"], w["q"])
+        st = P.report()["stage_ms"]
+        light = {"m2l", "p2p_free", "react_mfma", "p2m", "l2p"}
+        if level == 0:
+            assert all(v == 0 for v in st.values()), st
+        elif level == 1:
+            assert st["tree"] > 0 and st["m2l"] > 0 and st["jobs"] > 0, st
+        else:
+            assert all(st[k] > 0 for k in light), st
+            assert all(v == 0 for k, v in st.items() if k not in light), st
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
 def _cube(n, side, centre, seed):
     rng = np.random.default_rng(seed)
     pts = centre + side * (rng.random((n, 3)) - 0.5)
