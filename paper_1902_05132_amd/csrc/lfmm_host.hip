@@ -541,7 +541,13 @@ struct lfmm_plan_s {
     rb_used = off + bytes;
   }
   void rb_flush(hipStream_t s) {
-    HIPCHK(hipEventRecord(rb_ev, s));
+    rb_mark(s);
+    rb_wait();
+  }
+  // rb_flush in two halves, so that work queued on the stream between them runs while
+  // the host waits for the copies
+  void rb_mark(hipStream_t s) { HIPCHK(hipEventRecord(rb_ev, s)); }
+  void rb_wait() {
     hipError_t e;
     while ((e = hipEventQuery(rb_ev)) == hipErrorNotReady) {
     }
@@ -1547,9 +1553,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     lk_layer_count(n, NL, layer, lcnt, s);
     int* ts1 = P->dev<int>("scan_ts1", lk_scan_tsum_size((long long)NL * nbl));
     lk_scan_excl(lcnt, (long long)NL * nbl, loff, ts1, s);
-    lk_layer_scatter(n, NL, layer, loff, perm, s);
+    lk_layer_scatter(n, NL, layer, loff, perm, inv_perm, s);
   }
-  lk_inverse_perm(n, perm, inv_perm, s);
   int* d_lstart = P->upload("layer_start", layer_start, s);
   TreeInfo* d_trees = P->upload("trees", trees, s);
   // ---------------- keys and sort
@@ -1559,24 +1564,38 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* sg = P->dev<int>("sg", ntp);
   double* rec = P->dev<double>("tp_rec", 5 * (size_t)ntp);
   lk_tree_points(ntp, ntrees, d_trees, perm, d_lstart, x, y, z, q, st, keys, vals, rec, s);
-  int tbits = 1;
-  while ((1 << tbits) < ntrees) tbits++;
+  if (ntrees > 96) throw Fail{LFMM_ENOTSUP};  // at most 5 L + 1 trees: never for L <= 16
   {
+    // the points come grouped by tree (the key's top bits), so each tree's run is
+    // sorted on its own on the 24 Morton bits
+    std::vector<int> seg(ntrees + 1);
+    for (int t = 0; t < ntrees; t++) seg[t] = trees[t].pt_off;
+    seg[ntrees] = ntp;
     unsigned* ktmp = P->dev<unsigned>("keys_tmp", ntp);
     int* vtmp = P->dev<int>("vals_tmp", ntp);
-    int* rsw = P->dev<int>("rs_scratch", (size_t)lk_radix_sort_scratch(ntp));
-    lk_radix_sort_pairs(keys, vals, skeys, sg, ktmp, vtmp, ntp, 24 + tbits, 0xffffffffu, rsw, s);
+    int* rsw = P->dev<int>("rs_scratch", (size_t)lk_radix_sort_scratch(ntp, ntrees));
+    if (lk_radix_sort_segs(keys, vals, skeys, sg, ktmp, vtmp, ntp, ntrees, seg.data(), 24, 0xffffffffu, rsw, s))
+      throw Fail{LFMM_ENOTSUP};  // more trees than segments (excluded above)
   }
-  int* occ = P->dev<int>("occ", ntrees * 9);
-  int* slab = P->dev<int>("slab", ntrees * 18);
-  HIPCHK(hipMemsetAsync(occ, 0, sizeof(int) * ntrees * 9, s));
-  HIPCHK(hipMemsetAsync(slab, 0, sizeof(int) * ntrees * 18, s));
-  if (ntrees > 96) throw Fail{LFMM_ENOTSUP};  // at most 5 L + 1 trees: never for L <= 16
+  // fullest cell per (tree, level), then the slab flags: one fill, one readback
+  int* occ = P->dev<int>("occ", ntrees * 27);
+  int* slab = occ + ntrees * 9;
+  lk_fill_int(occ, (size_t)ntrees * 27, 0, s);
   lk_occupancy(ntp, ntrees, skeys, d_trees, P->leaf_max, occ, slab, s);
-  std::vector<int> hocc(ntrees * 9), hslab(ntrees * 18);
-  P->rb_add(hocc.data(), occ, sizeof(int) * ntrees * 9, s);
-  P->rb_add(hslab.data(), slab, sizeof(int) * ntrees * 18, s);
-  P->rb_flush(s);
+  std::vector<int> hos(ntrees * 27);
+  P->rb_add(hos.data(), occ, sizeof(int) * ntrees * 27, s);
+  P->rb_mark(s);
+  // particle data in sorted order (frame coordinates) and each tree point's particle:
+  // they need only the sort, and run while the host reads the occupancy back
+  double* px = P->dev<double>("px", ntp);
+  double* py = P->dev<double>("py", ntp);
+  double* pz = P->dev<double>("pz", ntp);
+  double* pq = P->dev<double>("pq", 2 * (size_t)ntp);
+  lk_gather(ntp, sg, rec, px, py, pz, pq, s);
+  int* tp_orig = P->dev<int>("tp_orig", ntp);
+  lk_point_origin(ntp, ntrees, d_trees, perm, d_lstart, sg, tp_orig, s);
+  P->rb_wait();
+  const std::vector<int> hocc(hos.begin(), hos.begin() + ntrees * 9), hslab(hos.begin() + ntrees * 9, hos.end());
   // depth rule: smallest depth whose fullest cell holds <= leaf_max points
   int Dr = -1;
   for (int t = 0; t < ntrees; t++) {
@@ -1617,16 +1636,18 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   d_trees = P->upload("trees", trees, s);
   // ---------------- boxes
   int nlev = Dmax + 1;
-  int* flags_all = P->dev<int>("flags_all", (size_t)nlev * ntp);
-  int* scan_all = P->dev<int>("scan_all", (size_t)nlev * ntp);
-  int* tb = P->dev<int>("tb", ntrees * 18);
-  HIPCHK(hipMemsetAsync(tb, 0, sizeof(int) * ntrees * 18, s));
-  // box flags of every level, one scan over all levels (global box rows), box ranges
+  const int nbt = lk_box_tiles(ntp);
+  int* box_tcnt = P->dev<int>("box_tcnt", (size_t)nlev * nbt + 1);
+  int* box_toff = P->dev<int>("box_toff", (size_t)nlev * nbt + 1);
+  int* tb = P->dev<int>("tb", ntrees * 18);  // every entry written by lk_tree_box_range_all
+  // boxes opened per tile and level, one scan over all levels (global box rows), box ranges
   if ((size_t)nlev * ntp >= ((size_t)1 << 31)) throw Fail{LFMM_ENOTSUP};
-  int* ts3 = P->dev<int>("scan_ts3", lk_scan_tsum_size((long long)nlev * ntp));
-  lk_box_flags_all(ntp, nlev, skeys, d_trees, flags_all, s);
-  lk_scan_excl(flags_all, (long long)nlev * ntp, scan_all, ts3, s);
-  lk_tree_box_range_all(ntrees, nlev, ntp, d_trees, flags_all, scan_all, tb, s);
+  int* ts3 = P->dev<int>("scan_ts3", lk_scan_tsum_size((long long)nlev * nbt + 1));
+  if (ntp) {
+    lk_box_count(ntp, nlev, skeys, d_trees, box_tcnt, s);
+    lk_scan_excl(box_tcnt, (long long)nlev * nbt + 1, box_toff, ts3, s);
+  }
+  lk_tree_box_range_all(ntrees, nlev, ntp, skeys, d_trees, box_toff, tb, s);
   std::vector<int> htb(ntrees * 18);
   P->rb_add(htb.data(), tb, sizeof(int) * ntrees * 18, s);
   P->rb_flush(s);
@@ -1643,11 +1664,8 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* box_tree = P->dev<int>("box_tree", NR + 1);
   int* box_level = P->dev<int>("box_level", NR + 1);
   int* box_cnt = P->dev<int>("box_cnt", NR + 1);
-  lk_box_fill_all(ntp, nlev, skeys, flags_all, scan_all, d_trees, box_start, box_code, box_tree, box_level, box_cnt,
-                  s);
-  int* d_lvl_off = P->upload("lvl_off", lvl_off, s);
   int* leafrow = P->dev<int>("leafrow", ntp);
-  lk_point_leaf(ntp, skeys, d_trees, flags_all, scan_all, d_lvl_off, leafrow, s);
+  lk_box_fill_all(ntp, nlev, skeys, box_toff, d_trees, box_start, box_code, box_tree, box_level, leafrow, s);
   // dense cell -> row grids
   std::vector<long long> grid_off(ntrees * 9, -1);
   long long gtot = 0;
@@ -1659,15 +1677,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
   int* grid = P->dev<int>("grid", (size_t)gtot);
   lk_fill_int(grid, (size_t)gtot, -1, s);
   long long* d_grid_off = P->upload("grid_off", grid_off, s);
-  lk_grid_fill_all(NR, box_code, box_tree, box_level, d_grid_off, grid, s);
-  // particle data in sorted order, frame coordinates
-  double* px = P->dev<double>("px", ntp);
-  double* py = P->dev<double>("py", ntp);
-  double* pz = P->dev<double>("pz", ntp);
-  double* pq = P->dev<double>("pq", 2 * (size_t)ntp);
-  lk_gather(ntp, sg, rec, px, py, pz, pq, s);
-  int* tp_orig = P->dev<int>("tp_orig", ntp);
-  lk_point_origin(ntp, ntrees, d_trees, perm, d_lstart, sg, tp_orig, s);
+  lk_grid_fill_all(NR, box_start, box_code, box_tree, box_level, d_trees, d_grid_off, grid, box_cnt, s);
   P->apply_ntp = ntp;
   P->apply_orig = tp_orig;
   P->apply_pq = pq;
@@ -2166,7 +2176,7 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
     while ((1LL << nbits) <= kend) nbits++;
     unsigned* kt = P->dev<unsigned>((t + "_ktmp").c_str(), NR + 1);
     int* vt = P->dev<int>((t + "_vtmp").c_str(), NR + 1);
-    int* rsw = P->dev<int>((t + "_rs").c_str(), (size_t)lk_radix_sort_scratch(NR));
+    int* rsw = P->dev<int>((t + "_rs").c_str(), (size_t)lk_radix_sort_scratch(NR, 1));
     lk_radix_sort_pairs((const unsigned*)J.gid, J.rowid, (unsigned*)J.sgid, J.srowid, kt, vt, NR, nbits,
                         (unsigned)((1LL << nbits) - 1), rsw, sj);
     if (mode == 2) lk_m2l_key_to_group(NR, J.sgid, sj);

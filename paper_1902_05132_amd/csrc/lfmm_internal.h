@@ -128,21 +128,18 @@ void lk_set_gl(const double* x, const double* w);
 void lk_zero(double* p, size_t n, hipStream_t s);
 void lk_fill_int(int* p, size_t n, int v, hipStream_t s);
 // stable partition by layer: per-block counts cnt[l * nb + b] (nb = ceil(n / 256)),
-// then, with off = their exclusive scan, perm[slot] = particle
+// then, with off = their exclusive scan, perm[slot] = particle and inv[particle] = slot
 void lk_layer_count(int n, int NL, const int* layer, int* cnt, hipStream_t s);
-void lk_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm, hipStream_t s);
+void lk_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm, int* inv, hipStream_t s);
 void lk_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out, hipStream_t s);
 void lk_classify(int n, const double* x, const double* y, const double* z, const int* lin, int* lout, Stack st,
                  double* partial, int nblocks, hipStream_t s);
 void lk_reduce_stats(int nblocks, int nl, const double* partial, double* stats, hipStream_t s);
-void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s);
 void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
                     const double* x, const double* y, const double* z, const double* q, Stack st, unsigned* keys,
                     int* vals, double* rec, hipStream_t s);
 void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees, int leaf_max, int* occ,
                   int* slab, hipStream_t s);
-void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all, const int* scan_all,
-                   const int* lvl_off, int* leafrow, hipStream_t s);
 void lk_gather(int ntp, const int* sg, const double* rec, double* px, double* py, double* pz, double* pq,
                hipStream_t s);
 void lk_point_origin(int ntp, int ntrees, const TreeInfo* trees, const int* perm, const int* layer_start,
@@ -230,23 +227,31 @@ void lk_gather_rows(int nrows, const int* idx, int ncol, int esz, const void* sr
 void lk_sur_norm(long n, int nout, float* T, const float* mu, const float* sd, hipStream_t s);
 void lk_sur_features(int n, const int* combo, const double* h, int nin, int c0, double lh0, double lh1,
                      unsigned short* X, hipStream_t s);
-void lk_box_flags_all(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* flags_all, hipStream_t s);
-void lk_tree_box_range_all(int ntrees, int nlev, int ntp, const TreeInfo* trees, const int* flags_all,
-                           const int* scan_all, int* tb, hipStream_t s);
-void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_all, const int* scan_all,
-                     const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level, int* box_cnt,
-                     hipStream_t s);
-void lk_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
-                      const long long* grid_off, int* grid, hipStream_t s);
+// box numbering: per tile of points and level the boxes opened there (lk_box_tiles(ntp)
+// tiles; cnt holds nlev * tiles + 1 ints), the exclusive scan of those counts gives
+// the tiles' first rows (off), from which the ranges and the box records follow
+int lk_box_tiles(int ntp);
+void lk_box_count(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* cnt, hipStream_t s);
+void lk_tree_box_range_all(int ntrees, int nlev, int ntp, const unsigned* skeys, const TreeInfo* trees,
+                           const int* off, int* tb, hipStream_t s);
+void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* off, const TreeInfo* trees, int* box_start,
+                     int* box_code, int* box_tree, int* box_level, int* leafrow, hipStream_t s);
+void lk_grid_fill_all(int nrows, const int* box_start, const int* box_code, const int* box_tree,
+                      const int* box_level, const TreeInfo* trees, const long long* grid_off, int* grid,
+                      int* box_cnt, hipStream_t s);
 void lk_m2l_key_to_group(int n, int* key, hipStream_t s);
 // exclusive prefix sum of n ints (out may equal in); tsum: lk_scan_tsum_size(n) ints
 void lk_scan_excl(const int* in, long long n, int* out, int* tsum, hipStream_t s);
 int lk_scan_tsum_size(long long n);
 // stable radix sort of (key, value) pairs on the low nbits bits of min(key, kcap);
-// scratch: lk_radix_sort_scratch(n) ints
-long long lk_radix_sort_scratch(int n);
+// scratch: lk_radix_sort_scratch(n, 1) ints
+long long lk_radix_sort_scratch(int n, int nseg);
 void lk_radix_sort_pairs(const unsigned* kin, const int* vin, unsigned* kout, int* vout, unsigned* ktmp, int* vtmp,
                          int n, int nbits, unsigned kcap, int* scratch, hipStream_t s);
+// the same within each of nseg <= 96 consecutive segments (host offsets, nseg + 1 of
+// them); scratch: lk_radix_sort_scratch(n, nseg) ints; -1 on a bad segment list
+int lk_radix_sort_segs(const unsigned* kin, const int* vin, unsigned* kout, int* vout, unsigned* ktmp, int* vtmp,
+                       int n, int nseg, const int* seg_off, int nbits, unsigned kcap, int* scratch, hipStream_t s);
 // group sizes of ids in [0, ng), added to cnt
 void lk_hist_ids(const int* ids, int n, int ng, int* cnt, hipStream_t s);
 void lk_tab_store(int ncls, const ClassDesc* cls, const double* dadd, const int* slot, Stack st, const double* Iall,

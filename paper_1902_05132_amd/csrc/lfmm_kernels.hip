@@ -228,7 +228,8 @@ __global__ __launch_bounds__(256) void k_layer_count(int n, int NL, const int* l
     cnt[(size_t)l * gridDim.x + blockIdx.x] = wc[0][l] + wc[1][l] + wc[2][l] + wc[3][l];
   }
 }
-__global__ __launch_bounds__(256) void k_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm) {
+__global__ __launch_bounds__(256) void k_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm,
+                                                       int* inv) {
   __shared__ int wc[4][LFMM_MAXL + 1];
   const int i = blockIdx.x * 256 + threadIdx.x, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int my = i < n ? layer[i] : -1;
@@ -244,13 +245,15 @@ __global__ __launch_bounds__(256) void k_layer_scatter(int n, int NL, const int*
     int pos = off[(size_t)my * gridDim.x + blockIdx.x] + rank;
     for (int w = 0; w < wave; w++) pos += wc[w][my];
     perm[pos] = i;
+    inv[i] = pos;
   }
 }
 extern "C" void lk_layer_count(int n, int NL, const int* layer, int* cnt, hipStream_t s) {
   if (n) k_layer_count<<<nblk(n, 256), 256, 0, s>>>(n, NL, layer, cnt);
 }
-extern "C" void lk_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm, hipStream_t s) {
-  if (n) k_layer_scatter<<<nblk(n, 256), 256, 0, s>>>(n, NL, layer, off, perm);
+extern "C" void lk_layer_scatter(int n, int NL, const int* layer, const int* off, int* perm, int* inv,
+                                 hipStream_t s) {
+  if (n) k_layer_scatter<<<nblk(n, 256), 256, 0, s>>>(n, NL, layer, off, perm, inv);
 }
 
 __global__ void k_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out) {
@@ -266,14 +269,6 @@ __global__ void k_dbg_dens(int n, const double* kr, Stack st, int l, int lp, dou
 }
 extern "C" void lk_dbg_dens(int n, const double* kr, Stack st, int l, int lp, double* out, hipStream_t s) {
   if (n) k_dbg_dens<<<nblk(n, 256), 256, 0, s>>>(n, kr, st, l, lp, out);
-}
-
-__global__ void k_inverse_perm(int n, const int* perm, int* inv) {
-  int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) inv[perm[i]] = i;
-}
-extern "C" void lk_inverse_perm(int n, const int* perm, int* inv, hipStream_t s) {
-  if (n) k_inverse_perm<<<nblk(n, 256), 256, 0, s>>>(n, perm, inv);
 }
 
 // ---------------------------------------------------------------------------
@@ -313,33 +308,15 @@ extern "C" void lk_tree_points(int ntp, int ntrees, const TreeInfo* trees, const
                                                  rec);
 }
 
-// end (exclusive) of the run of keys sharing key >> sh, starting at s, within [s, hi):
-// galloping search (steps 1, 2, 4, ... until the prefix changes), then bisection
-// inside the last step, so a run of length r costs O(log r) probes
-__device__ __forceinline__ int run_end(const unsigned* keys, int s, int hi, int sh) {
-  const unsigned pre = keys[s] >> sh;
-  int lo = s, step = 1, probe = s + 1;  // keys[lo] is in the run
-  while (probe < hi && (keys[probe] >> sh) == pre) {
-    lo = probe;
-    step <<= 1;
-    probe = s + step;
-  }
-  int a = lo + 1, b = probe < hi ? probe : hi;  // the run ends in [a, b]
-  while (a < b) {
-    int mid = (a + b) >> 1;
-    if ((keys[mid] >> sh) == pre) a = mid + 1;
-    else b = mid;
-  }
-  return a;
-}
-
 // occupancy[t*9 + l] = fullest cell of tree t at level l, capped at leaf_max + 1 (the
 // depth rule asks only whether it exceeds leaf_max: one probe leaf_max points ahead
 // of a cell's first point answers that); slab flags of reaction trees.
 // A workgroup scans a contiguous segment of the sorted keys and keeps its maxima
 // and flags in LDS (the keys are sorted by tree, so a segment touches few
-// trees); one flush per workgroup then updates the global tables.
-#define OCC_SEG 8192
+// trees); one flush per workgroup then updates the global tables.  A point's two
+// probes (its predecessor and the point leaf_max ahead) serve every level, and a
+// wave whose points all lie in one tree updates each LDS entry once (by ballots).
+#define OCC_SEG 2048
 #define OCC_TMAX 96
 __global__ __launch_bounds__(256) void k_occupancy(int ntp, int ntrees, const unsigned* skeys, const TreeInfo* trees,
                                                    int leaf_max, int* occ, int* slab) {
@@ -347,24 +324,47 @@ __global__ __launch_bounds__(256) void k_occupancy(int ntp, int ntrees, const un
   for (int i = threadIdx.x; i < ntrees * 9; i += 256) s_occ[i] = 0;
   for (int i = threadIdx.x; i < ntrees * 18; i += 256) s_slab[i] = 0;
   __syncthreads();
+  const int lane = threadIdx.x & 63;
   const int seg0 = blockIdx.x * OCC_SEG, seg1 = min(ntp, seg0 + OCC_SEG);
-  for (int s = seg0 + threadIdx.x; s < seg1; s += 256) {
-    unsigned key = skeys[s];
-    int t = (int)(key >> 24);
-    TreeInfo T = trees[t];
-    int hi = T.pt_off + T.npts, pt0 = T.pt_off;
+  for (int b0 = seg0; b0 < seg1; b0 += 256) {
+    // every lane of a wave takes part in the ballots; points past the segment are idle
+    const int s = b0 + threadIdx.x;
+    const bool valid = s < seg1;
+    const unsigned key = valid ? skeys[s] : 0u;
+    const int t = (int)(key >> 24);
+    const TreeInfo& T = trees[t];
+    const int pt0 = T.pt_off, hi = T.pt_off + T.npts;
+    const bool has_prev = valid && s > pt0;
+    const unsigned prev = has_prev ? skeys[s - 1] : 0u;
+    const bool has_far = valid && leaf_max < hi - s;
+    const unsigned far = has_far ? skeys[s + leaf_max] : 0u;
     int ix, iy, iz;
     demorton3(key & 0xFFFFFFu, 8, &ix, &iy, &iz);
+    const int kind = T.kind;
+    const unsigned long long act = __ballot(valid);
+    const int t0 = __shfl(t, act ? __ffsll((long long)act) - 1 : 0);
+    const bool one_tree = __ballot(valid && t != t0) == 0ull;
+    const bool leader = act && lane == __ffsll((long long)act) - 1;
     for (int l = 0; l <= 8; l++) {
-      int sh = 3 * (8 - l);
-      if (s == pt0 || (skeys[s - 1] >> sh) != (key >> sh)) {  // first point of its cell
-        const int v = (leaf_max < hi - s && (skeys[s + leaf_max] >> sh) == (key >> sh)) ? leaf_max + 1 : 1;
-        atomicMax(&s_occ[t * 9 + l], v);
-        if (l >= 1 && T.kind != 0) {
-          int izl = iz >> (8 - l), half = 1 << (l - 1);
-          int hgt = (T.kind == 1) ? izl - half : half - 1 - izl;
-          if (hgt == 0 || hgt == 1) s_slab[(t * 9 + l) * 2 + hgt] = 1;
+      const int sh = 3 * (8 - l);
+      const bool first = valid && (!has_prev || (prev >> sh) != (key >> sh));
+      const bool full = has_far && (far >> sh) == (key >> sh);
+      int hgt = -1;
+      if (l >= 1 && kind != 0) {
+        const int izl = iz >> (8 - l), half = 1 << (l - 1);
+        hgt = (kind == 1) ? izl - half : half - 1 - izl;
+      }
+      if (one_tree) {
+        const unsigned long long bf = __ballot(first), bfull = __ballot(first && full);
+        const unsigned long long b0s = __ballot(first && hgt == 0), b1s = __ballot(first && hgt == 1);
+        if (leader) {
+          if (bf) atomicMax(&s_occ[t0 * 9 + l], bfull ? leaf_max + 1 : 1);
+          if (b0s) s_slab[(t0 * 9 + l) * 2] = 1;
+          if (b1s) s_slab[(t0 * 9 + l) * 2 + 1] = 1;
         }
+      } else if (first) {
+        atomicMax(&s_occ[t * 9 + l], full ? leaf_max + 1 : 1);
+        if (hgt == 0 || hgt == 1) s_slab[(t * 9 + l) * 2 + hgt] = 1;
       }
     }
   }
@@ -379,98 +379,153 @@ extern "C" void lk_occupancy(int ntp, int ntrees, const unsigned* skeys, const T
   if (ntp) k_occupancy<<<(ntp + OCC_SEG - 1) / OCC_SEG, 256, 0, s>>>(ntp, ntrees, skeys, trees, leaf_max, occ, slab);
 }
 
-// run-start flags of the level-l boxes (only for trees of depth >= l)
-// leaf row of every sorted point (flags/scans of all levels stored level-major)
-__global__ void k_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all,
-                             const int* scan_all, const int* lvl_off, int* leafrow) {
-  int s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= ntp) return;
-  int t = skeys[s] >> 24;
-  int D = trees[t].depth;
-  size_t o = (size_t)D * ntp + s;
-  (void)lvl_off;  // the level-major scan already holds global rows
-  leafrow[s] = scan_all[o] + flags_all[o] - 1;
-}
-extern "C" void lk_point_leaf(int ntp, const unsigned* skeys, const TreeInfo* trees, const int* flags_all,
-                               const int* scan_all, const int* lvl_off, int* leafrow, hipStream_t s) {
-  if (ntp) k_point_leaf<<<nblk(ntp, 256), 256, 0, s>>>(ntp, skeys, trees, flags_all, scan_all, lvl_off, leafrow);
-}
-
-
-// All levels at once.  flags_all[l][s] = 1 where sorted point s opens a box of
-// level l (of its tree, if the tree reaches level l); one exclusive scan over the
-// level-major array then numbers the boxes of all levels: scan_all[l][s] is the
-// global row of that box (the rows of level l start at scan_all[l][0]).
-__global__ void k_box_flags_all(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* flags_all) {
-  const int s = blockIdx.x * 256 + threadIdx.x;
-  if (s >= ntp) return;
+// Box numbering.  Sorted point s opens a box of level l (of its tree, if the tree
+// reaches level l) where its key differs from its predecessor's above bit 3 (8 - l);
+// the boxes of all levels are numbered in level-major order (all level-0 boxes, then
+// level 1, ...), each level in point order.  The flags are not stored: one pass
+// counts them per tile of BOX_TILE points and level, one exclusive scan of those
+// counts (level-major) gives each tile's first row per level, and the passes that
+// need rows recount within the tile.
+#define BOX_TILE 2048
+__device__ __forceinline__ bool box_opens(const unsigned* skeys, const TreeInfo* trees, int s, int l) {
   const unsigned key = skeys[s];
-  const unsigned prev = s > 0 ? skeys[s - 1] : 0u;
-  const int D = trees[key >> 24].depth;
-  for (int l = 0; l < nlev; l++) {
-    const int sh = 3 * (8 - l);
-    flags_all[(size_t)l * ntp + s] = (l <= D && (s == 0 || (prev >> sh) != (key >> sh))) ? 1 : 0;
+  if (l > trees[key >> 24].depth) return false;
+  const int sh = 3 * (8 - l);
+  return s == 0 || (skeys[s - 1] >> sh) != (key >> sh);
+}
+// cnt[l * ntiles + tile] = boxes of level l opened in the tile; cnt[nlev * ntiles] = 0
+__global__ __launch_bounds__(256) void k_box_count(int ntp, int nlev, int ntiles, const unsigned* skeys,
+                                                   const TreeInfo* trees, int* cnt) {
+  __shared__ int c[9];
+  const int lane = threadIdx.x & 63, tile = blockIdx.x;
+  if (threadIdx.x < 9) c[threadIdx.x] = 0;
+  __syncthreads();
+  for (int r = 0; r < BOX_TILE / 256; r++) {
+    const int s = tile * BOX_TILE + r * 256 + threadIdx.x;
+    const bool valid = s < ntp;
+    const unsigned key = valid ? skeys[s] : 0u;
+    const unsigned prev = valid && s > 0 ? skeys[s - 1] : 0u;
+    const int D = valid ? trees[key >> 24].depth : -1;
+    for (int l = 0; l < nlev; l++) {
+      const int sh = 3 * (8 - l);
+      const bool f = valid && l <= D && (s == 0 || (prev >> sh) != (key >> sh));
+      const unsigned long long b = __ballot(f);
+      if (lane == 0 && b) atomicAdd(&c[l], __popcll(b));
+    }
   }
+  __syncthreads();
+  if (threadIdx.x < nlev) cnt[(size_t)threadIdx.x * ntiles + tile] = c[threadIdx.x];
+  if (tile == 0 && threadIdx.x == 0) cnt[(size_t)nlev * ntiles] = 0;
 }
-extern "C" void lk_box_flags_all(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* flags_all,
-                                 hipStream_t s) {
-  if (ntp) k_box_flags_all<<<nblk(ntp, 256), 256, 0, s>>>(ntp, nlev, skeys, trees, flags_all);
+extern "C" int lk_box_tiles(int ntp) { return (ntp + BOX_TILE - 1) / BOX_TILE; }
+extern "C" void lk_box_count(int ntp, int nlev, const unsigned* skeys, const TreeInfo* trees, int* cnt,
+                             hipStream_t s) {
+  const int nt = lk_box_tiles(ntp);
+  if (nt && nlev) k_box_count<<<nt, 256, 0, s>>>(ntp, nlev, nt, skeys, trees, cnt);
 }
-// per (tree, level): first box (level-local) and number of boxes
-__global__ void k_tree_box_range_all(int ntrees, int nlev, int ntp, const TreeInfo* trees, const int* flags_all,
-                                     const int* scan_all, int* tb) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= ntrees * nlev) return;
-  const int t = i / nlev, level = i % nlev;
+// global row of the first level-l box opened at or after point pos (pos <= ntp):
+// the tile's first row plus the boxes opened in the tile before pos
+__device__ int box_row_at(const unsigned* skeys, const TreeInfo* trees, const int* off, int ntiles, int l, int pos,
+                          int* red) {
+  const int tile = pos / BOX_TILE, t0 = tile * BOX_TILE;
+  int n = 0;
+  for (int s = t0 + (int)threadIdx.x; s < pos; s += 256) n += box_opens(skeys, trees, s, l) ? 1 : 0;
+  red[threadIdx.x] = n;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const int r = off[(size_t)l * ntiles + tile] + red[0];
+  __syncthreads();
+  return r;
+}
+// per (tree, level < 9): first box (level-local) and number of boxes (zeros past the
+// tree's depth or the last level); one workgroup each
+__global__ __launch_bounds__(256) void k_tree_box_range_all(int ntrees, int nlev, int ntp, const unsigned* skeys,
+                                                            const TreeInfo* trees, const int* off, int* tb) {
+  __shared__ int red[256];
+  const int t = blockIdx.x / 9, level = blockIdx.x % 9;
+  const int ntiles = (ntp + BOX_TILE - 1) / BOX_TILE;
   const TreeInfo T = trees[t];
-  const size_t o = (size_t)level * ntp;
   int first = 0, cnt = 0;
-  if (T.npts > 0 && level <= T.depth) {
-    first = scan_all[o + T.pt_off] - scan_all[o];
-    const int last = T.pt_off + T.npts - 1;
-    cnt = scan_all[o + last] + flags_all[o + last] - scan_all[o + T.pt_off];
+  if (ntp > 0 && T.npts > 0 && level < nlev && level <= T.depth) {
+    const int r0 = box_row_at(skeys, trees, off, ntiles, level, T.pt_off, red);
+    const int r1 = box_row_at(skeys, trees, off, ntiles, level, T.pt_off + T.npts, red);
+    first = r0 - off[(size_t)level * ntiles];
+    cnt = r1 - r0;
   }
-  tb[(t * 9 + level) * 2] = first;
-  tb[(t * 9 + level) * 2 + 1] = cnt;
+  if (threadIdx.x == 0) {
+    tb[(t * 9 + level) * 2] = first;
+    tb[(t * 9 + level) * 2 + 1] = cnt;
+  }
 }
-extern "C" void lk_tree_box_range_all(int ntrees, int nlev, int ntp, const TreeInfo* trees, const int* flags_all,
-                                      const int* scan_all, int* tb, hipStream_t s) {
-  if (ntrees * nlev) k_tree_box_range_all<<<nblk(ntrees * nlev, 256), 256, 0, s>>>(ntrees, nlev, ntp, trees, flags_all, scan_all, tb);
+extern "C" void lk_tree_box_range_all(int ntrees, int nlev, int ntp, const unsigned* skeys, const TreeInfo* trees,
+                                      const int* off, int* tb, hipStream_t s) {
+  if (ntrees) k_tree_box_range_all<<<ntrees * 9, 256, 0, s>>>(ntrees, nlev, ntp, skeys, trees, off, tb);
 }
-__global__ void k_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_all, const int* scan_all,
-                               const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
-                               int* box_cnt) {
-  const int s = blockIdx.x * 256 + threadIdx.x, level = blockIdx.y;
-  if (s >= ntp || level >= nlev) return;
-  const size_t o = (size_t)level * ntp + s;
-  if (!flags_all[o]) return;
-  const unsigned key = skeys[s];
-  const int t = key >> 24, sh = 3 * (8 - level);
-  const int R = scan_all[o];
-  box_start[R] = s;
-  box_code[R] = (int)((key & 0xFFFFFFu) >> sh);
-  box_tree[R] = t;
-  box_level[R] = level;
-  box_cnt[R] = run_end(skeys, s, trees[t].pt_off + trees[t].npts, sh) - s;
+// Box records (first point, Morton code at its level, tree, level) of every box, and
+// each point's leaf row (its box at its tree's depth); one workgroup per (tile,
+// level).  The point counts follow from the next box's first point (k_grid_fill_all).
+__global__ __launch_bounds__(256) void k_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* off,
+                                                      const TreeInfo* trees, int* box_start, int* box_code,
+                                                      int* box_tree, int* box_level, int* leafrow) {
+  __shared__ int wc[4];
+  const int tile = blockIdx.x, level = blockIdx.y, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ntiles = gridDim.x, sh = 3 * (8 - level);
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int run = off[(size_t)level * ntiles + tile];
+  for (int r = 0; r < BOX_TILE / 256; r++) {
+    const int s = tile * BOX_TILE + r * 256 + threadIdx.x;
+    const bool valid = s < ntp;
+    const unsigned key = valid ? skeys[s] : 0u;
+    const int t = key >> 24;
+    const int D = valid ? trees[t].depth : -1;
+    const bool f = valid && level <= D && (s == 0 || (skeys[s - 1] >> sh) != (key >> sh));
+    const unsigned long long b = __ballot(f);
+    if (lane == 0) wc[wave] = __popcll(b);
+    __syncthreads();
+    int R = run + __popcll(b & below);
+    for (int w = 0; w < wave; w++) R += wc[w];
+    if (f) {
+      box_start[R] = s;
+      box_code[R] = (int)((key & 0xFFFFFFu) >> sh);
+      box_tree[R] = t;
+      box_level[R] = level;
+    }
+    if (valid && D == level) leafrow[s] = R + (f ? 1 : 0) - 1;
+    run += wc[0] + wc[1] + wc[2] + wc[3];
+    __syncthreads();
+  }
 }
-extern "C" void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* flags_all, const int* scan_all,
-                                const TreeInfo* trees, int* box_start, int* box_code, int* box_tree, int* box_level,
-                                int* box_cnt, hipStream_t s) {
-  if (ntp && nlev)
-    k_box_fill_all<<<dim3(nblk(ntp, 256), nlev), 256, 0, s>>>(ntp, nlev, skeys, flags_all, scan_all, trees, box_start,
-                                                               box_code, box_tree, box_level, box_cnt);
+extern "C" void lk_box_fill_all(int ntp, int nlev, const unsigned* skeys, const int* off, const TreeInfo* trees,
+                                int* box_start, int* box_code, int* box_tree, int* box_level, int* leafrow,
+                                hipStream_t s) {
+  const int nt = lk_box_tiles(ntp);
+  if (nt && nlev)
+    k_box_fill_all<<<dim3(nt, nlev), 256, 0, s>>>(ntp, nlev, skeys, off, trees, box_start, box_code, box_tree,
+                                                   box_level, leafrow);
 }
-__global__ void k_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
-                                const long long* grid_off, int* grid) {
+// Each box's point count (a box ends where the next box of its tree and level starts,
+// or at the tree's last point) and its row in the dense cell -> row grid.
+__global__ void k_grid_fill_all(int nrows, const int* box_start, const int* box_code, const int* box_tree,
+                                const int* box_level, const TreeInfo* trees, const long long* grid_off, int* grid,
+                                int* box_cnt) {
   const int R = blockIdx.x * 256 + threadIdx.x;
   if (R >= nrows) return;
-  const long long go = grid_off[box_tree[R] * 9 + box_level[R]];
+  const int t = box_tree[R], l = box_level[R];
+  const bool next = R + 1 < nrows && box_tree[R + 1] == t && box_level[R + 1] == l;
+  box_cnt[R] = (next ? box_start[R + 1] : trees[t].pt_off + trees[t].npts) - box_start[R];
+  const long long go = grid_off[t * 9 + l];
   if (go < 0) return;
   grid[go + box_code[R]] = R;
 }
-extern "C" void lk_grid_fill_all(int nrows, const int* box_code, const int* box_tree, const int* box_level,
-                                 const long long* grid_off, int* grid, hipStream_t s) {
-  if (nrows) k_grid_fill_all<<<nblk(nrows, 256), 256, 0, s>>>(nrows, box_code, box_tree, box_level, grid_off, grid);
+extern "C" void lk_grid_fill_all(int nrows, const int* box_start, const int* box_code, const int* box_tree,
+                                 const int* box_level, const TreeInfo* trees, const long long* grid_off, int* grid,
+                                 int* box_cnt, hipStream_t s) {
+  if (nrows)
+    k_grid_fill_all<<<nblk(nrows, 256), 256, 0, s>>>(nrows, box_start, box_code, box_tree, box_level, trees,
+                                                      grid_off, grid, box_cnt);
 }
 
 // tree point records into Morton-sorted order, split into coordinate and charge arrays
@@ -1896,18 +1951,49 @@ extern "C" void lk_scan_excl(const int* in, long long n, int* out, int* tsum, hi
 extern "C" int lk_scan_tsum_size(long long n) { return (int)((n + SCAN_TILE - 1) / SCAN_TILE) + 1; }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of (u32 key, int32 value) pairs, 8 key bits per pass.
-// Per pass: digit counts of every tile of RS_TILE pairs (digit-major), one
-// exclusive scan of the counts (each digit's tiles in order), then a stable
-// scatter.  A tile is taken in rounds of 256 consecutive pairs; within a wave the
-// pairs with the same digit are found by eight ballots and ranked by lane, and the
-// waves' counts are added in wave order, the rounds in order.  The scatter first
-// places the tile's pairs in LDS in digit order, then writes each digit's run to
-// its consecutive global positions.  Keys above kcap sort as kcap (a sentinel of
-// the caller) but keep their value.
+// Stable LSD radix sort of (u32 key, int32 value) pairs, 8 key bits per pass,
+// within segments: the pairs come grouped in consecutive segments (the trees of
+// the particle sort, whose keys differ above the sorted bits) and each segment is
+// sorted on its own, so the bits that tell the segments apart need no pass.
+// Per pass: digit counts of every tile of at most RS_TILE pairs of one segment
+// (segment-major, then digit-major), one exclusive scan of the counts (each
+// segment's digits in order, each digit's tiles in order), then a stable scatter.
+// A tile is taken in rounds of 256 consecutive pairs; within a wave the pairs with
+// the same digit are found by eight ballots and ranked by lane, and the waves'
+// counts are added in wave order, the rounds in order.  The scatter first places
+// the tile's pairs in LDS in digit order, then writes each digit's run to its
+// consecutive global positions.  Keys above kcap sort as kcap (a sentinel of the
+// caller) but keep their value.
 // ---------------------------------------------------------------------------
 #define RS_TILE 4096
 #define RS_ROUNDS (RS_TILE / 256)
+#define RS_MAXSEG 96
+struct RsSegs {
+  int nseg;
+  int tile0[RS_MAXSEG + 1];  // first tile of each segment; tile0[nseg] = all tiles
+  int off[RS_MAXSEG + 1];    // first pair of each segment; off[nseg] = all pairs
+};
+// the workgroup's tile: first pair, end, and where its digit counts sit (digit d at
+// cbase + d * cstride)
+struct RsTile {
+  long long base, end;
+  size_t cbase, cstride;
+};
+__device__ __forceinline__ RsTile rs_tile(const RsSegs& S, int b) {
+  int lo = 0, hi = S.nseg - 1;  // last segment whose first tile is <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (S.tile0[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const int j = b - S.tile0[lo], ntl = S.tile0[lo + 1] - S.tile0[lo];
+  RsTile T;
+  T.base = S.off[lo] + (long long)j * RS_TILE;
+  T.end = T.base + RS_TILE < S.off[lo + 1] ? T.base + RS_TILE : S.off[lo + 1];
+  T.cbase = (size_t)256 * S.tile0[lo] + j;
+  T.cstride = (size_t)ntl;
+  return T;
+}
 __device__ __forceinline__ unsigned rs_digit(unsigned key, unsigned kcap, int shift) {
   return ((key < kcap ? key : kcap) >> shift) & 255u;
 }
@@ -1921,46 +2007,46 @@ __device__ __forceinline__ unsigned long long rs_same(unsigned d, bool valid) {
   }
   return same;
 }
-__global__ __launch_bounds__(256) void k_rs_count(const unsigned* keys, int n, unsigned kcap, int shift, int* cnt,
-                                                  int nb) {
+__global__ __launch_bounds__(256) void k_rs_count(const unsigned* keys, unsigned kcap, int shift, int* cnt,
+                                                  const RsSegs S) {
   __shared__ int h[256];
   const int tid = threadIdx.x, lane = tid & 63;
   const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const RsTile T = rs_tile(S, blockIdx.x);
   h[tid] = 0;
   __syncthreads();
-  const long long base = (long long)blockIdx.x * RS_TILE;
   for (int r = 0; r < RS_ROUNDS; r++) {
-    const long long g = base + r * 256 + tid;
-    const bool valid = g < n;
+    const long long g = T.base + r * 256 + tid;
+    const bool valid = g < T.end;
     const unsigned d = rs_digit(valid ? keys[g] : 0u, kcap, shift);
     const unsigned long long same = rs_same(d, valid);
     if (valid && (same & below) == 0) atomicAdd(&h[d], __popcll(same));
   }
   __syncthreads();
-  cnt[(size_t)tid * nb + blockIdx.x] = h[tid];
+  cnt[T.cbase + tid * T.cstride] = h[tid];
 }
-__global__ __launch_bounds__(256) void k_rs_scatter(const unsigned* kin, const int* vin, int n, unsigned kcap,
-                                                    int shift, const int* cnt, const int* off, int nb,
-                                                    unsigned* kout, int* vout) {
+__global__ __launch_bounds__(256) void k_rs_scatter(const unsigned* kin, const int* vin, unsigned kcap, int shift,
+                                                    const int* cnt, const int* off, unsigned* kout, int* vout,
+                                                    const RsSegs S) {
   __shared__ unsigned sk[RS_TILE];
   __shared__ int sv[RS_TILE];
   __shared__ int lstart[256], run[256], goff[256], sh[256];
   __shared__ int wcnt[4][256];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const RsTile T = rs_tile(S, blockIdx.x);
   // where each digit's pairs start in the tile's digit order, and globally
   int tot;
-  const int mine = cnt[(size_t)tid * nb + blockIdx.x];
+  const int mine = cnt[T.cbase + tid * T.cstride];
   const int ls = block_excl_scan256(mine, sh, &tot);
   lstart[tid] = ls;
   run[tid] = ls;
-  goff[tid] = off[(size_t)tid * nb + blockIdx.x];
-  const long long base = (long long)blockIdx.x * RS_TILE;
+  goff[tid] = off[T.cbase + tid * T.cstride];
   for (int r = 0; r < RS_ROUNDS; r++) {
     for (int w = 0; w < 4; w++) wcnt[w][tid] = 0;
     __syncthreads();
-    const long long g = base + r * 256 + tid;
-    const bool valid = g < n;
+    const long long g = T.base + r * 256 + tid;
+    const bool valid = g < T.end;
     const unsigned key = valid ? kin[g] : 0u;
     const int val = valid ? vin[g] : 0;
     const unsigned d = rs_digit(key, kcap, shift);
@@ -1978,7 +2064,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const unsigned* kin, const i
     run[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
   }
   __syncthreads();
-  const int nt = (int)(n - base < RS_TILE ? n - base : RS_TILE);
+  const int nt = (int)(T.end - T.base);
   for (int i = tid; i < nt; i += 256) {
     const unsigned key = sk[i];
     const unsigned d = rs_digit(key, kcap, shift);
@@ -1987,16 +2073,31 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const unsigned* kin, const i
     vout[gp] = sv[i];
   }
 }
-// Scratch (ints) the sort needs for n pairs: the counts, their offsets and the scan's tile sums.
-extern "C" long long lk_radix_sort_scratch(int n) {
-  const int nb = (n + RS_TILE - 1) / RS_TILE;
-  return 2LL * 256 * nb + lk_scan_tsum_size(256LL * nb);
+// Scratch (ints) the sort needs for n pairs in nseg segments: the counts, their
+// offsets and the scan's tile sums.
+extern "C" long long lk_radix_sort_scratch(int n, int nseg) {
+  const long long nt = (n + RS_TILE - 1) / RS_TILE + (nseg > 1 ? nseg : 1);
+  return 2LL * 256 * nt + lk_scan_tsum_size(256LL * nt);
 }
-// Sorts kin/vin (left unchanged) into kout/vout, with ktmp/vtmp (all n long) between passes.
-extern "C" void lk_radix_sort_pairs(const unsigned* kin, const int* vin, unsigned* kout, int* vout, unsigned* ktmp,
-                                    int* vtmp, int n, int nbits, unsigned kcap, int* scratch, hipStream_t s) {
-  if (n <= 0) return;
-  const int nb = (n + RS_TILE - 1) / RS_TILE;
+// Sorts kin/vin (left unchanged) into kout/vout, with ktmp/vtmp (all n long) between
+// passes; each of the nseg segments [seg_off[i], seg_off[i+1]) (host array;
+// seg_off[0] = 0, seg_off[nseg] = n, nondecreasing) is sorted on its own.
+extern "C" int lk_radix_sort_segs(const unsigned* kin, const int* vin, unsigned* kout, int* vout, unsigned* ktmp,
+                                  int* vtmp, int n, int nseg, const int* seg_off, int nbits, unsigned kcap,
+                                  int* scratch, hipStream_t s) {
+  if (n <= 0) return 0;
+  if (nseg < 1 || nseg > RS_MAXSEG || seg_off[0] != 0 || seg_off[nseg] != n) return -1;
+  RsSegs S;
+  S.nseg = nseg;
+  S.tile0[0] = 0;
+  for (int i = 0; i < nseg; i++) {
+    const int len = seg_off[i + 1] - seg_off[i];
+    if (len < 0) return -1;
+    S.off[i] = seg_off[i];
+    S.tile0[i + 1] = S.tile0[i] + (len + RS_TILE - 1) / RS_TILE;
+  }
+  S.off[nseg] = n;
+  const int nb = S.tile0[nseg];
   const int passes = nbits <= 0 ? 1 : (nbits + 7) / 8;
   int* cnt = scratch;
   int* off = scratch + 256LL * nb;
@@ -2007,12 +2108,19 @@ extern "C" void lk_radix_sort_pairs(const unsigned* kin, const int* vin, unsigne
     const bool to_out = ((passes - 1 - pss) & 1) == 0;
     unsigned* kd = to_out ? kout : ktmp;
     int* vd = to_out ? vout : vtmp;
-    k_rs_count<<<nb, 256, 0, s>>>(ks, n, kcap, 8 * pss, cnt, nb);
+    k_rs_count<<<nb, 256, 0, s>>>(ks, kcap, 8 * pss, cnt, S);
     lk_scan_excl(cnt, 256LL * nb, off, tsum, s);
-    k_rs_scatter<<<nb, 256, 0, s>>>(ks, vs, n, kcap, 8 * pss, cnt, off, nb, kd, vd);
+    k_rs_scatter<<<nb, 256, 0, s>>>(ks, vs, kcap, 8 * pss, cnt, off, kd, vd, S);
     ks = kd;
     vs = vd;
   }
+  return 0;
+}
+// The whole array as one segment.
+extern "C" void lk_radix_sort_pairs(const unsigned* kin, const int* vin, unsigned* kout, int* vout, unsigned* ktmp,
+                                    int* vtmp, int n, int nbits, unsigned kcap, int* scratch, hipStream_t s) {
+  const int so[2] = {0, n};
+  lk_radix_sort_segs(kin, vin, kout, vout, ktmp, vtmp, n, 1, so, nbits, kcap, scratch, s);
 }
 // Sizes of groups of sorted ids in [0, ng) (ids outside are skipped): one LDS
 // histogram per workgroup, added to cnt (zeroed by the caller).
