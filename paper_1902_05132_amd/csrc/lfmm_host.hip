@@ -2268,17 +2268,20 @@ int eval_impl(lfmm_plan_t* P, int64_t n64, const double* xyz, const int32_t* lay
                         NCK, ss);
     });
   }
+  // mixed precision: rescaled FP32 copy of the multipole expansions (it needs only the
+  // upward pass, so it runs before the wait for the reaction operators; its time is
+  // counted with the upward pass, so that the m2l stage brackets the GEMM alone)
+  float* M32 = nullptr;
+  if (!b_m2l.empty() && m2l32) {
+    M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
+    qrun([=](hipStream_t ss, const double*, double*) { lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, ss); });
+  }
   send(ST_M2M, s);
   // and the reaction operators from here on
   HIPCHK(hipStreamWaitEvent(s, P->join_ev, 0));
   sbeg(ST_M2L, s);
   // ---------------- M2L (every level, free and reaction)
   if (!b_m2l.empty() && m2l32) {
-    // mixed precision: rescaled FP32 copy of the multipole expansions (its time is
-    // counted with the upward pass, so that the m2l stage brackets the GEMM alone)
-    float* M32 = P->dev<float>("M32", (size_t)NR * NCK * 2);
-    qrun([=](hipStream_t ss, const double*, double*) { lk_m_to_f32(NR, NCK, NC, box_tree, box_level, d_sc, M, M32, ss); });
-    sbeg(ST_M2L, s);
     const int nb = (int)b_m2l.size();
     const int* srow = J_m2l.srowid;
     qrun([=](hipStream_t ss, const double*, double*) {

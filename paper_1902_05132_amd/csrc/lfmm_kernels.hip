@@ -2342,9 +2342,9 @@ __device__ __forceinline__ double rsqrt_nr(double r2) {
   return y;
 }
 // h0(x) = sin(x)/x - i cos(x)/x for x = k r, from u = x^2 > 0 and y = 1/x (hr + i hi).
-// FORM 1: series of sin(x)/x (10 terms) and cos(x) (11 terms) for x <= 1; FORM 2: 7 and
-// 8 terms for x <= 1/2 (the first dropped terms, x^14/15! and x^16/16!, are below 4.9e-17
-// and 8.3e-19 relative); FORM 0: sincos.  The series' signs are in their coefficients.
+// FORM 1: series of sin(x)/x (10 terms) and cos(x) (11 terms) for x <= 1; FORM 2:
+// fitted polynomials of degree 5 in u for x <= 1/2; FORM 0: sincos.  The signs are in
+// the coefficients.
 template <int FORM>
 __device__ __forceinline__ void h0_pair(double u, double y, double& hr, double& hi) {
   if constexpr (FORM > 0) {
@@ -2356,29 +2356,40 @@ __device__ __forceinline__ void h0_pair(double u, double y, double& hr, double& 
     static_assert(FORM == 1 || FORM == 2, "series forms 1 and 2");
     double ps, pc;
     if constexpr (FORM == 1) {
+      // Taylor series where x <= 1
       ps = fma(s9, u, s8);
       ps = fma(ps, u, s7);
       ps = fma(ps, u, s6);
+      ps = fma(ps, u, s5);
+      ps = fma(ps, u, s4);
+      ps = fma(ps, u, s3);
+      ps = fma(ps, u, s2);
+      ps = fma(ps, u, s1);
+      ps = fma(ps, u, 1.0);
       pc = fma(c10, u, c9);
       pc = fma(pc, u, c8);
       pc = fma(pc, u, c7);
+      pc = fma(pc, u, c6);
+      pc = fma(pc, u, c5);
+      pc = fma(pc, u, c4);
+      pc = fma(pc, u, c3);
+      pc = fma(pc, u, c2);
+      pc = fma(pc, u, c1);
+      pc = fma(pc, u, 1.0);
     } else {
-      ps = s6;
-      pc = c7;
+      // where x <= 1/2: polynomials of degree 5 in u fitted on [0, 1/4] (least squares
+      // on Chebyshev nodes; largest error 1.9e-17 for sin(x)/x, 2.5e-16 for cos x)
+      ps = fma(-2.493193700544346251e-8, u, 2.7556981496282984831e-6);
+      ps = fma(ps, u, -1.9841269403639427146e-4);
+      ps = fma(ps, u, 8.3333333330769671683e-3);
+      ps = fma(ps, u, -1.6666666666666117393e-1);
+      ps = fma(ps, u, 9.9999999999999998093e-1);
+      pc = fma(-2.740115064302131569e-7, u, 2.4801148458800499824e-5);
+      pc = fma(pc, u, -1.3888888320265660306e-3);
+      pc = fma(pc, u, 4.1666666663335758195e-2);
+      pc = fma(pc, u, -4.9999999999992863579e-1);
+      pc = fma(pc, u, 9.9999999999999975224e-1);
     }
-    ps = fma(ps, u, s5);
-    ps = fma(ps, u, s4);
-    ps = fma(ps, u, s3);
-    ps = fma(ps, u, s2);
-    ps = fma(ps, u, s1);
-    ps = fma(ps, u, 1.0);
-    pc = fma(pc, u, c6);
-    pc = fma(pc, u, c5);
-    pc = fma(pc, u, c4);
-    pc = fma(pc, u, c3);
-    pc = fma(pc, u, c2);
-    pc = fma(pc, u, c1);
-    pc = fma(pc, u, 1.0);
     hr = ps;       // sin(x)/x
     hi = -pc * y;  // -cos(x)/x
   } else {
@@ -2413,7 +2424,10 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
   demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
   const int s0 = box_start[R], nt = box_cnt[R];
   if (tid < 27) {
-    int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+    // the own leaf (offset 0, 0, 0) first: only its sources can coincide with a target
+    // (coincident points share a leaf), so only they need the select that drops them
+    const int o = tid == 0 ? 13 : (tid <= 13 ? tid - 1 : tid);
+    int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
     int Rn = grid_get(grid_off, grid, t, l, ix + dx, iy + dy, iz + dz);
     nb_start[tid] = Rn >= 0 ? box_start[Rn] : 0;
     nb_pre[tid + 1] = Rn >= 0 ? box_cnt[Rn] : 0;
@@ -2462,13 +2476,14 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
         const int tr = tv ? ti : 0;
         const double x0 = t_x[tr], y0 = t_y[tr], z0 = t_z[tr];
         double ax = 0.0, ay = 0.0;
-#pragma unroll 2
-        for (int j = b; j < nch; j += TB) {
+        // one pair: SELF where the source may be the target itself (its own leaf)
+        auto pair = [&](int j, auto self_tag) {
+          constexpr bool SELF = decltype(self_tag)::value;
           const double* rec = s_src + 5 * j;
           double dx = x0 - rec[0], dy = y0 - rec[1], dz = z0 - rec[2];
           double u = fma(dx, dx, fma(dy, dy, dz * dz));  // (k r)^2
-          bool ok = u > 0.0;  // the target itself (and coincident points) contribute nothing
-          const double us = ok ? u : 1.0;  // (a select of the input keeps the loop free of branches)
+          const bool ok = !SELF || u > 0.0;  // the target itself (and coincident points) contribute nothing
+          const double us = ok ? u : 1.0;    // (a select of the input keeps the loop free of branches)
           double hr, hi;
           h0_pair<FORM>(us, rsqrt_nr(us), hr, hi);  // 1 / (k r) from the refined rsq
           hr = ok ? hr : 0.0;
@@ -2476,7 +2491,14 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
           double qr = rec[3], qi = rec[4];
           ax = fma(qr, hr, fma(-qi, hi, ax));
           ay = fma(qr, hi, fma(qi, hr, ay));
-        }
+        };
+        // the chunk's sources of the own leaf (the first nt of the concatenation), then the rest
+        const int nown = nt - base < nch ? (nt - base > 0 ? nt - base : 0) : nch;
+        int j = b;
+#pragma unroll 2
+        for (; j < nown; j += TB) pair(j, std::true_type{});
+#pragma unroll 2
+        for (; j < nch; j += TB) pair(j, std::false_type{});
 #pragma unroll
         for (int m = TB / 2; m >= 1; m >>= 1) {
           ax += __shfl_xor(ax, m, 64);
@@ -2504,10 +2526,14 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
 // summed in FP32, and each target's sum is accumulated in FP64.  With coordinates in
 // units of 1/k, r2 is (k r)^2 and the reciprocal square root gives 1/(k r) directly.
 // A source is one 32-byte LDS record (x, y, z, xl | yl, zl, Re q, Im q): two 16-byte
-// reads at offsets the compiler folds into the instruction.  NS: the number of terms of
-// the series of sin(x)/x and cos(x), x = k r (v_rsq_f32 for 1/x): 7 where x <= 1 on
-// every pair (truncation below 1e-11), 5 where x <= 1/2 (the next terms, x^10/11! and
-// x^10/10!, are below 2.5e-11 and 2.7e-10, 3.1e-10 of cos x); 0 takes sincosf.
+// reads at offsets the compiler folds into the instruction.  NS selects how sin(x)/x and
+// cos(x), x = k r, are evaluated (v_rsq_f32 for 1/x): 7, their Taylor series to seven
+// terms where x <= 1 on every pair (truncation below 1e-11); 5, where x <= 1/2,
+// polynomials of degree 3 in u = x^2 fitted on [0, 1/4] by Chebyshev interpolation
+// (largest error 8.4e-11 for sin(x)/x and 7.5e-10 for cos x, against 6e-8 for one
+// FP32 rounding); 0 takes sincosf.  The neighbour leaves are taken with the target's
+// own leaf first: only its sources can coincide with a target (coincident points
+// share a leaf), so only they go through the select that drops coincident pairs.
 template <int NS, int TA, int CH>
 __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row0, const int* seg_prefix,
                                                     const int* box_start, const int* box_cnt, const int* box_code,
@@ -2531,7 +2557,8 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
   demorton3((unsigned)box_code[R], l, &ix, &iy, &iz);
   const int s0 = box_start[R], nt = box_cnt[R];
   if (tid < 27) {
-    int dx = tid / 9 - 1, dy = (tid / 3) % 3 - 1, dz = tid % 3 - 1;
+    const int o = tid == 0 ? 13 : (tid <= 13 ? tid - 1 : tid);  // the own leaf (offset 0, 0, 0) first
+    int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
     int Rn = grid_get(grid_off, grid, t, l, ix + dx, iy + dy, iz + dz);
     nb_start[tid] = Rn >= 0 ? box_start[Rn] : 0;
     nb_pre[tid + 1] = Rn >= 0 ? box_cnt[Rn] : 0;
@@ -2585,39 +2612,45 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
         const int tr = tv ? ti : 0;
         const float x0 = t_x[tr], y0 = t_y[tr], z0 = t_z[tr], x0l = t_xl[tr], y0l = t_yl[tr], z0l = t_zl[tr];
         float ax = 0.f, ay = 0.f;
-#pragma unroll 4
-        for (int j = b; j < nch; j += TB) {
+        // one pair: SELF where the source may be the target itself (its own leaf)
+        auto pair = [&](int j, auto self_tag) {
+          constexpr bool SELF = decltype(self_tag)::value;
           const float4 A = s_src[2 * j], B = s_src[2 * j + 1];
           float dx = (x0 - A.x) + (x0l - A.w), dy = (y0 - A.y) + (y0l - B.x), dz = (z0 - A.z) + (z0l - B.y);
           float u = fmaf(dx, dx, fmaf(dy, dy, dz * dz));  // (k r)^2
-          const bool ok = u > 0.f;                        // coincident points contribute nothing
+          const bool ok = !SELF || u > 0.f;               // coincident points contribute nothing
           const float y = ok ? __builtin_amdgcn_rsqf(u) : 0.f;  // 1 / (k r)
           float hr, hi;
           if constexpr (NS > 0) {
-            // sin(x)/x and cos(x) as polynomials in u = x^2, the signs in the coefficients
-            constexpr float s1 = (float)-inv_fact(3), s2 = (float)inv_fact(5), s3 = (float)-inv_fact(7),
-                            s4 = (float)inv_fact(9), s5 = (float)-inv_fact(11), s6 = (float)inv_fact(13);
-            constexpr float c1 = (float)-inv_fact(2), c2 = (float)inv_fact(4), c3 = (float)-inv_fact(6),
-                            c4 = (float)inv_fact(8), c5 = (float)-inv_fact(10), c6 = (float)inv_fact(12);
             static_assert(NS == 5 || NS == 7, "series of 5 or 7 terms");
             float ps, pc;
             if constexpr (NS == 7) {
+              // Taylor series, the signs in the coefficients
+              constexpr float s1 = (float)-inv_fact(3), s2 = (float)inv_fact(5), s3 = (float)-inv_fact(7),
+                              s4 = (float)inv_fact(9), s5 = (float)-inv_fact(11), s6 = (float)inv_fact(13);
+              constexpr float c1 = (float)-inv_fact(2), c2 = (float)inv_fact(4), c3 = (float)-inv_fact(6),
+                              c4 = (float)inv_fact(8), c5 = (float)-inv_fact(10), c6 = (float)inv_fact(12);
               ps = fmaf(s6, u, s5);
               ps = fmaf(ps, u, s4);
+              ps = fmaf(ps, u, s3);
+              ps = fmaf(ps, u, s2);
+              ps = fmaf(ps, u, s1);
+              ps = fmaf(ps, u, 1.f);
               pc = fmaf(c6, u, c5);
               pc = fmaf(pc, u, c4);
+              pc = fmaf(pc, u, c3);
+              pc = fmaf(pc, u, c2);
+              pc = fmaf(pc, u, c1);
+              pc = fmaf(pc, u, 1.f);
             } else {
-              ps = s4;
-              pc = c4;
+              // the fitted cubics in u on [0, 1/4]
+              ps = fmaf(-1.9703922747e-04f, u, 8.3331189572e-03f);
+              ps = fmaf(ps, u, -1.6666665595e-01f);
+              ps = fmaf(ps, u, 9.9999999992e-01f);
+              pc = fmaf(-1.3765364239e-03f, u, 4.1664739108e-02f);
+              pc = fmaf(pc, u, -4.9999990368e-01f);
+              pc = fmaf(pc, u, 9.9999999925e-01f);
             }
-            ps = fmaf(ps, u, s3);
-            ps = fmaf(ps, u, s2);
-            ps = fmaf(ps, u, s1);
-            ps = fmaf(ps, u, 1.f);
-            pc = fmaf(pc, u, c3);
-            pc = fmaf(pc, u, c2);
-            pc = fmaf(pc, u, c1);
-            pc = fmaf(pc, u, 1.f);
             hr = ok ? ps : 0.f;
             hi = -pc * y;
           } else {
@@ -2630,7 +2663,14 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
           const float qr = B.z, qi = B.w;
           ax = fmaf(qr, hr, fmaf(-qi, hi, ax));
           ay = fmaf(qr, hi, fmaf(qi, hr, ay));
-        }
+        };
+        // the chunk's sources of the own leaf (the first nt of the concatenation), then the rest
+        const int nown = nt - base < nch ? (nt - base > 0 ? nt - base : 0) : nch;
+        int j = b;
+#pragma unroll 4
+        for (; j < nown; j += TB) pair(j, std::true_type{});
+#pragma unroll 4
+        for (; j < nch; j += TB) pair(j, std::false_type{});
 #pragma unroll
         for (int m = TB / 2; m >= 1; m >>= 1) {
           ax += __shfl_xor(ax, m, 64);

@@ -54,7 +54,8 @@ def test_noalloc_rejects_oversized_workspace_and_recovers():
     s = W.small_three_layer(n_per_layer=50, seed=64, p=8, leaf=16)
     xs, qs = _dev(s)
     a, b = torch.empty_like(qs), torch.empty_like(qs)
-    P2 = lfmm.Plan(s["d"], s["k"], p=8, leaf_max=16)
+    # a fresh plan with the same settings: the same trees, so the same summation order
+    P2 = lfmm.Plan(w["d"], w["k"], p=8, leaf_max=64)
     P.eval_device(xs, qs, a)
     P2.eval_device(xs, qs, b)
     torch.cuda.synchronize()
