@@ -32,7 +32,7 @@ PEAK = {("mfma", 64): 78.6, ("mfma", 32): 157.3, ("alu", 64): 78.6, ("alu", 32):
 # cos(x) series (9 + 10 fma), -cos(kr)/(kr) (1), complex multiply-add (8) = 65.  FP32: hi/lo
 # differences (9), (kr)^2 (5), rsqrt (1), series (6 + 6 fma), -cos(kr)/(kr) (1), complex
 # multiply-add (8) = 48.
-P2P_FLOPS_PER_PAIR = {64: 65, 32: 48}  # series forms for k r <= 1
+P2P_FLOPS_PER_PAIR = {64: 55, 32: 40}  # the fitted polynomials for k r <= 1 (7 + 7 and 4 + 4 fma)
 P2P_SHORT_FLOPS_PER_PAIR = {64: 47, 32: 36}  # the fitted polynomials for k r <= 1/2 (5 + 5 and 3 + 3 fma)
 # what one near-field pair needs by the method's own count: differences, r^2, k r, the complex
 # multiply-add (about 20 flops) and sqrt, reciprocal, sin, cos (one operation each)

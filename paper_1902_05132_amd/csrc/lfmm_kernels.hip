@@ -2328,12 +2328,11 @@ extern "C" void lk_src_l2l(int nent, const int* trow, const int* box_code, const
 // 64/TA source columns are combined by a butterfly over lanes, and each wave owns
 // whole target blocks, so the sums are formed in a fixed order.
 // When k r <= 1 holds for every pair the kernel can meet (host-checked bound),
-// sin(x)/x and cos(x) are evaluated as their Taylor series in u = x^2 (ten
-// terms each: truncation below 1e-18 relative on u <= 1), and 1/r comes from the
-// hardware reciprocal square root refined by two Newton steps, so a pair costs
-// no division, no square root and no argument reduction.
+// sin(x)/x and cos(x) are evaluated as polynomials in u = x^2 fitted on the range
+// of u (errors below FP64 rounding), and 1/r comes from the hardware reciprocal
+// square root refined by two Newton steps, so a pair costs no division, no square
+// root and no argument reduction.
 // ---------------------------------------------------------------------------
-__device__ constexpr double inv_fact(int n) { return n <= 1 ? 1.0 : inv_fact(n - 1) / (double)n; }
 __device__ __forceinline__ double rsqrt_nr(double r2) {
   double y = __builtin_amdgcn_rsq(r2);
   double hh = 0.5 * r2;
@@ -2342,40 +2341,30 @@ __device__ __forceinline__ double rsqrt_nr(double r2) {
   return y;
 }
 // h0(x) = sin(x)/x - i cos(x)/x for x = k r, from u = x^2 > 0 and y = 1/x (hr + i hi).
-// FORM 1: series of sin(x)/x (10 terms) and cos(x) (11 terms) for x <= 1; FORM 2:
-// fitted polynomials of degree 5 in u for x <= 1/2; FORM 0: sincos.  The signs are in
-// the coefficients.
+// FORM 1: fitted polynomials of degree 7 in u for x <= 1; FORM 2: of degree 5 for
+// x <= 1/2; FORM 0: sincos.
 template <int FORM>
 __device__ __forceinline__ void h0_pair(double u, double y, double& hr, double& hi) {
   if constexpr (FORM > 0) {
-    constexpr double s1 = -inv_fact(3), s2 = inv_fact(5), s3 = -inv_fact(7), s4 = inv_fact(9), s5 = -inv_fact(11),
-                     s6 = inv_fact(13), s7 = -inv_fact(15), s8 = inv_fact(17), s9 = -inv_fact(19);
-    constexpr double c1 = -inv_fact(2), c2 = inv_fact(4), c3 = -inv_fact(6), c4 = inv_fact(8), c5 = -inv_fact(10),
-                     c6 = inv_fact(12), c7 = -inv_fact(14), c8 = inv_fact(16), c9 = -inv_fact(18),
-                     c10 = inv_fact(20);
     static_assert(FORM == 1 || FORM == 2, "series forms 1 and 2");
     double ps, pc;
     if constexpr (FORM == 1) {
-      // Taylor series where x <= 1
-      ps = fma(s9, u, s8);
-      ps = fma(ps, u, s7);
-      ps = fma(ps, u, s6);
-      ps = fma(ps, u, s5);
-      ps = fma(ps, u, s4);
-      ps = fma(ps, u, s3);
-      ps = fma(ps, u, s2);
-      ps = fma(ps, u, s1);
-      ps = fma(ps, u, 1.0);
-      pc = fma(c10, u, c9);
-      pc = fma(pc, u, c8);
-      pc = fma(pc, u, c7);
-      pc = fma(pc, u, c6);
-      pc = fma(pc, u, c5);
-      pc = fma(pc, u, c4);
-      pc = fma(pc, u, c3);
-      pc = fma(pc, u, c2);
-      pc = fma(pc, u, c1);
-      pc = fma(pc, u, 1.0);
+      // where x <= 1: polynomials of degree 7 in u fitted on [0, 1] (least squares on
+      // Chebyshev nodes; largest error 1.1e-18 for sin(x)/x, 1.6e-17 for cos x)
+      ps = fma(-7.5354880644876129003e-13, u, 1.6057233337039861802e-10);
+      ps = fma(ps, u, -2.5052093083699723249e-8);
+      ps = fma(ps, u, 2.7557319152309194144e-6);
+      ps = fma(ps, u, -1.9841269841087476663e-4);
+      ps = fma(ps, u, 8.3333333333331054536e-3);
+      ps = fma(ps, u, -1.6666666666666665582e-1);
+      ps = fma(ps, u, 9.9999999999999999992e-1);
+      pc = fma(-1.1281052794952459614e-11, u, 2.0873682510844004151e-9);
+      pc = fma(pc, u, -2.7557293243107711753e-7);
+      pc = fma(pc, u, 2.480158717989726233e-5);
+      pc = fma(pc, u, -1.3888888888579294079e-3);
+      pc = fma(pc, u, 4.1666666666662798174e-2);
+      pc = fma(pc, u, -4.9999999999999981584e-1);
+      pc = fma(pc, u, 9.9999999999999999856e-1);
     } else {
       // where x <= 1/2: polynomials of degree 5 in u fitted on [0, 1/4] (least squares
       // on Chebyshev nodes; largest error 1.9e-17 for sin(x)/x, 2.5e-16 for cos x)
@@ -2527,11 +2516,12 @@ __global__ __launch_bounds__(256, 5) void k_p2p_free(int nseg, const int* seg_ro
 // units of 1/k, r2 is (k r)^2 and the reciprocal square root gives 1/(k r) directly.
 // A source is one 32-byte LDS record (x, y, z, xl | yl, zl, Re q, Im q): two 16-byte
 // reads at offsets the compiler folds into the instruction.  NS selects how sin(x)/x and
-// cos(x), x = k r, are evaluated (v_rsq_f32 for 1/x): 7, their Taylor series to seven
-// terms where x <= 1 on every pair (truncation below 1e-11); 5, where x <= 1/2,
-// polynomials of degree 3 in u = x^2 fitted on [0, 1/4] by Chebyshev interpolation
-// (largest error 8.4e-11 for sin(x)/x and 7.5e-10 for cos x, against 6e-8 for one
-// FP32 rounding); 0 takes sincosf.  The neighbour leaves are taken with the target's
+// cos(x), x = k r, are evaluated (v_rsq_f32 for 1/x): 7, where x <= 1 on every pair,
+// polynomials of degree 4 in u = x^2 fitted on [0, 1]; 5, where x <= 1/2, polynomials
+// of degree 3 fitted on [0, 1/4] (least squares on Chebyshev nodes; with the
+// coefficients rounded to FP32 the largest errors are 7.1e-9 and 4.7e-9 on [0, 1],
+// 8.4e-11 and 7.5e-10 on [0, 1/4], against 6e-8 for one FP32 rounding); 0 takes
+// sincosf.  The neighbour leaves are taken with the target's
 // own leaf first: only its sources can coincide with a target (coincident points
 // share a leaf), so only they go through the select that drops coincident pairs.
 template <int NS, int TA, int CH>
@@ -2625,23 +2615,15 @@ __global__ __launch_bounds__(256) void k_p2p_free32(int nseg, const int* seg_row
             static_assert(NS == 5 || NS == 7, "series of 5 or 7 terms");
             float ps, pc;
             if constexpr (NS == 7) {
-              // Taylor series, the signs in the coefficients
-              constexpr float s1 = (float)-inv_fact(3), s2 = (float)inv_fact(5), s3 = (float)-inv_fact(7),
-                              s4 = (float)inv_fact(9), s5 = (float)-inv_fact(11), s6 = (float)inv_fact(13);
-              constexpr float c1 = (float)-inv_fact(2), c2 = (float)inv_fact(4), c3 = (float)-inv_fact(6),
-                              c4 = (float)inv_fact(8), c5 = (float)-inv_fact(10), c6 = (float)inv_fact(12);
-              ps = fmaf(s6, u, s5);
-              ps = fmaf(ps, u, s4);
-              ps = fmaf(ps, u, s3);
-              ps = fmaf(ps, u, s2);
-              ps = fmaf(ps, u, s1);
-              ps = fmaf(ps, u, 1.f);
-              pc = fmaf(c6, u, c5);
-              pc = fmaf(pc, u, c4);
-              pc = fmaf(pc, u, c3);
-              pc = fmaf(pc, u, c2);
-              pc = fmaf(pc, u, c1);
-              pc = fmaf(pc, u, 1.f);
+              // the fitted quartics in u on [0, 1]
+              ps = fmaf(2.6937597576e-06f, u, -1.9835866409e-04f);
+              ps = fmaf(ps, u, 8.3333140695e-03f);
+              ps = fmaf(ps, u, -1.6666666426e-01f);
+              ps = fmaf(ps, u, 9.9999999995e-01f);
+              pc = fmaf(2.4121201082e-05f, u, -1.3882960343e-03f);
+              pc = fmaf(pc, u, 4.1666455375e-02f);
+              pc = fmaf(pc, u, -4.9999997362e-01f);
+              pc = fmaf(pc, u, 9.9999999947e-01f);
             } else {
               // the fitted cubics in u on [0, 1/4]
               ps = fmaf(-1.9703922747e-04f, u, 8.3331189572e-03f);

@@ -66,7 +66,7 @@ def test_mixed_precision_near_field_library_path():
 def test_mixed_near_field_forms_against_oracle(side, k, form):
     """One medium, every particle in one leaf: the FP32 near field alone against the
     oracle's direct sum, in each form of h0.  The host bounds k r by 2 k side sqrt(3):
-    0.35 <= 1/2 at side 0.05 (fitted cubics), 0.69 <= 1 at side 0.1 (seven Taylor terms),
+    0.35 <= 1/2 at side 0.05 (fitted cubics), 0.69 <= 1 at side 0.1 (fitted quartics),
     6.9 at side 1 (sincosf)."""
     import oracle as O
     from paper_1902_05132_amd import lfmm
